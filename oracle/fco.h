@@ -1,0 +1,99 @@
+/*
+ * fco.h -- CPU FP64 oracle for leaf-patch AMR wave propagation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This code is a plain, slow, independent
+ * restatement of what one time step of the forest-of-quadtrees leaf-patch
+ * method computes (ForestClaw, Burstedde, Calhoun, Mandli, Terrel, arXiv
+ * 1308.1472).  Only the test-suite, the smoke check and the CPU-baseline leg
+ * of the benchmark may load it.  It shares no code, header, table or
+ * constant with the HIP library it checks.
+ *
+ * Conventions (2D, quadtrees):
+ *   - every tree is the reference square [0,1]^2 (Sec. 2, "each block is a
+ *     reference unit cube with its own geometric mapping");
+ *   - a leaf at level l with integer coordinates (ix, iy) in [0, 2^l)^2
+ *     covers [ix, ix+1] 2^-l x [iy, iy+1] 2^-l and houses one m x m patch
+ *     (Sec. 2, the 1:1 leaf <-> patch correspondence);
+ *   - patch cells (i, j), i, j = 1..m; two ghost layers i, j in
+ *     {-1, 0, m+1, m+2} (Sec. 3, "two layers of ghost cells");
+ *   - face ids 0 = xi-low, 1 = xi-high, 2 = eta-low, 3 = eta-high;
+ *   - per-patch state is stored "framed": q[p][k][(j+1)*(m+4) + (i+1)],
+ *     i.e. a (m+4)^2 array per component with i fastest.
+ */
+#ifndef FCO_H
+#define FCO_H
+
+#include <stdint.h>
+
+#define FCO_S 30                      /* tree side = 2^30 integer units  */
+#define FCO_SIDE ((int64_t)1 << FCO_S)
+#define FCO_MAXEQ 4
+
+typedef struct { int32_t tree, level, ix, iy; } fco_leaf;
+
+/* Per tree face: bc == 0 means connected to (nbr_tree, nbr_face) with
+ * orient 0 (tangential coordinate runs the same way) or 1 (reversed);
+ * bc == 1 reflecting wall; bc == 2 zero-order extrapolation. */
+typedef struct {
+  int32_t nbr_tree[4], nbr_face[4], orient[4], bc[4];
+} fco_tree;
+
+enum { FCO_ADVECTION = 0, FCO_SHALLOW = 1, FCO_SPHERE = 2 };
+
+typedef struct {
+  int32_t m;           /* cells per patch side (even, >= 4)            */
+  int32_t meqn;        /* 1 advection, 3 planar shallow water, 4 sphere */
+  int32_t physics;     /* FCO_ADVECTION / FCO_SHALLOW / FCO_SPHERE      */
+  int32_t limiter;     /* 0 none, 1 minmod, 2 superbee, 3 van Leer, 4 MC */
+  int32_t transverse;  /* 0 none, 1 fluctuations, 2 fluctuations + corrections */
+  int32_t pad;
+  double g;            /* gravity (shallow water)                      */
+  double ax, ay;       /* advection velocity (computational coords)    */
+} fco_params;
+
+typedef struct fco_mesh fco_mesh;
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- forest ------------------------------------------------------- */
+int  fco_sfc_sort(int64_t n, fco_leaf *leaves);
+fco_mesh *fco_mesh_new(int32_t ntrees, const fco_tree *trees, int64_t n,
+                       const fco_leaf *leaves, int32_t m, int32_t sphere);
+void fco_mesh_free(fco_mesh *mesh);
+int64_t fco_mesh_size(const fco_mesh *mesh);
+int  fco_is_balanced(const fco_mesh *mesh);
+int  fco_balance(int32_t ntrees, const fco_tree *trees, int64_t n,
+                 const fco_leaf *in, int64_t cap, fco_leaf *out,
+                 int64_t *nout);
+int  fco_locate_leaf(const fco_mesh *mesh, int32_t tree, int64_t x,
+                     int64_t y, int64_t *leaf);
+
+/* ---- ghost fill, step, sums ---------------------------------------- */
+int  fco_ghost_fill(const fco_mesh *mesh, const fco_params *par, double *q,
+                    int32_t *max_depth);
+int  fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
+              double *qn, double dt, int32_t reflux, double *numax);
+int  fco_sums(const fco_mesh *mesh, const fco_params *par, const double *q,
+              double *sums);
+
+/* ---- regrid --------------------------------------------------------- */
+int  fco_tags(const fco_mesh *mesh, const fco_params *par, const double *q,
+              int32_t criterion, double threshold, int32_t lmin,
+              int32_t lmax, int8_t *tags);
+int  fco_regrid(const fco_mesh *mesh, const int8_t *tags, int32_t lmin,
+                int32_t lmax, int64_t cap, fco_leaf *out, int64_t *nout);
+int  fco_transfer(const fco_mesh *old_mesh, const fco_mesh *new_mesh,
+                  const fco_params *par, const double *q_old, double *q_new);
+
+/* ---- pieces exposed for pinning ------------------------------------ */
+double fco_phi(int32_t limiter, double theta);
+int  fco_riemann(const fco_params *par, int32_t dir, const double *ql,
+                 const double *qr, double *waves, double *speeds,
+                 double *amdq, double *apdq);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,224 @@
+/*
+ * fco_regrid.c -- refinement tags and mesh modification of the CPU oracle
+ * (test infrastructure only).
+ *
+ * Sec. 2: the only information passed to the mesher is a set of per-patch
+ * refine / coarsen flags computed from the numerical state; the mesher then
+ * refines, coarsens and restores 2:1 balance.  Sec. 5: a patch is tagged for
+ * refinement when its criterion exceeds a threshold, and a family of 2^d
+ * patches is coarsened when the parent patch would not be tagged.
+ *
+ * Criteria:
+ *   0: max - min of the first component over the patch interior (Sec. 5);
+ *   1: max over interior cells of |grad h| by central differences over the
+ *      ghost-extended data, in physical spacing.
+ * The parent test uses the 2x2 (capacity-weighted) averages of the four
+ * children, central differences inside and one-sided differences on the
+ * outer ring (reading: no parent ghost cells are formed).
+ * Comparisons are made on squared quantities with no fused operations so
+ * that an independent implementation can reproduce every decision exactly.
+ *
+ * Tags: +1 refine (criterion true, level < lmax); -1 on all four members
+ * of a family of leaf siblings above lmin none of which is tagged +1 and
+ * whose parent fails the criterion; 0 otherwise.
+ * Apply: refine +1 leaves, merge families tagged -1, then restore balance
+ * by refinement only (a merge that would break balance is undone).
+ */
+#include "fco_internal.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+static double qv(const double *q, int32_t m, int32_t meqn, int64_t p, int k,
+                 int32_t i, int32_t j) {
+  return q[(p * meqn + k) * fco_frame(m) + fco_fidx(m, i, j)];
+}
+
+/* physical spacing between the centres of cells a and b of patch p */
+static double spacing(const fco_mesh *mesh, int64_t p, int32_t ia, int32_t ja,
+                      int32_t ib, int32_t jb) {
+  if (!mesh->sphere) {
+    int32_t n = abs(ib - ia) + abs(jb - ja);
+    return n * (ldexp(1.0, -mesh->leaves[p].level) / mesh->m);
+  }
+  double ra[3], rb[3];
+  fco_sphere_centre(mesh, p, ia, ja, ra);
+  fco_sphere_centre(mesh, p, ib, jb, rb);
+  double cx = ra[1] * rb[2] - ra[2] * rb[1];
+  double cy = ra[2] * rb[0] - ra[0] * rb[2];
+  double cz = ra[0] * rb[1] - ra[1] * rb[0];
+  double dot = ra[0] * rb[0] + ra[1] * rb[1] + ra[2] * rb[2];
+  return atan2(sqrt(cx * cx + cy * cy + cz * cz), dot);
+}
+
+static int refine_criterion(const fco_mesh *mesh, const fco_params *par,
+                            const double *q, int64_t p, int criterion,
+                            double thr) {
+  const int32_t m = mesh->m, meqn = par->meqn;
+  if (criterion == 0) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int32_t j = 1; j <= m; ++j)
+      for (int32_t i = 1; i <= m; ++i) {
+        double v = qv(q, m, meqn, p, 0, i, j);
+        lo = fmin(lo, v);
+        hi = fmax(hi, v);
+      }
+    return (hi - lo) > thr;
+  }
+  const double t2 = thr * thr;
+  for (int32_t j = 1; j <= m; ++j)
+    for (int32_t i = 1; i <= m; ++i) {
+      double gx = (qv(q, m, meqn, p, 0, i + 1, j) - qv(q, m, meqn, p, 0, i - 1, j)) /
+                  spacing(mesh, p, i - 1, j, i + 1, j);
+      double gy = (qv(q, m, meqn, p, 0, i, j + 1) - qv(q, m, meqn, p, 0, i, j - 1)) /
+                  spacing(mesh, p, i, j - 1, i, j + 1);
+      double s = gx * gx;
+      s = s + gy * gy;
+      if (s > t2) return 1;
+    }
+  return 0;
+}
+
+/* criterion on the averaged parent of the family whose first child is p */
+static int parent_criterion(const fco_mesh *mesh, const fco_params *par,
+                            const double *q, const int64_t kids[4],
+                            int criterion, double thr) {
+  const int32_t m = mesh->m, meqn = par->meqn, h = m / 2;
+  double *P = (double *)malloc(sizeof(double) * m * m);
+  double *cx = (double *)malloc(sizeof(double) * m * m * 3);
+  for (int32_t J = 1; J <= m; ++J)
+    for (int32_t I = 1; I <= m; ++I) {
+      int c = ((I - 1) >= h) + 2 * ((J - 1) >= h);
+      int64_t kp = kids[c];
+      int32_t ii = 2 * ((I - 1) % h) + 1, jj = 2 * ((J - 1) % h) + 1;
+      double acc = 0.0, w = 0.0;
+      double r[3] = {0, 0, 0};
+      for (int b = 0; b < 4; ++b) {
+        int32_t i2 = ii + (b & 1), j2 = jj + (b >> 1);
+        double kap = mesh->sphere ? fco_sphere_kappa(mesh, kp, i2, j2) : 1.0;
+        acc += kap * qv(q, m, meqn, kp, 0, i2, j2);
+        w += kap;
+        if (mesh->sphere) {
+          double rc[3];
+          fco_sphere_centre(mesh, kp, i2, j2, rc);
+          for (int d = 0; d < 3; ++d) r[d] += rc[d];
+        }
+      }
+      P[(J - 1) * m + (I - 1)] = acc / w;
+      if (mesh->sphere) {
+        double nr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+        for (int d = 0; d < 3; ++d) cx[((J - 1) * m + (I - 1)) * 3 + d] = r[d] / nr;
+      }
+    }
+  int res = 0;
+  if (criterion == 0) {
+    double lo = INFINITY, hi = -INFINITY;
+    for (int32_t k = 0; k < m * m; ++k) {
+      lo = fmin(lo, P[k]);
+      hi = fmax(hi, P[k]);
+    }
+    res = (hi - lo) > thr;
+  } else {
+    const double dxp = ldexp(1.0, -(mesh->leaves[kids[0]].level - 1)) / m;
+    const double t2 = thr * thr;
+    for (int32_t J = 1; J <= m && !res; ++J)
+      for (int32_t I = 1; I <= m && !res; ++I) {
+        int32_t ia = I > 1 ? I - 1 : I, ib = I < m ? I + 1 : I;
+        int32_t ja = J > 1 ? J - 1 : J, jb = J < m ? J + 1 : J;
+        double sx, sy;
+        if (mesh->sphere) {
+          const double *a = &cx[((J - 1) * m + (ia - 1)) * 3];
+          const double *b = &cx[((J - 1) * m + (ib - 1)) * 3];
+          double c0 = a[1] * b[2] - a[2] * b[1], c1 = a[2] * b[0] - a[0] * b[2],
+                 c2 = a[0] * b[1] - a[1] * b[0];
+          sx = atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2),
+                     a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+          a = &cx[((ja - 1) * m + (I - 1)) * 3];
+          b = &cx[((jb - 1) * m + (I - 1)) * 3];
+          c0 = a[1] * b[2] - a[2] * b[1]; c1 = a[2] * b[0] - a[0] * b[2];
+          c2 = a[0] * b[1] - a[1] * b[0];
+          sy = atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2),
+                     a[0] * b[0] + a[1] * b[1] + a[2] * b[2]);
+        } else {
+          sx = (ib - ia) * dxp;
+          sy = (jb - ja) * dxp;
+        }
+        double gx = (P[(J - 1) * m + (ib - 1)] - P[(J - 1) * m + (ia - 1)]) / sx;
+        double gy = (P[(jb - 1) * m + (I - 1)] - P[(ja - 1) * m + (I - 1)]) / sy;
+        double s = gx * gx;
+        s = s + gy * gy;
+        if (s > t2) res = 1;
+      }
+  }
+  free(P);
+  free(cx);
+  return res;
+}
+
+int fco_tags(const fco_mesh *mesh, const fco_params *par, const double *q,
+             int32_t criterion, double threshold, int32_t lmin, int32_t lmax,
+             int8_t *tags) {
+  if (!mesh || !par || !q || !tags || (criterion != 0 && criterion != 1))
+    return -1;
+  const int64_t n = mesh->n;
+  char *crit = (char *)malloc((size_t)n);
+  for (int64_t p = 0; p < n; ++p) {
+    crit[p] = (char)refine_criterion(mesh, par, q, p, criterion, threshold);
+    tags[p] = (crit[p] && mesh->leaves[p].level < lmax) ? 1 : 0;
+  }
+  for (int64_t p = 0; p < n; ++p) {
+    const fco_leaf *a = &mesh->leaves[p];
+    if (a->level <= lmin || (a->ix & 1) || (a->iy & 1)) continue;
+    int64_t kids[4];
+    int ok = 1;
+    for (int c = 0; c < 4 && ok; ++c) {
+      kids[c] = fco_find(mesh, a->tree, a->level, a->ix + (c & 1),
+                         a->iy + (c >> 1));
+      if (kids[c] < 0 || tags[kids[c]] == 1) ok = 0;
+    }
+    if (!ok) continue;
+    if (!parent_criterion(mesh, par, q, kids, criterion, threshold))
+      for (int c = 0; c < 4; ++c) tags[kids[c]] = -1;
+  }
+  free(crit);
+  return 0;
+}
+
+int fco_regrid(const fco_mesh *mesh, const int8_t *tags, int32_t lmin,
+               int32_t lmax, int64_t cap, fco_leaf *out, int64_t *nout) {
+  const int64_t n = mesh->n;
+  fco_leaf *tmp = (fco_leaf *)malloc(sizeof(fco_leaf) * (size_t)(4 * n));
+  int64_t k = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    const fco_leaf *a = &mesh->leaves[p];
+    if (tags[p] > 0 && a->level < lmax) {
+      for (int c = 0; c < 4; ++c) {
+        fco_leaf ch = {a->tree, a->level + 1, 2 * a->ix + (c & 1),
+                       2 * a->iy + (c >> 1)};
+        tmp[k++] = ch;
+      }
+      continue;
+    }
+    if (tags[p] < 0 && a->level > lmin) {
+      /* the family merges only when all four siblings are leaves tagged -1 */
+      int all = 1;
+      int32_t bx = a->ix & ~1, by = a->iy & ~1;
+      for (int c = 0; c < 4 && all; ++c) {
+        int64_t s = fco_find(mesh, a->tree, a->level, bx + (c & 1), by + (c >> 1));
+        if (s < 0 || tags[s] >= 0) all = 0;
+      }
+      if (all) {
+        if (a->ix == bx && a->iy == by) {
+          fco_leaf par = {a->tree, a->level - 1, a->ix / 2, a->iy / 2};
+          tmp[k++] = par;
+        }
+        continue;
+      }
+    }
+    tmp[k++] = *a;
+  }
+  int rc = fco_balance(mesh->ntrees, mesh->trees, k, tmp, cap, out, nout);
+  free(tmp);
+  return rc;
+}

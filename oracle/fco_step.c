@@ -1,0 +1,531 @@
+/*
+ * fco_step.c -- one wave-propagation time step on every leaf patch, for the
+ * CPU oracle (test infrastructure only).
+ *
+ * Sec. 3 of the paper: each patch is advanced by the wave-propagation
+ * algorithm of LeVeque (JCP 1997; "Finite Volume Methods for Hyperbolic
+ * Problems", 2002) -- piecewise-constant states, a Riemann problem at every
+ * cell edge giving waves and speeds, wave limiters for the second-order
+ * corrections, and (from the cited unsplit method) transverse propagation.
+ * For systems a Roe solver is used (Roe 1981, cited in Sec. 3).
+ *
+ * Per patch, on the ghost-extended array Q (time level n) and a given dt:
+ *   xi-sweep over rows j = 0..m+1, edges i-1/2 for i = 0..m+2:
+ *     Riemann(Q[i-1], Q[i]) -> waves W^p, speeds s^p,
+ *     A-dq = sum min(s,0) W,  A+dq = sum max(s,0) W;
+ *   at edges i = 1..m+1: theta^p = W^p_upwind . W^p / W^p . W^p (upwind
+ *     edge i-3/2 if s > 0, else i+1/2), limited wave phi(theta) W,
+ *     correction flux Ft = 1/2 sum |s| (1 - nu |s|) Wlim with
+ *     nu = 1/2 (dt/(kappa_l dx) + dt/(kappa_r dx));
+ *   transverse (mode 2): A-dq + C and A+dq - C, C = sum |s|(1-nu|s|) Wlim,
+ *     split by the eta-eigenstructure into down/up parts that are
+ *     subtracted, times dt/(2 kappa dx) of the receiving cell, from the
+ *     eta-correction flux of the cell's lower/upper edge;
+ *   eta-sweep symmetric (both sweeps read Q^n: the scheme is unsplit);
+ *   update of interior cells with the unmodified fluctuations:
+ *     Q' = Q - dt/(kappa dx) [A+dq(i-1/2) + A-dq(i+1/2) + Ft(i+1/2) - Ft(i-1/2)]
+ *            - dt/(kappa dy) [B+dq(j-1/2) + B-dq(j+1/2) + Gt(j+1/2) - Gt(j-1/2)].
+ * Accumulation order is fixed: xi-rows ascending, then eta-columns
+ * ascending, edges ascending inside each.
+ *
+ * Reflux (reading of Sec. 4, "correction factors are propagated back from
+ * fine to coarse levels", with one global dt): at every coarse-fine face
+ * the coarse cell's face term is replaced by the sum of the fine face
+ * terms.  The Roe property turns the missing f(Q_fine) - f(Q_coarse) into
+ * the fluctuation sum of one extra Riemann problem per fine cell.
+ */
+#include "fco_internal.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MW 3   /* at most three waves */
+
+double fco_phi(int32_t limiter, double th) {
+  switch (limiter) {
+    case 0: return 1.0;                                   /* Lax-Wendroff */
+    case 1: return fmax(0.0, fmin(1.0, th));              /* minmod */
+    case 2: return fmax(0.0, fmax(fmin(1.0, 2.0 * th), fmin(2.0, th)));
+    case 3: return (th + fabs(th)) / (1.0 + fabs(th));    /* van Leer */
+    case 4: return fmax(0.0, fmin(fmin(0.5 * (1.0 + th), 2.0), 2.0 * th));
+    default: return NAN;
+  }
+}
+
+/* ---------------- edge geometry (Cartesian or mapped) ---------------- */
+typedef struct {
+  double gamma;       /* edge length / computational edge length */
+  double n[3], t[3];  /* sphere: unit normal and tangent */
+} edge_geom;
+
+/* ---------------- Riemann solvers ------------------------------------ */
+/* Normal solvers fill waves[w*meqn+k], speeds[w], amdq, apdq; return the
+ * number of waves, or -1 if a depth is not positive. */
+static int rp_advection(const fco_params *par, int dir, const double *ql,
+                        const double *qr, double *W, double *s, double *am,
+                        double *ap) {
+  double a = dir == 0 ? par->ax : par->ay;
+  W[0] = qr[0] - ql[0];
+  s[0] = a;
+  am[0] = fmin(a, 0.0) * W[0];
+  ap[0] = fmax(a, 0.0) * W[0];
+  return 1;
+}
+
+typedef struct { double u, v, c; } roe_avg;
+
+/* Roe averages of the edge pair, velocities in the (normal, tangential)
+ * frame given by the momentum indices mu, mv */
+static int roe_average(const fco_params *par, const double *ql,
+                       const double *qr, int mu, int mv, roe_avg *r) {
+  double hl = ql[0], hr = qr[0];
+  if (!(hl > 0.0) || !(hr > 0.0)) return -1;
+  double sl = sqrt(hl), sr = sqrt(hr);
+  r->u = (ql[mu] / sl + qr[mu] / sr) / (sl + sr);
+  r->v = (ql[mv] / sl + qr[mv] / sr) / (sl + sr);
+  r->c = sqrt(par->g * 0.5 * (hl + hr));
+  return 0;
+}
+
+static int rp_shallow(const fco_params *par, int dir, const double *ql,
+                      const double *qr, double *W, double *s, double *am,
+                      double *ap) {
+  const int mu = 1 + dir, mv = 2 - dir;
+  roe_avg r;
+  if (roe_average(par, ql, qr, mu, mv, &r) != 0) return -1;
+  double d0 = qr[0] - ql[0], d1 = qr[mu] - ql[mu], d2 = qr[mv] - ql[mv];
+  double a1 = ((r.u + r.c) * d0 - d1) / (2.0 * r.c);
+  double a2 = d2 - r.v * d0;
+  double a3 = (d1 - (r.u - r.c) * d0) / (2.0 * r.c);
+  memset(W, 0, sizeof(double) * 3 * 3);
+  W[0 * 3 + 0] = a1; W[0 * 3 + mu] = a1 * (r.u - r.c); W[0 * 3 + mv] = a1 * r.v;
+  W[1 * 3 + mv] = a2;
+  W[2 * 3 + 0] = a3; W[2 * 3 + mu] = a3 * (r.u + r.c); W[2 * 3 + mv] = a3 * r.v;
+  s[0] = r.u - r.c; s[1] = r.u; s[2] = r.u + r.c;
+  for (int k = 0; k < 3; ++k) {
+    am[k] = 0.0;
+    ap[k] = 0.0;
+    for (int w = 0; w < 3; ++w) {
+      am[k] += fmin(s[w], 0.0) * W[w * 3 + k];
+      ap[k] += fmax(s[w], 0.0) * W[w * 3 + k];
+    }
+  }
+  return 3;
+}
+
+/* Transverse splitting of a normal fluctuation asdq (from the edge with
+ * states ql, qr) into parts moving down / up in the other direction. */
+static int tsplit_advection(const fco_params *par, int dir, const double *asdq,
+                            double *bm, double *bp) {
+  double b = dir == 0 ? par->ay : par->ax;
+  bm[0] = fmin(b, 0.0) * asdq[0];
+  bp[0] = fmax(b, 0.0) * asdq[0];
+  return 0;
+}
+
+static int tsplit_shallow(const fco_params *par, int dir, const double *ql,
+                          const double *qr, const double *psi, double *bm,
+                          double *bp) {
+  const int mu = 1 + dir, mv = 2 - dir;
+  roe_avg r;
+  if (roe_average(par, ql, qr, mu, mv, &r) != 0) return -1;
+  double b1 = ((r.v + r.c) * psi[0] - psi[mv]) / (2.0 * r.c);
+  double b2 = psi[mu] - r.u * psi[0];
+  double b3 = (psi[mv] - (r.v - r.c) * psi[0]) / (2.0 * r.c);
+  double lam[3] = {r.v - r.c, r.v, r.v + r.c};
+  double R[3][3];
+  R[0][0] = 1.0; R[0][mu] = r.u; R[0][mv] = r.v - r.c;
+  R[1][0] = 0.0; R[1][mu] = 1.0; R[1][mv] = 0.0;
+  R[2][0] = 1.0; R[2][mu] = r.u; R[2][mv] = r.v + r.c;
+  double beta[3] = {b1, b2, b3};
+  for (int k = 0; k < 3; ++k) {
+    bm[k] = 0.0;
+    bp[k] = 0.0;
+    for (int w = 0; w < 3; ++w) {
+      bm[k] += fmin(lam[w], 0.0) * beta[w] * R[w][k];
+      bp[k] += fmax(lam[w], 0.0) * beta[w] * R[w][k];
+    }
+  }
+  return 0;
+}
+
+/* sphere solvers live in fco_sphere.c */
+int fco_rp_sphere(const fco_params *par, const edge_geom *e, const double *ql,
+                  const double *qr, double *W, double *s, double *am,
+                  double *ap);
+int fco_tsplit_sphere(const fco_params *par, const double *ql,
+                      const double *qr, const edge_geom *normal_edge,
+                      const edge_geom *tedge, const double *psi, double *bsdq,
+                      int up);
+
+static int riemann(const fco_params *par, int dir, const edge_geom *e,
+                   const double *ql, const double *qr, double *W, double *s,
+                   double *am, double *ap) {
+  switch (par->physics) {
+    case FCO_ADVECTION: return rp_advection(par, dir, ql, qr, W, s, am, ap);
+    case FCO_SHALLOW: return rp_shallow(par, dir, ql, qr, W, s, am, ap);
+    case FCO_SPHERE: return fco_rp_sphere(par, e, ql, qr, W, s, am, ap);
+    default: return -1;
+  }
+}
+
+int fco_riemann(const fco_params *par, int32_t dir, const double *ql,
+                const double *qr, double *waves, double *speeds, double *amdq,
+                double *apdq) {
+  edge_geom e = {1.0, {0}, {0}};
+  return riemann(par, dir, &e, ql, qr, waves, speeds, amdq, apdq);
+}
+
+/* ---------------- one patch ------------------------------------------ */
+typedef struct {
+  int32_t m, meqn;
+  double *F[2], *AM[2], *AP[2];   /* [edge 0..m+2][row 0..m+1][meqn] */
+  double *W, *S;                   /* one row: [edge][MW][meqn], [edge][MW] */
+  double *kap;                     /* frame of capacities */
+  edge_geom *eg;                   /* one row of edge geometry */
+  edge_geom *tg;                   /* transverse edges of one row */
+} work;
+
+static int64_t eidx(int32_t m, int32_t e, int32_t r) {
+  return (int64_t)e * (m + 2) + r;
+}
+
+static void cell_of(int d, int32_t nidx, int32_t r, int32_t *i, int32_t *j) {
+  if (d == 0) { *i = nidx; *j = r; } else { *i = r; *j = nidx; }
+}
+
+static double qval(const double *Q, int32_t m, int k, int32_t i, int32_t j) {
+  return Q[k * fco_frame(m) + fco_fidx(m, i, j)];
+}
+
+static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
+                      const double *Q, double *Qn, double dt, work *wk,
+                      double *phi, double *numax) {
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const fco_leaf *a = &mesh->leaves[p];
+  const double dx = ldexp(1.0, -a->level) / m;   /* computational spacing */
+  const int64_t NE = (int64_t)(m + 3) * (m + 2);
+  for (int d = 0; d < 2; ++d) {
+    memset(wk->F[d], 0, sizeof(double) * NE * meqn);
+    memset(wk->AM[d], 0, sizeof(double) * NE * meqn);
+    memset(wk->AP[d], 0, sizeof(double) * NE * meqn);
+  }
+  for (int32_t j = -1; j <= m + 2; ++j)
+    for (int32_t i = -1; i <= m + 2; ++i)
+      wk->kap[fco_fidx(m, i, j)] =
+          mesh->sphere ? fco_sphere_kappa(mesh, p, i, j) : 1.0;
+#define KAP(i, j) (wk->kap[fco_fidx(m, (i), (j))])
+  double nmax = 0.0;
+  double ql[FCO_MAXEQ], qr[FCO_MAXEQ], cq[FCO_MAXEQ], amt[FCO_MAXEQ],
+      apt[FCO_MAXEQ], bm[FCO_MAXEQ], bp[FCO_MAXEQ];
+  int nw = 0;
+  for (int d = 0; d < 2; ++d) {
+    double *F = wk->F[d], *FO = wk->F[1 - d];
+    for (int32_t r = 0; r <= m + 1; ++r) {
+      /* Riemann problems at every edge of the row */
+      for (int32_t e = 0; e <= m + 2; ++e) {
+        int32_t il, jl, ir, jr;
+        cell_of(d, e - 1, r, &il, &jl);
+        cell_of(d, e, r, &ir, &jr);
+        for (int k = 0; k < meqn; ++k) {
+          ql[k] = qval(Q, m, k, il, jl);
+          qr[k] = qval(Q, m, k, ir, jr);
+        }
+        edge_geom *eg = &wk->eg[e];
+        if (mesh->sphere) {
+          fco_sphere_edge(mesh, p, d, ir, jr, &eg->gamma, eg->n, eg->t);
+        } else {
+          eg->gamma = 1.0;
+        }
+        nw = riemann(par, d, eg, ql, qr, &wk->W[e * MW * meqn], &wk->S[e * MW],
+                     &wk->AM[d][eidx(m, e, r) * meqn],
+                     &wk->AP[d][eidx(m, e, r) * meqn]);
+        if (nw < 0) return -4;
+      }
+      /* limiter, correction and transverse terms at edges 1..m+1 */
+      for (int32_t e = 1; e <= m + 1; ++e) {
+        int32_t il, jl, ir, jr;
+        cell_of(d, e - 1, r, &il, &jl);
+        cell_of(d, e, r, &ir, &jr);
+        double dtdl = dt / (KAP(il, jl) * dx), dtdr = dt / (KAP(ir, jr) * dx);
+        double nu = 0.5 * (dtdl + dtdr);
+        for (int k = 0; k < meqn; ++k) cq[k] = 0.0;
+        for (int w = 0; w < nw; ++w) {
+          const double *Wc = &wk->W[(e * MW + w) * meqn];
+          double sw = wk->S[e * MW + w];
+          if (r >= 1 && r <= m) {
+            nmax = fmax(nmax, dtdr * fmax(sw, 0.0));
+            nmax = fmax(nmax, dtdl * fmax(-sw, 0.0));
+          }
+          double wn2 = 0.0;
+          for (int k = 0; k < meqn; ++k) wn2 += Wc[k] * Wc[k];
+          if (wn2 == 0.0) continue;
+          int32_t up = sw > 0.0 ? e - 1 : e + 1;
+          const double *Wu = &wk->W[(up * MW + w) * meqn];
+          double dot = 0.0;
+          for (int k = 0; k < meqn; ++k) dot += Wu[k] * Wc[k];
+          double lim = fco_phi(par->limiter, dot / wn2);
+          double as = fabs(sw);
+          for (int k = 0; k < meqn; ++k)
+            cq[k] += as * (1.0 - nu * as) * lim * Wc[k];
+        }
+        double *Fe = &F[eidx(m, e, r) * meqn];
+        for (int k = 0; k < meqn; ++k) Fe[k] += 0.5 * cq[k];
+        if (par->transverse == 0) continue;
+        const double *AMe = &wk->AM[d][eidx(m, e, r) * meqn];
+        const double *APe = &wk->AP[d][eidx(m, e, r) * meqn];
+        for (int k = 0; k < meqn; ++k) {
+          ql[k] = qval(Q, m, k, il, jl);
+          qr[k] = qval(Q, m, k, ir, jr);
+          amt[k] = AMe[k] + (par->transverse == 2 ? cq[k] : 0.0);
+          apt[k] = APe[k] - (par->transverse == 2 ? cq[k] : 0.0);
+        }
+        /* left-going part enters column e-1, right-going part column e;
+         * the lower edge of row r has index r, the upper edge r+1 */
+        for (int side = 0; side < 2; ++side) {
+          const double *psi = side == 0 ? amt : apt;
+          int32_t col = side == 0 ? e - 1 : e;
+          double dtd = side == 0 ? dtdl : dtdr;
+          int rc;
+          if (par->physics == FCO_ADVECTION) {
+            rc = tsplit_advection(par, d, psi, bm, bp);
+          } else if (par->physics == FCO_SHALLOW) {
+            rc = tsplit_shallow(par, d, ql, qr, psi, bm, bp);
+          } else {
+            /* transverse edges of the receiving cell, lower and upper */
+            int32_t ci, cj, ui, uj;
+            cell_of(d, col, r, &ci, &cj);
+            cell_of(d, col, r + 1, &ui, &uj);
+            edge_geom lo, hi;
+            fco_sphere_edge(mesh, p, 1 - d, ci, cj, &lo.gamma, lo.n, lo.t);
+            fco_sphere_edge(mesh, p, 1 - d, ui, uj, &hi.gamma, hi.n, hi.t);
+            rc = fco_tsplit_sphere(par, ql, qr, &wk->eg[e], &lo, psi, bm, 0);
+            if (rc == 0)
+              rc = fco_tsplit_sphere(par, ql, qr, &wk->eg[e], &hi, psi, bp, 1);
+          }
+          if (rc != 0) return -4;
+          double *Flo = &FO[eidx(m, r, col) * meqn];
+          double *Fhi = &FO[eidx(m, r + 1, col) * meqn];
+          for (int k = 0; k < meqn; ++k) {
+            Flo[k] -= 0.5 * dtd * bm[k];
+            Fhi[k] -= 0.5 * dtd * bp[k];
+          }
+        }
+      }
+    }
+  }
+  /* update */
+  const int64_t FR = fco_frame(m);
+  for (int32_t j = 1; j <= m; ++j)
+    for (int32_t i = 1; i <= m; ++i) {
+      double dtd = dt / (KAP(i, j) * dx);
+      for (int k = 0; k < meqn; ++k) {
+        double fx = wk->AP[0][eidx(m, i, j) * meqn + k] +
+                    wk->AM[0][eidx(m, i + 1, j) * meqn + k] +
+                    wk->F[0][eidx(m, i + 1, j) * meqn + k] -
+                    wk->F[0][eidx(m, i, j) * meqn + k];
+        double gy = wk->AP[1][eidx(m, j, i) * meqn + k] +
+                    wk->AM[1][eidx(m, j + 1, i) * meqn + k] +
+                    wk->F[1][eidx(m, j + 1, i) * meqn + k] -
+                    wk->F[1][eidx(m, j, i) * meqn + k];
+        Qn[k * FR + fco_fidx(m, i, j)] =
+            Q[k * FR + fco_fidx(m, i, j)] - dtd * fx - dtd * gy;
+      }
+    }
+  /* face terms for the reflux: the cell's own contribution through each
+   * patch face, times the computational face length dx */
+  if (phi) {
+    for (int f = 0; f < 4; ++f)
+      for (int32_t t = 1; t <= m; ++t)
+        for (int k = 0; k < meqn; ++k) {
+          double v;
+          switch (f) {
+            case 0: v = wk->AP[0][eidx(m, 1, t) * meqn + k] -
+                        wk->F[0][eidx(m, 1, t) * meqn + k]; break;
+            case 1: v = wk->AM[0][eidx(m, m + 1, t) * meqn + k] +
+                        wk->F[0][eidx(m, m + 1, t) * meqn + k]; break;
+            case 2: v = wk->AP[1][eidx(m, 1, t) * meqn + k] -
+                        wk->F[1][eidx(m, 1, t) * meqn + k]; break;
+            default: v = wk->AM[1][eidx(m, m + 1, t) * meqn + k] +
+                         wk->F[1][eidx(m, m + 1, t) * meqn + k]; break;
+          }
+          phi[((int64_t)f * m + (t - 1)) * meqn + k] = dx * v;
+        }
+  }
+#undef KAP
+  *numax = nmax;
+  return 0;
+}
+
+/* ---------------- reflux --------------------------------------------- */
+/* fine-cell position in the leaf that contains point (x, y) of tree t */
+static int fine_cell(const fco_mesh *mesh, int32_t t, int64_t x, int64_t y,
+                     int64_t *L, int32_t *i, int32_t *j, int32_t *tt,
+                     int64_t *xx, int64_t *yy) {
+  if (fco_locate(mesh->trees, t, x, y, tt, xx, yy) != 0) return -1;
+  *L = fco_leaf_at(mesh, *tt, *xx, *yy);
+  if (*L < 0) return -1;
+  const fco_leaf *a = &mesh->leaves[*L];
+  int64_t size = FCO_SIDE >> a->level, cs = size / mesh->m;
+  *i = (int32_t)((*xx - (int64_t)a->ix * size) / cs) + 1;
+  *j = (int32_t)((*yy - (int64_t)a->iy * size) / cs) + 1;
+  return 0;
+}
+
+static int reflux(const fco_mesh *mesh, const fco_params *par, const double *q,
+                  double *qn, double dt, const double *phi) {
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const int64_t FR = fco_frame(m);
+  double W[MW * FCO_MAXEQ], S[MW], am[FCO_MAXEQ], ap[FCO_MAXEQ];
+  double ql[FCO_MAXEQ], qr[FCO_MAXEQ], qc[FCO_MAXEQ], qf[FCO_MAXEQ];
+  for (int f = 0; f < 4; ++f) {
+    const int d = f / 2, hi = f % 2;
+    for (int64_t p = 0; p < mesh->n; ++p) {
+      if (fco_wall_face(mesh, p, f)) continue;
+      const fco_leaf *a = &mesh->leaves[p];
+      const int64_t size = FCO_SIDE >> a->level, cs = size / m;
+      const int64_t x0 = (int64_t)a->ix * size, y0 = (int64_t)a->iy * size;
+      const double dx = ldexp(1.0, -a->level) / m;
+      for (int32_t t = 1; t <= m; ++t) {
+        int32_t ic = d == 0 ? (hi ? m : 1) : t;
+        int32_t jc = d == 0 ? t : (hi ? m : 1);
+        double corr[FCO_MAXEQ] = {0};
+        int fine = 1;
+        for (int k2 = 0; k2 < 2 && fine; ++k2) {
+          /* centre of the k2-th fine cell across the face, and a point a
+           * quarter fine cell closer to the face (same fine cell) */
+          int64_t nrm_out = hi ? size + cs / 4 : -cs / 4;
+          int64_t nrm_in = hi ? size + cs / 8 : -cs / 8;
+          int64_t tan = (int64_t)(t - 1) * cs + (k2 == 0 ? cs / 4 : 3 * cs / 4);
+          int64_t xa, ya, xb, yb;
+          if (d == 0) { xa = x0 + nrm_out; ya = y0 + tan; xb = x0 + nrm_in; yb = ya; }
+          else { xa = x0 + tan; ya = y0 + nrm_out; xb = xa; yb = y0 + nrm_in; }
+          int64_t L, L2, X, Y, X2, Y2;
+          int32_t fi, fj, fi2, fj2, tt, tt2;
+          if (fine_cell(mesh, a->tree, xa, ya, &L, &fi, &fj, &tt, &X, &Y) != 0 ||
+              fine_cell(mesh, a->tree, xb, yb, &L2, &fi2, &fj2, &tt2, &X2, &Y2) != 0)
+            return -5;
+          if (mesh->leaves[L].level != a->level + 1) { fine = 0; break; }
+          /* the direction towards the coarse cell, in the fine leaf's frame,
+           * names the fine leaf's face */
+          int ff;
+          if (X2 != X) ff = X2 > X ? 1 : 0;
+          else ff = Y2 > Y ? 3 : 2;
+          int32_t ft = (ff < 2) ? fj : fi;
+          const double *phif = &phi[((L * 4 + ff) * m + (ft - 1)) * meqn];
+          for (int k = 0; k < meqn; ++k) {
+            qc[k] = q[(p * meqn + k) * FR + fco_fidx(m, ic, jc)];
+            qf[k] = q[(L * meqn + k) * FR + fco_fidx(m, fi, fj)];
+          }
+          for (int k = 0; k < meqn; ++k) {
+            ql[k] = hi ? qc[k] : qf[k];
+            qr[k] = hi ? qf[k] : qc[k];
+          }
+          edge_geom eg = {1.0, {0}, {0}};
+          double flen = 0.5 * dx;
+          if (mesh->sphere) {
+            /* the fine edge, seen from the fine leaf */
+            int32_t ei = fi, ej = fj, ed = ff / 2;
+            if (ff == 1) ei = fi + 1;
+            if (ff == 3) ej = fj + 1;
+            fco_sphere_edge(mesh, L, ed, ei, ej, &eg.gamma, eg.n, eg.t);
+            /* orient the normal from the left state to the right state */
+            double sgn = 1.0;
+            if ((ff % 2 == 1) != (hi == 0)) sgn = -1.0;
+            for (int c = 0; c < 3; ++c) eg.n[c] *= sgn;
+            for (int c = 0; c < 3; ++c) eg.t[c] *= sgn;
+          }
+          if (riemann(par, d, &eg, ql, qr, W, S, am, ap) < 0) return -4;
+          for (int k = 0; k < meqn; ++k)
+            corr[k] += flen * (am[k] + ap[k]) - phif[k];
+        }
+        if (!fine) continue;
+        const double *phic = &phi[((p * 4 + f) * m + (t - 1)) * meqn];
+        double kc = mesh->sphere ? fco_sphere_kappa(mesh, p, ic, jc) : 1.0;
+        for (int k = 0; k < meqn; ++k)
+          qn[(p * meqn + k) * FR + fco_fidx(m, ic, jc)] -=
+              dt / (kc * dx * dx) * (corr[k] - phic[k]);
+      }
+    }
+  }
+  return 0;
+}
+
+void fco_sphere_project(const fco_mesh *mesh, const fco_params *par,
+                        double *qn);
+
+int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
+             double *qn, double dt, int32_t do_reflux, double *numax) {
+  if (!mesh || !par || !q || !qn || par->m != mesh->m || par->meqn < 1 ||
+      par->meqn > FCO_MAXEQ)
+    return -1;
+  if ((par->physics == FCO_SPHERE) != (mesh->sphere != 0)) return -1;
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const int64_t NE = (int64_t)(m + 3) * (m + 2), FR = fco_frame(m);
+  work wk;
+  wk.m = m;
+  wk.meqn = meqn;
+  for (int d = 0; d < 2; ++d) {
+    wk.F[d] = (double *)malloc(sizeof(double) * NE * meqn);
+    wk.AM[d] = (double *)malloc(sizeof(double) * NE * meqn);
+    wk.AP[d] = (double *)malloc(sizeof(double) * NE * meqn);
+  }
+  wk.W = (double *)malloc(sizeof(double) * (m + 3) * MW * meqn);
+  wk.S = (double *)malloc(sizeof(double) * (m + 3) * MW);
+  wk.kap = (double *)malloc(sizeof(double) * FR);
+  wk.eg = (edge_geom *)malloc(sizeof(edge_geom) * (m + 3));
+  wk.tg = NULL;
+  double *phi = do_reflux
+                    ? (double *)malloc(sizeof(double) * mesh->n * 4 * m * meqn)
+                    : NULL;
+  double nmax = 0.0;
+  int rc = 0;
+  for (int64_t p = 0; p < mesh->n && rc == 0; ++p) {
+    double nu = 0.0;
+    rc = step_patch(mesh, par, p, &q[p * meqn * FR], &qn[p * meqn * FR], dt,
+                    &wk, phi ? &phi[p * 4 * m * meqn] : NULL, &nu);
+    nmax = fmax(nmax, nu);
+  }
+  if (rc == 0 && do_reflux) rc = reflux(mesh, par, q, qn, dt, phi);
+  if (rc == 0 && mesh->sphere) fco_sphere_project(mesh, par, qn);
+  for (int d = 0; d < 2; ++d) {
+    free(wk.F[d]);
+    free(wk.AM[d]);
+    free(wk.AP[d]);
+  }
+  free(wk.W);
+  free(wk.S);
+  free(wk.kap);
+  free(wk.eg);
+  free(phi);
+  if (numax) *numax = nmax;
+  return rc;
+}
+
+/* ---------------- conservation sums ---------------------------------- */
+/* M_k = sum over interior cells of kappa Q_k dxi deta, with Neumaier's
+ * compensated summation. */
+int fco_sums(const fco_mesh *mesh, const fco_params *par, const double *q,
+             double *sums) {
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const int64_t FR = fco_frame(m);
+  for (int k = 0; k < meqn; ++k) {
+    double s = 0.0, c = 0.0;
+    for (int64_t p = 0; p < mesh->n; ++p) {
+      const double dx = ldexp(1.0, -mesh->leaves[p].level) / m;
+      for (int32_t j = 1; j <= m; ++j)
+        for (int32_t i = 1; i <= m; ++i) {
+          double kap = mesh->sphere ? fco_sphere_kappa(mesh, p, i, j) : 1.0;
+          double v = kap * q[(p * meqn + k) * FR + fco_fidx(m, i, j)] * dx * dx;
+          double t = s + v;
+          if (fabs(s) >= fabs(v)) c += (s - t) + v;
+          else c += (v - t) + s;
+          s = t;
+        }
+    }
+    sums[k] = s + c;
+  }
+  return 0;
+}

@@ -1,0 +1,230 @@
+"""ctypes front end of the CPU FP64 oracle.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py, never by the product path.  The C sources next
+to this file state what is computed and where the paper says so.
+
+State arrays handed to the oracle are "framed": (P, meqn, m+4, m+4) indexed
+[p, k, j+1, i+1] for cells i, j in -1..m+2; the interior is
+[..., 2:m+2, 2:m+2].
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "liboracle.so")
+
+LEAF_DTYPE = np.dtype([("tree", "<i4"), ("level", "<i4"), ("ix", "<i4"),
+                       ("iy", "<i4")])
+TREE_DTYPE = np.dtype([("nbr_tree", "<i4", (4,)), ("nbr_face", "<i4", (4,)),
+                       ("orient", "<i4", (4,)), ("bc", "<i4", (4,))])
+
+ADVECTION, SHALLOW, SPHERE = 0, 1, 2
+S = 30
+SIDE = 1 << S
+
+
+class Params(C.Structure):
+    _fields_ = [("m", C.c_int32), ("meqn", C.c_int32), ("physics", C.c_int32),
+                ("limiter", C.c_int32), ("transverse", C.c_int32),
+                ("pad", C.c_int32), ("g", C.c_double), ("ax", C.c_double),
+                ("ay", C.c_double)]
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with make (gcc)."""
+    if force or not os.path.exists(LIB_PATH):
+        subprocess.run(["make", "-B" if force else "-s", "-C", HERE],
+                       check=True, capture_output=True)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.fco_sfc_sort.argtypes = [i64, vp]
+        L.fco_mesh_new.argtypes = [i32, vp, i64, vp, i32, i32]
+        L.fco_mesh_new.restype = vp
+        L.fco_mesh_free.argtypes = [vp]
+        L.fco_is_balanced.argtypes = [vp]
+        L.fco_balance.argtypes = [i32, vp, i64, vp, i64, vp, vp]
+        L.fco_locate_leaf.argtypes = [vp, i32, i64, i64, vp]
+        L.fco_ghost_fill.argtypes = [vp, vp, vp, vp]
+        L.fco_step.argtypes = [vp, vp, vp, vp, dp, i32, vp]
+        L.fco_sums.argtypes = [vp, vp, vp, vp]
+        L.fco_tags.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp]
+        L.fco_regrid.argtypes = [vp, vp, i32, i32, i64, vp, vp]
+        L.fco_transfer.argtypes = [vp, vp, vp, vp, vp]
+        L.fco_phi.argtypes = [i32, dp]
+        L.fco_phi.restype = dp
+        L.fco_riemann.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def params(m, physics=ADVECTION, limiter=4, transverse=2, g=1.0, ax=0.0,
+           ay=0.0):
+    meqn = {ADVECTION: 1, SHALLOW: 3, SPHERE: 4}[physics]
+    return Params(m, meqn, physics, limiter, transverse, 0, g, ax, ay)
+
+
+def sfc_sort(leaves: np.ndarray) -> np.ndarray:
+    a = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE).copy()
+    lib().fco_sfc_sort(len(a), _ptr(a))
+    return a
+
+
+def balance(trees, leaves) -> np.ndarray:
+    trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
+    leaves = sfc_sort(leaves)
+    cap = max(16, 64 * len(leaves))
+    out = np.zeros(cap, dtype=LEAF_DTYPE)
+    n = C.c_int64()
+    rc = lib().fco_balance(len(trees), _ptr(trees), len(leaves), _ptr(leaves),
+                           cap, _ptr(out), C.byref(n))
+    if rc != 0:
+        raise RuntimeError(f"fco_balance failed ({rc})")
+    return out[: n.value].copy()
+
+
+class Mesh:
+    def __init__(self, trees, leaves, m, sphere=False):
+        self.trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
+        self.leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+        self.m = m
+        self.sphere = sphere
+        self.h = lib().fco_mesh_new(len(self.trees), _ptr(self.trees),
+                                    len(self.leaves), _ptr(self.leaves), m,
+                                    int(sphere))
+        if not self.h:
+            raise ValueError("invalid forest (unsorted, overlapping or bad "
+                             "connectivity)")
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().fco_mesh_free(self.h)
+            self.h = None
+
+    def __len__(self):
+        return len(self.leaves)
+
+    def balanced(self) -> bool:
+        return bool(lib().fco_is_balanced(self.h))
+
+    def locate(self, tree, x, y) -> int:
+        out = C.c_int64()
+        lib().fco_locate_leaf(self.h, tree, x, y, C.byref(out))
+        return out.value
+
+
+def framed(q: np.ndarray, m: int) -> np.ndarray:
+    """(P, meqn, m, m) interior -> (P, meqn, m+4, m+4) with NaN ghosts."""
+    P, meqn = q.shape[:2]
+    f = np.full((P, meqn, m + 4, m + 4), np.nan)
+    f[:, :, 2:m + 2, 2:m + 2] = q
+    return f
+
+
+def interior(f: np.ndarray, m: int) -> np.ndarray:
+    return np.ascontiguousarray(f[:, :, 2:m + 2, 2:m + 2])
+
+
+def ghost_fill(mesh: Mesh, par: Params, qf: np.ndarray) -> int:
+    """Fill the ghost frame of qf in place; returns the interpolation
+    nesting depth seen."""
+    assert qf.dtype == np.float64 and qf.flags.c_contiguous
+    depth = C.c_int32()
+    rc = lib().fco_ghost_fill(mesh.h, C.byref(par), _ptr(qf), C.byref(depth))
+    if rc != 0:
+        raise RuntimeError(f"fco_ghost_fill failed ({rc})")
+    return depth.value
+
+
+def step(mesh: Mesh, par: Params, qf: np.ndarray, dt: float, reflux=True):
+    """One step from a ghost-filled frame; returns (new frame, nu_max)."""
+    qn = np.array(qf, copy=True)
+    numax = C.c_double()
+    rc = lib().fco_step(mesh.h, C.byref(par), _ptr(qf), _ptr(qn), dt,
+                        int(reflux), C.byref(numax))
+    if rc != 0:
+        raise RuntimeError(f"fco_step failed ({rc})")
+    return qn, numax.value
+
+
+def sums(mesh: Mesh, par: Params, qf: np.ndarray) -> np.ndarray:
+    out = np.zeros(par.meqn)
+    lib().fco_sums(mesh.h, C.byref(par), _ptr(qf), _ptr(out))
+    return out
+
+
+def tags(mesh, par, qf, criterion, threshold, lmin, lmax) -> np.ndarray:
+    out = np.zeros(len(mesh), dtype=np.int8)
+    rc = lib().fco_tags(mesh.h, C.byref(par), _ptr(qf), criterion, threshold,
+                        lmin, lmax, _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"fco_tags failed ({rc})")
+    return out
+
+
+def regrid(mesh, tg, lmin, lmax) -> np.ndarray:
+    tg = np.ascontiguousarray(tg, dtype=np.int8)
+    cap = 64 * len(mesh) + 64
+    out = np.zeros(cap, dtype=LEAF_DTYPE)
+    n = C.c_int64()
+    rc = lib().fco_regrid(mesh.h, _ptr(tg), lmin, lmax, cap, _ptr(out),
+                          C.byref(n))
+    if rc != 0:
+        raise RuntimeError(f"fco_regrid failed ({rc})")
+    return out[: n.value].copy()
+
+
+def transfer(old: Mesh, new: Mesh, par, qf_old) -> np.ndarray:
+    qn = np.full((len(new), par.meqn, new.m + 4, new.m + 4), np.nan)
+    rc = lib().fco_transfer(old.h, new.h, C.byref(par), _ptr(qf_old), _ptr(qn))
+    if rc != 0:
+        raise RuntimeError(f"fco_transfer failed ({rc})")
+    return qn
+
+
+def phi(limiter: int, theta: float) -> float:
+    return lib().fco_phi(limiter, theta)
+
+
+def riemann(par, direction, ql, qr):
+    ql = np.ascontiguousarray(ql, dtype=np.float64)
+    qr = np.ascontiguousarray(qr, dtype=np.float64)
+    W = np.zeros((3, par.meqn))
+    s = np.zeros(3)
+    am = np.zeros(par.meqn)
+    ap = np.zeros(par.meqn)
+    nw = lib().fco_riemann(C.byref(par), direction, _ptr(ql), _ptr(qr), _ptr(W),
+                           _ptr(s), _ptr(am), _ptr(ap))
+    if nw < 0:
+        raise RuntimeError("riemann failed")
+    return W[:nw], s[:nw], am, ap
+
+
+# -------------------------------------------------------------------------
+# a plain driver: ghost fill + step, fixed or CFL-controlled dt, regrid
+# -------------------------------------------------------------------------
+def advance(mesh, par, q, dt, reflux=True):
+    """q: interior (P, meqn, m, m) -> (new interior, nu_max)."""
+    f = framed(q, mesh.m)
+    ghost_fill(mesh, par, f)
+    fn, nu = step(mesh, par, f, dt, reflux)
+    return interior(fn, mesh.m), nu
