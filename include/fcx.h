@@ -1,0 +1,196 @@
+/*
+ * fcx.h -- C ABI of the MI355X leaf-patch AMR library (libfcx.so).
+ *
+ * One time step of the forest-of-quadtrees leaf-patch method of
+ * Burstedde, Calhoun, Mandli and Terrel (ForestClaw, arXiv 1308.1472):
+ * every leaf of a 2:1-balanced forest houses one m x m finite-volume patch
+ * with two ghost layers (Sec. 2, Sec. 3); a step fills the ghost cells from
+ * neighbouring patches (copy, average, limited interpolation; Sec. 3) and
+ * advances every patch by the wave-propagation algorithm the paper adopts
+ * from Clawpack (Sec. 3).
+ *
+ * Conventions
+ *   - A tree is the reference square [0,1]^2 (Sec. 2).  A leaf
+ *     (tree, level, ix, iy) covers [ix, ix+1] 2^-level x [iy, iy+1] 2^-level.
+ *   - Patch ids are positions in the uploaded leaf array, which must be in
+ *     space-filling-curve order: tree-major, then Morton order of the
+ *     lower-left corner (x in the even bits).  fcx_sfc_sort produces it.
+ *   - State "q" (device memory, owned by the caller) is compact:
+ *     q[((p*meqn + k)*m + (j-1))*m + (i-1)] for patch p, component k,
+ *     cell (i, j), i, j = 1..m.  Element type float (precision 32) or
+ *     double (precision 64).
+ *   - Ghost buffer "ghost" (device, caller-owned) holds the two-layer frame
+ *     of every patch: ghost[(p*meqn + k)*G + g], G = 8m + 16, with g
+ *     = (j+1)(m+4) + (i+1) for rows j = -1, 0; 2(m+4) + (j-m-1)(m+4) + (i+1)
+ *     for rows j = m+1, m+2 (i = -1..m+2); 4(m+4) + 4(j-1) + s for rows
+ *     j = 1..m with s = 0, 1, 2, 3 for i = -1, 0, m+1, m+2.  The four
+ *     outermost corner cells are never read or written.
+ *   - dt, nu_max and sums are device doubles.
+ *   - "stream" is a hipStream_t passed as void* (NULL = default stream).
+ *     Every call that takes a stream only enqueues work on it.
+ *
+ * Errors: every entry point returns FCX_OK (0) or a negative code; none
+ * throws or aborts.  fcx_last_error() returns a message for the calling
+ * thread, owned by the library and valid until the next call.
+ */
+#ifndef FCX_H
+#define FCX_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FCX_OK 0
+#define FCX_EINVAL (-1)    /* bad argument, size or unsorted leaves        */
+#define FCX_EBALANCE (-2)  /* forest not 2:1 balanced over faces, corners  */
+#define FCX_ENOMEM (-3)    /* device or host allocation failed             */
+#define FCX_EHIP (-4)      /* HIP runtime error (text in fcx_last_error)   */
+#define FCX_ECFL (-5)      /* reported through fcx_next_dt's status word   */
+#define FCX_ENEG (-6)      /* non-positive depth met by a Riemann solve    */
+#define FCX_ESTATE (-7)    /* call out of order (e.g. no forest uploaded)  */
+
+enum { FCX_ADVECTION = 0, FCX_SHALLOW = 1 };
+
+typedef struct fcx_ctx fcx_ctx;
+typedef struct fcx_batch fcx_batch;
+
+typedef struct {
+  int32_t tree, level, ix, iy;
+} fcx_leaf;
+
+/* Tree connectivity (Sec. 2: blocks glued by a connectivity; Sec. 4:
+ * neighbour access across blocks applies a coordinate transformation).
+ * Face ids 0 = xi-low, 1 = xi-high, 2 = eta-low, 3 = eta-high.  bc[f] = 0:
+ * face f is glued to face nbr_face[f] of tree nbr_tree[f]; orient[f] = 0
+ * if the tangential coordinates run the same way, 1 if reversed.
+ * bc[f] = 1: reflecting wall; bc[f] = 2: zero-order extrapolation. */
+typedef struct {
+  int32_t nbr_tree[4], nbr_face[4], orient[4], bc[4];
+} fcx_tree;
+
+typedef struct {
+  int32_t m;           /* cells per patch side: 8, 16 or 32               */
+  int32_t precision;   /* 32 or 64: element type of q and ghost           */
+  int32_t physics;     /* FCX_ADVECTION (meqn 1) or FCX_SHALLOW (meqn 3)  */
+  int32_t limiter;     /* wave limiter: 0 none, 1 minmod, 2 superbee,
+                          3 van Leer, 4 MC (LeVeque 2002, Sec. 6.12)      */
+  int32_t transverse;  /* 0 none, 1 fluctuations, 2 fluctuations and
+                          second-order corrections                         */
+  int32_t tile;        /* cells per LDS tile side (0 = library default)  */
+  double g;            /* gravity (shallow water)                         */
+  double ax, ay;       /* advection velocity in reference coordinates     */
+  double cfl_desired;  /* target Courant number for the next dt           */
+  double cfl_max;      /* larger Courant numbers flag the step            */
+} fcx_config;
+
+const char *fcx_last_error(void);
+int32_t fcx_version(void);
+
+/* ---- host-only forest utilities (integer work; no device needed) ---- */
+
+/* Sort leaves in place into space-filling-curve order. */
+int fcx_sfc_sort(int64_t n, fcx_leaf *leaves);
+
+/* Coarsest forest that refines `in` (a tiling of every tree, any order)
+ * and is 2:1 balanced across faces and corners, through the connectivity
+ * (Sec. 2: the 2:1 balance condition).  Writes at most `cap` leaves in SFC
+ * order to `out` and their number to *n_out (FCX_EINVAL if cap is short,
+ * with *n_out set to the size needed). */
+int fcx_balance(int32_t n_trees, const fcx_tree *trees, int64_t n,
+                const fcx_leaf *in, int64_t cap, fcx_leaf *out,
+                int64_t *n_out);
+
+/* ---- context -------------------------------------------------------- */
+
+/* Creates a context for one forest on the current HIP device.  The
+ * connectivity is copied. */
+int fcx_create(const fcx_config *cfg, int32_t n_trees, const fcx_tree *trees,
+               fcx_ctx **out);
+int fcx_destroy(fcx_ctx *ctx);
+
+/* Uploads a forest (Sec. 2: the leaf <-> patch correspondence).  Leaves
+ * must be SFC-sorted and tile every tree; FCX_EBALANCE if not 2:1 balanced
+ * (faces and corners), FCX_EINVAL otherwise.  Builds the neighbour records
+ * (Sec. 2: constant-time neighbour lookup with relative orientation) and
+ * copies them to the device.  Synchronous. */
+int fcx_upload_forest(fcx_ctx *ctx, int64_t n, const fcx_leaf *leaves);
+
+int64_t fcx_num_patches(const fcx_ctx *ctx);
+int64_t fcx_state_elems(const fcx_ctx *ctx);   /* P * meqn * m * m        */
+int64_t fcx_ghost_elems(const fcx_ctx *ctx);   /* P * meqn * (8m + 16)    */
+int fcx_get_leaves(const fcx_ctx *ctx, int64_t cap, fcx_leaf *out);
+
+/* ---- the time step -------------------------------------------------- */
+
+/* Ghost fill (Sec. 3): each ghost cell takes its value from the leaf that
+ * contains its centre: copy from a same-level leaf, mean of the 2x2 cells of
+ * a finer leaf, or limited (minmod) conservative linear interpolation from a
+ * coarser leaf; reflecting / extrapolation walls; at a corner where no leaf
+ * exists (three trees meeting) the mean of the two mirrored face ghosts.
+ * Reads q, writes ghost. */
+int fcx_ghost_fill(fcx_ctx *ctx, const void *q, void *ghost, void *stream);
+
+/* Wave-propagation update of every patch (Sec. 3; LeVeque 1997): Riemann
+ * problems at all edges, limited second-order corrections, transverse
+ * propagation, for the given dt.  Reads q and ghost, writes q_new (must not
+ * alias q).  Raises *nu_max (device double, atomically) to the largest
+ * Courant number seen at interior edges; records the face terms used by
+ * fcx_reflux in the context. */
+int fcx_patch_step(fcx_ctx *ctx, const void *q, const void *ghost, void *q_new,
+                   const double *dt, double *nu_max, void *stream);
+
+/* Same result as fcx_ghost_fill followed by fcx_patch_step, in one launch:
+ * ghost values are evaluated from q directly into LDS; no ghost buffer. */
+int fcx_fused_step(fcx_ctx *ctx, const void *q, void *q_new, const double *dt,
+                   double *nu_max, void *stream);
+
+/* Coarse-fine correction with one global dt (Sec. 4: correction factors
+ * propagated back from fine to coarse levels): each coarse cell at a
+ * coarse-fine face gets the sum of the two fine face terms instead of its
+ * own.  Needs the face terms of the preceding patch step on the same q. */
+int fcx_reflux(fcx_ctx *ctx, const void *q, void *q_new, const double *dt,
+               void *stream);
+
+/* dt <- dt * cfl_desired / nu_max (unchanged if nu_max == 0); nu_max <- 0;
+ * status (device int32): bit 0 set if nu_max > cfl_max (FCX_ECFL), bit 1 if
+ * a non-positive depth was met since the last call (FCX_ENEG).  Bits are
+ * sticky until the caller clears them. */
+int fcx_next_dt(fcx_ctx *ctx, double *nu_max, double *dt, int32_t *status,
+                void *stream);
+
+/* sums[k] = sum over interior cells of q_k * cell area, in FP64, reduced in
+ * a fixed order (deterministic). */
+int fcx_conservation_sums(fcx_ctx *ctx, const void *q, double *sums,
+                          void *stream);
+
+/* ---- regrid (Sec. 2: per-patch flags are the only mesher input) ----- */
+
+/* tags (device int8, one per patch): +1 if the criterion exceeds the
+ * threshold and level < lmax; -1 on the four members of a family of leaf
+ * siblings above lmin, none tagged +1, whose averaged parent stays below
+ * the threshold; 0 otherwise.  criterion 0: max - min of component 0 over
+ * the interior (Sec. 5); 1: max |grad q_0| by central differences over the
+ * ghost-extended data (needs a ghost fill of the same q). */
+int fcx_regrid_tags(fcx_ctx *ctx, const void *q, const void *ghost,
+                    int32_t criterion, double threshold, int32_t lmin,
+                    int32_t lmax, int8_t *tags, void *stream);
+
+/* Applies host tags: refine +1, merge families tagged -1, restore balance by
+ * refinement.  The context switches to the new forest; the old one is kept
+ * for fcx_regrid_transfer.  *n_new receives the new patch count. */
+int fcx_regrid_apply(fcx_ctx *ctx, const int8_t *tags_host, int32_t lmin,
+                     int32_t lmax, int64_t *n_new);
+
+/* Data transfer after fcx_regrid_apply (Sec. 3: interpolate to new fine
+ * patches, average to new coarse patches): kept patches copy, refined ones
+ * interpolate with minmod slopes (the old ghost buffer must hold a fill of
+ * q_old), merged ones take the mean of the 2x2 children cells. */
+int fcx_regrid_transfer(fcx_ctx *ctx, const void *q_old, const void *ghost_old,
+                        void *q_new, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,472 @@
+// api.hip -- the C ABI of libfcx.so (declared in include/fcx.h): context,
+// forest upload, and the launches of the ghost-fill, patch-step, reflux,
+// dt, sum, tag and transfer kernels.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <algorithm>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "aux_kernels.hpp"
+#include "forest.hpp"
+#include "step.hpp"
+
+using namespace fcx;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                        \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return fail(FCX_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T* p = nullptr;
+  size_t n = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t count) {
+    if (count <= n && p) return hipSuccess;
+    release();
+    const size_t c = count ? count : 1;
+    hipError_t e = hipMalloc(&p, c * sizeof(T));
+    if (e == hipSuccess) n = c;
+    return e;
+  }
+  hipError_t upload(const std::vector<T>& v) {
+    hipError_t e = ensure(v.size());
+    if (e != hipSuccess || v.empty()) return e;
+    return hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+  }
+};
+
+int log2i(int m) {
+  int l = 0;
+  while ((1 << l) < m) ++l;
+  return l;
+}
+}  // namespace
+
+struct DevForest {
+  DevBuf<PatchRec> rec;
+  DevBuf<int32_t> phislot, family;
+  DevBuf<RefluxItem> reflux;
+  int32_t n_reflux_x = 0, n_reflux_y = 0;
+  int32_t nslots = 0;
+  int64_t P = 0;
+};
+
+struct fcx_ctx {
+  fcx_config cfg{};
+  int meqn = 1;
+  int tile = 16;
+  std::vector<fcx_tree> trees;
+  Forest forest, old_forest;
+  bool have_forest = false, have_old = false;
+  DevForest cur, old;
+  DevBuf<uint8_t> phi;             // face terms of the last patch step
+  DevBuf<double> partial;
+  DevBuf<int32_t> first;           // [0, P] for the sum reduction
+  DevBuf<int32_t> err;
+  DevBuf<int32_t> xkind, xsrc;     // transfer plan
+};
+
+// The entry points below are declared extern "C" in fcx.h.
+
+const char* fcx_last_error(void) { return g_err.c_str(); }
+int32_t fcx_version(void) { return 1; }
+
+int fcx_sfc_sort(int64_t n, fcx_leaf* leaves) {
+  if (n < 0 || (n > 0 && !leaves)) return fail(FCX_EINVAL, "bad arguments");
+  std::sort(leaves, leaves + n, leaf_less);
+  return FCX_OK;
+}
+
+int fcx_balance(int32_t n_trees, const fcx_tree* trees, int64_t n,
+                const fcx_leaf* in, int64_t cap, fcx_leaf* out,
+                int64_t* n_out) {
+  if (n_trees <= 0 || !trees || n < 0 || (n > 0 && !in) || !n_out)
+    return fail(FCX_EINVAL, "bad arguments");
+  std::vector<fcx_tree> t(trees, trees + n_trees);
+  std::vector<fcx_leaf> res;
+  std::string err;
+  const int rc = balance(t, std::vector<fcx_leaf>(in, in + n), res, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  *n_out = int64_t(res.size());
+  if (int64_t(res.size()) > cap || (!out && !res.empty()))
+    return fail(FCX_EINVAL, "output capacity too small");
+  std::copy(res.begin(), res.end(), out);
+  return FCX_OK;
+}
+
+int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
+               fcx_ctx** out) {
+  if (!cfg || !out || n_trees <= 0 || !trees) return fail(FCX_EINVAL, "bad arguments");
+  *out = nullptr;
+  if (cfg->m != 8 && cfg->m != 16 && cfg->m != 32)
+    return fail(FCX_EINVAL, "m must be 8, 16 or 32");
+  if (cfg->precision != 32 && cfg->precision != 64)
+    return fail(FCX_EINVAL, "precision must be 32 or 64");
+  if (cfg->physics != FCX_ADVECTION && cfg->physics != FCX_SHALLOW)
+    return fail(FCX_EINVAL, "unknown physics");
+  if (cfg->limiter < 0 || cfg->limiter > 4 || cfg->transverse < 0 ||
+      cfg->transverse > 2)
+    return fail(FCX_EINVAL, "bad limiter or transverse mode");
+  int tile = cfg->tile ? cfg->tile : (cfg->m >= 16 ? 16 : 8);
+  if ((tile != 8 && tile != 16) || tile > cfg->m)
+    return fail(FCX_EINVAL, "tile must be 8 or 16 and at most m");
+  std::vector<fcx_tree> t(trees, trees + n_trees);
+  std::string err;
+  if (check_connectivity(t, err) != FCX_OK) return fail(FCX_EINVAL, err);
+  if (cfg->physics == FCX_SHALLOW) {
+    // planar momentum is not rotated across trees: only translations
+    for (const auto& T : t)
+      for (int f = 0; f < 4; ++f)
+        if (T.bc[f] == 0 && (T.nbr_face[f] != (f ^ 1) || T.orient[f] != 0))
+          return fail(FCX_EINVAL, "shallow water needs axis-aligned tree gluing");
+  }
+  fcx_ctx* c = new fcx_ctx;
+  c->cfg = *cfg;
+  c->cfg.tile = tile;
+  c->tile = tile;
+  c->meqn = cfg->physics == FCX_ADVECTION ? 1 : 3;
+  c->trees = t;
+  if (c->err.ensure(1) != hipSuccess) {
+    delete c;
+    return fail(FCX_ENOMEM, "hipMalloc failed");
+  }
+  if (hipMemset(c->err.p, 0, sizeof(int32_t)) != hipSuccess) {
+    delete c;
+    return fail(FCX_EHIP, "hipMemset failed");
+  }
+  *out = c;
+  return FCX_OK;
+}
+
+int fcx_destroy(fcx_ctx* ctx) {
+  delete ctx;
+  return FCX_OK;
+}
+
+static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev) {
+  Plan plan;
+  std::string err;
+  int rc = build_plan(f, c->cfg.m, plan, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  // reflux items: xi faces first, then eta faces
+  std::vector<RefluxItem> items;
+  for (const auto& it : plan.reflux) if (it.face < 2) items.push_back(it);
+  dev.n_reflux_x = int32_t(items.size());
+  for (const auto& it : plan.reflux) if (it.face >= 2) items.push_back(it);
+  dev.n_reflux_y = int32_t(items.size()) - dev.n_reflux_x;
+  HIPCHK(dev.rec.upload(plan.recs));
+  HIPCHK(dev.phislot.upload(plan.phislot));
+  HIPCHK(dev.family.upload(plan.family));
+  HIPCHK(dev.reflux.upload(items));
+  dev.nslots = plan.nslots;
+  dev.P = int64_t(f.leaves.size());
+  return FCX_OK;
+}
+
+static int finish_upload(fcx_ctx* c) {
+  const int64_t P = c->cur.P;
+  const size_t esz = c->cfg.precision == 64 ? 8 : 4;
+  HIPCHK(c->phi.ensure(size_t(c->cur.nslots) * 4 * c->cfg.m * c->meqn * esz));
+  HIPCHK(c->partial.ensure(size_t(P) * c->meqn));
+  std::vector<int32_t> first = {0, int32_t(P)};
+  HIPCHK(c->first.upload(first));
+  return FCX_OK;
+}
+
+int fcx_upload_forest(fcx_ctx* c, int64_t n, const fcx_leaf* leaves) {
+  if (!c || n <= 0 || !leaves) return fail(FCX_EINVAL, "bad arguments");
+  if (n > (int64_t(1) << 28)) return fail(FCX_EINVAL, "too many leaves");
+  std::vector<fcx_leaf> l(leaves, leaves + n);
+  std::string err;
+  Forest f;
+  int rc = f.assign(c->trees, l, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  std::vector<fcx_leaf> bal;
+  rc = balance(c->trees, l, bal, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  if (bal.size() != l.size()) return fail(FCX_EBALANCE, "forest is not 2:1 balanced");
+  c->forest = std::move(f);
+  c->have_forest = true;
+  c->have_old = false;
+  rc = upload_plan(c, c->forest, c->cur);
+  if (rc != FCX_OK) { c->have_forest = false; return rc; }
+  return finish_upload(c);
+}
+
+int64_t fcx_num_patches(const fcx_ctx* c) {
+  return c && c->have_forest ? int64_t(c->forest.leaves.size()) : -1;
+}
+int64_t fcx_state_elems(const fcx_ctx* c) {
+  if (!c || !c->have_forest) return -1;
+  return int64_t(c->forest.leaves.size()) * c->meqn * c->cfg.m * c->cfg.m;
+}
+int64_t fcx_ghost_elems(const fcx_ctx* c) {
+  if (!c || !c->have_forest) return -1;
+  return int64_t(c->forest.leaves.size()) * c->meqn * (8 * c->cfg.m + 16);
+}
+int fcx_get_leaves(const fcx_ctx* c, int64_t cap, fcx_leaf* out) {
+  if (!c || !c->have_forest) return fail(FCX_ESTATE, "no forest");
+  if (cap < int64_t(c->forest.leaves.size()) || !out)
+    return fail(FCX_EINVAL, "capacity too small");
+  std::copy(c->forest.leaves.begin(), c->forest.leaves.end(), out);
+  return FCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+static KPhys kphys(const fcx_ctx* c) {
+  return KPhys{c->cfg.g, c->cfg.ax, c->cfg.ay, c->cfg.limiter, c->cfg.transverse};
+}
+
+template <typename R, int PHYS>
+static int launch_ghost(fcx_ctx* c, const void* q, void* ghost, hipStream_t s) {
+  const int m = c->cfg.m;
+  const int64_t tot = c->cur.P * (8 * m + 16);
+  const unsigned blocks = unsigned((tot + 255) / 256);
+  hipLaunchKernelGGL((k_ghost_fill<R, PHYS>), dim3(blocks), dim3(256), 0, s,
+                     static_cast<const R*>(q), static_cast<R*>(ghost),
+                     c->cur.rec.p, int32_t(c->cur.P), m, log2i(m), c->err.p);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_ghost_fill(fcx_ctx* c, const void* q, void* ghost, void* stream) {
+  if (!c || !q || !ghost) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_ADVECTION)
+    return dp ? launch_ghost<double, FCX_ADVECTION>(c, q, ghost, s)
+              : launch_ghost<float, FCX_ADVECTION>(c, q, ghost, s);
+  return dp ? launch_ghost<double, FCX_SHALLOW>(c, q, ghost, s)
+            : launch_ghost<float, FCX_SHALLOW>(c, q, ghost, s);
+}
+
+template <typename R, int PHYS, int M, int T, bool FUSED>
+static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
+                         const double* dt, double* numax, hipStream_t s) {
+  StepArgs<R> a;
+  a.q = static_cast<const R*>(q);
+  a.ghost = static_cast<const R*>(ghost);
+  a.qn = static_cast<R*>(qn);
+  a.dt = dt;
+  a.numax = numax;
+  a.rec = c->cur.rec.p;
+  a.phislot = c->cur.phislot.p;
+  a.phi = reinterpret_cast<R*>(c->phi.p);
+  a.err = c->err.p;
+  a.P = int32_t(c->cur.P);
+  a.ph = kphys(c);
+  constexpr int TPS = M / T;
+  const unsigned blocks = unsigned(c->cur.P * TPS * TPS);
+  hipLaunchKernelGGL((k_step<R, PHYS, M, T, FUSED>), dim3(blocks),
+                     dim3(TileThreads<T>::value), 0, s, a);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+template <typename R, int PHYS, bool FUSED>
+static int launch_step_m(fcx_ctx* c, const void* q, const void* ghost, void* qn,
+                         const double* dt, double* numax, hipStream_t s) {
+  const int m = c->cfg.m, t = c->tile;
+  if (m == 8) return launch_step_t<R, PHYS, 8, 8, FUSED>(c, q, ghost, qn, dt, numax, s);
+  if (m == 16 && t == 8) return launch_step_t<R, PHYS, 16, 8, FUSED>(c, q, ghost, qn, dt, numax, s);
+  if (m == 16) return launch_step_t<R, PHYS, 16, 16, FUSED>(c, q, ghost, qn, dt, numax, s);
+  if (t == 8) return launch_step_t<R, PHYS, 32, 8, FUSED>(c, q, ghost, qn, dt, numax, s);
+  return launch_step_t<R, PHYS, 32, 16, FUSED>(c, q, ghost, qn, dt, numax, s);
+}
+
+template <bool FUSED>
+static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
+                         const double* dt, double* numax, void* stream) {
+  if (!c || !q || !qn || !dt || !numax || (!FUSED && !ghost))
+    return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (q == qn) return fail(FCX_EINVAL, "q_new must not alias q");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_ADVECTION)
+    return dp ? launch_step_m<double, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s)
+              : launch_step_m<float, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s);
+  return dp ? launch_step_m<double, FCX_SHALLOW, FUSED>(c, q, ghost, qn, dt, numax, s)
+            : launch_step_m<float, FCX_SHALLOW, FUSED>(c, q, ghost, qn, dt, numax, s);
+}
+
+int fcx_patch_step(fcx_ctx* c, const void* q, const void* ghost, void* qn,
+                   const double* dt, double* numax, void* stream) {
+  return step_dispatch<false>(c, q, ghost, qn, dt, numax, stream);
+}
+
+int fcx_fused_step(fcx_ctx* c, const void* q, void* qn, const double* dt,
+                   double* numax, void* stream) {
+  return step_dispatch<true>(c, q, nullptr, qn, dt, numax, stream);
+}
+
+template <typename R, int PHYS>
+static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
+                         hipStream_t s) {
+  const int m = c->cfg.m;
+  for (int axis = 0; axis < 2; ++axis) {
+    const int32_t n = axis == 0 ? c->cur.n_reflux_x : c->cur.n_reflux_y;
+    if (n == 0) continue;
+    const RefluxItem* items = c->cur.reflux.p + (axis == 0 ? 0 : c->cur.n_reflux_x);
+    const int64_t tot = int64_t(n) * m;
+    hipLaunchKernelGGL((k_reflux<R, PHYS>), dim3(unsigned((tot + 255) / 256)),
+                       dim3(256), 0, s, static_cast<const R*>(q),
+                       static_cast<R*>(qn), items, n, c->cur.rec.p,
+                       c->cur.phislot.p, reinterpret_cast<const R*>(c->phi.p), dt,
+                       m, kphys(c), c->err.p);
+    HIPCHK(hipGetLastError());
+  }
+  return FCX_OK;
+}
+
+int fcx_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt, void* stream) {
+  if (!c || !q || !qn || !dt) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_ADVECTION)
+    return dp ? launch_reflux<double, FCX_ADVECTION>(c, q, qn, dt, s)
+              : launch_reflux<float, FCX_ADVECTION>(c, q, qn, dt, s);
+  return dp ? launch_reflux<double, FCX_SHALLOW>(c, q, qn, dt, s)
+            : launch_reflux<float, FCX_SHALLOW>(c, q, qn, dt, s);
+}
+
+int fcx_next_dt(fcx_ctx* c, double* numax, double* dt, int32_t* status, void* stream) {
+  if (!c || !numax || !dt || !status) return fail(FCX_EINVAL, "bad arguments");
+  hipLaunchKernelGGL(k_next_dt, dim3(1), dim3(64), 0,
+                     static_cast<hipStream_t>(stream), numax, dt, status, c->err.p,
+                     1, c->cfg.cfl_desired, c->cfg.cfl_max);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+template <typename R, int MEQN>
+static int launch_sums(fcx_ctx* c, const void* q, double* sums, hipStream_t s) {
+  hipLaunchKernelGGL((k_sums_patch<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
+                     0, s, static_cast<const R*>(q), c->cur.rec.p, c->cfg.m,
+                     c->partial.p);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((k_sums_reduce<MEQN>), dim3(1), dim3(1024), 0, s,
+                     c->partial.p, c->first.p, sums);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_conservation_sums(fcx_ctx* c, const void* q, double* sums, void* stream) {
+  if (!c || !q || !sums) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dp = c->cfg.precision == 64;
+  if (c->meqn == 1)
+    return dp ? launch_sums<double, 1>(c, q, sums, s) : launch_sums<float, 1>(c, q, sums, s);
+  return dp ? launch_sums<double, 3>(c, q, sums, s) : launch_sums<float, 3>(c, q, sums, s);
+}
+
+template <typename R, int MEQN>
+static int launch_tags(fcx_ctx* c, const void* q, const void* ghost, int criterion,
+                       double thr, int lmin, int lmax, int8_t* tags, hipStream_t s) {
+  const int m = c->cfg.m;
+  hipLaunchKernelGGL((k_tag_refine<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
+                     0, s, static_cast<const R*>(q), static_cast<const R*>(ghost),
+                     c->cur.rec.p, m, criterion, thr, lmax, tags);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((k_tag_family<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
+                     size_t(m) * m * sizeof(double), s, static_cast<const R*>(q),
+                     c->cur.rec.p, c->cur.family.p, m, criterion, thr, lmin, tags);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criterion,
+                    double thr, int32_t lmin, int32_t lmax, int8_t* tags,
+                    void* stream) {
+  if (!c || !q || !tags || (criterion != 0 && criterion != 1) ||
+      (criterion == 1 && !ghost))
+    return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dp = c->cfg.precision == 64;
+  if (c->meqn == 1)
+    return dp ? launch_tags<double, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
+              : launch_tags<float, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
+  return dp ? launch_tags<double, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
+            : launch_tags<float, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
+}
+
+int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
+                     int64_t* n_new) {
+  if (!c || !tags || !n_new || lmin < 0 || lmax < lmin || lmax > kMaxLevel)
+    return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  std::vector<fcx_leaf> out;
+  std::string err;
+  int rc = regrid(c->forest, tags, lmin, lmax, out, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  Forest nf;
+  rc = nf.assign(c->trees, out, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  std::vector<int32_t> kind, src;
+  rc = transfer_plan(c->forest, nf, kind, src, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  // the current device forest becomes the old one
+  std::swap(c->cur, c->old);
+  c->old_forest = std::move(c->forest);
+  c->forest = std::move(nf);
+  c->have_old = true;
+  rc = upload_plan(c, c->forest, c->cur);
+  if (rc != FCX_OK) return rc;
+  HIPCHK(c->xkind.upload(kind));
+  HIPCHK(c->xsrc.upload(src));
+  rc = finish_upload(c);
+  if (rc != FCX_OK) return rc;
+  *n_new = int64_t(c->forest.leaves.size());
+  return FCX_OK;
+}
+
+template <typename R, int MEQN>
+static int launch_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
+                           hipStream_t s) {
+  const int m = c->cfg.m;
+  const int64_t tot = c->cur.P * MEQN * m * m;
+  hipLaunchKernelGGL((k_transfer<R, MEQN>), dim3(unsigned((tot + 255) / 256)),
+                     dim3(256), 0, s, static_cast<const R*>(qo),
+                     static_cast<const R*>(go), static_cast<R*>(qn), c->cur.rec.p,
+                     c->xkind.p, c->xsrc.p, int32_t(c->cur.P), m);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_regrid_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
+                        void* stream) {
+  if (!c || !qo || !go || !qn) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_old) return fail(FCX_ESTATE, "no regrid applied");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dp = c->cfg.precision == 64;
+  if (c->meqn == 1)
+    return dp ? launch_transfer<double, 1>(c, qo, go, qn, s)
+              : launch_transfer<float, 1>(c, qo, go, qn, s);
+  return dp ? launch_transfer<double, 3>(c, qo, go, qn, s)
+            : launch_transfer<float, 3>(c, qo, go, qn, s);
+}
+

@@ -1,0 +1,360 @@
+// aux_kernels.hpp -- the kernels around the patch update: ghost fill,
+// coarse-fine reflux, next dt, conservation sums, refinement tags and
+// regrid transfer (arXiv 1308.1472, Sec. 2-4).
+#pragma once
+
+#include "device.hpp"
+
+namespace fcx {
+
+// ---------------------------------------------------------------------------
+// Ghost fill: one thread per (patch, frame cell); consecutive threads write
+// consecutive ghost-buffer entries of one patch.
+template <typename R, int PHYS>
+__global__ void __launch_bounds__(256)
+k_ghost_fill(const R* __restrict__ q, R* __restrict__ ghost,
+             const PatchRec* __restrict__ rec, int32_t P, int m, int lm,
+             int32_t* err) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  const int G = 8 * m + 16;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(P) * G) return;
+  const int p = int(t / G), g = int(t - int64_t(p) * G);
+  int i, j;
+  ghost_cell(m, g, i, j);
+  if ((i == -1 || i == m + 2) && (j == -1 || j == m + 2)) return;
+  GhostView<R, MEQN> gv{q, rec, m, lm, err};
+  R v[MEQN];
+  frame_value<R, MEQN, PHYS, true>(gv, p, i, j, v);
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) ghost[size_t(p * MEQN + k) * G + g] = v[k];
+}
+
+// ---------------------------------------------------------------------------
+// Sum of the fluctuations of one Riemann problem, which by Roe's property
+// equals f(q_r) - f(q_l) in direction d.
+template <typename R, int PHYS>
+__device__ void fluct_sum(const KPhys& ph, int d, const R* ql, const R* qr,
+                          R* out, int32_t* err) {
+  if (PHYS == FCX_ADVECTION) {
+    out[0] = R(d == 0 ? ph.ax : ph.ay) * (qr[0] - ql[0]);
+    return;
+  }
+  const int mu = 1 + d, mv = 2 - d;
+  const R hl = ql[0], hr = qr[0];
+  if (!(hl > R(0) && hr > R(0))) {
+    atomicOr(err, kErrNegDepth);
+    out[0] = out[1] = out[2] = R(0);
+    return;
+  }
+  const R sl = sqrt(hl), sr = sqrt(hr), inv = R(1) / (sl + sr);
+  const R u = (ql[mu] / sl + qr[mu] / sr) * inv;
+  const R v = (ql[mv] / sl + qr[mv] / sr) * inv;
+  const R c = sqrt(R(ph.g) * R(0.5) * (hl + hr));
+  const R d0 = hr - hl, d1 = qr[mu] - ql[mu], d2 = qr[mv] - ql[mv];
+  const R a1 = ((u + c) * d0 - d1) * (R(0.5) / c);
+  const R a2 = d2 - v * d0;
+  const R a3 = (d1 - (u - c) * d0) * (R(0.5) / c);
+  const R s1 = u - c, s3 = u + c;
+  out[0] = s1 * a1 + s3 * a3;
+  out[mu] = s1 * a1 * s1 + s3 * a3 * s3;
+  out[mv] = s1 * a1 * v + u * a2 + s3 * a3 * v;
+}
+
+// Reflux: one thread per (coarse-fine face item, coarse cell along it).
+template <typename R, int PHYS>
+__global__ void __launch_bounds__(256)
+k_reflux(const R* __restrict__ q, R* __restrict__ qn,
+         const RefluxItem* __restrict__ items, int32_t nitems,
+         const PatchRec* __restrict__ rec, const int32_t* __restrict__ phislot,
+         const R* __restrict__ phi, const double* dtp, int m, KPhys ph,
+         int32_t* err) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(nitems) * m) return;
+  const RefluxItem it = items[t / m];
+  const int tc = int(t % m) + 1;                 // coarse cell along the face
+  const int f = it.face, d = f >> 1, hi = f & 1;
+  const int C = it.coarse;
+  const int ic = d == 0 ? (hi ? m : 1) : tc, jc = d == 0 ? tc : (hi ? m : 1);
+  const int k2 = (tc - 1) / (m / 2);
+  const int fp = it.fine[k2], ff = it.fine_face[k2];
+  const double dxc = ldexp(1.0, -rec[C].level) / m;
+  R qc[MEQN];
+  read_interior<R, MEQN>(q, m, C, ic, jc, qc);
+  R corr[MEQN];
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) corr[k] = R(0);
+  const R* phf = phi + size_t(phislot[fp]) * 4 * m * MEQN;
+  for (int s = 0; s < 2; ++s) {
+    int pos = 2 * (tc - 1 - k2 * (m / 2)) + 1 + s;
+    if (it.fine_rev[k2]) pos = m + 1 - pos;
+    const int fi = ff < 2 ? (ff == 0 ? 1 : m) : pos;
+    const int fj = ff < 2 ? pos : (ff == 2 ? 1 : m);
+    R qf[MEQN], fs[MEQN];
+    read_interior<R, MEQN>(q, m, fp, fi, fj, qf);
+    if (hi) fluct_sum<R, PHYS>(ph, d, qc, qf, fs, err);
+    else fluct_sum<R, PHYS>(ph, d, qf, qc, fs, err);
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k)
+      corr[k] += R(0.5 * dxc) * fs[k] - phf[(ff * m + (pos - 1)) * MEQN + k];
+  }
+  const R* phc = phi + size_t(phislot[C]) * 4 * m * MEQN;
+  const R fac = R(*dtp / (dxc * dxc));
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) {
+    const size_t o = (size_t(C * MEQN + k) * m + (jc - 1)) * m + (ic - 1);
+    qn[o] -= fac * (corr[k] - phc[(f * m + (tc - 1)) * MEQN + k]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ void k_next_dt(double* numax, double* dt, int32_t* status,
+                          int32_t* err, int32_t nforest, double cfl_desired,
+                          double cfl_max) {
+  const int f = blockIdx.x * blockDim.x + threadIdx.x;
+  if (f >= nforest) return;
+  const double nu = numax[f];
+  int32_t st = 0;
+  if (nu > cfl_max) st |= 1;
+  if (f == 0) {
+    if (*err & kErrNegDepth) st |= 2;
+    if (*err & kErrNested) st |= 4;
+    *err = 0;
+  }
+  status[f] |= st;
+  if (nu > 0.0) dt[f] = dt[f] * cfl_desired / nu;
+  numax[f] = 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// Conservation sums: per-patch FP64 partials in a fixed thread order, then
+// a fixed pairwise reduction over patches.
+template <typename R, int MEQN>
+__global__ void __launch_bounds__(256)
+k_sums_patch(const R* __restrict__ q, const PatchRec* __restrict__ rec,
+             int m, double* __restrict__ partial) {
+  __shared__ double red[4][MEQN];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const double dx = ldexp(1.0, -rec[p].level) / m;
+  double acc[MEQN];
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) acc[k] = 0.0;
+  for (int c = tid; c < m * m; c += 256)
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) acc[k] += double(q[size_t(p * MEQN + k) * m * m + c]);
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) red[tid >> 6][k] = v;
+  }
+  __syncthreads();
+  if (tid < MEQN)
+    partial[size_t(p) * MEQN + tid] =
+        ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) * dx * dx;
+}
+
+template <int MEQN>
+__global__ void __launch_bounds__(1024)
+k_sums_reduce(const double* __restrict__ partial, const int32_t* __restrict__ first,
+              double* __restrict__ sums) {
+  __shared__ double red[16][MEQN];
+  const int f = blockIdx.x, tid = threadIdx.x;
+  const int p0 = first[f], p1 = first[f + 1];
+  double acc[MEQN];
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) acc[k] = 0.0;
+  for (int p = p0 + tid; p < p1; p += 1024)
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) acc[k] += partial[size_t(p) * MEQN + k];
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) red[tid >> 6][k] = v;
+  }
+  __syncthreads();
+  if (tid < MEQN) {
+    double v[16];
+    for (int w = 0; w < 16; ++w) v[w] = red[w][tid];
+    for (int s = 8; s > 0; s >>= 1)
+      for (int w = 0; w < s; ++w) v[w] = v[w] + v[w + s];
+    sums[size_t(f) * MEQN + tid] = v[0];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Refinement tags.  Decisions are taken on squared quantities with no fused
+// multiply-add so that they reproduce an independent FP64 evaluation.
+template <typename R, int MEQN>
+__device__ __forceinline__ double frame_q0(const R* q, const R* ghost, int m,
+                                           int p, int i, int j) {
+  if (i >= 1 && i <= m && j >= 1 && j <= m)
+    return double(q[size_t(p * MEQN) * m * m + size_t(j - 1) * m + (i - 1)]);
+  return double(ghost[size_t(p * MEQN) * (8 * m + 16) + ghost_index(m, i, j)]);
+}
+
+template <typename R, int MEQN>
+__global__ void __launch_bounds__(256)
+k_tag_refine(const R* __restrict__ q, const R* __restrict__ ghost,
+             const PatchRec* __restrict__ rec, int m, int criterion,
+             double thr, int lmax, int8_t* __restrict__ tags) {
+#pragma clang fp contract(off)
+  __shared__ double rlo[4], rhi[4];
+  __shared__ int rflag[4];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  const double dx = ldexp(1.0, -rec[p].level) / m;
+  double lo = 1e300, hi = -1e300;
+  int flag = 0;
+  const double t2 = thr * thr;
+  for (int c = tid; c < m * m; c += 256) {
+    const int i = c % m + 1, j = c / m + 1;
+    const double v = frame_q0<R, MEQN>(q, ghost, m, p, i, j);
+    lo = fmin(lo, v);
+    hi = fmax(hi, v);
+    if (criterion == 1) {
+      const double gx = (frame_q0<R, MEQN>(q, ghost, m, p, i + 1, j) -
+                         frame_q0<R, MEQN>(q, ghost, m, p, i - 1, j)) / (2.0 * dx);
+      const double gy = (frame_q0<R, MEQN>(q, ghost, m, p, i, j + 1) -
+                         frame_q0<R, MEQN>(q, ghost, m, p, i, j - 1)) / (2.0 * dx);
+      double s = gx * gx;
+      s = s + gy * gy;
+      if (s > t2) flag = 1;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    flag |= __shfl_xor(flag, off);
+  }
+  if ((tid & 63) == 0) { rlo[tid >> 6] = lo; rhi[tid >> 6] = hi; rflag[tid >> 6] = flag; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 1; w < 4; ++w) {
+      lo = fmin(lo, rlo[w]);
+      hi = fmax(hi, rhi[w]);
+      flag |= rflag[w];
+    }
+    lo = fmin(lo, rlo[0]);
+    hi = fmax(hi, rhi[0]);
+    flag |= rflag[0];
+    const bool crit = criterion == 0 ? (hi - lo) > thr : flag != 0;
+    tags[p] = (crit && rec[p].level < lmax) ? int8_t(1) : int8_t(0);
+  }
+}
+
+// A complete family of leaf siblings whose first child is p coarsens when
+// none of its members is tagged +1 and its averaged parent fails the test.
+template <typename R, int MEQN>
+__global__ void __launch_bounds__(256)
+k_tag_family(const R* __restrict__ q, const PatchRec* __restrict__ rec,
+             const int32_t* __restrict__ family, int m, int criterion,
+             double thr, int lmin, int8_t* __restrict__ tags) {
+#pragma clang fp contract(off)
+  extern __shared__ double par[];          // m * m averaged parent values
+  __shared__ double rlo[4], rhi[4];
+  __shared__ int rflag[4];
+  const int p = blockIdx.x, tid = threadIdx.x;
+  if (!family[p] || rec[p].level <= lmin) return;
+  if (tags[p] == 1 || tags[p + 1] == 1 || tags[p + 2] == 1 || tags[p + 3] == 1)
+    return;
+  const int h = m / 2;
+  for (int c = tid; c < m * m; c += 256) {
+    const int I = c % m + 1, J = c / m + 1;
+    const int kid = p + ((I - 1) >= h) + 2 * ((J - 1) >= h);
+    const int ii = 2 * ((I - 1) % h) + 1, jj = 2 * ((J - 1) % h) + 1;
+    const R* b = q + size_t(kid * MEQN) * m * m;
+    double acc = 0.0;
+    acc = acc + double(b[size_t(jj - 1) * m + (ii - 1)]);
+    acc = acc + double(b[size_t(jj - 1) * m + ii]);
+    acc = acc + double(b[size_t(jj) * m + (ii - 1)]);
+    acc = acc + double(b[size_t(jj) * m + ii]);
+    par[c] = acc / 4.0;
+  }
+  __syncthreads();
+  const double dxp = ldexp(1.0, -(rec[p].level - 1)) / m;
+  const double t2 = thr * thr;
+  double lo = 1e300, hi = -1e300;
+  int flag = 0;
+  for (int c = tid; c < m * m; c += 256) {
+    const int I = c % m + 1, J = c / m + 1;
+    lo = fmin(lo, par[c]);
+    hi = fmax(hi, par[c]);
+    if (criterion == 1) {
+      const int ia = I > 1 ? I - 1 : I, ib = I < m ? I + 1 : I;
+      const int ja = J > 1 ? J - 1 : J, jb = J < m ? J + 1 : J;
+      const double gx = (par[(J - 1) * m + (ib - 1)] - par[(J - 1) * m + (ia - 1)]) /
+                        (double(ib - ia) * dxp);
+      const double gy = (par[(jb - 1) * m + (I - 1)] - par[(ja - 1) * m + (I - 1)]) /
+                        (double(jb - ja) * dxp);
+      double s = gx * gx;
+      s = s + gy * gy;
+      if (s > t2) flag = 1;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    flag |= __shfl_xor(flag, off);
+  }
+  if ((tid & 63) == 0) { rlo[tid >> 6] = lo; rhi[tid >> 6] = hi; rflag[tid >> 6] = flag; }
+  __syncthreads();
+  if (tid == 0) {
+    for (int w = 0; w < 4; ++w) {
+      lo = fmin(lo, rlo[w]);
+      hi = fmax(hi, rhi[w]);
+      flag |= rflag[w];
+    }
+    const bool crit = criterion == 0 ? (hi - lo) > thr : flag != 0;
+    if (!crit)
+      for (int c = 0; c < 4; ++c) tags[p + c] = int8_t(-1);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Regrid transfer: one thread per (new patch, cell, component).
+template <typename R, int MEQN>
+__global__ void __launch_bounds__(256)
+k_transfer(const R* __restrict__ qo, const R* __restrict__ go,
+           R* __restrict__ qn, const PatchRec* __restrict__ rec_new,
+           const int32_t* __restrict__ kind, const int32_t* __restrict__ src,
+           int32_t P, int m) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t per = int64_t(MEQN) * m * m;
+  if (t >= int64_t(P) * per) return;
+  const int p = int(t / per);
+  const int rem = int(t - int64_t(p) * per);
+  const int k = rem / (m * m), c = rem % (m * m);
+  const int i = c % m + 1, j = c / m + 1;
+  const int s = src[p];
+  const int G = 8 * m + 16;
+  auto oval = [&](int pp, int ii, int jj) -> R {
+    if (ii >= 1 && ii <= m && jj >= 1 && jj <= m)
+      return qo[(size_t(pp * MEQN + k) * m + (jj - 1)) * m + (ii - 1)];
+    return go[size_t(pp * MEQN + k) * G + ghost_index(m, ii, jj)];
+  };
+  R v;
+  if (kind[p] == 0) {
+    v = oval(s, i, j);
+  } else if (kind[p] == 1) {
+    const int cx = rec_new[p].ix & 1, cy = rec_new[p].iy & 1;
+    const int ic = cx * (m / 2) + (i - 1) / 2 + 1;
+    const int jc = cy * (m / 2) + (j - 1) / 2 + 1;
+    const R dx = (i & 1) ? R(-0.25) : R(0.25);
+    const R dy = (j & 1) ? R(-0.25) : R(0.25);
+    const R qc = oval(s, ic, jc);
+    const R sx = minmod(oval(s, ic + 1, jc) - qc, qc - oval(s, ic - 1, jc));
+    const R sy = minmod(oval(s, ic, jc + 1) - qc, qc - oval(s, ic, jc - 1));
+    v = qc + dx * sx + dy * sy;
+  } else {
+    const int h = m / 2;
+    const int kid = s + ((i - 1) >= h) + 2 * ((j - 1) >= h);
+    const int ii = 2 * ((i - 1) % h) + 1, jj = 2 * ((j - 1) % h) + 1;
+    v = (((oval(kid, ii, jj) + oval(kid, ii + 1, jj)) + oval(kid, ii, jj + 1)) +
+         oval(kid, ii + 1, jj + 1)) / R(4);
+  }
+  qn[size_t(p) * per + rem] = v;
+}
+
+}  // namespace fcx

@@ -1,0 +1,220 @@
+// device.hpp -- device-side helpers shared by the fcx kernels: patch
+// records, coordinate transforms, and the ghost-cell value of a patch frame
+// cell (arXiv 1308.1472, Sec. 3: copy from a same-level neighbour, average
+// from finer neighbours, limited conservative interpolation from a coarser
+// one).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "forest.hpp"
+
+namespace fcx {
+
+// error bits raised by kernels
+constexpr int32_t kErrNegDepth = 2;
+constexpr int32_t kErrNested = 4;
+
+struct KPhys {
+  double g, ax, ay;
+  int32_t limiter, transverse;
+};
+
+template <int PHYS> struct PhysTraits;
+template <> struct PhysTraits<FCX_ADVECTION> { static constexpr int MEQN = 1; };
+template <> struct PhysTraits<FCX_SHALLOW> { static constexpr int MEQN = 3; };
+
+__device__ __forceinline__ void xf_apply(int32_t code, int32_t x, int32_t y,
+                                         int32_t& xo, int32_t& yo) {
+  int32_t u = (code & 1) ? y : x;
+  int32_t v = (code & 1) ? x : y;
+  if (code & 2) u = -u;
+  if (code & 4) v = -v;
+  xo = u + (((code >> 3) & 7) - 4) * int32_t(kSide);
+  yo = v + (((code >> 6) & 7) - 4) * int32_t(kSide);
+}
+
+template <typename R>
+__device__ __forceinline__ R minmod(R a, R b) {
+  if (a * b <= R(0)) return R(0);
+  return fabs(a) <= fabs(b) ? a : b;
+}
+
+// Compact state: q[((p*MEQN + k)*m + (j-1))*m + (i-1)]
+template <typename R, int MEQN>
+__device__ __forceinline__ void read_interior(const R* __restrict__ q, int m,
+                                              int p, int i, int j,
+                                              R (&out)[MEQN]) {
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k)
+    out[k] = q[(size_t(p * MEQN + k) * m + (j - 1)) * m + (i - 1)];
+}
+
+// Mirror (i, j) across the physical walls of a patch: xi walls first, then
+// eta walls; a reflecting wall flips the normal momentum, an extrapolation
+// wall repeats the first interior cell.
+__device__ __forceinline__ void resolve_walls(int32_t flags, int m, int& i,
+                                              int& j, bool& negx, bool& negy) {
+  if (i < 1 && (flags & 1)) {
+    if (flags & 16) i = 1; else { i = 1 - i; negx = !negx; }
+  } else if (i > m && (flags & 2)) {
+    if (flags & 32) i = m; else { i = 2 * m + 1 - i; negx = !negx; }
+  }
+  if (j < 1 && (flags & 4)) {
+    if (flags & 64) j = 1; else { j = 1 - j; negy = !negy; }
+  } else if (j > m && (flags & 8)) {
+    if (flags & 128) j = m; else { j = 2 * m + 1 - j; negy = !negy; }
+  }
+}
+
+template <typename R, int MEQN>
+struct GhostView {
+  const R* __restrict__ q;
+  const PatchRec* __restrict__ rec;
+  int m, lm;                      // m = 2^lm
+  int32_t* err;
+};
+
+// The leaf that holds the centre of non-interior, non-wall frame cell (i, j)
+// of patch p, and that centre in the leaf's tree coordinates.  Returns the
+// leaf id, or kNbrValence3.
+template <typename R, int MEQN>
+__device__ __forceinline__ int32_t holder(const GhostView<R, MEQN>& g,
+                                          const PatchRec& r, int i, int j,
+                                          int32_t& X, int32_t& Y) {
+  const int m = g.m;
+  int32_t nb, code;
+  if (i >= 1 && i <= m) {
+    const int f = j < 1 ? 2 : 3;
+    nb = r.nbr[2 * f + (i > (m >> 1))];
+    code = r.xf[f];
+  } else if (j >= 1 && j <= m) {
+    const int f = i < 1 ? 0 : 1;
+    nb = r.nbr[2 * f + (j > (m >> 1))];
+    code = r.xf[f];
+  } else {
+    const int c = (i > m) + 2 * (j > m);
+    nb = r.nbr[8 + c];
+    code = r.xf[4 + c];
+  }
+  const int sh = kS - r.level;                  // log2 of leaf size
+  const int32_t half = int32_t(1) << (sh - g.lm - 1);
+  const int32_t x = (r.ix << sh) + (2 * i - 1) * half;
+  const int32_t y = (r.iy << sh) + (2 * j - 1) * half;
+  xf_apply(code, x, y, X, Y);
+  return nb;
+}
+
+// Copy or 2x2 average from leaf nb at the point (X, Y); interpolation from a
+// coarser leaf if ALLOW_INTERP (its slope stencil uses frame values of the
+// coarse leaf, which never need interpolation themselves under full 2:1
+// balance with m >= 4).
+template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP>
+__device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
+                          int32_t X, int32_t Y, R (&out)[MEQN]);
+
+template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP>
+__device__ void frame_value(const GhostView<R, MEQN>& g, int p, int i, int j,
+                            R (&out)[MEQN]) {
+  const PatchRec& r = g.rec[p];
+  bool nx = false, ny = false;
+  resolve_walls(r.flags, g.m, i, j, nx, ny);
+  if (i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
+    read_interior<R, MEQN>(g.q, g.m, p, i, j, out);
+  } else {
+    int32_t X, Y;
+    const int32_t nb = holder(g, r, i, j, X, Y);
+    if (nb == kNbrValence3) {
+      // three trees meet: mean of the two mirrored face ghosts
+      const int mi = i < 1 ? 1 - i : 2 * g.m + 1 - i;
+      const int mj = j < 1 ? 1 - j : 2 * g.m + 1 - j;
+      R a[MEQN], b[MEQN];
+      int32_t Xa, Ya, Xb, Yb;
+      const int32_t na = holder(g, r, i, mj, Xa, Ya);
+      const int32_t nb2 = holder(g, r, mi, j, Xb, Yb);
+      from_leaf<R, MEQN, PHYS, ALLOW_INTERP>(g, r.level, na, Xa, Ya, a);
+      from_leaf<R, MEQN, PHYS, ALLOW_INTERP>(g, r.level, nb2, Xb, Yb, b);
+#pragma unroll
+      for (int k = 0; k < MEQN; ++k) out[k] = R(0.5) * (a[k] + b[k]);
+    } else {
+      from_leaf<R, MEQN, PHYS, ALLOW_INTERP>(g, r.level, nb, X, Y, out);
+    }
+  }
+  if (PHYS == FCX_SHALLOW) {
+    if (nx) out[1] = -out[1];
+    if (ny) out[2 % MEQN] = -out[2 % MEQN];
+  }
+}
+
+template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP>
+__device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
+                          int32_t X, int32_t Y, R (&out)[MEQN]) {
+  const PatchRec& n = g.rec[nb];
+  const int shn = kS - n.level;
+  const int csh = shn - g.lm;                    // log2 of n's cell size
+  const int32_t u = X - (n.ix << shn), v = Y - (n.iy << shn);
+  if (n.level == lev) {
+    read_interior<R, MEQN>(g.q, g.m, nb, (u >> csh) + 1, (v >> csh) + 1, out);
+  } else if (n.level == lev + 1) {
+    // the centre is the common corner of four cells of the finer leaf
+    const int i0 = u >> csh, j0 = v >> csh;
+    R a[MEQN], b[MEQN], c[MEQN], d[MEQN];
+    read_interior<R, MEQN>(g.q, g.m, nb, i0, j0, a);
+    read_interior<R, MEQN>(g.q, g.m, nb, i0 + 1, j0, b);
+    read_interior<R, MEQN>(g.q, g.m, nb, i0, j0 + 1, c);
+    read_interior<R, MEQN>(g.q, g.m, nb, i0 + 1, j0 + 1, d);
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) out[k] = (((a[k] + b[k]) + c[k]) + d[k]) / R(4);
+  } else if (ALLOW_INTERP) {
+    // coarser leaf: minmod-limited linear interpolation at offset +-1/4
+    const int ic = (u >> csh) + 1, jc = (v >> csh) + 1;
+    const int32_t cs = int32_t(1) << csh;
+    const R dx = (2 * u > (2 * ic - 1) * cs) ? R(0.25) : R(-0.25);
+    const R dy = (2 * v > (2 * jc - 1) * cs) ? R(0.25) : R(-0.25);
+    R qc[MEQN], qe[MEQN], qw[MEQN], qn[MEQN], qs[MEQN];
+    read_interior<R, MEQN>(g.q, g.m, nb, ic, jc, qc);
+    frame_value<R, MEQN, PHYS, false>(g, nb, ic + 1, jc, qe);
+    frame_value<R, MEQN, PHYS, false>(g, nb, ic - 1, jc, qw);
+    frame_value<R, MEQN, PHYS, false>(g, nb, ic, jc + 1, qn);
+    frame_value<R, MEQN, PHYS, false>(g, nb, ic, jc - 1, qs);
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) {
+      const R sx = minmod(qe[k] - qc[k], qc[k] - qw[k]);
+      const R sy = minmod(qn[k] - qc[k], qc[k] - qs[k]);
+      out[k] = qc[k] + dx * sx + dy * sy;
+    }
+  } else {
+    // a slope stencil reached a coarser leaf: cannot happen on a 2:1
+    // balanced forest; flag it and use the coarse cell value
+    atomicOr(g.err, kErrNested);
+    read_interior<R, MEQN>(g.q, g.m, nb, (u >> csh) + 1, (v >> csh) + 1, out);
+  }
+}
+
+// Ghost-buffer index of frame cell (i, j) of an m x m patch.
+__device__ __forceinline__ int ghost_index(int m, int i, int j) {
+  if (j <= 0) return (j + 1) * (m + 4) + (i + 1);
+  if (j > m) return 2 * (m + 4) + (j - m - 1) * (m + 4) + (i + 1);
+  const int s = i == -1 ? 0 : i == 0 ? 1 : i == m + 1 ? 2 : 3;
+  return 4 * (m + 4) + 4 * (j - 1) + s;
+}
+
+__device__ __forceinline__ void ghost_cell(int m, int g, int& i, int& j) {
+  const int w = m + 4;
+  if (g < 2 * w) { j = g / w - 1; i = g % w - 1; return; }
+  if (g < 4 * w) { g -= 2 * w; j = m + 1 + g / w; i = g % w - 1; return; }
+  g -= 4 * w;
+  j = g / 4 + 1;
+  const int s = g % 4;
+  i = s == 0 ? -1 : s == 1 ? 0 : s == 2 ? m + 1 : m + 2;
+}
+
+__device__ __forceinline__ void atomic_max_pos(double* addr, double v) {
+  // non-negative doubles order like their bit patterns
+  atomicMax(reinterpret_cast<unsigned long long*>(addr),
+            static_cast<unsigned long long>(__double_as_longlong(v)));
+}
+
+}  // namespace fcx

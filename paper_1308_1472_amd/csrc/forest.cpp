@@ -1,0 +1,511 @@
+// forest.cpp -- host-side forest: SFC order, validation, point location
+// through the connectivity, 2:1 balance by ripple propagation, neighbour
+// records for the kernels, regrid and transfer plans.  Integer work only.
+#include "forest.hpp"
+
+#include <algorithm>
+#include <deque>
+#include <unordered_set>
+
+namespace fcx {
+
+// ---------------------------------------------------------------------------
+void Xform::apply(int64_t x, int64_t y, int64_t& xo, int64_t& yo) const {
+  int64_t u = (code & 1) ? y : x;
+  int64_t v = (code & 1) ? x : y;
+  if (code & 2) u = -u;
+  if (code & 4) v = -v;
+  xo = u + int64_t(((code >> 3) & 7) - 4) * kSide;
+  yo = v + int64_t(((code >> 6) & 7) - 4) * kSide;
+}
+
+// spread the low 32 bits of v to the even bit positions
+static inline uint64_t spread(uint64_t v) {
+  v &= 0xffffffffull;
+  v = (v | (v << 16)) & 0x0000ffff0000ffffull;
+  v = (v | (v << 8)) & 0x00ff00ff00ff00ffull;
+  v = (v | (v << 4)) & 0x0f0f0f0f0f0f0f0full;
+  v = (v | (v << 2)) & 0x3333333333333333ull;
+  v = (v | (v << 1)) & 0x5555555555555555ull;
+  return v;
+}
+
+uint64_t morton_key(const fcx_leaf& a) {
+  const int sh = kS - a.level;
+  return spread(uint64_t(a.ix) << sh) | (spread(uint64_t(a.iy) << sh) << 1);
+}
+
+bool leaf_less(const fcx_leaf& a, const fcx_leaf& b) {
+  if (a.tree != b.tree) return a.tree < b.tree;
+  const uint64_t ka = morton_key(a), kb = morton_key(b);
+  if (ka != kb) return ka < kb;
+  return a.level < b.level;
+}
+
+static inline uint64_t pack_key(int32_t tree, int32_t level, int64_t ix,
+                                int64_t iy) {
+  return (uint64_t(tree) << 53) | (uint64_t(level) << 48) |
+         (uint64_t(ix) << 24) | uint64_t(iy);
+}
+
+// ---------------------------------------------------------------------------
+int check_connectivity(const std::vector<fcx_tree>& trees, std::string& err) {
+  const int n = int(trees.size());
+  if (n <= 0 || n > 64) { err = "tree count must be 1..64"; return FCX_EINVAL; }
+  for (int t = 0; t < n; ++t)
+    for (int f = 0; f < 4; ++f) {
+      const fcx_tree& T = trees[t];
+      if (T.bc[f] < 0 || T.bc[f] > 2) { err = "bad bc"; return FCX_EINVAL; }
+      if (T.bc[f] != 0) continue;
+      const int t2 = T.nbr_tree[f], f2 = T.nbr_face[f];
+      if (t2 < 0 || t2 >= n || f2 < 0 || f2 > 3 || T.orient[f] < 0 ||
+          T.orient[f] > 1) {
+        err = "bad face connection";
+        return FCX_EINVAL;
+      }
+      const fcx_tree& U = trees[t2];
+      if (U.bc[f2] != 0 || U.nbr_tree[f2] != t || U.nbr_face[f2] != f ||
+          U.orient[f2] != T.orient[f]) {
+        err = "face connections are not symmetric";
+        return FCX_EINVAL;
+      }
+    }
+  return FCX_OK;
+}
+
+int Forest::assign(const std::vector<fcx_tree>& t,
+                   const std::vector<fcx_leaf>& l, std::string& err) {
+  int rc = check_connectivity(t, err);
+  if (rc != FCX_OK) return rc;
+  trees = t;
+  leaves = l;
+  index_.clear();
+  index_.reserve(l.size() * 2);
+  maxlevel = 0;
+  size_t k = 0;
+  for (int32_t tr = 0; tr < int32_t(trees.size()); ++tr) {
+    uint64_t next = 0;
+    for (; k < leaves.size() && leaves[k].tree == tr; ++k) {
+      const fcx_leaf& a = leaves[k];
+      if (a.level < 0 || a.level > kMaxLevel || a.ix < 0 || a.iy < 0 ||
+          a.ix >= (1 << a.level) || a.iy >= (1 << a.level)) {
+        err = "leaf coordinates out of range";
+        return FCX_EINVAL;
+      }
+      if (morton_key(a) != next) {
+        err = "leaves are not SFC-sorted or do not tile the tree";
+        return FCX_EINVAL;
+      }
+      next += uint64_t(1) << (2 * (kS - a.level));
+      maxlevel = std::max(maxlevel, int(a.level));
+      index_[pack_key(a.tree, a.level, a.ix, a.iy)] = int32_t(k);
+    }
+    if (next != (uint64_t(1) << (2 * kS))) {
+      err = "leaves do not tile every tree";
+      return FCX_EINVAL;
+    }
+  }
+  if (k != leaves.size()) {
+    err = "leaf with an unknown tree";
+    return FCX_EINVAL;
+  }
+  return FCX_OK;
+}
+
+int64_t Forest::find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const {
+  auto it = index_.find(pack_key(tree, level, ix, iy));
+  return it == index_.end() ? -1 : it->second;
+}
+
+int64_t Forest::leaf_at(int32_t tree, int64_t x, int64_t y) const {
+  if (x < 0 || y < 0 || x >= kSide || y >= kSide) return -1;
+  for (int l = maxlevel; l >= 0; --l) {
+    int64_t s = find(tree, l, x >> (kS - l), y >> (kS - l));
+    if (s >= 0) return s;
+  }
+  return -1;
+}
+
+bool Forest::wall_face(int64_t p, int f) const {
+  const fcx_leaf& a = leaves[p];
+  const int32_t last = (1 << a.level) - 1;
+  const bool on = (f == 0 && a.ix == 0) || (f == 1 && a.ix == last) ||
+                  (f == 2 && a.iy == 0) || (f == 3 && a.iy == last);
+  return on && trees[a.tree].bc[f] != 0;
+}
+
+// ---------------------------------------------------------------------------
+// Crossing face f of tree t maps a point beyond the face into the glued tree:
+// its depth beyond face f becomes its depth inside face f2; the tangential
+// coordinate is kept or reversed by the orientation.
+static void cross_point(const fcx_tree& T, int f, int64_t x, int64_t y,
+                        int64_t& xo, int64_t& yo) {
+  const int f2 = T.nbr_face[f];
+  const int64_t n = (f < 2) ? x : y, tg = (f < 2) ? y : x;
+  const int64_t depth = (f & 1) ? n - kSide : -n;
+  const int64_t n2 = (f2 & 1) ? kSide - depth : depth;
+  const int64_t t2 = T.orient[f] ? kSide - tg : tg;
+  if (f2 < 2) { xo = n2; yo = t2; } else { xo = t2; yo = n2; }
+}
+
+struct Path {
+  int n = 0;
+  int tree[3];
+  int face[3];
+};
+
+static void run_path(const std::vector<fcx_tree>& trees, const Path& p,
+                     int64_t x, int64_t y, int64_t& xo, int64_t& yo) {
+  for (int k = 0; k < p.n; ++k) {
+    int64_t a, b;
+    cross_point(trees[p.tree[k]], p.face[k], x, y, a, b);
+    x = a;
+    y = b;
+  }
+  xo = x;
+  yo = y;
+}
+
+static Xform xform_of(const std::vector<fcx_tree>& trees, const Path& p) {
+  int64_t bx, by, ax, ay, cx, cy;
+  run_path(trees, p, 0, 0, bx, by);
+  run_path(trees, p, kSide, 0, ax, ay);
+  run_path(trees, p, 0, kSide, cx, cy);
+  const int64_t c0x = (ax - bx) / kSide, c0y = (ay - by) / kSide;
+  const int64_t c1x = (cx - bx) / kSide, c1y = (cy - by) / kSide;
+  Xform xf;
+  int code = 0;
+  if (c0x == 0) {                 // x feeds y': axes swap
+    code |= 1;
+    if (c1x < 0) code |= 2;
+    if (c0y < 0) code |= 4;
+  } else {
+    if (c0x < 0) code |= 2;
+    if (c1y < 0) code |= 4;
+  }
+  code |= int((bx / kSide) + 4) << 3;
+  code |= int((by / kSide) + 4) << 6;
+  xf.code = code;
+  return xf;
+}
+
+static int outside_axis_face(int64_t v, int axis) {
+  if (v < 0) return 2 * axis;
+  if (v >= kSide) return 2 * axis + 1;
+  return -1;
+}
+
+// follow faces, preferring `axis` when the point is outside in both
+static int follow(const std::vector<fcx_tree>& trees, int32_t t, int64_t x,
+                  int64_t y, int axis, Path& path, int32_t& tout, int64_t& xo,
+                  int64_t& yo) {
+  path.n = 0;
+  for (int hop = 0; hop < 3; ++hop) {
+    const int fx = outside_axis_face(x, 0), fy = outside_axis_face(y, 1);
+    if (fx < 0 && fy < 0) {
+      tout = t;
+      xo = x;
+      yo = y;
+      return 0;
+    }
+    if (hop == 2) return 3;
+    const int f = (fx >= 0 && fy >= 0) ? (axis == 0 ? fx : fy)
+                                       : (fx >= 0 ? fx : fy);
+    const fcx_tree& T = trees[t];
+    if (T.bc[f] != 0) return 1;
+    path.tree[path.n] = t;
+    path.face[path.n] = f;
+    ++path.n;
+    int64_t a, b;
+    cross_point(T, f, x, y, a, b);
+    x = a;
+    y = b;
+    t = T.nbr_tree[f];
+    axis ^= 1;
+  }
+  return 3;
+}
+
+int Forest::locate(int32_t tree, int64_t x, int64_t y, int32_t& tout,
+                   int64_t& xo, int64_t& yo, Xform& xf) const {
+  Path pa, pb;
+  int32_t ta, tb;
+  int64_t xa, ya, xb, yb;
+  const int ra = follow(trees, tree, x, y, 0, pa, ta, xa, ya);
+  const bool corner = outside_axis_face(x, 0) >= 0 && outside_axis_face(y, 1) >= 0;
+  if (!corner) {
+    if (ra != 0) return ra == 1 ? 1 : 3;
+    tout = ta;
+    xo = xa;
+    yo = ya;
+    xf = xform_of(trees, pa);
+    return 0;
+  }
+  const int rb = follow(trees, tree, x, y, 1, pb, tb, xb, yb);
+  if (ra == 0 && rb == 0) {
+    if (ta != tb || xa != xb || ya != yb) return 2;   // three trees meet
+    tout = ta;
+    xo = xa;
+    yo = ya;
+    xf = xform_of(trees, pa);
+    return 0;
+  }
+  if (ra == 1 && rb == 1) return 1;
+  return 3;
+}
+
+// ---------------------------------------------------------------------------
+// Balance by ripple propagation.  A leaf L of level l needs the leaf holding
+// each of its eight same-size neighbour boxes to have level >= l - 1; when
+// that leaf is coarser it is split (and its children queued), until every
+// constraint holds.  Only forced splits are made, so the result is the
+// coarsest balanced refinement.
+int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
+            std::vector<fcx_leaf>& out, std::string& err) {
+  int rc = check_connectivity(trees, err);
+  if (rc != FCX_OK) return rc;
+  std::unordered_set<uint64_t> set;
+  set.reserve(in.size() * 4);
+  std::deque<fcx_leaf> work;
+  for (const auto& a : in) {
+    if (a.tree < 0 || a.tree >= int32_t(trees.size()) || a.level < 0 ||
+        a.level > kMaxLevel) {
+      err = "leaf out of range";
+      return FCX_EINVAL;
+    }
+    set.insert(pack_key(a.tree, a.level, a.ix, a.iy));
+    work.push_back(a);
+  }
+  Forest geo;            // connectivity only (for locate)
+  geo.trees = trees;
+  while (!work.empty()) {
+    const fcx_leaf L = work.front();
+    work.pop_front();
+    if (!set.count(pack_key(L.tree, L.level, L.ix, L.iy))) continue;
+    if (L.level < 2) continue;
+    const int64_t size = kSide >> L.level;
+    for (int dy = -1; dy <= 1; ++dy)
+      for (int dx = -1; dx <= 1; ++dx) {
+        if (!dx && !dy) continue;
+        const int64_t px = (int64_t(L.ix + dx) * 2 + 1) * (size / 2);
+        const int64_t py = (int64_t(L.iy + dy) * 2 + 1) * (size / 2);
+        int32_t t2;
+        int64_t x2, y2;
+        Xform xf;
+        if (geo.locate(L.tree, px, py, t2, x2, y2, xf) != 0) continue;
+        for (;;) {
+          // leaf among the ancestors of the neighbour box (level <= L.level)
+          int found = -1;
+          for (int lev = L.level; lev >= 0; --lev)
+            if (set.count(pack_key(t2, lev, x2 >> (kS - lev), y2 >> (kS - lev)))) {
+              found = lev;
+              break;
+            }
+          if (found < 0 || found >= L.level - 1) break;
+          const int64_t ax = x2 >> (kS - found), ay = y2 >> (kS - found);
+          set.erase(pack_key(t2, found, ax, ay));
+          for (int c = 0; c < 4; ++c) {
+            fcx_leaf ch{t2, found + 1, int32_t(2 * ax + (c & 1)),
+                        int32_t(2 * ay + (c >> 1))};
+            set.insert(pack_key(ch.tree, ch.level, ch.ix, ch.iy));
+            work.push_back(ch);
+          }
+        }
+      }
+  }
+  out.clear();
+  out.reserve(set.size());
+  for (uint64_t k : set) {
+    fcx_leaf a;
+    a.tree = int32_t(k >> 53);
+    a.level = int32_t((k >> 48) & 31);
+    a.ix = int32_t((k >> 24) & 0xffffff);
+    a.iy = int32_t(k & 0xffffff);
+    out.push_back(a);
+  }
+  std::sort(out.begin(), out.end(), leaf_less);
+  return FCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
+  const int64_t n = int64_t(f.leaves.size());
+  plan.recs.assign(n, PatchRec{});
+  plan.phislot.assign(n, -1);
+  plan.family.assign(n, 0);
+  plan.reflux.clear();
+  plan.nslots = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    const fcx_leaf& a = f.leaves[p];
+    PatchRec& r = plan.recs[p];
+    r.level = a.level;
+    r.ix = a.ix;
+    r.iy = a.iy;
+    r.flags = 0;
+    const int64_t size = kSide >> a.level, half = size / (2 * m);
+    const int64_t x0 = int64_t(a.ix) * size, y0 = int64_t(a.iy) * size;
+    auto centre = [&](int i, int j, int64_t& x, int64_t& y) {
+      x = x0 + (2 * i - 1) * half;
+      y = y0 + (2 * j - 1) * half;
+    };
+    bool mixed = false;
+    for (int fc = 0; fc < 4; ++fc) {
+      if (f.wall_face(p, fc)) {
+        r.flags |= 1 << fc;
+        if (f.trees[a.tree].bc[fc] == 2) r.flags |= 16 << fc;
+        r.nbr[2 * fc] = r.nbr[2 * fc + 1] = kNbrWall;
+        r.xf[fc] = Xform().code;
+        continue;
+      }
+      int32_t ids[2];
+      Xform xf;
+      for (int s = 0; s < 2; ++s) {
+        const int t = s == 0 ? 1 : m;
+        int64_t x, y;
+        if (fc < 2) centre(fc == 0 ? 0 : m + 1, t, x, y);
+        else centre(t, fc == 2 ? 0 : m + 1, x, y);
+        int32_t t2;
+        int64_t x2, y2;
+        if (f.locate(a.tree, x, y, t2, x2, y2, xf) != 0) {
+          err = "face neighbour not found";
+          return FCX_EINVAL;
+        }
+        ids[s] = int32_t(f.leaf_at(t2, x2, y2));
+        if (ids[s] < 0) { err = "face neighbour missing"; return FCX_EINVAL; }
+      }
+      const int l0 = f.leaves[ids[0]].level, l1 = f.leaves[ids[1]].level;
+      if (ids[0] != ids[1] ? (l0 != a.level + 1 || l1 != a.level + 1)
+                           : (l0 > a.level || l0 < a.level - 1)) {
+        err = "forest is not 2:1 balanced";
+        return FCX_EBALANCE;
+      }
+      if (l0 != a.level) mixed = true;
+      r.nbr[2 * fc] = ids[0];
+      r.nbr[2 * fc + 1] = ids[1];
+      r.xf[fc] = xf.code;
+      if (ids[0] != ids[1]) {
+        RefluxItem it{};
+        it.coarse = int32_t(p);
+        it.face = fc;
+        // linear part of the map, applied to directions
+        Xform lin = xf;
+        lin.code = (xf.code & 7) | (4 << 3) | (4 << 6);
+        int64_t dx = 0, dy = 0, tx = 0, ty = 0;
+        if (fc < 2) { dx = (fc == 1) ? -1 : 1; ty = 1; } else { dy = (fc == 3) ? -1 : 1; tx = 1; }
+        int64_t ddx, ddy, tdx, tdy;
+        lin.apply(dx, dy, ddx, ddy);
+        lin.apply(tx, ty, tdx, tdy);
+        // the direction towards the coarse patch names the fine face
+        int ff = ddx > 0 ? 1 : ddx < 0 ? 0 : ddy > 0 ? 3 : 2;
+        int rev = (ff < 2) ? (tdy < 0) : (tdx < 0);
+        for (int s = 0; s < 2; ++s) {
+          it.fine[s] = ids[s];
+          it.fine_face[s] = ff;
+          it.fine_rev[s] = rev;
+        }
+        plan.reflux.push_back(it);
+      }
+    }
+    for (int c = 0; c < 4; ++c) {
+      const int fx = c & 1, fy = 2 + (c >> 1);
+      if ((r.flags >> fx & 1) || (r.flags >> fy & 1)) {
+        r.nbr[8 + c] = kNbrWall;
+        r.xf[4 + c] = Xform().code;
+        continue;
+      }
+      int64_t x, y;
+      centre((c & 1) ? m + 1 : 0, (c >> 1) ? m + 1 : 0, x, y);
+      int32_t t2;
+      int64_t x2, y2;
+      Xform xf;
+      const int st = f.locate(a.tree, x, y, t2, x2, y2, xf);
+      if (st == 2) {
+        r.nbr[8 + c] = kNbrValence3;
+        r.xf[4 + c] = Xform().code;
+        continue;
+      }
+      if (st != 0) { err = "corner neighbour not found"; return FCX_EINVAL; }
+      const int64_t id = f.leaf_at(t2, x2, y2);
+      if (id < 0) { err = "corner neighbour missing"; return FCX_EINVAL; }
+      const int lc = f.leaves[id].level;
+      if (lc < a.level - 1 || lc > a.level + 1) {
+        err = "forest is not 2:1 balanced at a corner";
+        return FCX_EBALANCE;
+      }
+      r.nbr[8 + c] = int32_t(id);
+      r.xf[4 + c] = xf.code;
+    }
+    if (mixed) plan.phislot[p] = plan.nslots++;
+    // first child of a complete family of leaf siblings
+    if (a.level > 0 && !(a.ix & 1) && !(a.iy & 1)) {
+      bool all = true;
+      for (int c = 1; c < 4; ++c)
+        if (f.find(a.tree, a.level, a.ix + (c & 1), a.iy + (c >> 1)) != p + c)
+          all = false;
+      plan.family[p] = all ? 1 : 0;
+    }
+  }
+  return FCX_OK;
+}
+
+// ---------------------------------------------------------------------------
+int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
+           std::vector<fcx_leaf>& out, std::string& err) {
+  std::vector<fcx_leaf> next;
+  const int64_t n = int64_t(f.leaves.size());
+  next.reserve(n + 16);
+  for (int64_t p = 0; p < n; ++p) {
+    const fcx_leaf& a = f.leaves[p];
+    if (tags[p] > 0 && a.level < lmax) {
+      for (int c = 0; c < 4; ++c)
+        next.push_back({a.tree, a.level + 1, 2 * a.ix + (c & 1), 2 * a.iy + (c >> 1)});
+      continue;
+    }
+    if (tags[p] < 0 && a.level > lmin) {
+      const int32_t bx = a.ix & ~1, by = a.iy & ~1;
+      bool all = true;
+      for (int c = 0; c < 4; ++c) {
+        const int64_t s = f.find(a.tree, a.level, bx + (c & 1), by + (c >> 1));
+        if (s < 0 || tags[s] >= 0) { all = false; break; }
+      }
+      if (all) {
+        if (a.ix == bx && a.iy == by)
+          next.push_back({a.tree, a.level - 1, a.ix >> 1, a.iy >> 1});
+        continue;
+      }
+    }
+    next.push_back(a);
+  }
+  return balance(f.trees, std::move(next), out, err);
+}
+
+int transfer_plan(const Forest& old_f, const Forest& new_f,
+                  std::vector<int32_t>& kind, std::vector<int32_t>& src,
+                  std::string& err) {
+  const int64_t n = int64_t(new_f.leaves.size());
+  kind.assign(n, 0);
+  src.assign(n, -1);
+  for (int64_t p = 0; p < n; ++p) {
+    const fcx_leaf& a = new_f.leaves[p];
+    int64_t s = old_f.find(a.tree, a.level, a.ix, a.iy);
+    if (s >= 0) { kind[p] = 0; src[p] = int32_t(s); continue; }
+    if (a.level > 0) {
+      s = old_f.find(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1);
+      if (s >= 0) { kind[p] = 1; src[p] = int32_t(s); continue; }
+    }
+    s = old_f.find(a.tree, a.level + 1, 2 * a.ix, 2 * a.iy);
+    bool all = s >= 0;
+    for (int c = 1; c < 4 && all; ++c)
+      all = old_f.find(a.tree, a.level + 1, 2 * a.ix + (c & 1),
+                       2 * a.iy + (c >> 1)) == s + c;
+    if (!all) {
+      err = "new leaf is not a copy, child or parent of old leaves";
+      return FCX_EINVAL;
+    }
+    kind[p] = 2;
+    src[p] = int32_t(s);
+  }
+  return FCX_OK;
+}
+
+}  // namespace fcx

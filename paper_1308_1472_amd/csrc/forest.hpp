@@ -1,0 +1,105 @@
+// forest.hpp -- host-side forest of quadtrees for the fcx library.
+//
+// A forest is a set of trees (each the reference square [0,1]^2, glued by a
+// face connectivity) whose leaves tile every tree; each leaf houses one
+// m x m patch (arXiv 1308.1472, Sec. 2: one leaf <-> one patch).  Leaves
+// are stored in space-filling-curve order (Sec. 4): tree-major, then Morton
+// order of the lower-left corner.  All work here is integer work.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/fcx.h"
+
+namespace fcx {
+
+constexpr int kS = 24;                       // tree side = 2^24 units
+constexpr int64_t kSide = int64_t(1) << kS;
+constexpr int kMaxLevel = 18;
+
+// Affine map between tree coordinate systems: x' = A x + b, A a signed
+// permutation (bit 0 swap, bit 1 negate first, bit 2 negate second), b in
+// units of the tree side (bits 3..5 and 6..8, biased by 4).
+struct Xform {
+  int32_t code = 4 << 3 | 4 << 6;            // identity
+  void apply(int64_t x, int64_t y, int64_t& xo, int64_t& yo) const;
+};
+
+uint64_t morton_key(const fcx_leaf& a);
+bool leaf_less(const fcx_leaf& a, const fcx_leaf& b);
+
+class Forest {
+ public:
+  std::vector<fcx_tree> trees;
+  std::vector<fcx_leaf> leaves;              // SFC order
+  int maxlevel = 0;
+
+  // Validates connectivity and leaves (sorted, exact tiling); builds the
+  // leaf index.  Returns FCX_OK or an error code with a message in err.
+  int assign(const std::vector<fcx_tree>& t, const std::vector<fcx_leaf>& l,
+             std::string& err);
+  int64_t find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const;
+  // leaf containing an in-tree point, -1 if none
+  int64_t leaf_at(int32_t tree, int64_t x, int64_t y) const;
+
+  // Map a point (possibly outside its tree) into the tree containing it.
+  // Returns 0 (found), 1 (beyond a physical boundary), 2 (valence-3
+  // corner: no tree contains it), 3 (inconsistent connectivity).  The map
+  // used is returned in xf.
+  int locate(int32_t tree, int64_t x, int64_t y, int32_t& tout, int64_t& xo,
+             int64_t& yo, Xform& xf) const;
+  bool wall_face(int64_t p, int f) const;
+
+ private:
+  std::unordered_map<uint64_t, int32_t> index_;
+};
+
+int check_connectivity(const std::vector<fcx_tree>& trees, std::string& err);
+
+// Coarsest 2:1 (face + corner) balanced forest refining `in` (any order).
+int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
+            std::vector<fcx_leaf>& out, std::string& err);
+
+// Per-patch neighbour records consumed by the kernels.
+struct PatchRec {
+  int32_t level, ix, iy, flags;              // flags: bit f wall on face f,
+                                             // bit 4+f extrapolation wall
+  int32_t nbr[12];                           // faces 2 slots each, corners
+  int32_t xf[8];                             // face / corner transforms
+};
+static_assert(sizeof(PatchRec) == 96, "PatchRec layout");
+
+constexpr int32_t kNbrWall = -1;
+constexpr int32_t kNbrValence3 = -2;
+
+// One coarse patch face with two finer neighbours (reflux work item).
+struct RefluxItem {
+  int32_t coarse, face, fine[2], fine_face[2], fine_rev[2];
+};
+
+struct Plan {
+  std::vector<PatchRec> recs;
+  std::vector<int32_t> phislot;              // -1 or slot of the patch
+  int32_t nslots = 0;
+  std::vector<RefluxItem> reflux;
+  std::vector<int32_t> family;               // 1 at the first child of a
+                                             // complete leaf family
+};
+
+int build_plan(const Forest& f, int m, Plan& plan, std::string& err);
+
+// Regrid: refine +1, merge complete families tagged -1, then balance.
+int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
+           std::vector<fcx_leaf>& out, std::string& err);
+
+// Transfer plan from an old to a new forest: per new patch kind
+// (0 copy, 1 refined from an old coarser patch, 2 merged from four old
+// children) and the old patch index (first child for kind 2).
+int transfer_plan(const Forest& old_f, const Forest& new_f,
+                  std::vector<int32_t>& kind, std::vector<int32_t>& src,
+                  std::string& err);
+
+}  // namespace fcx

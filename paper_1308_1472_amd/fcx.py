@@ -1,0 +1,246 @@
+"""Python binding of libfcx.so (include/fcx.h): argument marshalling only.
+
+Every numerical step runs in the library's HIP kernels; this module only
+checks shapes and dtypes, takes device pointers from torch tensors and the
+current HIP stream, and translates error codes into exceptions.  It raises
+if the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "_build", "libfcx.so")
+
+LEAF_DTYPE = np.dtype([("tree", "<i4"), ("level", "<i4"), ("ix", "<i4"),
+                       ("iy", "<i4")])
+TREE_DTYPE = np.dtype([("nbr_tree", "<i4", (4,)), ("nbr_face", "<i4", (4,)),
+                       ("orient", "<i4", (4,)), ("bc", "<i4", (4,))])
+
+FCX_ADVECTION, FCX_SHALLOW = 0, 1
+ERRORS = {-1: "FCX_EINVAL", -2: "FCX_EBALANCE", -3: "FCX_ENOMEM",
+          -4: "FCX_EHIP", -5: "FCX_ECFL", -6: "FCX_ENEG", -7: "FCX_ESTATE"}
+
+# the symbols include/fcx.h declares
+EXPORTS = [
+    "fcx_last_error", "fcx_version", "fcx_sfc_sort", "fcx_balance",
+    "fcx_create", "fcx_destroy", "fcx_upload_forest", "fcx_num_patches",
+    "fcx_state_elems", "fcx_ghost_elems", "fcx_get_leaves", "fcx_ghost_fill",
+    "fcx_patch_step", "fcx_fused_step", "fcx_reflux", "fcx_next_dt",
+    "fcx_conservation_sums", "fcx_regrid_tags", "fcx_regrid_apply",
+    "fcx_regrid_transfer",
+]
+
+
+class FcxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Config(C.Structure):
+    _fields_ = [("m", C.c_int32), ("precision", C.c_int32),
+                ("physics", C.c_int32), ("limiter", C.c_int32),
+                ("transverse", C.c_int32), ("tile", C.c_int32),
+                ("g", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
+                ("cfl_desired", C.c_double), ("cfl_max", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(
+                f"{LIB_PATH} is missing: build it with "
+                "`python -m paper_1308_1472_amd.build` (there is no fallback)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+        L.fcx_last_error.restype = C.c_char_p
+        L.fcx_version.restype = i32
+        L.fcx_sfc_sort.argtypes = [i64, vp]
+        L.fcx_balance.argtypes = [i32, vp, i64, vp, i64, vp, vp]
+        L.fcx_create.argtypes = [vp, i32, vp, vp]
+        L.fcx_destroy.argtypes = [vp]
+        L.fcx_upload_forest.argtypes = [vp, i64, vp]
+        for f in ("fcx_num_patches", "fcx_state_elems", "fcx_ghost_elems"):
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = i64
+        L.fcx_get_leaves.argtypes = [vp, i64, vp]
+        L.fcx_ghost_fill.argtypes = [vp, vp, vp, vp]
+        L.fcx_patch_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fcx_fused_step.argtypes = [vp, vp, vp, vp, vp, vp]
+        L.fcx_reflux.argtypes = [vp, vp, vp, vp, vp]
+        L.fcx_next_dt.argtypes = [vp, vp, vp, vp, vp]
+        L.fcx_conservation_sums.argtypes = [vp, vp, vp, vp]
+        L.fcx_regrid_tags.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp]
+        L.fcx_regrid_apply.argtypes = [vp, vp, i32, i32, vp]
+        L.fcx_regrid_transfer.argtypes = [vp, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise FcxError(rc, lib().fcx_last_error().decode())
+
+
+def _np_ptr(a):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def sfc_sort(leaves) -> np.ndarray:
+    a = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE).copy()
+    _check(lib().fcx_sfc_sort(len(a), _np_ptr(a)))
+    return a
+
+
+def balance(trees, leaves) -> np.ndarray:
+    trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
+    leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+    n = C.c_int64()
+    cap = 16 * len(leaves) + 64
+    while True:
+        out = np.zeros(cap, dtype=LEAF_DTYPE)
+        rc = lib().fcx_balance(len(trees), _np_ptr(trees), len(leaves),
+                               _np_ptr(leaves), cap, _np_ptr(out), C.byref(n))
+        if rc == -1 and n.value > cap:
+            cap = n.value
+            continue
+        _check(rc)
+        return out[: n.value].copy()
+
+
+def config(m, precision=64, physics=FCX_SHALLOW, limiter=4, transverse=2,
+           tile=0, g=1.0, ax=0.0, ay=0.0, cfl_desired=0.9, cfl_max=1.0):
+    return Config(m, precision, physics, limiter, transverse, tile, g, ax, ay,
+                  cfl_desired, cfl_max)
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+class Context:
+    """One forest on the current HIP device (fcx_ctx)."""
+
+    def __init__(self, cfg: Config, trees):
+        self.cfg = cfg
+        self.meqn = 1 if cfg.physics == FCX_ADVECTION else 3
+        self.trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
+        h = C.c_void_p()
+        _check(lib().fcx_create(C.byref(cfg), len(self.trees),
+                                _np_ptr(self.trees), C.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().fcx_destroy(self.h)
+            self.h = None
+
+    # ---- forest -------------------------------------------------------
+    def upload_forest(self, leaves):
+        leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+        _check(lib().fcx_upload_forest(self.h, len(leaves), _np_ptr(leaves)))
+
+    def num_patches(self) -> int:
+        return lib().fcx_num_patches(self.h)
+
+    def state_elems(self) -> int:
+        return lib().fcx_state_elems(self.h)
+
+    def ghost_elems(self) -> int:
+        return lib().fcx_ghost_elems(self.h)
+
+    def leaves(self) -> np.ndarray:
+        out = np.zeros(self.num_patches(), dtype=LEAF_DTYPE)
+        _check(lib().fcx_get_leaves(self.h, len(out), _np_ptr(out)))
+        return out
+
+    # ---- tensors ------------------------------------------------------
+    def _dt(self):
+        import torch
+        return torch.float64 if self.cfg.precision == 64 else torch.float32
+
+    def _state(self, t, n):
+        import torch
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == self._dt()
+                and t.is_contiguous() and t.numel() == n):
+            raise ValueError(f"expected a contiguous {self._dt()} device tensor "
+                             f"of {n} elements")
+        return C.c_void_p(t.data_ptr())
+
+    def _q(self, t):
+        return self._state(t, self.state_elems())
+
+    def _g(self, t):
+        return self._state(t, self.ghost_elems())
+
+    @staticmethod
+    def _d(t, n=1, dtype=None):
+        import torch
+        dtype = dtype or torch.float64
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype
+                and t.numel() >= n):
+            raise ValueError(f"expected a {dtype} device tensor")
+        return C.c_void_p(t.data_ptr())
+
+    # ---- the step -----------------------------------------------------
+    def ghost_fill(self, q, ghost, stream=None):
+        _check(lib().fcx_ghost_fill(self.h, self._q(q), self._g(ghost),
+                                    _stream(stream)))
+
+    def patch_step(self, q, ghost, q_new, dt, numax, stream=None):
+        _check(lib().fcx_patch_step(self.h, self._q(q), self._g(ghost),
+                                    self._q(q_new), self._d(dt), self._d(numax),
+                                    _stream(stream)))
+
+    def fused_step(self, q, q_new, dt, numax, stream=None):
+        _check(lib().fcx_fused_step(self.h, self._q(q), self._q(q_new),
+                                    self._d(dt), self._d(numax), _stream(stream)))
+
+    def reflux(self, q, q_new, dt, stream=None):
+        _check(lib().fcx_reflux(self.h, self._q(q), self._q(q_new), self._d(dt),
+                                _stream(stream)))
+
+    def next_dt(self, numax, dt, status, stream=None):
+        import torch
+        _check(lib().fcx_next_dt(self.h, self._d(numax), self._d(dt),
+                                 self._d(status, 1, torch.int32), _stream(stream)))
+
+    def conservation_sums(self, q, sums, stream=None):
+        _check(lib().fcx_conservation_sums(self.h, self._q(q),
+                                           self._d(sums, self.meqn),
+                                           _stream(stream)))
+
+    # ---- regrid -------------------------------------------------------
+    def regrid_tags(self, q, ghost, criterion, threshold, lmin, lmax, tags,
+                    stream=None):
+        import torch
+        g = self._g(ghost) if ghost is not None else None
+        _check(lib().fcx_regrid_tags(self.h, self._q(q), g, criterion, threshold,
+                                     lmin, lmax,
+                                     self._d(tags, self.num_patches(), torch.int8),
+                                     _stream(stream)))
+
+    def regrid_apply(self, tags_host, lmin, lmax) -> int:
+        t = np.ascontiguousarray(tags_host, dtype=np.int8)
+        if len(t) != self.num_patches():
+            raise ValueError("one tag per patch expected")
+        n = C.c_int64()
+        _check(lib().fcx_regrid_apply(self.h, _np_ptr(t), lmin, lmax, C.byref(n)))
+        return n.value
+
+    def regrid_transfer(self, q_old, ghost_old, q_new, stream=None):
+        # q_old / ghost_old are laid out on the previous forest
+        _check(lib().fcx_regrid_transfer(self.h, C.c_void_p(q_old.data_ptr()),
+                                         C.c_void_p(ghost_old.data_ptr()),
+                                         self._q(q_new), _stream(stream)))

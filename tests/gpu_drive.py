@@ -1,0 +1,155 @@
+"""Test-side drivers: run the same scenario through the HIP library (via the
+binding) and through the CPU oracle, and convert between their layouts.
+
+Layouts: the library keeps compact interiors (P, meqn, m, m) and a separate
+ghost buffer (P, meqn, 8m+16); the oracle keeps framed arrays
+(P, meqn, m+4, m+4).
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle import oracle as O
+from paper_1308_1472_amd import fcx
+from paper_1308_1472_amd import inputs as I
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def ghost_positions(m):
+    """Frame (i, j) of every ghost-buffer entry, per the layout in fcx.h."""
+    pos = []
+    for j in (-1, 0):
+        for i in range(-1, m + 3):
+            pos.append((i, j))
+    for j in (m + 1, m + 2):
+        for i in range(-1, m + 3):
+            pos.append((i, j))
+    for j in range(1, m + 1):
+        for i in (-1, 0, m + 1, m + 2):
+            pos.append((i, j))
+    assert len(pos) == 8 * m + 16
+    return pos
+
+
+def ghost_to_frame(ghost, q, m):
+    """(P, meqn, G) ghost buffer + (P, meqn, m, m) interior -> framed."""
+    P, meqn = q.shape[:2]
+    f = np.full((P, meqn, m + 4, m + 4), np.nan)
+    f[:, :, 2:m + 2, 2:m + 2] = q
+    for g, (i, j) in enumerate(ghost_positions(m)):
+        if (i in (-1, m + 2)) and (j in (-1, m + 2)):
+            continue
+        f[:, :, j + 1, i + 1] = ghost[:, :, g]
+    return f
+
+
+def needed_mask(m):
+    g = np.ones((m + 4, m + 4), bool)
+    g[2:m + 2, 2:m + 2] = False
+    for a in (0, m + 3):
+        for b in (0, m + 3):
+            g[a, b] = False
+    return g
+
+
+class Gpu:
+    """One forest in the library, FP32 or FP64."""
+
+    def __init__(self, cfg, trees, leaves):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.ctx = fcx.Context(cfg, trees)
+        self.ctx.upload_forest(leaves)
+        self.m = cfg.m
+        self.meqn = self.ctx.meqn
+        self.dtype = torch.float64 if cfg.precision == 64 else torch.float32
+        dev = "cuda"
+        self.dt = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.numax = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.sums = torch.zeros(self.meqn, dtype=torch.float64, device=dev)
+        self._alloc()
+
+    def _alloc(self):
+        t = self.torch
+        self.q = t.zeros(self.ctx.state_elems(), dtype=self.dtype, device="cuda")
+        self.qn = t.zeros_like(self.q)
+        self.ghost = t.zeros(self.ctx.ghost_elems(), dtype=self.dtype, device="cuda")
+
+    def set_state(self, q_np):
+        self.q.copy_(self.torch.from_numpy(np.ascontiguousarray(q_np).ravel()).to(
+            self.dtype).cuda())
+
+    def state(self):
+        P = self.ctx.num_patches()
+        return self.q.double().cpu().numpy().reshape(P, self.meqn, self.m, self.m)
+
+    def ghosts(self):
+        P = self.ctx.num_patches()
+        return self.ghost.double().cpu().numpy().reshape(P, self.meqn, 8 * self.m + 16)
+
+    def fill(self):
+        self.ctx.ghost_fill(self.q, self.ghost)
+
+    def step(self, dt=None, fused=False, reflux=True, auto_dt=False):
+        if dt is not None:
+            self.dt.fill_(dt)
+        if fused:
+            self.ctx.fused_step(self.q, self.qn, self.dt, self.numax)
+        else:
+            self.ctx.ghost_fill(self.q, self.ghost)
+            self.ctx.patch_step(self.q, self.ghost, self.qn, self.dt, self.numax)
+        if reflux:
+            self.ctx.reflux(self.q, self.qn, self.dt)
+        nu = float(self.numax.item())
+        used = float(self.dt.item())
+        if auto_dt:
+            self.ctx.next_dt(self.numax, self.dt, self.status)
+        else:
+            self.numax.zero_()
+        self.q, self.qn = self.qn, self.q
+        return nu, used
+
+    def conservation_sums(self):
+        self.ctx.conservation_sums(self.q, self.sums)
+        return self.sums.cpu().numpy().copy()
+
+    def tags(self, criterion, thr, lmin, lmax):
+        t = self.torch.zeros(self.ctx.num_patches(), dtype=self.torch.int8,
+                             device="cuda")
+        self.fill()
+        self.ctx.regrid_tags(self.q, self.ghost, criterion, thr, lmin, lmax, t)
+        return t.cpu().numpy()
+
+    def regrid(self, tags, lmin, lmax):
+        self.fill()
+        q_old, g_old = self.q, self.ghost
+        self.ctx.regrid_apply(tags, lmin, lmax)
+        self._alloc()
+        self.ctx.regrid_transfer(q_old, g_old, self.q)
+        self.torch.cuda.synchronize()
+
+
+def oracle_params(cfg):
+    phys = O.ADVECTION if cfg.physics == fcx.FCX_ADVECTION else O.SHALLOW
+    return O.params(cfg.m, phys, limiter=cfg.limiter, transverse=cfg.transverse,
+                    g=cfg.g, ax=cfg.ax, ay=cfg.ay)
+
+
+def smooth_sw_state(leaves, m, pl, seed):
+    rng = np.random.default_rng(seed)
+    c = rng.uniform(0.2, 0.8, 4)
+    def fn(x, y):
+        h = 1.0 + 0.4 * np.exp(-20 * ((x - c[0]) ** 2 + (y - c[1]) ** 2)) \
+            + 0.1 * np.sin(3 * x + 2 * y)
+        hu = 0.2 * np.sin(2 * np.pi * y + c[2])
+        hv = 0.15 * np.cos(2 * np.pi * x + c[3])
+        return np.stack([h, hu, hv], axis=1)
+    return I.state_from(leaves, m, fn, pl)
