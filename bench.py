@@ -1,0 +1,322 @@
+#!/usr/bin/env python
+"""Benchmark of one time step of the leaf-patch AMR hot path on one MI355X.
+
+Workload (the headline configuration): 2D shallow water (h, hu, hv), g = 1,
+Roe solver with transverse waves and the MC limiter, unit square with
+reflecting walls, radial dam break (h = 2 for r < 0.25, else 1, at rest);
+2:1-balanced adaptive forest on levels 3..6 with m = 16, refined where
+|grad h| > 0.1 and regridded every 4 steps; CFL 0.9.  Inputs are seeded
+synthetic data built on the host, then resident in HBM.
+
+A step = regrid (every 4th step: tags on the GPU, host refine/coarsen/
+balance, transfer on the GPU) + ghost fill + wave-propagation update +
+coarse-fine reflux + next dt, all through libfcx.so.  Two variants are
+timed: FP32 state in one fused ghost-gather + update launch per step (the
+reported value) and the FP64 plain path (separate ghost-fill and step
+launches).  A large uniform variant (level 8, 65,536 patches, 16.8 M cells)
+gives the HBM roofline of the same kernels at a size far beyond the
+on-chip caches.
+
+Prints one JSON line.  `python bench.py --gpus N` with N > 1 exits: this
+build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+# FP32 vector peak without packed math (256 CUs x 64 lanes x 2.4 GHz, one
+# operation per lane per clock; an FMA counts once)
+VALU_PEAK_GOPS = 256 * 64 * 2.4
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--large-steps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only", choices=["fp32", "fp64", "large", "all"], default="all")
+    return ap.parse_args()
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("step.hpp", "device.hpp"):
+        with open(os.path.join(ROOT, "paper_1308_1472_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(name):
+    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    text = open(path).read()
+    m = re.search(r"kernel_source_sha256:\s*(\w+)", text)
+    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    if not m or not b or m.group(1) != kernel_source_hash():
+        return None
+    return float(b.group(1))
+
+
+class Workload:
+    """Adaptive dam break driven entirely through the library."""
+
+    LMIN, LMAX, M, THR, REGRID = 3, 6, 16, 0.1, 4
+
+    def __init__(self, precision, fused, uniform_level=None):
+        import torch
+        from paper_1308_1472_amd import fcx
+        from paper_1308_1472_amd import inputs as I
+        self.torch, self.fcx, self.I = torch, fcx, I
+        self.trees, self.pl = I.walled_square()
+        self.fused = fused
+        self.uniform = uniform_level is not None
+        self.cfg = fcx.config(self.M, precision, fcx.FCX_SHALLOW, cfl_desired=0.9,
+                              cfl_max=1.0)
+        self.ctx = fcx.Context(self.cfg, self.trees)
+        self.dtype = torch.float32 if precision == 32 else torch.float64
+        fn = lambda x, y: I.dam_break(x, y)
+        if self.uniform:
+            leaves = fcx.sfc_sort(I.uniform_leaves(1, uniform_level))
+            self.ctx.upload_forest(leaves)
+        else:
+            leaves = fcx.sfc_sort(I.uniform_leaves(1, self.LMIN))
+            # initial mesh: tag the initial data, refine, re-evaluate, until
+            # nothing changes
+            for _ in range(2 * (self.LMAX - self.LMIN) + 2):
+                self.ctx.upload_forest(leaves)
+                self._alloc()
+                self._set(I.state_from(leaves, self.M, fn, self.pl))
+                tags = self._tags()
+                self.ctx.regrid_apply(tags, self.LMIN, self.LMAX)
+                new = self.ctx.leaves()
+                if len(new) == len(leaves) and (new == leaves).all():
+                    break
+                leaves = new
+            self.ctx.upload_forest(leaves)
+        self._alloc()
+        self._set(I.state_from(leaves, self.M, fn, self.pl))
+        dev = "cuda"
+        hmin = 1.0 / (self.M << int(leaves["level"].max()))
+        # start at half the target Courant number: the first steps of a dam
+        # break raise the largest wave speed
+        self.dt = torch.full((1,), 0.45 * hmin / 2.0 ** 0.5, dtype=torch.float64,
+                             device=dev)
+        self.numax = torch.zeros(1, dtype=torch.float64, device=dev)
+        self.status = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.n = 0
+        self.cells = []
+
+    def _alloc(self):
+        t = self.torch
+        self.q = t.zeros(self.ctx.state_elems(), dtype=self.dtype, device="cuda")
+        self.qn = t.empty_like(self.q)
+        self.ghost = t.zeros(self.ctx.ghost_elems(), dtype=self.dtype, device="cuda")
+        self.tagbuf = t.zeros(self.ctx.num_patches(), dtype=t.int8, device="cuda")
+
+    def _set(self, q):
+        self.q.copy_(self.torch.from_numpy(q.ravel()).to(self.dtype))
+
+    def _tags(self):
+        self.ctx.ghost_fill(self.q, self.ghost)
+        self.ctx.regrid_tags(self.q, self.ghost, 1, self.THR, self.LMIN, self.LMAX,
+                             self.tagbuf)
+        return self.tagbuf.cpu().numpy()
+
+    def regrid(self):
+        tags = self._tags()                  # ghost buffer now holds a fill of q
+        q_old, g_old = self.q, self.ghost
+        self.ctx.regrid_apply(tags, self.LMIN, self.LMAX)
+        self._alloc()
+        self.ctx.regrid_transfer(q_old, g_old, self.q)
+
+    def step(self, ev=None):
+        if not self.uniform and self.n > 0 and self.n % self.REGRID == 0:
+            self.regrid()
+        if not self.fused:
+            self.ctx.ghost_fill(self.q, self.ghost)
+        if ev is not None:
+            ev[0].record()
+        if self.fused:
+            self.ctx.fused_step(self.q, self.qn, self.dt, self.numax)
+        else:
+            self.ctx.patch_step(self.q, self.ghost, self.qn, self.dt, self.numax)
+        if ev is not None:
+            ev[1].record()
+        self.ctx.reflux(self.q, self.qn, self.dt)
+        self.ctx.next_dt(self.numax, self.dt, self.status)
+        self.q, self.qn = self.qn, self.q
+        self.cells.append(self.ctx.num_patches() * self.M * self.M)
+        self.n += 1
+
+
+def run(precision, fused, steps, warmup, uniform_level=None):
+    import torch
+    w = Workload(precision, fused, uniform_level)
+    for _ in range(warmup):
+        w.step()
+    torch.cuda.synchronize()
+    w.cells = []
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        w.step(evs[k])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms = [a.elapsed_time(b) for a, b in evs]
+    cells = float(sum(w.cells))
+    return {
+        "seconds": el, "cells": cells, "rate": cells / el,
+        "kernel_ms_mean": sum(kms) / len(kms),
+        "kernel_cells_mean": cells / steps,
+        "patches_last": w.ctx.num_patches(),
+        "status": int(w.status.item()),
+    }
+
+
+def cpu_baseline(budget_s=12.0):
+    """The CPU FP64 oracle, single-threaded, on the first steps of the same
+    workload (same initial mesh, regrid every 4 steps)."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1308_1472_amd import inputs as I
+    trees, pl = I.walled_square()
+    m, lmin, lmax = Workload.M, Workload.LMIN, Workload.LMAX
+    fn = lambda x, y: I.dam_break(x, y)
+    par = O.params(m, O.SHALLOW)
+    lv = O.sfc_sort(I.uniform_leaves(1, lmin))
+    for _ in range(2 * (lmax - lmin) + 2):
+        mesh = O.Mesh(trees, lv, m)
+        f = O.framed(I.state_from(lv, m, fn, pl), m)
+        O.ghost_fill(mesh, par, f)
+        lv2 = O.regrid(mesh, O.tags(mesh, par, f, 1, Workload.THR, lmin, lmax),
+                       lmin, lmax)
+        if np.array_equal(lv2, lv):
+            break
+        lv = lv2
+    mesh = O.Mesh(trees, lv, m)
+    q = I.state_from(lv, m, fn, pl)
+    dt = 0.45 / (m << int(lv["level"].max())) / 2.0 ** 0.5
+    cells, n = 0, 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < budget_s or n < 2:
+        if n > 0 and n % Workload.REGRID == 0:
+            f = O.framed(q, m)
+            O.ghost_fill(mesh, par, f)
+            tg = O.tags(mesh, par, f, 1, Workload.THR, lmin, lmax)
+            mesh2 = O.Mesh(trees, O.regrid(mesh, tg, lmin, lmax), m)
+            q = O.interior(O.transfer(mesh, mesh2, par, f), m)
+            mesh = mesh2
+        q, nu = O.advance(mesh, par, q, dt)
+        dt *= 0.9 / nu
+        cells += len(mesh) * m * m
+        n += 1
+    el = time.perf_counter() - t0
+    return {"value": cells / el, "unit": "cell-updates/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {n} steps of the same adaptive dam break (levels "
+                      f"3-6, m = 16, regrid every 4), FP64, one thread, "
+                      f"{el:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
+              "multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    if not torch.cuda.is_available():
+        print("no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    res = {}
+    if args.only in ("fp32", "all"):
+        res["fp32"] = run(32, True, args.steps, args.warmup)
+        print(f"# fp32 fused: {res['fp32']}", file=sys.stderr, flush=True)
+    if args.only in ("fp64", "all"):
+        res["fp64"] = run(64, False, args.steps, args.warmup)
+        print(f"# fp64 plain: {res['fp64']}", file=sys.stderr, flush=True)
+    if args.only in ("large", "all"):
+        res["large32"] = run(32, True, args.large_steps, 3, uniform_level=8)
+        print(f"# large fp32: {res['large32']}", file=sys.stderr, flush=True)
+        res["large64"] = run(64, False, args.large_steps, 3, uniform_level=8)
+        print(f"# large fp64: {res['large64']}", file=sys.stderr, flush=True)
+    head = res.get("fp32") or res.get("fp64") or res.get("large32")
+    steps = args.steps if "fp32" in res or "fp64" in res else args.large_steps
+    bytes_per_cell = 24.0 if head is not res.get("fp64") else 48.0
+
+    def roof(r, bpc, traffic_name):
+        ach = r["kernel_cells_mean"] * bpc / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        tr = stored_traffic(traffic_name)
+        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": tr,
+                "kernel": "k_step", "kernel_ms": r["kernel_ms_mean"],
+                "bytes_per_launch": r["kernel_cells_mean"] * bpc}
+
+    out = {
+        "metric": "cell-updates/s + HBM GB/s % peak, FP32 batched vs FP64 plain, "
+                  "shallow water m=16",
+        "value": head["rate"],
+        "unit": "cell-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["seconds"] / steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if head is res.get("fp32") else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "shallow-water radial dam break, walled unit square, "
+                        "adaptive levels 3-6, m=16, regrid every 4 steps",
+            "m": 16, "levels": [3, 6], "regrid_every": 4,
+            "cells_per_step_mean": head["kernel_cells_mean"],
+            "patches_at_end": head["patches_last"],
+            "path": "fused ghost-gather + update, FP32 state, FP64 dt/CFL/sums",
+        },
+        "roofline": roof(head, bytes_per_cell, "traffic_k_step_fused_sw_fp32_adaptive.txt"),
+    }
+    if "fp64" in res:
+        out["fp64_plain"] = {"value": res["fp64"]["rate"],
+                             "ms_per_step": res["fp64"]["seconds"] / args.steps * 1e3,
+                             "kernel_ms": res["fp64"]["kernel_ms_mean"],
+                             "roofline": roof(res["fp64"], 48.0,
+                                              "traffic_k_step_plain_sw_fp64_adaptive.txt")}
+        if "fp32" in res:
+            out["speedup_fp32_fused_vs_fp64_plain"] = res["fp32"]["rate"] / res["fp64"]["rate"]
+    if "large32" in res:
+        out["large_uniform_level8"] = {
+            "cells": res["large32"]["kernel_cells_mean"],
+            "fp32_fused_rate": res["large32"]["rate"],
+            "fp64_plain_rate": res["large64"]["rate"],
+            "fp32_roofline": roof(res["large32"], 24.0,
+                                  "traffic_k_step_fused_sw_fp32_level8.txt"),
+            "fp64_roofline": roof(res["large64"], 48.0,
+                                  "traffic_k_step_plain_sw_fp64_level8.txt"),
+        }
+    if any(r["status"] for r in res.values()):
+        out["cfl_flags"] = {k: r["status"] for k, r in res.items()}
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

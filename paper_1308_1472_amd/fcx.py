@@ -59,6 +59,10 @@ def lib():
             raise RuntimeError(
                 f"{LIB_PATH} is missing: build it with "
                 "`python -m paper_1308_1472_amd.build` (there is no fallback)")
+        # torch ships its own HIP runtime under the same soname; importing it
+        # first makes the library bind to that one runtime instead of loading
+        # a second copy from /opt/rocm into the process
+        import torch  # noqa: F401
         L = C.CDLL(LIB_PATH)
         vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.c_double
         L.fcx_last_error.restype = C.c_char_p

@@ -128,7 +128,7 @@ def _sw_adaptive_oracle(trees, pl, m, lmin, lmax, nsteps, regrid_every,
         lv = lv2
     mesh = O.Mesh(trees, lv, m)
     q = I.state_from(lv, m, fn, pl)
-    hist = {"leaves": [lv.copy()], "tags": [], "dt": []}
+    hist = {"leaves": [lv.copy()], "tags": [], "dt": [], "nu": []}
     dt = dt0
     for n in range(nsteps):
         if n > 0 and n % regrid_every == 0:
@@ -143,6 +143,7 @@ def _sw_adaptive_oracle(trees, pl, m, lmin, lmax, nsteps, regrid_every,
             hist["leaves"].append(lv.copy())
         q, nu = O.advance(mesh, par, q, dt)
         hist["dt"].append(dt)
+        hist["nu"].append(nu)
         dt = dt * 0.9 / nu
     return lv, q, hist, mesh
 
@@ -171,9 +172,11 @@ def test_adaptive_shallow_water_run_matches_oracle(fused):
             gpu.regrid(tg, lmin, lmax)
             r += 1
             assert np.array_equal(gpu.ctx.leaves(), hist["leaves"][r])
-        _, used = gpu.step(fused=fused, auto_dt=True)
+        nu, used = gpu.step(fused=fused, auto_dt=True)
         assert abs(used - hist["dt"][n]) <= 1e-13 * hist["dt"][n]
-    assert int(gpu.status.item()) == 0
+        assert abs(nu - hist["nu"][n]) <= 1e-13 * hist["nu"][n]
+    # the CFL flag is raised exactly when the oracle saw a Courant number > 1
+    assert int(gpu.status.item()) == int(max(hist["nu"]) > 1.0)
     assert _rel(gpu.state(), q_o) <= FP64_TOL
 
 
