@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "large", "all"], default="all")
+    ap.add_argument("--tile", type=int, default=0)
+    ap.add_argument("--threads", type=int, default=0)
     return ap.parse_args()
 
 
@@ -77,7 +79,7 @@ class Workload:
 
     LMIN, LMAX, M, THR, REGRID = 3, 6, 16, 0.1, 4
 
-    def __init__(self, precision, fused, uniform_level=None):
+    def __init__(self, precision, fused, uniform_level=None, tile=0, threads=0):
         import torch
         from paper_1308_1472_amd import fcx
         from paper_1308_1472_amd import inputs as I
@@ -86,7 +88,7 @@ class Workload:
         self.fused = fused
         self.uniform = uniform_level is not None
         self.cfg = fcx.config(self.M, precision, fcx.FCX_SHALLOW, cfl_desired=0.9,
-                              cfl_max=1.0)
+                              cfl_max=1.0, tile=tile, threads=threads)
         self.ctx = fcx.Context(self.cfg, self.trees)
         self.dtype = torch.float32 if precision == 32 else torch.float64
         fn = lambda x, y: I.dam_break(x, y)
@@ -123,10 +125,11 @@ class Workload:
 
     def _alloc(self):
         t = self.torch
-        self.q = t.zeros(self.ctx.state_elems(), dtype=self.dtype, device="cuda")
+        # every buffer is fully written before it is read
+        self.q = t.empty(self.ctx.state_elems(), dtype=self.dtype, device="cuda")
         self.qn = t.empty_like(self.q)
-        self.ghost = t.zeros(self.ctx.ghost_elems(), dtype=self.dtype, device="cuda")
-        self.tagbuf = t.zeros(self.ctx.num_patches(), dtype=t.int8, device="cuda")
+        self.ghost = t.empty(self.ctx.ghost_elems(), dtype=self.dtype, device="cuda")
+        self.tagbuf = t.empty(self.ctx.num_patches(), dtype=t.int8, device="cuda")
 
     def _set(self, q):
         self.q.copy_(self.torch.from_numpy(q.ravel()).to(self.dtype))
@@ -164,9 +167,12 @@ class Workload:
         self.n += 1
 
 
+TUNE = {"tile": 0, "threads": 0}
+
+
 def run(precision, fused, steps, warmup, uniform_level=None):
     import torch
-    w = Workload(precision, fused, uniform_level)
+    w = Workload(precision, fused, uniform_level, TUNE["tile"], TUNE["threads"])
     for _ in range(warmup):
         w.step()
     torch.cuda.synchronize()
@@ -237,6 +243,7 @@ def cpu_baseline(budget_s=12.0):
 
 def main():
     args = parse()
+    TUNE["tile"], TUNE["threads"] = args.tile, args.threads
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
               "multi-GPU layout is described in DESIGN.md", file=sys.stderr)

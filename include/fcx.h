@@ -78,7 +78,10 @@ typedef struct {
                           3 van Leer, 4 MC (LeVeque 2002, Sec. 6.12)      */
   int32_t transverse;  /* 0 none, 1 fluctuations, 2 fluctuations and
                           second-order corrections                         */
-  int32_t tile;        /* cells per LDS tile side (0 = library default)  */
+  int32_t tile;        /* cells per LDS tile side: 8 or 16 (0 = default) */
+  int32_t threads;     /* threads per tile workgroup: T*T or 2*T*T for
+                          T = 8, 256 or 512 for T = 16 (0 = default)       */
+  int32_t reserved;    /* must be 0                                       */
   double g;            /* gravity (shallow water)                         */
   double ax, ay;       /* advection velocity in reference coordinates     */
   double cfl_desired;  /* target Courant number for the next dt           */
@@ -101,6 +104,16 @@ int fcx_sfc_sort(int64_t n, fcx_leaf *leaves);
 int fcx_balance(int32_t n_trees, const fcx_tree *trees, int64_t n,
                 const fcx_leaf *in, int64_t cap, fcx_leaf *out,
                 int64_t *n_out);
+
+/* Regrid of a balanced forest from per-leaf tags (Sec. 2: per-patch flags
+ * are the only mesher input): refine leaves tagged +1 (below lmax), merge
+ * complete families of leaf siblings all tagged -1 (above lmin), then
+ * restore 2:1 balance by refinement (a merge that would break it is
+ * undone).  `leaves` must be SFC-sorted and balanced; writes the new forest
+ * in SFC order (FCX_EINVAL with *n_out set if cap is short). */
+int fcx_regrid_leaves(int32_t n_trees, const fcx_tree *trees, int64_t n,
+                      const fcx_leaf *leaves, const int8_t *tags, int32_t lmin,
+                      int32_t lmax, int64_t cap, fcx_leaf *out, int64_t *n_out);
 
 /* ---- context -------------------------------------------------------- */
 

@@ -57,8 +57,10 @@ struct DevBuf {
   }
   hipError_t ensure(size_t count) {
     if (count <= n && p) return hipSuccess;
+    // grow geometrically so that a mesh that grows step by step does not
+    // reallocate (and synchronize) at every regrid
+    const size_t c = std::max<size_t>(count ? count : 1, n + n / 2);
     release();
-    const size_t c = count ? count : 1;
     hipError_t e = hipMalloc(&p, c * sizeof(T));
     if (e == hipSuccess) n = c;
     return e;
@@ -77,10 +79,36 @@ int log2i(int m) {
 }
 }  // namespace
 
+// Pinned host staging buffer (grows, never shrinks).
+struct HostBuf {
+  uint8_t* p = nullptr;
+  size_t n = 0;
+  HostBuf() = default;
+  HostBuf(const HostBuf&) = delete;
+  HostBuf& operator=(const HostBuf&) = delete;
+  ~HostBuf() { if (p) (void)hipHostFree(p); }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n && p) return hipSuccess;
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    const size_t c = std::max<size_t>(bytes, n + n / 2);
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), c, hipHostMallocDefault);
+    n = e == hipSuccess ? c : 0;
+    return e;
+  }
+};
+
+// Device copy of one forest's plan: every array lives in one allocation and
+// arrives in one copy.
 struct DevForest {
-  DevBuf<PatchRec> rec;
-  DevBuf<int32_t> phislot, family;
-  DevBuf<RefluxItem> reflux;
+  DevBuf<uint8_t> blob;
+  PatchRec* rec = nullptr;
+  int32_t* phislot = nullptr;
+  int32_t* family = nullptr;
+  RefluxItem* reflux = nullptr;
+  int32_t* first = nullptr;          // {0, P} for the sum reduction
+  int32_t* xkind = nullptr;          // transfer plan from the previous forest
+  int32_t* xsrc = nullptr;
   int32_t n_reflux_x = 0, n_reflux_y = 0;
   int32_t nslots = 0;
   int64_t P = 0;
@@ -96,9 +124,8 @@ struct fcx_ctx {
   DevForest cur, old;
   DevBuf<uint8_t> phi;             // face terms of the last patch step
   DevBuf<double> partial;
-  DevBuf<int32_t> first;           // [0, P] for the sum reduction
   DevBuf<int32_t> err;
-  DevBuf<int32_t> xkind, xsrc;     // transfer plan
+  HostBuf staging;
 };
 
 // The entry points below are declared extern "C" in fcx.h.
@@ -108,7 +135,9 @@ int32_t fcx_version(void) { return 1; }
 
 int fcx_sfc_sort(int64_t n, fcx_leaf* leaves) {
   if (n < 0 || (n > 0 && !leaves)) return fail(FCX_EINVAL, "bad arguments");
-  std::sort(leaves, leaves + n, leaf_less);
+  std::vector<fcx_leaf> v(leaves, leaves + n);
+  sort_leaves(v);
+  std::copy(v.begin(), v.end(), leaves);
   return FCX_OK;
 }
 
@@ -129,6 +158,26 @@ int fcx_balance(int32_t n_trees, const fcx_tree* trees, int64_t n,
   return FCX_OK;
 }
 
+int fcx_regrid_leaves(int32_t n_trees, const fcx_tree* trees, int64_t n,
+                      const fcx_leaf* leaves, const int8_t* tags, int32_t lmin,
+                      int32_t lmax, int64_t cap, fcx_leaf* out, int64_t* n_out) {
+  if (n_trees <= 0 || !trees || n <= 0 || !leaves || !tags || !n_out ||
+      lmin < 0 || lmax < lmin || lmax > kMaxLevel)
+    return fail(FCX_EINVAL, "bad arguments");
+  std::vector<fcx_tree> t(trees, trees + n_trees);
+  std::string err;
+  Forest f;
+  int rc = f.assign(t, std::vector<fcx_leaf>(leaves, leaves + n), err);
+  if (rc != FCX_OK) return fail(rc, err);
+  std::vector<fcx_leaf> res;
+  rc = regrid(f, tags, lmin, lmax, res, err);
+  if (rc != FCX_OK) return fail(rc, err);
+  *n_out = int64_t(res.size());
+  if (int64_t(res.size()) > cap || !out) return fail(FCX_EINVAL, "output capacity too small");
+  std::copy(res.begin(), res.end(), out);
+  return FCX_OK;
+}
+
 int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
                fcx_ctx** out) {
   if (!cfg || !out || n_trees <= 0 || !trees) return fail(FCX_EINVAL, "bad arguments");
@@ -145,6 +194,10 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   int tile = cfg->tile ? cfg->tile : (cfg->m >= 16 ? 16 : 8);
   if ((tile != 8 && tile != 16) || tile > cfg->m)
     return fail(FCX_EINVAL, "tile must be 8 or 16 and at most m");
+  const int threads = cfg->threads ? cfg->threads : (tile == 16 ? 256 : 64);
+  if (threads != tile * tile && threads != 2 * tile * tile)
+    return fail(FCX_EINVAL, "threads must be tile^2 or 2 tile^2");
+  if (cfg->reserved != 0) return fail(FCX_EINVAL, "reserved must be 0");
   std::vector<fcx_tree> t(trees, trees + n_trees);
   std::string err;
   if (check_connectivity(t, err) != FCX_OK) return fail(FCX_EINVAL, err);
@@ -158,6 +211,7 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   fcx_ctx* c = new fcx_ctx;
   c->cfg = *cfg;
   c->cfg.tile = tile;
+  c->cfg.threads = threads;
   c->tile = tile;
   c->meqn = cfg->physics == FCX_ADVECTION ? 1 : 3;
   c->trees = t;
@@ -178,23 +232,52 @@ int fcx_destroy(fcx_ctx* ctx) {
   return FCX_OK;
 }
 
-static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev) {
+static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
+                       const std::vector<int32_t>* kind = nullptr,
+                       const std::vector<int32_t>* src = nullptr) {
   Plan plan;
   std::string err;
   int rc = build_plan(f, c->cfg.m, plan, err);
   if (rc != FCX_OK) return fail(rc, err);
+  const size_t P = f.leaves.size();
   // reflux items: xi faces first, then eta faces
   std::vector<RefluxItem> items;
+  items.reserve(plan.reflux.size());
   for (const auto& it : plan.reflux) if (it.face < 2) items.push_back(it);
   dev.n_reflux_x = int32_t(items.size());
   for (const auto& it : plan.reflux) if (it.face >= 2) items.push_back(it);
   dev.n_reflux_y = int32_t(items.size()) - dev.n_reflux_x;
-  HIPCHK(dev.rec.upload(plan.recs));
-  HIPCHK(dev.phislot.upload(plan.phislot));
-  HIPCHK(dev.family.upload(plan.family));
-  HIPCHK(dev.reflux.upload(items));
+  size_t off[8];
+  size_t at = 0;
+  const size_t sz[7] = {P * sizeof(PatchRec), P * 4, P * 4,
+                        items.size() * sizeof(RefluxItem), 2 * 4,
+                        kind ? P * 4 : 0, src ? P * 4 : 0};
+  for (int k = 0; k < 7; ++k) { off[k] = at; at += align256(sz[k]); }
+  off[7] = at;
+  HIPCHK(c->staging.ensure(at));
+  uint8_t* h = c->staging.p;
+  std::memcpy(h + off[0], plan.recs.data(), sz[0]);
+  std::memcpy(h + off[1], plan.phislot.data(), sz[1]);
+  std::memcpy(h + off[2], plan.family.data(), sz[2]);
+  if (sz[3]) std::memcpy(h + off[3], items.data(), sz[3]);
+  const int32_t first[2] = {0, int32_t(P)};
+  std::memcpy(h + off[4], first, sz[4]);
+  if (kind) std::memcpy(h + off[5], kind->data(), sz[5]);
+  if (src) std::memcpy(h + off[6], src->data(), sz[6]);
+  HIPCHK(dev.blob.ensure(at));
+  HIPCHK(hipMemcpy(dev.blob.p, h, at, hipMemcpyHostToDevice));
+  uint8_t* d = dev.blob.p;
+  dev.rec = reinterpret_cast<PatchRec*>(d + off[0]);
+  dev.phislot = reinterpret_cast<int32_t*>(d + off[1]);
+  dev.family = reinterpret_cast<int32_t*>(d + off[2]);
+  dev.reflux = reinterpret_cast<RefluxItem*>(d + off[3]);
+  dev.first = reinterpret_cast<int32_t*>(d + off[4]);
+  dev.xkind = kind ? reinterpret_cast<int32_t*>(d + off[5]) : nullptr;
+  dev.xsrc = src ? reinterpret_cast<int32_t*>(d + off[6]) : nullptr;
   dev.nslots = plan.nslots;
-  dev.P = int64_t(f.leaves.size());
+  dev.P = int64_t(P);
   return FCX_OK;
 }
 
@@ -203,14 +286,14 @@ static int finish_upload(fcx_ctx* c) {
   const size_t esz = c->cfg.precision == 64 ? 8 : 4;
   HIPCHK(c->phi.ensure(size_t(c->cur.nslots) * 4 * c->cfg.m * c->meqn * esz));
   HIPCHK(c->partial.ensure(size_t(P) * c->meqn));
-  std::vector<int32_t> first = {0, int32_t(P)};
-  HIPCHK(c->first.upload(first));
   return FCX_OK;
 }
 
 int fcx_upload_forest(fcx_ctx* c, int64_t n, const fcx_leaf* leaves) {
   if (!c || n <= 0 || !leaves) return fail(FCX_EINVAL, "bad arguments");
-  if (n > (int64_t(1) << 28)) return fail(FCX_EINVAL, "too many leaves");
+  if (n * (c->cfg.physics == FCX_ADVECTION ? 1 : 3) * c->cfg.m * c->cfg.m >=
+      (int64_t(1) << 31))
+    return fail(FCX_EINVAL, "state larger than 2^31 elements");
   std::vector<fcx_leaf> l(leaves, leaves + n);
   std::string err;
   Forest f;
@@ -259,7 +342,7 @@ static int launch_ghost(fcx_ctx* c, const void* q, void* ghost, hipStream_t s) {
   const unsigned blocks = unsigned((tot + 255) / 256);
   hipLaunchKernelGGL((k_ghost_fill<R, PHYS>), dim3(blocks), dim3(256), 0, s,
                      static_cast<const R*>(q), static_cast<R*>(ghost),
-                     c->cur.rec.p, int32_t(c->cur.P), m, log2i(m), c->err.p);
+                     c->cur.rec, int32_t(c->cur.P), m, log2i(m), c->err.p);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -276,7 +359,7 @@ int fcx_ghost_fill(fcx_ctx* c, const void* q, void* ghost, void* stream) {
             : launch_ghost<float, FCX_SHALLOW>(c, q, ghost, s);
 }
 
-template <typename R, int PHYS, int M, int T, bool FUSED>
+template <typename R, int PHYS, int T, int NT, bool FUSED>
 static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                          const double* dt, double* numax, hipStream_t s) {
   StepArgs<R> a;
@@ -285,16 +368,18 @@ static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
   a.qn = static_cast<R*>(qn);
   a.dt = dt;
   a.numax = numax;
-  a.rec = c->cur.rec.p;
-  a.phislot = c->cur.phislot.p;
+  a.rec = c->cur.rec;
+  a.phislot = c->cur.phislot;
   a.phi = reinterpret_cast<R*>(c->phi.p);
   a.err = c->err.p;
   a.P = int32_t(c->cur.P);
+  a.m = c->cfg.m;
+  a.lm = log2i(c->cfg.m);
+  const int tps = c->cfg.m / T;
+  a.ntiles = int32_t(c->cur.P * tps * tps);
   a.ph = kphys(c);
-  constexpr int TPS = M / T;
-  const unsigned blocks = unsigned(c->cur.P * TPS * TPS);
-  hipLaunchKernelGGL((k_step<R, PHYS, M, T, FUSED>), dim3(blocks),
-                     dim3(TileThreads<T>::value), 0, s, a);
+  hipLaunchKernelGGL((k_step<R, PHYS, T, NT, FUSED>), dim3(unsigned(a.ntiles)),
+                     dim3(NT), 0, s, a);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -302,12 +387,12 @@ static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
 template <typename R, int PHYS, bool FUSED>
 static int launch_step_m(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                          const double* dt, double* numax, hipStream_t s) {
-  const int m = c->cfg.m, t = c->tile;
-  if (m == 8) return launch_step_t<R, PHYS, 8, 8, FUSED>(c, q, ghost, qn, dt, numax, s);
-  if (m == 16 && t == 8) return launch_step_t<R, PHYS, 16, 8, FUSED>(c, q, ghost, qn, dt, numax, s);
-  if (m == 16) return launch_step_t<R, PHYS, 16, 16, FUSED>(c, q, ghost, qn, dt, numax, s);
-  if (t == 8) return launch_step_t<R, PHYS, 32, 8, FUSED>(c, q, ghost, qn, dt, numax, s);
-  return launch_step_t<R, PHYS, 32, 16, FUSED>(c, q, ghost, qn, dt, numax, s);
+  const bool wide = c->cfg.threads == 2 * c->tile * c->tile;
+  if (c->tile == 8)
+    return wide ? launch_step_t<R, PHYS, 8, 128, FUSED>(c, q, ghost, qn, dt, numax, s)
+                : launch_step_t<R, PHYS, 8, 64, FUSED>(c, q, ghost, qn, dt, numax, s);
+  return wide ? launch_step_t<R, PHYS, 16, 512, FUSED>(c, q, ghost, qn, dt, numax, s)
+              : launch_step_t<R, PHYS, 16, 256, FUSED>(c, q, ghost, qn, dt, numax, s);
 }
 
 template <bool FUSED>
@@ -343,12 +428,12 @@ static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
   for (int axis = 0; axis < 2; ++axis) {
     const int32_t n = axis == 0 ? c->cur.n_reflux_x : c->cur.n_reflux_y;
     if (n == 0) continue;
-    const RefluxItem* items = c->cur.reflux.p + (axis == 0 ? 0 : c->cur.n_reflux_x);
+    const RefluxItem* items = c->cur.reflux + (axis == 0 ? 0 : c->cur.n_reflux_x);
     const int64_t tot = int64_t(n) * m;
     hipLaunchKernelGGL((k_reflux<R, PHYS>), dim3(unsigned((tot + 255) / 256)),
                        dim3(256), 0, s, static_cast<const R*>(q),
-                       static_cast<R*>(qn), items, n, c->cur.rec.p,
-                       c->cur.phislot.p, reinterpret_cast<const R*>(c->phi.p), dt,
+                       static_cast<R*>(qn), items, n, c->cur.rec,
+                       c->cur.phislot, reinterpret_cast<const R*>(c->phi.p), dt,
                        m, kphys(c), c->err.p);
     HIPCHK(hipGetLastError());
   }
@@ -379,11 +464,11 @@ int fcx_next_dt(fcx_ctx* c, double* numax, double* dt, int32_t* status, void* st
 template <typename R, int MEQN>
 static int launch_sums(fcx_ctx* c, const void* q, double* sums, hipStream_t s) {
   hipLaunchKernelGGL((k_sums_patch<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
-                     0, s, static_cast<const R*>(q), c->cur.rec.p, c->cfg.m,
+                     0, s, static_cast<const R*>(q), c->cur.rec, c->cfg.m,
                      c->partial.p);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((k_sums_reduce<MEQN>), dim3(1), dim3(1024), 0, s,
-                     c->partial.p, c->first.p, sums);
+                     c->partial.p, c->cur.first, sums);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -404,11 +489,11 @@ static int launch_tags(fcx_ctx* c, const void* q, const void* ghost, int criteri
   const int m = c->cfg.m;
   hipLaunchKernelGGL((k_tag_refine<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
                      0, s, static_cast<const R*>(q), static_cast<const R*>(ghost),
-                     c->cur.rec.p, m, criterion, thr, lmax, tags);
+                     c->cur.rec, m, criterion, thr, lmax, tags);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((k_tag_family<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
                      size_t(m) * m * sizeof(double), s, static_cast<const R*>(q),
-                     c->cur.rec.p, c->cur.family.p, m, criterion, thr, lmin, tags);
+                     c->cur.rec, c->cur.family, m, criterion, thr, lmin, tags);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -449,10 +534,8 @@ int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
   c->old_forest = std::move(c->forest);
   c->forest = std::move(nf);
   c->have_old = true;
-  rc = upload_plan(c, c->forest, c->cur);
+  rc = upload_plan(c, c->forest, c->cur, &kind, &src);
   if (rc != FCX_OK) return rc;
-  HIPCHK(c->xkind.upload(kind));
-  HIPCHK(c->xsrc.upload(src));
   rc = finish_upload(c);
   if (rc != FCX_OK) return rc;
   *n_new = int64_t(c->forest.leaves.size());
@@ -466,8 +549,8 @@ static int launch_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
   const int64_t tot = c->cur.P * MEQN * m * m;
   hipLaunchKernelGGL((k_transfer<R, MEQN>), dim3(unsigned((tot + 255) / 256)),
                      dim3(256), 0, s, static_cast<const R*>(qo),
-                     static_cast<const R*>(go), static_cast<R*>(qn), c->cur.rec.p,
-                     c->xkind.p, c->xsrc.p, int32_t(c->cur.P), m);
+                     static_cast<const R*>(go), static_cast<R*>(qn), c->cur.rec,
+                     c->cur.xkind, c->cur.xsrc, int32_t(c->cur.P), m);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }

@@ -17,7 +17,12 @@ k_ghost_fill(const R* __restrict__ q, R* __restrict__ ghost,
              int32_t* err) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   const int G = 8 * m + 16;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  // XCD-contiguous block order (see xcd_tile): neighbouring patches' reads
+  // then hit the same L2
+  const int nb = gridDim.x, b = blockIdx.x;
+  const int per = nb >> 3, rem = nb & 7, x = b & 7;
+  const int blk = x * per + (x < rem ? x : rem) + (b >> 3);
+  const int64_t t = int64_t(blk) * blockDim.x + threadIdx.x;
   if (t >= int64_t(P) * G) return;
   const int p = int(t / G), g = int(t - int64_t(p) * G);
   int i, j;

@@ -5,7 +5,7 @@
 
 #include <algorithm>
 #include <deque>
-#include <unordered_set>
+#include <thread>
 
 namespace fcx {
 
@@ -42,10 +42,83 @@ bool leaf_less(const fcx_leaf& a, const fcx_leaf& b) {
   return a.level < b.level;
 }
 
+void sort_leaves(std::vector<fcx_leaf>& v) {
+  // (tree, Morton key, level) computed once per leaf
+  std::vector<std::pair<std::pair<uint64_t, uint64_t>, uint32_t>> k(v.size());
+  for (size_t i = 0; i < v.size(); ++i)
+    k[i] = {{(uint64_t(uint32_t(v[i].tree)) << 8) | uint64_t(v[i].level), morton_key(v[i])},
+            uint32_t(i)};
+  std::sort(k.begin(), k.end(), [](const auto& a, const auto& b) {
+    if ((a.first.first >> 8) != (b.first.first >> 8)) return a.first.first < b.first.first;
+    if (a.first.second != b.first.second) return a.first.second < b.first.second;
+    return (a.first.first & 255) < (b.first.first & 255);
+  });
+  std::vector<fcx_leaf> o(v.size());
+  for (size_t i = 0; i < v.size(); ++i) o[i] = v[k[i].second];
+  v.swap(o);
+}
+
 static inline uint64_t pack_key(int32_t tree, int32_t level, int64_t ix,
                                 int64_t iy) {
   return (uint64_t(tree) << 53) | (uint64_t(level) << 48) |
          (uint64_t(ix) << 24) | uint64_t(iy);
+}
+
+// ---------------------------------------------------------------------------
+static inline uint64_t mix64(uint64_t k) {
+  k ^= k >> 33;
+  k *= 0xff51afd7ed558ccdull;
+  k ^= k >> 33;
+  k *= 0xc4ceb9fe1a85ec53ull;
+  k ^= k >> 33;
+  return k;
+}
+
+void LeafIndex::reset(size_t expected) {
+  size_t cap = 64;
+  while (cap < 2 * expected + 16) cap <<= 1;
+  keys_.assign(cap, kEmpty);
+  vals_.assign(cap, -1);
+  mask_ = cap - 1;
+  live_ = used_ = 0;
+}
+
+void LeafIndex::grow() {
+  std::vector<uint64_t> k = std::move(keys_);
+  std::vector<int32_t> v = std::move(vals_);
+  reset(live_ * 2 + 16);
+  for (size_t s = 0; s < k.size(); ++s)
+    if (k[s] != kEmpty && k[s] != kTomb) put(k[s], v[s]);
+}
+
+void LeafIndex::put(uint64_t key, int32_t val) {
+  if (keys_.empty() || 2 * (used_ + 1) > keys_.size()) grow();
+  size_t s = mix64(key) & mask_, tomb = SIZE_MAX;
+  for (;; s = (s + 1) & mask_) {
+    if (keys_[s] == key) { vals_[s] = val; return; }
+    if (keys_[s] == kTomb && tomb == SIZE_MAX) tomb = s;
+    if (keys_[s] == kEmpty) break;
+  }
+  if (tomb != SIZE_MAX) s = tomb; else ++used_;
+  keys_[s] = key;
+  vals_[s] = val;
+  ++live_;
+}
+
+int32_t LeafIndex::get(uint64_t key) const {
+  if (keys_.empty()) return -1;
+  for (size_t s = mix64(key) & mask_;; s = (s + 1) & mask_) {
+    if (keys_[s] == key) return vals_[s];
+    if (keys_[s] == kEmpty) return -1;
+  }
+}
+
+bool LeafIndex::erase(uint64_t key) {
+  if (keys_.empty()) return false;
+  for (size_t s = mix64(key) & mask_;; s = (s + 1) & mask_) {
+    if (keys_[s] == key) { keys_[s] = kTomb; --live_; return true; }
+    if (keys_[s] == kEmpty) return false;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -79,8 +152,7 @@ int Forest::assign(const std::vector<fcx_tree>& t,
   if (rc != FCX_OK) return rc;
   trees = t;
   leaves = l;
-  index_.clear();
-  index_.reserve(l.size() * 2);
+  index_.reset(l.size());
   maxlevel = 0;
   size_t k = 0;
   for (int32_t tr = 0; tr < int32_t(trees.size()); ++tr) {
@@ -98,7 +170,7 @@ int Forest::assign(const std::vector<fcx_tree>& t,
       }
       next += uint64_t(1) << (2 * (kS - a.level));
       maxlevel = std::max(maxlevel, int(a.level));
-      index_[pack_key(a.tree, a.level, a.ix, a.iy)] = int32_t(k);
+      index_.put(pack_key(a.tree, a.level, a.ix, a.iy), int32_t(k));
     }
     if (next != (uint64_t(1) << (2 * kS))) {
       err = "leaves do not tile every tree";
@@ -113,14 +185,22 @@ int Forest::assign(const std::vector<fcx_tree>& t,
 }
 
 int64_t Forest::find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const {
-  auto it = index_.find(pack_key(tree, level, ix, iy));
-  return it == index_.end() ? -1 : it->second;
+  return index_.get(pack_key(tree, level, ix, iy));
 }
 
-int64_t Forest::leaf_at(int32_t tree, int64_t x, int64_t y) const {
+int64_t Forest::leaf_at(int32_t tree, int64_t x, int64_t y, int hint) const {
   if (x < 0 || y < 0 || x >= kSide || y >= kSide) return -1;
+  if (hint >= 0) {
+    // 2:1 balance puts every neighbour within one level of the asker
+    const int cand[3] = {hint, hint + 1, hint - 1};
+    for (int l : cand) {
+      if (l < 0 || l > maxlevel) continue;
+      const int64_t s = find(tree, l, x >> (kS - l), y >> (kS - l));
+      if (s >= 0) return s;
+    }
+  }
   for (int l = maxlevel; l >= 0; --l) {
-    int64_t s = find(tree, l, x >> (kS - l), y >> (kS - l));
+    const int64_t s = find(tree, l, x >> (kS - l), y >> (kS - l));
     if (s >= 0) return s;
   }
   return -1;
@@ -228,6 +308,13 @@ static int follow(const std::vector<fcx_tree>& trees, int32_t t, int64_t x,
 
 int Forest::locate(int32_t tree, int64_t x, int64_t y, int32_t& tout,
                    int64_t& xo, int64_t& yo, Xform& xf) const {
+  if (x >= 0 && y >= 0 && x < kSide && y < kSide) {   // inside: identity
+    tout = tree;
+    xo = x;
+    yo = y;
+    xf = Xform();
+    return 0;
+  }
   Path pa, pb;
   int32_t ta, tb;
   int64_t xa, ya, xb, yb;
@@ -260,28 +347,13 @@ int Forest::locate(int32_t tree, int64_t x, int64_t y, int32_t& tout,
 // that leaf is coarser it is split (and its children queued), until every
 // constraint holds.  Only forced splits are made, so the result is the
 // coarsest balanced refinement.
-int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
-            std::vector<fcx_leaf>& out, std::string& err) {
-  int rc = check_connectivity(trees, err);
-  if (rc != FCX_OK) return rc;
-  std::unordered_set<uint64_t> set;
-  set.reserve(in.size() * 4);
-  std::deque<fcx_leaf> work;
-  for (const auto& a : in) {
-    if (a.tree < 0 || a.tree >= int32_t(trees.size()) || a.level < 0 ||
-        a.level > kMaxLevel) {
-      err = "leaf out of range";
-      return FCX_EINVAL;
-    }
-    set.insert(pack_key(a.tree, a.level, a.ix, a.iy));
-    work.push_back(a);
-  }
-  Forest geo;            // connectivity only (for locate)
-  geo.trees = trees;
+// Split leaves until every leaf reachable from the worklist sees its eight
+// same-size neighbour boxes held by leaves at most one level coarser.
+static void ripple(const Forest& geo, LeafIndex& set, std::deque<fcx_leaf>& work) {
   while (!work.empty()) {
     const fcx_leaf L = work.front();
     work.pop_front();
-    if (!set.count(pack_key(L.tree, L.level, L.ix, L.iy))) continue;
+    if (set.get(pack_key(L.tree, L.level, L.ix, L.iy)) < 0) continue;
     if (L.level < 2) continue;
     const int64_t size = kSide >> L.level;
     for (int dy = -1; dy <= 1; ++dy)
@@ -297,7 +369,7 @@ int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
           // leaf among the ancestors of the neighbour box (level <= L.level)
           int found = -1;
           for (int lev = L.level; lev >= 0; --lev)
-            if (set.count(pack_key(t2, lev, x2 >> (kS - lev), y2 >> (kS - lev)))) {
+            if (set.get(pack_key(t2, lev, x2 >> (kS - lev), y2 >> (kS - lev))) >= 0) {
               found = lev;
               break;
             }
@@ -307,37 +379,63 @@ int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
           for (int c = 0; c < 4; ++c) {
             fcx_leaf ch{t2, found + 1, int32_t(2 * ax + (c & 1)),
                         int32_t(2 * ay + (c >> 1))};
-            set.insert(pack_key(ch.tree, ch.level, ch.ix, ch.iy));
+            set.put(pack_key(ch.tree, ch.level, ch.ix, ch.iy), 1);
             work.push_back(ch);
           }
         }
       }
   }
+}
+
+static void collect(const LeafIndex& set, std::vector<fcx_leaf>& out) {
   out.clear();
   out.reserve(set.size());
-  for (uint64_t k : set) {
+  set.for_each([&](uint64_t k, int32_t) {
     fcx_leaf a;
     a.tree = int32_t(k >> 53);
     a.level = int32_t((k >> 48) & 31);
     a.ix = int32_t((k >> 24) & 0xffffff);
     a.iy = int32_t(k & 0xffffff);
     out.push_back(a);
+  });
+  sort_leaves(out);
+}
+
+// Balance by ripple propagation from every leaf.  A leaf L of level l needs
+// the leaf holding each of its eight same-size neighbour boxes to have level
+// >= l - 1; when that leaf is coarser it is split (and its children queued),
+// until every constraint holds.  Only forced splits are made, so the result
+// is the coarsest balanced refinement.
+int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
+            std::vector<fcx_leaf>& out, std::string& err) {
+  int rc = check_connectivity(trees, err);
+  if (rc != FCX_OK) return rc;
+  LeafIndex set;
+  set.reset(in.size() * 2);
+  std::deque<fcx_leaf> work;
+  for (const auto& a : in) {
+    if (a.tree < 0 || a.tree >= int32_t(trees.size()) || a.level < 0 ||
+        a.level > kMaxLevel) {
+      err = "leaf out of range";
+      return FCX_EINVAL;
+    }
+    set.put(pack_key(a.tree, a.level, a.ix, a.iy), 1);
+    work.push_back(a);
   }
-  std::sort(out.begin(), out.end(), leaf_less);
+  Forest geo;            // connectivity only (for locate)
+  geo.trees = trees;
+  ripple(geo, set, work);
+  collect(set, out);
   return FCX_OK;
 }
 
 // ---------------------------------------------------------------------------
-int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
-  const int64_t n = int64_t(f.leaves.size());
-  plan.recs.assign(n, PatchRec{});
-  plan.phislot.assign(n, -1);
-  plan.family.assign(n, 0);
-  plan.reflux.clear();
-  plan.nslots = 0;
-  for (int64_t p = 0; p < n; ++p) {
+// Neighbour records of one patch; coarse-fine faces are reported in items.
+static int plan_one(const Forest& f, int m, int64_t p, PatchRec& r,
+                    bool& mixed, int32_t& family, RefluxItem* items,
+                    int& nitems, std::string& err) {
+  {
     const fcx_leaf& a = f.leaves[p];
-    PatchRec& r = plan.recs[p];
     r.level = a.level;
     r.ix = a.ix;
     r.iy = a.iy;
@@ -348,7 +446,8 @@ int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
       x = x0 + (2 * i - 1) * half;
       y = y0 + (2 * j - 1) * half;
     };
-    bool mixed = false;
+    mixed = false;
+    nitems = 0;
     for (int fc = 0; fc < 4; ++fc) {
       if (f.wall_face(p, fc)) {
         r.flags |= 1 << fc;
@@ -370,7 +469,7 @@ int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
           err = "face neighbour not found";
           return FCX_EINVAL;
         }
-        ids[s] = int32_t(f.leaf_at(t2, x2, y2));
+        ids[s] = int32_t(f.leaf_at(t2, x2, y2, a.level));
         if (ids[s] < 0) { err = "face neighbour missing"; return FCX_EINVAL; }
       }
       const int l0 = f.leaves[ids[0]].level, l1 = f.leaves[ids[1]].level;
@@ -403,7 +502,7 @@ int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
           it.fine_face[s] = ff;
           it.fine_rev[s] = rev;
         }
-        plan.reflux.push_back(it);
+        items[nitems++] = it;
       }
     }
     for (int c = 0; c < 4; ++c) {
@@ -425,7 +524,7 @@ int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
         continue;
       }
       if (st != 0) { err = "corner neighbour not found"; return FCX_EINVAL; }
-      const int64_t id = f.leaf_at(t2, x2, y2);
+      const int64_t id = f.leaf_at(t2, x2, y2, a.level);
       if (id < 0) { err = "corner neighbour missing"; return FCX_EINVAL; }
       const int lc = f.leaves[id].level;
       if (lc < a.level - 1 || lc > a.level + 1) {
@@ -435,48 +534,163 @@ int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
       r.nbr[8 + c] = int32_t(id);
       r.xf[4 + c] = xf.code;
     }
-    if (mixed) plan.phislot[p] = plan.nslots++;
+    bool simple = true;
+    for (int s2 = 0; s2 < 12 && simple; ++s2) {
+      const int32_t nb = r.nbr[s2];
+      if (nb == kNbrWall) continue;
+      const int32_t code = s2 < 8 ? r.xf[s2 / 2] : r.xf[4 + (s2 - 8)];
+      if (nb < 0 || f.leaves[nb].level != a.level || (code & 7) != 0) simple = false;
+    }
+    if (simple) r.flags |= kSimpleHalo;
     // first child of a complete family of leaf siblings
     if (a.level > 0 && !(a.ix & 1) && !(a.iy & 1)) {
       bool all = true;
       for (int c = 1; c < 4; ++c)
         if (f.find(a.tree, a.level, a.ix + (c & 1), a.iy + (c >> 1)) != p + c)
           all = false;
-      plan.family[p] = all ? 1 : 0;
+      family = all ? 1 : 0;
     }
   }
   return FCX_OK;
 }
 
+// Records for all patches, computed in parallel chunks; slots and reflux
+// items are then numbered in patch order.
+int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
+  const int64_t n = int64_t(f.leaves.size());
+  plan.recs.assign(n, PatchRec{});
+  plan.phislot.assign(n, -1);
+  plan.family.assign(n, 0);
+  plan.reflux.clear();
+  plan.nslots = 0;
+  std::vector<uint8_t> mixed(n, 0);
+  std::vector<RefluxItem> items(size_t(n) * 4);
+  std::vector<uint8_t> nitems(n, 0);
+  const int hw = int(std::max(1u, std::thread::hardware_concurrency()));
+  const int nth = int(std::max<int64_t>(1, std::min<int64_t>(std::min(hw, 16), n / 512)));
+  std::vector<int> rcs(nth, FCX_OK);
+  std::vector<std::string> errs(nth);
+  auto work = [&](int t) {
+    const int64_t lo = n * t / nth, hi = n * (t + 1) / nth;
+    for (int64_t p = lo; p < hi; ++p) {
+      bool mx = false;
+      int ni = 0;
+      int32_t fam = 0;
+      const int rc = plan_one(f, m, p, plan.recs[p], mx, fam, &items[size_t(p) * 4],
+                              ni, errs[t]);
+      if (rc != FCX_OK) { rcs[t] = rc; return; }
+      mixed[p] = mx;
+      nitems[p] = uint8_t(ni);
+      plan.family[p] = fam;
+    }
+  };
+  if (nth == 1) {
+    work(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int t = 0; t < nth; ++t) th.emplace_back(work, t);
+    for (auto& x : th) x.join();
+  }
+  for (int t = 0; t < nth; ++t)
+    if (rcs[t] != FCX_OK) { err = errs[t]; return rcs[t]; }
+  for (int64_t p = 0; p < n; ++p) {
+    if (mixed[p]) plan.phislot[p] = plan.nslots++;
+    for (int k = 0; k < nitems[p]; ++k) plan.reflux.push_back(items[size_t(p) * 4 + k]);
+  }
+  return FCX_OK;
+}
+
 // ---------------------------------------------------------------------------
+// Regrid of a balanced forest.  The tentative forest refines +1 leaves and
+// merges complete families tagged -1.  A merged parent P (level l - 1) that
+// touches a tentative leaf of level >= l + 1 must be split again in every
+// balanced refinement, so that merge is cancelled up front.  After that, only
+// new leaves can break balance, and the ripple is seeded with the refined
+// children alone; the result is the coarsest balanced refinement of the
+// tentative forest, as a full ripple would give.
 int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
            std::vector<fcx_leaf>& out, std::string& err) {
-  std::vector<fcx_leaf> next;
   const int64_t n = int64_t(f.leaves.size());
-  next.reserve(n + 16);
+  LeafIndex set;
+  set.reset(size_t(n) * 2 + 64);
+  std::deque<fcx_leaf> work;
+  std::vector<int64_t> merged;                 // first child of each merge
   for (int64_t p = 0; p < n; ++p) {
     const fcx_leaf& a = f.leaves[p];
     if (tags[p] > 0 && a.level < lmax) {
-      for (int c = 0; c < 4; ++c)
-        next.push_back({a.tree, a.level + 1, 2 * a.ix + (c & 1), 2 * a.iy + (c >> 1)});
+      for (int c = 0; c < 4; ++c) {
+        fcx_leaf ch{a.tree, a.level + 1, 2 * a.ix + (c & 1), 2 * a.iy + (c >> 1)};
+        set.put(pack_key(ch.tree, ch.level, ch.ix, ch.iy), 1);
+        work.push_back(ch);
+      }
       continue;
     }
     if (tags[p] < 0 && a.level > lmin) {
       const int32_t bx = a.ix & ~1, by = a.iy & ~1;
       bool all = true;
       for (int c = 0; c < 4; ++c) {
-        const int64_t s = f.find(a.tree, a.level, bx + (c & 1), by + (c >> 1));
-        if (s < 0 || tags[s] >= 0) { all = false; break; }
+        const int64_t s2 = f.find(a.tree, a.level, bx + (c & 1), by + (c >> 1));
+        if (s2 < 0 || tags[s2] >= 0) { all = false; break; }
       }
       if (all) {
-        if (a.ix == bx && a.iy == by)
-          next.push_back({a.tree, a.level - 1, a.ix >> 1, a.iy >> 1});
+        if (a.ix == bx && a.iy == by) {
+          set.put(pack_key(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1), 1);
+          merged.push_back(p);
+        }
         continue;
       }
     }
-    next.push_back(a);
+    set.put(pack_key(a.tree, a.level, a.ix, a.iy), 1);
   }
-  return balance(f.trees, std::move(next), out, err);
+  // cancel merges whose parent would touch a leaf two levels finer; a
+  // cancellation restores finer leaves and can force others, so repeat
+  // until no merge changes
+  std::vector<uint8_t> cancelled(merged.size(), 0);
+  for (bool again = true; again;) {
+  again = false;
+  for (size_t mi = 0; mi < merged.size(); ++mi) {
+    if (cancelled[mi]) continue;
+    const int64_t p = merged[mi];
+    const fcx_leaf& a = f.leaves[p];                 // child level l
+    const int l = a.level, pl = l - 1;
+    const int32_t pix = a.ix >> 1, piy = a.iy >> 1;
+    const int64_t psize = kSide >> pl, csz = kSide >> l;
+    bool bad = false;
+    for (int dy = -1; dy <= 1 && !bad; ++dy)
+      for (int dx = -1; dx <= 1 && !bad; ++dx) {
+        if (!dx && !dy) continue;
+        // level-l boxes of the neighbour region that touch P
+        for (int s1 = 0; s1 < 2 && !bad; ++s1) {
+          if ((dx != 0 && dy != 0) && s1 == 1) break;
+          int64_t cx, cy;                            // box centre, P's tree
+          const int64_t x0 = int64_t(pix) * psize, y0 = int64_t(piy) * psize;
+          if (dx == 0) cx = x0 + s1 * csz + csz / 2;
+          else cx = dx < 0 ? x0 - csz / 2 : x0 + psize + csz / 2;
+          if (dy == 0) cy = y0 + s1 * csz + csz / 2;
+          else cy = dy < 0 ? y0 - csz / 2 : y0 + psize + csz / 2;
+          int32_t t2;
+          int64_t x2, y2;
+          Xform xf;
+          if (f.locate(a.tree, cx, cy, t2, x2, y2, xf) != 0) continue;
+          bool covered = false;
+          for (int lev = l; lev >= 0 && !covered; --lev)
+            covered = set.get(pack_key(t2, lev, x2 >> (kS - lev), y2 >> (kS - lev))) >= 0;
+          if (!covered) bad = true;
+        }
+      }
+    if (bad) {
+      set.erase(pack_key(a.tree, pl, pix, piy));
+      for (int c = 0; c < 4; ++c)
+        set.put(pack_key(a.tree, l, 2 * pix + (c & 1), 2 * piy + (c >> 1)), 1);
+      cancelled[mi] = 1;
+      again = true;
+    }
+  }
+  }
+  ripple(f, set, work);
+  collect(set, out);
+  (void)err;
+  return FCX_OK;
 }
 
 int transfer_plan(const Forest& old_f, const Forest& new_f,

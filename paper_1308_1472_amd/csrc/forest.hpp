@@ -9,7 +9,6 @@
 
 #include <cstdint>
 #include <string>
-#include <unordered_map>
 #include <vector>
 
 #include "../../include/fcx.h"
@@ -28,8 +27,31 @@ struct Xform {
   void apply(int64_t x, int64_t y, int64_t& xo, int64_t& yo) const;
 };
 
+// Open-addressing hash map from packed leaf keys to leaf indices (linear
+// probing, power-of-two capacity, no deletion except clear).
+class LeafIndex {
+ public:
+  void reset(size_t expected);
+  void put(uint64_t key, int32_t val);
+  int32_t get(uint64_t key) const;
+  bool erase(uint64_t key);            // tombstone
+  size_t size() const { return live_; }
+  template <typename F> void for_each(F f) const {
+    for (size_t s = 0; s < keys_.size(); ++s)
+      if (keys_[s] != kEmpty && keys_[s] != kTomb) f(keys_[s], vals_[s]);
+  }
+
+ private:
+  static constexpr uint64_t kEmpty = ~uint64_t(0), kTomb = ~uint64_t(0) - 1;
+  std::vector<uint64_t> keys_;
+  std::vector<int32_t> vals_;
+  size_t mask_ = 0, live_ = 0, used_ = 0;
+  void grow();
+};
+
 uint64_t morton_key(const fcx_leaf& a);
 bool leaf_less(const fcx_leaf& a, const fcx_leaf& b);
+void sort_leaves(std::vector<fcx_leaf>& v);          // SFC order
 
 class Forest {
  public:
@@ -42,8 +64,9 @@ class Forest {
   int assign(const std::vector<fcx_tree>& t, const std::vector<fcx_leaf>& l,
              std::string& err);
   int64_t find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const;
-  // leaf containing an in-tree point, -1 if none
-  int64_t leaf_at(int32_t tree, int64_t x, int64_t y) const;
+  // leaf containing an in-tree point, -1 if none; levels near `hint` are
+  // probed first
+  int64_t leaf_at(int32_t tree, int64_t x, int64_t y, int hint = -1) const;
 
   // Map a point (possibly outside its tree) into the tree containing it.
   // Returns 0 (found), 1 (beyond a physical boundary), 2 (valence-3
@@ -54,7 +77,7 @@ class Forest {
   bool wall_face(int64_t p, int f) const;
 
  private:
-  std::unordered_map<uint64_t, int32_t> index_;
+  LeafIndex index_;
 };
 
 int check_connectivity(const std::vector<fcx_tree>& trees, std::string& err);
@@ -66,13 +89,17 @@ int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
 // Per-patch neighbour records consumed by the kernels.
 struct PatchRec {
   int32_t level, ix, iy, flags;              // flags: bit f wall on face f,
-                                             // bit 4+f extrapolation wall
+                                             // bit 4+f extrapolation wall,
+                                             // kSimpleHalo
   int32_t nbr[12];                           // faces 2 slots each, corners
   int32_t xf[8];                             // face / corner transforms
 };
 static_assert(sizeof(PatchRec) == 96, "PatchRec layout");
 
 constexpr int32_t kNbrWall = -1;
+// PatchRec.flags bit: every neighbour region is a wall or a same-level leaf
+// glued by a pure translation (ghost cells are plain copies)
+constexpr int32_t kSimpleHalo = 1 << 8;
 constexpr int32_t kNbrValence3 = -2;
 
 // One coarse patch face with two finer neighbours (reflux work item).

@@ -6,16 +6,19 @@
 // One workgroup advances one T x T tile of one patch.  The tile and its
 // two-cell halo are staged in LDS -- from the compact state plus the ghost
 // buffer (plain path) or straight from neighbouring patches' interiors
-// (fused path).  Each sweep direction runs three phases separated by
-// barriers:
+// (fused path).  Per-cell primitive quantities (sqrt h, u, v) are formed
+// once per staged cell.  Each sweep direction then runs three phases
+// separated by barriers:
 //   A  one Riemann solve per edge of the (T+2) x (T+3) edge set; compact
-//      wave data (shallow water: strengths and Roe averages) go to LDS;
+//      wave data (strengths and Roe averages) go to LDS;
 //   B  per edge: wave limiter from the neighbour edges' waves, second-order
-//      correction, transverse splitting of the corrected fluctuations;
-//      results go to LDS per edge;
-//   C  per interior cell: gather the normal fluctuations and correction
-//      fluxes of its two edges and the transverse fluxes of its two
-//      transverse edges into a register accumulator.
+//      correction, transverse splitting of the corrected fluctuations.  The
+//      edge's contributions go to per-cell LDS accumulators in two race-free
+//      sub-passes: the cell on its left first, then (after a barrier) the
+//      cell on its right -- every cell gets exactly one of each;
+//   C  per interior cell: the normal flux difference and the difference of
+//      the transverse fluxes at its two transverse edges go into a register
+//      accumulator.
 // After both sweeps q_new = q + dq is written with coalesced stores.
 #pragma once
 
@@ -35,10 +38,19 @@ struct StepArgs {
   R* __restrict__ phi;
   int32_t* err;
   int32_t P;
+  int32_t m, lm;          // patch size and its log2
+  int32_t ntiles;         // total tiles = P * (m / T)^2
   KPhys ph;
 };
 
 template <int T> struct TileThreads { static constexpr int value = T * T >= 256 ? 256 : T * T; };
+
+// Fast reciprocal / root: hardware approximations in FP32 (the FP32 path is
+// held to 1e-5), correctly rounded operations in FP64.
+__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 
 template <typename R>
 __device__ __forceinline__ R limiter_phi(int lim, R th) {
@@ -46,63 +58,124 @@ __device__ __forceinline__ R limiter_phi(int lim, R th) {
     case 0: return R(1);
     case 1: return fmax(R(0), fmin(R(1), th));
     case 2: return fmax(R(0), fmax(fmin(R(1), R(2) * th), fmin(R(2), th)));
-    case 3: return (th + fabs(th)) / (R(1) + fabs(th));
+    case 3: return (th + fabs(th)) * rcp_(R(1) + fabs(th));
     default: return fmax(R(0), fmin(fmin(R(0.5) * (R(1) + th), R(2)), R(2) * th));
   }
 }
 
-template <typename R, int PHYS, int M, int T, bool FUSED>
-__global__ void __launch_bounds__(TileThreads<T>::value)
-k_step(StepArgs<R> A) {
+// Map a linear block index so that the blocks one XCD receives (the
+// dispatcher deals blocks round-robin over the 8 XCDs) form a contiguous
+// range of tiles: neighbouring patches in SFC order then share an L2.
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int per = n >> 3, rem = n & 7;
+  const int x = b & 7, k = b >> 3;
+  // XCD x owns tiles [start(x), start(x) + per + (x < rem))
+  const int start = x * per + (x < rem ? x : rem);
+  return start + k;
+}
+
+// Halo of a patch flagged kSimpleHalo: every neighbour region is a wall or a
+// same-level leaf glued by a pure translation, so a ghost cell is a copy of
+// cell (i -+ m, j -+ m) of that neighbour.
+
+template <typename R, int MEQN, int PHYS>
+__device__ __forceinline__ void simple_halo(const R* __restrict__ q,
+                                            const PatchRec& r, int m, int lm,
+                                            int p, int i, int j, R (&out)[MEQN]) {
+  bool nx = false, ny = false;
+  resolve_walls(r.flags, m, i, j, nx, ny);
+  int src = p;
+  if (i < 1 || i > m || j < 1 || j > m) {
+    int slot;
+    if (i >= 1 && i <= m) slot = j < 1 ? 4 : 6;
+    else if (j >= 1 && j <= m) slot = i < 1 ? 0 : 2;
+    else slot = 8 + (i > m) + 2 * (j > m);
+    src = r.nbr[slot];
+    i = i < 1 ? i + m : (i > m ? i - m : i);
+    j = j < 1 ? j + m : (j > m ? j - m : j);
+  }
+  const uint32_t base = (uint32_t(src) * MEQN << (2 * lm)) + (uint32_t(j - 1) << lm) + (i - 1);
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) out[k] = q[base + (uint32_t(k) << (2 * lm))];
+  if (PHYS == FCX_SHALLOW) {
+    if (nx) out[1] = -out[1];
+    if (ny) out[2 % MEQN] = -out[2 % MEQN];
+  }
+}
+
+template <typename R, int PHYS, int T, int NT, bool FUSED>
+__device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, int ty) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   constexpr int WD = PHYS == FCX_ADVECTION ? 1 : 6;   // wave data per edge
+  constexpr int NPR = PHYS == FCX_ADVECTION ? 1 : 3;  // primitives per cell
   constexpr int F = T + 4, NR = T + 2, NE = T + 3;
-  constexpr int NT = TileThreads<T>::value;
-  constexpr int TPS = M / T;
   constexpr int CPT = (T * T + NT - 1) / NT;
-  constexpr int LM = M == 8 ? 3 : M == 16 ? 4 : 5;
-  constexpr int G = 8 * M + 16;
+  constexpr int EPT = (NR * (T + 1) + NT - 1) / NT;   // phase-B edges per thread
 
   __shared__ R qs[MEQN][F * F];
+  __shared__ R pr[NPR][F * F];
   __shared__ R wb[WD][NR * NE];
-  __shared__ R tl[MEQN][T * (T + 1)];
-  __shared__ R tr[MEQN][T * (T + 1)];
-  __shared__ R tq[4][MEQN][NR * (T + 1)];
+  __shared__ R fn[MEQN][T * T];          // normal fluxes, per interior cell
+  __shared__ R tup[MEQN][NR * T];        // transverse flux at a cell's upper
+  __shared__ R tdn[MEQN][NR * T];        //   and lower transverse edge
+  __shared__ R fb[2][MEQN][T];           // normal terms at the tile's two faces
   __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
 
+  const int m = A.m, lm = A.lm;
   const int tid = threadIdx.x;
-  const int blk = blockIdx.x;
-  const int p = blk / (TPS * TPS);
-  const int tile = blk - p * (TPS * TPS);
-  const int tx = tile % TPS, ty = tile / TPS;
   const PatchRec& rp = A.rec[p];
   const int level = rp.level;
-  const double dxd = ldexp(1.0, -level) / M;
+  const double dxd = ldexp(1.0, -level - lm);
   const double dtv = *A.dt;
   const double dtdx_d = dtv / dxd;
   const R dtdx = R(dtdx_d);
+  const uint32_t pbase = uint32_t(p) * MEQN << (2 * lm);
 
   // ---- stage the tile and its halo ----------------------------------
-  GhostView<R, MEQN> gv{A.q, A.rec, M, LM, A.err};
+  const bool simple = (rp.flags & kSimpleHalo) != 0;
+  const int i0 = tx * T, j0 = ty * T;
   for (int c = tid; c < F * F; c += NT) {
     const int ci = c % F - 1, cj = c / F - 1;
-    const int i = tx * T + ci, j = ty * T + cj;
+    const int i = i0 + ci, j = j0 + cj;
     R v[MEQN];
     const bool outer = (ci == -1 || ci == T + 2) && (cj == -1 || cj == T + 2);
     if (outer) {
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) v[k] = R(0);
-    } else if (i >= 1 && i <= M && j >= 1 && j <= M) {
-      read_interior<R, MEQN>(A.q, M, p, i, j, v);
-    } else if (FUSED) {
-      frame_value<R, MEQN, PHYS, true>(gv, p, i, j, v);
-    } else {
-      const int gi = ghost_index(M, i, j);
+    } else if (i >= 1 && i <= m && j >= 1 && j <= m) {
+      const uint32_t o = pbase + (uint32_t(j - 1) << lm) + (i - 1);
 #pragma unroll
-      for (int k = 0; k < MEQN; ++k) v[k] = A.ghost[size_t(p * MEQN + k) * G + gi];
+      for (int k = 0; k < MEQN; ++k) v[k] = A.q[o + (uint32_t(k) << (2 * lm))];
+    } else if (FUSED) {
+      if (simple) {
+        simple_halo<R, MEQN, PHYS>(A.q, rp, m, lm, p, i, j, v);
+      } else {
+        GhostView<R, MEQN> gv{A.q, A.rec, m, lm, A.err};
+        frame_value<R, MEQN, PHYS, true>(gv, p, i, j, v);
+      }
+    } else {
+      const int G = 8 * m + 16;
+      const uint32_t o = uint32_t(p) * MEQN * G + ghost_index(m, i, j);
+#pragma unroll
+      for (int k = 0; k < MEQN; ++k) v[k] = A.ghost[o + uint32_t(k) * G];
     }
 #pragma unroll
     for (int k = 0; k < MEQN; ++k) qs[k][c] = v[k];
+    if (PHYS == FCX_SHALLOW) {
+      // primitives: sqrt(h), u, v (zero for a non-positive depth)
+      const R h = v[0];
+      if (h > R(0)) {
+        const R ih = rcp_(h);
+        pr[0][c] = sqrt_(h);
+        pr[1][c] = v[1] * ih;
+        pr[2][c] = v[2 % MEQN] * ih;
+      } else {
+        pr[0][c] = R(0);
+        pr[1][c] = R(0);
+        pr[2][c] = R(0);
+        if (!outer) atomicOr(A.err, kErrNegDepth);
+      }
+    }
   }
   __syncthreads();
 
@@ -114,6 +187,7 @@ k_step(StepArgs<R> A) {
   double numax = 0.0;
   const int lim = A.ph.limiter, trans = A.ph.transverse;
   const R half_dtdx = R(0.5) * dtdx;
+  const R ghalf = R(0.5 * A.ph.g);
 
 #pragma unroll
   for (int d = 0; d < 2; ++d) {
@@ -122,13 +196,14 @@ k_step(StepArgs<R> A) {
     const R an = R(d == 0 ? A.ph.ax : A.ph.ay);
     const R at = R(d == 0 ? A.ph.ay : A.ph.ax);
     auto bidx = [&](int r, int e) { return d == 0 ? r * NE + e : e * NR + r; };
-    auto lidx = [&](int r, int e) { return d == 0 ? (r - 1) * (T + 1) + (e - 1)
-                                                  : (e - 1) * T + (r - 1); };
     auto qidx = [&](int r, int e) {   // cell (normal e, transverse r)
       return d == 0 ? (r + 1) * F + (e + 1) : (e + 1) * F + (r + 1);
     };
-    auto tidx = [&](int r, int e) { return d == 0 ? r * (T + 1) + (e - 1)
-                                                  : (e - 1) * NR + r; };
+    // per-cell accumulators of cell (normal n in 1..T, transverse r)
+    auto nidx = [&](int r, int n) { return d == 0 ? (r - 1) * T + (n - 1)
+                                                  : (n - 1) * T + (r - 1); };
+    auto uidx = [&](int r, int n) { return d == 0 ? r * T + (n - 1)
+                                                  : (n - 1) * NR + r; };
 
     // ---- phase A: Riemann solves ------------------------------------
     for (int idx = tid; idx < NR * NE; idx += NT) {
@@ -138,22 +213,20 @@ k_step(StepArgs<R> A) {
       if (PHYS == FCX_ADVECTION) {
         wb[0][bidx(r, e)] = qs[0][cr] - qs[0][cl];
       } else {
-        const R hl = qs[0][cl], hr = qs[0][cr];
+        const R sl = pr[0][cl], sr = pr[0][cr];
         R a1 = 0, a2 = 0, a3 = 0, u = 0, v = 0, c = 1;
-        if (hl > R(0) && hr > R(0)) {
-          const R sl = sqrt(hl), sr = sqrt(hr);
-          const R inv = R(1) / (sl + sr);
-          u = (qs[mu][cl] / sl + qs[mu][cr] / sr) * inv;
-          v = (qs[mv][cl] / sl + qs[mv][cr] / sr) * inv;
-          c = sqrt(R(A.ph.g) * R(0.5) * (hl + hr));
+        if (sl > R(0) && sr > R(0)) {
+          const R inv = rcp_(sl + sr);
+          u = (sl * pr[mu][cl] + sr * pr[mu][cr]) * inv;
+          v = (sl * pr[mv][cl] + sr * pr[mv][cr]) * inv;
+          const R hl = qs[0][cl], hr = qs[0][cr];
+          c = sqrt_(ghalf * (hl + hr));
+          const R i2c = R(0.5) * rcp_(c);
           const R d0 = hr - hl, d1 = qs[mu][cr] - qs[mu][cl];
           const R d2 = qs[mv][cr] - qs[mv][cl];
-          const R i2c = R(0.5) / c;
           a1 = ((u + c) * d0 - d1) * i2c;
           a2 = d2 - v * d0;
           a3 = (d1 - (u - c) * d0) * i2c;
-        } else {
-          atomicOr(A.err, kErrNegDepth);
         }
         const int b = bidx(r, e);
         wb[0][b] = a1; wb[1][b] = a2; wb[2][b] = a3;
@@ -163,7 +236,11 @@ k_step(StepArgs<R> A) {
     __syncthreads();
 
     // ---- phase B: limiter, corrections, transverse splitting ---------
-    for (int idx = tid; idx < NR * (T + 1); idx += NT) {
+    R keep[EPT][3][MEQN];                  // right-cell terms across the barrier
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+      const int idx = tid + it * NT;
+      if (idx >= NR * (T + 1)) break;
       const int r = d == 0 ? idx / (T + 1) : idx % NR;
       const int e = d == 0 ? idx % (T + 1) + 1 : idx / NR + 1;
       const bool inner = (r >= 1 && r <= T);
@@ -176,7 +253,7 @@ k_step(StepArgs<R> A) {
         if (inner) numax = fmax(numax, dtdx_d * fabs(double(an)));
         if (w != R(0)) {
           const R wu = wb[0][bidx(r, an > R(0) ? e - 1 : e + 1)];
-          const R th = (wu * w) / (w * w);
+          const R th = (wu * w) * rcp_(w * w);
           const R s = fabs(an);
           cq[0] = s * (R(1) - dtdx * s) * limiter_phi(lim, th) * w;
         }
@@ -186,9 +263,9 @@ k_step(StepArgs<R> A) {
         const R al[3] = {wb[0][b], wb[1][b], wb[2][b]};
         const R s[3] = {u - c, u, u + c};
         // waves in (h, normal, tangential) order
-        R W[3][3] = {{al[0], al[0] * (u - c), al[0] * v},
-                     {R(0), R(0), al[1]},
-                     {al[2], al[2] * (u + c), al[2] * v}};
+        const R W[3][3] = {{al[0], al[0] * (u - c), al[0] * v},
+                           {R(0), R(0), al[1]},
+                           {al[2], al[2] * (u + c), al[2] * v}};
         R amh[3] = {0, 0, 0}, aph[3] = {0, 0, 0}, cqh[3] = {0, 0, 0};
 #pragma unroll
         for (int w = 0; w < 3; ++w) {
@@ -198,37 +275,31 @@ k_step(StepArgs<R> A) {
             amh[k] += smn * W[w][k];
             aph[k] += smx * W[w][k];
           }
-          if (inner) numax = fmax(numax, dtdx_d * fabs(double(s[w])));
           const R wn2 = W[w][0] * W[w][0] + W[w][1] * W[w][1] + W[w][2] * W[w][2];
           if (wn2 != R(0)) {
             const int bu = bidx(r, s[w] > R(0) ? e - 1 : e + 1);
-            const R uu = wb[3][bu], vu = wb[4][bu], cu = wb[5][bu];
             R dot;
             if (w == 1) {
               dot = wb[1][bu] * al[1];
             } else {
-              const R au = wb[w][bu];
+              const R au = wb[w][bu], uu = wb[3][bu], vu = wb[4][bu], cu = wb[5][bu];
               const R nu_ = w == 0 ? uu - cu : uu + cu;
-              dot = au * W[w][0] + au * nu_ * W[w][1] + au * vu * W[w][2];
+              dot = au * (W[w][0] + nu_ * W[w][1] + vu * W[w][2]);
             }
-            const R phi = limiter_phi(lim, dot / wn2);
+            const R phi = limiter_phi(lim, dot * rcp_(wn2));
             const R as = fabs(s[w]);
             const R f = as * (R(1) - dtdx * as) * phi;
 #pragma unroll
             for (int k = 0; k < 3; ++k) cqh[k] += f * W[w][k];
           }
         }
+        if (inner) {
+          const double sm = fmax(fabs(double(s[0])), fabs(double(s[2])));
+          numax = fmax(numax, dtdx_d * sm);
+        }
         am[0] = amh[0]; am[mu] = amh[1]; am[mv] = amh[2];
         ap[0] = aph[0]; ap[mu] = aph[1]; ap[mv] = aph[2];
         cq[0] = cqh[0]; cq[mu] = cqh[1]; cq[mv] = cqh[2];
-      }
-      if (inner) {
-        const int li = lidx(r, e);
-#pragma unroll
-        for (int k = 0; k < MEQN; ++k) {
-          tl[k][li] = am[k] + R(0.5) * cq[k];
-          tr[k][li] = ap[k] - R(0.5) * cq[k];
-        }
       }
       // transverse: left-going part to the cell left of the edge, right-going
       // part to the cell on its right, each split into down / up parts
@@ -243,51 +314,75 @@ k_step(StepArgs<R> A) {
           apt[k] = ap[k] - (trans == 2 ? cq[k] : R(0));
         }
         if (PHYS == FCX_ADVECTION) {
-          const R bm = fmin(at, R(0)), bp = fmax(at, R(0));
-          ldn[0] = -half_dtdx * bm * amt[0];
-          lup[0] = -half_dtdx * bp * amt[0];
-          rdn[0] = -half_dtdx * bm * apt[0];
-          rup[0] = -half_dtdx * bp * apt[0];
+          const R bm = -half_dtdx * fmin(at, R(0)), bp = -half_dtdx * fmax(at, R(0));
+          ldn[0] = bm * amt[0];
+          lup[0] = bp * amt[0];
+          rdn[0] = bm * apt[0];
+          rup[0] = bp * apt[0];
         } else {
           const int b = bidx(r, e);
           const R u = wb[3][b], v = wb[4][b], c = wb[5][b];
-          const R i2c = R(0.5) / c;
-          const R lam[3] = {v - c, v, v + c};
+          const R i2c = R(0.5) * rcp_(c);
+          const R lmn[3] = {-half_dtdx * fmin(v - c, R(0)), -half_dtdx * fmin(v, R(0)),
+                            -half_dtdx * fmin(v + c, R(0))};
+          const R lmx[3] = {-half_dtdx * fmax(v - c, R(0)), -half_dtdx * fmax(v, R(0)),
+                            -half_dtdx * fmax(v + c, R(0))};
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
             const R* psi = side == 0 ? amt : apt;
             const R ph = psi[0], pn = psi[mu], pt = psi[mv];
-            const R be[3] = {((v + c) * ph - pt) * i2c, pn - u * ph,
-                             (pt - (v - c) * ph) * i2c};
-            R bmh[3] = {0, 0, 0}, bph[3] = {0, 0, 0};
-#pragma unroll
-            for (int w = 0; w < 3; ++w) {
-              const R rv[3] = {w == 1 ? R(0) : R(1), w == 1 ? R(1) : u,
-                               w == 0 ? v - c : w == 1 ? R(0) : v + c};
-              const R fm = fmin(lam[w], R(0)) * be[w];
-              const R fp = fmax(lam[w], R(0)) * be[w];
-#pragma unroll
-              for (int k = 0; k < 3; ++k) {
-                bmh[k] += fm * rv[k];
-                bph[k] += fp * rv[k];
-              }
-            }
+            const R b1 = ((v + c) * ph - pt) * i2c, b2 = pn - u * ph;
+            const R b3 = (pt - (v - c) * ph) * i2c;
+            // eigenvectors (1, u, v - c), (0, 1, 0), (1, u, v + c)
+            const R m1 = lmn[0] * b1, m2 = lmn[1] * b2, m3 = lmn[2] * b3;
+            const R p1 = lmx[0] * b1, p2 = lmx[1] * b2, p3 = lmx[2] * b3;
             R* dn = side == 0 ? ldn : rdn;
             R* up = side == 0 ? lup : rup;
-            dn[0] = -half_dtdx * bmh[0]; dn[mu] = -half_dtdx * bmh[1];
-            dn[mv] = -half_dtdx * bmh[2];
-            up[0] = -half_dtdx * bph[0]; up[mu] = -half_dtdx * bph[1];
-            up[mv] = -half_dtdx * bph[2];
+            dn[0] = m1 + m3;
+            dn[mu] = u * (m1 + m3) + m2;
+            dn[mv] = (v - c) * m1 + (v + c) * m3;
+            up[0] = p1 + p3;
+            up[mu] = u * (p1 + p3) + p2;
+            up[mv] = (v - c) * p1 + (v + c) * p3;
           }
         }
       }
-      const int ti = tidx(r, e);
+      // left cell (e - 1) now; right cell (e) after the barrier
+      if (e >= 2) {
+#pragma unroll
+        for (int k = 0; k < MEQN; ++k) {
+          tup[k][uidx(r, e - 1)] = lup[k];
+          tdn[k][uidx(r, e - 1)] = ldn[k];
+          if (inner) fn[k][nidx(r, e - 1)] = am[k] + R(0.5) * cq[k];
+        }
+      }
+      if (inner && (e == 1 || e == T + 1)) {
+#pragma unroll
+        for (int k = 0; k < MEQN; ++k)
+          fb[e == 1 ? 0 : 1][k][r - 1] = e == 1 ? ap[k] - R(0.5) * cq[k]
+                                              : am[k] + R(0.5) * cq[k];
+      }
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) {
-        tq[0][k][ti] = ldn[k];
-        tq[1][k][ti] = lup[k];
-        tq[2][k][ti] = rdn[k];
-        tq[3][k][ti] = rup[k];
+        keep[it][0][k] = ap[k] - R(0.5) * cq[k];
+        keep[it][1][k] = rup[k];
+        keep[it][2][k] = rdn[k];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < EPT; ++it) {
+      const int idx = tid + it * NT;
+      if (idx >= NR * (T + 1)) break;
+      const int r = d == 0 ? idx / (T + 1) : idx % NR;
+      const int e = d == 0 ? idx % (T + 1) + 1 : idx / NR + 1;
+      if (e > T) continue;
+      const bool inner = (r >= 1 && r <= T);
+#pragma unroll
+      for (int k = 0; k < MEQN; ++k) {
+        tup[k][uidx(r, e)] += keep[it][1][k];
+        tdn[k][uidx(r, e)] += keep[it][2][k];
+        if (inner) fn[k][nidx(r, e)] += keep[it][0][k];
       }
     }
     __syncthreads();
@@ -301,23 +396,20 @@ k_step(StepArgs<R> A) {
       const int n = d == 0 ? ci : cj;         // normal index
       const int r = d == 0 ? cj : ci;         // transverse index
       const int pn = (d == 0 ? tx : ty) * T + n;   // patch-level indices
-      const int pr = (d == 0 ? ty : tx) * T + r;
+      const int prr = (d == 0 ? ty : tx) * T + r;
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) {
-        const R fR = tr[k][lidx(r, n)], fL = tl[k][lidx(r, n + 1)];
         // other-direction flux at the transverse edges r + 1/2 and r - 1/2
-        const R gup = tq[1][k][tidx(r, n + 1)] + tq[3][k][tidx(r, n)] +
-                      tq[0][k][tidx(r + 1, n + 1)] + tq[2][k][tidx(r + 1, n)];
-        const R gdn = tq[1][k][tidx(r - 1, n + 1)] + tq[3][k][tidx(r - 1, n)] +
-                      tq[0][k][tidx(r, n + 1)] + tq[2][k][tidx(r, n)];
-        dq[c][k] -= dtdx * (fR + fL) + dtdx * (gup - gdn);
+        const R gup = tup[k][uidx(r, n)] + tdn[k][uidx(r + 1, n)];
+        const R gdn = tup[k][uidx(r - 1, n)] + tdn[k][uidx(r, n)];
+        dq[c][k] -= dtdx * (fn[k][nidx(r, n)] + (gup - gdn));
         // face terms through the patch faces (for the reflux)
         R& pnrm = d == 0 ? phx[c][k] : phy[c][k];
         R& ptrn = d == 0 ? phy[c][k] : phx[c][k];
-        if (pn == 1) pnrm += fR;
-        if (pn == M) pnrm += fL;
-        if (pr == 1) ptrn -= gdn;
-        if (pr == M) ptrn += gup;
+        if (pn == 1) pnrm += fb[0][k][r - 1];
+        if (pn == m) pnrm += fb[1][k][r - 1];
+        if (prr == 1) ptrn -= gdn;
+        if (prr == m) ptrn += gup;
       }
     }
     __syncthreads();
@@ -330,21 +422,20 @@ k_step(StepArgs<R> A) {
     const int cell = tid + c * NT;
     if (cell >= T * T) break;
     const int ci = cell % T + 1, cj = cell / T + 1;
-    const int i = tx * T + ci, j = ty * T + cj;
+    const int i = i0 + ci, j = j0 + cj;
+    const uint32_t o = pbase + (uint32_t(j - 1) << lm) + (i - 1);
 #pragma unroll
-    for (int k = 0; k < MEQN; ++k) {
-      const size_t o = (size_t(p * MEQN + k) * M + (j - 1)) * M + (i - 1);
-      A.qn[o] = qs[k][(cj + 1) * F + (ci + 1)] + dq[c][k];
-    }
+    for (int k = 0; k < MEQN; ++k)
+      A.qn[o + (uint32_t(k) << (2 * lm))] = qs[k][(cj + 1) * F + (ci + 1)] + dq[c][k];
     if (slot >= 0) {
-      R* ph = A.phi + size_t(slot) * 4 * M * MEQN;
+      R* ph = A.phi + size_t(slot) * 4 * m * MEQN;
       const R dxr = R(dxd);
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) {
-        if (i == 1) ph[(0 * M + (j - 1)) * MEQN + k] = dxr * phx[c][k];
-        if (i == M) ph[(1 * M + (j - 1)) * MEQN + k] = dxr * phx[c][k];
-        if (j == 1) ph[(2 * M + (i - 1)) * MEQN + k] = dxr * phy[c][k];
-        if (j == M) ph[(3 * M + (i - 1)) * MEQN + k] = dxr * phy[c][k];
+        if (i == 1) ph[(0 * m + (j - 1)) * MEQN + k] = dxr * phx[c][k];
+        if (i == m) ph[(1 * m + (j - 1)) * MEQN + k] = dxr * phx[c][k];
+        if (j == 1) ph[(2 * m + (i - 1)) * MEQN + k] = dxr * phy[c][k];
+        if (j == m) ph[(3 * m + (i - 1)) * MEQN + k] = dxr * phy[c][k];
       }
     }
   }
@@ -359,6 +450,17 @@ k_step(StepArgs<R> A) {
     for (int w = 1; w < NT / 64; ++w) v = fmax(v, red[w]);
     atomic_max_pos(A.numax, v);
   }
+}
+
+// One workgroup per tile, over all tiles of one forest.
+template <typename R, int PHYS, int T, int NT, bool FUSED>
+__global__ void __launch_bounds__(NT)
+k_step(StepArgs<R> A) {
+  const int t = xcd_tile(blockIdx.x, A.ntiles);
+  const int tps = A.m / T;
+  const int p = t / (tps * tps);
+  const int tile = t - p * (tps * tps);
+  tile_step<R, PHYS, T, NT, FUSED>(A, p, tile % tps, tile / tps);
 }
 
 }  // namespace fcx

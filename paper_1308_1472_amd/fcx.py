@@ -27,6 +27,7 @@ ERRORS = {-1: "FCX_EINVAL", -2: "FCX_EBALANCE", -3: "FCX_ENOMEM",
 # the symbols include/fcx.h declares
 EXPORTS = [
     "fcx_last_error", "fcx_version", "fcx_sfc_sort", "fcx_balance",
+    "fcx_regrid_leaves",
     "fcx_create", "fcx_destroy", "fcx_upload_forest", "fcx_num_patches",
     "fcx_state_elems", "fcx_ghost_elems", "fcx_get_leaves", "fcx_ghost_fill",
     "fcx_patch_step", "fcx_fused_step", "fcx_reflux", "fcx_next_dt",
@@ -45,6 +46,7 @@ class Config(C.Structure):
     _fields_ = [("m", C.c_int32), ("precision", C.c_int32),
                 ("physics", C.c_int32), ("limiter", C.c_int32),
                 ("transverse", C.c_int32), ("tile", C.c_int32),
+                ("threads", C.c_int32), ("reserved", C.c_int32),
                 ("g", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
                 ("cfl_desired", C.c_double), ("cfl_max", C.c_double)]
 
@@ -69,6 +71,7 @@ def lib():
         L.fcx_version.restype = i32
         L.fcx_sfc_sort.argtypes = [i64, vp]
         L.fcx_balance.argtypes = [i32, vp, i64, vp, i64, vp, vp]
+        L.fcx_regrid_leaves.argtypes = [i32, vp, i64, vp, vp, i32, i32, i64, vp, vp]
         L.fcx_create.argtypes = [vp, i32, vp, vp]
         L.fcx_destroy.argtypes = [vp]
         L.fcx_upload_forest.argtypes = [vp, i64, vp]
@@ -120,10 +123,31 @@ def balance(trees, leaves) -> np.ndarray:
         return out[: n.value].copy()
 
 
+def regrid_leaves(trees, leaves, tags, lmin, lmax) -> np.ndarray:
+    trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
+    leaves = np.ascontiguousarray(leaves, dtype=LEAF_DTYPE)
+    tags = np.ascontiguousarray(tags, dtype=np.int8)
+    if len(tags) != len(leaves):
+        raise ValueError("one tag per leaf expected")
+    n = C.c_int64()
+    cap = 16 * len(leaves) + 64
+    while True:
+        out = np.zeros(cap, dtype=LEAF_DTYPE)
+        rc = lib().fcx_regrid_leaves(len(trees), _np_ptr(trees), len(leaves),
+                                     _np_ptr(leaves), _np_ptr(tags), lmin, lmax,
+                                     cap, _np_ptr(out), C.byref(n))
+        if rc == -1 and n.value > cap:
+            cap = n.value
+            continue
+        _check(rc)
+        return out[: n.value].copy()
+
+
 def config(m, precision=64, physics=FCX_SHALLOW, limiter=4, transverse=2,
-           tile=0, g=1.0, ax=0.0, ay=0.0, cfl_desired=0.9, cfl_max=1.0):
-    return Config(m, precision, physics, limiter, transverse, tile, g, ax, ay,
-                  cfl_desired, cfl_max)
+           tile=0, threads=0, g=1.0, ax=0.0, ay=0.0, cfl_desired=0.9,
+           cfl_max=1.0):
+    return Config(m, precision, physics, limiter, transverse, tile, threads, 0,
+                  g, ax, ay, cfl_desired, cfl_max)
 
 
 def _stream(stream):

@@ -72,3 +72,25 @@ def test_balance_rejects_bad_connectivity():
     with pytest.raises(fcx.FcxError) as e:
         fcx.balance(bad, I.uniform_leaves(1, 1))
     assert e.value.code == -1
+
+
+@pytest.mark.parametrize("domain", ["walled", "periodic", "brick", "sphere"])
+@pytest.mark.parametrize("seed", range(4))
+def test_regrid_leaves_matches_oracle(domain, seed):
+    """Host regrid (incremental balance) against the oracle's plain
+    refine / merge / full re-balance, on random tags."""
+    if domain == "walled":
+        trees, _ = I.walled_square(); nt = 1
+    elif domain == "periodic":
+        trees, _ = I.periodic_square(); nt = 1
+    elif domain == "brick":
+        trees, _ = I.brick(2, 2, orient_codes=[0, 1, 6, 3]); nt = 4
+    else:
+        trees = I.cubed_sphere(); nt = 6
+    lv = O.balance(trees, I.random_leaves(200 + seed, nt, 1, 6, 50))
+    rng = np.random.default_rng(seed)
+    for lmin, lmax in ((1, 7), (2, 5)):
+        tg = rng.choice(np.array([-1, -1, 0, 1], np.int8), len(lv))
+        a = fcx.regrid_leaves(trees, lv, tg, lmin, lmax)
+        b = O.regrid(O.Mesh(trees, lv, 8), tg, lmin, lmax)
+        assert np.array_equal(a, b)
