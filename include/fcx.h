@@ -203,6 +203,47 @@ int fcx_regrid_apply(fcx_ctx *ctx, const int8_t *tags_host, int32_t lmin,
 int fcx_regrid_transfer(fcx_ctx *ctx, const void *q_old, const void *ghost_old,
                         void *q_new, void *stream);
 
+/* ---- batches of independent forests ---------------------------------- */
+
+/* A batch advances every leaf of n independent forests (each created and
+ * uploaded as its own context; their m and physics may differ, their
+ * precision must agree) in one persistent fused ghost-gather + update launch
+ * per tile class (8 x 8 tiles for m = 8, the tuned tile size otherwise).
+ * The contexts must outlive the batch.  The state of all forests is one
+ * caller-owned buffer: forest f starts at fcx_batch_state_offset(f) and uses
+ * the compact layout of its own context.  dt, nu_max and status are device
+ * arrays of n entries (per forest); cfl_desired and cfl_max are those of the
+ * first forest. */
+int fcx_batch_create(int32_t n, fcx_ctx *const *forests, fcx_batch **out);
+int fcx_batch_destroy(fcx_batch *batch);
+int64_t fcx_batch_state_elems(const fcx_batch *batch);
+int64_t fcx_batch_state_offset(const fcx_batch *batch, int32_t f);
+int64_t fcx_batch_num_patches(const fcx_batch *batch);
+
+/* Tunables (chosen by the autotuner): tile of forests with m >= 16 (8 or
+ * 16), threads per 8 x 8 tile (64 or 128) and per 16 x 16 tile (256 or 512),
+ * resident workgroups per CU of the persistent kernels (0 = from LDS use).
+ * Drops any captured graph. */
+int fcx_batch_set_tuning(fcx_batch *batch, int32_t tile_big, int32_t threads8,
+                         int32_t threads16, int32_t wg_per_cu);
+
+/* One step of every forest: fused ghost gather + update (per forest: its own
+ * dt), reflux, per-forest next dt as fcx_next_dt.  q_new must not alias q. */
+int fcx_batch_step(fcx_batch *batch, const void *q, void *q_new, double *dt,
+                   double *nu_max, int32_t *status, void *stream);
+
+/* Records `steps` batch steps, alternating q_a -> q_b -> q_a ..., into a HIP
+ * graph (captured on a private stream; no memset nodes).  The pointers are
+ * baked into the graph and must stay valid until the next capture or
+ * fcx_batch_destroy.  After an odd number of steps the state is in q_b. */
+int fcx_batch_capture(fcx_batch *batch, int32_t steps, void *q_a, void *q_b,
+                      double *dt, double *nu_max, int32_t *status);
+int fcx_batch_replay(fcx_batch *batch, void *stream);
+
+/* sums[4 f + k]: FP64 conservation sums of forest f (k < meqn; others 0),
+ * reduced in a fixed order. */
+int fcx_batch_sums(fcx_batch *batch, const void *q, double *sums, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "aux_kernels.hpp"
+#include "batch.hpp"
 #include "forest.hpp"
 #include "step.hpp"
 
@@ -568,3 +569,329 @@ int fcx_regrid_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
             : launch_transfer<float, 3>(c, qo, go, qn, s);
 }
 
+
+// ===========================================================================
+// Batches of independent forests
+// ===========================================================================
+struct fcx_batch {
+  int32_t n = 0;
+  int precision = 64;
+  double cfl_desired = 0.9, cfl_max = 1.0;
+  std::vector<fcx_ctx*> ctx;
+  std::vector<ForestDev> fh;
+  std::vector<int64_t> state_off;
+  int64_t state_elems = 0, P = 0;
+  // tuning: tile used by forests with m >= 16, threads per tile class,
+  // resident workgroups per CU of the persistent kernels
+  int32_t tile_big = 16, threads8 = 64, threads16 = 256, wg_per_cu = 0;
+  // device data
+  DevBuf<uint8_t> blob;
+  PatchRec* rec = nullptr;
+  int32_t* phislot = nullptr;
+  int32_t* pforest = nullptr;
+  ForestDev* forests = nullptr;
+  uint32_t* items = nullptr;
+  int32_t* range = nullptr;           // [2][9]
+  RefluxItem* reflux = nullptr;
+  int32_t* reflux_forest = nullptr;
+  int32_t* first = nullptr;           // [n + 1] patch offsets
+  int32_t n_reflux_x = 0, n_reflux_y = 0;
+  int32_t nitems[2] = {0, 0}, item0[2] = {0, 0};
+  DevBuf<uint8_t> phi;
+  DevBuf<double> partial;
+  DevBuf<int32_t> counters, err;
+  HostBuf staging;
+  int cus = 256;
+  // captured graph
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  ~fcx_batch() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+  }
+};
+
+static int batch_build(fcx_batch* b) {
+  // concatenated tables, items per tile class, cost-balanced XCD ranges
+  std::vector<PatchRec> recs;
+  std::vector<int32_t> phislot, pforest, first(1, 0);
+  std::vector<RefluxItem> rx, ry;
+  std::vector<int32_t> rfx, rfy;
+  std::vector<uint32_t> items[2];
+  std::vector<int32_t> cost[2];
+  int64_t phi_elems = 0, slot_base = 0;
+  b->fh.clear();
+  b->state_off.clear();
+  int64_t sbase = 0, pbase = 0;
+  for (int f = 0; f < b->n; ++f) {
+    fcx_ctx* c = b->ctx[f];
+    Plan plan;
+    std::string err;
+    int rc = build_plan(c->forest, c->cfg.m, plan, err);
+    if (rc != FCX_OK) return fail(rc, err);
+    const int64_t P = int64_t(c->forest.leaves.size());
+    ForestDev F{};
+    F.m = c->cfg.m;
+    F.lm = log2i(c->cfg.m);
+    F.meqn = c->meqn;
+    F.physics = c->cfg.physics;
+    F.patch_base = int32_t(pbase);
+    F.slot_base = int32_t(slot_base);
+    F.state_base = sbase;
+    F.phi_base = phi_elems;
+    F.ph = kphys(c);
+    b->fh.push_back(F);
+    b->state_off.push_back(sbase);
+    for (int64_t p = 0; p < P; ++p) {
+      PatchRec r = plan.recs[p];
+      for (int k = 0; k < 12; ++k)
+        if (r.nbr[k] >= 0) r.nbr[k] += int32_t(pbase);
+      recs.push_back(r);
+      phislot.push_back(plan.phislot[p] >= 0 ? plan.phislot[p] + int32_t(slot_base) : -1);
+      pforest.push_back(f);
+      const int T = F.m == 8 ? 8 : b->tile_big;
+      const int cls = T == 8 ? 0 : 1;
+      const int tps = F.m / T;
+      for (int t = 0; t < tps * tps; ++t) {
+        items[cls].push_back((uint32_t(pbase + p) << 4) | uint32_t(t));
+        cost[cls].push_back(F.physics == FCX_SHALLOW ? 3 : 1);
+      }
+    }
+    for (auto it : plan.reflux) {
+      it.coarse += int32_t(pbase);
+      for (int s2 = 0; s2 < 2; ++s2) it.fine[s2] += int32_t(pbase);
+      if (it.face < 2) { rx.push_back(it); rfx.push_back(f); }
+      else { ry.push_back(it); rfy.push_back(f); }
+    }
+    slot_base += plan.nslots;
+    phi_elems += int64_t(plan.nslots) * 4 * F.m * F.meqn;
+    sbase += P * F.meqn * F.m * F.m;
+    pbase += P;
+    first.push_back(int32_t(pbase));
+  }
+  if (sbase >= (int64_t(1) << 31) || pbase >= (int64_t(1) << 27))
+    return fail(FCX_EINVAL, "batch too large");
+  b->P = pbase;
+  b->state_elems = sbase;
+  b->n_reflux_x = int32_t(rx.size());
+  b->n_reflux_y = int32_t(ry.size());
+  rx.insert(rx.end(), ry.begin(), ry.end());
+  rfx.insert(rfx.end(), rfy.begin(), rfy.end());
+  // per class: XCD ranges of equal cost
+  std::vector<int32_t> ranges(18, 0);
+  std::vector<uint32_t> all;
+  for (int cls = 0; cls < 2; ++cls) {
+    b->item0[cls] = int32_t(all.size());
+    b->nitems[cls] = int32_t(items[cls].size());
+    int64_t tot = 0;
+    for (int32_t v : cost[cls]) tot += v;
+    int64_t acc = 0;
+    int x = 1;
+    ranges[cls * 9] = b->item0[cls];
+    for (size_t i = 0; i < items[cls].size(); ++i) {
+      acc += cost[cls][i];
+      while (x < 8 && acc * 8 >= tot * x) ranges[cls * 9 + x++] = b->item0[cls] + int32_t(i + 1);
+    }
+    while (x <= 8) ranges[cls * 9 + x++] = b->item0[cls] + int32_t(items[cls].size());
+    all.insert(all.end(), items[cls].begin(), items[cls].end());
+  }
+  // one packed upload
+  const size_t sz[9] = {recs.size() * sizeof(PatchRec), phislot.size() * 4,
+                        pforest.size() * 4, b->fh.size() * sizeof(ForestDev),
+                        all.size() * 4, ranges.size() * 4, rx.size() * sizeof(RefluxItem),
+                        rfx.size() * 4, first.size() * 4};
+  const void* src[9] = {recs.data(), phislot.data(), pforest.data(), b->fh.data(),
+                        all.data(), ranges.data(), rx.data(), rfx.data(), first.data()};
+  size_t off[9], at = 0;
+  for (int k = 0; k < 9; ++k) { off[k] = at; at += align256(sz[k]); }
+  HIPCHK(b->staging.ensure(at));
+  for (int k = 0; k < 9; ++k)
+    if (sz[k]) std::memcpy(b->staging.p + off[k], src[k], sz[k]);
+  HIPCHK(b->blob.ensure(at));
+  HIPCHK(hipMemcpy(b->blob.p, b->staging.p, at, hipMemcpyHostToDevice));
+  uint8_t* d = b->blob.p;
+  b->rec = reinterpret_cast<PatchRec*>(d + off[0]);
+  b->phislot = reinterpret_cast<int32_t*>(d + off[1]);
+  b->pforest = reinterpret_cast<int32_t*>(d + off[2]);
+  b->forests = reinterpret_cast<ForestDev*>(d + off[3]);
+  b->items = reinterpret_cast<uint32_t*>(d + off[4]);
+  b->range = reinterpret_cast<int32_t*>(d + off[5]);
+  b->reflux = reinterpret_cast<RefluxItem*>(d + off[6]);
+  b->reflux_forest = reinterpret_cast<int32_t*>(d + off[7]);
+  b->first = reinterpret_cast<int32_t*>(d + off[8]);
+  const size_t esz = b->precision == 64 ? 8 : 4;
+  HIPCHK(b->phi.ensure(size_t(phi_elems) * esz));
+  HIPCHK(b->partial.ensure(size_t(pbase) * 4));
+  HIPCHK(b->counters.ensure(16));
+  return FCX_OK;
+}
+
+int fcx_batch_create(int32_t n, fcx_ctx* const* forests, fcx_batch** out) {
+  if (n <= 0 || !forests || !out) return fail(FCX_EINVAL, "bad arguments");
+  *out = nullptr;
+  for (int f = 0; f < n; ++f) {
+    if (!forests[f] || !forests[f]->have_forest)
+      return fail(FCX_ESTATE, "every context needs an uploaded forest");
+    if (forests[f]->cfg.precision != forests[0]->cfg.precision)
+      return fail(FCX_EINVAL, "all forests of a batch share one precision");
+  }
+  fcx_batch* b = new fcx_batch;
+  b->n = n;
+  b->ctx.assign(forests, forests + n);
+  b->precision = forests[0]->cfg.precision;
+  b->cfl_desired = forests[0]->cfg.cfl_desired;
+  b->cfl_max = forests[0]->cfg.cfl_max;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    b->cus = prop.multiProcessorCount;
+  int rc = batch_build(b);
+  if (rc == FCX_OK && b->err.ensure(1) != hipSuccess) rc = fail(FCX_ENOMEM, "hipMalloc failed");
+  if (rc == FCX_OK && hipMemset(b->err.p, 0, 4) != hipSuccess) rc = fail(FCX_EHIP, "hipMemset failed");
+  if (rc != FCX_OK) { delete b; return rc; }
+  *out = b;
+  return FCX_OK;
+}
+
+int fcx_batch_destroy(fcx_batch* b) {
+  delete b;
+  return FCX_OK;
+}
+
+int64_t fcx_batch_state_elems(const fcx_batch* b) { return b ? b->state_elems : -1; }
+int64_t fcx_batch_state_offset(const fcx_batch* b, int32_t f) {
+  return (b && f >= 0 && f < b->n) ? b->state_off[f] : -1;
+}
+int64_t fcx_batch_num_patches(const fcx_batch* b) { return b ? b->P : -1; }
+
+int fcx_batch_set_tuning(fcx_batch* b, int32_t tile_big, int32_t threads8,
+                         int32_t threads16, int32_t wg_per_cu) {
+  if (!b || (tile_big != 8 && tile_big != 16) || (threads8 != 64 && threads8 != 128) ||
+      (threads16 != 256 && threads16 != 512) || wg_per_cu < 0 || wg_per_cu > 16)
+    return fail(FCX_EINVAL, "bad tuning");
+  const bool rebuild = tile_big != b->tile_big;
+  b->tile_big = tile_big;
+  b->threads8 = threads8;
+  b->threads16 = threads16;
+  b->wg_per_cu = wg_per_cu;
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  return rebuild ? batch_build(b) : FCX_OK;
+}
+
+template <typename R, int T, int NT>
+static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
+                              const double* dt, double* numax, hipStream_t s) {
+  if (b->nitems[cls] == 0) return FCX_OK;
+  BatchArgs<R> B;
+  B.q = static_cast<const R*>(q);
+  B.qn = static_cast<R*>(qn);
+  B.dt = dt;
+  B.numax = numax;
+  B.rec = b->rec;
+  B.phislot = b->phislot;
+  B.pforest = b->pforest;
+  B.forests = b->forests;
+  B.phi = reinterpret_cast<R*>(b->phi.p);
+  B.err = b->err.p;
+  B.items = b->items;
+  B.range = b->range + cls * 9;
+  B.counters = b->counters.p + cls * 8;
+  // resident workgroups: LDS allows about 160 KB / sizeof(tile LDS) per CU
+  int per_cu = b->wg_per_cu;
+  if (per_cu == 0) {
+    const int lds = int(sizeof(TileLds<R, FCX_SHALLOW, T, NT>));
+    per_cu = std::max(1, std::min(160 * 1024 / (lds + 64), 32 * 64 / NT));
+  }
+  int grid = std::min(b->cus * per_cu, (b->nitems[cls] + 7) / 8 * 8);
+  grid = std::max(8, (grid + 7) / 8 * 8);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->counters.p + cls * 8, 8);
+  hipLaunchKernelGGL((k_batch_step<R, T, NT>), dim3(grid), dim3(NT), 0, s, B);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+template <typename R>
+static int batch_step_t(fcx_batch* b, const void* q, void* qn, double* dt,
+                        double* numax, int32_t* status, hipStream_t s) {
+  int rc = b->threads8 == 128 ? launch_batch_class<R, 8, 128>(b, 0, q, qn, dt, numax, s)
+                              : launch_batch_class<R, 8, 64>(b, 0, q, qn, dt, numax, s);
+  if (rc != FCX_OK) return rc;
+  rc = b->threads16 == 512 ? launch_batch_class<R, 16, 512>(b, 1, q, qn, dt, numax, s)
+                           : launch_batch_class<R, 16, 256>(b, 1, q, qn, dt, numax, s);
+  if (rc != FCX_OK) return rc;
+  for (int axis = 0; axis < 2; ++axis) {
+    const int32_t n = axis == 0 ? b->n_reflux_x : b->n_reflux_y;
+    if (n == 0) continue;
+    const int32_t o = axis == 0 ? 0 : b->n_reflux_x;
+    const int64_t tot = int64_t(n) * 32;
+    hipLaunchKernelGGL((k_batch_reflux<R>), dim3(unsigned((tot + 255) / 256)), dim3(256),
+                       0, s, static_cast<const R*>(q), static_cast<R*>(qn),
+                       b->reflux + o, b->reflux_forest + o, n, b->rec, b->phislot,
+                       b->forests, reinterpret_cast<const R*>(b->phi.p), dt, b->err.p);
+    HIPCHK(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_next_dt, dim3((b->n + 63) / 64), dim3(64), 0, s, numax, dt,
+                     status, b->err.p, b->n, b->cfl_desired, b->cfl_max);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_batch_step(fcx_batch* b, const void* q, void* qn, double* dt, double* numax,
+                   int32_t* status, void* stream) {
+  if (!b || !q || !qn || q == qn || !dt || !numax || !status)
+    return fail(FCX_EINVAL, "bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return b->precision == 64 ? batch_step_t<double>(b, q, qn, dt, numax, status, s)
+                            : batch_step_t<float>(b, q, qn, dt, numax, status, s);
+}
+
+int fcx_batch_capture(fcx_batch* b, int32_t steps, void* qa, void* qb, double* dt,
+                      double* numax, int32_t* status) {
+  if (!b || steps <= 0 || !qa || !qb || qa == qb || !dt || !numax || !status)
+    return fail(FCX_EINVAL, "bad arguments");
+  if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+  if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+  if (!b->cap) HIPCHK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+  int rc = FCX_OK;
+  for (int k = 0; k < steps && rc == FCX_OK; ++k) {
+    void* src = (k & 1) ? qb : qa;
+    void* dst = (k & 1) ? qa : qb;
+    rc = fcx_batch_step(b, src, dst, dt, numax, status, b->cap);
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(b->cap, &g);
+  if (rc != FCX_OK) { if (g) (void)hipGraphDestroy(g); return rc; }
+  HIPCHK(e);
+  b->graph = g;
+  HIPCHK(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+  return FCX_OK;
+}
+
+int fcx_batch_replay(fcx_batch* b, void* stream) {
+  if (!b || !b->exec) return fail(FCX_ESTATE, "nothing captured");
+  HIPCHK(hipGraphLaunch(b->exec, static_cast<hipStream_t>(stream)));
+  return FCX_OK;
+}
+
+template <typename R>
+static int batch_sums_t(fcx_batch* b, const void* q, double* sums, hipStream_t s) {
+  hipLaunchKernelGGL((k_batch_sums_patch<R>), dim3(unsigned(b->P)), dim3(256), 0, s,
+                     static_cast<const R*>(q), b->rec, b->pforest, b->forests,
+                     b->partial.p);
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL((k_sums_reduce<4>), dim3(unsigned(b->n)), dim3(1024), 0, s,
+                     b->partial.p, b->first, sums);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_batch_sums(fcx_batch* b, const void* q, double* sums, void* stream) {
+  if (!b || !q || !sums) return fail(FCX_EINVAL, "bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  return b->precision == 64 ? batch_sums_t<double>(b, q, sums, s)
+                            : batch_sums_t<float>(b, q, sums, s);
+}

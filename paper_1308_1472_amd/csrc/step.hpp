@@ -103,23 +103,39 @@ __device__ __forceinline__ void simple_halo(const R* __restrict__ q,
   }
 }
 
+// LDS layout of one tile update (carved from a caller-provided buffer so that
+// kernels handling several physics share one allocation).
+template <typename R, int PHYS, int T, int NT>
+struct TileLds {
+  static constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  static constexpr int WD = PHYS == FCX_ADVECTION ? 1 : 6;   // wave data per edge
+  static constexpr int NPR = PHYS == FCX_ADVECTION ? 1 : 3;  // primitives per cell
+  static constexpr int F = T + 4, NR = T + 2, NE = T + 3;
+  R qs[MEQN][F * F];
+  R pr[NPR][F * F];
+  R wb[WD][NR * NE];
+  R fn[MEQN][T * T];          // normal fluxes, per interior cell
+  R tup[MEQN][NR * T];        // transverse flux at a cell's upper
+  R tdn[MEQN][NR * T];        //   and lower transverse edge
+  R fb[2][MEQN][T];           // normal terms at the tile's two faces
+  double red[NT / 64 > 0 ? NT / 64 : 1];
+};
+
 template <typename R, int PHYS, int T, int NT, bool FUSED>
-__device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, int ty) {
+__device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, int ty,
+                                          TileLds<R, PHYS, T, NT>& L) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
-  constexpr int WD = PHYS == FCX_ADVECTION ? 1 : 6;   // wave data per edge
-  constexpr int NPR = PHYS == FCX_ADVECTION ? 1 : 3;  // primitives per cell
   constexpr int F = T + 4, NR = T + 2, NE = T + 3;
   constexpr int CPT = (T * T + NT - 1) / NT;
   constexpr int EPT = (NR * (T + 1) + NT - 1) / NT;   // phase-B edges per thread
-
-  __shared__ R qs[MEQN][F * F];
-  __shared__ R pr[NPR][F * F];
-  __shared__ R wb[WD][NR * NE];
-  __shared__ R fn[MEQN][T * T];          // normal fluxes, per interior cell
-  __shared__ R tup[MEQN][NR * T];        // transverse flux at a cell's upper
-  __shared__ R tdn[MEQN][NR * T];        //   and lower transverse edge
-  __shared__ R fb[2][MEQN][T];           // normal terms at the tile's two faces
-  __shared__ double red[NT / 64 > 0 ? NT / 64 : 1];
+  auto& qs = L.qs;
+  auto& pr = L.pr;
+  auto& wb = L.wb;
+  auto& fn = L.fn;
+  auto& tup = L.tup;
+  auto& tdn = L.tdn;
+  auto& fb = L.fb;
+  auto& red = L.red;
 
   const int m = A.m, lm = A.lm;
   const int tid = threadIdx.x;
@@ -456,11 +472,12 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
 template <typename R, int PHYS, int T, int NT, bool FUSED>
 __global__ void __launch_bounds__(NT)
 k_step(StepArgs<R> A) {
+  __shared__ TileLds<R, PHYS, T, NT> lds;
   const int t = xcd_tile(blockIdx.x, A.ntiles);
   const int tps = A.m / T;
   const int p = t / (tps * tps);
   const int tile = t - p * (tps * tps);
-  tile_step<R, PHYS, T, NT, FUSED>(A, p, tile % tps, tile / tps);
+  tile_step<R, PHYS, T, NT, FUSED>(A, p, tile % tps, tile / tps, lds);
 }
 
 }  // namespace fcx

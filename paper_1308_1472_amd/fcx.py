@@ -32,7 +32,10 @@ EXPORTS = [
     "fcx_state_elems", "fcx_ghost_elems", "fcx_get_leaves", "fcx_ghost_fill",
     "fcx_patch_step", "fcx_fused_step", "fcx_reflux", "fcx_next_dt",
     "fcx_conservation_sums", "fcx_regrid_tags", "fcx_regrid_apply",
-    "fcx_regrid_transfer",
+    "fcx_regrid_transfer", "fcx_batch_create", "fcx_batch_destroy",
+    "fcx_batch_state_elems", "fcx_batch_state_offset", "fcx_batch_num_patches",
+    "fcx_batch_set_tuning", "fcx_batch_step", "fcx_batch_capture",
+    "fcx_batch_replay", "fcx_batch_sums",
 ]
 
 
@@ -88,6 +91,18 @@ def lib():
         L.fcx_regrid_tags.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp]
         L.fcx_regrid_apply.argtypes = [vp, vp, i32, i32, vp]
         L.fcx_regrid_transfer.argtypes = [vp, vp, vp, vp, vp]
+        L.fcx_batch_create.argtypes = [i32, vp, vp]
+        L.fcx_batch_destroy.argtypes = [vp]
+        for f in ("fcx_batch_state_elems", "fcx_batch_num_patches"):
+            getattr(L, f).argtypes = [vp]
+            getattr(L, f).restype = i64
+        L.fcx_batch_state_offset.argtypes = [vp, i32]
+        L.fcx_batch_state_offset.restype = i64
+        L.fcx_batch_set_tuning.argtypes = [vp, i32, i32, i32, i32]
+        L.fcx_batch_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fcx_batch_capture.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.fcx_batch_replay.argtypes = [vp, vp]
+        L.fcx_batch_sums.argtypes = [vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -272,3 +287,70 @@ class Context:
         _check(lib().fcx_regrid_transfer(self.h, C.c_void_p(q_old.data_ptr()),
                                          C.c_void_p(ghost_old.data_ptr()),
                                          self._q(q_new), _stream(stream)))
+
+
+class Batch:
+    """Independent forests advanced together (fcx_batch).  The contexts
+    must outlive the batch; the binding keeps references to them."""
+
+    def __init__(self, contexts):
+        self.contexts = list(contexts)
+        arr = (C.c_void_p * len(self.contexts))(*[c.h.value for c in self.contexts])
+        h = C.c_void_p()
+        _check(lib().fcx_batch_create(len(self.contexts), arr, C.byref(h)))
+        self.h = h
+        self.n = len(self.contexts)
+        self.precision = self.contexts[0].cfg.precision
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib().fcx_batch_destroy(self.h)
+            self.h = None
+
+    def state_elems(self) -> int:
+        return lib().fcx_batch_state_elems(self.h)
+
+    def state_offset(self, f) -> int:
+        return lib().fcx_batch_state_offset(self.h, f)
+
+    def num_patches(self) -> int:
+        return lib().fcx_batch_num_patches(self.h)
+
+    def set_tuning(self, tile_big=16, threads8=64, threads16=256, wg_per_cu=0):
+        _check(lib().fcx_batch_set_tuning(self.h, tile_big, threads8, threads16,
+                                          wg_per_cu))
+
+    def _q(self, t):
+        import torch
+        dt = torch.float64 if self.precision == 64 else torch.float32
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt
+                and t.is_contiguous() and t.numel() == self.state_elems()):
+            raise ValueError("expected the batch state tensor")
+        return C.c_void_p(t.data_ptr())
+
+    def _per_forest(self, t, dtype):
+        return Context._d(t, self.n, dtype)
+
+    def step(self, q, q_new, dt, numax, status, stream=None):
+        import torch
+        _check(lib().fcx_batch_step(self.h, self._q(q), self._q(q_new),
+                                    self._per_forest(dt, torch.float64),
+                                    self._per_forest(numax, torch.float64),
+                                    self._per_forest(status, torch.int32),
+                                    _stream(stream)))
+
+    def capture(self, steps, q_a, q_b, dt, numax, status):
+        import torch
+        _check(lib().fcx_batch_capture(self.h, steps, self._q(q_a), self._q(q_b),
+                                       self._per_forest(dt, torch.float64),
+                                       self._per_forest(numax, torch.float64),
+                                       self._per_forest(status, torch.int32)))
+
+    def replay(self, stream=None):
+        _check(lib().fcx_batch_replay(self.h, _stream(stream)))
+
+    def sums(self, q, out, stream=None):
+        import torch
+        _check(lib().fcx_batch_sums(self.h, self._q(q),
+                                    Context._d(out, 4 * self.n, torch.float64),
+                                    _stream(stream)))

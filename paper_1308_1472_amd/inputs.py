@@ -372,3 +372,46 @@ def batch_forest_spec(seed: int) -> dict:
         spec.update(cx=cx, cy=cy, r=0.15 + 0.15 * g.uniform(),
                     hin=1.5 + 1.5 * g.uniform())
     return spec
+
+
+def batch_forest(seed: int, lmin: int = 2, lmax: int = 8):
+    """One forest of a batch: (spec, trees, placement, leaves, initial-data
+    function).  Mesh: uniform at lmin, then repeatedly refine the leaves
+    closest to the feature (the Gaussian's centre, or the dam's rim) below
+    lmax until there are at least spec["target"] leaves (not balanced)."""
+    spec = batch_forest_spec(seed)
+    if spec["physics"] == "advection":
+        trees, pl = periodic_square()
+        cx, cy = spec["cx"], spec["cy"]
+        def dist(x, y):
+            return np.hypot(x - cx, y - cy)
+        w2 = spec["width2"]
+        fn = lambda x, y: periodic_gaussian(x, y, cx, cy, w2)
+    else:
+        trees, pl = walled_square()
+        cx, cy, r = spec["cx"], spec["cy"], spec["r"]
+        def dist(x, y):
+            return np.abs(np.hypot(x - cx, y - cy) - r)
+        fn = lambda x, y: dam_break(x, y, cx, cy, r, spec["hin"], 1.0)
+    leaves = [tuple(a) for a in uniform_leaves(1, lmin).tolist()]
+    target = spec["target"]
+    while len(leaves) < target:
+        arr = np.array(leaves, dtype=LEAF_DTYPE)
+        h = np.ldexp(1.0, -arr["level"].astype(np.int64))
+        d = dist((arr["ix"] + 0.5) * h, (arr["iy"] + 0.5) * h)
+        d = np.where(arr["level"] < lmax, d, np.inf)
+        order = np.lexsort((np.arange(len(arr)), d))
+        k = max(1, -(-(target - len(leaves)) // 3))
+        pick = [int(i) for i in order[:k] if np.isfinite(d[i])]
+        if not pick:
+            break
+        chosen = set(pick)
+        nxt = []
+        for i, (t, l, x, y) in enumerate(leaves):
+            if i in chosen:
+                for c in range(4):
+                    nxt.append((t, l + 1, 2 * x + (c & 1), 2 * y + (c >> 1)))
+            else:
+                nxt.append((t, l, x, y))
+        leaves = nxt
+    return spec, trees, pl, np.array(leaves, dtype=LEAF_DTYPE), fn
