@@ -46,7 +46,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "large", "all"], default="all")
+    ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "all"],
+                    default="all")
+    ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     return ap.parse_args()
@@ -196,6 +198,69 @@ def run(precision, fused, steps, warmup, uniform_level=None):
     }
 
 
+def run_batch(steps, warmup, nforests=64, graph_steps=10):
+    """The 64-forest batch: seeded forests (advection or shallow water by
+    seed parity, m in {8, 16, 32}, patch counts log-uniform in 16..16384,
+    levels 2..8), FP32, one persistent launch per tile class, captured in a
+    graph of `graph_steps` steps, tunables from the autotuner."""
+    import torch
+    from paper_1308_1472_amd import autotune, fcx
+    from paper_1308_1472_amd import inputs as I
+    ctxs, states = [], []
+    for seed in range(nforests):
+        spec, trees, pl, raw, fn = I.batch_forest(seed)
+        lv = fcx.balance(trees, raw)
+        phys = fcx.FCX_ADVECTION if spec["physics"] == "advection" else fcx.FCX_SHALLOW
+        cfg = fcx.config(spec["m"], 32, phys, ax=spec.get("ax", 0.0),
+                         ay=spec.get("ay", 0.0))
+        ctx = fcx.Context(cfg, trees)
+        ctx.upload_forest(lv)
+        ctxs.append(ctx)
+        states.append(I.state_from(lv, spec["m"], fn, pl))
+    batch = fcx.Batch(ctxs)
+    q = torch.empty(batch.state_elems(), dtype=torch.float32, device="cuda")
+    for f, st in enumerate(states):
+        o = batch.state_offset(f)
+        q[o:o + st.size].copy_(torch.from_numpy(st.ravel()))
+    cells = float(sum(st.size // c.meqn for st, c in zip(states, ctxs)))
+    # algorithmic bytes: read and write every state value once (FP32)
+    step_bytes = float(sum(st.size * 4 * 2 for st in states))
+    best, timings = autotune.tune(batch, q, steps=2, reps=2)
+    qa, qb = q.clone(), torch.empty_like(q)
+    n = batch.n
+    # per-forest dt at Courant number 0.45 of its finest cells
+    dts = []
+    for c, st in zip(ctxs, states):
+        lv = c.leaves()
+        h = 1.0 / (c.cfg.m << int(lv["level"].max()))
+        speed = 1.0 if c.meqn == 1 else 2.0 ** 0.5 * 1.5
+        dts.append(0.45 * h / speed)
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    nu = torch.zeros(n, dtype=torch.float64, device="cuda")
+    status = torch.zeros(n, dtype=torch.int32, device="cuda")
+    batch.capture(graph_steps, qa, qb, dt, nu, status)
+    for _ in range(max(1, warmup // graph_steps)):
+        batch.replay()
+    torch.cuda.synchronize()
+    reps = max(1, steps // graph_steps)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    a.record()
+    for _ in range(reps):
+        batch.replay()
+    b.record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms = a.elapsed_time(b)
+    nst = reps * graph_steps
+    return {"forests": n, "patches": batch.num_patches(), "cells": cells,
+            "steps": nst, "seconds": el, "rate": cells * nst / el,
+            "ms_per_step": ms / nst, "tuning": best,
+            "status_flags": int((status != 0).sum().item()),
+            "bytes_per_step": step_bytes}
+
+
 def cpu_baseline(budget_s=12.0):
     """The CPU FP64 oracle, single-threaded, on the first steps of the same
     workload (same initial mesh, regrid every 4 steps)."""
@@ -264,7 +329,13 @@ def main():
         print(f"# large fp32: {res['large32']}", file=sys.stderr, flush=True)
         res["large64"] = run(64, False, args.large_steps, 3, uniform_level=8)
         print(f"# large fp64: {res['large64']}", file=sys.stderr, flush=True)
+    if args.only in ("batch", "all"):
+        res["batch"] = run_batch(args.batch_steps, 10)
+        print(f"# batch fp32: {res['batch']}", file=sys.stderr, flush=True)
     head = res.get("fp32") or res.get("fp64") or res.get("large32")
+    if head is None:
+        print(json.dumps({"batch": res.get("batch")}), flush=True)
+        return
     steps = args.steps if "fp32" in res or "fp64" in res else args.large_steps
     bytes_per_cell = 24.0 if head is not res.get("fp64") else 48.0
 
@@ -318,8 +389,23 @@ def main():
             "fp64_roofline": roof(res["large64"], 48.0,
                                   "traffic_k_step_plain_sw_fp64_level8.txt"),
         }
-    if any(r["status"] for r in res.values()):
-        out["cfl_flags"] = {k: r["status"] for k, r in res.items()}
+    if "batch" in res:
+        rb = res["batch"]
+        ach = rb["bytes_per_step"] / (rb["ms_per_step"] * 1e-3) / 1e9
+        out["batched_64_forests"] = {
+            "workload": "64 seeded forests, advection or shallow water, m in "
+                        "{8,16,32}, 16..16384 patches each, levels 2-8, FP32, "
+                        "one persistent launch per tile class in a HIP graph",
+            "patches": rb["patches"], "cells": rb["cells"], "rate": rb["rate"],
+            "ms_per_step": rb["ms_per_step"], "tuning": rb["tuning"],
+            "hbm_GBps_algorithmic_whole_step": ach,
+            "hbm_frac_whole_step": ach / HBM_PEAK_GBS,
+            "speedup_vs_fp64_plain_adaptive": (rb["rate"] / res["fp64"]["rate"]
+                                               if "fp64" in res else None),
+        }
+    flags = {k: r["status"] for k, r in res.items() if "status" in r and r["status"]}
+    if flags:
+        out["cfl_flags"] = flags
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     print(json.dumps(out), flush=True)

@@ -79,8 +79,9 @@ typedef struct {
   int32_t transverse;  /* 0 none, 1 fluctuations, 2 fluctuations and
                           second-order corrections                         */
   int32_t tile;        /* cells per LDS tile side: 8 or 16 (0 = default) */
-  int32_t threads;     /* threads per tile workgroup: T*T or 2*T*T for
-                          T = 8, 256 or 512 for T = 16 (0 = default)       */
+  int32_t threads;     /* threads per tile workgroup: T*T or 2*T*T
+                          (0 = default: 512 for FP64 16 x 16 tiles, else
+                          T*T)                                              */
   int32_t reserved;    /* must be 0                                       */
   double g;            /* gravity (shallow water)                         */
   double ax, ay;       /* advection velocity in reference coordinates     */

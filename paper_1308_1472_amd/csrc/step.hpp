@@ -148,17 +148,58 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
   const uint32_t pbase = uint32_t(p) * MEQN << (2 * lm);
 
   // ---- stage the tile and its halo ----------------------------------
+  // interior cells first (coalesced), then the 8T + 12 halo cells strip by
+  // strip (bottom, top, left, right), so that the lanes of a wavefront
+  // mostly take the same ghost-cell path
   const bool simple = (rp.flags & kSimpleHalo) != 0;
   const int i0 = tx * T, j0 = ty * T;
-  for (int c = tid; c < F * F; c += NT) {
-    const int ci = c % F - 1, cj = c / F - 1;
+  auto stage = [&](int c, const R (&v)[MEQN]) {
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) qs[k][c] = v[k];
+    if (PHYS == FCX_SHALLOW) {
+      // primitives: sqrt(h), u, v (zero for a non-positive depth)
+      const R h = v[0];
+      if (h > R(0)) {
+        const R ih = rcp_(h);
+        pr[0][c] = sqrt_(h);
+        pr[1][c] = v[1] * ih;
+        pr[2][c] = v[2 % MEQN] * ih;
+      } else {
+        pr[0][c] = R(0);
+        pr[1][c] = R(0);
+        pr[2][c] = R(0);
+        atomicOr(A.err, kErrNegDepth);
+      }
+    }
+  };
+  for (int c = tid; c < T * T; c += NT) {
+    const int ci = c % T + 1, cj = c / T + 1;
+    const uint32_t o = pbase + (uint32_t(j0 + cj - 1) << lm) + (i0 + ci - 1);
+    R v[MEQN];
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) v[k] = A.q[o + (uint32_t(k) << (2 * lm))];
+    stage((cj + 1) * F + (ci + 1), v);
+  }
+  for (int h = tid; h < 8 * T + 12; h += NT) {
+    int ci, cj;
+    if (h < 2 * F - 2) {                     // bottom rows cj = -1, 0
+      const int r = h < F - 2 ? 0 : 1;
+      ci = r == 0 ? h : h - (F - 2) - 1;
+      cj = r == 0 ? -1 : 0;
+    } else if (h < 4 * F - 4) {              // top rows cj = T+1, T+2
+      const int g = h - (2 * F - 2);
+      const int r = g < F ? 0 : 1;
+      ci = r == 0 ? g - 1 : g - F;
+      cj = r == 0 ? T + 1 : T + 2;
+    } else {                                 // side columns, rows 1..T
+      const int g = h - (4 * F - 4);
+      cj = g / 4 + 1;
+      const int s2 = g % 4;
+      ci = s2 == 0 ? -1 : s2 == 1 ? 0 : s2 == 2 ? T + 1 : T + 2;
+    }
     const int i = i0 + ci, j = j0 + cj;
     R v[MEQN];
-    const bool outer = (ci == -1 || ci == T + 2) && (cj == -1 || cj == T + 2);
-    if (outer) {
-#pragma unroll
-      for (int k = 0; k < MEQN; ++k) v[k] = R(0);
-    } else if (i >= 1 && i <= m && j >= 1 && j <= m) {
+    if (i >= 1 && i <= m && j >= 1 && j <= m) {
       const uint32_t o = pbase + (uint32_t(j - 1) << lm) + (i - 1);
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) v[k] = A.q[o + (uint32_t(k) << (2 * lm))];
@@ -175,23 +216,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) v[k] = A.ghost[o + uint32_t(k) * G];
     }
-#pragma unroll
-    for (int k = 0; k < MEQN; ++k) qs[k][c] = v[k];
-    if (PHYS == FCX_SHALLOW) {
-      // primitives: sqrt(h), u, v (zero for a non-positive depth)
-      const R h = v[0];
-      if (h > R(0)) {
-        const R ih = rcp_(h);
-        pr[0][c] = sqrt_(h);
-        pr[1][c] = v[1] * ih;
-        pr[2][c] = v[2 % MEQN] * ih;
-      } else {
-        pr[0][c] = R(0);
-        pr[1][c] = R(0);
-        pr[2][c] = R(0);
-        if (!outer) atomicOr(A.err, kErrNegDepth);
-      }
-    }
+    stage((cj + 1) * F + (ci + 1), v);
   }
   __syncthreads();
 
