@@ -87,6 +87,18 @@ int  fco_regrid(const fco_mesh *mesh, const int8_t *tags, int32_t lmin,
 int  fco_transfer(const fco_mesh *old_mesh, const fco_mesh *new_mesh,
                   const fco_params *par, const double *q_old, double *q_new);
 
+/* ---- learned tagging (extension; see fco_mlp.c) ------------------- */
+int  fco_features(const fco_mesh *mesh, const fco_params *par, const double *q,
+                  double *feats);
+double fco_bf16(double x);
+double fco_mlp(const double *P, const double *norm, int64_t M, const double *x,
+               const int32_t *y, const double *cw, double scale, int32_t round,
+               double *logits, double *grad);
+void fco_adam(int64_t n, double *P, const double *g, double *m1, double *m2,
+              int32_t t, double lr, double beta1, double beta2, double eps);
+void fco_learned_tags(int64_t M, const double *logits, const int8_t *plain,
+                      double confidence, int8_t *tags);
+
 /* ---- pieces exposed for pinning ------------------------------------ */
 double fco_phi(int32_t limiter, double theta);
 int  fco_riemann(const fco_params *par, int32_t dir, const double *ql,

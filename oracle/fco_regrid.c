@@ -222,3 +222,39 @@ int fco_regrid(const fco_mesh *mesh, const int8_t *tags, int32_t lmin,
   free(tmp);
   return rc;
 }
+
+/* Per-patch statistics for learned tagging (an extension; the paper tags by
+ * a threshold on one criterion, Sec. 5).  For each of the first three
+ * components (zero where meqn is smaller): min, max and plain mean over the
+ * interior cells, and the largest |grad q_k| by the same central
+ * differences as criterion 1 (needs filled ghosts); then the level; then
+ * three zeros.  feats[p * 16 + f]. */
+int fco_features(const fco_mesh *mesh, const fco_params *par, const double *q,
+                 double *feats) {
+  const int32_t m = mesh->m, meqn = par->meqn;
+  for (int64_t p = 0; p < mesh->n; ++p) {
+    double *f = feats + p * 16;
+    for (int f0 = 0; f0 < 16; ++f0) f[f0] = 0.0;
+    for (int k = 0; k < 3 && k < meqn; ++k) {
+      double lo = INFINITY, hi = -INFINITY, sum = 0.0, gmax = 0.0;
+      for (int32_t j = 1; j <= m; ++j)
+        for (int32_t i = 1; i <= m; ++i) {
+          double v = qv(q, m, meqn, p, k, i, j);
+          lo = fmin(lo, v);
+          hi = fmax(hi, v);
+          sum += v;
+          double gx = (qv(q, m, meqn, p, k, i + 1, j) - qv(q, m, meqn, p, k, i - 1, j)) /
+                      spacing(mesh, p, i - 1, j, i + 1, j);
+          double gy = (qv(q, m, meqn, p, k, i, j + 1) - qv(q, m, meqn, p, k, i, j - 1)) /
+                      spacing(mesh, p, i, j - 1, i, j + 1);
+          gmax = fmax(gmax, sqrt(gx * gx + gy * gy));
+        }
+      f[4 * k + 0] = lo;
+      f[4 * k + 1] = hi;
+      f[4 * k + 2] = sum / ((double)m * m);
+      f[4 * k + 3] = gmax;
+    }
+    f[12] = mesh->leaves[p].level;
+  }
+  return 0;
+}

@@ -69,6 +69,13 @@ def lib():
         L.fco_phi.argtypes = [i32, dp]
         L.fco_phi.restype = dp
         L.fco_riemann.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.fco_features.argtypes = [vp, vp, vp, vp]
+        L.fco_bf16.argtypes = [dp]
+        L.fco_bf16.restype = dp
+        L.fco_mlp.argtypes = [vp, vp, i64, vp, vp, vp, dp, i32, vp, vp]
+        L.fco_mlp.restype = dp
+        L.fco_adam.argtypes = [i64, vp, vp, vp, vp, i32, dp, dp, dp, dp]
+        L.fco_learned_tags.argtypes = [i64, vp, vp, dp, vp]
         _lib = L
     return _lib
 
@@ -228,3 +235,56 @@ def advance(mesh, par, q, dt, reflux=True):
     ghost_fill(mesh, par, f)
     fn, nu = step(mesh, par, f, dt, reflux)
     return interior(fn, mesh.m), nu
+
+
+# -------------------------------------------------------------------------
+# learned tagging (an extension of the paper's criterion tagging)
+# -------------------------------------------------------------------------
+MLP_IN, MLP_HID, MLP_OUT = 16, 64, 3
+MLP_PARAMS = MLP_IN * MLP_HID + MLP_HID + MLP_HID * MLP_HID + MLP_HID + \
+    MLP_HID * MLP_OUT + MLP_OUT
+
+
+def features(mesh, par, qf) -> np.ndarray:
+    """(P, 16) per-patch statistics from a ghost-filled frame."""
+    out = np.zeros((len(mesh), MLP_IN))
+    lib().fco_features(mesh.h, C.byref(par), _ptr(qf), _ptr(out))
+    return out
+
+
+def bf16(x) -> np.ndarray:
+    f = lib().fco_bf16
+    return np.vectorize(f, otypes=[np.float64])(np.asarray(x, np.float64))
+
+
+def mlp(params, norm, x, y=None, cw=None, scale=1.0, round_bf16=True,
+        want_grad=True):
+    """Returns (loss, logits (M, 3), grad (5443,) or None)."""
+    P = np.ascontiguousarray(params, np.float64)
+    nm = np.ascontiguousarray(norm, np.float64)
+    x = np.ascontiguousarray(x, np.float64)
+    M = len(x)
+    assert P.size == MLP_PARAMS and nm.size == 2 * MLP_IN and x.shape[1] == MLP_IN
+    logits = np.zeros((M, MLP_OUT))
+    grad = np.zeros(MLP_PARAMS) if (want_grad and y is not None) else None
+    yy = None if y is None else np.ascontiguousarray(y, np.int32)
+    cw = np.ones(MLP_OUT) if cw is None else np.ascontiguousarray(cw, np.float64)
+    loss = lib().fco_mlp(_ptr(P), _ptr(nm), M, _ptr(x),
+                         None if yy is None else _ptr(yy), _ptr(cw), scale,
+                         int(round_bf16), _ptr(logits),
+                         None if grad is None else _ptr(grad))
+    return loss, logits, grad
+
+
+def adam(params, grad, m1, m2, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In place on float64 arrays."""
+    lib().fco_adam(params.size, _ptr(params), _ptr(np.ascontiguousarray(grad)),
+                   _ptr(m1), _ptr(m2), t, lr, beta1, beta2, eps)
+
+
+def learned_tags(logits, plain, confidence=0.6) -> np.ndarray:
+    z = np.ascontiguousarray(logits, np.float64)
+    pl = np.ascontiguousarray(plain, np.int8)
+    out = np.zeros(len(pl), np.int8)
+    lib().fco_learned_tags(len(pl), _ptr(z), _ptr(pl), confidence, _ptr(out))
+    return out
