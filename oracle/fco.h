@@ -98,6 +98,8 @@ void fco_adam(int64_t n, double *P, const double *g, double *m1, double *m2,
               int32_t t, double lr, double beta1, double beta2, double eps);
 void fco_learned_tags(int64_t M, const double *logits, const int8_t *plain,
                       double confidence, int8_t *tags);
+int  fco_dilate_tags(const fco_mesh *mesh, const int8_t *in, int32_t lmax,
+                     int8_t *out);
 
 /* ---- pieces exposed for pinning ------------------------------------ */
 double fco_phi(int32_t limiter, double theta);

@@ -258,3 +258,34 @@ int fco_features(const fco_mesh *mesh, const fco_params *par, const double *q,
   }
   return 0;
 }
+
+/* Refinement buffer for tags applied several steps after they are computed
+ * (an extension, used with learned tagging): a leaf below lmax that touches
+ * (over a face or a corner) a leaf tagged +1 is tagged +1 as well; other
+ * tags are unchanged.  The touching leaves are found by locating the
+ * centres of the first ghost ring of the patch at its own resolution. */
+int fco_dilate_tags(const fco_mesh *mesh, const int8_t *in, int32_t lmax,
+                    int8_t *out) {
+  const int32_t m = mesh->m;
+  for (int64_t p = 0; p < mesh->n; ++p) {
+    const fco_leaf *a = &mesh->leaves[p];
+    out[p] = in[p];
+    if (in[p] == 1 || a->level >= lmax) continue;
+    const int64_t side = (int64_t)1 << (FCO_S - a->level), half = side / (2 * m);
+    for (int32_t j = 0; j <= m + 1 && out[p] != 1; ++j)
+      for (int32_t i = 0; i <= m + 1; ++i) {
+        if (i != 0 && i != m + 1 && j != 0 && j != m + 1) continue;
+        const int64_t x = a->ix * side + (2 * i - 1) * half;
+        const int64_t y = a->iy * side + (2 * j - 1) * half;
+        int32_t t;
+        int64_t xx, yy;
+        if (fco_locate(mesh->trees, a->tree, x, y, &t, &xx, &yy) != 0) continue;
+        const int64_t q = fco_leaf_at(mesh, t, xx, yy);
+        if (q >= 0 && in[q] == 1) {
+          out[p] = 1;
+          break;
+        }
+      }
+  }
+  return 0;
+}

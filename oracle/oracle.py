@@ -76,6 +76,7 @@ def lib():
         L.fco_mlp.restype = dp
         L.fco_adam.argtypes = [i64, vp, vp, vp, vp, i32, dp, dp, dp, dp]
         L.fco_learned_tags.argtypes = [i64, vp, vp, dp, vp]
+        L.fco_dilate_tags.argtypes = [vp, vp, i32, vp]
         _lib = L
     return _lib
 
@@ -287,4 +288,11 @@ def learned_tags(logits, plain, confidence=0.6) -> np.ndarray:
     pl = np.ascontiguousarray(plain, np.int8)
     out = np.zeros(len(pl), np.int8)
     lib().fco_learned_tags(len(pl), _ptr(z), _ptr(pl), confidence, _ptr(out))
+    return out
+
+
+def dilate_tags(mesh, tg, lmax) -> np.ndarray:
+    tg = np.ascontiguousarray(tg, np.int8)
+    out = np.zeros_like(tg)
+    lib().fco_dilate_tags(mesh.h, _ptr(tg), lmax, _ptr(out))
     return out

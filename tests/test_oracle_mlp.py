@@ -202,3 +202,36 @@ def test_features_of_linear_data_are_exact():
         assert F[p, 12] == a["level"]
         assert np.all(F[p, 13:] == 0)
     assert inner >= 10
+
+
+@pytest.mark.parametrize("domain", ["walled", "periodic", "sphere"])
+def test_dilation_is_the_touching_neighbourhood(domain):
+    """A leaf below lmax becomes +1 exactly when a leaf it touches (closed
+    boxes intersect, found by brute force) is +1."""
+    from tests.helpers import leaf_boxes_cube, leaf_boxes_plane, touching_pairs
+    if domain == "sphere":
+        trees = I.cubed_sphere(); nt = 6
+    elif domain == "periodic":
+        trees, pl = I.periodic_square(); nt = 1
+    else:
+        trees, pl = I.walled_square(); nt = 1
+    lv = O.balance(trees, I.random_leaves(31, nt, 1, 5, 30))
+    mesh = O.Mesh(trees, lv, 8)
+    if domain == "sphere":
+        lo, hi = leaf_boxes_cube(lv)
+        pairs = touching_pairs(lo, hi)
+    else:
+        lo, hi = leaf_boxes_plane(lv, pl)
+        pairs = touching_pairs(lo, hi, (1.0, 1.0) if domain == "periodic" else None)
+    rng = np.random.default_rng(4)
+    tg = rng.choice(np.array([-1, 0, 0, 0, 0, 1], np.int8), len(lv))
+    lmax = 4
+    out = O.dilate_tags(mesh, tg, lmax)
+    want = tg.copy()
+    for a, b in pairs:
+        if tg[b] == 1 and lv[a]["level"] < lmax:
+            want[a] = 1
+        if tg[a] == 1 and lv[b]["level"] < lmax:
+            want[b] = 1
+    assert np.array_equal(out, want)
+    assert np.sum(out == 1) > np.sum(tg == 1)
