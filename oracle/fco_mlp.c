@@ -16,8 +16,9 @@
  * bfloat16 (8 significant bits, round to nearest, ties to even): the
  * standardised inputs, the three weight matrices, both hidden activations,
  * and in the backward pass the logit gradient and both pre-activation
- * gradients; biases and element-wise work stay unrounded.  Everything is
- * evaluated in FP64, so the result is the exact value (to FP64 rounding)
+ * gradients; biases and element-wise work stay unrounded.  The standardised
+ * input that is rounded is formed in FP32 (see standardise32).  Everything
+ * else is evaluated in FP64, so the result is the exact value (to FP64 rounding)
  * of the network on those rounded operands.  With round = 0 it is the plain
  * FP64 network, whose gradient is exactly the derivative of its loss.
  *
@@ -42,6 +43,17 @@ double fco_bf16(double x) {
 
 static double rnd(double x, int round) { return round ? fco_bf16(x) : x; }
 
+/* The rounded network standardises its inputs in FP32, (x - mu) * (1 / sigma)
+ * with each operation rounded to FP32, because the bfloat16 code of the
+ * result is a decision taken in the precision of the matrix-core network;
+ * the plain network standardises in FP64. */
+static double standardise32(double x, double mu, double sigma) {
+  const float d = (float)x - (float)mu;
+  const float is = 1.0f / (float)sigma;
+  const float v = d * is;
+  return (double)v;
+}
+
 static double gelu(double z) { return 0.5 * z * (1.0 + erf(z / sqrt(2.0))); }
 
 /* d/dz [z Phi(z)] = Phi(z) + z phi(z) */
@@ -64,7 +76,8 @@ double fco_mlp(const double *P, const double *norm, int64_t M, const double *x,
     /* forward */
     double xn[NI], z1[NH], h1[NH], z2[NH], h2[NH], z3[NO];
     for (int f = 0; f < NI; ++f)
-      xn[f] = rnd((x[r * NI + f] - norm[f]) / norm[NI + f], round);
+      xn[f] = round ? fco_bf16(standardise32(x[r * NI + f], norm[f], norm[NI + f]))
+                    : (x[r * NI + f] - norm[f]) / norm[NI + f];
     for (int o = 0; o < NH; ++o) {
       double s = 0.0;
       for (int f = 0; f < NI; ++f) s += xn[f] * W1[f * NH + o];
