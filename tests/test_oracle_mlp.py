@@ -170,7 +170,8 @@ def test_learned_tags_rule():
 def test_features_of_linear_data_are_exact():
     """h, hu, hv linear in x and y on an adaptive walled forest: on every
     patch away from the walls the min / max sit at the corner cell centres,
-    the mean at the patch centre, and max |grad| is the slope norm, because
+    the mean at the patch centre, and max |grad| is the slope norm (the
+    feature is its log1p), because
     copies, 2x2 means and limited interpolation all reproduce linear data."""
     trees, pl = I.walled_square()
     m = 8
@@ -197,7 +198,7 @@ def test_features_of_linear_data_are_exact():
         for k, c in enumerate(coef):
             corners = [c[0] + c[1] * xx + c[2] * yy for xx in (lo_x, hi_x) for yy in (lo_y, hi_y)]
             mid = c[0] + c[1] * (x0 + h / 2) + c[2] * (y0 + h / 2)
-            want = [min(corners), max(corners), mid, np.hypot(c[1], c[2])]
+            want = [min(corners), max(corners), mid, np.log1p(np.hypot(c[1], c[2]))]
             np.testing.assert_allclose(F[p, 4 * k:4 * k + 4], want, rtol=1e-11, atol=1e-12)
         assert F[p, 12] == a["level"]
         assert np.all(F[p, 13:] == 0)
