@@ -245,6 +245,69 @@ int fcx_batch_replay(fcx_batch *batch, void *stream);
  * reduced in a fixed order. */
 int fcx_batch_sums(fcx_batch *batch, const void *q, double *sums, void *stream);
 
+/* ---- learned tagging (an extension of the Sec. 5 criterion tags) ------
+ *
+ * A small network predicts, per patch, the tag the criterion will give a
+ * few steps later, so that regridding can run less often.  Inputs are 16
+ * per-patch statistics (fcx_features); the network is 16 -> 64 -> 64 -> 3
+ * with GELU (exact erf form) after both hidden layers; the 3 outputs are
+ * logits of refine / keep / coarsen.  Parameters (caller-owned device FP32
+ * array of FCX_MLP_PARAMS values, row = input unit, column = output unit):
+ *   W1[16][64] b1[64] W2[64][64] b2[64] W3[64][3] b3[3]
+ * norm (device FP32[32]): mu[16] then sigma[16]; inputs are used as
+ * (x - mu) / sigma.  Products run on the matrix cores with bfloat16
+ * operands (round to nearest even: normalised inputs, weights, hidden
+ * activations, and in the backward pass the logit and pre-activation
+ * gradients) and FP32 accumulation; the rest is FP32.  Row-major arrays:
+ * x[rows][16], logits[rows][3]. */
+#define FCX_MLP_INPUTS 16
+#define FCX_MLP_HIDDEN 64
+#define FCX_MLP_CLASSES 3
+#define FCX_MLP_PARAMS 5443
+
+/* feats[p * 16 + f] (device FP32): for each of the first three components
+ * (zero where meqn is smaller) its min, max and mean over the interior and
+ * log(1 + its largest |grad|) by central differences in reference
+ * coordinates; then the patch level; then three zeros.  Needs a ghost fill
+ * of q. */
+int fcx_features(fcx_ctx *ctx, const void *q, const void *ghost, float *feats,
+                 void *stream);
+
+/* logits[rows][3] of the network on x[rows][16]. */
+int fcx_mlp_forward(const float *params, const float *norm, int64_t rows,
+                    const float *x, float *logits, void *stream);
+
+/* Overwrites *loss with scale * sum_r class_weight[y_r] * (-log softmax_r[y_r])
+ * and grad[FCX_MLP_PARAMS] with its gradient (labels: device int32, 0
+ * refine, 1 keep, 2 coarsen; rows with other labels contribute nothing;
+ * class_weight: device FP32[3]).  Accumulation order is not fixed (FP32
+ * atomics), so results vary in the last bits between calls. */
+int fcx_mlp_backward(const float *params, const float *norm, int64_t rows,
+                     const float *x, const int32_t *labels,
+                     const float *class_weight, float scale, float *grad,
+                     float *loss, void *stream);
+
+/* One Adam update at step t >= 1 (Kingma and Ba 2015, with bias
+ * correction) of n parameters; m1 and m2 are the caller's moment arrays
+ * (zero before step 1). */
+int fcx_adam_step(int64_t n, float *params, const float *grad, float *m1,
+                  float *m2, int32_t t, float lr, float beta1, float beta2,
+                  float eps, void *stream);
+
+/* tags[r] (device int8) from logits with the criterion as fallback: +1
+ * where plain[r] is +1; plain[r] where the largest softmax probability is
+ * below `confidence`; otherwise +1 / 0 / -1 for the most likely class
+ * refine / keep / coarsen (lowest class on ties). */
+int fcx_learned_tags(int64_t rows, const float *logits, const int8_t *plain,
+                     float confidence, int8_t *tags, void *stream);
+
+/* Refinement buffer for tags used several steps after they were computed:
+ * out[p] = +1 if in[p] = +1, or if the level of p is below lmax and a patch
+ * touching p over a face or a corner has in = +1; out[p] = in[p] otherwise.
+ * in and out are device int8 arrays of one entry per patch; no aliasing. */
+int fcx_dilate_tags(fcx_ctx *ctx, const int8_t *in, int32_t lmax, int8_t *out,
+                    void *stream);
+
 #ifdef __cplusplus
 }
 #endif

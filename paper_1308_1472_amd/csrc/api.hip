@@ -12,6 +12,7 @@
 #include "aux_kernels.hpp"
 #include "batch.hpp"
 #include "forest.hpp"
+#include "mlp.hpp"
 #include "step.hpp"
 
 using namespace fcx;
@@ -897,4 +898,114 @@ int fcx_batch_sums(fcx_batch* b, const void* q, double* sums, void* stream) {
   hipStream_t s = static_cast<hipStream_t>(stream);
   return b->precision == 64 ? batch_sums_t<double>(b, q, sums, s)
                             : batch_sums_t<float>(b, q, sums, s);
+}
+
+// ---- learned tagging ----------------------------------------------------
+
+int fcx_features(fcx_ctx* c, const void* q, const void* ghost, float* feats,
+                 void* stream) {
+  if (!c || !q || !ghost || !feats) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cur.P == 0) return FCX_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const unsigned grid = unsigned(c->cur.P);
+  const int m = c->cfg.m;
+  const bool dp = c->cfg.precision == 64;
+  if (c->meqn == 1) {
+    if (dp)
+      hipLaunchKernelGGL((k_features<double, 1>), dim3(grid), dim3(256), 0, s,
+                         static_cast<const double*>(q), static_cast<const double*>(ghost),
+                         c->cur.rec, m, feats);
+    else
+      hipLaunchKernelGGL((k_features<float, 1>), dim3(grid), dim3(256), 0, s,
+                         static_cast<const float*>(q), static_cast<const float*>(ghost),
+                         c->cur.rec, m, feats);
+  } else {
+    if (dp)
+      hipLaunchKernelGGL((k_features<double, 3>), dim3(grid), dim3(256), 0, s,
+                         static_cast<const double*>(q), static_cast<const double*>(ghost),
+                         c->cur.rec, m, feats);
+    else
+      hipLaunchKernelGGL((k_features<float, 3>), dim3(grid), dim3(256), 0, s,
+                         static_cast<const float*>(q), static_cast<const float*>(ghost),
+                         c->cur.rec, m, feats);
+  }
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+static unsigned mlp_grid(int64_t rows, int64_t blocks_per_wave, unsigned cap) {
+  const int64_t blocks = (rows + 15) / 16;
+  const int64_t wg = (blocks + 4 * blocks_per_wave - 1) / (4 * blocks_per_wave);
+  return unsigned(std::max<int64_t>(1, std::min<int64_t>(wg, cap)));
+}
+
+int fcx_mlp_forward(const float* params, const float* norm, int64_t rows,
+                    const float* x, float* logits, void* stream) {
+  if (!params || !norm || rows < 0 || (rows > 0 && (!x || !logits)) ||
+      rows > (int64_t(1) << 40))
+    return fail(FCX_EINVAL, "bad arguments");
+  if (rows == 0) return FCX_OK;
+  hipLaunchKernelGGL(k_mlp_forward, dim3(mlp_grid(rows, 1, 2048)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), params, norm, x, rows, logits);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_mlp_backward(const float* params, const float* norm, int64_t rows,
+                     const float* x, const int32_t* labels, const float* class_weight,
+                     float scale, float* grad, float* loss, void* stream) {
+  if (!params || !norm || !class_weight || !grad || !loss || rows < 0 ||
+      (rows > 0 && (!x || !labels)) || rows > (int64_t(1) << 40))
+    return fail(FCX_EINVAL, "bad arguments");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_zero_f32, dim3((kMlpParams + 255) / 256), dim3(256), 0, s,
+                     grad, int64_t(kMlpParams));
+  HIPCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, loss, int64_t(1));
+  HIPCHK(hipGetLastError());
+  if (rows == 0) return FCX_OK;
+  hipLaunchKernelGGL(k_mlp_backward, dim3(mlp_grid(rows, 4, 256)), dim3(256), 0, s,
+                     params, norm, x, labels, class_weight, scale, rows, grad, loss);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_adam_step(int64_t n, float* params, const float* grad, float* m1, float* m2,
+                  int32_t t, float lr, float beta1, float beta2, float eps,
+                  void* stream) {
+  if (n < 0 || t < 1 || (n > 0 && (!params || !grad || !m1 || !m2)) ||
+      !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) ||
+      !(eps >= 0.0f))
+    return fail(FCX_EINVAL, "bad arguments");
+  if (n == 0) return FCX_OK;
+  hipLaunchKernelGGL(k_adam, dim3(unsigned((n + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), params, grad, m1, m2, n, t, lr,
+                     beta1, beta2, eps);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_learned_tags(int64_t rows, const float* logits, const int8_t* plain,
+                     float confidence, int8_t* tags, void* stream) {
+  if (rows < 0 || (rows > 0 && (!logits || !plain || !tags)))
+    return fail(FCX_EINVAL, "bad arguments");
+  if (rows == 0) return FCX_OK;
+  hipLaunchKernelGGL(k_learned_tags, dim3(unsigned((rows + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), logits, plain, rows, confidence,
+                     tags);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_dilate_tags(fcx_ctx* c, const int8_t* in, int32_t lmax, int8_t* out,
+                    void* stream) {
+  if (!c || !in || !out || in == out) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  const int64_t P = c->cur.P;
+  if (P == 0) return FCX_OK;
+  hipLaunchKernelGGL(k_dilate_tags, dim3(unsigned((P + 255) / 256)), dim3(256), 0,
+                     static_cast<hipStream_t>(stream), in, c->cur.rec, P, lmax, out);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
 }

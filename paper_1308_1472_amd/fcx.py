@@ -35,8 +35,11 @@ EXPORTS = [
     "fcx_regrid_transfer", "fcx_batch_create", "fcx_batch_destroy",
     "fcx_batch_state_elems", "fcx_batch_state_offset", "fcx_batch_num_patches",
     "fcx_batch_set_tuning", "fcx_batch_step", "fcx_batch_capture",
-    "fcx_batch_replay", "fcx_batch_sums",
+    "fcx_batch_replay", "fcx_batch_sums", "fcx_features", "fcx_mlp_forward",
+    "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
 ]
+
+MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
 
 
 class FcxError(RuntimeError):
@@ -103,6 +106,13 @@ def lib():
         L.fcx_batch_capture.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.fcx_batch_replay.argtypes = [vp, vp]
         L.fcx_batch_sums.argtypes = [vp, vp, vp, vp]
+        fl = C.c_float
+        L.fcx_features.argtypes = [vp, vp, vp, vp, vp]
+        L.fcx_mlp_forward.argtypes = [vp, vp, i64, vp, vp, vp]
+        L.fcx_mlp_backward.argtypes = [vp, vp, i64, vp, vp, vp, fl, vp, vp, vp]
+        L.fcx_adam_step.argtypes = [i64, vp, vp, vp, vp, i32, fl, fl, fl, fl, vp]
+        L.fcx_learned_tags.argtypes = [i64, vp, vp, fl, vp, vp]
+        L.fcx_dilate_tags.argtypes = [vp, vp, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -170,6 +180,58 @@ def _stream(stream):
         import torch
         return C.c_void_p(torch.cuda.current_stream().cuda_stream)
     return C.c_void_p(int(stream))
+
+
+def _dev(t, n, dtype):
+    """Pointer of a contiguous device tensor of `dtype` with >= n elements."""
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype
+            and t.is_contiguous() and t.numel() >= n):
+        raise ValueError(f"expected a contiguous {dtype} device tensor of "
+                         f">= {n} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+# ---- learned tagging: context-free network calls ------------------------
+def mlp_forward(params, norm, x, logits, stream=None):
+    import torch
+    rows = x.numel() // MLP_INPUTS
+    f32 = torch.float32
+    _check(lib().fcx_mlp_forward(_dev(params, MLP_PARAMS, f32), _dev(norm, 32, f32),
+                                 rows, _dev(x, rows * MLP_INPUTS, f32),
+                                 _dev(logits, rows * MLP_CLASSES, f32),
+                                 _stream(stream)))
+
+
+def mlp_backward(params, norm, x, labels, class_weight, scale, grad, loss,
+                 stream=None):
+    import torch
+    rows = x.numel() // MLP_INPUTS
+    f32 = torch.float32
+    _check(lib().fcx_mlp_backward(_dev(params, MLP_PARAMS, f32), _dev(norm, 32, f32),
+                                  rows, _dev(x, rows * MLP_INPUTS, f32),
+                                  _dev(labels, rows, torch.int32),
+                                  _dev(class_weight, MLP_CLASSES, f32), float(scale),
+                                  _dev(grad, MLP_PARAMS, f32), _dev(loss, 1, f32),
+                                  _stream(stream)))
+
+
+def adam_step(params, grad, m1, m2, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
+              stream=None):
+    import torch
+    n = params.numel()
+    f32 = torch.float32
+    _check(lib().fcx_adam_step(n, _dev(params, n, f32), _dev(grad, n, f32),
+                               _dev(m1, n, f32), _dev(m2, n, f32), int(t), lr, beta1,
+                               beta2, eps, _stream(stream)))
+
+
+def learned_tags(logits, plain, confidence, tags, stream=None):
+    import torch
+    rows = plain.numel()
+    _check(lib().fcx_learned_tags(rows, _dev(logits, 3 * rows, torch.float32),
+                                  _dev(plain, rows, torch.int8), float(confidence),
+                                  _dev(tags, rows, torch.int8), _stream(stream)))
 
 
 class Context:
@@ -273,6 +335,18 @@ class Context:
                                      lmin, lmax,
                                      self._d(tags, self.num_patches(), torch.int8),
                                      _stream(stream)))
+
+    def features(self, q, ghost, feats, stream=None):
+        import torch
+        _check(lib().fcx_features(self.h, self._q(q), self._g(ghost),
+                                  _dev(feats, MLP_INPUTS * self.num_patches(),
+                                       torch.float32), _stream(stream)))
+
+    def dilate_tags(self, tags_in, lmax, tags_out, stream=None):
+        import torch
+        n = self.num_patches()
+        _check(lib().fcx_dilate_tags(self.h, _dev(tags_in, n, torch.int8), lmax,
+                                     _dev(tags_out, n, torch.int8), _stream(stream)))
 
     def regrid_apply(self, tags_host, lmin, lmax) -> int:
         t = np.ascontiguousarray(tags_host, dtype=np.int8)

@@ -415,3 +415,11 @@ def batch_forest(seed: int, lmin: int = 2, lmax: int = 8):
                 nxt.append((t, l, x, y))
         leaves = nxt
     return spec, trees, pl, np.array(leaves, dtype=LEAF_DTYPE), fn
+
+
+def dam_break_spec(seed: int) -> dict:
+    """Random radial dam break of the learned-tagging runs: centre in
+    [0.3, 0.7]^2, radius in [0.15, 0.3], inner depth in [1.5, 3]."""
+    g = SplitMix64(0x5EED_DA4B_0000 + seed)
+    return {"centre": (0.3 + 0.4 * g.uniform(), 0.3 + 0.4 * g.uniform()),
+            "radius": 0.15 + 0.15 * g.uniform(), "h_in": 1.5 + 1.5 * g.uniform()}

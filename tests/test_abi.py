@@ -94,3 +94,14 @@ def test_regrid_leaves_matches_oracle(domain, seed):
         a = fcx.regrid_leaves(trees, lv, tg, lmin, lmax)
         b = O.regrid(O.Mesh(trees, lv, 8), tg, lmin, lmax)
         assert np.array_equal(a, b)
+
+
+def test_committed_tagger_weights_load_safely():
+    import json
+    from paper_1308_1472_amd import learned as L
+    z = np.load(L.WEIGHTS, allow_pickle=False)
+    assert z["params"].shape == (fcx.MLP_PARAMS,) and z["params"].dtype == np.float32
+    assert z["norm"].shape == (2 * fcx.MLP_INPUTS,) and np.all(z["norm"][16:] > 0)
+    meta = json.loads(str(z["meta"]))
+    assert meta["labels"] == "n+4" and meta["train_seeds"] == 180
+    assert np.all(np.isfinite(z["params"]))
