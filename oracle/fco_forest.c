@@ -96,8 +96,8 @@ int64_t fco_leaf_at(const fco_mesh *mesh, int32_t tree, int64_t x,
 /* tree.  The distance d beyond the face becomes the distance inside   */
 /* the neighbour's face; the tangential coordinate is kept or mirrored */
 /* according to the orientation.                                       */
-static int cross_face(const fco_tree *trees, int32_t t, int32_t f,
-                      int64_t *x, int64_t *y, int32_t *tout) {
+int fco_cross_face(const fco_tree *trees, int32_t t, int32_t f, int64_t *x,
+                   int64_t *y, int32_t *tout) {
   const fco_tree *T = &trees[t];
   if (T->bc[f] != 0) return -1;
   int32_t t2 = T->nbr_tree[f], f2 = T->nbr_face[f], o = T->orient[f];
@@ -128,7 +128,7 @@ static int walk(const fco_tree *trees, int32_t t, int64_t x, int64_t y,
     int f;
     if (fx >= 0 && fy >= 0) f = (axis == 0) ? fx : fy;
     else f = (fx >= 0) ? fx : fy;
-    if (cross_face(trees, t, f, &x, &y, &t) != 0) return 1;
+    if (fco_cross_face(trees, t, f, &x, &y, &t) != 0) return 1;
     axis = 1 - axis;
   }
   return 3;
@@ -235,6 +235,10 @@ fco_mesh *fco_mesh_new(int32_t ntrees, const fco_tree *trees, int64_t n,
     while (mesh->hslot[h] >= 0) h = (h + 1) & (uint64_t)(cap - 1);
     mesh->hslot[h] = s;
   }
+  if (sphere && (ntrees != 6 || fco_sphere_build(mesh) != 0)) {
+    fco_mesh_free(mesh);
+    return NULL;
+  }
   return mesh;
 }
 
@@ -243,6 +247,7 @@ void fco_mesh_free(fco_mesh *mesh) {
   free(mesh->trees);
   free(mesh->leaves);
   free(mesh->hslot);
+  free(mesh->geo);
   free(mesh);
 }
 

@@ -15,6 +15,7 @@ struct fco_mesh {
   int32_t maxlevel;
   int64_t hcap;
   int64_t *hslot;     /* open-addressing table of leaf indices, -1 = free */
+  double *geo;        /* sphere: per-patch cell and edge geometry (fco_sphere.c) */
 };
 
 /* frame index of cell (i, j), i, j in -1..m+2 */
@@ -30,10 +31,32 @@ int64_t fco_find(const fco_mesh *mesh, int32_t tree, int32_t level,
  * boundary, 2 at a valence-3 corner (no tree contains it), 3 otherwise. */
 int fco_locate(const fco_tree *trees, int32_t tree, int64_t x, int64_t y,
                int32_t *tout, int64_t *xout, int64_t *yout);
+/* Carry a point beyond face f of tree t into the neighbour tree (in place);
+ * -1 if the face is a physical boundary. */
+int fco_cross_face(const fco_tree *trees, int32_t t, int32_t f, int64_t *x,
+                   int64_t *y, int32_t *tout);
+/* geometry tables of a sphere mesh (called by fco_mesh_new) */
+int fco_sphere_build(fco_mesh *mesh);
 /* leaf (index) containing an in-tree point, -1 if none */
 int64_t fco_leaf_at(const fco_mesh *mesh, int32_t tree, int64_t x, int64_t y);
 /* 1 if face f of leaf p lies on a physical boundary of its tree */
 int fco_wall_face(const fco_mesh *mesh, int64_t p, int32_t f);
+
+/* geometry of one edge: gamma = arc length / computational length, unit
+ * normal n and unit tangent t (3D) */
+typedef struct {
+  double gamma;
+  double n[3], t[3];
+} fco_edge_geom;
+
+/* sphere solver pieces (fco_sphere.c) */
+int fco_rp_sphere(const fco_params *par, const fco_edge_geom *e, const double *ql,
+                  const double *qr, double *W, double *s, double *am,
+                  double *ap, double *fl);
+int fco_tsplit_sphere(const fco_params *par, const double *ql, const double *qr,
+                      const fco_edge_geom *tedge, const double *psi, double *out,
+                      int up);
+void fco_sphere_project(const fco_mesh *mesh, const fco_params *par, double *qn);
 
 /* Cell geometry of mapped (sphere) trees: capacity kappa of cell (i, j)
  * of patch p, computed from the mapping (fco_sphere.c). */

@@ -33,6 +33,13 @@
  * the coarse cell's face term is replaced by the sum of the fine face
  * terms.  The Roe property turns the missing f(Q_fine) - f(Q_coarse) into
  * the fluctuation sum of one extra Riemann problem per fine cell.
+ *
+ * Cubed sphere (reading): the mass component is in flux form, so its fine
+ * face terms replace the coarse one as they are; and at same-level faces
+ * across cube edges the mass face term of the higher-numbered patch is set
+ * to minus its neighbour's, which keeps mass exact also next to the cube
+ * vertices, where the two sides' transverse terms read different corner
+ * ghost values.
  */
 #include "fco_internal.h"
 
@@ -55,10 +62,7 @@ double fco_phi(int32_t limiter, double th) {
 }
 
 /* ---------------- edge geometry (Cartesian or mapped) ---------------- */
-typedef struct {
-  double gamma;       /* edge length / computational edge length */
-  double n[3], t[3];  /* sphere: unit normal and tangent */
-} edge_geom;
+typedef fco_edge_geom edge_geom;   /* gamma = 1 on Cartesian grids */
 
 /* ---------------- Riemann solvers ------------------------------------ */
 /* Normal solvers fill waves[w*meqn+k], speeds[w], amdq, apdq; return the
@@ -151,22 +155,14 @@ static int tsplit_shallow(const fco_params *par, int dir, const double *ql,
   return 0;
 }
 
-/* sphere solvers live in fco_sphere.c */
-int fco_rp_sphere(const fco_params *par, const edge_geom *e, const double *ql,
-                  const double *qr, double *W, double *s, double *am,
-                  double *ap);
-int fco_tsplit_sphere(const fco_params *par, const double *ql,
-                      const double *qr, const edge_geom *normal_edge,
-                      const edge_geom *tedge, const double *psi, double *bsdq,
-                      int up);
-
+/* sphere solvers live in fco_sphere.c; *fl receives the mass flux there */
 static int riemann(const fco_params *par, int dir, const edge_geom *e,
                    const double *ql, const double *qr, double *W, double *s,
-                   double *am, double *ap) {
+                   double *am, double *ap, double *fl) {
   switch (par->physics) {
     case FCO_ADVECTION: return rp_advection(par, dir, ql, qr, W, s, am, ap);
     case FCO_SHALLOW: return rp_shallow(par, dir, ql, qr, W, s, am, ap);
-    case FCO_SPHERE: return fco_rp_sphere(par, e, ql, qr, W, s, am, ap);
+    case FCO_SPHERE: return fco_rp_sphere(par, e, ql, qr, W, s, am, ap, fl);
     default: return -1;
   }
 }
@@ -175,13 +171,14 @@ int fco_riemann(const fco_params *par, int32_t dir, const double *ql,
                 const double *qr, double *waves, double *speeds, double *amdq,
                 double *apdq) {
   edge_geom e = {1.0, {0}, {0}};
-  return riemann(par, dir, &e, ql, qr, waves, speeds, amdq, apdq);
+  return riemann(par, dir, &e, ql, qr, waves, speeds, amdq, apdq, NULL);
 }
 
 /* ---------------- one patch ------------------------------------------ */
 typedef struct {
   int32_t m, meqn;
   double *F[2], *AM[2], *AP[2];   /* [edge 0..m+2][row 0..m+1][meqn] */
+  double *FL[2];                   /* sphere: mass flux [edge][row] */
   double *W, *S;                   /* one row: [edge][MW][meqn], [edge][MW] */
   double *kap;                     /* frame of capacities */
   edge_geom *eg;                   /* one row of edge geometry */
@@ -241,7 +238,7 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
         }
         nw = riemann(par, d, eg, ql, qr, &wk->W[e * MW * meqn], &wk->S[e * MW],
                      &wk->AM[d][eidx(m, e, r) * meqn],
-                     &wk->AP[d][eidx(m, e, r) * meqn]);
+                     &wk->AP[d][eidx(m, e, r) * meqn], &wk->FL[d][eidx(m, e, r)]);
         if (nw < 0) return -4;
       }
       /* limiter, correction and transverse terms at edges 1..m+1 */
@@ -301,9 +298,8 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
             edge_geom lo, hi;
             fco_sphere_edge(mesh, p, 1 - d, ci, cj, &lo.gamma, lo.n, lo.t);
             fco_sphere_edge(mesh, p, 1 - d, ui, uj, &hi.gamma, hi.n, hi.t);
-            rc = fco_tsplit_sphere(par, ql, qr, &wk->eg[e], &lo, psi, bm, 0);
-            if (rc == 0)
-              rc = fco_tsplit_sphere(par, ql, qr, &wk->eg[e], &hi, psi, bp, 1);
+            rc = fco_tsplit_sphere(par, ql, qr, &lo, psi, bm, 0);
+            if (rc == 0) rc = fco_tsplit_sphere(par, ql, qr, &hi, psi, bp, 1);
           }
           if (rc != 0) return -4;
           double *Flo = &FO[eidx(m, r, col) * meqn];
@@ -322,14 +318,18 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
     for (int32_t i = 1; i <= m; ++i) {
       double dtd = dt / (KAP(i, j) * dx);
       for (int k = 0; k < meqn; ++k) {
-        double fx = wk->AP[0][eidx(m, i, j) * meqn + k] +
-                    wk->AM[0][eidx(m, i + 1, j) * meqn + k] +
-                    wk->F[0][eidx(m, i + 1, j) * meqn + k] -
-                    wk->F[0][eidx(m, i, j) * meqn + k];
-        double gy = wk->AP[1][eidx(m, j, i) * meqn + k] +
-                    wk->AM[1][eidx(m, j + 1, i) * meqn + k] +
-                    wk->F[1][eidx(m, j + 1, i) * meqn + k] -
-                    wk->F[1][eidx(m, j, i) * meqn + k];
+        double fx, gy;
+        if (mesh->sphere && k == 0) {   /* mass in flux form */
+          fx = wk->FL[0][eidx(m, i + 1, j)] - wk->FL[0][eidx(m, i, j)];
+          gy = wk->FL[1][eidx(m, j + 1, i)] - wk->FL[1][eidx(m, j, i)];
+        } else {
+          fx = wk->AP[0][eidx(m, i, j) * meqn + k] + wk->AM[0][eidx(m, i + 1, j) * meqn + k];
+          gy = wk->AP[1][eidx(m, j, i) * meqn + k] + wk->AM[1][eidx(m, j + 1, i) * meqn + k];
+        }
+        fx = fx + (wk->F[0][eidx(m, i + 1, j) * meqn + k] -
+                   wk->F[0][eidx(m, i, j) * meqn + k]);
+        gy = gy + (wk->F[1][eidx(m, j + 1, i) * meqn + k] -
+                   wk->F[1][eidx(m, j, i) * meqn + k]);
         Qn[k * FR + fco_fidx(m, i, j)] =
             Q[k * FR + fco_fidx(m, i, j)] - dtd * fx - dtd * gy;
       }
@@ -340,17 +340,15 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
     for (int f = 0; f < 4; ++f)
       for (int32_t t = 1; t <= m; ++t)
         for (int k = 0; k < meqn; ++k) {
-          double v;
-          switch (f) {
-            case 0: v = wk->AP[0][eidx(m, 1, t) * meqn + k] -
-                        wk->F[0][eidx(m, 1, t) * meqn + k]; break;
-            case 1: v = wk->AM[0][eidx(m, m + 1, t) * meqn + k] +
-                        wk->F[0][eidx(m, m + 1, t) * meqn + k]; break;
-            case 2: v = wk->AP[1][eidx(m, 1, t) * meqn + k] -
-                        wk->F[1][eidx(m, 1, t) * meqn + k]; break;
-            default: v = wk->AM[1][eidx(m, m + 1, t) * meqn + k] +
-                         wk->F[1][eidx(m, m + 1, t) * meqn + k]; break;
-          }
+          const int fd = f / 2;
+          const int64_t ei = eidx(m, (f & 1) ? m + 1 : 1, t);
+          double fluct;
+          if (mesh->sphere && k == 0)   /* flux form: -F in, +F out */
+            fluct = (f & 1) ? wk->FL[fd][ei] : -wk->FL[fd][ei];
+          else
+            fluct = (f & 1) ? wk->AM[fd][ei * meqn + k] : wk->AP[fd][ei * meqn + k];
+          const double corr = wk->F[fd][ei * meqn + k];
+          const double v = (f & 1) ? fluct + corr : fluct - corr;
           phi[((int64_t)f * m + (t - 1)) * meqn + k] = dx * v;
         }
   }
@@ -407,6 +405,22 @@ static int reflux(const fco_mesh *mesh, const fco_params *par, const double *q,
           if (fine_cell(mesh, a->tree, xa, ya, &L, &fi, &fj, &tt, &X, &Y) != 0 ||
               fine_cell(mesh, a->tree, xb, yb, &L2, &fi2, &fj2, &tt2, &X2, &Y2) != 0)
             return -5;
+          if (mesh->sphere && k2 == 0 && mesh->leaves[L].level == a->level &&
+              tt != a->tree && L < p) {
+            /* same-level faces across cube edges: the mass face term of the
+             * higher-numbered patch becomes minus its neighbour's, so that
+             * both sides agree also next to a cube vertex (where their
+             * transverse terms read different corner ghosts) */
+            int ffs;
+            if (X2 != X) ffs = X2 > X ? 1 : 0;
+            else ffs = Y2 > Y ? 3 : 2;
+            const int32_t fts = (ffs < 2) ? fj : fi;
+            const double phin = phi[((L * 4 + ffs) * m + (fts - 1)) * meqn];
+            const double phio = phi[((p * 4 + f) * m + (t - 1)) * meqn];
+            const double ks = fco_sphere_kappa(mesh, p, ic, jc);
+            qn[(p * meqn) * FR + fco_fidx(m, ic, jc)] -=
+                dt / (ks * dx * dx) * (-phin - phio);
+          }
           if (mesh->leaves[L].level != a->level + 1) { fine = 0; break; }
           /* the direction towards the coarse cell, in the fine leaf's frame,
            * names the fine leaf's face */
@@ -437,9 +451,11 @@ static int reflux(const fco_mesh *mesh, const fco_params *par, const double *q,
             for (int c = 0; c < 3; ++c) eg.n[c] *= sgn;
             for (int c = 0; c < 3; ++c) eg.t[c] *= sgn;
           }
-          if (riemann(par, d, &eg, ql, qr, W, S, am, ap) < 0) return -4;
+          if (riemann(par, d, &eg, ql, qr, W, S, am, ap, NULL) < 0) return -4;
+          /* the mass of a sphere is in flux form: its face terms already
+           * are fluxes, so the fine terms replace the coarse one as they are */
           for (int k = 0; k < meqn; ++k)
-            corr[k] += flen * (am[k] + ap[k]) - phif[k];
+            corr[k] += (mesh->sphere && k == 0 ? 0.0 : flen * (am[k] + ap[k])) - phif[k];
         }
         if (!fine) continue;
         const double *phic = &phi[((p * 4 + f) * m + (t - 1)) * meqn];
@@ -452,9 +468,6 @@ static int reflux(const fco_mesh *mesh, const fco_params *par, const double *q,
   }
   return 0;
 }
-
-void fco_sphere_project(const fco_mesh *mesh, const fco_params *par,
-                        double *qn);
 
 int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
              double *qn, double dt, int32_t do_reflux, double *numax) {
@@ -471,6 +484,7 @@ int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
     wk.F[d] = (double *)malloc(sizeof(double) * NE * meqn);
     wk.AM[d] = (double *)malloc(sizeof(double) * NE * meqn);
     wk.AP[d] = (double *)malloc(sizeof(double) * NE * meqn);
+    wk.FL[d] = (double *)calloc(NE, sizeof(double));
   }
   wk.W = (double *)malloc(sizeof(double) * (m + 3) * MW * meqn);
   wk.S = (double *)malloc(sizeof(double) * (m + 3) * MW);
@@ -494,6 +508,7 @@ int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
     free(wk.F[d]);
     free(wk.AM[d]);
     free(wk.AP[d]);
+    free(wk.FL[d]);
   }
   free(wk.W);
   free(wk.S);

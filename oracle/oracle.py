@@ -77,6 +77,11 @@ def lib():
         L.fco_adam.argtypes = [i64, vp, vp, vp, vp, i32, dp, dp, dp, dp]
         L.fco_learned_tags.argtypes = [i64, vp, vp, dp, vp]
         L.fco_dilate_tags.argtypes = [vp, vp, i32, vp]
+        L.fco_sphere_kappa.argtypes = [vp, i64, i32, i32]
+        L.fco_sphere_kappa.restype = dp
+        L.fco_sphere_edge.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
+        L.fco_sphere_centre.argtypes = [vp, i64, i32, i32, vp]
+        L.fco_rp_sphere.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -296,3 +301,45 @@ def dilate_tags(mesh, tg, lmax) -> np.ndarray:
     out = np.zeros_like(tg)
     lib().fco_dilate_tags(mesh.h, _ptr(tg), lmax, _ptr(out))
     return out
+
+
+# -------------------------------------------------------------------------
+# cubed sphere geometry and solver pieces
+# -------------------------------------------------------------------------
+class EdgeGeom(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("n", C.c_double * 3), ("t", C.c_double * 3)]
+
+
+def sphere_kappa(mesh, p, i, j) -> float:
+    return lib().fco_sphere_kappa(mesh.h, p, i, j)
+
+
+def sphere_edge(mesh, p, direction, i, j):
+    """(gamma, n, t) of the low-side edge of frame cell (i, j)."""
+    g = C.c_double()
+    n = np.zeros(3)
+    t = np.zeros(3)
+    lib().fco_sphere_edge(mesh.h, p, direction, i, j, C.byref(g), _ptr(n), _ptr(t))
+    return g.value, n, t
+
+
+def sphere_centre(mesh, p, i, j) -> np.ndarray:
+    r = np.zeros(3)
+    lib().fco_sphere_centre(mesh.h, p, i, j, _ptr(r))
+    return r
+
+
+def riemann_sphere(par, gamma, n, t, ql, qr):
+    e = EdgeGeom(gamma, (C.c_double * 3)(*n), (C.c_double * 3)(*t))
+    ql = np.ascontiguousarray(ql, dtype=np.float64)
+    qr = np.ascontiguousarray(qr, dtype=np.float64)
+    W = np.zeros((3, 4))
+    s = np.zeros(3)
+    am = np.zeros(4)
+    ap = np.zeros(4)
+    fl = C.c_double()
+    nw = lib().fco_rp_sphere(C.byref(par), C.byref(e), _ptr(ql), _ptr(qr), _ptr(W),
+                             _ptr(s), _ptr(am), _ptr(ap), C.byref(fl))
+    if nw < 0:
+        raise RuntimeError("riemann failed")
+    return W, s, am, ap, fl.value

@@ -423,3 +423,25 @@ def dam_break_spec(seed: int) -> dict:
     g = SplitMix64(0x5EED_DA4B_0000 + seed)
     return {"centre": (0.3 + 0.4 * g.uniform(), 0.3 + 0.4 * g.uniform()),
             "radius": 0.15 + 0.15 * g.uniform(), "h_in": 1.5 + 1.5 * g.uniform()}
+
+
+def sphere_centres(leaves: np.ndarray, m: int) -> np.ndarray:
+    """Unit vectors of the mapped cell centres, shape (P, 3, m, m)."""
+    xi, eta = cell_centres(leaves, m)
+    out = np.empty((len(leaves), 3, m, m))
+    for t in range(6):
+        s = leaves["tree"] == t
+        if s.any():
+            out[s] = np.moveaxis(sphere_point(t, xi[s], eta[s]), 0, 1)
+    return out
+
+
+def sphere_bump(leaves, m, lat=0.3, lon=0.5, amp=0.1, width=100.0):
+    """h = 1 + amp exp(-width d^2), d the great-circle distance to the
+    point (lat, lon); fluid at rest.  (P, 4, m, m): h, hu, hv, hw."""
+    c = np.array([np.cos(lat) * np.cos(lon), np.cos(lat) * np.sin(lon), np.sin(lat)])
+    r = sphere_centres(leaves, m)
+    d = np.arccos(np.clip(np.einsum("pkij,k->pij", r, c), -1.0, 1.0))
+    q = np.zeros((len(leaves), 4, m, m))
+    q[:, 0] = 1.0 + amp * np.exp(-width * d * d)
+    return q
