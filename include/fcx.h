@@ -51,7 +51,7 @@ extern "C" {
 #define FCX_ENEG (-6)      /* non-positive depth met by a Riemann solve    */
 #define FCX_ESTATE (-7)    /* call out of order (e.g. no forest uploaded)  */
 
-enum { FCX_ADVECTION = 0, FCX_SHALLOW = 1 };
+enum { FCX_ADVECTION = 0, FCX_SHALLOW = 1, FCX_SPHERE = 2 };
 
 typedef struct fcx_ctx fcx_ctx;
 typedef struct fcx_batch fcx_batch;
@@ -73,7 +73,9 @@ typedef struct {
 typedef struct {
   int32_t m;           /* cells per patch side: 8, 16 or 32               */
   int32_t precision;   /* 32 or 64: element type of q and ghost           */
-  int32_t physics;     /* FCX_ADVECTION (meqn 1) or FCX_SHALLOW (meqn 3)  */
+  int32_t physics;     /* FCX_ADVECTION (meqn 1), FCX_SHALLOW (meqn 3) or
+                          FCX_SPHERE (meqn 4: h and 3D momentum on the
+                          cubed sphere; see fcx_sphere_geometry)          */
   int32_t limiter;     /* wave limiter: 0 none, 1 minmod, 2 superbee,
                           3 van Leer, 4 MC (LeVeque 2002, Sec. 6.12)      */
   int32_t transverse;  /* 0 none, 1 fluctuations, 2 fluctuations and
@@ -244,6 +246,39 @@ int fcx_batch_replay(fcx_batch *batch, void *stream);
 /* sums[4 f + k]: FP64 conservation sums of forest f (k < meqn; others 0),
  * reduced in a fixed order. */
 int fcx_batch_sums(fcx_batch *batch, const void *q, double *sums, void *stream);
+
+/* ---- cubed sphere (Sec. 2: six mapped trees; Sec. 4: capacity and edge
+ * metrics of mapped blocks) ---------------------------------------------
+ *
+ * With physics FCX_SPHERE the six trees are the faces of the cube, tree t
+ * spanned by centre c_t and axes u_t, v_t (u x v = c):
+ *   0: (+x, +y, +z)  1: (+y, -x, +z)  2: (-x, -y, +z)  3: (-y, +x, +z)
+ *   4: (+z, +y, -x)  5: (-z, +y, +x)
+ * glued edge to edge as the cube dictates (fcx_create checks it).  A point
+ * (xi, eta) of tree t maps to c + T(xi) u + T(eta) v normalised to the unit
+ * sphere, T(s) = tan((s - 1/2) pi/2) (gnomonic, equiangular).  The state is
+ * (h, hu, hv, hw) with Cartesian momentum; each edge solves the Roe problem
+ * in its (normal, tangent) frame with speeds scaled by the edge length; mass
+ * is advanced in flux form; momentum is projected on the tangent plane
+ * after the step.  fcx_patch_step, fcx_ghost_fill, fcx_reflux (which also
+ * makes the mass face terms of same-level faces across cube edges agree:
+ * call it after every step), fcx_next_dt, fcx_conservation_sums (capacity
+ * weighted) and fcx_dilate_tags support the sphere; fused steps, regrid
+ * tags and transfer, features and batches return FCX_EINVAL. */
+
+/* Geometry table of every patch (device doubles, caller-owned, P * 18 *
+ * (m+4)^2 values), per patch 18 frames of (m+4)^2 values indexed by frame
+ * cell (i, j), i, j = -1 .. m+2, at (j+1)(m+4) + (i+1):
+ *   frame 0: capacity kappa = cell area / dxi^2;
+ *   frames 1-3 (interleaved, 3 per cell): unit vector of the cell centre;
+ *   frames 4-10 (7 per cell): the cell's low-side xi-edge: gamma = arc
+ *     length / dxi, unit normal (towards higher i), unit tangent;
+ *   frames 11-17: the same for the low-side eta-edge.
+ * Ghost cells carry the geometry of the cells they copy (points outside
+ * the tree are mapped in the tree that holds them); at a cube vertex, where
+ * no tree covers the corner region, that region uses the patch's own face
+ * mapping extended. */
+int fcx_sphere_geometry(fcx_ctx *ctx, double *geo, void *stream);
 
 /* ---- learned tagging (an extension of the Sec. 5 criterion tags) ------
  *

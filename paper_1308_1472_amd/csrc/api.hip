@@ -13,6 +13,7 @@
 #include "batch.hpp"
 #include "forest.hpp"
 #include "mlp.hpp"
+#include "sphere.hpp"
 #include "step.hpp"
 
 using namespace fcx;
@@ -114,6 +115,7 @@ struct DevForest {
   int32_t n_reflux_x = 0, n_reflux_y = 0;
   int32_t nslots = 0;
   int64_t P = 0;
+  DevBuf<double> geo;                // sphere: per-patch geometry tables
 };
 
 struct fcx_ctx {
@@ -128,7 +130,45 @@ struct fcx_ctx {
   DevBuf<double> partial;
   DevBuf<int32_t> err;
   HostBuf staging;
+  DevBuf<uint8_t> sscratch;        // sphere step: per-workgroup edge data
+  int cus = 256;
 };
+
+// Cube faces as (centre, u, v) axis vectors, the same frames as the device
+// mapping of sphere.hpp.
+static const int kCubeAxes[6][3][3] = {
+    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},  {{0, 1, 0}, {-1, 0, 0}, {0, 0, 1}},
+    {{-1, 0, 0}, {0, -1, 0}, {0, 0, 1}}, {{0, -1, 0}, {1, 0, 0}, {0, 0, 1}},
+    {{0, 0, 1}, {0, 1, 0}, {-1, 0, 0}}, {{0, 0, -1}, {0, 1, 0}, {1, 0, 0}},
+};
+
+// 1 if the connectivity glues the six cube faces as the cube does: the two
+// end points of every glued face coincide, in the stated orientation.
+static bool cube_connectivity(const std::vector<fcx_tree>& t) {
+  if (t.size() != 6) return false;
+  auto ends = [](int tree, int f, int pt[2][3]) {
+    const int a = f / 2, s = f % 2;
+    for (int e = 0; e < 2; ++e) {
+      const int xi = a == 0 ? s : e, eta = a == 0 ? e : s;
+      for (int c = 0; c < 3; ++c)
+        pt[e][c] = kCubeAxes[tree][0][c] + (2 * xi - 1) * kCubeAxes[tree][1][c] +
+                   (2 * eta - 1) * kCubeAxes[tree][2][c];
+    }
+  };
+  for (int tr = 0; tr < 6; ++tr)
+    for (int f = 0; f < 4; ++f) {
+      const fcx_tree& T = t[tr];
+      if (T.bc[f] != 0) return false;
+      int a[2][3], b[2][3];
+      ends(tr, f, a);
+      ends(T.nbr_tree[f], T.nbr_face[f], b);
+      const int o = T.orient[f];
+      for (int e = 0; e < 2; ++e)
+        for (int c = 0; c < 3; ++c)
+          if (a[e][c] != b[o ? 1 - e : e][c]) return false;
+    }
+  return true;
+}
 
 // The entry points below are declared extern "C" in fcx.h.
 
@@ -188,7 +228,8 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
     return fail(FCX_EINVAL, "m must be 8, 16 or 32");
   if (cfg->precision != 32 && cfg->precision != 64)
     return fail(FCX_EINVAL, "precision must be 32 or 64");
-  if (cfg->physics != FCX_ADVECTION && cfg->physics != FCX_SHALLOW)
+  if (cfg->physics != FCX_ADVECTION && cfg->physics != FCX_SHALLOW &&
+      cfg->physics != FCX_SPHERE)
     return fail(FCX_EINVAL, "unknown physics");
   if (cfg->limiter < 0 || cfg->limiter > 4 || cfg->transverse < 0 ||
       cfg->transverse > 2)
@@ -213,12 +254,21 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
         if (T.bc[f] == 0 && (T.nbr_face[f] != (f ^ 1) || T.orient[f] != 0))
           return fail(FCX_EINVAL, "shallow water needs axis-aligned tree gluing");
   }
+  if (cfg->physics == FCX_SPHERE && !cube_connectivity(t))
+    return fail(FCX_EINVAL, "the sphere needs the six cube faces glued as the cube");
   fcx_ctx* c = new fcx_ctx;
   c->cfg = *cfg;
   c->cfg.tile = tile;
   c->cfg.threads = threads;
   c->tile = tile;
-  c->meqn = cfg->physics == FCX_ADVECTION ? 1 : 3;
+  c->meqn = cfg->physics == FCX_ADVECTION ? 1 : (cfg->physics == FCX_SHALLOW ? 3 : 4);
+  {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipGetDeviceProperties(&prop, dev) == hipSuccess)
+      c->cus = prop.multiProcessorCount;
+  }
   c->trees = t;
   if (c->err.ensure(1) != hipSuccess) {
     delete c;
@@ -244,7 +294,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
                        const std::vector<int32_t>* src = nullptr) {
   Plan plan;
   std::string err;
-  int rc = build_plan(f, c->cfg.m, plan, err);
+  int rc = build_plan(f, c->cfg.m, plan, err, c->cfg.physics == FCX_SPHERE);
   if (rc != FCX_OK) return fail(rc, err);
   const size_t P = f.leaves.size();
   // reflux items: xi faces first, then eta faces
@@ -291,12 +341,24 @@ static int finish_upload(fcx_ctx* c) {
   const size_t esz = c->cfg.precision == 64 ? 8 : 4;
   HIPCHK(c->phi.ensure(size_t(c->cur.nslots) * 4 * c->cfg.m * c->meqn * esz));
   HIPCHK(c->partial.ensure(size_t(P) * c->meqn));
+  if (c->cfg.physics == FCX_SPHERE) {
+    const int m = c->cfg.m;
+    const size_t FR = size_t(m + 4) * (m + 4);
+    HIPCHK(c->cur.geo.ensure(size_t(P) * kGeoN * FR));
+    const size_t lds = sizeof(double) * 3 * (m + 5) * (m + 5);
+    hipLaunchKernelGGL(k_sphere_metrics, dim3(unsigned(P)), dim3(256), lds, 0,
+                       c->cur.rec, m, log2i(m), c->cur.geo.p);
+    HIPCHK(hipGetLastError());
+    const int slots = int(std::min<int64_t>(P, int64_t(c->cus) * 2));
+    HIPCHK(c->sscratch.ensure(size_t(slots) * sphere_scratch(m) * esz));
+    HIPCHK(hipDeviceSynchronize());
+  }
   return FCX_OK;
 }
 
 int fcx_upload_forest(fcx_ctx* c, int64_t n, const fcx_leaf* leaves) {
   if (!c || n <= 0 || !leaves) return fail(FCX_EINVAL, "bad arguments");
-  if (n * (c->cfg.physics == FCX_ADVECTION ? 1 : 3) * c->cfg.m * c->cfg.m >=
+  if (n * c->meqn * c->cfg.m * c->cfg.m >=
       (int64_t(1) << 31))
     return fail(FCX_EINVAL, "state larger than 2^31 elements");
   std::vector<fcx_leaf> l(leaves, leaves + n);
@@ -347,7 +409,8 @@ static int launch_ghost(fcx_ctx* c, const void* q, void* ghost, hipStream_t s) {
   const unsigned blocks = unsigned((tot + 255) / 256);
   hipLaunchKernelGGL((k_ghost_fill<R, PHYS>), dim3(blocks), dim3(256), 0, s,
                      static_cast<const R*>(q), static_cast<R*>(ghost),
-                     c->cur.rec, int32_t(c->cur.P), m, log2i(m), c->err.p);
+                     c->cur.rec, int32_t(c->cur.P), m, log2i(m), c->err.p,
+                     c->cur.geo.p);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -360,6 +423,9 @@ int fcx_ghost_fill(fcx_ctx* c, const void* q, void* ghost, void* stream) {
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_ghost<double, FCX_ADVECTION>(c, q, ghost, s)
               : launch_ghost<float, FCX_ADVECTION>(c, q, ghost, s);
+  if (c->cfg.physics == FCX_SPHERE)
+    return dp ? launch_ghost<double, FCX_SPHERE>(c, q, ghost, s)
+              : launch_ghost<float, FCX_SPHERE>(c, q, ghost, s);
   return dp ? launch_ghost<double, FCX_SHALLOW>(c, q, ghost, s)
             : launch_ghost<float, FCX_SHALLOW>(c, q, ghost, s);
 }
@@ -400,6 +466,35 @@ static int launch_step_m(fcx_ctx* c, const void* q, const void* ghost, void* qn,
               : launch_step_t<R, PHYS, 16, 256, FUSED>(c, q, ghost, qn, dt, numax, s);
 }
 
+template <typename R>
+static int launch_sphere_step(fcx_ctx* c, const void* q, const void* ghost, void* qn,
+                              const double* dt, double* numax, hipStream_t s) {
+  SphereArgs<R> a;
+  a.q = static_cast<const R*>(q);
+  a.ghost = static_cast<const R*>(ghost);
+  a.qn = static_cast<R*>(qn);
+  a.dt = dt;
+  a.numax = numax;
+  a.rec = c->cur.rec;
+  a.phislot = c->cur.phislot;
+  a.phi = reinterpret_cast<R*>(c->phi.p);
+  a.err = c->err.p;
+  a.geo = c->cur.geo.p;
+  a.scratch = reinterpret_cast<R*>(c->sscratch.p);
+  a.P = int32_t(c->cur.P);
+  a.m = c->cfg.m;
+  a.lm = log2i(c->cfg.m);
+  a.limiter = c->cfg.limiter;
+  a.transverse = c->cfg.transverse;
+  a.g = c->cfg.g;
+  const int FR = (a.m + 4) * (a.m + 4);
+  const size_t lds = sizeof(R) * 4 * FR + sizeof(double) * FR;
+  const int slots = int(std::min<int64_t>(c->cur.P, int64_t(c->cus) * 2));
+  hipLaunchKernelGGL((k_sphere_step<R>), dim3(unsigned(slots)), dim3(256), lds, s, a);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
 template <bool FUSED>
 static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                          const double* dt, double* numax, void* stream) {
@@ -409,6 +504,11 @@ static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
   if (q == qn) return fail(FCX_EINVAL, "q_new must not alias q");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_SPHERE) {
+    if (FUSED) return fail(FCX_EINVAL, "no fused step on the sphere");
+    return dp ? launch_sphere_step<double>(c, q, ghost, qn, dt, numax, s)
+              : launch_sphere_step<float>(c, q, ghost, qn, dt, numax, s);
+  }
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_step_m<double, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s)
               : launch_step_m<float, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s);
@@ -445,11 +545,32 @@ static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
   return FCX_OK;
 }
 
+template <typename R>
+static int launch_sphere_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
+                                hipStream_t s) {
+  const int m = c->cfg.m;
+  for (int axis = 0; axis < 2; ++axis) {
+    const int32_t n = axis == 0 ? c->cur.n_reflux_x : c->cur.n_reflux_y;
+    if (n == 0) continue;
+    const RefluxItem* items = c->cur.reflux + (axis == 0 ? 0 : c->cur.n_reflux_x);
+    const int64_t tot = int64_t(n) * 32;
+    hipLaunchKernelGGL((k_sphere_reflux<R>), dim3(unsigned((tot + 255) / 256)), dim3(256),
+                       0, s, static_cast<const R*>(q), static_cast<R*>(qn), items, n,
+                       c->cur.rec, c->cur.phislot, reinterpret_cast<const R*>(c->phi.p),
+                       c->cur.geo.p, dt, c->cfg.g, m, c->err.p);
+    HIPCHK(hipGetLastError());
+  }
+  return FCX_OK;
+}
+
 int fcx_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt, void* stream) {
   if (!c || !q || !qn || !dt) return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_SPHERE)
+    return dp ? launch_sphere_reflux<double>(c, q, qn, dt, s)
+              : launch_sphere_reflux<float>(c, q, qn, dt, s);
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_reflux<double, FCX_ADVECTION>(c, q, qn, dt, s)
               : launch_reflux<float, FCX_ADVECTION>(c, q, qn, dt, s);
@@ -483,6 +604,21 @@ int fcx_conservation_sums(fcx_ctx* c, const void* q, double* sums, void* stream)
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_SPHERE) {
+    if (dp)
+      hipLaunchKernelGGL((k_sphere_sums_patch<double>), dim3(unsigned(c->cur.P)), dim3(256),
+                         0, s, static_cast<const double*>(q), c->cur.rec, c->cur.geo.p,
+                         c->cfg.m, c->partial.p);
+    else
+      hipLaunchKernelGGL((k_sphere_sums_patch<float>), dim3(unsigned(c->cur.P)), dim3(256),
+                         0, s, static_cast<const float*>(q), c->cur.rec, c->cur.geo.p,
+                         c->cfg.m, c->partial.p);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((k_sums_reduce<4>), dim3(1), dim3(1024), 0, s, c->partial.p,
+                       c->cur.first, sums);
+    HIPCHK(hipGetLastError());
+    return FCX_OK;
+  }
   if (c->meqn == 1)
     return dp ? launch_sums<double, 1>(c, q, sums, s) : launch_sums<float, 1>(c, q, sums, s);
   return dp ? launch_sums<double, 3>(c, q, sums, s) : launch_sums<float, 3>(c, q, sums, s);
@@ -510,6 +646,7 @@ int fcx_regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criter
       (criterion == 1 && !ghost))
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no regrid on the sphere");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
   if (c->meqn == 1)
@@ -524,6 +661,7 @@ int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
   if (!c || !tags || !n_new || lmin < 0 || lmax < lmin || lmax > kMaxLevel)
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no regrid on the sphere");
   std::vector<fcx_leaf> out;
   std::string err;
   int rc = regrid(c->forest, tags, lmin, lmax, out, err);
@@ -740,6 +878,8 @@ int fcx_batch_create(int32_t n, fcx_ctx* const* forests, fcx_batch** out) {
       return fail(FCX_ESTATE, "every context needs an uploaded forest");
     if (forests[f]->cfg.precision != forests[0]->cfg.precision)
       return fail(FCX_EINVAL, "all forests of a batch share one precision");
+    if (forests[f]->cfg.physics == FCX_SPHERE)
+      return fail(FCX_EINVAL, "sphere forests are not batched");
   }
   fcx_batch* b = new fcx_batch;
   b->n = n;
@@ -906,6 +1046,7 @@ int fcx_features(fcx_ctx* c, const void* q, const void* ghost, float* feats,
                  void* stream) {
   if (!c || !q || !ghost || !feats) return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no features on the sphere");
   if (c->cur.P == 0) return FCX_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const unsigned grid = unsigned(c->cur.P);
@@ -1007,5 +1148,17 @@ int fcx_dilate_tags(fcx_ctx* c, const int8_t* in, int32_t lmax, int8_t* out,
   hipLaunchKernelGGL(k_dilate_tags, dim3(unsigned((P + 255) / 256)), dim3(256), 0,
                      static_cast<hipStream_t>(stream), in, c->cur.rec, P, lmax, out);
   HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+// ---- cubed sphere ---------------------------------------------------------
+
+int fcx_sphere_geometry(fcx_ctx* c, double* geo, void* stream) {
+  if (!c || !geo) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cfg.physics != FCX_SPHERE) return fail(FCX_EINVAL, "not a sphere context");
+  const size_t FR = size_t(c->cfg.m + 4) * (c->cfg.m + 4);
+  HIPCHK(hipMemcpyAsync(geo, c->cur.geo.p, sizeof(double) * c->cur.P * kGeoN * FR,
+                        hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
   return FCX_OK;
 }

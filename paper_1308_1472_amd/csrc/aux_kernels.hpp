@@ -14,7 +14,7 @@ template <typename R, int PHYS>
 __global__ void __launch_bounds__(256)
 k_ghost_fill(const R* __restrict__ q, R* __restrict__ ghost,
              const PatchRec* __restrict__ rec, int32_t P, int m, int lm,
-             int32_t* err) {
+             int32_t* err, const double* __restrict__ geo) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   const int G = 8 * m + 16;
   // XCD-contiguous block order (see xcd_tile): neighbouring patches' reads
@@ -28,7 +28,7 @@ k_ghost_fill(const R* __restrict__ q, R* __restrict__ ghost,
   int i, j;
   ghost_cell(m, g, i, j);
   if ((i == -1 || i == m + 2) && (j == -1 || j == m + 2)) return;
-  GhostView<R, MEQN> gv{q, rec, m, lm, err};
+  GhostView<R, MEQN> gv{q, rec, m, lm, err, geo};
   R v[MEQN];
   frame_value<R, MEQN, PHYS, true>(gv, p, i, j, v);
 #pragma unroll

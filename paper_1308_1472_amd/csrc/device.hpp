@@ -25,6 +25,7 @@ struct KPhys {
 template <int PHYS> struct PhysTraits;
 template <> struct PhysTraits<FCX_ADVECTION> { static constexpr int MEQN = 1; };
 template <> struct PhysTraits<FCX_SHALLOW> { static constexpr int MEQN = 3; };
+template <> struct PhysTraits<FCX_SPHERE> { static constexpr int MEQN = 4; };
 
 __device__ __forceinline__ void xf_apply(int32_t code, int32_t x, int32_t y,
                                          int32_t& xo, int32_t& yo) {
@@ -75,7 +76,15 @@ struct GhostView {
   const PatchRec* __restrict__ rec;
   int m, lm;                      // m = 2^lm
   int32_t* err;
+  const double* geo = nullptr;    // sphere: per-patch geometry tables
 };
+
+// capacity of interior cell (i, j) of patch p from a sphere geometry table
+// (kappa is the first frame of (m+4)^2 values, then 17 more frames)
+__device__ __forceinline__ double geo_kappa(const double* geo, int m, int p, int i, int j) {
+  const int FR = (m + 4) * (m + 4);
+  return geo[size_t(p) * 18 * FR + (j + 1) * (m + 4) + (i + 1)];
+}
 
 // The leaf that holds the centre of non-interior, non-wall frame cell (i, j)
 // of patch p, and that centre in the leaf's tree coordinates.  Returns the
@@ -165,8 +174,20 @@ __device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
     read_interior<R, MEQN>(g.q, g.m, nb, i0 + 1, j0, b);
     read_interior<R, MEQN>(g.q, g.m, nb, i0, j0 + 1, c);
     read_interior<R, MEQN>(g.q, g.m, nb, i0 + 1, j0 + 1, d);
+    if (PHYS == FCX_SPHERE) {
+      // capacity-weighted mean
+      const R ka = R(geo_kappa(g.geo, g.m, nb, i0, j0));
+      const R kb = R(geo_kappa(g.geo, g.m, nb, i0 + 1, j0));
+      const R kc = R(geo_kappa(g.geo, g.m, nb, i0, j0 + 1));
+      const R kd = R(geo_kappa(g.geo, g.m, nb, i0 + 1, j0 + 1));
+      const R w = ((ka + kb) + kc) + kd;
 #pragma unroll
-    for (int k = 0; k < MEQN; ++k) out[k] = (((a[k] + b[k]) + c[k]) + d[k]) / R(4);
+      for (int k = 0; k < MEQN; ++k)
+        out[k] = (((ka * a[k] + kb * b[k]) + kc * c[k]) + kd * d[k]) / w;
+    } else {
+#pragma unroll
+      for (int k = 0; k < MEQN; ++k) out[k] = (((a[k] + b[k]) + c[k]) + d[k]) / R(4);
+    }
   } else if (ALLOW_INTERP) {
     // coarser leaf: minmod-limited linear interpolation at offset +-1/4
     const int ic = (u >> csh) + 1, jc = (v >> csh) + 1;

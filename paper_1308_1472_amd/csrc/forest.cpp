@@ -433,13 +433,13 @@ int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
 // Neighbour records of one patch; coarse-fine faces are reported in items.
 static int plan_one(const Forest& f, int m, int64_t p, PatchRec& r,
                     bool& mixed, int32_t& family, RefluxItem* items,
-                    int& nitems, std::string& err) {
+                    int& nitems, bool sync, std::string& err) {
   {
     const fcx_leaf& a = f.leaves[p];
     r.level = a.level;
     r.ix = a.ix;
     r.iy = a.iy;
-    r.flags = 0;
+    r.flags = a.tree << kTreeShift;
     const int64_t size = kSide >> a.level, half = size / (2 * m);
     const int64_t x0 = int64_t(a.ix) * size, y0 = int64_t(a.iy) * size;
     auto centre = [&](int i, int j, int64_t& x, int64_t& y) {
@@ -482,7 +482,11 @@ static int plan_one(const Forest& f, int m, int64_t p, PatchRec& r,
       r.nbr[2 * fc] = ids[0];
       r.nbr[2 * fc + 1] = ids[1];
       r.xf[fc] = xf.code;
-      if (ids[0] != ids[1]) {
+      // same-level face across trees, kept consistent by a face sync
+      const bool synced = sync && ids[0] == ids[1] && l0 == a.level &&
+                          f.leaves[ids[0]].tree != a.tree;
+      if (synced) mixed = true;
+      if (ids[0] != ids[1] || (synced && ids[0] < p)) {
         RefluxItem it{};
         it.coarse = int32_t(p);
         it.face = fc;
@@ -502,6 +506,7 @@ static int plan_one(const Forest& f, int m, int64_t p, PatchRec& r,
           it.fine_face[s] = ff;
           it.fine_rev[s] = rev;
         }
+        if (ids[0] == ids[1]) it.fine[1] = kSyncItem;
         items[nitems++] = it;
       }
     }
@@ -556,7 +561,7 @@ static int plan_one(const Forest& f, int m, int64_t p, PatchRec& r,
 
 // Records for all patches, computed in parallel chunks; slots and reflux
 // items are then numbered in patch order.
-int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
+int build_plan(const Forest& f, int m, Plan& plan, std::string& err, bool sync) {
   const int64_t n = int64_t(f.leaves.size());
   plan.recs.assign(n, PatchRec{});
   plan.phislot.assign(n, -1);
@@ -577,7 +582,7 @@ int build_plan(const Forest& f, int m, Plan& plan, std::string& err) {
       int ni = 0;
       int32_t fam = 0;
       const int rc = plan_one(f, m, p, plan.recs[p], mx, fam, &items[size_t(p) * 4],
-                              ni, errs[t]);
+                              ni, sync, errs[t]);
       if (rc != FCX_OK) { rcs[t] = rc; return; }
       mixed[p] = mx;
       nitems[p] = uint8_t(ni);

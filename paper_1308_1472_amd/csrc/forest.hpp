@@ -90,7 +90,7 @@ int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
 struct PatchRec {
   int32_t level, ix, iy, flags;              // flags: bit f wall on face f,
                                              // bit 4+f extrapolation wall,
-                                             // kSimpleHalo
+                                             // kSimpleHalo, tree << kTreeShift
   int32_t nbr[12];                           // faces 2 slots each, corners
   int32_t xf[8];                             // face / corner transforms
 };
@@ -101,11 +101,16 @@ constexpr int32_t kNbrWall = -1;
 // glued by a pure translation (ghost cells are plain copies)
 constexpr int32_t kSimpleHalo = 1 << 8;
 constexpr int32_t kNbrValence3 = -2;
+// PatchRec.flags bits 16.. hold the patch's tree
+constexpr int kTreeShift = 16;
 
-// One coarse patch face with two finer neighbours (reflux work item).
+// One coarse patch face with two finer neighbours (reflux work item), or,
+// with fine[1] == kSyncItem, a same-level face across trees whose face
+// terms the patch `coarse` takes over from its neighbour fine[0].
 struct RefluxItem {
   int32_t coarse, face, fine[2], fine_face[2], fine_rev[2];
 };
+constexpr int32_t kSyncItem = -3;
 
 struct Plan {
   std::vector<PatchRec> recs;
@@ -116,7 +121,10 @@ struct Plan {
                                              // complete leaf family
 };
 
-int build_plan(const Forest& f, int m, Plan& plan, std::string& err);
+// sync: also emit face-sync items for same-level faces across trees (used
+// by the cubed sphere, whose mass face terms must agree there).
+int build_plan(const Forest& f, int m, Plan& plan, std::string& err,
+               bool sync = false);
 
 // Regrid: refine +1, merge complete families tagged -1, then balance.
 int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,

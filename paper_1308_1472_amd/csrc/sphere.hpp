@@ -1,0 +1,564 @@
+// sphere.hpp -- the cubed sphere: geometry of patches and of their ghost
+// layers from the gnomonic equiangular map (Sec. 2: six mapped trees), and
+// the shallow-water step with 3D Cartesian momentum on mapped cells (the
+// capacity form of the wave-propagation method the paper adopts for mapped
+// grids, Calhoun, Helzel and LeVeque 2008).
+//
+// Tree t is cube face t with centre c, axes u, v (u x v = c); reference
+// point (xi, eta) -> c + T(xi) u + T(eta) v -> unit sphere, T(s) =
+// tan((s - 1/2) pi/2) with T(0) = -1, T(1) = 1, T(1 - s) = -T(s) exactly,
+// so points on a cube edge get the same coordinates from either face.
+//
+// Geometry table of a patch, indexed by frame cell f = (j+1)(m+4) + (i+1),
+// i, j = -1 .. m+2 (doubles, kGeoN frames per patch):
+//   [kGeoK] capacity kappa = cell area / dxi^2;
+//   [kGeoC] cell centre (3 per cell);
+//   [kGeoE] low-side edge of the cell in direction 0 (xi) then 1 (eta):
+//           gamma = arc length / dxi, normal n (towards higher index),
+//           tangent t = r_mid x n (7 per cell and direction).
+// Corner points outside the patch's tree are carried into the tree that
+// holds them (ghost cells get the geometry of the cells they copy); the
+// corner region at a cube vertex, which no tree covers, uses the patch's own
+// face mapping extended, for its cells and for edges between two of them.
+#pragma once
+
+#include "device.hpp"
+#include "step.hpp"
+
+namespace fcx {
+
+constexpr int kGeoK = 0, kGeoC = 1, kGeoE = 4, kGeoN = 18;
+
+__constant__ double kCubeFace[6][3][3] = {
+    {{1, 0, 0}, {0, 1, 0}, {0, 0, 1}},
+    {{0, 1, 0}, {-1, 0, 0}, {0, 0, 1}},
+    {{-1, 0, 0}, {0, -1, 0}, {0, 0, 1}},
+    {{0, -1, 0}, {1, 0, 0}, {0, 0, 1}},
+    {{0, 0, 1}, {0, 1, 0}, {-1, 0, 0}},
+    {{0, 0, -1}, {0, 1, 0}, {1, 0, 0}},
+};
+
+__device__ __forceinline__ int fidx(int m, int i, int j) { return (j + 1) * (m + 4) + (i + 1); }
+
+__device__ inline double tline(int32_t X) {
+  const int64_t d = 2 * int64_t(X) - kSide;
+  if (d == 0) return 0.0;
+  const int64_t ad = d < 0 ? -d : d;
+  const double t = ad == kSide ? 1.0 : tan(ldexp(double(ad), -kS) * 0.78539816339744830962);
+  return d < 0 ? -t : t;
+}
+
+__device__ inline void face_point(int t, int32_t X, int32_t Y, double* r) {
+  const double a = tline(X), b = tline(Y);
+  double p[3];
+  for (int c = 0; c < 3; ++c) p[c] = kCubeFace[t][0][c] + a * kCubeFace[t][1][c] + b * kCubeFace[t][2][c];
+  const double s = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
+  for (int c = 0; c < 3; ++c) r[c] = p[c] / s;
+}
+
+// Sphere point of tree coordinates (X, Y) of patch r's tree, carried into
+// the tree that holds it (trees closed; own face extended at a cube vertex).
+__device__ inline void patch_point(const PatchRec* __restrict__ rec, const PatchRec& r,
+                                   int32_t X, int32_t Y, double* out) {
+  const int tree = r.flags >> kTreeShift;
+  const int32_t side = int32_t(kSide);
+  const bool ox = X < 0 || X > side, oy = Y < 0 || Y > side;
+  if (!ox && !oy) { face_point(tree, X, Y, out); return; }
+  int32_t code, nb;
+  if (ox && !oy) {
+    const int f = X < 0 ? 0 : 1;
+    code = r.xf[f];
+    nb = r.nbr[2 * f];
+  } else if (oy && !ox) {
+    const int f = Y < 0 ? 2 : 3;
+    code = r.xf[f];
+    nb = r.nbr[2 * f];
+  } else {
+    const int c = (X > 0) + 2 * (Y > 0);
+    nb = r.nbr[8 + c];
+    code = r.xf[4 + c];
+    if (nb < 0) { face_point(tree, X, Y, out); return; }   // cube vertex
+  }
+  int32_t X2, Y2;
+  xf_apply(code, X, Y, X2, Y2);
+  face_point(rec[nb].flags >> kTreeShift, X2, Y2, out);
+}
+
+__device__ __forceinline__ void cross3(const double* a, const double* b, double* o) {
+  o[0] = a[1] * b[2] - a[2] * b[1];
+  o[1] = a[2] * b[0] - a[0] * b[2];
+  o[2] = a[0] * b[1] - a[1] * b[0];
+}
+__device__ __forceinline__ double dot3(const double* a, const double* b) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+// solid angle of the counter-clockwise spherical triangle (Van Oosterom and
+// Strackee)
+__device__ __forceinline__ double tri_area(const double* a, const double* b, const double* c) {
+  double bc[3];
+  cross3(b, c, bc);
+  return 2.0 * atan2(dot3(a, bc), 1.0 + dot3(a, b) + dot3(b, c) + dot3(c, a));
+}
+
+// frame cell (i, j) lies in a corner region at a cube vertex
+__device__ __forceinline__ bool vertex_cell(const PatchRec& r, int m, int i, int j) {
+  if ((i >= 1 && i <= m) || (j >= 1 && j <= m)) return false;
+  return r.nbr[8 + (i > m) + 2 * (j > m)] == kNbrValence3;
+}
+
+// One workgroup per patch: the geometry table (dynamic LDS: the canonical
+// corner grid of (m+5)^2 points; own-face points are recomputed where a
+// cube-vertex region needs them).
+__global__ void __launch_bounds__(256)
+k_sphere_metrics(const PatchRec* __restrict__ rec, int m, int lm, double* __restrict__ geo) {
+  extern __shared__ double can[];
+  const int NC = m + 5, FR = (m + 4) * (m + 4);
+  const int p = blockIdx.x;
+  const PatchRec r = rec[p];
+  const int tree = r.flags >> kTreeShift;
+  const int sh = kS - r.level;
+  const int32_t cs = int32_t(1) << (sh - lm);
+  const int32_t x0 = r.ix << sh, y0 = r.iy << sh;
+  for (int k = threadIdx.x; k < NC * NC; k += blockDim.x) {
+    const int32_t X = x0 + (k % NC - 2) * cs, Y = y0 + (k / NC - 2) * cs;
+    patch_point(rec, r, X, Y, can + 3 * k);
+  }
+  __syncthreads();
+  const double dx = ldexp(1.0, -r.level) / m;
+  double* g = geo + size_t(p) * kGeoN * FR;
+  // corner (I, J): canonical from LDS, or the own face mapping into buf
+  auto pt = [&](bool own, int I, int J, double* buf) -> const double* {
+    if (!own) return can + 3 * ((J + 2) * NC + (I + 2));
+    face_point(tree, x0 + I * cs, y0 + J * cs, buf);
+    return buf;
+  };
+  for (int f = threadIdx.x; f < FR; f += blockDim.x) {
+    const int i = f % (m + 4) - 1, j = f / (m + 4) - 1;
+    const bool vc = vertex_cell(r, m, i, j);
+    double ba[3], bb[3], bc[3], bd[3];
+    const double *A = pt(vc, i - 1, j - 1, ba), *B = pt(vc, i, j - 1, bb),
+                 *C = pt(vc, i, j, bc), *D = pt(vc, i - 1, j, bd);
+    g[kGeoK * FR + f] = (tri_area(A, B, C) + tri_area(A, C, D)) / (dx * dx);
+    patch_point(rec, r, x0 + (2 * i - 1) * (cs >> 1), y0 + (2 * j - 1) * (cs >> 1),
+                g + kGeoC * FR + 3 * f);
+    for (int dir = 0; dir < 2; ++dir) {
+      const bool vn = dir == 0 ? vertex_cell(r, m, i - 1, j) : vertex_cell(r, m, i, j - 1);
+      const bool own = vc && vn;
+      double be[3], bf[3];
+      const double* ea = pt(own, i - 1, j - 1, be);
+      const double* eb = dir == 0 ? pt(own, i - 1, j, bf) : pt(own, i, j - 1, bf);
+      double cr[3], nn[3], rm[3], tt[3];
+      cross3(ea, eb, cr);
+      const double len = sqrt(dot3(cr, cr));
+      const double sg = dir == 0 ? -1.0 : 1.0;
+      for (int c = 0; c < 3; ++c) nn[c] = sg * cr[c] / len;
+      for (int c = 0; c < 3; ++c) rm[c] = ea[c] + eb[c];
+      const double rl = sqrt(dot3(rm, rm));
+      for (int c = 0; c < 3; ++c) rm[c] /= rl;
+      cross3(rm, nn, tt);
+      double* e = g + kGeoE * FR + (dir * FR + f) * 7;
+      e[0] = atan2(len, dot3(ea, eb)) / dx;
+      for (int c = 0; c < 3; ++c) e[1 + c] = nn[c];
+      for (int c = 0; c < 3; ++c) e[4 + c] = tt[c];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// rotated Roe solver and transverse splitting
+
+template <typename R>
+struct SEdge {
+  R g, n[3], t[3];
+};
+
+template <typename R>
+__device__ __forceinline__ SEdge<R> load_edge(const double* e) {
+  SEdge<R> s;
+  s.g = R(e[0]);
+  for (int c = 0; c < 3; ++c) { s.n[c] = R(e[1 + c]); s.t[c] = R(e[4 + c]); }
+  return s;
+}
+
+// waves W[w][k], speeds s[w] (times gamma), fluctuations, mass flux fl;
+// false if a depth is not positive
+template <typename R>
+__device__ bool rp_sphere(R grav, const SEdge<R>& e, const R* ql, const R* qr, R (*W)[4],
+                          R* s, R* am, R* ap, R& fl) {
+  const R hl = ql[0], hr = qr[0];
+  if (!(hl > R(0) && hr > R(0))) return false;
+  const R nl = ql[1] * e.n[0] + ql[2] * e.n[1] + ql[3] * e.n[2];
+  const R nr = qr[1] * e.n[0] + qr[2] * e.n[1] + qr[3] * e.n[2];
+  const R tl = ql[1] * e.t[0] + ql[2] * e.t[1] + ql[3] * e.t[2];
+  const R tr = qr[1] * e.t[0] + qr[2] * e.t[1] + qr[3] * e.t[2];
+  const R sl = sqrt(hl), sr = sqrt(hr);
+  const R u = (nl / sl + nr / sr) / (sl + sr);
+  const R v = (tl / sl + tr / sr) / (sl + sr);
+  const R c = sqrt(grav * R(0.5) * (hl + hr));
+  const R d0 = hr - hl, d1 = nr - nl, d2 = tr - tl;
+  const R a1 = ((u + c) * d0 - d1) / (R(2) * c);
+  const R a2 = d2 - v * d0;
+  const R a3 = (d1 - (u - c) * d0) / (R(2) * c);
+  const R wv[3][3] = {{a1, a1 * (u - c), a1 * v}, {R(0), R(0), a2}, {a3, a3 * (u + c), a3 * v}};
+  const R sp[3] = {u - c, u, u + c};
+  for (int w = 0; w < 3; ++w) {
+    W[w][0] = wv[w][0];
+    for (int k = 0; k < 3; ++k) W[w][1 + k] = wv[w][1] * e.n[k] + wv[w][2] * e.t[k];
+    s[w] = e.g * sp[w];
+  }
+  for (int k = 0; k < 4; ++k) {
+    R m_ = R(0), p_ = R(0);
+    for (int w = 0; w < 3; ++w) {
+      m_ += fmin(s[w], R(0)) * W[w][k];
+      p_ += fmax(s[w], R(0)) * W[w][k];
+    }
+    am[k] = m_;
+    ap[k] = p_;
+  }
+  fl = R(0.5) * e.g * (nl + nr) - R(0.5) * (ap[0] - am[0]);
+  return true;
+}
+
+// part of psi crossing the transverse edge te of the receiving cell, down
+// (up = false) or up; Roe averages of the normal edge's states
+template <typename R>
+__device__ bool tsplit_sphere(R grav, const R* ql, const R* qr, const SEdge<R>& te,
+                              const R* psi, bool up, R* out) {
+  const R hl = ql[0], hr = qr[0];
+  if (!(hl > R(0) && hr > R(0))) return false;
+  const R sl = sqrt(hl), sr = sqrt(hr);
+  R ub[3];
+  for (int k = 0; k < 3; ++k) ub[k] = (ql[1 + k] / sl + qr[1 + k] / sr) / (sl + sr);
+  const R c = sqrt(grav * R(0.5) * (hl + hr));
+  const R un = ub[0] * te.n[0] + ub[1] * te.n[1] + ub[2] * te.n[2];
+  const R ut = ub[0] * te.t[0] + ub[1] * te.t[1] + ub[2] * te.t[2];
+  const R pn = psi[1] * te.n[0] + psi[2] * te.n[1] + psi[3] * te.n[2];
+  const R pt = psi[1] * te.t[0] + psi[2] * te.t[1] + psi[3] * te.t[2];
+  const R beta[3] = {((un + c) * psi[0] - pn) / (R(2) * c), pt - ut * psi[0],
+                     (pn - (un - c) * psi[0]) / (R(2) * c)};
+  const R lam[3] = {te.g * (un - c), te.g * un, te.g * (un + c)};
+  R Rv[3][4];
+  Rv[0][0] = R(1); Rv[1][0] = R(0); Rv[2][0] = R(1);
+  for (int k = 0; k < 3; ++k) {
+    Rv[0][1 + k] = (un - c) * te.n[k] + ut * te.t[k];
+    Rv[1][1 + k] = te.t[k];
+    Rv[2][1 + k] = (un + c) * te.n[k] + ut * te.t[k];
+  }
+  for (int k = 0; k < 4; ++k) {
+    R acc = R(0);
+    for (int w = 0; w < 3; ++w) {
+      const R l = up ? fmax(lam[w], R(0)) : fmin(lam[w], R(0));
+      acc += l * beta[w] * Rv[w][k];
+    }
+    out[k] = acc;
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// the step
+
+template <typename R>
+struct SphereArgs {
+  const R* q;
+  const R* ghost;
+  R* qn;
+  const double* dt;
+  double* numax;
+  const PatchRec* __restrict__ rec;
+  const int32_t* __restrict__ phislot;
+  R* phi;
+  int32_t* err;
+  const double* __restrict__ geo;
+  R* scratch;                    // per workgroup: sphere_scratch(m) elements
+  int P, m, lm, limiter, transverse;
+  double g;
+};
+
+// scratch per direction and edge (e, r) -> e (m+2) + r:
+//   W 12, S 3, AM 4, AP 4, FL 1, FO 4 (own correction), T 16 (transverse
+//   parts [side][lo/hi][k], already scaled by -dt/(2 kappa dx))
+constexpr int kSEw = 0, kSEs = 12, kSEam = 15, kSEap = 19, kSEfl = 23, kSEfo = 24,
+              kSEt = 28, kSEn = 44;
+__host__ __device__ inline size_t sphere_scratch(int m) {
+  return size_t(2) * (m + 3) * (m + 2) * kSEn;
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_sphere_step(SphereArgs<R> A) {
+  extern __shared__ unsigned char smem_raw[];
+  const int m = A.m, FR = (m + 4) * (m + 4), M2 = m + 2, NE = (m + 3) * (m + 2);
+  R* Qs = reinterpret_cast<R*>(smem_raw);                    // [4][FR]
+  // 4 FR R values (a multiple of 8 bytes), then FR capacities
+  double* kap = reinterpret_cast<double*>(smem_raw + sizeof(R) * 4 * FR);
+  __shared__ double red[4];
+  R* scr = A.scratch + size_t(blockIdx.x) * sphere_scratch(m);
+  auto E = [&](int d, int e, int r) { return scr + (size_t(d) * NE + size_t(e) * M2 + r) * kSEn; };
+  auto cell_i = [](int d, int n, int r) { return d == 0 ? n : r; };
+  auto cell_j = [](int d, int n, int r) { return d == 0 ? r : n; };
+  const double dt = *A.dt;
+  const R grav = R(A.g);
+  const int G = 8 * m + 16;
+  for (int p = blockIdx.x; p < A.P; p += gridDim.x) {
+    const PatchRec& rp = A.rec[p];
+    const double dx = ldexp(1.0, -rp.level) / m;
+    const double* geo = A.geo + size_t(p) * kGeoN * FR;
+    __syncthreads();
+    for (int f = threadIdx.x; f < FR; f += blockDim.x) {
+      const int i = f % (m + 4) - 1, j = f / (m + 4) - 1;
+      const bool outer = (i == -1 || i == m + 2) && (j == -1 || j == m + 2);
+      for (int k = 0; k < 4; ++k) {
+        R v;
+        if (i >= 1 && i <= m && j >= 1 && j <= m)
+          v = A.q[(size_t(p * 4 + k) * m + (j - 1)) * m + (i - 1)];
+        else
+          v = outer ? R(0) : A.ghost[size_t(p * 4 + k) * G + ghost_index(m, i, j)];
+        Qs[k * FR + f] = v;
+      }
+      kap[f] = geo[kGeoK * FR + f];
+    }
+    __syncthreads();
+    // phase 1: Riemann problems at every edge of rows 0..m+1, both directions
+    double nmax = 0.0;
+    for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+      const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+      const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
+      const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
+      R ql[4], qr[4];
+      for (int k = 0; k < 4; ++k) {
+        ql[k] = Qs[k * FR + fidx(m, il, jl)];
+        qr[k] = Qs[k * FR + fidx(m, ir, jr)];
+      }
+      const SEdge<R> eg = load_edge<R>(geo + kGeoE * FR + (d * FR + fidx(m, ir, jr)) * 7);
+      R* o = E(d, e, r);
+      R W[3][4], s[3], am[4], ap[4], fl;
+      if (!rp_sphere<R>(grav, eg, ql, qr, W, s, am, ap, fl)) {
+        atomicOr(A.err, kErrNegDepth);
+        for (int w = 0; w < 3; ++w) { s[w] = R(0); for (int k = 0; k < 4; ++k) W[w][k] = R(0); }
+        for (int k = 0; k < 4; ++k) am[k] = ap[k] = R(0);
+        fl = R(0);
+      }
+      for (int w = 0; w < 3; ++w) {
+        for (int k = 0; k < 4; ++k) o[kSEw + 4 * w + k] = W[w][k];
+        o[kSEs + w] = s[w];
+      }
+      for (int k = 0; k < 4; ++k) { o[kSEam + k] = am[k]; o[kSEap + k] = ap[k]; }
+      o[kSEfl] = fl;
+      if (r >= 1 && r <= m) {
+        const double dtdl = dt / (kap[fidx(m, il, jl)] * dx), dtdr = dt / (kap[fidx(m, ir, jr)] * dx);
+        for (int w = 0; w < 3; ++w) {
+          nmax = fmax(nmax, dtdr * fmax(double(s[w]), 0.0));
+          nmax = fmax(nmax, dtdl * fmax(-double(s[w]), 0.0));
+        }
+      }
+    }
+    __syncthreads();
+    // phase 2: limited corrections and transverse parts at edges 1..m+1
+    for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+      const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+      if (e < 1 || e > m + 1) continue;
+      const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
+      const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
+      const double dtdl = dt / (kap[fidx(m, il, jl)] * dx), dtdr = dt / (kap[fidx(m, ir, jr)] * dx);
+      const R nu = R(0.5 * (dtdl + dtdr));
+      R* o = E(d, e, r);
+      R cq[4] = {R(0), R(0), R(0), R(0)};
+      for (int w = 0; w < 3; ++w) {
+        const R* Wc = o + kSEw + 4 * w;
+        const R sw = o[kSEs + w];
+        R wn2 = R(0);
+        for (int k = 0; k < 4; ++k) wn2 += Wc[k] * Wc[k];
+        if (wn2 == R(0)) continue;
+        const R* Wu = E(d, sw > R(0) ? e - 1 : e + 1, r) + kSEw + 4 * w;
+        R dot = R(0);
+        for (int k = 0; k < 4; ++k) dot += Wu[k] * Wc[k];
+        const R lim = limiter_phi<R>(A.limiter, dot / wn2);
+        const R as = fabs(sw);
+        for (int k = 0; k < 4; ++k) cq[k] += as * (R(1) - nu * as) * lim * Wc[k];
+      }
+      for (int k = 0; k < 4; ++k) o[kSEfo + k] = R(0.5) * cq[k];
+      if (A.transverse == 0) {
+        for (int k = 0; k < 16; ++k) o[kSEt + k] = R(0);
+        continue;
+      }
+      R ql[4], qr[4], amt[4], apt[4];
+      for (int k = 0; k < 4; ++k) {
+        ql[k] = Qs[k * FR + fidx(m, il, jl)];
+        qr[k] = Qs[k * FR + fidx(m, ir, jr)];
+        const R c2 = A.transverse == 2 ? cq[k] : R(0);
+        amt[k] = o[kSEam + k] + c2;
+        apt[k] = o[kSEap + k] - c2;
+      }
+      for (int side = 0; side < 2; ++side) {
+        const int col = side == 0 ? e - 1 : e;
+        const R h = R(-0.5 * (side == 0 ? dtdl : dtdr));
+        const int ci = cell_i(d, col, r), cj = cell_j(d, col, r);
+        const int ui = cell_i(d, col, r + 1), uj = cell_j(d, col, r + 1);
+        const SEdge<R> lo = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + fidx(m, ci, cj)) * 7);
+        const SEdge<R> hi = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + fidx(m, ui, uj)) * 7);
+        R bm[4], bp[4];
+        const R* psi = side == 0 ? amt : apt;
+        if (!tsplit_sphere<R>(grav, ql, qr, lo, psi, false, bm) ||
+            !tsplit_sphere<R>(grav, ql, qr, hi, psi, true, bp)) {
+          atomicOr(A.err, kErrNegDepth);
+          for (int k = 0; k < 4; ++k) bm[k] = bp[k] = R(0);
+        }
+        for (int k = 0; k < 4; ++k) {
+          o[kSEt + (side * 2 + 0) * 4 + k] = h * bm[k];
+          o[kSEt + (side * 2 + 1) * 4 + k] = h * bp[k];
+        }
+      }
+    }
+    __syncthreads();
+    // phase 3: update of interior cells and face terms
+    // total correction flux of edge (e, r) in direction d: own part, then the
+    // transverse parts of the other sweep's edges
+    auto Ftot = [&](int d, int e, int r, int k) -> R {
+      const int o = 1 - d;
+      R v = E(d, e, r)[kSEfo + k];
+      v += E(o, r, e - 1)[kSEt + (1 * 2 + 1) * 4 + k];
+      v += E(o, r + 1, e - 1)[kSEt + (0 * 2 + 1) * 4 + k];
+      v += E(o, r, e)[kSEt + (1 * 2 + 0) * 4 + k];
+      v += E(o, r + 1, e)[kSEt + (0 * 2 + 0) * 4 + k];
+      return v;
+    };
+    for (int c = threadIdx.x; c < m * m; c += blockDim.x) {
+      const int i = c % m + 1, j = c / m + 1;
+      const int f = fidx(m, i, j);
+      const R dtd = R(dt / (kap[f] * dx));
+      R out[4];
+      for (int k = 0; k < 4; ++k) {
+        R fx, gy;
+        if (k == 0) {
+          fx = E(0, i + 1, j)[kSEfl] - E(0, i, j)[kSEfl];
+          gy = E(1, j + 1, i)[kSEfl] - E(1, j, i)[kSEfl];
+        } else {
+          fx = E(0, i, j)[kSEap + k] + E(0, i + 1, j)[kSEam + k];
+          gy = E(1, j, i)[kSEap + k] + E(1, j + 1, i)[kSEam + k];
+        }
+        fx = fx + (Ftot(0, i + 1, j, k) - Ftot(0, i, j, k));
+        gy = gy + (Ftot(1, j + 1, i, k) - Ftot(1, j, i, k));
+        out[k] = Qs[k * FR + f] - dtd * fx - dtd * gy;
+      }
+      // momentum onto the tangent plane at the cell centre
+      const double* rc = geo + kGeoC * FR + 3 * f;
+      const R mr = out[1] * R(rc[0]) + out[2] * R(rc[1]) + out[3] * R(rc[2]);
+      for (int k = 0; k < 3; ++k) out[1 + k] -= mr * R(rc[k]);
+      for (int k = 0; k < 4; ++k) A.qn[(size_t(p * 4 + k) * m + (j - 1)) * m + (i - 1)] = out[k];
+    }
+    const int slot = A.phislot[p];
+    if (slot >= 0) {
+      R* ph = A.phi + size_t(slot) * 4 * m * 4;
+      for (int it = threadIdx.x; it < 4 * m * 4; it += blockDim.x) {
+        const int k = it % 4, t = (it / 4) % m + 1, fc = it / (4 * m);
+        const int d = fc / 2, e = (fc & 1) ? m + 1 : 1;
+        const R* o = E(d, e, t);
+        R fluct;
+        if (k == 0) fluct = (fc & 1) ? o[kSEfl] : -o[kSEfl];
+        else fluct = (fc & 1) ? o[kSEam + k] : o[kSEap + k];
+        const R corr = Ftot(d, e, t, k);
+        ph[it] = R(dx) * ((fc & 1) ? fluct + corr : fluct - corr);
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nmax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double v = red[0];
+      for (int w = 1; w < int(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+      atomic_max_pos(A.numax, v);
+    }
+  }
+}
+
+// Coarse-fine correction and cube-edge mass sync (one thread per item and
+// coarse cell); momentum corrections are projected like the step's output.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_sphere_reflux(const R* q, R* qn, const RefluxItem* __restrict__ items, int32_t nitems,
+                const PatchRec* __restrict__ rec, const int32_t* __restrict__ phislot,
+                const R* phi, const double* __restrict__ geo, const double* dt, double g,
+                int m, int32_t* err) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(nitems) * 32) return;
+  const int ii = int(t >> 5), tc = int(t & 31) + 1;
+  if (tc > m) return;
+  const int FR = (m + 4) * (m + 4);
+  const RefluxItem it = items[ii];
+  const int fc = it.face, d = fc >> 1, hi = fc & 1, C = it.coarse;
+  const int ic = d == 0 ? (hi ? m : 1) : tc, jc = d == 0 ? tc : (hi ? m : 1);
+  const double dxc = ldexp(1.0, -rec[C].level) / m;
+  const double kc = geo[size_t(C) * kGeoN * FR + kGeoK * FR + fidx(m, ic, jc)];
+  const R* pc = phi + size_t(phislot[C]) * 4 * m * 4 + (fc * m + (tc - 1)) * 4;
+  const double fac = *dt / (kc * dxc * dxc);
+  if (it.fine[1] == kSyncItem) {
+    const int L = it.fine[0], ff = it.fine_face[0];
+    const int pos = it.fine_rev[0] ? m + 1 - tc : tc;
+    const R* pn = phi + size_t(phislot[L]) * 4 * m * 4 + (ff * m + (pos - 1)) * 4;
+    qn[(size_t(C * 4) * m + (jc - 1)) * m + (ic - 1)] -= R(fac) * (-pn[0] - pc[0]);
+    return;
+  }
+  const int k2 = (tc - 1) / (m / 2);
+  const int fp = it.fine[k2], ff = it.fine_face[k2];
+  R qc[4], corr[4] = {R(0), R(0), R(0), R(0)};
+  for (int k = 0; k < 4; ++k) qc[k] = q[(size_t(C * 4 + k) * m + (jc - 1)) * m + (ic - 1)];
+  const R* pf = phi + size_t(phislot[fp]) * 4 * m * 4;
+  for (int s = 0; s < 2; ++s) {
+    int pos = 2 * (tc - 1 - k2 * (m / 2)) + 1 + s;
+    if (it.fine_rev[k2]) pos = m + 1 - pos;
+    const int fi = ff < 2 ? (ff == 0 ? 1 : m) : pos;
+    const int fj = ff < 2 ? pos : (ff == 2 ? 1 : m);
+    R qv[4];
+    for (int k = 0; k < 4; ++k) qv[k] = q[(size_t(fp * 4 + k) * m + (fj - 1)) * m + (fi - 1)];
+    // the fine edge as the fine leaf sees it, normal turned from the left
+    // state to the right one
+    const int ei = ff == 1 ? fi + 1 : fi, ej = ff == 3 ? fj + 1 : fj;
+    SEdge<R> eg = load_edge<R>(geo + size_t(fp) * kGeoN * FR + kGeoE * FR +
+                               ((ff / 2) * FR + fidx(m, ei, ej)) * 7);
+    if (((ff & 1) == 1) != (hi == 0))
+      for (int c = 0; c < 3; ++c) { eg.n[c] = -eg.n[c]; eg.t[c] = -eg.t[c]; }
+    R W[3][4], sp[3], am[4], ap[4], fl;
+    const bool ok = hi ? rp_sphere<R>(R(g), eg, qc, qv, W, sp, am, ap, fl)
+                       : rp_sphere<R>(R(g), eg, qv, qc, W, sp, am, ap, fl);
+    if (!ok) {
+      atomicOr(err, kErrNegDepth);
+      for (int k = 0; k < 4; ++k) am[k] = ap[k] = R(0);
+    }
+    for (int k = 0; k < 4; ++k)
+      corr[k] += (k == 0 ? R(0) : R(0.5 * dxc) * (am[k] + ap[k])) - pf[(ff * m + (pos - 1)) * 4 + k];
+  }
+  R dq[4];
+  for (int k = 0; k < 4; ++k) dq[k] = -R(fac) * (corr[k] - pc[k]);
+  const double* rc = geo + size_t(C) * kGeoN * FR + kGeoC * FR + 3 * fidx(m, ic, jc);
+  const R mr = dq[1] * R(rc[0]) + dq[2] * R(rc[1]) + dq[3] * R(rc[2]);
+  for (int k = 0; k < 3; ++k) dq[1 + k] -= mr * R(rc[k]);
+  for (int k = 0; k < 4; ++k) qn[(size_t(C * 4 + k) * m + (jc - 1)) * m + (ic - 1)] += dq[k];
+}
+
+// Per-patch FP64 partial sums of kappa q dxi^2.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_sphere_sums_patch(const R* __restrict__ q, const PatchRec* __restrict__ rec,
+                    const double* __restrict__ geo, int m, double* __restrict__ partial) {
+  __shared__ double red[4][4];
+  const int p = blockIdx.x, tid = threadIdx.x, FR = (m + 4) * (m + 4);
+  const double dx = ldexp(1.0, -rec[p].level) / m;
+  const double* kap = geo + size_t(p) * kGeoN * FR + kGeoK * FR;
+  double acc[4] = {0, 0, 0, 0};
+  for (int c = tid; c < m * m; c += 256) {
+    const double kk = kap[fidx(m, c % m + 1, c / m + 1)];
+    for (int k = 0; k < 4; ++k) acc[k] += kk * double(q[size_t(p * 4 + k) * m * m + c]);
+  }
+  for (int k = 0; k < 4; ++k) {
+    double v = acc[k];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((tid & 63) == 0) red[tid >> 6][k] = v;
+  }
+  __syncthreads();
+  if (tid < 4)
+    partial[size_t(p) * 4 + tid] =
+        ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) * dx * dx;
+}
+
+}  // namespace fcx

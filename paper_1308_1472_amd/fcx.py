@@ -20,7 +20,8 @@ LEAF_DTYPE = np.dtype([("tree", "<i4"), ("level", "<i4"), ("ix", "<i4"),
 TREE_DTYPE = np.dtype([("nbr_tree", "<i4", (4,)), ("nbr_face", "<i4", (4,)),
                        ("orient", "<i4", (4,)), ("bc", "<i4", (4,))])
 
-FCX_ADVECTION, FCX_SHALLOW = 0, 1
+FCX_ADVECTION, FCX_SHALLOW, FCX_SPHERE = 0, 1, 2
+GEO_FRAMES = 18          # geometry table frames per patch (fcx_sphere_geometry)
 ERRORS = {-1: "FCX_EINVAL", -2: "FCX_EBALANCE", -3: "FCX_ENOMEM",
           -4: "FCX_EHIP", -5: "FCX_ECFL", -6: "FCX_ENEG", -7: "FCX_ESTATE"}
 
@@ -37,6 +38,7 @@ EXPORTS = [
     "fcx_batch_set_tuning", "fcx_batch_step", "fcx_batch_capture",
     "fcx_batch_replay", "fcx_batch_sums", "fcx_features", "fcx_mlp_forward",
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
+    "fcx_sphere_geometry",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -113,6 +115,7 @@ def lib():
         L.fcx_adam_step.argtypes = [i64, vp, vp, vp, vp, i32, fl, fl, fl, fl, vp]
         L.fcx_learned_tags.argtypes = [i64, vp, vp, fl, vp, vp]
         L.fcx_dilate_tags.argtypes = [vp, vp, i32, vp, vp]
+        L.fcx_sphere_geometry.argtypes = [vp, vp, vp]
         _lib = L
     return _lib
 
@@ -239,7 +242,7 @@ class Context:
 
     def __init__(self, cfg: Config, trees):
         self.cfg = cfg
-        self.meqn = 1 if cfg.physics == FCX_ADVECTION else 3
+        self.meqn = {FCX_ADVECTION: 1, FCX_SHALLOW: 3, FCX_SPHERE: 4}[cfg.physics]
         self.trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
         h = C.c_void_p()
         _check(lib().fcx_create(C.byref(cfg), len(self.trees),
@@ -347,6 +350,17 @@ class Context:
         n = self.num_patches()
         _check(lib().fcx_dilate_tags(self.h, _dev(tags_in, n, torch.int8), lmax,
                                      _dev(tags_out, n, torch.int8), _stream(stream)))
+
+    def sphere_geometry(self, out=None, stream=None):
+        """(P, 18, m+4, m+4) geometry tables of a sphere context (device)."""
+        import torch
+        m = self.cfg.m
+        n = self.num_patches() * GEO_FRAMES * (m + 4) ** 2
+        if out is None:
+            out = torch.empty(n, dtype=torch.float64, device="cuda")
+        _check(lib().fcx_sphere_geometry(self.h, _dev(out, n, torch.float64),
+                                         _stream(stream)))
+        return out.view(self.num_patches(), GEO_FRAMES, m + 4, m + 4)
 
     def regrid_apply(self, tags_host, lmin, lmax) -> int:
         t = np.ascontiguousarray(tags_host, dtype=np.int8)

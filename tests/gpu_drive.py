@@ -138,7 +138,8 @@ class Gpu:
 
 
 def oracle_params(cfg):
-    phys = O.ADVECTION if cfg.physics == fcx.FCX_ADVECTION else O.SHALLOW
+    phys = {fcx.FCX_ADVECTION: O.ADVECTION, fcx.FCX_SHALLOW: O.SHALLOW,
+            fcx.FCX_SPHERE: O.SPHERE}[cfg.physics]
     return O.params(cfg.m, phys, limiter=cfg.limiter, transverse=cfg.transverse,
                     g=cfg.g, ax=cfg.ax, ay=cfg.ay)
 
