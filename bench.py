@@ -46,7 +46,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "all"],
+    ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "sphere",
+                                       "mlp", "copy", "all"],
                     default="all")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--tile", type=int, default=0)
@@ -62,18 +63,23 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def stored_traffic(name):
-    """HBM bytes per launch from a committed rocprofv3 counter summary, if it
-    was taken on the current kernel source."""
+def stored_profile(name, key):
+    """A figure of a committed rocprofv3 summary under profiles/, if it was
+    taken on the current kernel source."""
     path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     text = open(path).read()
     m = re.search(r"kernel_source_sha256:\s*(\w+)", text)
-    b = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", text)
+    b = re.search(key + r":\s*([0-9.eE+]+)", text)
     if not m or not b or m.group(1) != kernel_source_hash():
         return None
     return float(b.group(1))
+
+
+def stored_traffic(name):
+    """HBM bytes per launch (memory counters scaled by a plain copy)."""
+    return stored_profile(name, "hbm_bytes_per_launch")
 
 
 class Workload:
@@ -178,6 +184,7 @@ def run(precision, fused, steps, warmup, uniform_level=None):
     for _ in range(warmup):
         w.step()
     torch.cuda.synchronize()
+    w.status.zero_()                      # CFL flags of the timed steps only
     w.cells = []
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(steps)]
@@ -261,6 +268,101 @@ def run_batch(steps, warmup, nforests=64, graph_steps=10):
             "bytes_per_step": step_bytes}
 
 
+def run_sphere(steps, precision=32, level=4, m=16):
+    """Cubed sphere: 6 trees uniform at `level`, m x m patches, a Gaussian
+    height bump on h = 1 at rest, plain path (ghost fill + step + reflux with
+    cube-edge mass sync), fixed dt."""
+    import numpy as np
+    import torch
+    from paper_1308_1472_amd import fcx
+    from paper_1308_1472_amd import inputs as I
+    trees = I.cubed_sphere()
+    lv = fcx.sfc_sort(I.uniform_leaves(6, level))
+    ctx = fcx.Context(fcx.config(m, precision, fcx.FCX_SPHERE), trees)
+    ctx.upload_forest(lv)
+    dtype = torch.float32 if precision == 32 else torch.float64
+    q = torch.from_numpy(I.sphere_bump(lv, m).ravel()).to(dtype).cuda()
+    qn = torch.empty_like(q)
+    ghost = torch.empty(ctx.ghost_elems(), dtype=dtype, device="cuda")
+    dt = torch.full((1,), 0.3 * (np.pi / 2) / (m << level), dtype=torch.float64,
+                    device="cuda")
+    nu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    sums = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ctx.conservation_sums(q, sums)
+    m0 = sums[0].item()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    for k in range(steps + 3):
+        if k == 3:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            ev[0].record()
+        ctx.ghost_fill(q, ghost)
+        ctx.patch_step(q, ghost, qn, dt, nu)
+        ctx.reflux(q, qn, dt)
+        q, qn = qn, q
+    ev[1].record()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ctx.conservation_sums(q, sums)
+    cells = len(lv) * m * m
+    return {"patches": len(lv), "cells": cells, "steps": steps,
+            "rate": cells * steps / el, "ms_per_step": ev[0].elapsed_time(ev[1]) / steps,
+            "mass_rel_change": sums[0].item() / m0 - 1.0,
+            "nu_last": nu.item()}
+
+
+def run_mlp(rows=50000, reps=50):
+    """Tag network: forward (inference) and forward + backward + Adam
+    (training step) throughput on seeded inputs, bfloat16 MFMA kernels."""
+    import numpy as np
+    import torch
+    from paper_1308_1472_amd import fcx
+    rng = np.random.default_rng(0)
+    P = torch.from_numpy(rng.normal(0, 0.2, fcx.MLP_PARAMS).astype(np.float32)).cuda()
+    norm = torch.cat([torch.zeros(16), torch.ones(16)]).cuda()
+    x = torch.from_numpy(rng.normal(size=(rows, 16)).astype(np.float32)).cuda()
+    y = torch.from_numpy(rng.integers(0, 3, rows).astype(np.int32)).cuda()
+    cw = torch.ones(3, device="cuda")
+    z = torch.empty(rows, 3, device="cuda")
+    g = torch.empty(fcx.MLP_PARAMS, device="cuda")
+    loss = torch.empty(1, device="cuda")
+    m1, m2 = torch.zeros_like(g), torch.zeros_like(g)
+    out = {}
+    for name in ("forward", "train_step"):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        for k in range(reps + 3):
+            if k == 3:
+                ev[0].record()
+            if name == "forward":
+                fcx.mlp_forward(P, norm, x, z)
+            else:
+                fcx.mlp_backward(P, norm, x, y, cw, 1.0 / rows, g, loss)
+                fcx.adam_step(P, g, m1, m2, k + 1)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms = ev[0].elapsed_time(ev[1]) / reps
+        # matrix products: 16x64 + 64x64 + 64x3 MACs per row forward; the
+        # backward forms the same products twice more (weights and inputs)
+        macs = 16 * 64 + 64 * 64 + 64 * 3
+        flops = 2 * macs * rows * (1 if name == "forward" else 3)
+        out[name] = {"rows": rows, "ms": ms, "rows_per_s": rows / (ms * 1e-3),
+                     "tflops_bf16": flops / (ms * 1e-3) / 1e12}
+    return out
+
+
+def copy_calibration():
+    """A plain device copy of known size (1 GiB, three times), whose memory
+    counters scale the counters of the step kernels."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}), flush=True)
+
+
 def cpu_baseline(budget_s=12.0):
     """The CPU FP64 oracle, single-threaded, on the first steps of the same
     workload (same initial mesh, regrid every 4 steps)."""
@@ -317,6 +419,9 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.only == "copy":
+        copy_calibration()
+        return
     res = {}
     if args.only in ("fp32", "all"):
         res["fp32"] = run(32, True, args.steps, args.warmup)
@@ -332,20 +437,36 @@ def main():
     if args.only in ("batch", "all"):
         res["batch"] = run_batch(args.batch_steps, 10)
         print(f"# batch fp32: {res['batch']}", file=sys.stderr, flush=True)
+    if args.only in ("sphere", "all"):
+        res["sphere"] = run_sphere(20)
+        print(f"# sphere fp32: {res['sphere']}", file=sys.stderr, flush=True)
+    if args.only in ("mlp", "all"):
+        res["mlp"] = run_mlp()
+        print(f"# mlp: {res['mlp']}", file=sys.stderr, flush=True)
     head = res.get("fp32") or res.get("fp64") or res.get("large32")
     if head is None:
-        print(json.dumps({"batch": res.get("batch")}), flush=True)
+        print(json.dumps({k: res.get(k) for k in ("batch", "sphere", "mlp") if k in res}),
+              flush=True)
         return
     steps = args.steps if "fp32" in res or "fp64" in res else args.large_steps
     bytes_per_cell = 24.0 if head is not res.get("fp64") else 48.0
 
-    def roof(r, bpc, traffic_name):
-        ach = r["kernel_cells_mean"] * bpc / (r["kernel_ms_mean"] * 1e-3) / 1e9
-        tr = stored_traffic(traffic_name)
-        return {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": tr,
-                "kernel": "k_step", "kernel_ms": r["kernel_ms_mean"],
-                "bytes_per_launch": r["kernel_cells_mean"] * bpc}
+    def roof(r, bpc, profile):
+        """HBM roofline of the step kernel: algorithmic bytes (read and write
+        every state value once) per launch over the launch time measured
+        with HIP events on the launch stream."""
+        alg = r["kernel_cells_mean"] * bpc
+        ach = alg / (r["kernel_ms_mean"] * 1e-3) / 1e9
+        out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+               "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+               "traffic": stored_traffic(profile),
+               "kernel": "k_step", "kernel_ms": r["kernel_ms_mean"],
+               "bytes_per_launch": alg, "profile": "profiles/" + profile}
+        frac = stored_profile(profile, "valu_issue_frac")
+        if frac is not None:
+            out["valu_issue_frac"] = frac
+            out["valu_lane_ops_per_cell"] = stored_profile(profile, "valu_lane_ops_per_cell")
+        return out
 
     out = {
         "metric": "cell-updates/s + HBM GB/s % peak, FP32 batched vs FP64 plain, "
@@ -369,14 +490,20 @@ def main():
             "patches_at_end": head["patches_last"],
             "path": "fused ghost-gather + update, FP32 state, FP64 dt/CFL/sums",
         },
-        "roofline": roof(head, bytes_per_cell, "traffic_k_step_fused_sw_fp32_adaptive.txt"),
+        # the adaptive state (about 8 MB in FP32) lives in the 256 MB
+        # last-level cache, so the HBM roofline is quoted on the same kernel
+        # at uniform level 8 (16.8 M cells, 0.4 GB per step) when it ran
+        "roofline": (roof(res["large32"], 24.0, "k_step_fused_sw_fp32_level8.txt")
+                     if "large32" in res else
+                     roof(head, bytes_per_cell, "k_step_fused_sw_fp32_adaptive.txt")),
+        "roofline_adaptive": roof(head, bytes_per_cell, "k_step_fused_sw_fp32_adaptive.txt"),
     }
     if "fp64" in res:
         out["fp64_plain"] = {"value": res["fp64"]["rate"],
                              "ms_per_step": res["fp64"]["seconds"] / args.steps * 1e3,
                              "kernel_ms": res["fp64"]["kernel_ms_mean"],
                              "roofline": roof(res["fp64"], 48.0,
-                                              "traffic_k_step_plain_sw_fp64_adaptive.txt")}
+                                              "k_step_plain_sw_fp64_adaptive.txt")}
         if "fp32" in res:
             out["speedup_fp32_fused_vs_fp64_plain"] = res["fp32"]["rate"] / res["fp64"]["rate"]
     if "large32" in res:
@@ -384,10 +511,8 @@ def main():
             "cells": res["large32"]["kernel_cells_mean"],
             "fp32_fused_rate": res["large32"]["rate"],
             "fp64_plain_rate": res["large64"]["rate"],
-            "fp32_roofline": roof(res["large32"], 24.0,
-                                  "traffic_k_step_fused_sw_fp32_level8.txt"),
-            "fp64_roofline": roof(res["large64"], 48.0,
-                                  "traffic_k_step_plain_sw_fp64_level8.txt"),
+            "fp32_roofline": roof(res["large32"], 24.0, "k_step_fused_sw_fp32_level8.txt"),
+            "fp64_roofline": roof(res["large64"], 48.0, "k_step_plain_sw_fp64_level8.txt"),
         }
     if "batch" in res:
         rb = res["batch"]
@@ -403,6 +528,12 @@ def main():
             "speedup_vs_fp64_plain_adaptive": (rb["rate"] / res["fp64"]["rate"]
                                                if "fp64" in res else None),
         }
+    if "sphere" in res:
+        out["cubed_sphere"] = dict(res["sphere"], workload=(
+            "shallow water on the cubed sphere, 6 trees uniform level 4, m=16, "
+            "FP32 state, FP64 geometry and sums, plain path with reflux"))
+    if "mlp" in res:
+        out["learned_tagging_mlp"] = res["mlp"]
     flags = {k: r["status"] for k, r in res.items() if "status" in r and r["status"]}
     if flags:
         out["cfl_flags"] = flags
