@@ -162,8 +162,8 @@ int fcx_patch_step(fcx_ctx *ctx, const void *q, const void *ghost, void *q_new,
 int fcx_fused_step(fcx_ctx *ctx, const void *q, void *q_new, const double *dt,
                    double *nu_max, void *stream);
 
-/* Coarse-fine correction with one global dt (Sec. 4: correction factors
- * propagated back from fine to coarse levels): each coarse cell at a
+/* Coarse-fine correction with one global dt (Sec. 4: fine-level corrections
+ * are carried back to the coarse level): each coarse cell at a
  * coarse-fine face gets the sum of the two fine face terms instead of its
  * own.  Needs the face terms of the preceding patch step on the same q. */
 int fcx_reflux(fcx_ctx *ctx, const void *q, void *q_new, const double *dt,

@@ -5,7 +5,7 @@
  * Sec. 3 of the paper: every patch is surrounded by two ghost layers; a
  * same-level neighbour copies its edge cells into them, finer neighbours
  * average their edge cells into them, and a coarser neighbour fills them by
- * conservative, limited interpolation.
+ * interpolation that is conservative and limited.
  *
  * The oracle states this as one definition, applied cell by cell:
  *

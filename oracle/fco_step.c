@@ -28,8 +28,8 @@
  * Accumulation order is fixed: xi-rows ascending, then eta-columns
  * ascending, edges ascending inside each.
  *
- * Reflux (reading of Sec. 4, "correction factors are propagated back from
- * fine to coarse levels", with one global dt): at every coarse-fine face
+ * Reflux (reading of Sec. 4, where fine-level corrections are carried back to
+ * the coarse level after each step; here with one global dt): at every coarse-fine face
  * the coarse cell's face term is replaced by the sum of the fine face
  * terms.  The Roe property turns the missing f(Q_fine) - f(Q_coarse) into
  * the fluctuation sum of one extra Riemann problem per fine cell.
