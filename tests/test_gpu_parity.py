@@ -88,7 +88,7 @@ def test_one_step_matches_oracle(domain, phys, m, fused, reflux):
     assert abs(nu - nu_o) <= 1e-14 * nu_o
 
 
-def _cfg1_run(fused):
+def _advection_16_patches_run(fused):
     trees, pl = I.periodic_square()
     lv = O.sfc_sort(I.uniform_leaves(1, 2))
     cfg = fcx.config(8, 64, fcx.FCX_ADVECTION, ax=1.0, ay=0.5)
@@ -104,7 +104,7 @@ def _cfg1_run(fused):
 def test_advection_16_patches_100_steps(fused):
     """16 patches of 8x8, a = (1, 0.5), periodic, CFL 0.9, MC + transverse."""
     say(f"[cfg-small] fused={fused}")
-    trees, lv, cfg, q0, got = _cfg1_run(fused)
+    trees, lv, cfg, q0, got = _advection_16_patches_run(fused)
     mesh = O.Mesh(trees, lv, 8)
     par = oracle_params(cfg)
     q = q0
