@@ -158,6 +158,13 @@ class Workload:
     def step(self, ev=None):
         if not self.uniform and self.n > 0 and self.n % self.REGRID == 0:
             self.regrid()
+        if self.fused and ev is None:
+            # fused step, reflux and next dt in one library call
+            self.ctx.advance(self.q, self.qn, self.dt, self.numax, self.status)
+            self.q, self.qn = self.qn, self.q
+            self.cells.append(self.ctx.num_patches() * self.M * self.M)
+            self.n += 1
+            return
         if not self.fused:
             self.ctx.ghost_fill(self.q, self.ghost)
         if ev is not None:
@@ -186,22 +193,36 @@ def run(precision, fused, steps, warmup, uniform_level=None):
     torch.cuda.synchronize()
     w.status.zero_()                      # CFL flags of the timed steps only
     w.cells = []
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(steps):
-        w.step(evs[k])
+        w.step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    kms = [a.elapsed_time(b) for a, b in evs]
     cells = float(sum(w.cells))
+    status = int(w.status.item())
+    # the step kernel alone: nk back-to-back launches on the current mesh
+    # between two HIP events on the launch stream (the launch is idempotent:
+    # it reads q and writes q_new)
+    nk = 20
+    if not w.fused:
+        w.ctx.ghost_fill(w.q, w.ghost)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(nk):
+        if w.fused:
+            w.ctx.fused_step(w.q, w.qn, w.dt, w.numax)
+        else:
+            w.ctx.patch_step(w.q, w.ghost, w.qn, w.dt, w.numax)
+    b.record()
+    torch.cuda.synchronize()
+    w.numax.zero_()
     return {
         "seconds": el, "cells": cells, "rate": cells / el,
-        "kernel_ms_mean": sum(kms) / len(kms),
-        "kernel_cells_mean": cells / steps,
+        "kernel_ms_mean": a.elapsed_time(b) / nk,
+        "kernel_cells_mean": float(w.ctx.num_patches() * w.M * w.M),
         "patches_last": w.ctx.num_patches(),
-        "status": int(w.status.item()),
+        "status": status,
     }
 
 

@@ -176,6 +176,12 @@ int fcx_reflux(fcx_ctx *ctx, const void *q, void *q_new, const double *dt,
 int fcx_next_dt(fcx_ctx *ctx, double *nu_max, double *dt, int32_t *status,
                 void *stream);
 
+/* One whole step of the fused path in one call: fcx_fused_step (q ->
+ * q_new), fcx_reflux, fcx_next_dt (dt is updated for the next step, nu_max
+ * cleared, status flags raised).  Planar forests only. */
+int fcx_advance(fcx_ctx *ctx, const void *q, void *q_new, double *dt,
+                double *nu_max, int32_t *status, void *stream);
+
 /* sums[k] = sum over interior cells of q_k * cell area, in FP64, reduced in
  * a fixed order (deterministic). */
 int fcx_conservation_sums(fcx_ctx *ctx, const void *q, double *sums,

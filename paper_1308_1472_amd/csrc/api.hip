@@ -132,6 +132,7 @@ struct fcx_ctx {
   HostBuf staging;
   DevBuf<uint8_t> sscratch;        // sphere step: per-workgroup edge data
   int cus = 256;
+  Plan plan;                       // host copy of the current forest's plan
 };
 
 // Cube faces as (centre, u, v) axis vectors, the same frames as the device
@@ -294,7 +295,11 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
                        const std::vector<int32_t>* src = nullptr) {
   Plan plan;
   std::string err;
-  int rc = build_plan(f, c->cfg.m, plan, err, c->cfg.physics == FCX_SPHERE);
+  const bool sync = c->cfg.physics == FCX_SPHERE;
+  // after a regrid only the patches next to a change are planned afresh
+  int rc = (kind && src && c->plan.recs.size() == c->old_forest.leaves.size())
+               ? update_plan(f, c->cfg.m, c->plan, *kind, *src, plan, err, sync)
+               : build_plan(f, c->cfg.m, plan, err, sync);
   if (rc != FCX_OK) return fail(rc, err);
   const size_t P = f.leaves.size();
   // reflux items: xi faces first, then eta faces
@@ -333,6 +338,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   dev.xsrc = src ? reinterpret_cast<int32_t*>(d + off[6]) : nullptr;
   dev.nslots = plan.nslots;
   dev.P = int64_t(P);
+  c->plan = std::move(plan);
   return FCX_OK;
 }
 
@@ -1161,4 +1167,16 @@ int fcx_sphere_geometry(fcx_ctx* c, double* geo, void* stream) {
   HIPCHK(hipMemcpyAsync(geo, c->cur.geo.p, sizeof(double) * c->cur.P * kGeoN * FR,
                         hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
   return FCX_OK;
+}
+
+// ---- one whole step --------------------------------------------------------
+
+int fcx_advance(fcx_ctx* c, const void* q, void* qn, double* dt, double* numax,
+                int32_t* status, void* stream) {
+  if (!c || !status) return fail(FCX_EINVAL, "bad arguments");
+  int rc = fcx_fused_step(c, q, qn, dt, numax, stream);
+  if (rc != FCX_OK) return rc;
+  rc = fcx_reflux(c, q, qn, dt, stream);
+  if (rc != FCX_OK) return rc;
+  return fcx_next_dt(c, numax, dt, status, stream);
 }

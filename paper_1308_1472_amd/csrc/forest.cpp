@@ -459,6 +459,8 @@ static int plan_one(const Forest& f, int m, int64_t p, PatchRec& r,
       int32_t ids[2];
       Xform xf;
       for (int s = 0; s < 2; ++s) {
+        // a same-level or coarser neighbour holds both halves of the face
+        if (s == 1 && f.leaves[ids[0]].level <= a.level) { ids[1] = ids[0]; break; }
         const int t = s == 0 ? 1 : m;
         int64_t x, y;
         if (fc < 2) centre(fc == 0 ? 0 : m + 1, t, x, y);
@@ -559,6 +561,20 @@ static int plan_one(const Forest& f, int m, int64_t p, PatchRec& r,
   return FCX_OK;
 }
 
+// Slots and reflux items numbered in patch order.
+static void finish_plan(Plan& plan, const std::vector<uint8_t>& mixed,
+                        const std::vector<RefluxItem>& items,
+                        const std::vector<uint8_t>& nitems) {
+  const int64_t n = int64_t(mixed.size());
+  plan.item_first.assign(n + 1, 0);
+  for (int64_t p = 0; p < n; ++p) {
+    if (mixed[p]) plan.phislot[p] = plan.nslots++;
+    plan.item_first[p] = int32_t(plan.reflux.size());
+    for (int k = 0; k < nitems[p]; ++k) plan.reflux.push_back(items[size_t(p) * 4 + k]);
+  }
+  plan.item_first[n] = int32_t(plan.reflux.size());
+}
+
 // Records for all patches, computed in parallel chunks; slots and reflux
 // items are then numbered in patch order.
 int build_plan(const Forest& f, int m, Plan& plan, std::string& err, bool sync) {
@@ -598,10 +614,67 @@ int build_plan(const Forest& f, int m, Plan& plan, std::string& err, bool sync) 
   }
   for (int t = 0; t < nth; ++t)
     if (rcs[t] != FCX_OK) { err = errs[t]; return rcs[t]; }
-  for (int64_t p = 0; p < n; ++p) {
-    if (mixed[p]) plan.phislot[p] = plan.nslots++;
-    for (int k = 0; k < nitems[p]; ++k) plan.reflux.push_back(items[size_t(p) * 4 + k]);
+  finish_plan(plan, mixed, items, nitems);
+  return FCX_OK;
+}
+
+int update_plan(const Forest& f, int m, const Plan& old,
+                const std::vector<int32_t>& kind, const std::vector<int32_t>& src,
+                Plan& plan, std::string& err, bool sync) {
+  const int64_t n = int64_t(f.leaves.size());
+  const int64_t no = int64_t(old.recs.size());
+  if (int64_t(kind.size()) != n || int64_t(src.size()) != n ||
+      int64_t(old.item_first.size()) != no + 1) {
+    err = "plan update: inconsistent inputs";
+    return FCX_EINVAL;
   }
+  std::vector<int32_t> o2n(no, -1);
+  for (int64_t p = 0; p < n; ++p)
+    if (kind[p] == 0) o2n[src[p]] = int32_t(p);
+  plan.recs.resize(n);
+  plan.phislot.resize(n);
+  plan.family.resize(n);
+  plan.item_first.resize(n + 1);
+  plan.reflux.clear();
+  plan.reflux.reserve(old.reflux.size() + 64);
+  plan.nslots = 0;
+  RefluxItem fresh[4];
+  for (int64_t p = 0; p < n; ++p) {
+    bool reuse = kind[p] == 0;
+    const int32_t o = src[p];
+    PatchRec& r = plan.recs[p];
+    if (reuse) {
+      r = old.recs[o];
+      for (int s2 = 0; s2 < 12 && reuse; ++s2) {
+        const int32_t nb = r.nbr[s2];
+        if (nb < 0) continue;
+        if (o2n[nb] < 0) reuse = false;
+        else r.nbr[s2] = o2n[nb];
+      }
+    }
+    plan.item_first[p] = int32_t(plan.reflux.size());
+    bool mixed;
+    if (reuse) {
+      mixed = old.phislot[o] >= 0;
+      plan.family[p] = old.family[o];
+      for (int32_t t = old.item_first[o]; t < old.item_first[o + 1]; ++t) {
+        RefluxItem it = old.reflux[t];
+        it.coarse = int32_t(p);
+        for (int s2 = 0; s2 < 2; ++s2)
+          if (it.fine[s2] >= 0) it.fine[s2] = o2n[it.fine[s2]];
+        plan.reflux.push_back(it);
+      }
+    } else {
+      int ni = 0;
+      int32_t fam = 0;
+      const int rc = plan_one(f, m, p, r, mixed, fam, fresh, ni, sync, err);
+      if (rc != FCX_OK) return rc;
+      plan.family[p] = fam;
+      for (int k = 0; k < ni; ++k) plan.reflux.push_back(fresh[k]);
+    }
+    plan.phislot[p] = mixed ? plan.nslots++ : -1;
+  }
+  plan.item_first[n] = int32_t(plan.reflux.size());
   return FCX_OK;
 }
 
@@ -693,8 +766,44 @@ int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
   }
   }
   ripple(f, set, work);
-  collect(set, out);
-  (void)err;
+  // the new leaves in SFC order, by walking the old ones in order: an old
+  // leaf is kept, the first child of a merged family, or the root of a
+  // subtree of new leaves (refined, possibly split further by the ripple)
+  out.clear();
+  out.reserve(set.size());
+  std::vector<fcx_leaf> stack;
+  for (int64_t p = 0; p < n; ++p) {
+    const fcx_leaf& a = f.leaves[p];
+    if (set.get(pack_key(a.tree, a.level, a.ix, a.iy)) >= 0) { out.push_back(a); continue; }
+    if (a.level > 0 && set.get(pack_key(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1)) >= 0) {
+      if (!(a.ix & 1) && !(a.iy & 1)) out.push_back({a.tree, a.level - 1, a.ix >> 1, a.iy >> 1});
+      continue;
+    }
+    stack.assign(1, a);
+    while (!stack.empty()) {
+      const fcx_leaf b = stack.back();
+      stack.pop_back();
+      // children pushed in reverse Morton order so they pop in order
+      for (int c = 3; c >= 0; --c) {
+        const fcx_leaf ch{b.tree, b.level + 1, 2 * b.ix + (c & 1), 2 * b.iy + (c >> 1)};
+        if (set.get(pack_key(ch.tree, ch.level, ch.ix, ch.iy)) >= 0) {
+          stack.push_back({-1 - ch.tree, ch.level, ch.ix, ch.iy});   // marked: emit
+        } else {
+          stack.push_back(ch);
+        }
+      }
+      while (!stack.empty() && stack.back().tree < 0) {
+        fcx_leaf e = stack.back();
+        stack.pop_back();
+        e.tree = -1 - e.tree;
+        out.push_back(e);
+      }
+    }
+  }
+  if (out.size() != set.size()) {
+    err = "regrid: new leaves do not tile the forest";
+    return FCX_EINVAL;
+  }
   return FCX_OK;
 }
 

@@ -116,7 +116,8 @@ struct Plan {
   std::vector<PatchRec> recs;
   std::vector<int32_t> phislot;              // -1 or slot of the patch
   int32_t nslots = 0;
-  std::vector<RefluxItem> reflux;
+  std::vector<RefluxItem> reflux;            // in patch order
+  std::vector<int32_t> item_first;           // items of patch p: [first[p], first[p+1])
   std::vector<int32_t> family;               // 1 at the first child of a
                                              // complete leaf family
 };
@@ -125,6 +126,14 @@ struct Plan {
 // by the cubed sphere, whose mass face terms must agree there).
 int build_plan(const Forest& f, int m, Plan& plan, std::string& err,
                bool sync = false);
+
+// Plan of forest f obtained by a regrid of the forest whose plan is `old`
+// (kind / src from transfer_plan): a kept patch whose twelve neighbour
+// regions are all held by kept leaves keeps its record, renumbered; every
+// other patch is planned afresh.  Same result as build_plan.
+int update_plan(const Forest& f, int m, const Plan& old,
+                const std::vector<int32_t>& kind, const std::vector<int32_t>& src,
+                Plan& plan, std::string& err, bool sync = false);
 
 // Regrid: refine +1, merge complete families tagged -1, then balance.
 int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,

@@ -38,7 +38,7 @@ EXPORTS = [
     "fcx_batch_set_tuning", "fcx_batch_step", "fcx_batch_capture",
     "fcx_batch_replay", "fcx_batch_sums", "fcx_features", "fcx_mlp_forward",
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
-    "fcx_sphere_geometry",
+    "fcx_sphere_geometry", "fcx_advance",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -116,6 +116,7 @@ def lib():
         L.fcx_learned_tags.argtypes = [i64, vp, vp, fl, vp, vp]
         L.fcx_dilate_tags.argtypes = [vp, vp, i32, vp, vp]
         L.fcx_sphere_geometry.argtypes = [vp, vp, vp]
+        L.fcx_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -314,6 +315,13 @@ class Context:
     def fused_step(self, q, q_new, dt, numax, stream=None):
         _check(lib().fcx_fused_step(self.h, self._q(q), self._q(q_new),
                                     self._d(dt), self._d(numax), _stream(stream)))
+
+    def advance(self, q, q_new, dt, numax, status, stream=None):
+        """Fused step + reflux + next dt in one call."""
+        import torch
+        _check(lib().fcx_advance(self.h, self._q(q), self._q(q_new), self._d(dt),
+                                 self._d(numax), self._d(status, 1, torch.int32),
+                                 _stream(stream)))
 
     def reflux(self, q, q_new, dt, stream=None):
         _check(lib().fcx_reflux(self.h, self._q(q), self._q(q_new), self._d(dt),
