@@ -149,9 +149,10 @@ class Workload:
         return self.tagbuf.cpu().numpy()
 
     def regrid(self):
-        tags = self._tags()                  # ghost buffer now holds a fill of q
+        # ghost fill, tags and mesh change in one call; the ghost buffer then
+        # holds the fill of q that the transfer needs
         q_old, g_old = self.q, self.ghost
-        self.ctx.regrid_apply(tags, self.LMIN, self.LMAX)
+        self.ctx.regrid(q_old, g_old, 1, self.THR, self.LMIN, self.LMAX)
         self._alloc()
         self.ctx.regrid_transfer(q_old, g_old, self.q)
 

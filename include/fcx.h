@@ -205,6 +205,14 @@ int fcx_regrid_tags(fcx_ctx *ctx, const void *q, const void *ghost,
 int fcx_regrid_apply(fcx_ctx *ctx, const int8_t *tags_host, int32_t lmin,
                      int32_t lmax, int64_t *n_new);
 
+/* fcx_ghost_fill of q into ghost, fcx_regrid_tags, the tags to the host
+ * and fcx_regrid_apply, in one call (synchronises the stream).  The ghost
+ * buffer then holds the fill that fcx_regrid_transfer needs; *n_new
+ * receives the new patch count. */
+int fcx_regrid(fcx_ctx *ctx, const void *q, void *ghost, int32_t criterion,
+               double threshold, int32_t lmin, int32_t lmax, int64_t *n_new,
+               void *stream);
+
 /* Data transfer after fcx_regrid_apply (Sec. 3: interpolate to new fine
  * patches, average to new coarse patches): kept patches copy, refined ones
  * interpolate with minmod slopes (the old ghost buffer must hold a fill of

@@ -60,9 +60,9 @@ struct DevBuf {
   }
   hipError_t ensure(size_t count) {
     if (count <= n && p) return hipSuccess;
-    // grow geometrically so that a mesh that grows step by step does not
-    // reallocate (and synchronize) at every regrid
-    const size_t c = std::max<size_t>(count ? count : 1, n + n / 2);
+    // grow geometrically, from at least 256 KiB, so that a mesh that grows
+    // step by step does not reallocate (and synchronize) at every regrid
+    const size_t c = std::max({count, 2 * n, (size_t(256) << 10) / sizeof(T) + 1});
     release();
     hipError_t e = hipMalloc(&p, c * sizeof(T));
     if (e == hipSuccess) n = c;
@@ -94,7 +94,8 @@ struct HostBuf {
     if (bytes <= n && p) return hipSuccess;
     if (p) (void)hipHostFree(p);
     p = nullptr;
-    const size_t c = std::max<size_t>(bytes, n + n / 2);
+    // pinned allocations are slow: grow by doubling, from 1 MiB
+    const size_t c = std::max({bytes, 2 * n, size_t(1) << 20});
     hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&p), c, hipHostMallocDefault);
     n = e == hipSuccess ? c : 0;
     return e;
@@ -133,6 +134,8 @@ struct fcx_ctx {
   DevBuf<uint8_t> sscratch;        // sphere step: per-workgroup edge data
   int cus = 256;
   Plan plan;                       // host copy of the current forest's plan
+  DevBuf<int8_t> tags_dev;         // fcx_regrid: tags on the device
+  HostBuf tags_host;               //   and their pinned host copy
 };
 
 // Cube faces as (centre, u, v) axis vectors, the same frames as the device
@@ -1179,4 +1182,24 @@ int fcx_advance(fcx_ctx* c, const void* q, void* qn, double* dt, double* numax,
   rc = fcx_reflux(c, q, qn, dt, stream);
   if (rc != FCX_OK) return rc;
   return fcx_next_dt(c, numax, dt, status, stream);
+}
+
+// ---- tags and mesh change in one call ---------------------------------------
+
+int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double threshold,
+               int32_t lmin, int32_t lmax, int64_t* n_new, void* stream) {
+  if (!c || !q || !ghost || !n_new) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  const int64_t P = c->cur.P;
+  HIPCHK(c->tags_dev.ensure(size_t(P)));
+  HIPCHK(c->tags_host.ensure(size_t(P)));
+  int rc = fcx_ghost_fill(c, q, ghost, stream);
+  if (rc != FCX_OK) return rc;
+  rc = fcx_regrid_tags(c, q, ghost, criterion, threshold, lmin, lmax, c->tags_dev.p, stream);
+  if (rc != FCX_OK) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(hipMemcpyAsync(c->tags_host.p, c->tags_dev.p, size_t(P), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return fcx_regrid_apply(c, reinterpret_cast<const int8_t*>(c->tags_host.p), lmin, lmax,
+                          n_new);
 }

@@ -38,7 +38,7 @@ EXPORTS = [
     "fcx_batch_set_tuning", "fcx_batch_step", "fcx_batch_capture",
     "fcx_batch_replay", "fcx_batch_sums", "fcx_features", "fcx_mlp_forward",
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
-    "fcx_sphere_geometry", "fcx_advance",
+    "fcx_sphere_geometry", "fcx_advance", "fcx_regrid",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -117,6 +117,7 @@ def lib():
         L.fcx_dilate_tags.argtypes = [vp, vp, i32, vp, vp]
         L.fcx_sphere_geometry.argtypes = [vp, vp, vp]
         L.fcx_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+        L.fcx_regrid.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp]
         _lib = L
     return _lib
 
@@ -369,6 +370,15 @@ class Context:
         _check(lib().fcx_sphere_geometry(self.h, _dev(out, n, torch.float64),
                                          _stream(stream)))
         return out.view(self.num_patches(), GEO_FRAMES, m + 4, m + 4)
+
+    def regrid(self, q, ghost, criterion, threshold, lmin, lmax, stream=None) -> int:
+        """Ghost fill, tags, and mesh change in one call; returns the new
+        patch count (then allocate the new state and call regrid_transfer
+        with q and ghost)."""
+        n = C.c_int64()
+        _check(lib().fcx_regrid(self.h, self._q(q), self._g(ghost), criterion, threshold,
+                                lmin, lmax, C.byref(n), _stream(stream)))
+        return n.value
 
     def regrid_apply(self, tags_host, lmin, lmax) -> int:
         t = np.ascontiguousarray(tags_host, dtype=np.int8)

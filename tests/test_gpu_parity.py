@@ -214,6 +214,32 @@ def test_regrid_transfer_matches_oracle():
     assert _rel(gpu.state(), want) <= 1e-15
 
 
+def test_one_call_regrid_equals_the_separate_calls():
+    """fcx_regrid (ghost fill, criterion tags, apply) gives the oracle's
+    tags-then-regrid forest, and the transfer on its ghost fill the oracle's
+    state."""
+    import torch
+    say("[regrid one call]")
+    trees, pl, lv, cfg, q = _setup("walled", fcx.FCX_SHALLOW, 16, 7)
+    gpu = Gpu(cfg, trees, lv)
+    gpu.set_state(q)
+    mesh = O.Mesh(trees, lv, 16)
+    par = oracle_params(cfg)
+    f = O.framed(q, 16)
+    O.ghost_fill(mesh, par, f)
+    tg = O.tags(mesh, par, f, 1, 0.5, 1, 6)
+    assert (tg != 0).any()
+    q_old, g_old = gpu.q, gpu.ghost
+    n = gpu.ctx.regrid(q_old, g_old, 1, 0.5, 1, 6)
+    lv2 = O.regrid(mesh, tg, 1, 6)
+    assert n == len(lv2) and np.array_equal(gpu.ctx.leaves(), lv2)
+    gpu._alloc()
+    gpu.ctx.regrid_transfer(q_old, g_old, gpu.q)
+    torch.cuda.synchronize()
+    want = O.interior(O.transfer(mesh, O.Mesh(trees, lv2, 16), par, f), 16)
+    assert _rel(gpu.state(), want) <= 1e-15
+
+
 def test_conservation_sums_match_oracle():
     say("[sums]")
     for domain, phys, m in CASES:
