@@ -83,7 +83,9 @@ def stored_traffic(name):
 
 
 class Workload:
-    """Adaptive dam break driven entirely through the library."""
+    """Adaptive dam break driven entirely through the library: the timed
+    steps run in the library's own run loop (fcx_run) on two state buffers
+    sized for the finest forest the run can reach."""
 
     LMIN, LMAX, M, THR, REGRID = 3, 6, 16, 0.1, 4
 
@@ -102,24 +104,31 @@ class Workload:
         fn = lambda x, y: I.dam_break(x, y)
         if self.uniform:
             leaves = fcx.sfc_sort(I.uniform_leaves(1, uniform_level))
-            self.ctx.upload_forest(leaves)
         else:
             leaves = fcx.sfc_sort(I.uniform_leaves(1, self.LMIN))
             # initial mesh: tag the initial data, refine, re-evaluate, until
             # nothing changes
             for _ in range(2 * (self.LMAX - self.LMIN) + 2):
                 self.ctx.upload_forest(leaves)
-                self._alloc()
-                self._set(I.state_from(leaves, self.M, fn, self.pl))
-                tags = self._tags()
-                self.ctx.regrid_apply(tags, self.LMIN, self.LMAX)
+                q = self._tensor(I.state_from(leaves, self.M, fn, self.pl))
+                g = torch.empty(self.ctx.ghost_elems(), dtype=self.dtype, device="cuda")
+                self.ctx.regrid(q, g, 1, self.THR, self.LMIN, self.LMAX)
                 new = self.ctx.leaves()
                 if len(new) == len(leaves) and (new == leaves).all():
                     break
                 leaves = new
-            self.ctx.upload_forest(leaves)
-        self._alloc()
-        self._set(I.state_from(leaves, self.M, fn, self.pl))
+        self.ctx.upload_forest(leaves)
+        # capacity: every patch at the finest level the run can reach
+        finest = uniform_level if self.uniform else self.LMAX
+        pmax = 1 << (2 * finest)
+        meqn = self.ctx.meqn
+        cap = pmax * meqn * self.M * self.M
+        self.buf = [torch.empty(cap, dtype=self.dtype, device="cuda") for _ in range(2)]
+        self.ghost = torch.empty(pmax * meqn * (8 * self.M + 16), dtype=self.dtype,
+                                 device="cuda")
+        q0 = self._tensor(I.state_from(leaves, self.M, fn, self.pl))
+        self.buf[0][:q0.numel()].copy_(q0)
+        self.cur = 0
         dev = "cuda"
         hmin = 1.0 / (self.M << int(leaves["level"].max()))
         # start at half the target Courant number: the first steps of a dam
@@ -129,58 +138,25 @@ class Workload:
         self.numax = torch.zeros(1, dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.n = 0
-        self.cells = []
 
-    def _alloc(self):
-        t = self.torch
-        # every buffer is fully written before it is read
-        self.q = t.empty(self.ctx.state_elems(), dtype=self.dtype, device="cuda")
-        self.qn = t.empty_like(self.q)
-        self.ghost = t.empty(self.ctx.ghost_elems(), dtype=self.dtype, device="cuda")
-        self.tagbuf = t.empty(self.ctx.num_patches(), dtype=t.int8, device="cuda")
+    def _tensor(self, q):
+        return self.torch.from_numpy(q.ravel()).to(self.dtype).cuda()
 
-    def _set(self, q):
-        self.q.copy_(self.torch.from_numpy(q.ravel()).to(self.dtype))
+    def state(self):
+        """(current state, the other buffer) as tensors of the forest's size."""
+        n = self.ctx.state_elems()
+        return self.buf[self.cur][:n], self.buf[1 - self.cur][:n]
 
-    def _tags(self):
-        self.ctx.ghost_fill(self.q, self.ghost)
-        self.ctx.regrid_tags(self.q, self.ghost, 1, self.THR, self.LMIN, self.LMAX,
-                             self.tagbuf)
-        return self.tagbuf.cpu().numpy()
-
-    def regrid(self):
-        # ghost fill, tags and mesh change in one call; the ghost buffer then
-        # holds the fill of q that the transfer needs
-        q_old, g_old = self.q, self.ghost
-        self.ctx.regrid(q_old, g_old, 1, self.THR, self.LMIN, self.LMAX)
-        self._alloc()
-        self.ctx.regrid_transfer(q_old, g_old, self.q)
-
-    def step(self, ev=None):
-        if not self.uniform and self.n > 0 and self.n % self.REGRID == 0:
-            self.regrid()
-        if self.fused and ev is None:
-            # fused step, reflux and next dt in one library call
-            self.ctx.advance(self.q, self.qn, self.dt, self.numax, self.status)
-            self.q, self.qn = self.qn, self.q
-            self.cells.append(self.ctx.num_patches() * self.M * self.M)
-            self.n += 1
-            return
-        if not self.fused:
-            self.ctx.ghost_fill(self.q, self.ghost)
-        if ev is not None:
-            ev[0].record()
-        if self.fused:
-            self.ctx.fused_step(self.q, self.qn, self.dt, self.numax)
-        else:
-            self.ctx.patch_step(self.q, self.ghost, self.qn, self.dt, self.numax)
-        if ev is not None:
-            ev[1].record()
-        self.ctx.reflux(self.q, self.qn, self.dt)
-        self.ctx.next_dt(self.numax, self.dt, self.status)
-        self.q, self.qn = self.qn, self.q
-        self.cells.append(self.ctx.num_patches() * self.M * self.M)
-        self.n += 1
+    def advance(self, steps):
+        """`steps` steps in the library's run loop; returns cell updates."""
+        which, cells = self.ctx.run(
+            self.buf[self.cur], self.buf[1 - self.cur], self.ghost, steps, self.n,
+            0 if self.uniform else self.REGRID, 1, self.THR, self.LMIN, self.LMAX,
+            self.dt, self.numax, self.status, fused=self.fused)
+        if which == 1:
+            self.cur = 1 - self.cur
+        self.n += steps
+        return cells
 
 
 TUNE = {"tile": 0, "threads": 0}
@@ -189,32 +165,31 @@ TUNE = {"tile": 0, "threads": 0}
 def run(precision, fused, steps, warmup, uniform_level=None):
     import torch
     w = Workload(precision, fused, uniform_level, TUNE["tile"], TUNE["threads"])
-    for _ in range(warmup):
-        w.step()
+    if warmup:
+        w.advance(warmup)
     torch.cuda.synchronize()
     w.status.zero_()                      # CFL flags of the timed steps only
-    w.cells = []
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for k in range(steps):
-        w.step()
+    cells = float(w.advance(steps))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    cells = float(sum(w.cells))
     status = int(w.status.item())
     # the step kernel alone: nk back-to-back launches on the current mesh
     # between two HIP events on the launch stream (the launch is idempotent:
     # it reads q and writes q_new)
     nk = 20
+    q, qn = w.state()
+    g = w.ghost[:w.ctx.ghost_elems()]
     if not w.fused:
-        w.ctx.ghost_fill(w.q, w.ghost)
+        w.ctx.ghost_fill(q, g)
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(nk):
         if w.fused:
-            w.ctx.fused_step(w.q, w.qn, w.dt, w.numax)
+            w.ctx.fused_step(q, qn, w.dt, w.numax)
         else:
-            w.ctx.patch_step(w.q, w.ghost, w.qn, w.dt, w.numax)
+            w.ctx.patch_step(q, g, qn, w.dt, w.numax)
     b.record()
     torch.cuda.synchronize()
     w.numax.zero_()

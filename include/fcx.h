@@ -182,6 +182,24 @@ int fcx_next_dt(fcx_ctx *ctx, double *nu_max, double *dt, int32_t *status,
 int fcx_advance(fcx_ctx *ctx, const void *q, void *q_new, double *dt,
                 double *nu_max, int32_t *status, void *stream);
 
+/* A run of `steps` whole steps on two caller buffers of `cap` elements
+ * each (enough for the finest forest the run can reach): step n = step0 +
+ * k first regrids when regrid_every > 0, n > 0 and n % regrid_every == 0
+ * (fcx_regrid with the given criterion, then fcx_regrid_transfer into the
+ * other buffer, using `ghost` of ghost_cap elements), then advances into
+ * the other buffer: fcx_advance if `fused`, else fcx_ghost_fill,
+ * fcx_patch_step, fcx_reflux and fcx_next_dt.  The state starts in q0; *which
+ * receives the buffer (0 or 1) holding the final state, *cell_updates the
+ * number of interior cells advanced.  FCX_ENOMEM if a capacity is short
+ * (the state is then where the last completed step left it).  Planar
+ * forests only. */
+int fcx_run(fcx_ctx *ctx, int32_t fused, void *q0, void *q1, int64_t cap,
+            void *ghost, int64_t ghost_cap, int32_t steps, int32_t step0,
+            int32_t regrid_every, int32_t criterion, double threshold,
+            int32_t lmin, int32_t lmax, double *dt, double *nu_max,
+            int32_t *status, int32_t *which, int64_t *cell_updates,
+            void *stream);
+
 /* sums[k] = sum over interior cells of q_k * cell area, in FP64, reduced in
  * a fixed order (deterministic). */
 int fcx_conservation_sums(fcx_ctx *ctx, const void *q, double *sums,

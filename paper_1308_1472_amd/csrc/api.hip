@@ -1203,3 +1203,51 @@ int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double
   return fcx_regrid_apply(c, reinterpret_cast<const int8_t*>(c->tags_host.p), lmin, lmax,
                           n_new);
 }
+
+// ---- a run of many steps ----------------------------------------------------
+
+int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* ghost,
+            int64_t ghost_cap, int32_t steps, int32_t step0, int32_t regrid_every,
+            int32_t criterion,
+            double threshold, int32_t lmin, int32_t lmax, double* dt, double* nu_max,
+            int32_t* status, int32_t* which, int64_t* cell_updates, void* stream) {
+  if (!c || !q0 || !q1 || !ghost || !dt || !nu_max || !status || !which || !cell_updates ||
+      steps < 0 || step0 < 0 || regrid_every < 0 || q0 == q1)
+    return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no fused run on the sphere");
+  void* buf[2] = {q0, q1};
+  int cur = 0;
+  int64_t cells = 0;
+  const int64_t mm = int64_t(c->cfg.m) * c->cfg.m;
+  for (int32_t k = 0; k < steps; ++k) {
+    const int64_t n = int64_t(step0) + k;
+    if (regrid_every > 0 && n > 0 && n % regrid_every == 0) {
+      if (fcx_ghost_elems(c) > ghost_cap) return fail(FCX_ENOMEM, "ghost capacity exceeded");
+      int64_t pn = 0;
+      int rc = fcx_regrid(c, buf[cur], ghost, criterion, threshold, lmin, lmax, &pn, stream);
+      if (rc != FCX_OK) return rc;
+      if (fcx_state_elems(c) > cap) return fail(FCX_ENOMEM, "state capacity exceeded");
+      rc = fcx_regrid_transfer(c, buf[cur], ghost, buf[1 - cur], stream);
+      if (rc != FCX_OK) return rc;
+      cur = 1 - cur;
+    }
+    if (fcx_state_elems(c) > cap) return fail(FCX_ENOMEM, "state capacity exceeded");
+    int rc;
+    if (fused) {
+      rc = fcx_advance(c, buf[cur], buf[1 - cur], dt, nu_max, status, stream);
+    } else {
+      if (fcx_ghost_elems(c) > ghost_cap) return fail(FCX_ENOMEM, "ghost capacity exceeded");
+      rc = fcx_ghost_fill(c, buf[cur], ghost, stream);
+      if (rc == FCX_OK) rc = fcx_patch_step(c, buf[cur], ghost, buf[1 - cur], dt, nu_max, stream);
+      if (rc == FCX_OK) rc = fcx_reflux(c, buf[cur], buf[1 - cur], dt, stream);
+      if (rc == FCX_OK) rc = fcx_next_dt(c, nu_max, dt, status, stream);
+    }
+    if (rc != FCX_OK) return rc;
+    cur = 1 - cur;
+    cells += c->cur.P * mm;
+  }
+  *which = cur;
+  *cell_updates = cells;
+  return FCX_OK;
+}

@@ -38,7 +38,7 @@ EXPORTS = [
     "fcx_batch_set_tuning", "fcx_batch_step", "fcx_batch_capture",
     "fcx_batch_replay", "fcx_batch_sums", "fcx_features", "fcx_mlp_forward",
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
-    "fcx_sphere_geometry", "fcx_advance", "fcx_regrid",
+    "fcx_sphere_geometry", "fcx_advance", "fcx_regrid", "fcx_run",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -118,6 +118,8 @@ def lib():
         L.fcx_sphere_geometry.argtypes = [vp, vp, vp]
         L.fcx_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.fcx_regrid.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp]
+        L.fcx_run.argtypes = [vp, i32, vp, vp, i64, vp, i64, i32, i32, i32, i32, dp, i32,
+                              i32, vp, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -379,6 +381,27 @@ class Context:
         _check(lib().fcx_regrid(self.h, self._q(q), self._g(ghost), criterion, threshold,
                                 lmin, lmax, C.byref(n), _stream(stream)))
         return n.value
+
+    def run(self, q0, q1, ghost, steps, step0, regrid_every, criterion, threshold,
+            lmin, lmax, dt, numax, status, fused=True, stream=None):
+        """`steps` whole steps with periodic regrids on two capacity buffers;
+        returns (index of the buffer with the result, cell updates)."""
+        import torch
+        dtype = torch.float64 if self.cfg.precision == 64 else torch.float32
+        for t in (q0, q1, ghost):
+            if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype
+                    and t.is_contiguous()):
+                raise ValueError("expected contiguous state tensors of the context's type")
+        which = C.c_int32()
+        cells = C.c_int64()
+        _check(lib().fcx_run(self.h, int(fused), C.c_void_p(q0.data_ptr()),
+                             C.c_void_p(q1.data_ptr()),
+                             min(q0.numel(), q1.numel()), C.c_void_p(ghost.data_ptr()),
+                             ghost.numel(), steps, step0, regrid_every, criterion,
+                             threshold, lmin, lmax, self._d(dt), self._d(numax),
+                             self._d(status, 1, torch.int32), C.byref(which),
+                             C.byref(cells), _stream(stream)))
+        return which.value, cells.value
 
     def regrid_apply(self, tags_host, lmin, lmax) -> int:
         t = np.ascontiguousarray(tags_host, dtype=np.int8)

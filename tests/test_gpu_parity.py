@@ -240,6 +240,66 @@ def test_one_call_regrid_equals_the_separate_calls():
     assert _rel(gpu.state(), want) <= 1e-15
 
 
+@pytest.mark.parametrize("fused", [True, False])
+def test_native_run_loop_equals_single_calls(fused):
+    """fcx_run (steps with a regrid every 3) gives bit for bit the state,
+    forest, dt and flags of the same sequence of single calls."""
+    import torch
+    say(f"[run loop] fused={fused}")
+    trees, pl = I.walled_square()
+    m, lmin, lmax = 8, 2, 4
+    lv = fcx.balance(trees, I.random_leaves(4, 1, 2, 4, 10))
+    q0 = I.state_from(lv, m, lambda x, y: I.dam_break(x, y, 0.45, 0.5, 0.2), pl)
+    cfg = fcx.config(m, 64, fcx.FCX_SHALLOW)
+    dt0 = 0.4 / (m << lmax) / 1.5
+    steps = 10
+
+    def fresh():
+        ctx = fcx.Context(cfg, trees)
+        ctx.upload_forest(lv)
+        dt = torch.full((1,), dt0, dtype=torch.float64, device="cuda")
+        return ctx, dt, torch.zeros_like(dt), torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    # single calls
+    ctx, dt, nu, st = fresh()
+    q = torch.from_numpy(q0.ravel().copy()).cuda()
+    for n in range(steps):
+        if n > 0 and n % 3 == 0:
+            g = torch.empty(ctx.ghost_elems(), dtype=torch.float64, device="cuda")
+            ctx.regrid(q, g, 1, 0.3, lmin, lmax)
+            q2 = torch.empty(ctx.state_elems(), dtype=torch.float64, device="cuda")
+            ctx.regrid_transfer(q, g, q2)
+            q = q2
+        qn = torch.empty_like(q)
+        if fused:
+            ctx.advance(q, qn, dt, nu, st)
+        else:
+            g = torch.empty(ctx.ghost_elems(), dtype=torch.float64, device="cuda")
+            ctx.ghost_fill(q, g)
+            ctx.patch_step(q, g, qn, dt, nu)
+            ctx.reflux(q, qn, dt)
+            ctx.next_dt(nu, dt, st)
+        q = qn
+    want, want_lv, want_dt = q.cpu().numpy(), ctx.leaves(), dt.item()
+    # the run loop
+    ctx, dt, nu, st = fresh()
+    cap = (1 << (2 * lmax)) * 3 * m * m
+    bufs = [torch.empty(cap, dtype=torch.float64, device="cuda") for _ in range(2)]
+    bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
+    ghost = torch.empty((1 << (2 * lmax)) * 3 * (8 * m + 16), dtype=torch.float64,
+                        device="cuda")
+    which, cells = ctx.run(bufs[0], bufs[1], ghost, steps, 0, 3, 1, 0.3, lmin, lmax,
+                           dt, nu, st, fused=fused)
+    got = bufs[which][:ctx.state_elems()].cpu().numpy()
+    assert np.array_equal(ctx.leaves(), want_lv)
+    assert np.array_equal(got, want) and dt.item() == want_dt
+    assert cells > 0
+    # a capacity that is too small is refused
+    with pytest.raises(fcx.FcxError):
+        ctx.run(bufs[which][:10], bufs[1 - which], ghost, 1, steps, 0, 1, 0.3, lmin, lmax,
+                dt, nu, st, fused=fused)
+
+
 def test_conservation_sums_match_oracle():
     say("[sums]")
     for domain, phys, m in CASES:
