@@ -242,7 +242,7 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   if ((tile != 8 && tile != 16) || tile > cfg->m)
     return fail(FCX_EINVAL, "tile must be 8 or 16 and at most m");
   // measured defaults: FP64 16 x 16 tiles run best with two threads per
-  // cell (more resident waves at its register count), the rest with one
+  // cell (more resident waves at their register count), the rest with one
   const int threads = cfg->threads ? cfg->threads
                                    : (tile == 16 ? (cfg->precision == 64 ? 512 : 256) : 64);
   if (threads != tile * tile && threads != 2 * tile * tile)

@@ -233,9 +233,14 @@ __device__ __forceinline__ void ghost_cell(int m, int g, int& i, int& j) {
 }
 
 __device__ __forceinline__ void atomic_max_pos(double* addr, double v) {
-  // non-negative doubles order like their bit patterns
-  atomicMax(reinterpret_cast<unsigned long long*>(addr),
-            static_cast<unsigned long long>(__double_as_longlong(v)));
+  // Many workgroups update one word: read it first and skip the atomic when
+  // it already holds at least v (a stale read is never larger than the
+  // true value, so no update is lost).  Non-negative doubles order like
+  // their bit patterns.
+  unsigned long long* w = reinterpret_cast<unsigned long long*>(addr);
+  const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(v));
+  if (b <= __atomic_load_n(w, __ATOMIC_RELAXED)) return;
+  atomicMax(w, b);
 }
 
 }  // namespace fcx

@@ -108,7 +108,7 @@ __device__ __forceinline__ void simple_halo(const R* __restrict__ q,
 template <typename R, int PHYS, int T, int NT>
 struct TileLds {
   static constexpr int MEQN = PhysTraits<PHYS>::MEQN;
-  static constexpr int WD = PHYS == FCX_ADVECTION ? 1 : 6;   // wave data per edge
+  static constexpr int WD = PHYS == FCX_ADVECTION ? 1 : 7;   // wave data per edge
   static constexpr int NPR = PHYS == FCX_ADVECTION ? 1 : 3;  // primitives per cell
   static constexpr int F = T + 4, NR = T + 2, NE = T + 3;
   R qs[MEQN][F * F];
@@ -152,6 +152,9 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
   // strip (bottom, top, left, right), so that the lanes of a wavefront
   // mostly take the same ghost-cell path
   const bool simple = (rp.flags & kSimpleHalo) != 0;
+  // face terms are kept only for patches on a coarse-fine face
+  const int slot = A.phislot[p];
+  const bool faces = slot >= 0;
   const int i0 = tx * T, j0 = ty * T;
   auto stage = [&](int c, const R (&v)[MEQN]) {
 #pragma unroll
@@ -225,7 +228,9 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
   for (int c = 0; c < CPT; ++c)
 #pragma unroll
     for (int k = 0; k < MEQN; ++k) dq[c][k] = phx[c][k] = phy[c][k] = R(0);
-  double numax = 0.0;
+  // largest |speed| over interior edges; the Courant number is formed once
+  // at the end (monotone rounding: the same as the largest product)
+  R smax = R(0);
   const int lim = A.ph.limiter, trans = A.ph.transverse;
   const R half_dtdx = R(0.5) * dtdx;
   const R ghalf = R(0.5 * A.ph.g);
@@ -255,23 +260,24 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
         wb[0][bidx(r, e)] = qs[0][cr] - qs[0][cl];
       } else {
         const R sl = pr[0][cl], sr = pr[0][cr];
-        R a1 = 0, a2 = 0, a3 = 0, u = 0, v = 0, c = 1;
+        R a1 = 0, a2 = 0, a3 = 0, u = 0, v = 0, c = 1, i2c_ = R(0.5);
         if (sl > R(0) && sr > R(0)) {
           const R inv = rcp_(sl + sr);
           u = (sl * pr[mu][cl] + sr * pr[mu][cr]) * inv;
           v = (sl * pr[mv][cl] + sr * pr[mv][cr]) * inv;
           const R hl = qs[0][cl], hr = qs[0][cr];
           c = sqrt_(ghalf * (hl + hr));
-          const R i2c = R(0.5) * rcp_(c);
+          i2c_ = R(0.5) * rcp_(c);
           const R d0 = hr - hl, d1 = qs[mu][cr] - qs[mu][cl];
           const R d2 = qs[mv][cr] - qs[mv][cl];
-          a1 = ((u + c) * d0 - d1) * i2c;
+          a1 = ((u + c) * d0 - d1) * i2c_;
           a2 = d2 - v * d0;
-          a3 = (d1 - (u - c) * d0) * i2c;
+          a3 = (d1 - (u - c) * d0) * i2c_;
         }
         const int b = bidx(r, e);
         wb[0][b] = a1; wb[1][b] = a2; wb[2][b] = a3;
         wb[3][b] = u; wb[4][b] = v; wb[5][b] = c;
+        wb[6][b] = i2c_;
       }
     }
     __syncthreads();
@@ -291,7 +297,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
         am[0] = fmin(an, R(0)) * w;
         ap[0] = fmax(an, R(0)) * w;
         cq[0] = R(0);
-        if (inner) numax = fmax(numax, dtdx_d * fabs(double(an)));
+        if (inner) smax = fmax(smax, fabs(an));
         if (w != R(0)) {
           const R wu = wb[0][bidx(r, an > R(0) ? e - 1 : e + 1)];
           const R th = (wu * w) * rcp_(w * w);
@@ -299,45 +305,44 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
           cq[0] = s * (R(1) - dtdx * s) * limiter_phi(lim, th) * w;
         }
       } else {
+        // waves in (h, normal, tangential) order: a1 (1, u - c, v),
+        // (0, 0, a2), a3 (1, u + c, v); speeds u - c, u, u + c
         const int b = bidx(r, e);
         const R u = wb[3][b], v = wb[4][b], c = wb[5][b];
-        const R al[3] = {wb[0][b], wb[1][b], wb[2][b]};
-        const R s[3] = {u - c, u, u + c};
-        // waves in (h, normal, tangential) order
-        const R W[3][3] = {{al[0], al[0] * (u - c), al[0] * v},
-                           {R(0), R(0), al[1]},
-                           {al[2], al[2] * (u + c), al[2] * v}};
-        R amh[3] = {0, 0, 0}, aph[3] = {0, 0, 0}, cqh[3] = {0, 0, 0};
+        const R a1 = wb[0][b], a2 = wb[1][b], a3 = wb[2][b];
+        const R s1 = u - c, s3 = u + c;
+        const R b1m = fmin(s1, R(0)) * a1, b2m = fmin(u, R(0)) * a2, b3m = fmin(s3, R(0)) * a3;
+        const R b1p = fmax(s1, R(0)) * a1, b2p = fmax(u, R(0)) * a2, b3p = fmax(s3, R(0)) * a3;
+        const R m0 = b1m + b3m, p0 = b1p + b3p;
+        R amh[3] = {m0, b1m * s1 + b3m * s3, m0 * v + b2m};
+        R aph[3] = {p0, b1p * s1 + b3p * s3, p0 * v + b2p};
+        // limited corrections: g_w = |s|(1 - dtdx |s|) phi(theta) a_w
+        R g[3] = {R(0), R(0), R(0)};
+        const R nv = R(1) + v * v;
+        const R sp[3] = {s1, u, s3};
 #pragma unroll
         for (int w = 0; w < 3; ++w) {
-          const R smn = fmin(s[w], R(0)), smx = fmax(s[w], R(0));
-#pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            amh[k] += smn * W[w][k];
-            aph[k] += smx * W[w][k];
-          }
-          const R wn2 = W[w][0] * W[w][0] + W[w][1] * W[w][1] + W[w][2] * W[w][2];
+          const R aw = w == 0 ? a1 : (w == 1 ? a2 : a3);
+          const R r2 = w == 1 ? R(1) : sp[w] * sp[w] + nv;     // |r_w|^2
+          const R wn2 = (aw * aw) * r2;
           if (wn2 != R(0)) {
-            const int bu = bidx(r, s[w] > R(0) ? e - 1 : e + 1);
+            const int bu = bidx(r, sp[w] > R(0) ? e - 1 : e + 1);
             R dot;
             if (w == 1) {
-              dot = wb[1][bu] * al[1];
+              dot = wb[1][bu] * a2;
             } else {
               const R au = wb[w][bu], uu = wb[3][bu], vu = wb[4][bu], cu = wb[5][bu];
               const R nu_ = w == 0 ? uu - cu : uu + cu;
-              dot = au * (W[w][0] + nu_ * W[w][1] + vu * W[w][2]);
+              dot = (au * aw) * (R(1) + nu_ * sp[w] + vu * v);
             }
             const R phi = limiter_phi(lim, dot * rcp_(wn2));
-            const R as = fabs(s[w]);
-            const R f = as * (R(1) - dtdx * as) * phi;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) cqh[k] += f * W[w][k];
+            const R as = fabs(sp[w]);
+            g[w] = as * (R(1) - dtdx * as) * phi * aw;
           }
         }
-        if (inner) {
-          const double sm = fmax(fabs(double(s[0])), fabs(double(s[2])));
-          numax = fmax(numax, dtdx_d * sm);
-        }
+        const R g13 = g[0] + g[2];
+        R cqh[3] = {g13, g[0] * s1 + g[2] * s3, g13 * v + g[1]};
+        if (inner) smax = fmax(smax, fmax(fabs(s1), fabs(s3)));
         am[0] = amh[0]; am[mu] = amh[1]; am[mv] = amh[2];
         ap[0] = aph[0]; ap[mu] = aph[1]; ap[mv] = aph[2];
         cq[0] = cqh[0]; cq[mu] = cqh[1]; cq[mv] = cqh[2];
@@ -363,7 +368,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
         } else {
           const int b = bidx(r, e);
           const R u = wb[3][b], v = wb[4][b], c = wb[5][b];
-          const R i2c = R(0.5) * rcp_(c);
+          const R i2c = wb[6][b];
           const R lmn[3] = {-half_dtdx * fmin(v - c, R(0)), -half_dtdx * fmin(v, R(0)),
                             -half_dtdx * fmin(v + c, R(0))};
           const R lmx[3] = {-half_dtdx * fmax(v - c, R(0)), -half_dtdx * fmax(v, R(0)),
@@ -397,7 +402,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
           if (inner) fn[k][nidx(r, e - 1)] = am[k] + R(0.5) * cq[k];
         }
       }
-      if (inner && (e == 1 || e == T + 1)) {
+      if (faces && inner && (e == 1 || e == T + 1)) {
 #pragma unroll
         for (int k = 0; k < MEQN; ++k)
           fb[e == 1 ? 0 : 1][k][r - 1] = e == 1 ? ap[k] - R(0.5) * cq[k]
@@ -444,20 +449,21 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
         const R gup = tup[k][uidx(r, n)] + tdn[k][uidx(r + 1, n)];
         const R gdn = tup[k][uidx(r - 1, n)] + tdn[k][uidx(r, n)];
         dq[c][k] -= dtdx * (fn[k][nidx(r, n)] + (gup - gdn));
-        // face terms through the patch faces (for the reflux)
-        R& pnrm = d == 0 ? phx[c][k] : phy[c][k];
-        R& ptrn = d == 0 ? phy[c][k] : phx[c][k];
-        if (pn == 1) pnrm += fb[0][k][r - 1];
-        if (pn == m) pnrm += fb[1][k][r - 1];
-        if (prr == 1) ptrn -= gdn;
-        if (prr == m) ptrn += gup;
+        if (faces) {
+          // face terms through the patch faces (for the reflux)
+          R& pnrm = d == 0 ? phx[c][k] : phy[c][k];
+          R& ptrn = d == 0 ? phy[c][k] : phx[c][k];
+          if (pn == 1) pnrm += fb[0][k][r - 1];
+          if (pn == m) pnrm += fb[1][k][r - 1];
+          if (prr == 1) ptrn -= gdn;
+          if (prr == m) ptrn += gup;
+        }
       }
     }
     __syncthreads();
   }
 
   // ---- write q_new and face terms -----------------------------------
-  const int slot = A.phislot[p];
 #pragma unroll
   for (int c = 0; c < CPT; ++c) {
     const int cell = tid + c * NT;
@@ -468,7 +474,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
 #pragma unroll
     for (int k = 0; k < MEQN; ++k)
       A.qn[o + (uint32_t(k) << (2 * lm))] = qs[k][(cj + 1) * F + (ci + 1)] + dq[c][k];
-    if (slot >= 0) {
+    if (faces) {
       R* ph = A.phi + size_t(slot) * 4 * m * MEQN;
       const R dxr = R(dxd);
 #pragma unroll
@@ -482,6 +488,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
   }
 
   // ---- CFL number: wavefront max, then one atomic per workgroup -----
+  double numax = dtdx_d * double(smax);
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) numax = fmax(numax, __shfl_xor(numax, off));
   if ((tid & 63) == 0) red[tid >> 6] = numax;
