@@ -177,8 +177,9 @@ int fcx_next_dt(fcx_ctx *ctx, double *nu_max, double *dt, int32_t *status,
                 void *stream);
 
 /* One whole step of the fused path in one call: fcx_fused_step (q ->
- * q_new), fcx_reflux, fcx_next_dt (dt is updated for the next step, nu_max
- * cleared, status flags raised).  Planar forests only. */
+ * q_new), then fcx_reflux and fcx_next_dt in one launch (dt is updated for
+ * the next step, nu_max cleared, status flags raised); same result as the
+ * three calls.  Planar forests only. */
 int fcx_advance(fcx_ctx *ctx, const void *q, void *q_new, double *dt,
                 double *nu_max, int32_t *status, void *stream);
 

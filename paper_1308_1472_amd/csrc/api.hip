@@ -110,6 +110,7 @@ struct DevForest {
   int32_t* phislot = nullptr;
   int32_t* family = nullptr;
   RefluxItem* reflux = nullptr;
+  int32_t* links = nullptr;          // per reflux item: partners at its two ends
   int32_t* first = nullptr;          // {0, P} for the sum reduction
   int32_t* xkind = nullptr;          // transfer plan from the previous forest
   int32_t* xsrc = nullptr;
@@ -130,6 +131,7 @@ struct fcx_ctx {
   DevBuf<uint8_t> phi;             // face terms of the last patch step
   DevBuf<double> partial;
   DevBuf<int32_t> err;
+  DevBuf<uint32_t> ticket;         // last-workgroup ticket of the reflux
   HostBuf staging;
   DevBuf<uint8_t> sscratch;        // sphere step: per-workgroup edge data
   int cus = 256;
@@ -274,11 +276,12 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
       c->cus = prop.multiProcessorCount;
   }
   c->trees = t;
-  if (c->err.ensure(1) != hipSuccess) {
+  if (c->err.ensure(1) != hipSuccess || c->ticket.ensure(1) != hipSuccess) {
     delete c;
     return fail(FCX_ENOMEM, "hipMalloc failed");
   }
-  if (hipMemset(c->err.p, 0, sizeof(int32_t)) != hipSuccess) {
+  if (hipMemset(c->err.p, 0, sizeof(int32_t)) != hipSuccess ||
+      hipMemset(c->ticket.p, 0, sizeof(uint32_t)) != hipSuccess) {
     delete c;
     return fail(FCX_EHIP, "hipMemset failed");
   }
@@ -305,20 +308,42 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
                : build_plan(f, c->cfg.m, plan, err, sync);
   if (rc != FCX_OK) return fail(rc, err);
   const size_t P = f.leaves.size();
-  // reflux items: xi faces first, then eta faces
-  std::vector<RefluxItem> items;
-  items.reserve(plan.reflux.size());
-  for (const auto& it : plan.reflux) if (it.face < 2) items.push_back(it);
-  dev.n_reflux_x = int32_t(items.size());
-  for (const auto& it : plan.reflux) if (it.face >= 2) items.push_back(it);
-  dev.n_reflux_y = int32_t(items.size()) - dev.n_reflux_x;
-  size_t off[8];
+  // reflux items: xi faces first, then eta faces; each item links the items
+  // of the other direction on the same coarse patch whose faces meet its own
+  // at its low and high end (the corner cell both correct)
+  const size_t NI = plan.reflux.size();
+  std::vector<RefluxItem> items(NI);
+  std::vector<int32_t> links(2 * NI);
+  {
+    int32_t nx = 0;
+    for (const auto& it : plan.reflux) nx += it.face < 2;
+    dev.n_reflux_x = nx;
+    dev.n_reflux_y = int32_t(NI) - nx;
+    int32_t ix = 0, iy = nx;
+    for (size_t p = 0; p < P; ++p) {
+      const int32_t b = plan.item_first[p], e = plan.item_first[p + 1];
+      int32_t at_face[4] = {-1, -1, -1, -1}, pos[4];
+      for (int32_t t = b; t < e; ++t) {
+        const int f = plan.reflux[t].face;
+        pos[t - b] = f < 2 ? ix++ : iy++;
+        at_face[f] = pos[t - b];
+      }
+      for (int32_t t = b; t < e; ++t) {
+        const int32_t k = pos[t - b];
+        const int f = plan.reflux[t].face;
+        items[k] = plan.reflux[t];
+        links[2 * k] = at_face[f < 2 ? 2 : 0];
+        links[2 * k + 1] = at_face[f < 2 ? 3 : 1];
+      }
+    }
+  }
+  size_t off[9];
   size_t at = 0;
-  const size_t sz[7] = {P * sizeof(PatchRec), P * 4, P * 4,
-                        items.size() * sizeof(RefluxItem), 2 * 4,
-                        kind ? P * 4 : 0, src ? P * 4 : 0};
-  for (int k = 0; k < 7; ++k) { off[k] = at; at += align256(sz[k]); }
-  off[7] = at;
+  const size_t sz[8] = {P * sizeof(PatchRec), P * 4, P * 4,
+                        NI * sizeof(RefluxItem), 2 * 4,
+                        kind ? P * 4 : 0, src ? P * 4 : 0, NI * 2 * 4};
+  for (int k = 0; k < 8; ++k) { off[k] = at; at += align256(sz[k]); }
+  off[8] = at;
   HIPCHK(c->staging.ensure(at));
   uint8_t* h = c->staging.p;
   std::memcpy(h + off[0], plan.recs.data(), sz[0]);
@@ -329,6 +354,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   std::memcpy(h + off[4], first, sz[4]);
   if (kind) std::memcpy(h + off[5], kind->data(), sz[5]);
   if (src) std::memcpy(h + off[6], src->data(), sz[6]);
+  if (sz[7]) std::memcpy(h + off[7], links.data(), sz[7]);
   HIPCHK(dev.blob.ensure(at));
   HIPCHK(hipMemcpy(dev.blob.p, h, at, hipMemcpyHostToDevice));
   uint8_t* d = dev.blob.p;
@@ -339,6 +365,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   dev.first = reinterpret_cast<int32_t*>(d + off[4]);
   dev.xkind = kind ? reinterpret_cast<int32_t*>(d + off[5]) : nullptr;
   dev.xsrc = src ? reinterpret_cast<int32_t*>(d + off[6]) : nullptr;
+  dev.links = reinterpret_cast<int32_t*>(d + off[7]);
   dev.nslots = plan.nslots;
   dev.P = int64_t(P);
   c->plan = std::move(plan);
@@ -535,22 +562,22 @@ int fcx_fused_step(fcx_ctx* c, const void* q, void* qn, const double* dt,
   return step_dispatch<true>(c, q, nullptr, qn, dt, numax, stream);
 }
 
-template <typename R, int PHYS>
+// All reflux items in one launch; with NEXT the launch also takes the CFL
+// check and next dt (then it runs even without items).
+template <typename R, int PHYS, bool NEXT>
 static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
-                         hipStream_t s) {
+                         hipStream_t s, NextDtArgs nd = {}) {
   const int m = c->cfg.m;
-  for (int axis = 0; axis < 2; ++axis) {
-    const int32_t n = axis == 0 ? c->cur.n_reflux_x : c->cur.n_reflux_y;
-    if (n == 0) continue;
-    const RefluxItem* items = c->cur.reflux + (axis == 0 ? 0 : c->cur.n_reflux_x);
-    const int64_t tot = int64_t(n) * m;
-    hipLaunchKernelGGL((k_reflux<R, PHYS>), dim3(unsigned((tot + 255) / 256)),
-                       dim3(256), 0, s, static_cast<const R*>(q),
-                       static_cast<R*>(qn), items, n, c->cur.rec,
-                       c->cur.phislot, reinterpret_cast<const R*>(c->phi.p), dt,
-                       m, kphys(c), c->err.p);
-    HIPCHK(hipGetLastError());
-  }
+  const int32_t n = c->cur.n_reflux_x + c->cur.n_reflux_y;
+  if (n == 0 && !NEXT) return FCX_OK;
+  const int64_t tot = int64_t(n) * m;
+  const unsigned grid = unsigned(std::max<int64_t>(1, (tot + 255) / 256));
+  nd.ticket = c->ticket.p;
+  hipLaunchKernelGGL((k_reflux<R, PHYS, NEXT>), dim3(grid), dim3(256), 0, s,
+                     static_cast<const R*>(q), static_cast<R*>(qn), c->cur.reflux,
+                     c->cur.links, n, c->cur.rec, c->cur.phislot,
+                     reinterpret_cast<const R*>(c->phi.p), dt, m, kphys(c), c->err.p, nd);
+  HIPCHK(hipGetLastError());
   return FCX_OK;
 }
 
@@ -581,10 +608,10 @@ int fcx_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt, void* stre
     return dp ? launch_sphere_reflux<double>(c, q, qn, dt, s)
               : launch_sphere_reflux<float>(c, q, qn, dt, s);
   if (c->cfg.physics == FCX_ADVECTION)
-    return dp ? launch_reflux<double, FCX_ADVECTION>(c, q, qn, dt, s)
-              : launch_reflux<float, FCX_ADVECTION>(c, q, qn, dt, s);
-  return dp ? launch_reflux<double, FCX_SHALLOW>(c, q, qn, dt, s)
-            : launch_reflux<float, FCX_SHALLOW>(c, q, qn, dt, s);
+    return dp ? launch_reflux<double, FCX_ADVECTION, false>(c, q, qn, dt, s)
+              : launch_reflux<float, FCX_ADVECTION, false>(c, q, qn, dt, s);
+  return dp ? launch_reflux<double, FCX_SHALLOW, false>(c, q, qn, dt, s)
+            : launch_reflux<float, FCX_SHALLOW, false>(c, q, qn, dt, s);
 }
 
 int fcx_next_dt(fcx_ctx* c, double* numax, double* dt, int32_t* status, void* stream) {
@@ -1179,9 +1206,15 @@ int fcx_advance(fcx_ctx* c, const void* q, void* qn, double* dt, double* numax,
   if (!c || !status) return fail(FCX_EINVAL, "bad arguments");
   int rc = fcx_fused_step(c, q, qn, dt, numax, stream);
   if (rc != FCX_OK) return rc;
-  rc = fcx_reflux(c, q, qn, dt, stream);
-  if (rc != FCX_OK) return rc;
-  return fcx_next_dt(c, numax, dt, status, stream);
+  // reflux and next dt in one launch
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const NextDtArgs nd{numax, dt, status, nullptr, c->cfg.cfl_desired, c->cfg.cfl_max};
+  const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_ADVECTION)
+    return dp ? launch_reflux<double, FCX_ADVECTION, true>(c, q, qn, dt, s, nd)
+              : launch_reflux<float, FCX_ADVECTION, true>(c, q, qn, dt, s, nd);
+  return dp ? launch_reflux<double, FCX_SHALLOW, true>(c, q, qn, dt, s, nd)
+            : launch_reflux<float, FCX_SHALLOW, true>(c, q, qn, dt, s, nd);
 }
 
 // ---- tags and mesh change in one call ---------------------------------------

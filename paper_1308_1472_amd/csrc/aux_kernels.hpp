@@ -66,19 +66,16 @@ __device__ void fluct_sum(const KPhys& ph, int d, const R* ql, const R* qr,
   out[mv] = s1 * a1 * v + u * a2 + s3 * a3 * v;
 }
 
-// Reflux: one thread per (coarse-fine face item, coarse cell along it).
+// Reflux correction of one coarse cell (position tc along the face of item
+// it): the fine face terms minus the coarse one, subtracted from qn.
 template <typename R, int PHYS>
-__global__ void __launch_bounds__(256)
-k_reflux(const R* __restrict__ q, R* __restrict__ qn,
-         const RefluxItem* __restrict__ items, int32_t nitems,
-         const PatchRec* __restrict__ rec, const int32_t* __restrict__ phislot,
-         const R* __restrict__ phi, const double* dtp, int m, KPhys ph,
-         int32_t* err) {
+__device__ void reflux_cell(const R* __restrict__ q, R* __restrict__ qn,
+                            const RefluxItem& it, int tc,
+                            const PatchRec* __restrict__ rec,
+                            const int32_t* __restrict__ phislot,
+                            const R* __restrict__ phi, const double* dtp, int m,
+                            const KPhys& ph, int32_t* err) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t >= int64_t(nitems) * m) return;
-  const RefluxItem it = items[t / m];
-  const int tc = int(t % m) + 1;                 // coarse cell along the face
   const int f = it.face, d = f >> 1, hi = f & 1;
   const int C = it.coarse;
   const int ic = d == 0 ? (hi ? m : 1) : tc, jc = d == 0 ? tc : (hi ? m : 1);
@@ -113,23 +110,84 @@ k_reflux(const R* __restrict__ q, R* __restrict__ qn,
   }
 }
 
+// CFL check and next dt of forest f (status bits: 1 CFL exceeded,
+// 2 negative depth, 4 nesting error); clears numax and the error word.
+__device__ __forceinline__ void next_dt_one(double* numax, double* dt, int32_t* status,
+                                            int32_t* err, int f, double cfl_desired,
+                                            double cfl_max) {
+  const double nu = numax[f];
+  int32_t st = 0;
+  if (nu > cfl_max) st |= 1;
+  if (f == 0) {
+    const int32_t e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (e & kErrNegDepth) st |= 2;
+    if (e & kErrNested) st |= 4;
+    *err = 0;
+  }
+  status[f] |= st;
+  if (nu > 0.0) dt[f] = dt[f] * cfl_desired / nu;
+  numax[f] = 0.0;
+}
+
+struct NextDtArgs {
+  double* numax;
+  double* dt;
+  int32_t* status;
+  uint32_t* ticket;                          // zero between launches
+  double cfl_desired, cfl_max;
+};
+
+// Reflux: one thread per (coarse-fine face item, coarse cell along it), all
+// items in one launch.  Items of xi faces come first; a coarse corner cell
+// that lies on an xi item and an eta item gets both corrections, xi first,
+// from the xi item's thread (links[2i], links[2i+1]: for an xi item the eta
+// items at its low / high end, for an eta item the xi items there; -1 none),
+// so the result does not depend on the order the threads run in.  With NEXT,
+// the workgroup that finishes last also takes the CFL check and the next dt.
+template <typename R, int PHYS, bool NEXT>
+__global__ void __launch_bounds__(256)
+k_reflux(const R* __restrict__ q, R* __restrict__ qn,
+         const RefluxItem* __restrict__ items, const int32_t* __restrict__ links,
+         int32_t nitems, const PatchRec* __restrict__ rec,
+         const int32_t* __restrict__ phislot, const R* __restrict__ phi,
+         const double* dtp, int m, KPhys ph, int32_t* err, NextDtArgs nd) {
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t < int64_t(nitems) * m) {
+    const int32_t i = int32_t(t / m);
+    const int tc = int(t % m) + 1;
+    const RefluxItem it = items[i];
+    const int end = tc == 1 ? 0 : (tc == m ? 1 : -1);
+    const int32_t link = end >= 0 ? links[2 * i + end] : -1;
+    if (it.face < 2 || link < 0) {
+      reflux_cell<R, PHYS>(q, qn, it, tc, rec, phislot, phi, dtp, m, ph, err);
+      if (it.face < 2 && link >= 0)
+        reflux_cell<R, PHYS>(q, qn, items[link], it.face == 0 ? 1 : m, rec, phislot, phi,
+                             dtp, m, ph, err);
+    }
+  }
+  if (NEXT) {
+    __shared__ bool last;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      last = atomicAdd(nd.ticket, 1u) == gridDim.x - 1;
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+      __threadfence();
+      next_dt_one(nd.numax, nd.dt, nd.status, err, 0, nd.cfl_desired, nd.cfl_max);
+      *nd.ticket = 0;
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 __global__ void k_next_dt(double* numax, double* dt, int32_t* status,
                           int32_t* err, int32_t nforest, double cfl_desired,
                           double cfl_max) {
   const int f = blockIdx.x * blockDim.x + threadIdx.x;
   if (f >= nforest) return;
-  const double nu = numax[f];
-  int32_t st = 0;
-  if (nu > cfl_max) st |= 1;
-  if (f == 0) {
-    if (*err & kErrNegDepth) st |= 2;
-    if (*err & kErrNested) st |= 4;
-    *err = 0;
-  }
-  status[f] |= st;
-  if (nu > 0.0) dt[f] = dt[f] * cfl_desired / nu;
-  numax[f] = 0.0;
+  next_dt_one(numax, dt, status, err, f, cfl_desired, cfl_max);
 }
 
 // ---------------------------------------------------------------------------

@@ -146,13 +146,16 @@ int check_connectivity(const std::vector<fcx_tree>& trees, std::string& err) {
   return FCX_OK;
 }
 
+#ifndef FCX_DENSE_FACTOR
+#define FCX_DENSE_FACTOR 4     // dense map when cells <= factor * (leaves + 1024)
+#endif
+
 int Forest::assign(const std::vector<fcx_tree>& t,
                    const std::vector<fcx_leaf>& l, std::string& err) {
   int rc = check_connectivity(t, err);
   if (rc != FCX_OK) return rc;
   trees = t;
   leaves = l;
-  index_.reset(l.size());
   maxlevel = 0;
   size_t k = 0;
   for (int32_t tr = 0; tr < int32_t(trees.size()); ++tr) {
@@ -170,7 +173,6 @@ int Forest::assign(const std::vector<fcx_tree>& t,
       }
       next += uint64_t(1) << (2 * (kS - a.level));
       maxlevel = std::max(maxlevel, int(a.level));
-      index_.put(pack_key(a.tree, a.level, a.ix, a.iy), int32_t(k));
     }
     if (next != (uint64_t(1) << (2 * kS))) {
       err = "leaves do not tile every tree";
@@ -181,15 +183,50 @@ int Forest::assign(const std::vector<fcx_tree>& t,
     err = "leaf with an unknown tree";
     return FCX_EINVAL;
   }
+  const uint64_t cells = uint64_t(trees.size()) << (2 * maxlevel);
+  if (cells <= uint64_t(FCX_DENSE_FACTOR) * (leaves.size() + 1024)) {
+    dense_level_ = maxlevel;
+    index_.reset(0);
+    const int64_t side = int64_t(1) << maxlevel;
+    dense_.resize(size_t(cells));
+    for (size_t q = 0; q < leaves.size(); ++q) {
+      const fcx_leaf& a = leaves[q];
+      const int64_t s = int64_t(1) << (maxlevel - a.level);
+      int32_t* row = dense_.data() + (int64_t(a.tree) * side + int64_t(a.iy) * s) * side +
+                     int64_t(a.ix) * s;
+      for (int64_t r = 0; r < s; ++r, row += side) std::fill(row, row + s, int32_t(q));
+    }
+  } else {
+    dense_level_ = -1;
+    dense_.clear();
+    index_.reset(leaves.size());
+    for (size_t q = 0; q < leaves.size(); ++q) {
+      const fcx_leaf& a = leaves[q];
+      index_.put(pack_key(a.tree, a.level, a.ix, a.iy), int32_t(q));
+    }
+  }
   return FCX_OK;
 }
 
 int64_t Forest::find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const {
-  return index_.get(pack_key(tree, level, ix, iy));
+  if (dense_level_ < 0) return index_.get(pack_key(tree, level, ix, iy));
+  if (tree < 0 || tree >= int32_t(trees.size()) || level < 0 || level > dense_level_ ||
+      ix < 0 || iy < 0 || ix >= (int64_t(1) << level) || iy >= (int64_t(1) << level))
+    return -1;
+  const int sh = dense_level_ - level;
+  const int64_t side = int64_t(1) << dense_level_;
+  const int32_t q = dense_[size_t((int64_t(tree) * side + (iy << sh)) * side + (ix << sh))];
+  return leaves[q].level == level ? q : -1;
 }
 
 int64_t Forest::leaf_at(int32_t tree, int64_t x, int64_t y, int hint) const {
   if (x < 0 || y < 0 || x >= kSide || y >= kSide) return -1;
+  if (dense_level_ >= 0) {
+    if (tree < 0 || tree >= int32_t(trees.size())) return -1;
+    const int sh = kS - dense_level_;
+    const int64_t side = int64_t(1) << dense_level_;
+    return dense_[size_t((int64_t(tree) * side + (y >> sh)) * side + (x >> sh))];
+  }
   if (hint >= 0) {
     // 2:1 balance puts every neighbour within one level of the asker
     const int cand[3] = {hint, hint + 1, hint - 1};

@@ -77,7 +77,12 @@ class Forest {
   bool wall_face(int64_t p, int f) const;
 
  private:
+  // Leaf lookup: a dense map from the cells of the finest level present to
+  // leaf ids (rows of 2^dense_level_ cells, tree-major) when it is not much
+  // larger than the leaf set, otherwise a hash of (tree, level, ix, iy).
   LeafIndex index_;
+  std::vector<int32_t> dense_;
+  int dense_level_ = -1;
 };
 
 int check_connectivity(const std::vector<fcx_tree>& trees, std::string& err);

@@ -240,6 +240,64 @@ def test_one_call_regrid_equals_the_separate_calls():
     assert _rel(gpu.state(), want) <= 1e-15
 
 
+def _two_way_coarse_corners(lv):
+    """Number of (leaf, corner) pairs whose two faces at that corner both
+    border finer leaves: the corner cell takes a reflux correction from an
+    xi face and from an eta face."""
+    have = {(int(a["level"]), int(a["ix"]), int(a["iy"])) for a in lv}
+    n = 0
+    for a in lv:
+        l, x, y = int(a["level"]), int(a["ix"]), int(a["iy"])
+        finer = [(l + 1, 2 * x - 1, 2 * y) in have, (l + 1, 2 * x + 2, 2 * y) in have,
+                 (l + 1, 2 * x, 2 * y - 1) in have, (l + 1, 2 * x, 2 * y + 2) in have]
+        n += sum(finer[fx] and finer[2 + fy] for fx in (0, 1) for fy in (0, 1))
+    return n
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_advance_equals_the_three_calls(precision):
+    """fcx_advance (reflux and next dt in one launch) gives bit for bit the
+    state, dt and flags of fcx_fused_step + fcx_reflux + fcx_next_dt, on a
+    mesh where coarse corner cells take both an xi and an eta correction;
+    the last step exceeds cfl_max so the flag path runs too."""
+    import torch
+    say(f"[advance] precision={precision}")
+    trees, pl = I.walled_square()
+    m = 16
+    lv = fcx.balance(trees, I.random_leaves(21, 1, 2, 5, 40))
+    assert _two_way_coarse_corners(lv) > 0
+    q0 = smooth_sw_state(lv, m, pl, 5)
+    cfg = fcx.config(m, precision, fcx.FCX_SHALLOW)
+    dtype = torch.float64 if precision == 64 else torch.float32
+    dt0 = 0.3 / (m << 5)
+    results = []
+    for one_call in (False, True):
+        ctx = fcx.Context(cfg, trees)
+        ctx.upload_forest(lv)
+        q = torch.from_numpy(q0.ravel().copy()).to(dtype).cuda()
+        dt = torch.full((1,), dt0, dtype=torch.float64, device="cuda")
+        nu = torch.zeros_like(dt)
+        st = torch.zeros(1, dtype=torch.int32, device="cuda")
+        hist = []
+        for n in range(6):
+            if n == 5:
+                dt.mul_(2.0)
+            qn = torch.empty_like(q)
+            if one_call:
+                ctx.advance(q, qn, dt, nu, st)
+            else:
+                ctx.fused_step(q, qn, dt, nu)
+                ctx.reflux(q, qn, dt)
+                ctx.next_dt(nu, dt, st)
+            q = qn
+            hist.append((dt.item(), st.item(), nu.item()))
+        results.append((q.cpu().numpy(), hist))
+    (qa, ha), (qb, hb) = results
+    assert np.array_equal(qa, qb, equal_nan=True)
+    assert ha == hb
+    assert ha[-1][1] & 1 and not ha[-2][1] & 1
+
+
 @pytest.mark.parametrize("fused", [True, False])
 def test_native_run_loop_equals_single_calls(fused):
     """fcx_run (steps with a regrid every 3) gives bit for bit the state,
