@@ -379,18 +379,76 @@ int Forest::locate(int32_t tree, int64_t x, int64_t y, int32_t& tout,
 }
 
 // ---------------------------------------------------------------------------
+// The tentative leaves of a balance or regrid; they tile every tree at all
+// times.  has(): is (tree, level, ix, iy) a leaf; covering(): level of the
+// leaf holding the point (x, y) if it is at most maxlev, else -1; add():
+// insert a leaf; split(): replace a leaf by its four children.
+struct HashLeafSet {
+  LeafIndex idx;
+  explicit HashLeafSet(size_t n) { idx.reset(n); }
+  bool has(int32_t t, int l, int64_t ix, int64_t iy) const {
+    return idx.get(pack_key(t, l, ix, iy)) >= 0;
+  }
+  int covering(int32_t t, int64_t x, int64_t y, int maxlev) const {
+    for (int l = maxlev; l >= 0; --l)
+      if (has(t, l, x >> (kS - l), y >> (kS - l))) return l;
+    return -1;
+  }
+  void add(int32_t t, int l, int64_t ix, int64_t iy) { idx.put(pack_key(t, l, ix, iy), 1); }
+  void split(int32_t t, int l, int64_t ix, int64_t iy) {
+    idx.erase(pack_key(t, l, ix, iy));
+    for (int c = 0; c < 4; ++c) add(t, l + 1, 2 * ix + (c & 1), 2 * iy + (c >> 1));
+  }
+  size_t size() const { return idx.size(); }
+};
+
+// Dense form for shallow forests: the level of the leaf holding each cell of
+// level L (rows of 2^L cells, tree-major).  Leaves are at most level L.
+struct DenseLeafSet {
+  std::vector<int8_t> lev;
+  int L;
+  int64_t side;
+  size_t count = 0;
+  DenseLeafSet(int ntrees, int L_) : L(L_), side(int64_t(1) << L_) {
+    lev.assign(size_t(ntrees) * size_t(side) * size_t(side), int8_t(-1));
+  }
+  int8_t* at(int32_t t, int64_t cx, int64_t cy) {
+    return lev.data() + (int64_t(t) * side + cy) * side + cx;
+  }
+  int8_t get(int32_t t, int64_t cx, int64_t cy) const {
+    return lev[size_t((int64_t(t) * side + cy) * side + cx)];
+  }
+  bool has(int32_t t, int l, int64_t ix, int64_t iy) const {
+    return l <= L && get(t, ix << (L - l), iy << (L - l)) == l;
+  }
+  int covering(int32_t t, int64_t x, int64_t y, int maxlev) const {
+    const int v = get(t, x >> (kS - L), y >> (kS - L));
+    return v <= maxlev ? v : -1;
+  }
+  void fill(int32_t t, int l, int64_t ix, int64_t iy, int8_t v) {
+    const int64_t s = int64_t(1) << (L - l);
+    int8_t* row = at(t, ix * s, iy * s);
+    for (int64_t r = 0; r < s; ++r, row += side) std::fill(row, row + s, v);
+  }
+  void add(int32_t t, int l, int64_t ix, int64_t iy) { fill(t, l, ix, iy, int8_t(l)); ++count; }
+  void split(int32_t t, int l, int64_t ix, int64_t iy) {
+    fill(t, l, ix, iy, int8_t(l + 1));
+    count += 3;
+  }
+  size_t size() const { return count; }
+};
+
 // Balance by ripple propagation.  A leaf L of level l needs the leaf holding
 // each of its eight same-size neighbour boxes to have level >= l - 1; when
 // that leaf is coarser it is split (and its children queued), until every
-// constraint holds.  Only forced splits are made, so the result is the
-// coarsest balanced refinement.
-// Split leaves until every leaf reachable from the worklist sees its eight
-// same-size neighbour boxes held by leaves at most one level coarser.
-static void ripple(const Forest& geo, LeafIndex& set, std::deque<fcx_leaf>& work) {
+// leaf reachable from the worklist satisfies this.  Only forced splits are
+// made, so the result is the coarsest balanced refinement.
+template <class Set>
+static void ripple(const Forest& geo, Set& set, std::deque<fcx_leaf>& work) {
   while (!work.empty()) {
     const fcx_leaf L = work.front();
     work.pop_front();
-    if (set.get(pack_key(L.tree, L.level, L.ix, L.iy)) < 0) continue;
+    if (!set.has(L.tree, L.level, L.ix, L.iy)) continue;
     if (L.level < 2) continue;
     const int64_t size = kSide >> L.level;
     for (int dy = -1; dy <= 1; ++dy)
@@ -404,30 +462,22 @@ static void ripple(const Forest& geo, LeafIndex& set, std::deque<fcx_leaf>& work
         if (geo.locate(L.tree, px, py, t2, x2, y2, xf) != 0) continue;
         for (;;) {
           // leaf among the ancestors of the neighbour box (level <= L.level)
-          int found = -1;
-          for (int lev = L.level; lev >= 0; --lev)
-            if (set.get(pack_key(t2, lev, x2 >> (kS - lev), y2 >> (kS - lev))) >= 0) {
-              found = lev;
-              break;
-            }
+          const int found = set.covering(t2, x2, y2, L.level);
           if (found < 0 || found >= L.level - 1) break;
           const int64_t ax = x2 >> (kS - found), ay = y2 >> (kS - found);
-          set.erase(pack_key(t2, found, ax, ay));
-          for (int c = 0; c < 4; ++c) {
-            fcx_leaf ch{t2, found + 1, int32_t(2 * ax + (c & 1)),
-                        int32_t(2 * ay + (c >> 1))};
-            set.put(pack_key(ch.tree, ch.level, ch.ix, ch.iy), 1);
-            work.push_back(ch);
-          }
+          set.split(t2, found, ax, ay);
+          for (int c = 0; c < 4; ++c)
+            work.push_back({t2, found + 1, int32_t(2 * ax + (c & 1)),
+                            int32_t(2 * ay + (c >> 1))});
         }
       }
   }
 }
 
-static void collect(const LeafIndex& set, std::vector<fcx_leaf>& out) {
+static void collect(const HashLeafSet& set, std::vector<fcx_leaf>& out) {
   out.clear();
   out.reserve(set.size());
-  set.for_each([&](uint64_t k, int32_t) {
+  set.idx.for_each([&](uint64_t k, int32_t) {
     fcx_leaf a;
     a.tree = int32_t(k >> 53);
     a.level = int32_t((k >> 48) & 31);
@@ -438,17 +488,13 @@ static void collect(const LeafIndex& set, std::vector<fcx_leaf>& out) {
   sort_leaves(out);
 }
 
-// Balance by ripple propagation from every leaf.  A leaf L of level l needs
-// the leaf holding each of its eight same-size neighbour boxes to have level
-// >= l - 1; when that leaf is coarser it is split (and its children queued),
-// until every constraint holds.  Only forced splits are made, so the result
-// is the coarsest balanced refinement.
+// Coarsest balanced refinement of arbitrary leaves: the ripple seeded with
+// every leaf.
 int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
             std::vector<fcx_leaf>& out, std::string& err) {
   int rc = check_connectivity(trees, err);
   if (rc != FCX_OK) return rc;
-  LeafIndex set;
-  set.reset(in.size() * 2);
+  HashLeafSet set(in.size() * 2);
   std::deque<fcx_leaf> work;
   for (const auto& a : in) {
     if (a.tree < 0 || a.tree >= int32_t(trees.size()) || a.level < 0 ||
@@ -456,7 +502,7 @@ int balance(const std::vector<fcx_tree>& trees, std::vector<fcx_leaf> in,
       err = "leaf out of range";
       return FCX_EINVAL;
     }
-    set.put(pack_key(a.tree, a.level, a.ix, a.iy), 1);
+    set.add(a.tree, a.level, a.ix, a.iy);
     work.push_back(a);
   }
   Forest geo;            // connectivity only (for locate)
@@ -723,11 +769,10 @@ int update_plan(const Forest& f, int m, const Plan& old,
 // new leaves can break balance, and the ripple is seeded with the refined
 // children alone; the result is the coarsest balanced refinement of the
 // tentative forest, as a full ripple would give.
-int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
-           std::vector<fcx_leaf>& out, std::string& err) {
+template <class Set>
+static int regrid_with(const Forest& f, const int8_t* tags, int lmin, int lmax, Set& set,
+                       std::vector<fcx_leaf>& out, std::string& err) {
   const int64_t n = int64_t(f.leaves.size());
-  LeafIndex set;
-  set.reset(size_t(n) * 2 + 64);
   std::deque<fcx_leaf> work;
   std::vector<int64_t> merged;                 // first child of each merge
   for (int64_t p = 0; p < n; ++p) {
@@ -735,7 +780,7 @@ int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
     if (tags[p] > 0 && a.level < lmax) {
       for (int c = 0; c < 4; ++c) {
         fcx_leaf ch{a.tree, a.level + 1, 2 * a.ix + (c & 1), 2 * a.iy + (c >> 1)};
-        set.put(pack_key(ch.tree, ch.level, ch.ix, ch.iy), 1);
+        set.add(ch.tree, ch.level, ch.ix, ch.iy);
         work.push_back(ch);
       }
       continue;
@@ -749,13 +794,13 @@ int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
       }
       if (all) {
         if (a.ix == bx && a.iy == by) {
-          set.put(pack_key(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1), 1);
+          set.add(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1);
           merged.push_back(p);
         }
         continue;
       }
     }
-    set.put(pack_key(a.tree, a.level, a.ix, a.iy), 1);
+    set.add(a.tree, a.level, a.ix, a.iy);
   }
   // cancel merges whose parent would touch a leaf two levels finer; a
   // cancellation restores finer leaves and can force others, so repeat
@@ -787,16 +832,11 @@ int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
           int64_t x2, y2;
           Xform xf;
           if (f.locate(a.tree, cx, cy, t2, x2, y2, xf) != 0) continue;
-          bool covered = false;
-          for (int lev = l; lev >= 0 && !covered; --lev)
-            covered = set.get(pack_key(t2, lev, x2 >> (kS - lev), y2 >> (kS - lev))) >= 0;
-          if (!covered) bad = true;
+          if (set.covering(t2, x2, y2, l) < 0) bad = true;
         }
       }
     if (bad) {
-      set.erase(pack_key(a.tree, pl, pix, piy));
-      for (int c = 0; c < 4; ++c)
-        set.put(pack_key(a.tree, l, 2 * pix + (c & 1), 2 * piy + (c >> 1)), 1);
+      set.split(a.tree, pl, pix, piy);
       cancelled[mi] = 1;
       again = true;
     }
@@ -811,8 +851,8 @@ int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
   std::vector<fcx_leaf> stack;
   for (int64_t p = 0; p < n; ++p) {
     const fcx_leaf& a = f.leaves[p];
-    if (set.get(pack_key(a.tree, a.level, a.ix, a.iy)) >= 0) { out.push_back(a); continue; }
-    if (a.level > 0 && set.get(pack_key(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1)) >= 0) {
+    if (set.has(a.tree, a.level, a.ix, a.iy)) { out.push_back(a); continue; }
+    if (a.level > 0 && set.has(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1)) {
       if (!(a.ix & 1) && !(a.iy & 1)) out.push_back({a.tree, a.level - 1, a.ix >> 1, a.iy >> 1});
       continue;
     }
@@ -823,7 +863,7 @@ int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
       // children pushed in reverse Morton order so they pop in order
       for (int c = 3; c >= 0; --c) {
         const fcx_leaf ch{b.tree, b.level + 1, 2 * b.ix + (c & 1), 2 * b.iy + (c >> 1)};
-        if (set.get(pack_key(ch.tree, ch.level, ch.ix, ch.iy)) >= 0) {
+        if (set.has(ch.tree, ch.level, ch.ix, ch.iy)) {
           stack.push_back({-1 - ch.tree, ch.level, ch.ix, ch.iy});   // marked: emit
         } else {
           stack.push_back(ch);
@@ -842,6 +882,20 @@ int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
     return FCX_EINVAL;
   }
   return FCX_OK;
+}
+
+int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
+           std::vector<fcx_leaf>& out, std::string& err) {
+  const size_t n = f.leaves.size();
+  // the finest level the tentative leaves can reach
+  const int L = std::max(f.maxlevel, std::min(lmax, f.maxlevel + 1));
+  const uint64_t cells = uint64_t(f.trees.size()) << (2 * L);
+  if (L <= kMaxLevel && cells <= uint64_t(FCX_DENSE_FACTOR) * (n + 1024)) {
+    DenseLeafSet set(int(f.trees.size()), L);
+    return regrid_with(f, tags, lmin, lmax, set, out, err);
+  }
+  HashLeafSet set(n * 2 + 64);
+  return regrid_with(f, tags, lmin, lmax, set, out, err);
 }
 
 int transfer_plan(const Forest& old_f, const Forest& new_f,
