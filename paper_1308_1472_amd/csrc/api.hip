@@ -138,6 +138,14 @@ struct fcx_ctx {
   Plan plan;                       // host copy of the current forest's plan
   DevBuf<int8_t> tags_dev;         // fcx_regrid: tags on the device
   HostBuf tags_host;               //   and their pinned host copy
+  hipEvent_t staged = nullptr;     // end of the last stream-ordered plan upload
+  bool staged_pending = false;     //   from `staging`, not yet waited for
+  ~fcx_ctx() {
+    if (staged) {
+      (void)hipEventSynchronize(staged);
+      (void)hipEventDestroy(staged);
+    }
+  }
 };
 
 // Cube faces as (centre, u, v) axis vectors, the same frames as the device
@@ -296,9 +304,18 @@ int fcx_destroy(fcx_ctx* ctx) {
 
 static size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// The plan goes to the device in one copy from the pinned staging buffer:
+// a blocking copy, or with `s` a copy ordered on that stream (later work on
+// the stream sees the new plan; the staging buffer is not written again
+// before that copy has ended).
 static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
                        const std::vector<int32_t>* kind = nullptr,
-                       const std::vector<int32_t>* src = nullptr) {
+                       const std::vector<int32_t>* src = nullptr,
+                       hipStream_t s = nullptr, bool ordered = false) {
+  if (c->staged_pending) {
+    HIPCHK(hipEventSynchronize(c->staged));
+    c->staged_pending = false;
+  }
   Plan plan;
   std::string err;
   const bool sync = c->cfg.physics == FCX_SPHERE;
@@ -356,7 +373,14 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   if (src) std::memcpy(h + off[6], src->data(), sz[6]);
   if (sz[7]) std::memcpy(h + off[7], links.data(), sz[7]);
   HIPCHK(dev.blob.ensure(at));
-  HIPCHK(hipMemcpy(dev.blob.p, h, at, hipMemcpyHostToDevice));
+  if (ordered) {
+    if (!c->staged) HIPCHK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
+    HIPCHK(hipMemcpyAsync(dev.blob.p, h, at, hipMemcpyHostToDevice, s));
+    HIPCHK(hipEventRecord(c->staged, s));
+    c->staged_pending = true;
+  } else {
+    HIPCHK(hipMemcpy(dev.blob.p, h, at, hipMemcpyHostToDevice));
+  }
   uint8_t* d = dev.blob.p;
   dev.rec = reinterpret_cast<PatchRec*>(d + off[0]);
   dev.phislot = reinterpret_cast<int32_t*>(d + off[1]);
@@ -692,8 +716,8 @@ int fcx_regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criter
             : launch_tags<float, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
 }
 
-int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
-                     int64_t* n_new) {
+static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
+                        int64_t* n_new, hipStream_t s, bool ordered) {
   if (!c || !tags || !n_new || lmin < 0 || lmax < lmin || lmax > kMaxLevel)
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
@@ -703,7 +727,7 @@ int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
   int rc = regrid(c->forest, tags, lmin, lmax, out, err);
   if (rc != FCX_OK) return fail(rc, err);
   Forest nf;
-  rc = nf.assign(c->trees, out, err);
+  rc = nf.assign(c->trees, std::move(out), err);
   if (rc != FCX_OK) return fail(rc, err);
   std::vector<int32_t> kind, src;
   rc = transfer_plan(c->forest, nf, kind, src, err);
@@ -713,12 +737,17 @@ int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
   c->old_forest = std::move(c->forest);
   c->forest = std::move(nf);
   c->have_old = true;
-  rc = upload_plan(c, c->forest, c->cur, &kind, &src);
+  rc = upload_plan(c, c->forest, c->cur, &kind, &src, s, ordered);
   if (rc != FCX_OK) return rc;
   rc = finish_upload(c);
   if (rc != FCX_OK) return rc;
   *n_new = int64_t(c->forest.leaves.size());
   return FCX_OK;
+}
+
+int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
+                     int64_t* n_new) {
+  return regrid_apply(c, tags, lmin, lmax, n_new, nullptr, false);
 }
 
 template <typename R, int MEQN>
@@ -1233,8 +1262,8 @@ int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(hipMemcpyAsync(c->tags_host.p, c->tags_dev.p, size_t(P), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  return fcx_regrid_apply(c, reinterpret_cast<const int8_t*>(c->tags_host.p), lmin, lmax,
-                          n_new);
+  return regrid_apply(c, reinterpret_cast<const int8_t*>(c->tags_host.p), lmin, lmax, n_new,
+                      s, true);
 }
 
 // ---- a run of many steps ----------------------------------------------------

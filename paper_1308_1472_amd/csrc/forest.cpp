@@ -150,12 +150,12 @@ int check_connectivity(const std::vector<fcx_tree>& trees, std::string& err) {
 #define FCX_DENSE_FACTOR 4     // dense map when cells <= factor * (leaves + 1024)
 #endif
 
-int Forest::assign(const std::vector<fcx_tree>& t,
-                   const std::vector<fcx_leaf>& l, std::string& err) {
+int Forest::assign(const std::vector<fcx_tree>& t, std::vector<fcx_leaf> l,
+                   std::string& err) {
   int rc = check_connectivity(t, err);
   if (rc != FCX_OK) return rc;
   trees = t;
-  leaves = l;
+  leaves = std::move(l);
   maxlevel = 0;
   size_t k = 0;
   for (int32_t tr = 0; tr < int32_t(trees.size()); ++tr) {

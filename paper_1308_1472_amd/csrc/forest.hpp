@@ -61,7 +61,7 @@ class Forest {
 
   // Validates connectivity and leaves (sorted, exact tiling); builds the
   // leaf index.  Returns FCX_OK or an error code with a message in err.
-  int assign(const std::vector<fcx_tree>& t, const std::vector<fcx_leaf>& l,
+  int assign(const std::vector<fcx_tree>& t, std::vector<fcx_leaf> l,
              std::string& err);
   int64_t find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const;
   // leaf containing an in-tree point, -1 if none; levels near `hint` are
