@@ -136,6 +136,7 @@ struct fcx_ctx {
   DevBuf<uint8_t> sscratch;        // sphere step: per-workgroup edge data
   int cus = 256;
   Plan plan;                       // host copy of the current forest's plan
+  Plan spare;                      // the previous one, its storage reused
   DevBuf<int8_t> tags_dev;         // fcx_regrid: tags on the device
   HostBuf tags_host;               //   and their pinned host copy
   hipEvent_t staged = nullptr;     // end of the last stream-ordered plan upload
@@ -316,7 +317,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
     HIPCHK(hipEventSynchronize(c->staged));
     c->staged_pending = false;
   }
-  Plan plan;
+  Plan& plan = c->spare;
   std::string err;
   const bool sync = c->cfg.physics == FCX_SPHERE;
   // after a regrid only the patches next to a change are planned afresh
@@ -329,9 +330,18 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   // of the other direction on the same coarse patch whose faces meet its own
   // at its low and high end (the corner cell both correct)
   const size_t NI = plan.reflux.size();
-  std::vector<RefluxItem> items(NI);
-  std::vector<int32_t> links(2 * NI);
+  size_t off[9];
+  size_t at = 0;
+  const size_t sz[8] = {P * sizeof(PatchRec), P * 4, P * 4,
+                        NI * sizeof(RefluxItem), 2 * 4,
+                        kind ? P * 4 : 0, src ? P * 4 : 0, NI * 2 * 4};
+  for (int k = 0; k < 8; ++k) { off[k] = at; at += align256(sz[k]); }
+  off[8] = at;
+  HIPCHK(c->staging.ensure(at));
+  uint8_t* h = c->staging.p;
   {
+    RefluxItem* items = reinterpret_cast<RefluxItem*>(h + off[3]);
+    int32_t* links = reinterpret_cast<int32_t*>(h + off[7]);
     int32_t nx = 0;
     for (const auto& it : plan.reflux) nx += it.face < 2;
     dev.n_reflux_x = nx;
@@ -339,6 +349,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
     int32_t ix = 0, iy = nx;
     for (size_t p = 0; p < P; ++p) {
       const int32_t b = plan.item_first[p], e = plan.item_first[p + 1];
+      if (b == e) continue;
       int32_t at_face[4] = {-1, -1, -1, -1}, pos[4];
       for (int32_t t = b; t < e; ++t) {
         const int f = plan.reflux[t].face;
@@ -354,24 +365,13 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
       }
     }
   }
-  size_t off[9];
-  size_t at = 0;
-  const size_t sz[8] = {P * sizeof(PatchRec), P * 4, P * 4,
-                        NI * sizeof(RefluxItem), 2 * 4,
-                        kind ? P * 4 : 0, src ? P * 4 : 0, NI * 2 * 4};
-  for (int k = 0; k < 8; ++k) { off[k] = at; at += align256(sz[k]); }
-  off[8] = at;
-  HIPCHK(c->staging.ensure(at));
-  uint8_t* h = c->staging.p;
   std::memcpy(h + off[0], plan.recs.data(), sz[0]);
   std::memcpy(h + off[1], plan.phislot.data(), sz[1]);
   std::memcpy(h + off[2], plan.family.data(), sz[2]);
-  if (sz[3]) std::memcpy(h + off[3], items.data(), sz[3]);
   const int32_t first[2] = {0, int32_t(P)};
   std::memcpy(h + off[4], first, sz[4]);
   if (kind) std::memcpy(h + off[5], kind->data(), sz[5]);
   if (src) std::memcpy(h + off[6], src->data(), sz[6]);
-  if (sz[7]) std::memcpy(h + off[7], links.data(), sz[7]);
   HIPCHK(dev.blob.ensure(at));
   if (ordered) {
     if (!c->staged) HIPCHK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
@@ -392,7 +392,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   dev.links = reinterpret_cast<int32_t*>(d + off[7]);
   dev.nslots = plan.nslots;
   dev.P = int64_t(P);
-  c->plan = std::move(plan);
+  std::swap(c->plan, c->spare);
   return FCX_OK;
 }
 

@@ -3,7 +3,7 @@
 // regrid, the transfer plan, plan updates and fresh plan builds, with lookups
 // that hit and miss.  It prints one digest per forest (the caller compares
 // builds with different lookup structures) and exits non-zero if an updated
-// plan differs from a fresh build.
+// plan, written over the storage of an older one, differs from a fresh build.
 #include <cstdio>
 #include <cstring>
 #include <random>
@@ -81,7 +81,7 @@ int main() {
     Forest f;
     rc = f.assign(trees, bl, err);
     mix(&rc, 4);
-    Plan p;
+    Plan p, pu;    // pu: the plan before p, its storage reused as the library does
     rc = build_plan(f, 16, p, err, trial % 2);
     mix(&rc, 4); mixplan(p);
     for (int step = 0; step < 4; ++step) {
@@ -96,7 +96,7 @@ int main() {
       std::vector<int32_t> kind, src;
       rc = transfer_plan(f, nf, kind, src, err);
       mix(&rc, 4); mixv(kind); mixv(src);
-      Plan pu, pb;
+      Plan pb;
       rc = update_plan(nf, 16, p, kind, src, pu, err, trial % 2);
       mix(&rc, 4); mixplan(pu);
       rc = build_plan(nf, 16, pb, err, trial % 2);
@@ -115,7 +115,7 @@ int main() {
         mix(&r2, 8);
       }
       f = std::move(nf);
-      p = std::move(pu);
+      std::swap(p, pu);
     }
     std::printf("%d %zu %016llx\n", trial, f.leaves.size(), (unsigned long long)H);
   }
