@@ -82,6 +82,12 @@ int  fco_sums(const fco_mesh *mesh, const fco_params *par, const double *q,
 int  fco_tags(const fco_mesh *mesh, const fco_params *par, const double *q,
               int32_t criterion, double threshold, int32_t lmin,
               int32_t lmax, int8_t *tags);
+/* per patch: its criterion value (refine[p]) and, when p is the first
+ * child of a complete family, the value of the averaged parent (parent[p],
+ * NaN otherwise); a value passes when it exceeds thr (criterion 0) or thr^2
+ * (criterion 1) */
+int  fco_tag_values(const fco_mesh *mesh, const fco_params *par, const double *q,
+                    int32_t criterion, double *refine, double *parent);
 int  fco_regrid(const fco_mesh *mesh, const int8_t *tags, int32_t lmin,
                 int32_t lmax, int64_t cap, fco_leaf *out, int64_t *nout);
 int  fco_transfer(const fco_mesh *old_mesh, const fco_mesh *new_mesh,

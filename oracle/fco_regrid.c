@@ -52,9 +52,11 @@ static double spacing(const fco_mesh *mesh, int64_t p, int32_t ia, int32_t ja,
   return atan2(sqrt(cx * cx + cy * cy + cz * cz), dot);
 }
 
-static int refine_criterion(const fco_mesh *mesh, const fco_params *par,
-                            const double *q, int64_t p, int criterion,
-                            double thr) {
+/* criterion value of patch p: max - min of h (criterion 0) or the largest
+ * squared gradient of h (criterion 1); the patch passes when the value
+ * exceeds thr (criterion 0) or thr^2 (criterion 1) */
+static double refine_value(const fco_mesh *mesh, const fco_params *par,
+                           const double *q, int64_t p, int criterion) {
   const int32_t m = mesh->m, meqn = par->meqn;
   if (criterion == 0) {
     double lo = INFINITY, hi = -INFINITY;
@@ -64,9 +66,9 @@ static int refine_criterion(const fco_mesh *mesh, const fco_params *par,
         lo = fmin(lo, v);
         hi = fmax(hi, v);
       }
-    return (hi - lo) > thr;
+    return hi - lo;
   }
-  const double t2 = thr * thr;
+  double best = 0.0;
   for (int32_t j = 1; j <= m; ++j)
     for (int32_t i = 1; i <= m; ++i) {
       double gx = (qv(q, m, meqn, p, 0, i + 1, j) - qv(q, m, meqn, p, 0, i - 1, j)) /
@@ -75,15 +77,18 @@ static int refine_criterion(const fco_mesh *mesh, const fco_params *par,
                   spacing(mesh, p, i, j - 1, i, j + 1);
       double s = gx * gx;
       s = s + gy * gy;
-      if (s > t2) return 1;
+      best = fmax(best, s);
     }
-  return 0;
+  return best;
 }
 
-/* criterion on the averaged parent of the family whose first child is p */
-static int parent_criterion(const fco_mesh *mesh, const fco_params *par,
-                            const double *q, const int64_t kids[4],
-                            int criterion, double thr) {
+static int passes(int criterion, double value, double thr) {
+  return criterion == 0 ? value > thr : value > thr * thr;
+}
+
+/* criterion value of the averaged parent of the family kids[0..3] */
+static double parent_value(const fco_mesh *mesh, const fco_params *par,
+                           const double *q, const int64_t kids[4], int criterion) {
   const int32_t m = mesh->m, meqn = par->meqn, h = m / 2;
   double *P = (double *)malloc(sizeof(double) * m * m);
   double *cx = (double *)malloc(sizeof(double) * m * m * 3);
@@ -111,19 +116,18 @@ static int parent_criterion(const fco_mesh *mesh, const fco_params *par,
         for (int d = 0; d < 3; ++d) cx[((J - 1) * m + (I - 1)) * 3 + d] = r[d] / nr;
       }
     }
-  int res = 0;
+  double res = 0.0;
   if (criterion == 0) {
     double lo = INFINITY, hi = -INFINITY;
     for (int32_t k = 0; k < m * m; ++k) {
       lo = fmin(lo, P[k]);
       hi = fmax(hi, P[k]);
     }
-    res = (hi - lo) > thr;
+    res = hi - lo;
   } else {
     const double dxp = ldexp(1.0, -(mesh->leaves[kids[0]].level - 1)) / m;
-    const double t2 = thr * thr;
-    for (int32_t J = 1; J <= m && !res; ++J)
-      for (int32_t I = 1; I <= m && !res; ++I) {
+    for (int32_t J = 1; J <= m; ++J)
+      for (int32_t I = 1; I <= m; ++I) {
         int32_t ia = I > 1 ? I - 1 : I, ib = I < m ? I + 1 : I;
         int32_t ja = J > 1 ? J - 1 : J, jb = J < m ? J + 1 : J;
         double sx, sy;
@@ -148,12 +152,36 @@ static int parent_criterion(const fco_mesh *mesh, const fco_params *par,
         double gy = (P[(jb - 1) * m + (I - 1)] - P[(ja - 1) * m + (I - 1)]) / sy;
         double s = gx * gx;
         s = s + gy * gy;
-        if (s > t2) res = 1;
+        res = fmax(res, s);
       }
   }
   free(P);
   free(cx);
   return res;
+}
+
+/* the four members of the complete family whose first child is p, or 0 */
+static int family_of(const fco_mesh *mesh, int64_t p, int64_t kids[4]) {
+  const fco_leaf *a = &mesh->leaves[p];
+  if (a->level == 0 || (a->ix & 1) || (a->iy & 1)) return 0;
+  for (int c = 0; c < 4; ++c) {
+    kids[c] = fco_find(mesh, a->tree, a->level, a->ix + (c & 1), a->iy + (c >> 1));
+    if (kids[c] < 0) return 0;
+  }
+  return 1;
+}
+
+int fco_tag_values(const fco_mesh *mesh, const fco_params *par, const double *q,
+                   int32_t criterion, double *refine, double *parent) {
+  if (!mesh || !par || !q || !refine || !parent || (criterion != 0 && criterion != 1))
+    return -1;
+  for (int64_t p = 0; p < mesh->n; ++p) {
+    int64_t kids[4];
+    refine[p] = refine_value(mesh, par, q, p, criterion);
+    parent[p] = family_of(mesh, p, kids) ? parent_value(mesh, par, q, kids, criterion)
+                                         : NAN;
+  }
+  return 0;
 }
 
 int fco_tags(const fco_mesh *mesh, const fco_params *par, const double *q,
@@ -164,21 +192,18 @@ int fco_tags(const fco_mesh *mesh, const fco_params *par, const double *q,
   const int64_t n = mesh->n;
   char *crit = (char *)malloc((size_t)n);
   for (int64_t p = 0; p < n; ++p) {
-    crit[p] = (char)refine_criterion(mesh, par, q, p, criterion, threshold);
+    crit[p] = (char)passes(criterion, refine_value(mesh, par, q, p, criterion), threshold);
     tags[p] = (crit[p] && mesh->leaves[p].level < lmax) ? 1 : 0;
   }
   for (int64_t p = 0; p < n; ++p) {
     const fco_leaf *a = &mesh->leaves[p];
-    if (a->level <= lmin || (a->ix & 1) || (a->iy & 1)) continue;
     int64_t kids[4];
+    if (a->level <= lmin || !family_of(mesh, p, kids)) continue;
     int ok = 1;
-    for (int c = 0; c < 4 && ok; ++c) {
-      kids[c] = fco_find(mesh, a->tree, a->level, a->ix + (c & 1),
-                         a->iy + (c >> 1));
-      if (kids[c] < 0 || tags[kids[c]] == 1) ok = 0;
-    }
+    for (int c = 0; c < 4; ++c)
+      if (tags[kids[c]] == 1) ok = 0;
     if (!ok) continue;
-    if (!parent_criterion(mesh, par, q, kids, criterion, threshold))
+    if (!passes(criterion, parent_value(mesh, par, q, kids, criterion), threshold))
       for (int c = 0; c < 4; ++c) tags[kids[c]] = -1;
   }
   free(crit);

@@ -64,6 +64,7 @@ def lib():
         L.fco_step.argtypes = [vp, vp, vp, vp, dp, i32, vp]
         L.fco_sums.argtypes = [vp, vp, vp, vp]
         L.fco_tags.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp]
+        L.fco_tag_values.argtypes = [vp, vp, vp, i32, vp, vp]
         L.fco_regrid.argtypes = [vp, vp, i32, i32, i64, vp, vp]
         L.fco_transfer.argtypes = [vp, vp, vp, vp, vp]
         L.fco_phi.argtypes = [i32, dp]
@@ -192,6 +193,17 @@ def tags(mesh, par, qf, criterion, threshold, lmin, lmax) -> np.ndarray:
     if rc != 0:
         raise RuntimeError(f"fco_tags failed ({rc})")
     return out
+
+
+def tag_values(mesh, par, qf, criterion):
+    """(refine, parent) criterion values per patch (see fco_tag_values)."""
+    ref = np.zeros(len(mesh))
+    parent = np.zeros(len(mesh))
+    rc = lib().fco_tag_values(mesh.h, C.byref(par), _ptr(qf), criterion, _ptr(ref),
+                              _ptr(parent))
+    if rc != 0:
+        raise RuntimeError(f"fco_tag_values failed ({rc})")
+    return ref, parent
 
 
 def regrid(mesh, tg, lmin, lmax) -> np.ndarray:

@@ -48,6 +48,40 @@ def test_tags_known_cases():
     assert np.all(O.tags(mesh, par, f, 1, 0.1, 1, 2) != 1)
 
 
+def test_tag_values_on_linear_data_and_agreement_with_tags():
+    """h = 1 + a x + b y with walls far from the sampled cells: every
+    interior central difference is exact, so the squared gradient of each
+    patch and of each averaged parent is a^2 + b^2; max - min over a patch
+    of side s with m cells is (|a| + |b|) s (m - 1) / m.  The tags are the
+    decisions the values imply."""
+    trees, pl = I.periodic_square()
+    lv = O.sfc_sort(I.uniform_leaves(1, 3))
+    mesh = O.Mesh(trees, lv, M)
+    par = O.params(M, O.ADVECTION)
+    a, b = 0.375, -0.25
+    # periodic: a linear field jumps at the wrap; take patches away from it
+    q = I.state_from(lv, M, lambda x, y: (1.0 + a * x + b * y)[:, None], pl)
+    f = O.framed(q, M)
+    O.ghost_fill(mesh, par, f)
+    ref, parent = O.tag_values(mesh, par, f, 1)
+    inner = (lv["ix"] > 0) & (lv["ix"] < 7) & (lv["iy"] > 0) & (lv["iy"] < 7)
+    np.testing.assert_allclose(ref[inner], a * a + b * b, rtol=1e-12)
+    fam = ~np.isnan(parent)
+    assert fam.sum() == 16
+    inner_fam = fam & (lv["ix"] >= 2) & (lv["ix"] <= 4) & (lv["iy"] >= 2) & (lv["iy"] <= 4)
+    np.testing.assert_allclose(parent[inner_fam], a * a + b * b, rtol=1e-12)
+    ref0, _ = O.tag_values(mesh, par, f, 0)
+    s = 1.0 / 8
+    np.testing.assert_allclose(ref0[inner], (abs(a) + abs(b)) * s * (M - 1) / M,
+                               rtol=1e-12)
+    # tags follow the values: threshold between two distinct values
+    for crit, vals in ((1, ref), (0, ref0)):
+        thr = np.sqrt(a * a + b * b) * 0.999 if crit == 1 else ref0[inner][0] * 0.999
+        tg = O.tags(mesh, par, f, crit, thr, 1, 5)
+        t = thr * thr if crit == 1 else thr
+        assert np.array_equal(tg == 1, vals > t)
+
+
 def _regrid(mesh, par, q, tg, lmin, lmax, trees):
     f = O.framed(q, mesh.m)
     O.ghost_fill(mesh, par, f)
