@@ -192,8 +192,8 @@ int fcx_advance(fcx_ctx *ctx, const void *q, void *q_new, double *dt,
  * fcx_patch_step, fcx_reflux and fcx_next_dt.  The state starts in q0; *which
  * receives the buffer (0 or 1) holding the final state, *cell_updates the
  * number of interior cells advanced.  FCX_ENOMEM if a capacity is short
- * (the state is then where the last completed step left it).  Planar
- * forests only. */
+ * (the state is then where the last completed step left it).  On the
+ * sphere only with fused = 0. */
 int fcx_run(fcx_ctx *ctx, int32_t fused, void *q0, void *q1, int64_t cap,
             void *ghost, int64_t ghost_cap, int32_t steps, int32_t step0,
             int32_t regrid_every, int32_t criterion, double threshold,
@@ -213,7 +213,9 @@ int fcx_conservation_sums(fcx_ctx *ctx, const void *q, double *sums,
  * siblings above lmin, none tagged +1, whose averaged parent stays below
  * the threshold; 0 otherwise.  criterion 0: max - min of component 0 over
  * the interior (Sec. 5); 1: max |grad q_0| by central differences over the
- * ghost-extended data (needs a ghost fill of the same q). */
+ * ghost-extended data (needs a ghost fill of the same q).  On the sphere the
+ * spacing is the great-circle distance of the cell centres and the parent
+ * average is capacity weighted. */
 int fcx_regrid_tags(fcx_ctx *ctx, const void *q, const void *ghost,
                     int32_t criterion, double threshold, int32_t lmin,
                     int32_t lmax, int8_t *tags, void *stream);
@@ -237,7 +239,10 @@ int fcx_regrid(fcx_ctx *ctx, const void *q, void *ghost, int32_t criterion,
 /* Data transfer after fcx_regrid_apply (Sec. 3: interpolate to new fine
  * patches, average to new coarse patches): kept patches copy, refined ones
  * interpolate with minmod slopes (the old ghost buffer must hold a fill of
- * q_old), merged ones take the mean of the 2x2 children cells. */
+ * q_old), merged ones take the mean of the 2x2 children cells.  On the
+ * sphere the mean is capacity weighted and the four children of a refined
+ * cell are shifted by one common amount so that their capacity-weighted sum
+ * equals the coarse cell's content (conservative). */
 int fcx_regrid_transfer(fcx_ctx *ctx, const void *q_old, const void *ghost_old,
                         void *q_new, void *stream);
 
@@ -298,8 +303,9 @@ int fcx_batch_sums(fcx_batch *batch, const void *q, double *sums, void *stream);
  * after the step.  fcx_patch_step, fcx_ghost_fill, fcx_reflux (which also
  * makes the mass face terms of same-level faces across cube edges agree:
  * call it after every step), fcx_next_dt, fcx_conservation_sums (capacity
- * weighted) and fcx_dilate_tags support the sphere; fused steps, regrid
- * tags and transfer, features and batches return FCX_EINVAL. */
+ * weighted), the regrid calls (tags, apply, transfer, fcx_regrid), fcx_run
+ * with plain steps and fcx_dilate_tags support the sphere; fused steps,
+ * features and batches return FCX_EINVAL. */
 
 /* Geometry table of every patch (device doubles, caller-owned, P * 18 *
  * (m+4)^2 values), per patch 18 frames of (m+4)^2 values indexed by frame

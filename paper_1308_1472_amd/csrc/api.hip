@@ -396,7 +396,10 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   return FCX_OK;
 }
 
-static int finish_upload(fcx_ctx* c) {
+// Device tables that follow the plan: face-term slots, sum partials and, on
+// the sphere, the geometry of every patch (computed on stream s; without
+// `ordered` the call waits for it).
+static int finish_upload(fcx_ctx* c, hipStream_t s = nullptr, bool ordered = false) {
   const int64_t P = c->cur.P;
   const size_t esz = c->cfg.precision == 64 ? 8 : 4;
   HIPCHK(c->phi.ensure(size_t(c->cur.nslots) * 4 * c->cfg.m * c->meqn * esz));
@@ -406,12 +409,12 @@ static int finish_upload(fcx_ctx* c) {
     const size_t FR = size_t(m + 4) * (m + 4);
     HIPCHK(c->cur.geo.ensure(size_t(P) * kGeoN * FR));
     const size_t lds = sizeof(double) * 3 * (m + 5) * (m + 5);
-    hipLaunchKernelGGL(k_sphere_metrics, dim3(unsigned(P)), dim3(256), lds, 0,
+    hipLaunchKernelGGL(k_sphere_metrics, dim3(unsigned(P)), dim3(256), lds, s,
                        c->cur.rec, m, log2i(m), c->cur.geo.p);
     HIPCHK(hipGetLastError());
     const int slots = int(std::min<int64_t>(P, int64_t(c->cus) * 2));
     HIPCHK(c->sscratch.ensure(size_t(slots) * sphere_scratch(m) * esz));
-    HIPCHK(hipDeviceSynchronize());
+    if (!ordered) HIPCHK(hipDeviceSynchronize());
   }
   return FCX_OK;
 }
@@ -688,13 +691,15 @@ template <typename R, int MEQN>
 static int launch_tags(fcx_ctx* c, const void* q, const void* ghost, int criterion,
                        double thr, int lmin, int lmax, int8_t* tags, hipStream_t s) {
   const int m = c->cfg.m;
+  const double* geo = c->cfg.physics == FCX_SPHERE ? c->cur.geo.p : nullptr;
   hipLaunchKernelGGL((k_tag_refine<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
                      0, s, static_cast<const R*>(q), static_cast<const R*>(ghost),
-                     c->cur.rec, m, criterion, thr, lmax, tags);
+                     c->cur.rec, m, criterion, thr, lmax, tags, geo);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((k_tag_family<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
-                     size_t(m) * m * sizeof(double), s, static_cast<const R*>(q),
-                     c->cur.rec, c->cur.family, m, criterion, thr, lmin, tags);
+                     size_t(m) * m * sizeof(double) * (geo ? 4 : 1), s,
+                     static_cast<const R*>(q), c->cur.rec, c->cur.family, m, criterion,
+                     thr, lmin, tags, geo);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -706,12 +711,14 @@ int fcx_regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criter
       (criterion == 1 && !ghost))
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
-  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no regrid on the sphere");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
   if (c->meqn == 1)
     return dp ? launch_tags<double, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
               : launch_tags<float, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
+  if (c->meqn == 4)
+    return dp ? launch_tags<double, 4>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
+              : launch_tags<float, 4>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
   return dp ? launch_tags<double, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
             : launch_tags<float, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
 }
@@ -721,7 +728,6 @@ static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lm
   if (!c || !tags || !n_new || lmin < 0 || lmax < lmin || lmax > kMaxLevel)
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
-  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no regrid on the sphere");
   std::vector<fcx_leaf> out;
   std::string err;
   int rc = regrid(c->forest, tags, lmin, lmax, out, err);
@@ -739,7 +745,7 @@ static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lm
   c->have_old = true;
   rc = upload_plan(c, c->forest, c->cur, &kind, &src, s, ordered);
   if (rc != FCX_OK) return rc;
-  rc = finish_upload(c);
+  rc = finish_upload(c, s, ordered);
   if (rc != FCX_OK) return rc;
   *n_new = int64_t(c->forest.leaves.size());
   return FCX_OK;
@@ -763,12 +769,28 @@ static int launch_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
   return FCX_OK;
 }
 
+template <typename R>
+static int launch_transfer_sphere(fcx_ctx* c, const void* qo, const void* go, void* qn,
+                                  hipStream_t s) {
+  const int m = c->cfg.m;
+  const int64_t tot = c->cur.P * 4 * (m / 2) * (m / 2);
+  hipLaunchKernelGGL((k_transfer_sphere<R>), dim3(unsigned((tot + 255) / 256)), dim3(256),
+                     0, s, static_cast<const R*>(qo), static_cast<const R*>(go),
+                     static_cast<R*>(qn), c->cur.rec, c->cur.xkind, c->cur.xsrc,
+                     c->old.geo.p, c->cur.geo.p, int32_t(c->cur.P), m);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
 int fcx_regrid_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
                         void* stream) {
   if (!c || !qo || !go || !qn) return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_old) return fail(FCX_ESTATE, "no regrid applied");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_SPHERE)
+    return dp ? launch_transfer_sphere<double>(c, qo, go, qn, s)
+              : launch_transfer_sphere<float>(c, qo, go, qn, s);
   if (c->meqn == 1)
     return dp ? launch_transfer<double, 1>(c, qo, go, qn, s)
               : launch_transfer<float, 1>(c, qo, go, qn, s);
@@ -1277,7 +1299,8 @@ int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* gh
       steps < 0 || step0 < 0 || regrid_every < 0 || q0 == q1)
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
-  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no fused run on the sphere");
+  if (c->cfg.physics == FCX_SPHERE && fused)
+    return fail(FCX_EINVAL, "no fused run on the sphere");
   void* buf[2] = {q0, q1};
   int cur = 0;
   int64_t cells = 0;

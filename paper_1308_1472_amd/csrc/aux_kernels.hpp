@@ -249,7 +249,10 @@ k_sums_reduce(const double* __restrict__ partial, const int32_t* __restrict__ fi
 
 // ---------------------------------------------------------------------------
 // Refinement tags.  Decisions are taken on squared quantities with no fused
-// multiply-add so that they reproduce an independent FP64 evaluation.
+// multiply-add so that they reproduce an independent FP64 evaluation.  On
+// the sphere (geo given) differences are divided by the great-circle
+// distance of the cell centres and a parent value is the capacity-weighted
+// average of its four children, its centre their normalised sum.
 template <typename R, int MEQN>
 __device__ __forceinline__ double frame_q0(const R* q, const R* ghost, int m,
                                            int p, int i, int j) {
@@ -262,7 +265,8 @@ template <typename R, int MEQN>
 __global__ void __launch_bounds__(256)
 k_tag_refine(const R* __restrict__ q, const R* __restrict__ ghost,
              const PatchRec* __restrict__ rec, int m, int criterion,
-             double thr, int lmax, int8_t* __restrict__ tags) {
+             double thr, int lmax, int8_t* __restrict__ tags,
+             const double* __restrict__ geo) {
 #pragma clang fp contract(off)
   __shared__ double rlo[4], rhi[4];
   __shared__ int rflag[4];
@@ -277,10 +281,20 @@ k_tag_refine(const R* __restrict__ q, const R* __restrict__ ghost,
     lo = fmin(lo, v);
     hi = fmax(hi, v);
     if (criterion == 1) {
+      double sx = 2.0 * dx, sy = 2.0 * dx;
+      if (geo) {
+        double a[3], b[3];
+        geo_centre(geo, m, p, i - 1, j, a);
+        geo_centre(geo, m, p, i + 1, j, b);
+        sx = arc_between(a, b);
+        geo_centre(geo, m, p, i, j - 1, a);
+        geo_centre(geo, m, p, i, j + 1, b);
+        sy = arc_between(a, b);
+      }
       const double gx = (frame_q0<R, MEQN>(q, ghost, m, p, i + 1, j) -
-                         frame_q0<R, MEQN>(q, ghost, m, p, i - 1, j)) / (2.0 * dx);
+                         frame_q0<R, MEQN>(q, ghost, m, p, i - 1, j)) / sx;
       const double gy = (frame_q0<R, MEQN>(q, ghost, m, p, i, j + 1) -
-                         frame_q0<R, MEQN>(q, ghost, m, p, i, j - 1)) / (2.0 * dx);
+                         frame_q0<R, MEQN>(q, ghost, m, p, i, j - 1)) / sy;
       double s = gx * gx;
       s = s + gy * gy;
       if (s > t2) flag = 1;
@@ -313,9 +327,12 @@ template <typename R, int MEQN>
 __global__ void __launch_bounds__(256)
 k_tag_family(const R* __restrict__ q, const PatchRec* __restrict__ rec,
              const int32_t* __restrict__ family, int m, int criterion,
-             double thr, int lmin, int8_t* __restrict__ tags) {
+             double thr, int lmin, int8_t* __restrict__ tags,
+             const double* __restrict__ geo) {
 #pragma clang fp contract(off)
-  extern __shared__ double par[];          // m * m averaged parent values
+  // m * m averaged parent values, then (sphere) their 3 m * m centres
+  extern __shared__ double par[];
+  double* pc = par + m * m;
   __shared__ double rlo[4], rhi[4];
   __shared__ int rflag[4];
   const int p = blockIdx.x, tid = threadIdx.x;
@@ -328,12 +345,32 @@ k_tag_family(const R* __restrict__ q, const PatchRec* __restrict__ rec,
     const int kid = p + ((I - 1) >= h) + 2 * ((J - 1) >= h);
     const int ii = 2 * ((I - 1) % h) + 1, jj = 2 * ((J - 1) % h) + 1;
     const R* b = q + size_t(kid * MEQN) * m * m;
-    double acc = 0.0;
-    acc = acc + double(b[size_t(jj - 1) * m + (ii - 1)]);
-    acc = acc + double(b[size_t(jj - 1) * m + ii]);
-    acc = acc + double(b[size_t(jj) * m + (ii - 1)]);
-    acc = acc + double(b[size_t(jj) * m + ii]);
-    par[c] = acc / 4.0;
+    if (geo) {
+      double acc = 0.0, w = 0.0, r[3] = {0.0, 0.0, 0.0};
+      for (int e = 0; e < 4; ++e) {
+        const int i2 = ii + (e & 1), j2 = jj + (e >> 1);
+        const double kap = geo_kappa(geo, m, kid, i2, j2);
+        acc = acc + kap * double(b[size_t(j2 - 1) * m + (i2 - 1)]);
+        w = w + kap;
+        double rc[3];
+        geo_centre(geo, m, kid, i2, j2, rc);
+        r[0] = r[0] + rc[0];
+        r[1] = r[1] + rc[1];
+        r[2] = r[2] + rc[2];
+      }
+      par[c] = acc / w;
+      const double nr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+      pc[3 * c] = r[0] / nr;
+      pc[3 * c + 1] = r[1] / nr;
+      pc[3 * c + 2] = r[2] / nr;
+    } else {
+      double acc = 0.0;
+      acc = acc + double(b[size_t(jj - 1) * m + (ii - 1)]);
+      acc = acc + double(b[size_t(jj - 1) * m + ii]);
+      acc = acc + double(b[size_t(jj) * m + (ii - 1)]);
+      acc = acc + double(b[size_t(jj) * m + ii]);
+      par[c] = acc / 4.0;
+    }
   }
   __syncthreads();
   const double dxp = ldexp(1.0, -(rec[p].level - 1)) / m;
@@ -347,10 +384,13 @@ k_tag_family(const R* __restrict__ q, const PatchRec* __restrict__ rec,
     if (criterion == 1) {
       const int ia = I > 1 ? I - 1 : I, ib = I < m ? I + 1 : I;
       const int ja = J > 1 ? J - 1 : J, jb = J < m ? J + 1 : J;
-      const double gx = (par[(J - 1) * m + (ib - 1)] - par[(J - 1) * m + (ia - 1)]) /
-                        (double(ib - ia) * dxp);
-      const double gy = (par[(jb - 1) * m + (I - 1)] - par[(ja - 1) * m + (I - 1)]) /
-                        (double(jb - ja) * dxp);
+      double sx = double(ib - ia) * dxp, sy = double(jb - ja) * dxp;
+      if (geo) {
+        sx = arc_between(&pc[3 * ((J - 1) * m + (ia - 1))], &pc[3 * ((J - 1) * m + (ib - 1))]);
+        sy = arc_between(&pc[3 * ((ja - 1) * m + (I - 1))], &pc[3 * ((jb - 1) * m + (I - 1))]);
+      }
+      const double gx = (par[(J - 1) * m + (ib - 1)] - par[(J - 1) * m + (ia - 1)]) / sx;
+      const double gy = (par[(jb - 1) * m + (I - 1)] - par[(ja - 1) * m + (I - 1)]) / sy;
       double s = gx * gx;
       s = s + gy * gy;
       if (s > t2) flag = 1;
@@ -418,6 +458,74 @@ k_transfer(const R* __restrict__ qo, const R* __restrict__ go,
          oval(kid, ii + 1, jj + 1)) / R(4);
   }
   qn[size_t(p) * per + rem] = v;
+}
+
+// Regrid transfer on the cubed sphere: one thread per (new patch, component,
+// 2 x 2 block of cells).  A merged cell is the capacity-weighted average of
+// its four old cells; the four children of a refined cell are interpolated as
+// on the plane (limited slopes) and then shifted by one common amount so that
+// their capacity-weighted sum equals the old cell's content (a coarse cell
+// has four times a child's computational area).  Arithmetic in FP64.
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_transfer_sphere(const R* __restrict__ qo, const R* __restrict__ go,
+                  R* __restrict__ qn, const PatchRec* __restrict__ rec_new,
+                  const int32_t* __restrict__ kind, const int32_t* __restrict__ src,
+                  const double* __restrict__ geo_old, const double* __restrict__ geo_new,
+                  int32_t P, int m) {
+#pragma clang fp contract(off)
+  constexpr int MEQN = 4;
+  const int hb = m / 2, nb = hb * hb;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(P) * MEQN * nb) return;
+  const int p = int(t / (MEQN * nb));
+  const int rem = int(t - int64_t(p) * MEQN * nb);
+  const int k = rem / nb, b = rem % nb;
+  const int i0 = 2 * (b % hb) + 1, j0 = 2 * (b / hb) + 1;
+  const int s = src[p];
+  const int G = 8 * m + 16;
+  auto oval = [&](int pp, int ii, int jj) -> double {
+    if (ii >= 1 && ii <= m && jj >= 1 && jj <= m)
+      return double(qo[(size_t(pp * MEQN + k) * m + (jj - 1)) * m + (ii - 1)]);
+    return double(go[size_t(pp * MEQN + k) * G + ghost_index(m, ii, jj)]);
+  };
+  double v[4];
+  if (kind[p] == 0) {
+    for (int c = 0; c < 4; ++c) v[c] = oval(s, i0 + (c & 1), j0 + (c >> 1));
+  } else if (kind[p] == 1) {
+    const int cx = rec_new[p].ix & 1, cy = rec_new[p].iy & 1;
+    const int ic = cx * hb + (i0 - 1) / 2 + 1, jc = cy * hb + (j0 - 1) / 2 + 1;
+    const double qc = oval(s, ic, jc);
+    const double sx = minmod(oval(s, ic + 1, jc) - qc, qc - oval(s, ic - 1, jc));
+    const double sy = minmod(oval(s, ic, jc + 1) - qc, qc - oval(s, ic, jc - 1));
+    double ksum = 0.0, qsum = 0.0;
+    for (int c = 0; c < 4; ++c) {
+      const double dx = (c & 1) ? 0.25 : -0.25, dy = (c >> 1) ? 0.25 : -0.25;
+      v[c] = qc + dx * sx + dy * sy;
+      const double kf = geo_kappa(geo_new, m, p, i0 + (c & 1), j0 + (c >> 1));
+      ksum = ksum + kf;
+      qsum = qsum + kf * v[c];
+    }
+    const double kc = geo_kappa(geo_old, m, s, ic, jc);
+    const double shift = (4.0 * kc * qc - qsum) / ksum;
+    for (int c = 0; c < 4; ++c) v[c] = v[c] + shift;
+  } else {
+    for (int c = 0; c < 4; ++c) {
+      const int i = i0 + (c & 1), j = j0 + (c >> 1);
+      const int kid = s + ((i - 1) >= hb) + 2 * ((j - 1) >= hb);
+      const int ii = 2 * ((i - 1) % hb) + 1, jj = 2 * ((j - 1) % hb) + 1;
+      double acc = 0.0, w = 0.0;
+      for (int e = 0; e < 4; ++e) {
+        const int i2 = ii + (e & 1), j2 = jj + (e >> 1);
+        const double kap = geo_kappa(geo_old, m, kid, i2, j2);
+        acc = acc + kap * oval(kid, i2, j2);
+        w = w + kap;
+      }
+      v[c] = acc / w;
+    }
+  }
+  for (int c = 0; c < 4; ++c)
+    qn[(size_t(p * MEQN + k) * m + (j0 - 1 + (c >> 1))) * m + (i0 - 1 + (c & 1))] = R(v[c]);
 }
 
 }  // namespace fcx

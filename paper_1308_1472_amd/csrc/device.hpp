@@ -86,6 +86,27 @@ __device__ __forceinline__ double geo_kappa(const double* geo, int m, int p, int
   return geo[size_t(p) * 18 * FR + (j + 1) * (m + 4) + (i + 1)];
 }
 
+// centre (unit vector) of frame cell (i, j) of patch p from a sphere
+// geometry table (frames 1-3 hold the three coordinates of each cell in turn)
+__device__ __forceinline__ void geo_centre(const double* geo, int m, int p, int i, int j,
+                                           double r[3]) {
+  const int FR = (m + 4) * (m + 4);
+  const double* c = geo + size_t(p) * 18 * FR + FR + 3 * ((j + 1) * (m + 4) + (i + 1));
+  r[0] = c[0];
+  r[1] = c[1];
+  r[2] = c[2];
+}
+
+// great-circle angle between unit vectors a and b, as atan2(|a x b|, a . b)
+__device__ __forceinline__ double arc_between(const double a[3], const double b[3]) {
+#pragma clang fp contract(off)
+  const double c0 = a[1] * b[2] - a[2] * b[1];
+  const double c1 = a[2] * b[0] - a[0] * b[2];
+  const double c2 = a[0] * b[1] - a[1] * b[0];
+  const double dot = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+  return atan2(sqrt(c0 * c0 + c1 * c1 + c2 * c2), dot);
+}
+
 // The leaf that holds the centre of non-interior, non-wall frame cell (i, j)
 // of patch p, and that centre in the leaf's tree coordinates.  Returns the
 // leaf id, or kNbrValence3.

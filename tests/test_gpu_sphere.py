@@ -1,7 +1,9 @@
 """GPU parity of the cubed-sphere path against the CPU oracle: geometry
 tables, ghost fill with capacity-weighted averages, the rotated-Roe step
 with reflux and cube-edge mass sync (FP64 to 1e-12, FP32 to 1e-5 in relative
-L1), exact mass conservation and the lake at rest."""
+L1), exact mass conservation and the lake at rest; refinement tags, regrid
+with the conservative capacity-weighted transfer, and the run loop with
+regrids."""
 import numpy as np
 import pytest
 
@@ -166,3 +168,139 @@ def test_unsupported_sphere_calls_fail_loudly():
         ctx.fused_step(q, torch.zeros_like(q), dt, torch.zeros_like(dt))
     with pytest.raises(fcx.FcxError):
         fcx.Batch([ctx])
+
+
+def _gap_thresholds(values, squared):
+    """Two thresholds in the widest relative gaps between distinct criterion
+    values (lower and upper half), so that no decision sits within rounding
+    of a threshold; values at rounding-noise level (flat water) are left
+    out of the search."""
+    v = values[np.isfinite(values)]
+    v = np.unique(v[v > 1e-8 * v.max()])
+    out = []
+    for lo, hi in ((0.15, 0.5), (0.5, 0.85)):
+        a, b = int(lo * (len(v) - 1)), int(hi * (len(v) - 1))
+        r = v[a + 1:b + 1] / v[a:b]
+        k = a + int(np.argmax(r))
+        t = np.sqrt(v[k] * v[k + 1])
+        assert v[k + 1] / v[k] > 1 + 1e-6
+        out.append(np.sqrt(t) if squared else t)
+    return out
+
+
+def _sphere_state(lv, seed):
+    q = I.sphere_bump(lv, M) + I.sphere_bump(lv, M, lat=0.3, lon=2.0, amp=0.2)
+    rng = np.random.default_rng(seed)
+    q[:, 1:] = 0.05 * rng.normal(size=q[:, 1:].shape)
+    return q
+
+
+def test_regrid_tags_match_oracle():
+    say("[sphere] tags")
+    trees, lv = _forest(7, 1, 3, 14)
+    cfg = fcx.config(M, 64, fcx.FCX_SPHERE)
+    q = _sphere_state(lv, 1)
+    g = Gpu(cfg, trees, lv)
+    g.set_state(q)
+    mesh = O.Mesh(trees, lv, M, sphere=True)
+    par = oracle_params(cfg)
+    f = O.framed(q, M)
+    O.ghost_fill(mesh, par, f)
+    seen = set()
+    for crit in (1, 0):
+        ref, parent = O.tag_values(mesh, par, f, crit)
+        for thr in _gap_thresholds(np.concatenate([ref, parent]), crit == 1):
+            got = g.tags(crit, thr, 1, 4)
+            want = O.tags(mesh, par, f, crit, thr, 1, 4)
+            assert np.array_equal(got, want), (crit, thr)
+            seen.update(np.unique(want).tolist())
+    assert seen == {-1, 0, 1}
+
+
+def test_regrid_transfer_matches_oracle_and_conserves_mass():
+    say("[sphere] regrid transfer")
+    import torch
+    trees, lv = _forest(11, 1, 3, 14)
+    cfg = fcx.config(M, 64, fcx.FCX_SPHERE)
+    q = _sphere_state(lv, 2)
+    rng = np.random.default_rng(4)
+    tg = rng.integers(-1, 2, len(lv)).astype(np.int8)
+    g = Gpu(cfg, trees, lv)
+    g.set_state(q)
+    sums = torch.zeros(4, dtype=torch.float64, device="cuda")
+    g.ctx.conservation_sums(g.q, sums)
+    before = sums.cpu().numpy().copy()
+    g.regrid(tg, 1, 4)
+    g.ctx.conservation_sums(g.q, sums)
+    after = sums.cpu().numpy()
+    mesh = O.Mesh(trees, lv, M, sphere=True)
+    par = oracle_params(cfg)
+    f = O.framed(q, M)
+    O.ghost_fill(mesh, par, f)
+    lv2 = O.regrid(mesh, tg, 1, 4)
+    assert np.array_equal(g.ctx.leaves(), lv2)
+    assert len(lv2) != len(lv)
+    want = O.interior(O.transfer(mesh, O.Mesh(trees, lv2, M, sphere=True), par, f), M)
+    got = g.state()
+    assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    assert abs(after[0] - before[0]) <= 1e-13 * abs(before[0])
+
+
+def test_run_loop_with_regrids_equals_single_calls():
+    """fcx_run on the sphere (plain steps, a criterion regrid every 2 steps)
+    gives bit for bit the forest, state and dt of the same single calls, and
+    keeps the mass to rounding."""
+    import torch
+    say("[sphere] run loop")
+    trees, lv = _forest(13, 1, 3, 10)
+    lmin, lmax, steps, every, thr = 1, 4, 7, 2, 0.6
+    cfg = fcx.config(M, 64, fcx.FCX_SPHERE)
+    q0 = _sphere_state(lv, 3)
+    dt0 = 0.2 * (np.pi / 2) / (M << lmax)
+
+    def fresh():
+        ctx = fcx.Context(cfg, trees)
+        ctx.upload_forest(lv)
+        dt = torch.full((1,), dt0, dtype=torch.float64, device="cuda")
+        return ctx, dt, torch.zeros_like(dt), torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    ctx, dt, nu, st = fresh()
+    q = torch.from_numpy(q0.ravel().copy()).cuda()
+    sums = torch.zeros(4, dtype=torch.float64, device="cuda")
+    ctx.conservation_sums(q, sums)
+    mass0 = sums[0].item()
+    regrids = 0
+    for n in range(steps):
+        if n > 0 and n % every == 0:
+            gh = torch.empty(ctx.ghost_elems(), dtype=torch.float64, device="cuda")
+            before = ctx.num_patches()
+            ctx.regrid(q, gh, 1, thr, lmin, lmax)
+            regrids += ctx.num_patches() != before
+            q2 = torch.empty(ctx.state_elems(), dtype=torch.float64, device="cuda")
+            ctx.regrid_transfer(q, gh, q2)
+            q = q2
+        qn = torch.empty_like(q)
+        gh = torch.empty(ctx.ghost_elems(), dtype=torch.float64, device="cuda")
+        ctx.ghost_fill(q, gh)
+        ctx.patch_step(q, gh, qn, dt, nu)
+        ctx.reflux(q, qn, dt)
+        ctx.next_dt(nu, dt, st)
+        q = qn
+    assert regrids > 0
+    want, want_lv, want_dt = q.cpu().numpy(), ctx.leaves(), dt.item()
+    ctx.conservation_sums(q, sums)
+    assert abs(sums[0].item() - mass0) <= 1e-12 * abs(mass0)
+    ctx, dt, nu, st = fresh()
+    cap = 6 * (1 << (2 * lmax)) * 4 * M * M
+    bufs = [torch.empty(cap, dtype=torch.float64, device="cuda") for _ in range(2)]
+    bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
+    ghost = torch.empty(6 * (1 << (2 * lmax)) * 4 * (8 * M + 16), dtype=torch.float64,
+                        device="cuda")
+    which, cells = ctx.run(bufs[0], bufs[1], ghost, steps, 0, every, 1, thr, lmin, lmax,
+                           dt, nu, st, fused=False)
+    got = bufs[which][:ctx.state_elems()].cpu().numpy()
+    assert np.array_equal(ctx.leaves(), want_lv)
+    assert np.array_equal(got, want) and dt.item() == want_dt
+    with pytest.raises(fcx.FcxError):
+        ctx.run(bufs[which], bufs[1 - which], ghost, 1, steps, 0, 1, thr, lmin, lmax,
+                dt, nu, st, fused=True)
