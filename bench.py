@@ -265,47 +265,86 @@ def run_batch(steps, warmup, nforests=64, graph_steps=10):
             "bytes_per_step": step_bytes}
 
 
-def run_sphere(steps, precision=32, level=4, m=16):
-    """Cubed sphere: 6 trees uniform at `level`, m x m patches, a Gaussian
-    height bump on h = 1 at rest, plain path (ghost fill + step + reflux with
-    cube-edge mass sync), fixed dt."""
+def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000):
+    """Shallow water on the cubed sphere, adaptive: 6 trees, levels lmin..lmax,
+    m x m patches, a seeded sum of Gaussian height bumps on h = 1 at rest.
+    The initial mesh refines uniform level lmin by lmax - lmin regrids (|grad h|
+    criterion, data carried by the regrid transfer); the threshold is set by
+    bisection so that this mesh has target patches within 20 %.  Timed: the
+    library's run loop with plain steps (ghost fill, step, reflux with
+    cube-edge mass sync, next dt) and a regrid every `every` steps."""
+    import math
     import numpy as np
     import torch
     from paper_1308_1472_amd import fcx
     from paper_1308_1472_amd import inputs as I
     trees = I.cubed_sphere()
-    lv = fcx.sfc_sort(I.uniform_leaves(6, level))
-    ctx = fcx.Context(fcx.config(m, precision, fcx.FCX_SPHERE), trees)
-    ctx.upload_forest(lv)
+    lv0 = fcx.sfc_sort(I.uniform_leaves(6, lmin))
+    cfg = fcx.config(m, precision, fcx.FCX_SPHERE, cfl_desired=0.8, cfl_max=1.0)
     dtype = torch.float32 if precision == 32 else torch.float64
-    q = torch.from_numpy(I.sphere_bump(lv, m).ravel()).to(dtype).cuda()
-    qn = torch.empty_like(q)
-    ghost = torch.empty(ctx.ghost_elems(), dtype=dtype, device="cuda")
-    dt = torch.full((1,), 0.3 * (np.pi / 2) / (m << level), dtype=torch.float64,
+    q0 = torch.from_numpy(I.sphere_bumps(lv0, m).ravel()).to(dtype).cuda()
+    maxp = 6 << (2 * lmax)
+    cap = maxp * 4 * m * m
+    bufs = [torch.empty(cap, dtype=dtype, device="cuda") for _ in range(2)]
+    ghost = torch.empty(maxp * 4 * (8 * m + 16), dtype=dtype, device="cuda")
+
+    def initial(thr):
+        ctx = fcx.Context(cfg, trees)
+        ctx.upload_forest(lv0)
+        bufs[0][:q0.numel()].copy_(q0)
+        cur = 0
+        for _ in range(lmax - lmin):
+            n = ctx.state_elems()
+            ctx.regrid(bufs[cur][:n], ghost[:ctx.ghost_elems()], 1, thr, lmin, lmax)
+            ctx.regrid_transfer(bufs[cur][:n], ghost, bufs[1 - cur][:ctx.state_elems()])
+            cur = 1 - cur
+        torch.cuda.synchronize()
+        return ctx, cur
+
+    lo, hi = math.log(1e-4), math.log(10.0)
+    best = None
+    for _ in range(24):
+        mid = 0.5 * (lo + hi)
+        ctx, cur = initial(math.exp(mid))
+        P = ctx.num_patches()
+        if best is None or abs(P - target) < abs(best[1] - target):
+            best = (math.exp(mid), P)
+        if abs(P - target) <= 0.05 * target:
+            break
+        if P > target:
+            lo = mid          # too many patches: raise the threshold
+        else:
+            hi = mid
+    thr = best[0]
+    ctx, cur = initial(thr)
+    P0 = ctx.num_patches()
+    dt = torch.full((1,), 0.3 * (math.pi / 2) / (m << lmax), dtype=torch.float64,
                     device="cuda")
     nu = torch.zeros(1, dtype=torch.float64, device="cuda")
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
     sums = torch.zeros(4, dtype=torch.float64, device="cuda")
-    ctx.conservation_sums(q, sums)
+    ctx.conservation_sums(bufs[cur][:ctx.state_elems()], sums)
     m0 = sums[0].item()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    for k in range(steps + 3):
-        if k == 3:
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            ev[0].record()
-        ctx.ghost_fill(q, ghost)
-        ctx.patch_step(q, ghost, qn, dt, nu)
-        ctx.reflux(q, qn, dt)
-        q, qn = qn, q
-    ev[1].record()
+    q_a, q_b = bufs[cur], bufs[1 - cur]
+    # warm-up: a few steps and one regrid, outside the timed region
+    which, _ = ctx.run(q_a, q_b, ghost, every + 1, 0, every, 1, thr, lmin, lmax, dt, nu,
+                       st, fused=False)
+    if which == 1:
+        q_a, q_b = q_b, q_a
+    st.zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    which, cells = ctx.run(q_a, q_b, ghost, steps, every + 1, every, 1, thr, lmin, lmax,
+                           dt, nu, st, fused=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ctx.conservation_sums(q, sums)
-    cells = len(lv) * m * m
-    return {"patches": len(lv), "cells": cells, "steps": steps,
-            "rate": cells * steps / el, "ms_per_step": ev[0].elapsed_time(ev[1]) / steps,
-            "mass_rel_change": sums[0].item() / m0 - 1.0,
-            "nu_last": nu.item()}
+    q_end = (q_b if which == 1 else q_a)[:ctx.state_elems()]
+    ctx.conservation_sums(q_end, sums)
+    return {"threshold": thr, "patches_initial": P0, "patches_last": ctx.num_patches(),
+            "steps": steps, "regrid_every": every, "cells": cells,
+            "rate": cells / el, "ms_per_step": el / steps * 1e3,
+            "mass_rel_change": sums[0].item() / m0 - 1.0, "status": int(st.item()),
+            "dt": dt.item()}
 
 
 def run_mlp(rows=50000, reps=50):

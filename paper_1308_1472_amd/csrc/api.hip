@@ -133,8 +133,8 @@ struct fcx_ctx {
   DevBuf<int32_t> err;
   DevBuf<uint32_t> ticket;         // last-workgroup ticket of the reflux
   HostBuf staging;
-  DevBuf<uint8_t> sscratch;        // sphere step: per-workgroup edge data
   int cus = 256;
+  size_t lds_per_block = 65536;    // device limit of LDS per workgroup
   Plan plan;                       // host copy of the current forest's plan
   Plan spare;                      // the previous one, its storage reused
   DevBuf<int8_t> tags_dev;         // fcx_regrid: tags on the device
@@ -271,6 +271,8 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   }
   if (cfg->physics == FCX_SPHERE && !cube_connectivity(t))
     return fail(FCX_EINVAL, "the sphere needs the six cube faces glued as the cube");
+  if (cfg->physics == FCX_SPHERE && cfg->m % kSphereTile != 0)
+    return fail(FCX_EINVAL, "the sphere needs m a multiple of 8");
   fcx_ctx* c = new fcx_ctx;
   c->cfg = *cfg;
   c->cfg.tile = tile;
@@ -281,8 +283,10 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
     int dev = 0;
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess &&
-        hipGetDeviceProperties(&prop, dev) == hipSuccess)
+        hipGetDeviceProperties(&prop, dev) == hipSuccess) {
       c->cus = prop.multiProcessorCount;
+      c->lds_per_block = prop.sharedMemPerBlock;
+    }
   }
   c->trees = t;
   if (c->err.ensure(1) != hipSuccess || c->ticket.ensure(1) != hipSuccess) {
@@ -412,8 +416,6 @@ static int finish_upload(fcx_ctx* c, hipStream_t s = nullptr, bool ordered = fal
     hipLaunchKernelGGL(k_sphere_metrics, dim3(unsigned(P)), dim3(256), lds, s,
                        c->cur.rec, m, log2i(m), c->cur.geo.p);
     HIPCHK(hipGetLastError());
-    const int slots = int(std::min<int64_t>(P, int64_t(c->cus) * 2));
-    HIPCHK(c->sscratch.ensure(size_t(slots) * sphere_scratch(m) * esz));
     if (!ordered) HIPCHK(hipDeviceSynchronize());
   }
   return FCX_OK;
@@ -532,6 +534,9 @@ static int launch_step_m(fcx_ctx* c, const void* q, const void* ghost, void* qn,
 template <typename R>
 static int launch_sphere_step(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                               const double* dt, double* numax, hipStream_t s) {
+  const size_t lds = sphere_lds<R>();
+  if (lds > c->lds_per_block)
+    return fail(FCX_EINVAL, "sphere step tile does not fit this device's LDS");
   SphereArgs<R> a;
   a.q = static_cast<const R*>(q);
   a.ghost = static_cast<const R*>(ghost);
@@ -543,17 +548,16 @@ static int launch_sphere_step(fcx_ctx* c, const void* q, const void* ghost, void
   a.phi = reinterpret_cast<R*>(c->phi.p);
   a.err = c->err.p;
   a.geo = c->cur.geo.p;
-  a.scratch = reinterpret_cast<R*>(c->sscratch.p);
   a.P = int32_t(c->cur.P);
   a.m = c->cfg.m;
   a.lm = log2i(c->cfg.m);
   a.limiter = c->cfg.limiter;
   a.transverse = c->cfg.transverse;
   a.g = c->cfg.g;
-  const int FR = (a.m + 4) * (a.m + 4);
-  const size_t lds = sizeof(R) * 4 * FR + sizeof(double) * FR;
-  const int slots = int(std::min<int64_t>(c->cur.P, int64_t(c->cus) * 2));
-  hipLaunchKernelGGL((k_sphere_step<R>), dim3(unsigned(slots)), dim3(256), lds, s, a);
+  const int tps = a.m / kSphereTile;
+  const int64_t grid = c->cur.P * tps * tps;
+  hipLaunchKernelGGL((k_sphere_step<R>), dim3(unsigned(grid)), dim3(kSphereThreads), lds, s,
+                     a);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }

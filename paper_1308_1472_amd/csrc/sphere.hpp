@@ -270,205 +270,238 @@ struct SphereArgs {
   R* phi;
   int32_t* err;
   const double* __restrict__ geo;
-  R* scratch;                    // per workgroup: sphere_scratch(m) elements
   int P, m, lm, limiter, transverse;
   double g;
 };
 
-// scratch per direction and edge (e, r) -> e (m+2) + r:
-//   W 12, S 3, AM 4, AP 4, FL 1, FO 4 (own correction), T 16 (transverse
-//   parts [side][lo/hi][k], already scaled by -dt/(2 kappa dx))
-constexpr int kSEw = 0, kSEs = 12, kSEam = 15, kSEap = 19, kSEfl = 23, kSEfo = 24,
-              kSEt = 28, kSEn = 44;
-__host__ __device__ inline size_t sphere_scratch(int m) {
-  return size_t(2) * (m + 3) * (m + 2) * kSEn;
+// Edge records of one tile, per direction and edge (e, r) -> e (T+2) + r:
+//   W 12 and S 3 (waves and speeds, until every limiter has read them), then
+//   in their place T 16 (transverse parts [side][lo/hi][k], already scaled
+//   by -dt/(2 kappa dx)); AM 4, AP 4, FL 1, CQ 4 (limited correction; the
+//   edge's own correction flux is half of it)
+constexpr int kSEw = 0, kSEs = 12, kSEt = 0, kSEam = 16, kSEap = 20, kSEfl = 24,
+              kSEcq = 25, kSEn = 29;
+// the step works on T x T tiles of a patch, one workgroup each
+constexpr int kSphereTile = 8, kSphereThreads = 256;
+// LDS of one tile: the state with its 2-cell halo, the capacities, and the
+// edge records of both directions
+template <typename R>
+__host__ __device__ constexpr size_t sphere_lds() {
+  return sizeof(R) * 4 * (kSphereTile + 4) * (kSphereTile + 4) +
+         sizeof(double) * (kSphereTile + 4) * (kSphereTile + 4) +
+         sizeof(R) * 2 * (kSphereTile + 3) * (kSphereTile + 2) * kSEn;
 }
 
+// One workgroup per T x T tile of a patch: phase 1 solves the rotated Roe
+// problem at every edge of the tile and its halo rows, phase 2 forms the
+// limited corrections and then the transverse parts, phase 3 gathers each
+// cell's update in a fixed order, projects the momentum and writes the face
+// terms.
+// Everything between the staged input and the output stays in LDS.
 template <typename R>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(kSphereThreads)
 k_sphere_step(SphereArgs<R> A) {
+  constexpr int T = kSphereTile, FT = T + 4, FRT = FT * FT, M2 = T + 2,
+                NE = (T + 3) * (T + 2);
   extern __shared__ unsigned char smem_raw[];
-  const int m = A.m, FR = (m + 4) * (m + 4), M2 = m + 2, NE = (m + 3) * (m + 2);
-  R* Qs = reinterpret_cast<R*>(smem_raw);                    // [4][FR]
-  // 4 FR R values (a multiple of 8 bytes), then FR capacities
-  double* kap = reinterpret_cast<double*>(smem_raw + sizeof(R) * 4 * FR);
-  __shared__ double red[4];
-  R* scr = A.scratch + size_t(blockIdx.x) * sphere_scratch(m);
+  R* Qs = reinterpret_cast<R*>(smem_raw);                                  // [4][FRT]
+  double* kap = reinterpret_cast<double*>(smem_raw + sizeof(R) * 4 * FRT);  // [FRT]
+  R* scr = reinterpret_cast<R*>(smem_raw + sizeof(R) * 4 * FRT + sizeof(double) * FRT);
+  __shared__ double red[kSphereThreads / 64];
   auto E = [&](int d, int e, int r) { return scr + (size_t(d) * NE + size_t(e) * M2 + r) * kSEn; };
   auto cell_i = [](int d, int n, int r) { return d == 0 ? n : r; };
   auto cell_j = [](int d, int n, int r) { return d == 0 ? r : n; };
+  auto lf = [](int i, int j) { return (j + 1) * FT + (i + 1); };   // tile frame
+  const int m = A.m, FR = (m + 4) * (m + 4);
   const double dt = *A.dt;
   const R grav = R(A.g);
   const int G = 8 * m + 16;
-  for (int p = blockIdx.x; p < A.P; p += gridDim.x) {
-    const PatchRec& rp = A.rec[p];
-    const double dx = ldexp(1.0, -rp.level) / m;
-    const double* geo = A.geo + size_t(p) * kGeoN * FR;
-    __syncthreads();
-    for (int f = threadIdx.x; f < FR; f += blockDim.x) {
-      const int i = f % (m + 4) - 1, j = f / (m + 4) - 1;
-      const bool outer = (i == -1 || i == m + 2) && (j == -1 || j == m + 2);
-      for (int k = 0; k < 4; ++k) {
-        R v;
-        if (i >= 1 && i <= m && j >= 1 && j <= m)
-          v = A.q[(size_t(p * 4 + k) * m + (j - 1)) * m + (i - 1)];
-        else
-          v = outer ? R(0) : A.ghost[size_t(p * 4 + k) * G + ghost_index(m, i, j)];
-        Qs[k * FR + f] = v;
-      }
-      kap[f] = geo[kGeoK * FR + f];
+  const int tps = m / T;
+  const int p = blockIdx.x / (tps * tps), tile = blockIdx.x - p * (tps * tps);
+  const int i0 = (tile % tps) * T, j0 = (tile / tps) * T;
+  auto pf = [&](int i, int j) { return fidx(m, i0 + i, j0 + j); };  // patch frame
+  const PatchRec& rp = A.rec[p];
+  const double dx = ldexp(1.0, -rp.level) / m;
+  const double* geo = A.geo + size_t(p) * kGeoN * FR;
+  for (int f = threadIdx.x; f < FRT; f += blockDim.x) {
+    const int i = i0 + f % FT - 1, j = j0 + f / FT - 1;
+    const bool outer = (i == -1 || i == m + 2) && (j == -1 || j == m + 2);
+    for (int k = 0; k < 4; ++k) {
+      R v;
+      if (i >= 1 && i <= m && j >= 1 && j <= m)
+        v = A.q[(size_t(p * 4 + k) * m + (j - 1)) * m + (i - 1)];
+      else
+        v = outer ? R(0) : A.ghost[size_t(p * 4 + k) * G + ghost_index(m, i, j)];
+      Qs[k * FRT + f] = v;
     }
-    __syncthreads();
-    // phase 1: Riemann problems at every edge of rows 0..m+1, both directions
-    double nmax = 0.0;
-    for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
-      const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
-      const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
-      const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
-      R ql[4], qr[4];
-      for (int k = 0; k < 4; ++k) {
-        ql[k] = Qs[k * FR + fidx(m, il, jl)];
-        qr[k] = Qs[k * FR + fidx(m, ir, jr)];
+    kap[f] = geo[kGeoK * FR + fidx(m, i, j)];
+  }
+  __syncthreads();
+  // phase 1: Riemann problems at every edge of rows 0..T+1, both directions
+  double nmax = 0.0;
+  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+    const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
+    const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
+    R ql[4], qr[4];
+    for (int k = 0; k < 4; ++k) {
+      ql[k] = Qs[k * FRT + lf(il, jl)];
+      qr[k] = Qs[k * FRT + lf(ir, jr)];
+    }
+    const SEdge<R> eg = load_edge<R>(geo + kGeoE * FR + (d * FR + pf(ir, jr)) * 7);
+    R* o = E(d, e, r);
+    R W[3][4], s[3], am[4], ap[4], fl;
+    if (!rp_sphere<R>(grav, eg, ql, qr, W, s, am, ap, fl)) {
+      atomicOr(A.err, kErrNegDepth);
+      for (int w = 0; w < 3; ++w) { s[w] = R(0); for (int k = 0; k < 4; ++k) W[w][k] = R(0); }
+      for (int k = 0; k < 4; ++k) am[k] = ap[k] = R(0);
+      fl = R(0);
+    }
+    for (int w = 0; w < 3; ++w) {
+      for (int k = 0; k < 4; ++k) o[kSEw + 4 * w + k] = W[w][k];
+      o[kSEs + w] = s[w];
+    }
+    for (int k = 0; k < 4; ++k) { o[kSEam + k] = am[k]; o[kSEap + k] = ap[k]; }
+    o[kSEfl] = fl;
+    if (r >= 1 && r <= T) {
+      const double dtdl = dt / (kap[lf(il, jl)] * dx), dtdr = dt / (kap[lf(ir, jr)] * dx);
+      for (int w = 0; w < 3; ++w) {
+        nmax = fmax(nmax, dtdr * fmax(double(s[w]), 0.0));
+        nmax = fmax(nmax, dtdl * fmax(-double(s[w]), 0.0));
       }
-      const SEdge<R> eg = load_edge<R>(geo + kGeoE * FR + (d * FR + fidx(m, ir, jr)) * 7);
-      R* o = E(d, e, r);
-      R W[3][4], s[3], am[4], ap[4], fl;
-      if (!rp_sphere<R>(grav, eg, ql, qr, W, s, am, ap, fl)) {
+    }
+  }
+  __syncthreads();
+  // phase 2: limited corrections at edges 1..T+1 (reads the waves of the
+  // upwind edges) ...
+  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+    if (e < 1 || e > T + 1) continue;
+    const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
+    const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
+    const double dtdl = dt / (kap[lf(il, jl)] * dx), dtdr = dt / (kap[lf(ir, jr)] * dx);
+    const R nu = R(0.5 * (dtdl + dtdr));
+    R* o = E(d, e, r);
+    R cq[4] = {R(0), R(0), R(0), R(0)};
+    for (int w = 0; w < 3; ++w) {
+      const R* Wc = o + kSEw + 4 * w;
+      const R sw = o[kSEs + w];
+      R wn2 = R(0);
+      for (int k = 0; k < 4; ++k) wn2 += Wc[k] * Wc[k];
+      if (wn2 == R(0)) continue;
+      const R* Wu = E(d, sw > R(0) ? e - 1 : e + 1, r) + kSEw + 4 * w;
+      R dot = R(0);
+      for (int k = 0; k < 4; ++k) dot += Wu[k] * Wc[k];
+      const R lim = limiter_phi<R>(A.limiter, dot / wn2);
+      const R as = fabs(sw);
+      for (int k = 0; k < 4; ++k) cq[k] += as * (R(1) - nu * as) * lim * Wc[k];
+    }
+    for (int k = 0; k < 4; ++k) o[kSEcq + k] = cq[k];
+  }
+  __syncthreads();
+  // ... then the transverse parts, written over the waves
+  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+    if (e < 1 || e > T + 1) continue;
+    R* o = E(d, e, r);
+    if (A.transverse == 0) {
+      for (int k = 0; k < 16; ++k) o[kSEt + k] = R(0);
+      continue;
+    }
+    const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
+    const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
+    const double dtdl = dt / (kap[lf(il, jl)] * dx), dtdr = dt / (kap[lf(ir, jr)] * dx);
+    R ql[4], qr[4], amt[4], apt[4];
+    for (int k = 0; k < 4; ++k) {
+      ql[k] = Qs[k * FRT + lf(il, jl)];
+      qr[k] = Qs[k * FRT + lf(ir, jr)];
+      const R c2 = A.transverse == 2 ? o[kSEcq + k] : R(0);
+      amt[k] = o[kSEam + k] + c2;
+      apt[k] = o[kSEap + k] - c2;
+    }
+    for (int side = 0; side < 2; ++side) {
+      const int col = side == 0 ? e - 1 : e;
+      const R h = R(-0.5 * (side == 0 ? dtdl : dtdr));
+      const int ci = cell_i(d, col, r), cj = cell_j(d, col, r);
+      const int ui = cell_i(d, col, r + 1), uj = cell_j(d, col, r + 1);
+      const SEdge<R> lo = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + pf(ci, cj)) * 7);
+      const SEdge<R> hi = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + pf(ui, uj)) * 7);
+      R bm[4], bp[4];
+      const R* psi = side == 0 ? amt : apt;
+      if (!tsplit_sphere<R>(grav, ql, qr, lo, psi, false, bm) ||
+          !tsplit_sphere<R>(grav, ql, qr, hi, psi, true, bp)) {
         atomicOr(A.err, kErrNegDepth);
-        for (int w = 0; w < 3; ++w) { s[w] = R(0); for (int k = 0; k < 4; ++k) W[w][k] = R(0); }
-        for (int k = 0; k < 4; ++k) am[k] = ap[k] = R(0);
-        fl = R(0);
+        for (int k = 0; k < 4; ++k) bm[k] = bp[k] = R(0);
       }
-      for (int w = 0; w < 3; ++w) {
-        for (int k = 0; k < 4; ++k) o[kSEw + 4 * w + k] = W[w][k];
-        o[kSEs + w] = s[w];
-      }
-      for (int k = 0; k < 4; ++k) { o[kSEam + k] = am[k]; o[kSEap + k] = ap[k]; }
-      o[kSEfl] = fl;
-      if (r >= 1 && r <= m) {
-        const double dtdl = dt / (kap[fidx(m, il, jl)] * dx), dtdr = dt / (kap[fidx(m, ir, jr)] * dx);
-        for (int w = 0; w < 3; ++w) {
-          nmax = fmax(nmax, dtdr * fmax(double(s[w]), 0.0));
-          nmax = fmax(nmax, dtdl * fmax(-double(s[w]), 0.0));
-        }
-      }
-    }
-    __syncthreads();
-    // phase 2: limited corrections and transverse parts at edges 1..m+1
-    for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
-      const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
-      if (e < 1 || e > m + 1) continue;
-      const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
-      const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
-      const double dtdl = dt / (kap[fidx(m, il, jl)] * dx), dtdr = dt / (kap[fidx(m, ir, jr)] * dx);
-      const R nu = R(0.5 * (dtdl + dtdr));
-      R* o = E(d, e, r);
-      R cq[4] = {R(0), R(0), R(0), R(0)};
-      for (int w = 0; w < 3; ++w) {
-        const R* Wc = o + kSEw + 4 * w;
-        const R sw = o[kSEs + w];
-        R wn2 = R(0);
-        for (int k = 0; k < 4; ++k) wn2 += Wc[k] * Wc[k];
-        if (wn2 == R(0)) continue;
-        const R* Wu = E(d, sw > R(0) ? e - 1 : e + 1, r) + kSEw + 4 * w;
-        R dot = R(0);
-        for (int k = 0; k < 4; ++k) dot += Wu[k] * Wc[k];
-        const R lim = limiter_phi<R>(A.limiter, dot / wn2);
-        const R as = fabs(sw);
-        for (int k = 0; k < 4; ++k) cq[k] += as * (R(1) - nu * as) * lim * Wc[k];
-      }
-      for (int k = 0; k < 4; ++k) o[kSEfo + k] = R(0.5) * cq[k];
-      if (A.transverse == 0) {
-        for (int k = 0; k < 16; ++k) o[kSEt + k] = R(0);
-        continue;
-      }
-      R ql[4], qr[4], amt[4], apt[4];
       for (int k = 0; k < 4; ++k) {
-        ql[k] = Qs[k * FR + fidx(m, il, jl)];
-        qr[k] = Qs[k * FR + fidx(m, ir, jr)];
-        const R c2 = A.transverse == 2 ? cq[k] : R(0);
-        amt[k] = o[kSEam + k] + c2;
-        apt[k] = o[kSEap + k] - c2;
-      }
-      for (int side = 0; side < 2; ++side) {
-        const int col = side == 0 ? e - 1 : e;
-        const R h = R(-0.5 * (side == 0 ? dtdl : dtdr));
-        const int ci = cell_i(d, col, r), cj = cell_j(d, col, r);
-        const int ui = cell_i(d, col, r + 1), uj = cell_j(d, col, r + 1);
-        const SEdge<R> lo = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + fidx(m, ci, cj)) * 7);
-        const SEdge<R> hi = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + fidx(m, ui, uj)) * 7);
-        R bm[4], bp[4];
-        const R* psi = side == 0 ? amt : apt;
-        if (!tsplit_sphere<R>(grav, ql, qr, lo, psi, false, bm) ||
-            !tsplit_sphere<R>(grav, ql, qr, hi, psi, true, bp)) {
-          atomicOr(A.err, kErrNegDepth);
-          for (int k = 0; k < 4; ++k) bm[k] = bp[k] = R(0);
-        }
-        for (int k = 0; k < 4; ++k) {
-          o[kSEt + (side * 2 + 0) * 4 + k] = h * bm[k];
-          o[kSEt + (side * 2 + 1) * 4 + k] = h * bp[k];
-        }
+        o[kSEt + (side * 2 + 0) * 4 + k] = h * bm[k];
+        o[kSEt + (side * 2 + 1) * 4 + k] = h * bp[k];
       }
     }
-    __syncthreads();
-    // phase 3: update of interior cells and face terms
-    // total correction flux of edge (e, r) in direction d: own part, then the
-    // transverse parts of the other sweep's edges
-    auto Ftot = [&](int d, int e, int r, int k) -> R {
-      const int o = 1 - d;
-      R v = E(d, e, r)[kSEfo + k];
-      v += E(o, r, e - 1)[kSEt + (1 * 2 + 1) * 4 + k];
-      v += E(o, r + 1, e - 1)[kSEt + (0 * 2 + 1) * 4 + k];
-      v += E(o, r, e)[kSEt + (1 * 2 + 0) * 4 + k];
-      v += E(o, r + 1, e)[kSEt + (0 * 2 + 0) * 4 + k];
-      return v;
-    };
-    for (int c = threadIdx.x; c < m * m; c += blockDim.x) {
-      const int i = c % m + 1, j = c / m + 1;
-      const int f = fidx(m, i, j);
-      const R dtd = R(dt / (kap[f] * dx));
-      R out[4];
-      for (int k = 0; k < 4; ++k) {
-        R fx, gy;
-        if (k == 0) {
-          fx = E(0, i + 1, j)[kSEfl] - E(0, i, j)[kSEfl];
-          gy = E(1, j + 1, i)[kSEfl] - E(1, j, i)[kSEfl];
-        } else {
-          fx = E(0, i, j)[kSEap + k] + E(0, i + 1, j)[kSEam + k];
-          gy = E(1, j, i)[kSEap + k] + E(1, j + 1, i)[kSEam + k];
-        }
-        fx = fx + (Ftot(0, i + 1, j, k) - Ftot(0, i, j, k));
-        gy = gy + (Ftot(1, j + 1, i, k) - Ftot(1, j, i, k));
-        out[k] = Qs[k * FR + f] - dtd * fx - dtd * gy;
+  }
+  __syncthreads();
+  // phase 3: update of the tile's cells and face terms
+  // total correction flux of edge (e, r) in direction d: own part, then the
+  // transverse parts of the other sweep's edges
+  auto Ftot = [&](int d, int e, int r, int k) -> R {
+    const int o = 1 - d;
+    R v = R(0.5) * E(d, e, r)[kSEcq + k];
+    v += E(o, r, e - 1)[kSEt + (1 * 2 + 1) * 4 + k];
+    v += E(o, r + 1, e - 1)[kSEt + (0 * 2 + 1) * 4 + k];
+    v += E(o, r, e)[kSEt + (1 * 2 + 0) * 4 + k];
+    v += E(o, r + 1, e)[kSEt + (0 * 2 + 0) * 4 + k];
+    return v;
+  };
+  for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
+    const int i = c % T + 1, j = c / T + 1;
+    const int f = lf(i, j);
+    const R dtd = R(dt / (kap[f] * dx));
+    R out[4];
+    for (int k = 0; k < 4; ++k) {
+      R fx, gy;
+      if (k == 0) {
+        fx = E(0, i + 1, j)[kSEfl] - E(0, i, j)[kSEfl];
+        gy = E(1, j + 1, i)[kSEfl] - E(1, j, i)[kSEfl];
+      } else {
+        fx = E(0, i, j)[kSEap + k] + E(0, i + 1, j)[kSEam + k];
+        gy = E(1, j, i)[kSEap + k] + E(1, j + 1, i)[kSEam + k];
       }
-      // momentum onto the tangent plane at the cell centre
-      const double* rc = geo + kGeoC * FR + 3 * f;
-      const R mr = out[1] * R(rc[0]) + out[2] * R(rc[1]) + out[3] * R(rc[2]);
-      for (int k = 0; k < 3; ++k) out[1 + k] -= mr * R(rc[k]);
-      for (int k = 0; k < 4; ++k) A.qn[(size_t(p * 4 + k) * m + (j - 1)) * m + (i - 1)] = out[k];
+      fx = fx + (Ftot(0, i + 1, j, k) - Ftot(0, i, j, k));
+      gy = gy + (Ftot(1, j + 1, i, k) - Ftot(1, j, i, k));
+      out[k] = Qs[k * FRT + f] - dtd * fx - dtd * gy;
     }
-    const int slot = A.phislot[p];
-    if (slot >= 0) {
-      R* ph = A.phi + size_t(slot) * 4 * m * 4;
-      for (int it = threadIdx.x; it < 4 * m * 4; it += blockDim.x) {
-        const int k = it % 4, t = (it / 4) % m + 1, fc = it / (4 * m);
-        const int d = fc / 2, e = (fc & 1) ? m + 1 : 1;
-        const R* o = E(d, e, t);
-        R fluct;
-        if (k == 0) fluct = (fc & 1) ? o[kSEfl] : -o[kSEfl];
-        else fluct = (fc & 1) ? o[kSEam + k] : o[kSEap + k];
-        const R corr = Ftot(d, e, t, k);
-        ph[it] = R(dx) * ((fc & 1) ? fluct + corr : fluct - corr);
-      }
+    // momentum onto the tangent plane at the cell centre
+    const double* rc = geo + kGeoC * FR + 3 * pf(i, j);
+    const R mr = out[1] * R(rc[0]) + out[2] * R(rc[1]) + out[3] * R(rc[2]);
+    for (int k = 0; k < 3; ++k) out[1 + k] -= mr * R(rc[k]);
+    for (int k = 0; k < 4; ++k)
+      A.qn[(size_t(p * 4 + k) * m + (j0 + j - 1)) * m + (i0 + i - 1)] = out[k];
+  }
+  const int slot = A.phislot[p];
+  if (slot >= 0) {
+    // face terms of the patch faces this tile lies on
+    R* ph = A.phi + size_t(slot) * 4 * m * 4;
+    for (int it = threadIdx.x; it < 4 * T * 4; it += blockDim.x) {
+      const int k = it % 4, t = (it / 4) % T + 1, fc = it / (4 * T);
+      const bool on = fc == 0 ? i0 == 0 : fc == 1 ? i0 + T == m : fc == 2 ? j0 == 0 : j0 + T == m;
+      if (!on) continue;
+      const int d = fc / 2, e = (fc & 1) ? T + 1 : 1;
+      const R* o = E(d, e, t);
+      R fluct;
+      if (k == 0) fluct = (fc & 1) ? o[kSEfl] : -o[kSEfl];
+      else fluct = (fc & 1) ? o[kSEam + k] : o[kSEap + k];
+      const R corr = Ftot(d, e, t, k);
+      const int tp = (d == 0 ? j0 : i0) + t;
+      ph[(fc * m + (tp - 1)) * 4 + k] = R(dx) * ((fc & 1) ? fluct + corr : fluct - corr);
     }
-    for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nmax;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double v = red[0];
-      for (int w = 1; w < int(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
-      atomic_max_pos(A.numax, v);
-    }
+  }
+  for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = red[0];
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+    atomic_max_pos(A.numax, v);
   }
 }
 

@@ -436,6 +436,24 @@ def sphere_centres(leaves: np.ndarray, m: int) -> np.ndarray:
     return out
 
 
+def sphere_bumps(leaves, m, n=16, seed=0, amp=0.1, width=30.0):
+    """h = 1 + sum of n bumps amp exp(-width d_k^2) around seeded centres
+    drawn uniformly on the sphere (d_k the great-circle distance to centre
+    k); fluid at rest.  Spreads resolvable gradients over much of the
+    sphere, so that a criterion tags enough patches for a large adaptive
+    mesh.  (P, 4, m, m)."""
+    rng = np.random.default_rng(seed)
+    c = rng.normal(size=(n, 3))
+    c /= np.linalg.norm(c, axis=1, keepdims=True)
+    r = sphere_centres(leaves, m)
+    q = np.zeros((len(leaves), 4, m, m))
+    q[:, 0] = 1.0
+    for k in range(n):
+        d = np.arccos(np.clip(np.einsum("pkij,k->pij", r, c[k]), -1.0, 1.0))
+        q[:, 0] += amp * np.exp(-width * d * d)
+    return q
+
+
 def sphere_bump(leaves, m, lat=0.3, lon=0.5, amp=0.1, width=100.0):
     """h = 1 + amp exp(-width d^2), d the great-circle distance to the
     point (lat, lon); fluid at rest.  (P, 4, m, m): h, hu, hv, hw."""
