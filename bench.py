@@ -50,6 +50,7 @@ def parse():
                                        "mlp", "copy", "all"],
                     default="all")
     ap.add_argument("--batch-steps", type=int, default=100)
+    ap.add_argument("--sphere-steps", type=int, default=1000)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     return ap.parse_args()
@@ -474,7 +475,7 @@ def main():
         res["batch"] = run_batch(args.batch_steps, 10)
         print(f"# batch fp32: {res['batch']}", file=sys.stderr, flush=True)
     if args.only in ("sphere", "all"):
-        res["sphere"] = run_sphere(20)
+        res["sphere"] = run_sphere(args.sphere_steps)
         print(f"# sphere fp32: {res['sphere']}", file=sys.stderr, flush=True)
     if args.only in ("mlp", "all"):
         res["mlp"] = run_mlp()
@@ -566,8 +567,10 @@ def main():
         }
     if "sphere" in res:
         out["cubed_sphere"] = dict(res["sphere"], workload=(
-            "shallow water on the cubed sphere, 6 trees uniform level 4, m=16, "
-            "FP32 state, FP64 geometry and sums, plain path with reflux"))
+            "shallow water on the cubed sphere, 6 trees, adaptive levels 4-7, m=32, "
+            "seeded Gaussian height bumps, threshold set for ~50k initial patches, "
+            "regrid every 8 steps (|grad h| criterion), FP32 state, FP64 geometry "
+            "and sums, plain path with reflux, the library's run loop"))
     if "mlp" in res:
         out["learned_tagging_mlp"] = res["mlp"]
     flags = {k: r["status"] for k, r in res.items() if "status" in r and r["status"]}

@@ -824,12 +824,13 @@ struct fcx_batch {
   int32_t* pforest = nullptr;
   ForestDev* forests = nullptr;
   uint32_t* items = nullptr;
-  int32_t* range = nullptr;           // [2][9]
+  int32_t* range = nullptr;           // [kBatchClasses][9]
   RefluxItem* reflux = nullptr;
   int32_t* reflux_forest = nullptr;
   int32_t* first = nullptr;           // [n + 1] patch offsets
   int32_t n_reflux_x = 0, n_reflux_y = 0;
-  int32_t nitems[2] = {0, 0}, item0[2] = {0, 0};
+  // work classes: 8 x 8 or large tiles, times advection or shallow water
+  int32_t nitems[4] = {0, 0, 0, 0}, item0[4] = {0, 0, 0, 0};
   DevBuf<uint8_t> phi;
   DevBuf<double> partial;
   DevBuf<int32_t> counters, err;
@@ -852,8 +853,8 @@ static int batch_build(fcx_batch* b) {
   std::vector<int32_t> phislot, pforest, first(1, 0);
   std::vector<RefluxItem> rx, ry;
   std::vector<int32_t> rfx, rfy;
-  std::vector<uint32_t> items[2];
-  std::vector<int32_t> cost[2];
+  std::vector<uint32_t> items[4];
+  std::vector<int32_t> cost[4];
   int64_t phi_elems = 0, slot_base = 0;
   b->fh.clear();
   b->state_off.clear();
@@ -885,7 +886,7 @@ static int batch_build(fcx_batch* b) {
       phislot.push_back(plan.phislot[p] >= 0 ? plan.phislot[p] + int32_t(slot_base) : -1);
       pforest.push_back(f);
       const int T = F.m == 8 ? 8 : b->tile_big;
-      const int cls = T == 8 ? 0 : 1;
+      const int cls = (T == 8 ? 0 : 2) + (F.physics == FCX_SHALLOW ? 1 : 0);
       const int tps = F.m / T;
       for (int t = 0; t < tps * tps; ++t) {
         items[cls].push_back((uint32_t(pbase + p) << 4) | uint32_t(t));
@@ -913,9 +914,9 @@ static int batch_build(fcx_batch* b) {
   rx.insert(rx.end(), ry.begin(), ry.end());
   rfx.insert(rfx.end(), rfy.begin(), rfy.end());
   // per class: XCD ranges of equal cost
-  std::vector<int32_t> ranges(18, 0);
+  std::vector<int32_t> ranges(4 * 9, 0);
   std::vector<uint32_t> all;
-  for (int cls = 0; cls < 2; ++cls) {
+  for (int cls = 0; cls < 4; ++cls) {
     b->item0[cls] = int32_t(all.size());
     b->nitems[cls] = int32_t(items[cls].size());
     int64_t tot = 0;
@@ -957,7 +958,7 @@ static int batch_build(fcx_batch* b) {
   const size_t esz = b->precision == 64 ? 8 : 4;
   HIPCHK(b->phi.ensure(size_t(phi_elems) * esz));
   HIPCHK(b->partial.ensure(size_t(pbase) * 4));
-  HIPCHK(b->counters.ensure(16));
+  HIPCHK(b->counters.ensure(4 * 8 * kCounterStride));
   return FCX_OK;
 }
 
@@ -1016,7 +1017,7 @@ int fcx_batch_set_tuning(fcx_batch* b, int32_t tile_big, int32_t threads8,
   return rebuild ? batch_build(b) : FCX_OK;
 }
 
-template <typename R, int T, int NT>
+template <typename R, int PHYS, int T, int NT>
 static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
                               const double* dt, double* numax, hipStream_t s) {
   if (b->nitems[cls] == 0) return FCX_OK;
@@ -1033,17 +1034,18 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
   B.err = b->err.p;
   B.items = b->items;
   B.range = b->range + cls * 9;
-  B.counters = b->counters.p + cls * 8;
+  B.counters = b->counters.p + cls * 8 * kCounterStride;
   // resident workgroups: LDS allows about 160 KB / sizeof(tile LDS) per CU
   int per_cu = b->wg_per_cu;
   if (per_cu == 0) {
-    const int lds = int(sizeof(TileLds<R, FCX_SHALLOW, T, NT>));
+    const int lds = int(sizeof(TileLds<R, PHYS, T, NT>));
     per_cu = std::max(1, std::min(160 * 1024 / (lds + 64), 32 * 64 / NT));
   }
   int grid = std::min(b->cus * per_cu, (b->nitems[cls] + 7) / 8 * 8);
   grid = std::max(8, (grid + 7) / 8 * 8);
-  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, b->counters.p + cls * 8, 8);
-  hipLaunchKernelGGL((k_batch_step<R, T, NT>), dim3(grid), dim3(NT), 0, s, B);
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(8 * kCounterStride), 0, s,
+                     b->counters.p + cls * 8 * kCounterStride, 8 * kCounterStride);
+  hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT>), dim3(grid), dim3(NT), 0, s, B);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -1051,11 +1053,18 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
 template <typename R>
 static int batch_step_t(fcx_batch* b, const void* q, void* qn, double* dt,
                         double* numax, int32_t* status, hipStream_t s) {
-  int rc = b->threads8 == 128 ? launch_batch_class<R, 8, 128>(b, 0, q, qn, dt, numax, s)
-                              : launch_batch_class<R, 8, 64>(b, 0, q, qn, dt, numax, s);
-  if (rc != FCX_OK) return rc;
-  rc = b->threads16 == 512 ? launch_batch_class<R, 16, 512>(b, 1, q, qn, dt, numax, s)
-                           : launch_batch_class<R, 16, 256>(b, 1, q, qn, dt, numax, s);
+  const bool t8 = b->threads8 == 128, t16 = b->threads16 == 512;
+  int rc = t8 ? launch_batch_class<R, FCX_ADVECTION, 8, 128>(b, 0, q, qn, dt, numax, s)
+              : launch_batch_class<R, FCX_ADVECTION, 8, 64>(b, 0, q, qn, dt, numax, s);
+  if (rc == FCX_OK)
+    rc = t8 ? launch_batch_class<R, FCX_SHALLOW, 8, 128>(b, 1, q, qn, dt, numax, s)
+            : launch_batch_class<R, FCX_SHALLOW, 8, 64>(b, 1, q, qn, dt, numax, s);
+  if (rc == FCX_OK)
+    rc = t16 ? launch_batch_class<R, FCX_ADVECTION, 16, 512>(b, 2, q, qn, dt, numax, s)
+             : launch_batch_class<R, FCX_ADVECTION, 16, 256>(b, 2, q, qn, dt, numax, s);
+  if (rc == FCX_OK)
+    rc = t16 ? launch_batch_class<R, FCX_SHALLOW, 16, 512>(b, 3, q, qn, dt, numax, s)
+             : launch_batch_class<R, FCX_SHALLOW, 16, 256>(b, 3, q, qn, dt, numax, s);
   if (rc != FCX_OK) return rc;
   for (int axis = 0; axis < 2; ++axis) {
     const int32_t n = axis == 0 ? b->n_reflux_x : b->n_reflux_y;

@@ -36,7 +36,7 @@ struct BatchArgs {
   int32_t* err;
   const uint32_t* __restrict__ items;      // (patch << 4) | tile
   const int32_t* __restrict__ range;       // [9] item range of each XCD
-  int32_t* counters;                       // [8], zero at launch
+  int32_t* counters;                       // [8 * kCounterStride], zero at launch
 };
 
 // Step arguments of one forest, with base pointers shifted so that global
@@ -63,41 +63,62 @@ __device__ __forceinline__ StepArgs<R> forest_args(const BatchArgs<R>& B, int f,
   return A;
 }
 
-template <typename R, int T, int NT>
+// one work counter per XCD, each on a cache line of its own
+constexpr int kCounterStride = 32;
+
+// A value the whole wavefront agrees on, moved to scalar registers 32 bits
+// at a time (so that per-item parameters do not occupy vector registers for
+// the length of a tile).
+template <typename V>
+__device__ __forceinline__ V wave_uniform(const V& v) {
+  static_assert(sizeof(V) % 4 == 0, "32-bit multiple");
+  uint32_t w[sizeof(V) / 4];
+  __builtin_memcpy(w, &v, sizeof(V));
+#pragma unroll
+  for (int i = 0; i < int(sizeof(V) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+  V out;
+  __builtin_memcpy(&out, w, sizeof(V));
+  return out;
+}
+
+// Persistent launch over the work items of one class (tile size and
+// physics).  Thread 0 takes items through its XCD's counter (stealing from
+// the other XCDs once its own range is spent); the ticket for the next item
+// is drawn before the current tile is processed, so the atomic's latency
+// overlaps the tile's loads.
+template <typename R, int PHYS, int T, int NT>
 __global__ void __launch_bounds__(NT)
 k_batch_step(BatchArgs<R> B) {
-  __shared__ union {
-    TileLds<R, FCX_ADVECTION, T, NT> adv;
-    TileLds<R, FCX_SHALLOW, T, NT> sw;
-  } lds;
+  __shared__ TileLds<R, PHYS, T, NT> lds;
   __shared__ int item_sh;
-  const int home = blockIdx.x & 7;
-  int x = home, tries = 0;
-  for (;;) {
-    __syncthreads();                     // LDS of the previous item is free
-    if (threadIdx.x == 0) {
-      int it = -1;
-      while (tries < 8) {
-        const int k = atomicAdd(&B.counters[x], 1);
-        if (B.range[x] + k < B.range[x + 1]) { it = B.range[x] + k; break; }
-        x = (x + 1) & 7;                 // own range done: steal
-        ++tries;
-      }
-      item_sh = it;
+  int x = blockIdx.x & 7, tries = 0;
+  // resolve a ticket k drawn on counter x into an item, stealing when the
+  // range of x is spent; -1 once every range is
+  auto resolve = [&](int k) -> int {
+    for (;;) {
+      if (B.range[x] + k < B.range[x + 1]) return B.range[x] + k;
+      if (++tries >= 8) return -1;
+      x = (x + 1) & 7;
+      k = atomicAdd(&B.counters[x * kCounterStride], 1);
     }
-    __syncthreads();
-    const int it = item_sh;
+  };
+  if (threadIdx.x == 0) item_sh = resolve(atomicAdd(&B.counters[x * kCounterStride], 1));
+  __syncthreads();
+  for (;;) {
+    const int it = __builtin_amdgcn_readfirstlane(item_sh);
     if (it < 0) break;
-    const uint32_t w = B.items[it];
+    int ticket = 0;
+    if (threadIdx.x == 0 && tries < 8) ticket = atomicAdd(&B.counters[x * kCounterStride], 1);
+    const uint32_t w = __builtin_amdgcn_readfirstlane(B.items[it]);
     const int p = int(w >> 4), tile = int(w & 15);
-    const int f = B.pforest[p];
-    const ForestDev F = B.forests[f];
-    const StepArgs<R> A = forest_args(B, f, F);
+    const int f = __builtin_amdgcn_readfirstlane(B.pforest[p]);
+    const ForestDev F = wave_uniform(B.forests[f]);
+    const StepArgs<R> A = wave_uniform(forest_args(B, f, F));
     const int tps = F.m / T;
-    if (F.physics == FCX_ADVECTION)
-      tile_step<R, FCX_ADVECTION, T, NT, true>(A, p, tile % tps, tile / tps, lds.adv);
-    else
-      tile_step<R, FCX_SHALLOW, T, NT, true>(A, p, tile % tps, tile / tps, lds.sw);
+    tile_step<R, PHYS, T, NT, true>(A, p, tile % tps, tile / tps, lds);
+    __syncthreads();                     // item_sh and the tile's LDS are free
+    if (threadIdx.x == 0) item_sh = tries < 8 ? resolve(ticket) : -1;
+    __syncthreads();
   }
 }
 
