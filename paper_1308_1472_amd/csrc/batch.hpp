@@ -87,7 +87,7 @@ __device__ __forceinline__ V wave_uniform(const V& v) {
 // is drawn before the current tile is processed, so the atomic's latency
 // overlaps the tile's loads.
 template <typename R, int PHYS, int T, int NT>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2)
 k_batch_step(BatchArgs<R> B) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
   __shared__ int item_sh;
