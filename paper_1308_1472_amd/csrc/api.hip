@@ -110,7 +110,7 @@ struct DevForest {
   int32_t* phislot = nullptr;
   int32_t* family = nullptr;
   RefluxItem* reflux = nullptr;
-  int32_t* links = nullptr;          // per reflux item: partners at its two ends
+  RefluxAux* aux = nullptr;          // per reflux item: partners, slots, level
   int32_t* first = nullptr;          // {0, P} for the sum reduction
   int32_t* xkind = nullptr;          // transfer plan from the previous forest
   int32_t* xsrc = nullptr;
@@ -338,14 +338,14 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   size_t at = 0;
   const size_t sz[8] = {P * sizeof(PatchRec), P * 4, P * 4,
                         NI * sizeof(RefluxItem), 2 * 4,
-                        kind ? P * 4 : 0, src ? P * 4 : 0, NI * 2 * 4};
+                        kind ? P * 4 : 0, src ? P * 4 : 0, NI * sizeof(RefluxAux)};
   for (int k = 0; k < 8; ++k) { off[k] = at; at += align256(sz[k]); }
   off[8] = at;
   HIPCHK(c->staging.ensure(at));
   uint8_t* h = c->staging.p;
   {
     RefluxItem* items = reinterpret_cast<RefluxItem*>(h + off[3]);
-    int32_t* links = reinterpret_cast<int32_t*>(h + off[7]);
+    RefluxAux* aux = reinterpret_cast<RefluxAux*>(h + off[7]);
     int32_t nx = 0;
     for (const auto& it : plan.reflux) nx += it.face < 2;
     dev.n_reflux_x = nx;
@@ -362,10 +362,16 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
       }
       for (int32_t t = b; t < e; ++t) {
         const int32_t k = pos[t - b];
-        const int f = plan.reflux[t].face;
-        items[k] = plan.reflux[t];
-        links[2 * k] = at_face[f < 2 ? 2 : 0];
-        links[2 * k + 1] = at_face[f < 2 ? 3 : 1];
+        const RefluxItem& it = plan.reflux[t];
+        const int f = it.face;
+        items[k] = it;
+        RefluxAux& ax = aux[k];
+        ax.link[0] = at_face[f < 2 ? 2 : 0];
+        ax.link[1] = at_face[f < 2 ? 3 : 1];
+        ax.slot_c = plan.phislot[it.coarse];
+        for (int s2 = 0; s2 < 2; ++s2)
+          ax.slot_f[s2] = it.fine[s2] >= 0 ? plan.phislot[it.fine[s2]] : -1;
+        ax.level = plan.recs[it.coarse].level;
       }
     }
   }
@@ -393,7 +399,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   dev.first = reinterpret_cast<int32_t*>(d + off[4]);
   dev.xkind = kind ? reinterpret_cast<int32_t*>(d + off[5]) : nullptr;
   dev.xsrc = src ? reinterpret_cast<int32_t*>(d + off[6]) : nullptr;
-  dev.links = reinterpret_cast<int32_t*>(d + off[7]);
+  dev.aux = reinterpret_cast<RefluxAux*>(d + off[7]);
   dev.nslots = plan.nslots;
   dev.P = int64_t(P);
   std::swap(c->plan, c->spare);
@@ -606,8 +612,8 @@ static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
   nd.ticket = c->ticket.p;
   hipLaunchKernelGGL((k_reflux<R, PHYS, NEXT>), dim3(grid), dim3(256), 0, s,
                      static_cast<const R*>(q), static_cast<R*>(qn), c->cur.reflux,
-                     c->cur.links, n, c->cur.rec, c->cur.phislot,
-                     reinterpret_cast<const R*>(c->phi.p), dt, m, kphys(c), c->err.p, nd);
+                     c->cur.aux, n, reinterpret_cast<const R*>(c->phi.p), dt, m, kphys(c),
+                     c->err.p, nd);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }

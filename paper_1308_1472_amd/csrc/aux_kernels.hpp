@@ -66,28 +66,41 @@ __device__ void fluct_sum(const KPhys& ph, int d, const R* ql, const R* qr,
   out[mv] = s1 * a1 * v + u * a2 + s3 * a3 * v;
 }
 
+// Per reflux item, built with the plan: the items of the other direction on
+// the same coarse patch whose faces meet this one at its low and high end
+// (-1: none), the face-term slots of the coarse patch and of the two fine
+// patches, and the coarse patch's level.
+struct RefluxAux {
+  int32_t link[2], slot_c, slot_f[2], level;
+};
+
 // Reflux correction of one coarse cell (position tc along the face of item
-// it): the fine face terms minus the coarse one, subtracted from qn.
+// it): the coarse face term minus the two fine ones, per component; o is the
+// cell's offset in qn (component 0).
 template <typename R, int PHYS>
-__device__ void reflux_cell(const R* __restrict__ q, R* __restrict__ qn,
-                            const RefluxItem& it, int tc,
-                            const PatchRec* __restrict__ rec,
-                            const int32_t* __restrict__ phislot,
-                            const R* __restrict__ phi, const double* dtp, int m,
-                            const KPhys& ph, int32_t* err) {
+__device__ __forceinline__ void reflux_corr(const R* __restrict__ q, const RefluxItem& it,
+                                            const RefluxAux& ax, int tc,
+                                            const R* __restrict__ phi, int m,
+                                            const KPhys& ph, int32_t* err,
+                                            R (&corr)[PhysTraits<PHYS>::MEQN], size_t& o,
+                                            double& dxc) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   const int f = it.face, d = f >> 1, hi = f & 1;
   const int C = it.coarse;
   const int ic = d == 0 ? (hi ? m : 1) : tc, jc = d == 0 ? tc : (hi ? m : 1);
   const int k2 = (tc - 1) / (m / 2);
   const int fp = it.fine[k2], ff = it.fine_face[k2];
-  const double dxc = ldexp(1.0, -rec[C].level) / m;
+  dxc = ldexp(1.0, -ax.level) / m;
+  o = (size_t(C * MEQN) * m + (jc - 1)) * m + (ic - 1);
   R qc[MEQN];
   read_interior<R, MEQN>(q, m, C, ic, jc, qc);
-  R corr[MEQN];
+  const R* phf = phi + size_t(ax.slot_f[k2]) * 4 * m * MEQN;
+  const R* phc = phi + size_t(ax.slot_c) * 4 * m * MEQN;
 #pragma unroll
-  for (int k = 0; k < MEQN; ++k) corr[k] = R(0);
-  const R* phf = phi + size_t(phislot[fp]) * 4 * m * MEQN;
+  for (int k = 0; k < MEQN; ++k) corr[k] = -phc[(f * m + (tc - 1)) * MEQN + k];
+  R fine[MEQN];
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) fine[k] = R(0);
   for (int s = 0; s < 2; ++s) {
     int pos = 2 * (tc - 1 - k2 * (m / 2)) + 1 + s;
     if (it.fine_rev[k2]) pos = m + 1 - pos;
@@ -99,15 +112,10 @@ __device__ void reflux_cell(const R* __restrict__ q, R* __restrict__ qn,
     else fluct_sum<R, PHYS>(ph, d, qf, qc, fs, err);
 #pragma unroll
     for (int k = 0; k < MEQN; ++k)
-      corr[k] += R(0.5 * dxc) * fs[k] - phf[(ff * m + (pos - 1)) * MEQN + k];
+      fine[k] += R(0.5 * dxc) * fs[k] - phf[(ff * m + (pos - 1)) * MEQN + k];
   }
-  const R* phc = phi + size_t(phislot[C]) * 4 * m * MEQN;
-  const R fac = R(*dtp / (dxc * dxc));
 #pragma unroll
-  for (int k = 0; k < MEQN; ++k) {
-    const size_t o = (size_t(C * MEQN + k) * m + (jc - 1)) * m + (ic - 1);
-    qn[o] -= fac * (corr[k] - phc[(f * m + (tc - 1)) * MEQN + k]);
-  }
+  for (int k = 0; k < MEQN; ++k) corr[k] = fine[k] + corr[k];
 }
 
 // CFL check and next dt of forest f (status bits: 1 CFL exceeded,
@@ -140,29 +148,44 @@ struct NextDtArgs {
 // Reflux: one thread per (coarse-fine face item, coarse cell along it), all
 // items in one launch.  Items of xi faces come first; a coarse corner cell
 // that lies on an xi item and an eta item gets both corrections, xi first,
-// from the xi item's thread (links[2i], links[2i+1]: for an xi item the eta
-// items at its low / high end, for an eta item the xi items there; -1 none),
-// so the result does not depend on the order the threads run in.  With NEXT,
-// the workgroup that finishes last also takes the CFL check and the next dt.
+// from the xi item's thread (RefluxAux::link: for an xi item the eta items
+// at its low / high end, for an eta item the xi items there), so the result
+// does not depend on the order the threads run in; such a thread computes
+// both corrections before it updates the cell.  With NEXT, the workgroup
+// that finishes last also takes the CFL check and the next dt.
 template <typename R, int PHYS, bool NEXT>
 __global__ void __launch_bounds__(256)
 k_reflux(const R* __restrict__ q, R* __restrict__ qn,
-         const RefluxItem* __restrict__ items, const int32_t* __restrict__ links,
-         int32_t nitems, const PatchRec* __restrict__ rec,
-         const int32_t* __restrict__ phislot, const R* __restrict__ phi,
-         const double* dtp, int m, KPhys ph, int32_t* err, NextDtArgs nd) {
+         const RefluxItem* __restrict__ items, const RefluxAux* __restrict__ aux,
+         int32_t nitems, const R* __restrict__ phi, const double* dtp, int m, KPhys ph,
+         int32_t* err, NextDtArgs nd) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t < int64_t(nitems) * m) {
     const int32_t i = int32_t(t / m);
     const int tc = int(t % m) + 1;
     const RefluxItem it = items[i];
+    const RefluxAux ax = aux[i];
     const int end = tc == 1 ? 0 : (tc == m ? 1 : -1);
-    const int32_t link = end >= 0 ? links[2 * i + end] : -1;
+    const int32_t link = end >= 0 ? ax.link[end] : -1;
     if (it.face < 2 || link < 0) {
-      reflux_cell<R, PHYS>(q, qn, it, tc, rec, phislot, phi, dtp, m, ph, err);
-      if (it.face < 2 && link >= 0)
-        reflux_cell<R, PHYS>(q, qn, items[link], it.face == 0 ? 1 : m, rec, phislot, phi,
-                             dtp, m, ph, err);
+      R c0[MEQN], c1[MEQN];
+      size_t o, o1;
+      double dxc, dxc1;     // the second correction is on the same coarse cell
+      reflux_corr<R, PHYS>(q, it, ax, tc, phi, m, ph, err, c0, o, dxc);
+      const bool two = it.face < 2 && link >= 0;
+      if (two)
+        reflux_corr<R, PHYS>(q, items[link], aux[link], it.face == 0 ? 1 : m, phi, m, ph,
+                             err, c1, o1, dxc1);
+      const R fac = R(*dtp / (dxc * dxc));
+#pragma unroll
+      for (int k = 0; k < MEQN; ++k) {
+        const size_t ok = o + size_t(k) * m * m;
+        R v = qn[ok];
+        v -= fac * c0[k];
+        if (two) v -= fac * c1[k];
+        qn[ok] = v;
+      }
     }
   }
   if (NEXT) {
