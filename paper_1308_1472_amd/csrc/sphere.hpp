@@ -191,14 +191,16 @@ __device__ bool rp_sphere(R grav, const SEdge<R>& e, const R* ql, const R* qr, R
   const R nr = qr[1] * e.n[0] + qr[2] * e.n[1] + qr[3] * e.n[2];
   const R tl = ql[1] * e.t[0] + ql[2] * e.t[1] + ql[3] * e.t[2];
   const R tr = qr[1] * e.t[0] + qr[2] * e.t[1] + qr[3] * e.t[2];
-  const R sl = sqrt(hl), sr = sqrt(hr);
-  const R u = (nl / sl + nr / sr) / (sl + sr);
-  const R v = (tl / sl + tr / sr) / (sl + sr);
-  const R c = sqrt(grav * R(0.5) * (hl + hr));
+  const R sl = sqrt_(hl), sr = sqrt_(hr);
+  const R isl = rcp_(sl), isr = rcp_(sr), iss = rcp_(sl + sr);
+  const R u = (nl * isl + nr * isr) * iss;
+  const R v = (tl * isl + tr * isr) * iss;
+  const R c = sqrt_(grav * R(0.5) * (hl + hr));
+  const R i2c = R(0.5) * rcp_(c);
   const R d0 = hr - hl, d1 = nr - nl, d2 = tr - tl;
-  const R a1 = ((u + c) * d0 - d1) / (R(2) * c);
+  const R a1 = ((u + c) * d0 - d1) * i2c;
   const R a2 = d2 - v * d0;
-  const R a3 = (d1 - (u - c) * d0) / (R(2) * c);
+  const R a3 = (d1 - (u - c) * d0) * i2c;
   const R wv[3][3] = {{a1, a1 * (u - c), a1 * v}, {R(0), R(0), a2}, {a3, a3 * (u + c), a3 * v}};
   const R sp[3] = {u - c, u, u + c};
   for (int w = 0; w < 3; ++w) {
@@ -219,23 +221,38 @@ __device__ bool rp_sphere(R grav, const SEdge<R>& e, const R* ql, const R* qr, R
   return true;
 }
 
-// part of psi crossing the transverse edge te of the receiving cell, down
-// (up = false) or up; Roe averages of the normal edge's states
+// Roe averages of an edge's two states (3D velocity and celerity), shared by
+// the four transverse splits of that edge; false if a depth is not positive
 template <typename R>
-__device__ bool tsplit_sphere(R grav, const R* ql, const R* qr, const SEdge<R>& te,
-                              const R* psi, bool up, R* out) {
+struct SRoe {
+  R ub[3], c, i2c;
+};
+
+template <typename R>
+__device__ __forceinline__ bool roe_sphere(R grav, const R* ql, const R* qr, SRoe<R>& rs) {
   const R hl = ql[0], hr = qr[0];
   if (!(hl > R(0) && hr > R(0))) return false;
-  const R sl = sqrt(hl), sr = sqrt(hr);
-  R ub[3];
-  for (int k = 0; k < 3; ++k) ub[k] = (ql[1 + k] / sl + qr[1 + k] / sr) / (sl + sr);
-  const R c = sqrt(grav * R(0.5) * (hl + hr));
+  const R sl = sqrt_(hl), sr = sqrt_(hr);
+  const R isl = rcp_(sl), isr = rcp_(sr), iss = rcp_(sl + sr);
+  for (int k = 0; k < 3; ++k) rs.ub[k] = (ql[1 + k] * isl + qr[1 + k] * isr) * iss;
+  rs.c = sqrt_(grav * R(0.5) * (hl + hr));
+  rs.i2c = R(0.5) * rcp_(rs.c);
+  return true;
+}
+
+// part of psi crossing the transverse edge te of the receiving cell, down
+// (up = false) or up, with the Roe averages rs of the normal edge's states
+template <typename R>
+__device__ void tsplit_sphere(const SRoe<R>& rs, const SEdge<R>& te, const R* psi, bool up,
+                              R* out) {
+  const R* ub = rs.ub;
+  const R c = rs.c;
   const R un = ub[0] * te.n[0] + ub[1] * te.n[1] + ub[2] * te.n[2];
   const R ut = ub[0] * te.t[0] + ub[1] * te.t[1] + ub[2] * te.t[2];
   const R pn = psi[1] * te.n[0] + psi[2] * te.n[1] + psi[3] * te.n[2];
   const R pt = psi[1] * te.t[0] + psi[2] * te.t[1] + psi[3] * te.t[2];
-  const R beta[3] = {((un + c) * psi[0] - pn) / (R(2) * c), pt - ut * psi[0],
-                     (pn - (un - c) * psi[0]) / (R(2) * c)};
+  const R beta[3] = {((un + c) * psi[0] - pn) * rs.i2c, pt - ut * psi[0],
+                     (pn - (un - c) * psi[0]) * rs.i2c};
   const R lam[3] = {te.g * (un - c), te.g * un, te.g * (un + c)};
   R Rv[3][4];
   Rv[0][0] = R(1); Rv[1][0] = R(0); Rv[2][0] = R(1);
@@ -252,7 +269,6 @@ __device__ bool tsplit_sphere(R grav, const R* ql, const R* qr, const SEdge<R>& 
     }
     out[k] = acc;
   }
-  return true;
 }
 
 // ---------------------------------------------------------------------------
@@ -305,7 +321,8 @@ k_sphere_step(SphereArgs<R> A) {
                 NE = (T + 3) * (T + 2);
   extern __shared__ unsigned char smem_raw[];
   R* Qs = reinterpret_cast<R*>(smem_raw);                                  // [4][FRT]
-  double* kap = reinterpret_cast<double*>(smem_raw + sizeof(R) * 4 * FRT);  // [FRT]
+  // dt / (kappa dx) of each frame cell, the only form the step needs kappa in
+  double* dtk = reinterpret_cast<double*>(smem_raw + sizeof(R) * 4 * FRT);  // [FRT]
   R* scr = reinterpret_cast<R*>(smem_raw + sizeof(R) * 4 * FRT + sizeof(double) * FRT);
   __shared__ double red[kSphereThreads / 64];
   auto E = [&](int d, int e, int r) { return scr + (size_t(d) * NE + size_t(e) * M2 + r) * kSEn; };
@@ -334,7 +351,7 @@ k_sphere_step(SphereArgs<R> A) {
         v = outer ? R(0) : A.ghost[size_t(p * 4 + k) * G + ghost_index(m, i, j)];
       Qs[k * FRT + f] = v;
     }
-    kap[f] = geo[kGeoK * FR + fidx(m, i, j)];
+    dtk[f] = dt / (geo[kGeoK * FR + fidx(m, i, j)] * dx);
   }
   __syncthreads();
   // phase 1: Riemann problems at every edge of rows 0..T+1, both directions
@@ -364,7 +381,7 @@ k_sphere_step(SphereArgs<R> A) {
     for (int k = 0; k < 4; ++k) { o[kSEam + k] = am[k]; o[kSEap + k] = ap[k]; }
     o[kSEfl] = fl;
     if (r >= 1 && r <= T) {
-      const double dtdl = dt / (kap[lf(il, jl)] * dx), dtdr = dt / (kap[lf(ir, jr)] * dx);
+      const double dtdl = dtk[lf(il, jl)], dtdr = dtk[lf(ir, jr)];
       for (int w = 0; w < 3; ++w) {
         nmax = fmax(nmax, dtdr * fmax(double(s[w]), 0.0));
         nmax = fmax(nmax, dtdl * fmax(-double(s[w]), 0.0));
@@ -379,7 +396,7 @@ k_sphere_step(SphereArgs<R> A) {
     if (e < 1 || e > T + 1) continue;
     const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
     const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
-    const double dtdl = dt / (kap[lf(il, jl)] * dx), dtdr = dt / (kap[lf(ir, jr)] * dx);
+    const double dtdl = dtk[lf(il, jl)], dtdr = dtk[lf(ir, jr)];
     const R nu = R(0.5 * (dtdl + dtdr));
     R* o = E(d, e, r);
     R cq[4] = {R(0), R(0), R(0), R(0)};
@@ -392,7 +409,7 @@ k_sphere_step(SphereArgs<R> A) {
       const R* Wu = E(d, sw > R(0) ? e - 1 : e + 1, r) + kSEw + 4 * w;
       R dot = R(0);
       for (int k = 0; k < 4; ++k) dot += Wu[k] * Wc[k];
-      const R lim = limiter_phi<R>(A.limiter, dot / wn2);
+      const R lim = limiter_phi<R>(A.limiter, dot * rcp_(wn2));
       const R as = fabs(sw);
       for (int k = 0; k < 4; ++k) cq[k] += as * (R(1) - nu * as) * lim * Wc[k];
     }
@@ -410,7 +427,7 @@ k_sphere_step(SphereArgs<R> A) {
     }
     const int il = cell_i(d, e - 1, r), jl = cell_j(d, e - 1, r);
     const int ir = cell_i(d, e, r), jr = cell_j(d, e, r);
-    const double dtdl = dt / (kap[lf(il, jl)] * dx), dtdr = dt / (kap[lf(ir, jr)] * dx);
+    const double dtdl = dtk[lf(il, jl)], dtdr = dtk[lf(ir, jr)];
     R ql[4], qr[4], amt[4], apt[4];
     for (int k = 0; k < 4; ++k) {
       ql[k] = Qs[k * FRT + lf(il, jl)];
@@ -419,6 +436,9 @@ k_sphere_step(SphereArgs<R> A) {
       amt[k] = o[kSEam + k] + c2;
       apt[k] = o[kSEap + k] - c2;
     }
+    SRoe<R> rs;
+    const bool ok = roe_sphere<R>(grav, ql, qr, rs);
+    if (!ok) atomicOr(A.err, kErrNegDepth);
     for (int side = 0; side < 2; ++side) {
       const int col = side == 0 ? e - 1 : e;
       const R h = R(-0.5 * (side == 0 ? dtdl : dtdr));
@@ -428,9 +448,10 @@ k_sphere_step(SphereArgs<R> A) {
       const SEdge<R> hi = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + pf(ui, uj)) * 7);
       R bm[4], bp[4];
       const R* psi = side == 0 ? amt : apt;
-      if (!tsplit_sphere<R>(grav, ql, qr, lo, psi, false, bm) ||
-          !tsplit_sphere<R>(grav, ql, qr, hi, psi, true, bp)) {
-        atomicOr(A.err, kErrNegDepth);
+      if (ok) {
+        tsplit_sphere<R>(rs, lo, psi, false, bm);
+        tsplit_sphere<R>(rs, hi, psi, true, bp);
+      } else {
         for (int k = 0; k < 4; ++k) bm[k] = bp[k] = R(0);
       }
       for (int k = 0; k < 4; ++k) {
@@ -455,7 +476,7 @@ k_sphere_step(SphereArgs<R> A) {
   for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
     const int i = c % T + 1, j = c / T + 1;
     const int f = lf(i, j);
-    const R dtd = R(dt / (kap[f] * dx));
+    const R dtd = R(dtk[f]);
     R out[4];
     for (int k = 0; k < 4; ++k) {
       R fx, gy;
