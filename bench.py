@@ -356,10 +356,11 @@ def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000)
     torch.cuda.synchronize()
     kms = ev[0].elapsed_time(ev[1]) / 10
     kcells = ctx.num_patches() * m * m
-    # algorithmic bytes per cell: the FP32 state read and written (32 B) and
-    # the FP64 geometry of the cell (capacity 8 B, two edge frames 112 B,
-    # centre 24 B)
-    alg = kcells * 176.0
+    # algorithmic bytes per cell: the state read and written (32 B in FP32)
+    # and the geometry the step reads for the cell: the FP64 capacity (8 B),
+    # two edge frames and the centre (in FP32 for FP32 state: 56 + 12 B)
+    bpc = 32.0 + 8.0 + 68.0 if precision == 32 else 64.0 + 8.0 + 136.0
+    alg = kcells * bpc
     return {"threshold": thr, "patches_initial": P0, "patches_last": ctx.num_patches(),
             "steps": steps, "regrid_every": every, "cells": cells,
             "rate": cells / el, "ms_per_step": el / steps * 1e3,
@@ -370,7 +371,7 @@ def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000)
                                          "achieved": alg / (kms * 1e-3) / 1e9,
                                          "peak": HBM_PEAK_GBS,
                                          "frac": alg / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                                         "bytes_per_cell": 176.0}}}
+                                         "bytes_per_cell": bpc}}}
 
 
 def run_mlp(rows=50000, reps=50):

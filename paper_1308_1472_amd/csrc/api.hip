@@ -118,6 +118,7 @@ struct DevForest {
   int32_t nslots = 0;
   int64_t P = 0;
   DevBuf<double> geo;                // sphere: per-patch geometry tables
+  DevBuf<float> geo32;               //   and, for FP32 state, edges and centres in FP32
 };
 
 struct fcx_ctx {
@@ -422,6 +423,13 @@ static int finish_upload(fcx_ctx* c, hipStream_t s = nullptr, bool ordered = fal
     hipLaunchKernelGGL(k_sphere_metrics, dim3(unsigned(P)), dim3(256), lds, s,
                        c->cur.rec, m, log2i(m), c->cur.geo.p);
     HIPCHK(hipGetLastError());
+    if (c->cfg.precision == 32) {
+      const int64_t n32 = P * kG32N * int64_t(FR);
+      HIPCHK(c->cur.geo32.ensure(size_t(n32)));
+      hipLaunchKernelGGL(k_sphere_geo32, dim3(unsigned((n32 + 255) / 256)), dim3(256), 0, s,
+                         c->cur.geo.p, c->cur.geo32.p, P, m);
+      HIPCHK(hipGetLastError());
+    }
     if (!ordered) HIPCHK(hipDeviceSynchronize());
   }
   return FCX_OK;
@@ -554,6 +562,7 @@ static int launch_sphere_step(fcx_ctx* c, const void* q, const void* ghost, void
   a.phi = reinterpret_cast<R*>(c->phi.p);
   a.err = c->err.p;
   a.geo = c->cur.geo.p;
+  a.geo32 = c->cur.geo32.p;
   a.P = int32_t(c->cur.P);
   a.m = c->cfg.m;
   a.lm = log2i(c->cfg.m);

@@ -172,12 +172,31 @@ struct SEdge {
   R g, n[3], t[3];
 };
 
-template <typename R>
-__device__ __forceinline__ SEdge<R> load_edge(const double* e) {
+template <typename R, typename G>
+__device__ __forceinline__ SEdge<R> load_edge(const G* e) {
   SEdge<R> s;
   s.g = R(e[0]);
   for (int c = 0; c < 3; ++c) { s.n[c] = R(e[1 + c]); s.t[c] = R(e[4 + c]); }
   return s;
+}
+
+// The step's geometry in FP32 for FP32 state (the FP32 step rounds every
+// edge and centre value to FP32 anyway): per patch the two edge frames of
+// each frame cell (7 values each, interleaved, direction-major) and the
+// centre (3 values per cell).
+constexpr int kG32E = 0, kG32C = 14, kG32N = 17;
+
+__global__ void __launch_bounds__(256)
+k_sphere_geo32(const double* __restrict__ geo, float* __restrict__ g32, int64_t P, int m) {
+  const int FR = (m + 4) * (m + 4);
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P * kG32N * FR) return;
+  const int64_t p = t / (int64_t(kG32N) * FR);
+  const int v = int(t - p * kG32N * FR);
+  // frames kGeoE.. of the FP64 table hold the edges in the same order, and
+  // frames kGeoC.. the centres
+  const double* g = geo + size_t(p) * kGeoN * FR;
+  g32[t] = float(v < 14 * FR ? g[kGeoE * FR + v] : g[kGeoC * FR + (v - 14 * FR)]);
 }
 
 // waves W[w][k], speeds s[w] (times gamma), fluctuations, mass flux fl;
@@ -286,6 +305,7 @@ struct SphereArgs {
   R* phi;
   int32_t* err;
   const double* __restrict__ geo;
+  const float* __restrict__ geo32;   // FP32 state: edges and centres in FP32
   int P, m, lm, limiter, transverse;
   double g;
 };
@@ -340,6 +360,12 @@ k_sphere_step(SphereArgs<R> A) {
   const PatchRec& rp = A.rec[p];
   const double dx = ldexp(1.0, -rp.level) / m;
   const double* geo = A.geo + size_t(p) * kGeoN * FR;
+  // edge frames and centres: the FP32 copy for FP32 state
+  const float* g32 = sizeof(R) == 4 ? A.geo32 + size_t(p) * kG32N * FR : nullptr;
+  auto edge = [&](int d, int f) -> SEdge<R> {
+    if constexpr (sizeof(R) == 4) return load_edge<R>(g32 + kG32E * FR + (d * FR + f) * 7);
+    else return load_edge<R>(geo + kGeoE * FR + (d * FR + f) * 7);
+  };
   for (int f = threadIdx.x; f < FRT; f += blockDim.x) {
     const int i = i0 + f % FT - 1, j = j0 + f / FT - 1;
     const bool outer = (i == -1 || i == m + 2) && (j == -1 || j == m + 2);
@@ -365,7 +391,7 @@ k_sphere_step(SphereArgs<R> A) {
       ql[k] = Qs[k * FRT + lf(il, jl)];
       qr[k] = Qs[k * FRT + lf(ir, jr)];
     }
-    const SEdge<R> eg = load_edge<R>(geo + kGeoE * FR + (d * FR + pf(ir, jr)) * 7);
+    const SEdge<R> eg = edge(d, pf(ir, jr));
     R* o = E(d, e, r);
     R W[3][4], s[3], am[4], ap[4], fl;
     if (!rp_sphere<R>(grav, eg, ql, qr, W, s, am, ap, fl)) {
@@ -444,8 +470,8 @@ k_sphere_step(SphereArgs<R> A) {
       const R h = R(-0.5 * (side == 0 ? dtdl : dtdr));
       const int ci = cell_i(d, col, r), cj = cell_j(d, col, r);
       const int ui = cell_i(d, col, r + 1), uj = cell_j(d, col, r + 1);
-      const SEdge<R> lo = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + pf(ci, cj)) * 7);
-      const SEdge<R> hi = load_edge<R>(geo + kGeoE * FR + ((1 - d) * FR + pf(ui, uj)) * 7);
+      const SEdge<R> lo = edge(1 - d, pf(ci, cj));
+      const SEdge<R> hi = edge(1 - d, pf(ui, uj));
       R bm[4], bp[4];
       const R* psi = side == 0 ? amt : apt;
       if (ok) {
@@ -492,9 +518,12 @@ k_sphere_step(SphereArgs<R> A) {
       out[k] = Qs[k * FRT + f] - dtd * fx - dtd * gy;
     }
     // momentum onto the tangent plane at the cell centre
-    const double* rc = geo + kGeoC * FR + 3 * pf(i, j);
-    const R mr = out[1] * R(rc[0]) + out[2] * R(rc[1]) + out[3] * R(rc[2]);
-    for (int k = 0; k < 3; ++k) out[1 + k] -= mr * R(rc[k]);
+    R rc[3];
+    for (int k = 0; k < 3; ++k)
+      rc[k] = sizeof(R) == 4 ? R(g32[kG32C * FR + 3 * pf(i, j) + k])
+                             : R(geo[kGeoC * FR + 3 * pf(i, j) + k]);
+    const R mr = out[1] * rc[0] + out[2] * rc[1] + out[3] * rc[2];
+    for (int k = 0; k < 3; ++k) out[1 + k] -= mr * rc[k];
     for (int k = 0; k < 4; ++k)
       A.qn[(size_t(p * 4 + k) * m + (j0 + j - 1)) * m + (i0 + i - 1)] = out[k];
   }
