@@ -475,8 +475,8 @@ def main():
     args = parse()
     TUNE["tile"], TUNE["threads"] = args.tile, args.threads
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the "
-              "multi-GPU layout is described in DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the path "
+              "has no multi-GPU layout built", file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():

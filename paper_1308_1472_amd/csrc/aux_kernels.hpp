@@ -170,8 +170,8 @@ k_reflux(const R* __restrict__ q, R* __restrict__ qn,
     const int32_t link = end >= 0 ? ax.link[end] : -1;
     if (it.face < 2 || link < 0) {
       R c0[MEQN], c1[MEQN];
-      size_t o, o1;
-      double dxc, dxc1;     // the second correction is on the same coarse cell
+      size_t o, o1;          // o1 == o: the second correction is on the same cell
+      double dxc, dxc1;
       reflux_corr<R, PHYS>(q, it, ax, tc, phi, m, ph, err, c0, o, dxc);
       const bool two = it.face < 2 && link >= 0;
       if (two)
