@@ -194,13 +194,29 @@ def run(precision, fused, steps, warmup, uniform_level=None):
     b.record()
     torch.cuda.synchronize()
     w.numax.zero_()
-    return {
+    out = {
         "seconds": el, "cells": cells, "rate": cells / el,
         "kernel_ms_mean": a.elapsed_time(b) / nk,
         "kernel_cells_mean": float(w.ctx.num_patches() * w.M * w.M),
         "patches_last": w.ctx.num_patches(),
         "status": status,
     }
+    if uniform_level is not None:
+        out["_state"] = q                 # for the FP32-vs-FP64 comparison
+    return out
+
+
+def rel_l1(a, b, meqn, cells):
+    """Largest relative L1 difference over the components of two states of
+    one forest (compact layout: patch, component, cells), a against b."""
+    a = a.double().view(-1, meqn, cells)
+    b = b.double().view(-1, meqn, cells)
+    worst = 0.0
+    for k in range(meqn):
+        den = b[:, k].abs().sum().item()
+        if den > 0:
+            worst = max(worst, (a[:, k] - b[:, k]).abs().sum().item() / den)
+    return worst
 
 
 def run_batch(steps, warmup, nforests=64, graph_steps=10):
@@ -494,9 +510,15 @@ def main():
         print(f"# fp64 plain: {res['fp64']}", file=sys.stderr, flush=True)
     if args.only in ("large", "all"):
         res["large32"] = run(32, True, args.large_steps, 3, uniform_level=8)
+        s32 = res["large32"].pop("_state")
         print(f"# large fp32: {res['large32']}", file=sys.stderr, flush=True)
         res["large64"] = run(64, False, args.large_steps, 3, uniform_level=8)
-        print(f"# large fp64: {res['large64']}", file=sys.stderr, flush=True)
+        s64 = res["large64"].pop("_state")
+        # the same dam break, steps and dt rule in both precisions
+        res["large32"]["rel_l1_vs_fp64"] = rel_l1(s32, s64, 3, 16 * 16)
+        del s32, s64
+        print(f"# large fp64: {res['large64']}; fp32 vs fp64 rel L1 "
+              f"{res['large32']['rel_l1_vs_fp64']:.3e}", file=sys.stderr, flush=True)
     if args.only in ("batch", "all"):
         res["batch"] = run_batch(args.batch_steps, 10)
         print(f"# batch fp32: {res['batch']}", file=sys.stderr, flush=True)
@@ -576,6 +598,7 @@ def main():
             "cells": res["large32"]["kernel_cells_mean"],
             "fp32_fused_rate": res["large32"]["rate"],
             "fp64_plain_rate": res["large64"]["rate"],
+            "fp32_rel_l1_vs_fp64": res["large32"]["rel_l1_vs_fp64"],
             "fp32_roofline": roof(res["large32"], 24.0, "k_step_fused_sw_fp32_level8.txt"),
             "fp64_roofline": roof(res["large64"], 48.0, "k_step_plain_sw_fp64_level8.txt"),
         }
