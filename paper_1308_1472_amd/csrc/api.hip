@@ -748,14 +748,14 @@ static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lm
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   std::vector<fcx_leaf> out;
+  std::vector<int32_t> kind, src;
   std::string err;
-  int rc = regrid(c->forest, tags, lmin, lmax, out, err);
+  int rc = regrid(c->forest, tags, lmin, lmax, out, err, &kind, &src);
   if (rc != FCX_OK) return fail(rc, err);
+  for (int32_t k : kind)
+    if (k < 0) return fail(FCX_EINVAL, "new leaf is not a copy, child or parent of old leaves");
   Forest nf;
   rc = nf.assign(c->trees, std::move(out), err);
-  if (rc != FCX_OK) return fail(rc, err);
-  std::vector<int32_t> kind, src;
-  rc = transfer_plan(c->forest, nf, kind, src, err);
   if (rc != FCX_OK) return fail(rc, err);
   // the current device forest becomes the old one
   std::swap(c->cur, c->old);

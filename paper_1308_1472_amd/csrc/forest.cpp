@@ -771,7 +771,8 @@ int update_plan(const Forest& f, int m, const Plan& old,
 // tentative forest, as a full ripple would give.
 template <class Set>
 static int regrid_with(const Forest& f, const int8_t* tags, int lmin, int lmax, Set& set,
-                       std::vector<fcx_leaf>& out, std::string& err) {
+                       std::vector<fcx_leaf>& out, std::string& err,
+                       std::vector<int32_t>* kind, std::vector<int32_t>* src) {
   const int64_t n = int64_t(f.leaves.size());
   std::deque<fcx_leaf> work;
   std::vector<int64_t> merged;                 // first child of each merge
@@ -846,14 +847,26 @@ static int regrid_with(const Forest& f, const int8_t* tags, int lmin, int lmax, 
   // the new leaves in SFC order, by walking the old ones in order: an old
   // leaf is kept, the first child of a merged family, or the root of a
   // subtree of new leaves (refined, possibly split further by the ripple)
+  // with kind / src: the transfer plan of each new leaf (0 kept, 1 child of
+  // a refined old leaf, 2 parent of a merged family; -1 a leaf the transfer
+  // cannot fill) and its old leaf (the first child for a merge)
   out.clear();
   out.reserve(set.size());
+  if (kind) { kind->clear(); kind->reserve(set.size()); }
+  if (src) { src->clear(); src->reserve(set.size()); }
+  auto plan = [&](int32_t k, int64_t p) {
+    if (kind) kind->push_back(k);
+    if (src) src->push_back(int32_t(p));
+  };
   std::vector<fcx_leaf> stack;
   for (int64_t p = 0; p < n; ++p) {
     const fcx_leaf& a = f.leaves[p];
-    if (set.has(a.tree, a.level, a.ix, a.iy)) { out.push_back(a); continue; }
+    if (set.has(a.tree, a.level, a.ix, a.iy)) { out.push_back(a); plan(0, p); continue; }
     if (a.level > 0 && set.has(a.tree, a.level - 1, a.ix >> 1, a.iy >> 1)) {
-      if (!(a.ix & 1) && !(a.iy & 1)) out.push_back({a.tree, a.level - 1, a.ix >> 1, a.iy >> 1});
+      if (!(a.ix & 1) && !(a.iy & 1)) {
+        out.push_back({a.tree, a.level - 1, a.ix >> 1, a.iy >> 1});
+        plan(2, p);
+      }
       continue;
     }
     stack.assign(1, a);
@@ -874,6 +887,7 @@ static int regrid_with(const Forest& f, const int8_t* tags, int lmin, int lmax, 
         stack.pop_back();
         e.tree = -1 - e.tree;
         out.push_back(e);
+        plan(e.level == a.level + 1 ? 1 : -1, p);
       }
     }
   }
@@ -885,17 +899,18 @@ static int regrid_with(const Forest& f, const int8_t* tags, int lmin, int lmax, 
 }
 
 int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
-           std::vector<fcx_leaf>& out, std::string& err) {
+           std::vector<fcx_leaf>& out, std::string& err, std::vector<int32_t>* kind,
+           std::vector<int32_t>* src) {
   const size_t n = f.leaves.size();
   // the finest level the tentative leaves can reach
   const int L = std::max(f.maxlevel, std::min(lmax, f.maxlevel + 1));
   const uint64_t cells = uint64_t(f.trees.size()) << (2 * L);
   if (L <= kMaxLevel && cells <= uint64_t(FCX_DENSE_FACTOR) * (n + 1024)) {
     DenseLeafSet set(int(f.trees.size()), L);
-    return regrid_with(f, tags, lmin, lmax, set, out, err);
+    return regrid_with(f, tags, lmin, lmax, set, out, err, kind, src);
   }
   HashLeafSet set(n * 2 + 64);
-  return regrid_with(f, tags, lmin, lmax, set, out, err);
+  return regrid_with(f, tags, lmin, lmax, set, out, err, kind, src);
 }
 
 int transfer_plan(const Forest& old_f, const Forest& new_f,

@@ -140,9 +140,12 @@ int update_plan(const Forest& f, int m, const Plan& old,
                 const std::vector<int32_t>& kind, const std::vector<int32_t>& src,
                 Plan& plan, std::string& err, bool sync = false);
 
-// Regrid: refine +1, merge complete families tagged -1, then balance.
+// Regrid: refine +1, merge complete families tagged -1, then balance.  With
+// kind and src, also the transfer plan of the new leaves (as transfer_plan
+// gives it; kind -1 marks a leaf the transfer cannot fill).
 int regrid(const Forest& f, const int8_t* tags, int lmin, int lmax,
-           std::vector<fcx_leaf>& out, std::string& err);
+           std::vector<fcx_leaf>& out, std::string& err,
+           std::vector<int32_t>* kind = nullptr, std::vector<int32_t>* src = nullptr);
 
 // Transfer plan from an old to a new forest: per new patch kind
 // (0 copy, 1 refined from an old coarser patch, 2 merged from four old

@@ -3,7 +3,8 @@
 // regrid, the transfer plan, plan updates and fresh plan builds, with lookups
 // that hit and miss.  It prints one digest per forest (the caller compares
 // builds with different lookup structures) and exits non-zero if an updated
-// plan, written over the storage of an older one, differs from a fresh build.
+// plan, written over the storage of an older one, differs from a fresh build,
+// or if the transfer plan the regrid emits differs from transfer_plan's.
 #include <cstdio>
 #include <cstring>
 #include <random>
@@ -88,7 +89,8 @@ int main() {
       std::vector<int8_t> tags(f.leaves.size());
       for (auto& t : tags) { const int r = int(rng() % 10); t = r < 1 ? 1 : (r < 5 ? -1 : 0); }
       std::vector<fcx_leaf> out;
-      rc = regrid(f, tags.data(), 1, maxl + 1, out, err);
+      std::vector<int32_t> rkind, rsrc;
+      rc = regrid(f, tags.data(), 1, maxl + 1, out, err, &rkind, &rsrc);
       mix(&rc, 4); mixv(out);
       Forest nf;
       rc = nf.assign(trees, out, err);
@@ -96,6 +98,7 @@ int main() {
       std::vector<int32_t> kind, src;
       rc = transfer_plan(f, nf, kind, src, err);
       mix(&rc, 4); mixv(kind); mixv(src);
+      if (kind != rkind || src != rsrc) ++mismatches;   // the regrid's own plan
       Plan pb;
       rc = update_plan(nf, 16, p, kind, src, pu, err, trial % 2);
       mix(&rc, 4); mixplan(pu);
