@@ -138,6 +138,21 @@ int64_t fcx_state_elems(const fcx_ctx *ctx);   /* P * meqn * m * m        */
 int64_t fcx_ghost_elems(const fcx_ctx *ctx);   /* P * meqn * (8m + 16)    */
 int fcx_get_leaves(const fcx_ctx *ctx, int64_t cap, fcx_leaf *out);
 
+/* Read-only host copy of the current forest's patch tables (Sec. 2: each
+ * leaf's neighbours and their orientation), for tests and tools; waits for
+ * the device.  recs: P records of 24 int32 (level, ix, iy, flags, 12
+ * neighbour ids: faces 0-3 two slots each, then corners 0-3; 8 orientation
+ * codes: faces, then corners); phislot: P face-term slots (-1: none);
+ * family: P flags (1 at the first child of a complete family of leaf
+ * siblings); counts: {slots, xi items, eta items}.  With items / aux (either
+ * may be null), the coarse-fine items in reflux order, 8 int32 each (coarse
+ * patch, face, two fine patches, their faces, their reversal flags), and
+ * their companions, 6 int32 each (the other direction's items at the low and
+ * high end, the coarse and the two fine face-term slots, the coarse level);
+ * FCX_EINVAL if there are more than cap_items. */
+int fcx_patch_table(fcx_ctx *ctx, int64_t cap_items, void *recs, int32_t *phislot,
+                    int32_t *family, int32_t *counts, void *items, void *aux);
+
 /* ---- the time step -------------------------------------------------- */
 
 /* Ghost fill (Sec. 3): each ghost cell takes its value from the leaf that

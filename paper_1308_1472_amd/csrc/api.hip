@@ -111,6 +111,7 @@ struct DevForest {
   int32_t* family = nullptr;
   RefluxItem* reflux = nullptr;
   RefluxAux* aux = nullptr;          // per reflux item: partners, slots, level
+  int32_t* counts = nullptr;         // {slots, xi items, eta items} on the device
   int32_t* first = nullptr;          // {0, P} for the sum reduction
   int32_t* xkind = nullptr;          // transfer plan from the previous forest
   int32_t* xsrc = nullptr;
@@ -335,13 +336,13 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   // of the other direction on the same coarse patch whose faces meet its own
   // at its low and high end (the corner cell both correct)
   const size_t NI = plan.reflux.size();
-  size_t off[9];
+  size_t off[10];
   size_t at = 0;
-  const size_t sz[8] = {P * sizeof(PatchRec), P * 4, P * 4,
+  const size_t sz[9] = {P * sizeof(PatchRec), P * 4, P * 4,
                         NI * sizeof(RefluxItem), 2 * 4,
-                        kind ? P * 4 : 0, src ? P * 4 : 0, NI * sizeof(RefluxAux)};
-  for (int k = 0; k < 8; ++k) { off[k] = at; at += align256(sz[k]); }
-  off[8] = at;
+                        kind ? P * 4 : 0, src ? P * 4 : 0, NI * sizeof(RefluxAux), 3 * 4};
+  for (int k = 0; k < 9; ++k) { off[k] = at; at += align256(sz[k]); }
+  off[9] = at;
   HIPCHK(c->staging.ensure(at));
   uint8_t* h = c->staging.p;
   {
@@ -383,6 +384,8 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   std::memcpy(h + off[4], first, sz[4]);
   if (kind) std::memcpy(h + off[5], kind->data(), sz[5]);
   if (src) std::memcpy(h + off[6], src->data(), sz[6]);
+  const int32_t counts[3] = {plan.nslots, dev.n_reflux_x, dev.n_reflux_y};
+  std::memcpy(h + off[8], counts, sz[8]);
   HIPCHK(dev.blob.ensure(at));
   if (ordered) {
     if (!c->staged) HIPCHK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
@@ -401,6 +404,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   dev.xkind = kind ? reinterpret_cast<int32_t*>(d + off[5]) : nullptr;
   dev.xsrc = src ? reinterpret_cast<int32_t*>(d + off[6]) : nullptr;
   dev.aux = reinterpret_cast<RefluxAux*>(d + off[7]);
+  dev.counts = reinterpret_cast<int32_t*>(d + off[8]);
   dev.nslots = plan.nslots;
   dev.P = int64_t(P);
   std::swap(c->plan, c->spare);
@@ -473,6 +477,29 @@ int fcx_get_leaves(const fcx_ctx* c, int64_t cap, fcx_leaf* out) {
   if (cap < int64_t(c->forest.leaves.size()) || !out)
     return fail(FCX_EINVAL, "capacity too small");
   std::copy(c->forest.leaves.begin(), c->forest.leaves.end(), out);
+  return FCX_OK;
+}
+
+int fcx_patch_table(fcx_ctx* c, int64_t cap_items, void* recs, int32_t* phislot,
+                    int32_t* family, int32_t* counts, void* items, void* aux) {
+  if (!c || !recs || !phislot || !family || !counts)
+    return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  HIPCHK(hipDeviceSynchronize());
+  const size_t P = size_t(c->cur.P);
+  HIPCHK(hipMemcpy(counts, c->cur.counts, 3 * sizeof(int32_t), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(recs, c->cur.rec, P * sizeof(PatchRec), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(phislot, c->cur.phislot, P * 4, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(family, c->cur.family, P * 4, hipMemcpyDeviceToHost));
+  const int64_t n = int64_t(counts[1]) + counts[2];
+  if (n > 0 && (items || aux)) {
+    if (n > cap_items) return fail(FCX_EINVAL, "item capacity too small");
+    if (items)
+      HIPCHK(hipMemcpy(items, c->cur.reflux, size_t(n) * sizeof(RefluxItem),
+                       hipMemcpyDeviceToHost));
+    if (aux)
+      HIPCHK(hipMemcpy(aux, c->cur.aux, size_t(n) * sizeof(RefluxAux), hipMemcpyDeviceToHost));
+  }
   return FCX_OK;
 }
 

@@ -30,7 +30,8 @@ EXPORTS = [
     "fcx_last_error", "fcx_version", "fcx_sfc_sort", "fcx_balance",
     "fcx_regrid_leaves",
     "fcx_create", "fcx_destroy", "fcx_upload_forest", "fcx_num_patches",
-    "fcx_state_elems", "fcx_ghost_elems", "fcx_get_leaves", "fcx_ghost_fill",
+    "fcx_state_elems", "fcx_ghost_elems", "fcx_get_leaves", "fcx_patch_table",
+    "fcx_ghost_fill",
     "fcx_patch_step", "fcx_fused_step", "fcx_reflux", "fcx_next_dt",
     "fcx_conservation_sums", "fcx_regrid_tags", "fcx_regrid_apply",
     "fcx_regrid_transfer", "fcx_batch_create", "fcx_batch_destroy",
@@ -87,6 +88,7 @@ def lib():
             getattr(L, f).argtypes = [vp]
             getattr(L, f).restype = i64
         L.fcx_get_leaves.argtypes = [vp, i64, vp]
+        L.fcx_patch_table.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp]
         L.fcx_ghost_fill.argtypes = [vp, vp, vp, vp]
         L.fcx_patch_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.fcx_fused_step.argtypes = [vp, vp, vp, vp, vp, vp]
@@ -276,6 +278,26 @@ class Context:
         out = np.zeros(self.num_patches(), dtype=LEAF_DTYPE)
         _check(lib().fcx_get_leaves(self.h, len(out), _np_ptr(out)))
         return out
+
+    def patch_table(self) -> dict:
+        """Host copy of the patch tables: recs (P, 24), phislot, family,
+        counts (slots, xi items, eta items), items (n, 8), aux (n, 6)."""
+        P = self.num_patches()
+        recs = np.zeros((P, 24), dtype=np.int32)
+        phislot = np.zeros(P, dtype=np.int32)
+        family = np.zeros(P, dtype=np.int32)
+        counts = np.zeros(3, dtype=np.int32)
+        _check(lib().fcx_patch_table(self.h, 0, _np_ptr(recs), _np_ptr(phislot),
+                                     _np_ptr(family), _np_ptr(counts), None, None))
+        n = int(counts[1]) + int(counts[2])
+        items = np.zeros((n, 8), dtype=np.int32)
+        aux = np.zeros((n, 6), dtype=np.int32)
+        if n:
+            _check(lib().fcx_patch_table(self.h, n, _np_ptr(recs), _np_ptr(phislot),
+                                         _np_ptr(family), _np_ptr(counts), _np_ptr(items),
+                                         _np_ptr(aux)))
+        return {"recs": recs, "phislot": phislot, "family": family, "counts": counts,
+                "items": items, "aux": aux}
 
     # ---- tensors ------------------------------------------------------
     def _dt(self):

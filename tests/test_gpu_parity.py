@@ -240,6 +240,32 @@ def test_one_call_regrid_equals_the_separate_calls():
     assert _rel(gpu.state(), want) <= 1e-15
 
 
+@pytest.mark.parametrize("seed", [3, 8])
+def test_tables_after_a_regrid_equal_a_fresh_build(seed):
+    """After a regrid the patch tables are updated incrementally (patches
+    whose neighbourhood is unchanged keep their records, renumbered) and
+    reordered for the device; read back, they equal entry for entry the
+    tables of a fresh upload of the same leaves."""
+    say(f"[tables] seed={seed}")
+    trees, pl = I.walled_square()
+    cfg = fcx.config(16, 64, fcx.FCX_SHALLOW)
+    ctx = fcx.Context(cfg, trees)
+    ctx.upload_forest(fcx.balance(trees, I.random_leaves(seed, 1, 2, 5, 40)))
+    rng = np.random.default_rng(seed)
+    items = 0
+    for r in range(3):
+        tg = rng.integers(-1, 2, ctx.num_patches()).astype(np.int8)
+        ctx.regrid_apply(tg, 1, 6)
+        got = ctx.patch_table()
+        ref = fcx.Context(cfg, trees)
+        ref.upload_forest(ctx.leaves())
+        want = ref.patch_table()
+        for k in ("counts", "recs", "phislot", "family", "items", "aux"):
+            assert np.array_equal(got[k], want[k]), (r, k)
+        items += len(want["items"])
+    assert items > 0
+
+
 def _two_way_coarse_corners(lv):
     """Number of (leaf, corner) pairs whose two faces at that corner both
     border finer leaves: the corner cell takes a reflux correction from an
