@@ -151,43 +151,51 @@ struct NextDtArgs {
 // from the xi item's thread (RefluxAux::link: for an xi item the eta items
 // at its low / high end, for an eta item the xi items there), so the result
 // does not depend on the order the threads run in; such a thread computes
-// both corrections before it updates the cell.  With NEXT, the workgroup
-// that finishes last also takes the CFL check and the next dt.
+// both corrections before it updates the cell.
+template <typename R, int PHYS>
+__device__ __forceinline__ void reflux_cell(const R* __restrict__ q, R* __restrict__ qn,
+                                            const RefluxItem* __restrict__ items,
+                                            const RefluxAux* __restrict__ aux, int32_t i,
+                                            int tc, const R* __restrict__ phi,
+                                            const double* dtp, int m, const KPhys& ph,
+                                            int32_t* err) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  const RefluxItem it = items[i];
+  const RefluxAux ax = aux[i];
+  const int end = tc == 1 ? 0 : (tc == m ? 1 : -1);
+  const int32_t link = end >= 0 ? ax.link[end] : -1;
+  if (it.face >= 2 && link >= 0) return;
+  R c0[MEQN], c1[MEQN];
+  size_t o, o1;          // o1 == o: the second correction is on the same cell
+  double dxc, dxc1;
+  reflux_corr<R, PHYS>(q, it, ax, tc, phi, m, ph, err, c0, o, dxc);
+  const bool two = it.face < 2 && link >= 0;
+  if (two)
+    reflux_corr<R, PHYS>(q, items[link], aux[link], it.face == 0 ? 1 : m, phi, m, ph, err,
+                         c1, o1, dxc1);
+  const R fac = R(*dtp / (dxc * dxc));
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) {
+    const size_t ok = o + size_t(k) * m * m;
+    R v = qn[ok];
+    v -= fac * c0[k];
+    if (two) v -= fac * c1[k];
+    qn[ok] = v;
+  }
+}
+
+// All reflux items in one launch.  With NEXT, the workgroup that finishes
+// last also takes the CFL check and the next dt.
 template <typename R, int PHYS, bool NEXT>
 __global__ void __launch_bounds__(256)
 k_reflux(const R* __restrict__ q, R* __restrict__ qn,
          const RefluxItem* __restrict__ items, const RefluxAux* __restrict__ aux,
          int32_t nitems, const R* __restrict__ phi, const double* dtp, int m, KPhys ph,
          int32_t* err, NextDtArgs nd) {
-  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < int64_t(nitems) * m) {
-    const int32_t i = int32_t(t / m);
-    const int tc = int(t % m) + 1;
-    const RefluxItem it = items[i];
-    const RefluxAux ax = aux[i];
-    const int end = tc == 1 ? 0 : (tc == m ? 1 : -1);
-    const int32_t link = end >= 0 ? ax.link[end] : -1;
-    if (it.face < 2 || link < 0) {
-      R c0[MEQN], c1[MEQN];
-      size_t o, o1;          // o1 == o: the second correction is on the same cell
-      double dxc, dxc1;
-      reflux_corr<R, PHYS>(q, it, ax, tc, phi, m, ph, err, c0, o, dxc);
-      const bool two = it.face < 2 && link >= 0;
-      if (two)
-        reflux_corr<R, PHYS>(q, items[link], aux[link], it.face == 0 ? 1 : m, phi, m, ph,
-                             err, c1, o1, dxc1);
-      const R fac = R(*dtp / (dxc * dxc));
-#pragma unroll
-      for (int k = 0; k < MEQN; ++k) {
-        const size_t ok = o + size_t(k) * m * m;
-        R v = qn[ok];
-        v -= fac * c0[k];
-        if (two) v -= fac * c1[k];
-        qn[ok] = v;
-      }
-    }
-  }
+  if (t < int64_t(nitems) * m)
+    reflux_cell<R, PHYS>(q, qn, items, aux, int32_t(t / m), int(t % m) + 1, phi, dtp, m, ph,
+                         err);
   if (NEXT) {
     __shared__ bool last;
     __syncthreads();

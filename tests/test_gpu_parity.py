@@ -280,16 +280,17 @@ def _two_way_coarse_corners(lv):
     return n
 
 
-@pytest.mark.parametrize("precision", [64, 32])
-def test_advance_equals_the_three_calls(precision):
-    """fcx_advance (reflux and next dt in one launch) gives bit for bit the
+@pytest.mark.parametrize("precision,m", [(64, 16), (32, 16), (32, 8), (32, 32), (64, 32)])
+def test_advance_equals_the_three_calls(precision, m):
+    """fcx_advance (update, reflux and next dt in one launch: the tile that
+    completes an item's arrivals applies its reflux) gives bit for bit the
     state, dt and flags of fcx_fused_step + fcx_reflux + fcx_next_dt, on a
-    mesh where coarse corner cells take both an xi and an eta correction;
-    the last step exceeds cfl_max so the flag path runs too."""
+    mesh where coarse corner cells take both an xi and an eta correction,
+    with one tile per patch (m = 8, 16) and four (m = 32); the last step
+    exceeds cfl_max so the flag path runs too."""
     import torch
-    say(f"[advance] precision={precision}")
+    say(f"[advance] precision={precision} m={m}")
     trees, pl = I.walled_square()
-    m = 16
     lv = fcx.balance(trees, I.random_leaves(21, 1, 2, 5, 40))
     assert _two_way_coarse_corners(lv) > 0
     q0 = smooth_sw_state(lv, m, pl, 5)
