@@ -242,8 +242,9 @@ int fcx_regrid_apply(fcx_ctx *ctx, const int8_t *tags_host, int32_t lmin,
                      int32_t lmax, int64_t *n_new);
 
 /* fcx_ghost_fill of q into ghost, fcx_regrid_tags, the tags to the host
- * and fcx_regrid_apply, in one call (waits for the stream to reach the
- * tags).  The new forest's tables are copied to the device in the order of
+ * and fcx_regrid_apply, in one call (the calling thread polls until the
+ * stream has reached the tags, so it spins for as long as the work queued
+ * before them takes).  The new forest's tables are copied to the device in the order of
  * `stream`: later calls that use them go on the same stream or wait for it.
  * The ghost buffer then holds the fill that fcx_regrid_transfer needs;
  * *n_new receives the new patch count. */

@@ -143,11 +143,13 @@ struct fcx_ctx {
   HostBuf tags_host;               //   and their pinned host copy
   hipEvent_t staged = nullptr;     // end of the last stream-ordered plan upload
   bool staged_pending = false;     //   from `staging`, not yet waited for
+  hipEvent_t tags_ready = nullptr; // the tags of a regrid are on the host
   ~fcx_ctx() {
     if (staged) {
       (void)hipEventSynchronize(staged);
       (void)hipEventDestroy(staged);
     }
+    if (tags_ready) (void)hipEventDestroy(tags_ready);
   }
 };
 
@@ -782,8 +784,7 @@ static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lm
   for (int32_t k : kind)
     if (k < 0) return fail(FCX_EINVAL, "new leaf is not a copy, child or parent of old leaves");
   Forest nf;
-  rc = nf.assign(c->trees, std::move(out), err);
-  if (rc != FCX_OK) return fail(rc, err);
+  nf.adopt(c->trees, std::move(out));
   // the current device forest becomes the old one
   std::swap(c->cur, c->old);
   c->old_forest = std::move(c->forest);
@@ -1338,7 +1339,15 @@ int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double
   if (rc != FCX_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
   HIPCHK(hipMemcpyAsync(c->tags_host.p, c->tags_dev.p, size_t(P), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+  // the host planner is the next step of the critical path: poll for the
+  // tags rather than sleep until the runtime wakes this thread
+  if (!c->tags_ready) HIPCHK(hipEventCreateWithFlags(&c->tags_ready, hipEventDisableTiming));
+  HIPCHK(hipEventRecord(c->tags_ready, s));
+  for (;;) {
+    const hipError_t e = hipEventQuery(c->tags_ready);
+    if (e == hipSuccess) break;
+    if (e != hipErrorNotReady) HIPCHK(e);
+  }
   return regrid_apply(c, reinterpret_cast<const int8_t*>(c->tags_host.p), lmin, lmax, n_new,
                       s, true);
 }

@@ -183,6 +183,19 @@ int Forest::assign(const std::vector<fcx_tree>& t, std::vector<fcx_leaf> l,
     err = "leaf with an unknown tree";
     return FCX_EINVAL;
   }
+  build_index();
+  return FCX_OK;
+}
+
+void Forest::adopt(const std::vector<fcx_tree>& t, std::vector<fcx_leaf> l) {
+  trees = t;
+  leaves = std::move(l);
+  maxlevel = 0;
+  for (const fcx_leaf& a : leaves) maxlevel = std::max(maxlevel, int(a.level));
+  build_index();
+}
+
+void Forest::build_index() {
   const uint64_t cells = uint64_t(trees.size()) << (2 * maxlevel);
   if (cells <= uint64_t(FCX_DENSE_FACTOR) * (leaves.size() + 1024)) {
     dense_level_ = maxlevel;
@@ -205,7 +218,6 @@ int Forest::assign(const std::vector<fcx_tree>& t, std::vector<fcx_leaf> l,
       index_.put(pack_key(a.tree, a.level, a.ix, a.iy), int32_t(q));
     }
   }
-  return FCX_OK;
 }
 
 int64_t Forest::find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const {

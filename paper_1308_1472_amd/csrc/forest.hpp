@@ -63,6 +63,10 @@ class Forest {
   // leaf index.  Returns FCX_OK or an error code with a message in err.
   int assign(const std::vector<fcx_tree>& t, std::vector<fcx_leaf> l,
              std::string& err);
+  // Leaves that regrid() made from a forest over the same trees: they are
+  // SFC-sorted and tile every tree by construction, so only the leaf index
+  // is built.
+  void adopt(const std::vector<fcx_tree>& t, std::vector<fcx_leaf> l);
   int64_t find(int32_t tree, int32_t level, int64_t ix, int64_t iy) const;
   // leaf containing an in-tree point, -1 if none; levels near `hint` are
   // probed first
@@ -83,6 +87,7 @@ class Forest {
   LeafIndex index_;
   std::vector<int32_t> dense_;
   int dense_level_ = -1;
+  void build_index();
 };
 
 int check_connectivity(const std::vector<fcx_tree>& trees, std::string& err);

@@ -95,6 +95,10 @@ int main() {
       Forest nf;
       rc = nf.assign(trees, out, err);
       mix(&rc, 4);
+      if (rc != FCX_OK) ++mismatches;   // regrid output must validate
+      Forest na;                        // what the library keeps: no re-validation
+      na.adopt(trees, out);
+      if (na.maxlevel != nf.maxlevel) ++mismatches;
       std::vector<int32_t> kind, src;
       rc = transfer_plan(f, nf, kind, src, err);
       mix(&rc, 4); mixv(kind); mixv(src);
@@ -109,13 +113,17 @@ int main() {
         const int l = int(rng() % (maxl + 3)) - 1;
         int64_t ix = int64_t(rng() % 4096) - 8, iy = int64_t(rng() % 4096) - 8;
         if (l >= 0 && l < 12) { ix >>= (12 - l); iy >>= (12 - l); }
-        const int64_t r1 = nf.find(int32_t(rng() % (trees.size() + 1)), l, ix, iy);
+        const int32_t tf = int32_t(rng() % (trees.size() + 1));
+        const int64_t r1 = nf.find(tf, l, ix, iy);
         mix(&r1, 8);
+        if (na.find(tf, l, ix, iy) != r1) ++mismatches;
         const int64_t x = int64_t(rng()) % (kSide + 100) - 50;
         const int64_t y = int64_t(rng()) % (kSide + 100) - 50;
-        const int64_t r2 = nf.leaf_at(int32_t(rng() % trees.size()), x, y,
-                                      (k & 1) ? -1 : int(rng() % (maxl + 1)));
+        const int32_t tl = int32_t(rng() % trees.size());
+        const int hint = (k & 1) ? -1 : int(rng() % (maxl + 1));
+        const int64_t r2 = nf.leaf_at(tl, x, y, hint);
         mix(&r2, 8);
+        if (na.leaf_at(tl, x, y, hint) != r2) ++mismatches;
       }
       f = std::move(nf);
       std::swap(p, pu);
