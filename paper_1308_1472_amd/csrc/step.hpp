@@ -45,12 +45,14 @@ struct StepArgs {
 
 template <int T> struct TileThreads { static constexpr int value = T * T >= 256 ? 256 : T * T; };
 
-// Fast reciprocal / root: hardware approximations in FP32 (the FP32 path is
-// held to 1e-5), correctly rounded operations in FP64.
+// Fast reciprocal / root: the hardware instructions in FP32 (about 1 ulp;
+// the FP32 path is held to 1e-5, and a correctly rounded square root costs
+// some fifteen instructions more), correctly rounded operations in FP64.
 __device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
+__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
 
 template <typename R>
 __device__ __forceinline__ R limiter_phi(int lim, R th) {
@@ -109,10 +111,14 @@ template <typename R, int PHYS, int T, int NT>
 struct TileLds {
   static constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   static constexpr int WD = PHYS == FCX_ADVECTION ? 1 : 7;   // wave data per edge
-  static constexpr int NPR = PHYS == FCX_ADVECTION ? 1 : 3;  // primitives per cell
+  // per-cell primitives (sqrt h, u, v) are kept for FP64 shallow water; in
+  // FP32 each edge forms them from the state (an rsqrt and a few products),
+  // which leaves room in the LDS for one more resident tile per CU
+  static constexpr bool PRIM = PHYS == FCX_SHALLOW && sizeof(R) == 8;
+  static constexpr int NPR = PRIM ? 3 : 1;
   static constexpr int F = T + 4, NR = T + 2, NE = T + 3;
   R qs[MEQN][F * F];
-  R pr[NPR][F * F];
+  R pr[NPR][PRIM ? F * F : 1];
   R wb[WD][NR * NE];
   R fn[MEQN][T * T];          // normal fluxes, per interior cell
   R tup[MEQN][NR * T];        // transverse flux at a cell's upper
@@ -163,14 +169,18 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
       // primitives: sqrt(h), u, v (zero for a non-positive depth)
       const R h = v[0];
       if (h > R(0)) {
-        const R ih = rcp_(h);
-        pr[0][c] = sqrt_(h);
-        pr[1][c] = v[1] * ih;
-        pr[2][c] = v[2 % MEQN] * ih;
+        if constexpr (TileLds<R, PHYS, T, NT>::PRIM) {
+          const R ih = rcp_(h);
+          pr[0][c] = sqrt_(h);
+          pr[1][c] = v[1] * ih;
+          pr[2][c] = v[2 % MEQN] * ih;
+        }
       } else {
-        pr[0][c] = R(0);
-        pr[1][c] = R(0);
-        pr[2][c] = R(0);
+        if constexpr (TileLds<R, PHYS, T, NT>::PRIM) {
+          pr[0][c] = R(0);
+          pr[1][c] = R(0);
+          pr[2][c] = R(0);
+        }
         atomicOr(A.err, kErrNegDepth);
       }
     }
@@ -259,13 +269,22 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
       if (PHYS == FCX_ADVECTION) {
         wb[0][bidx(r, e)] = qs[0][cr] - qs[0][cl];
       } else {
-        const R sl = pr[0][cl], sr = pr[0][cr];
+        const R hl = qs[0][cl], hr = qs[0][cr];
         R a1 = 0, a2 = 0, a3 = 0, u = 0, v = 0, c = 1, i2c_ = R(0.5);
-        if (sl > R(0) && sr > R(0)) {
-          const R inv = rcp_(sl + sr);
-          u = (sl * pr[mu][cl] + sr * pr[mu][cr]) * inv;
-          v = (sl * pr[mv][cl] + sr * pr[mv][cr]) * inv;
-          const R hl = qs[0][cl], hr = qs[0][cr];
+        if (hl > R(0) && hr > R(0)) {
+          // Roe averages (sqrt(h_l) u_l + sqrt(h_r) u_r) / (sqrt(h_l) + sqrt(h_r))
+          if constexpr (TileLds<R, PHYS, T, NT>::PRIM) {
+            const R sl = pr[0][cl], sr = pr[0][cr];
+            const R inv = rcp_(sl + sr);
+            u = (sl * pr[mu][cl] + sr * pr[mu][cr]) * inv;
+            v = (sl * pr[mv][cl] + sr * pr[mv][cr]) * inv;
+          } else {
+            // sqrt(h) u = (h u) / sqrt(h)
+            const R il = rsq_(hl), ir = rsq_(hr);
+            const R inv = rcp_(hl * il + hr * ir);
+            u = (qs[mu][cl] * il + qs[mu][cr] * ir) * inv;
+            v = (qs[mv][cl] * il + qs[mv][cr] * ir) * inv;
+          }
           c = sqrt_(ghalf * (hl + hr));
           i2c_ = R(0.5) * rcp_(c);
           const R d0 = hr - hl, d1 = qs[mu][cr] - qs[mu][cl];
