@@ -222,8 +222,8 @@ def rel_l1(a, b, meqn, cells):
 def run_batch(steps, warmup, nforests=64, graph_steps=10):
     """The 64-forest batch: seeded forests (advection or shallow water by
     seed parity, m in {8, 16, 32}, patch counts log-uniform in 16..16384,
-    levels 2..8), FP32, one persistent launch per tile class, captured in a
-    graph of `graph_steps` steps, tunables from the autotuner."""
+    levels 2..8), FP32, one launch per tile class (a workgroup per tile),
+    captured in a graph of `graph_steps` steps, tunables from the autotuner."""
     import torch
     from paper_1308_1472_amd import autotune, fcx
     from paper_1308_1472_amd import inputs as I
@@ -608,7 +608,7 @@ def main():
         out["batched_64_forests"] = {
             "workload": "64 seeded forests, advection or shallow water, m in "
                         "{8,16,32}, 16..16384 patches each, levels 2-8, FP32, "
-                        "one persistent launch per tile class in a HIP graph",
+                        "one launch per tile class (a workgroup per tile) in a HIP graph",
             "patches": rb["patches"], "cells": rb["cells"], "rate": rb["rate"],
             "ms_per_step": rb["ms_per_step"], "tuning": rb["tuning"],
             "hbm_GBps_algorithmic_whole_step": ach,

@@ -1,9 +1,8 @@
-"""Autotuner of the batched persistent launch.
+"""Autotuner of the batched launch.
 
 Measures every combination of the batch tunables -- tile of forests with
-m >= 16 (8 or 16), threads per 8 x 8 and 16 x 16 tile, resident workgroups
-per CU -- on a scratch copy of the state, through captured graphs, and keeps
-the fastest.  Results are cached per device and batch composition in
+m >= 16 (8 or 16), threads per 8 x 8 and 16 x 16 tile -- on a scratch copy
+of the state, through captured graphs, and keeps the fastest.  Results are cached per device and batch composition in
 `_build/autotune.json` next to the library.
 """
 from __future__ import annotations
@@ -20,13 +19,14 @@ SPACE = {
     "tile_big": (8, 16),
     "threads8": (64, 128),
     "threads16": (256, 512),
-    "wg_per_cu": (0, 2, 4, 8),
 }
 
 
 def signature(batch) -> str:
     import torch
-    parts = [torch.cuda.get_device_name(0), str(batch.precision)]
+    # the tunables' names are part of the key: a change of the space voids
+    # cached choices
+    parts = [torch.cuda.get_device_name(0), str(batch.precision), ",".join(SPACE)]
     for c in batch.contexts:
         parts.append(f"{c.cfg.m}:{c.cfg.physics}:{c.num_patches()}")
     return hashlib.sha256("|".join(parts).encode()).hexdigest()[:20]

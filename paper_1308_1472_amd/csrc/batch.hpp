@@ -1,14 +1,13 @@
-// batch.hpp -- many independent forests advanced together: one persistent
-// fused ghost-gather + update launch per tile class over the tiles of every
-// forest, then per-forest reflux, dt and conservation sums.
+// batch.hpp -- many independent forests advanced together: one fused
+// ghost-gather + update launch per tile class over the tiles of every forest,
+// then per-forest reflux, dt and conservation sums.
 //
 // Forests keep their own patch size, physics and parameters.  Their patch
 // tables are concatenated (neighbour ids are global) and their states are
 // concatenated in one buffer; a small per-forest record gives the bases.
-// Work items (global patch, tile) are split into eight contiguous,
-// cost-balanced ranges, one per XCD: a workgroup takes items from the range
-// of its own XCD through an atomic counter (SFC neighbours then share an L2)
-// and steals from the other ranges once its own is empty.
+// The work items (global patch, tile) of a class all cost the same, so a
+// launch has one workgroup per item, with blocks mapped so that each XCD
+// takes a contiguous run of items (SFC neighbours then share an L2).
 #pragma once
 
 #include "step.hpp"
@@ -35,8 +34,7 @@ struct BatchArgs {
   R* phi;
   int32_t* err;
   const uint32_t* __restrict__ items;      // (patch << 4) | tile
-  const int32_t* __restrict__ range;       // [9] item range of each XCD
-  int32_t* counters;                       // [8 * kCounterStride], zero at launch
+  int32_t item0, nitems;                   // this class's items
 };
 
 // Step arguments of one forest, with base pointers shifted so that global
@@ -63,68 +61,22 @@ __device__ __forceinline__ StepArgs<R> forest_args(const BatchArgs<R>& B, int f,
   return A;
 }
 
-// one work counter per XCD, each on a cache line of its own
-constexpr int kCounterStride = 32;
-
-// A value the whole wavefront agrees on, moved to scalar registers 32 bits
-// at a time (so that per-item parameters do not occupy vector registers for
-// the length of a tile).
-template <typename V>
-__device__ __forceinline__ V wave_uniform(const V& v) {
-  static_assert(sizeof(V) % 4 == 0, "32-bit multiple");
-  uint32_t w[sizeof(V) / 4];
-  __builtin_memcpy(w, &v, sizeof(V));
-#pragma unroll
-  for (int i = 0; i < int(sizeof(V) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
-  V out;
-  __builtin_memcpy(&out, w, sizeof(V));
-  return out;
-}
-
-// Persistent launch over the work items of one class (tile size and
-// physics).  Thread 0 takes items through its XCD's counter (stealing from
-// the other XCDs once its own range is spent); the ticket for the next item
-// is drawn before the current tile is processed, so the atomic's latency
-// overlaps the tile's loads.
+// One workgroup per work item of one class (tile size and physics).  Each
+// tile keeps its registers to itself: a persistent form of this kernel, whose
+// loop over items kept the per-item state live across tiles, needed 128
+// registers per thread against 71 here and ran the batch a third slower.
 template <typename R, int PHYS, int T, int NT>
-__global__ void __launch_bounds__(NT, sizeof(R) == 4 ? 4 : 2)
+__global__ void __launch_bounds__(NT)
 k_batch_step(BatchArgs<R> B) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
-  __shared__ int item_sh;
-  int x = blockIdx.x & 7, tries = 0;
-  // resolve a ticket k drawn on counter x into an item, stealing when the
-  // range of x is spent; -1 once every range is
-  auto resolve = [&](int k) -> int {
-    for (;;) {
-      if (B.range[x] + k < B.range[x + 1]) return B.range[x] + k;
-      if (++tries >= 8) return -1;
-      x = (x + 1) & 7;
-      k = atomicAdd(&B.counters[x * kCounterStride], 1);
-    }
-  };
-  if (threadIdx.x == 0) item_sh = resolve(atomicAdd(&B.counters[x * kCounterStride], 1));
-  __syncthreads();
-  for (;;) {
-    const int it = __builtin_amdgcn_readfirstlane(item_sh);
-    if (it < 0) break;
-    int ticket = 0;
-    if (threadIdx.x == 0 && tries < 8) ticket = atomicAdd(&B.counters[x * kCounterStride], 1);
-    const uint32_t w = __builtin_amdgcn_readfirstlane(B.items[it]);
-    const int p = int(w >> 4), tile = int(w & 15);
-    const int f = __builtin_amdgcn_readfirstlane(B.pforest[p]);
-    const ForestDev F = wave_uniform(B.forests[f]);
-    const StepArgs<R> A = wave_uniform(forest_args(B, f, F));
-    const int tps = F.m / T;
-    tile_step<R, PHYS, T, NT, true>(A, p, tile % tps, tile / tps, lds);
-    __syncthreads();                     // item_sh and the tile's LDS are free
-    if (threadIdx.x == 0) item_sh = tries < 8 ? resolve(ticket) : -1;
-    __syncthreads();
-  }
-}
-
-__global__ void k_zero_i32(int32_t* a, int n) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) a[i] = 0;
+  const int it = B.item0 + xcd_tile(blockIdx.x, B.nitems);
+  const uint32_t w = B.items[it];
+  const int p = int(w >> 4), tile = int(w & 15);
+  const int f = B.pforest[p];
+  const ForestDev F = B.forests[f];
+  const StepArgs<R> A = forest_args(B, f, F);
+  const int tps = F.m / T;
+  tile_step<R, PHYS, T, NT, true>(A, p, tile % tps, tile / tps, lds);
 }
 
 // Reflux of a batch: one thread per (coarse-fine face item, coarse cell);
