@@ -267,8 +267,9 @@ int fcx_regrid_transfer(fcx_ctx *ctx, const void *q_old, const void *ghost_old,
 /* A batch advances every leaf of n independent forests (each created and
  * uploaded as its own context; their m and physics may differ, their
  * precision must agree) in one fused ghost-gather + update launch per tile
- * class (8 x 8 tiles for m = 8, the tuned tile size otherwise), one
- * workgroup per tile.
+ * class (8 x 8 tiles for m = 8, the tuned tile size otherwise): one
+ * workgroup per tile, or persistent workgroups that take tiles through
+ * per-XCD work counters.
  * The contexts must outlive the batch.  The state of all forests is one
  * caller-owned buffer: forest f starts at fcx_batch_state_offset(f) and uses
  * the compact layout of its own context.  dt, nu_max and status are device
@@ -281,10 +282,11 @@ int64_t fcx_batch_state_offset(const fcx_batch *batch, int32_t f);
 int64_t fcx_batch_num_patches(const fcx_batch *batch);
 
 /* Tunables (chosen by the autotuner): tile of forests with m >= 16 (8 or
- * 16), threads per 8 x 8 tile (64 or 128) and per 16 x 16 tile (256 or 512).
- * Drops any captured graph. */
+ * 16), threads per 8 x 8 tile (64 or 128) and per 16 x 16 tile (256 or 512),
+ * launch form (0: a workgroup per tile; 1: persistent).  Drops any captured
+ * graph. */
 int fcx_batch_set_tuning(fcx_batch *batch, int32_t tile_big, int32_t threads8,
-                         int32_t threads16);
+                         int32_t threads16, int32_t persistent);
 
 /* One step of every forest: fused ghost gather + update (per forest: its own
  * dt), reflux, per-forest next dt as fcx_next_dt.  q_new must not alias q. */

@@ -1,8 +1,9 @@
 """Autotuner of the batched launch.
 
 Measures every combination of the batch tunables -- tile of forests with
-m >= 16 (8 or 16), threads per 8 x 8 and 16 x 16 tile -- on a scratch copy
-of the state, through captured graphs, and keeps the fastest.  Results are cached per device and batch composition in
+m >= 16 (8 or 16), threads per 8 x 8 and 16 x 16 tile, a workgroup per tile
+or persistent workgroups -- on a scratch copy of the state, through captured
+graphs, and keeps the fastest.  Results are cached per device and batch composition in
 `_build/autotune.json` next to the library.
 """
 from __future__ import annotations
@@ -19,6 +20,7 @@ SPACE = {
     "tile_big": (8, 16),
     "threads8": (64, 128),
     "threads16": (256, 512),
+    "persistent": (0, 1),
 }
 
 

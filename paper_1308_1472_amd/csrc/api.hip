@@ -857,8 +857,9 @@ struct fcx_batch {
   std::vector<ForestDev> fh;
   std::vector<int64_t> state_off;
   int64_t state_elems = 0, P = 0;
-  // tuning: tile used by forests with m >= 16, threads per tile class
-  int32_t tile_big = 16, threads8 = 64, threads16 = 256;
+  // tuning: tile used by forests with m >= 16, threads per tile class, and
+  // the launch form (0: a workgroup per tile; 1: persistent workgroups)
+  int32_t tile_big = 16, threads8 = 64, threads16 = 256, persistent = 0;
   // device data
   DevBuf<uint8_t> blob;
   PatchRec* rec = nullptr;
@@ -866,6 +867,7 @@ struct fcx_batch {
   int32_t* pforest = nullptr;
   ForestDev* forests = nullptr;
   uint32_t* items = nullptr;
+  int32_t* range = nullptr;           // [class][9]: item range of each XCD
   RefluxItem* reflux = nullptr;
   int32_t* reflux_forest = nullptr;
   int32_t* first = nullptr;           // [n + 1] patch offsets
@@ -874,8 +876,9 @@ struct fcx_batch {
   int32_t nitems[4] = {0, 0, 0, 0}, item0[4] = {0, 0, 0, 0};
   DevBuf<uint8_t> phi;
   DevBuf<double> partial;
-  DevBuf<int32_t> err;
+  DevBuf<int32_t> counters, err;    // counters: persistent launches
   HostBuf staging;
+  int cus = 256;
   // captured graph
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
@@ -951,24 +954,30 @@ static int batch_build(fcx_batch* b) {
   b->n_reflux_y = int32_t(ry.size());
   rx.insert(rx.end(), ry.begin(), ry.end());
   rfx.insert(rfx.end(), rfy.begin(), rfy.end());
-  // the items of the four classes, one after the other
+  // the items of the four classes, one after the other; for persistent
+  // launches each class is cut into eight equal runs, one per XCD (the
+  // items of a class cost the same)
   std::vector<uint32_t> all;
+  std::vector<int32_t> ranges(4 * 9, 0);
   for (int cls = 0; cls < 4; ++cls) {
     b->item0[cls] = int32_t(all.size());
     b->nitems[cls] = int32_t(items[cls].size());
+    for (int x = 0; x <= 8; ++x)
+      ranges[cls * 9 + x] =
+          b->item0[cls] + int32_t(int64_t(b->nitems[cls]) * x / 8);
     all.insert(all.end(), items[cls].begin(), items[cls].end());
   }
   // one packed upload
-  const size_t sz[8] = {recs.size() * sizeof(PatchRec), phislot.size() * 4,
+  const size_t sz[9] = {recs.size() * sizeof(PatchRec), phislot.size() * 4,
                         pforest.size() * 4, b->fh.size() * sizeof(ForestDev),
                         all.size() * 4, rx.size() * sizeof(RefluxItem),
-                        rfx.size() * 4, first.size() * 4};
-  const void* src[8] = {recs.data(), phislot.data(), pforest.data(), b->fh.data(),
-                        all.data(), rx.data(), rfx.data(), first.data()};
-  size_t off[8], at = 0;
-  for (int k = 0; k < 8; ++k) { off[k] = at; at += align256(sz[k]); }
+                        rfx.size() * 4, first.size() * 4, ranges.size() * 4};
+  const void* src[9] = {recs.data(), phislot.data(), pforest.data(), b->fh.data(),
+                        all.data(), rx.data(), rfx.data(), first.data(), ranges.data()};
+  size_t off[9], at = 0;
+  for (int k = 0; k < 9; ++k) { off[k] = at; at += align256(sz[k]); }
   HIPCHK(b->staging.ensure(at));
-  for (int k = 0; k < 8; ++k)
+  for (int k = 0; k < 9; ++k)
     if (sz[k]) std::memcpy(b->staging.p + off[k], src[k], sz[k]);
   HIPCHK(b->blob.ensure(at));
   HIPCHK(hipMemcpy(b->blob.p, b->staging.p, at, hipMemcpyHostToDevice));
@@ -981,6 +990,8 @@ static int batch_build(fcx_batch* b) {
   b->reflux = reinterpret_cast<RefluxItem*>(d + off[5]);
   b->reflux_forest = reinterpret_cast<int32_t*>(d + off[6]);
   b->first = reinterpret_cast<int32_t*>(d + off[7]);
+  b->range = reinterpret_cast<int32_t*>(d + off[8]);
+  HIPCHK(b->counters.ensure(4 * 8 * kCounterStride));
   const size_t esz = b->precision == 64 ? 8 : 4;
   HIPCHK(b->phi.ensure(size_t(phi_elems) * esz));
   HIPCHK(b->partial.ensure(size_t(pbase) * 4));
@@ -1004,6 +1015,10 @@ int fcx_batch_create(int32_t n, fcx_ctx* const* forests, fcx_batch** out) {
   b->precision = forests[0]->cfg.precision;
   b->cfl_desired = forests[0]->cfg.cfl_desired;
   b->cfl_max = forests[0]->cfg.cfl_max;
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+    b->cus = prop.multiProcessorCount;
   int rc = batch_build(b);
   if (rc == FCX_OK && b->err.ensure(1) != hipSuccess) rc = fail(FCX_ENOMEM, "hipMalloc failed");
   if (rc == FCX_OK && hipMemset(b->err.p, 0, 4) != hipSuccess) rc = fail(FCX_EHIP, "hipMemset failed");
@@ -1024,14 +1039,15 @@ int64_t fcx_batch_state_offset(const fcx_batch* b, int32_t f) {
 int64_t fcx_batch_num_patches(const fcx_batch* b) { return b ? b->P : -1; }
 
 int fcx_batch_set_tuning(fcx_batch* b, int32_t tile_big, int32_t threads8,
-                         int32_t threads16) {
+                         int32_t threads16, int32_t persistent) {
   if (!b || (tile_big != 8 && tile_big != 16) || (threads8 != 64 && threads8 != 128) ||
-      (threads16 != 256 && threads16 != 512))
+      (threads16 != 256 && threads16 != 512) || (persistent != 0 && persistent != 1))
     return fail(FCX_EINVAL, "bad tuning");
   const bool rebuild = tile_big != b->tile_big;
   b->tile_big = tile_big;
   b->threads8 = threads8;
   b->threads16 = threads16;
+  b->persistent = persistent;
   if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
   if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
   return rebuild ? batch_build(b) : FCX_OK;
@@ -1055,8 +1071,25 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
   B.items = b->items;
   B.item0 = b->item0[cls];
   B.nitems = b->nitems[cls];
-  hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT>), dim3(unsigned(b->nitems[cls])), dim3(NT),
-                     0, s, B);
+  B.range = b->range + cls * 9;
+  B.counters = b->counters.p + cls * 8 * kCounterStride;
+  if (b->persistent) {
+    // about as many workgroups as the LDS lets be resident (at most one per
+    // item), a multiple of 8 so that every XCD starts on its own counter;
+    // any beyond residency start late, find the ranges spent and exit
+    const int lds = int(sizeof(TileLds<R, PHYS, T, NT>));
+    const int per_cu = std::max(1, std::min(160 * 1024 / (lds + 64), 32 * 64 / NT));
+    int grid = std::min(b->cus * per_cu, (b->nitems[cls] + 7) / 8 * 8);
+    grid = std::max(8, (grid + 7) / 8 * 8);
+    // a fill kernel, not a memset: the launch may be captured into a graph
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(8 * kCounterStride), 0, s, B.counters,
+                       8 * kCounterStride);
+    hipLaunchKernelGGL((k_batch_persist<R, PHYS, T, NT>), dim3(unsigned(grid)), dim3(NT), 0, s,
+                       B);
+  } else {
+    hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT>), dim3(unsigned(b->nitems[cls])),
+                       dim3(NT), 0, s, B);
+  }
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }

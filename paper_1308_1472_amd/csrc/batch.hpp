@@ -5,9 +5,12 @@
 // Forests keep their own patch size, physics and parameters.  Their patch
 // tables are concatenated (neighbour ids are global) and their states are
 // concatenated in one buffer; a small per-forest record gives the bases.
-// The work items (global patch, tile) of a class all cost the same, so a
-// launch has one workgroup per item, with blocks mapped so that each XCD
-// takes a contiguous run of items (SFC neighbours then share an L2).
+// The work items (global patch, tile) of a class all cost the same.  A launch
+// either has one workgroup per item, with blocks mapped so that each XCD
+// takes a contiguous run of items (SFC neighbours then share an L2), or is
+// persistent: resident workgroups take items from per-XCD ranges through
+// atomic counters and steal from other XCDs' ranges once their own is spent.
+// The autotuner picks the form.
 #pragma once
 
 #include "step.hpp"
@@ -35,6 +38,8 @@ struct BatchArgs {
   int32_t* err;
   const uint32_t* __restrict__ items;      // (patch << 4) | tile
   int32_t item0, nitems;                   // this class's items
+  const int32_t* __restrict__ range;       // persistent: [9] item range of each XCD
+  int32_t* counters;                       //   and [8 * kCounterStride] counters, zero at launch
 };
 
 // Step arguments of one forest, with base pointers shifted so that global
@@ -61,10 +66,10 @@ __device__ __forceinline__ StepArgs<R> forest_args(const BatchArgs<R>& B, int f,
   return A;
 }
 
-// One workgroup per work item of one class (tile size and physics).  Each
-// tile keeps its registers to itself: a persistent form of this kernel, whose
-// loop over items kept the per-item state live across tiles, needed 128
-// registers per thread against 71 here and ran the batch a third slower.
+// one work counter per XCD, each on a cache line of its own
+constexpr int kCounterStride = 32;
+
+// One workgroup per work item of one class (tile size and physics).
 template <typename R, int PHYS, int T, int NT>
 __global__ void __launch_bounds__(NT)
 k_batch_step(BatchArgs<R> B) {
@@ -77,6 +82,56 @@ k_batch_step(BatchArgs<R> B) {
   const StepArgs<R> A = forest_args(B, f, F);
   const int tps = F.m / T;
   tile_step<R, PHYS, T, NT, true>(A, p, tile % tps, tile / tps, lds);
+}
+
+// Persistent launch over the work items of one class.  Thread 0 takes items
+// through its XCD's counter (stealing from the other XCDs once its own range
+// is spent); the ticket for the next item is drawn before the current tile is
+// processed, so the atomic's latency overlaps the tile's loads.  The thread
+// index is hidden from the optimizer per item: otherwise the index arithmetic
+// derived from it is hoisted out of the loop and held in registers across
+// tiles (128 registers per thread under a four-wave cap, against 87 so).
+template <typename R, int PHYS, int T, int NT>
+__global__ void __launch_bounds__(NT)
+k_batch_persist(BatchArgs<R> B) {
+  __shared__ TileLds<R, PHYS, T, NT> lds;
+  __shared__ int item_sh;
+  int x = blockIdx.x & 7, tries = 0;
+  // resolve a ticket k drawn on counter x into an item, stealing when the
+  // range of x is spent; -1 once every range is
+  auto resolve = [&](int k) -> int {
+    for (;;) {
+      if (B.range[x] + k < B.range[x + 1]) return B.range[x] + k;
+      if (++tries >= 8) return -1;
+      x = (x + 1) & 7;
+      k = atomicAdd(&B.counters[x * kCounterStride], 1);
+    }
+  };
+  if (threadIdx.x == 0) item_sh = resolve(atomicAdd(&B.counters[x * kCounterStride], 1));
+  __syncthreads();
+  for (;;) {
+    const int it = __builtin_amdgcn_readfirstlane(item_sh);
+    if (it < 0) break;
+    int ticket = 0;
+    if (threadIdx.x == 0 && tries < 8) ticket = atomicAdd(&B.counters[x * kCounterStride], 1);
+    const uint32_t w = __builtin_amdgcn_readfirstlane(B.items[it]);
+    const int p = int(w >> 4), tile = int(w & 15);
+    const int f = __builtin_amdgcn_readfirstlane(B.pforest[p]);
+    const ForestDev F = B.forests[f];
+    const StepArgs<R> A = forest_args(B, f, F);
+    const int tps = F.m / T;
+    int tid = int(threadIdx.x);
+    asm volatile("" : "+v"(tid));
+    tile_step<R, PHYS, T, NT, true>(A, p, tile % tps, tile / tps, lds, tid);
+    __syncthreads();                     // item_sh and the tile's LDS are free
+    if (threadIdx.x == 0) item_sh = tries < 8 ? resolve(ticket) : -1;
+    __syncthreads();
+  }
+}
+
+__global__ void k_zero_i32(int32_t* a, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) a[i] = 0;
 }
 
 // Reflux of a batch: one thread per (coarse-fine face item, coarse cell);

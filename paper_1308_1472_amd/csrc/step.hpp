@@ -128,8 +128,11 @@ struct TileLds {
 };
 
 template <typename R, int PHYS, int T, int NT, bool FUSED>
+// tid_in: the thread's index when the caller has hidden it from the
+// optimizer (a loop over tiles then recomputes what depends on it per tile
+// rather than keeping it in registers across tiles); -1: threadIdx.x.
 __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, int ty,
-                                          TileLds<R, PHYS, T, NT>& L) {
+                                          TileLds<R, PHYS, T, NT>& L, int tid_in = -1) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   constexpr int F = T + 4, NR = T + 2, NE = T + 3;
   constexpr int CPT = (T * T + NT - 1) / NT;
@@ -144,7 +147,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
   auto& red = L.red;
 
   const int m = A.m, lm = A.lm;
-  const int tid = threadIdx.x;
+  const int tid = tid_in >= 0 ? tid_in : int(threadIdx.x);
   const PatchRec& rp = A.rec[p];
   const int level = rp.level;
   const double dxd = ldexp(1.0, -level - lm);

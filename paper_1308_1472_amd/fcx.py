@@ -105,7 +105,7 @@ def lib():
             getattr(L, f).restype = i64
         L.fcx_batch_state_offset.argtypes = [vp, i32]
         L.fcx_batch_state_offset.restype = i64
-        L.fcx_batch_set_tuning.argtypes = [vp, i32, i32, i32]
+        L.fcx_batch_set_tuning.argtypes = [vp, i32, i32, i32, i32]
         L.fcx_batch_step.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.fcx_batch_capture.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.fcx_batch_replay.argtypes = [vp, vp]
@@ -467,8 +467,9 @@ class Batch:
     def num_patches(self) -> int:
         return lib().fcx_batch_num_patches(self.h)
 
-    def set_tuning(self, tile_big=16, threads8=64, threads16=256):
-        _check(lib().fcx_batch_set_tuning(self.h, tile_big, threads8, threads16))
+    def set_tuning(self, tile_big=16, threads8=64, threads16=256, persistent=0):
+        _check(lib().fcx_batch_set_tuning(self.h, tile_big, threads8, threads16,
+                                          persistent))
 
     def _q(self, t):
         import torch

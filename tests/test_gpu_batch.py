@@ -139,17 +139,18 @@ def test_every_tuning_gives_the_same_state():
     for tb in (8, 16):
         for t8 in (64, 128):
             for t16 in (256, 512):
-                batch.set_tuning(tb, t8, t16)
-                dt = torch.tensor(_dts(n), device="cuda")
-                nu = torch.zeros(n, dtype=torch.float64, device="cuda")
-                st = torch.zeros(n, dtype=torch.int32, device="cuda")
-                qn = torch.empty_like(q0)
-                batch.step(q0, qn, dt, nu, st)
-                if ref is None:
-                    ref = qn.clone()
-                else:
-                    err = (qn - ref).abs().max().item()
-                    assert err <= 1e-13 * ref.abs().max().item(), (tb, t8, t16)
+                for pers in (0, 1):
+                    batch.set_tuning(tb, t8, t16, pers)
+                    dt = torch.tensor(_dts(n), device="cuda")
+                    nu = torch.zeros(n, dtype=torch.float64, device="cuda")
+                    st = torch.zeros(n, dtype=torch.int32, device="cuda")
+                    qn = torch.empty_like(q0)
+                    batch.step(q0, qn, dt, nu, st)
+                    if ref is None:
+                        ref = qn.clone()
+                    else:
+                        err = (qn - ref).abs().max().item()
+                        assert err <= 1e-13 * ref.abs().max().item(), (tb, t8, t16, pers)
 
 
 def test_batch_sums_match_oracle():
@@ -177,7 +178,7 @@ def test_autotuner_picks_a_valid_config(tmp_path, monkeypatch):
     combos = 1
     for vals in autotune.SPACE.values():
         combos *= len(vals)
-    assert len(timings) == combos == 8 and all(v > 0 for v in timings.values())
+    assert len(timings) == combos == 16 and all(v > 0 for v in timings.values())
     import torch
     assert torch.equal(q0, before)           # state untouched
     best2, _ = autotune.tune(batch, q0)      # second call: from the cache
