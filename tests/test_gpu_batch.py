@@ -91,10 +91,14 @@ def test_batch_step_matches_single_forests_and_oracle():
     assert int(st.sum().item()) == 0
 
 
-def test_graph_replays_equal_eager_steps():
+@pytest.mark.parametrize("persistent", [0, 1])
+def test_graph_replays_equal_eager_steps(persistent):
+    """Replays of a captured graph equal eager steps, in both launch forms
+    (the persistent one clears its work counters with a captured kernel)."""
     import torch
-    say("[batch] graph replay")
+    say(f"[batch] graph replay persistent={persistent}")
     batch, ctxs, meshes, states, pars, q0 = _make(32)
+    batch.set_tuning(16, 64, 256, persistent)
     n = batch.n
     mk = lambda: (torch.tensor(_dts(n), device="cuda"),
                   torch.zeros(n, dtype=torch.float64, device="cuda"),
