@@ -52,14 +52,26 @@ __device__ void fluct_sum(const KPhys& ph, int d, const R* ql, const R* qr,
     out[0] = out[1] = out[2] = R(0);
     return;
   }
-  const R sl = sqrt(hl), sr = sqrt(hr), inv = R(1) / (sl + sr);
-  const R u = (ql[mu] / sl + qr[mu] / sr) * inv;
-  const R v = (ql[mv] / sl + qr[mv] / sr) * inv;
-  const R c = sqrt(R(ph.g) * R(0.5) * (hl + hr));
+  R u, v, c, i2c;
+  if constexpr (sizeof(R) == 4) {
+    // hardware root and reciprocals, as in the patch update
+    const R il = rsq_(hl), ir = rsq_(hr);
+    const R inv = rcp_(hl * il + hr * ir);
+    u = (ql[mu] * il + qr[mu] * ir) * inv;
+    v = (ql[mv] * il + qr[mv] * ir) * inv;
+    c = sqrt_(R(ph.g) * R(0.5) * (hl + hr));
+    i2c = R(0.5) * rcp_(c);
+  } else {
+    const R sl = sqrt(hl), sr = sqrt(hr), inv = R(1) / (sl + sr);
+    u = (ql[mu] / sl + qr[mu] / sr) * inv;
+    v = (ql[mv] / sl + qr[mv] / sr) * inv;
+    c = sqrt(R(ph.g) * R(0.5) * (hl + hr));
+    i2c = R(0.5) / c;
+  }
   const R d0 = hr - hl, d1 = qr[mu] - ql[mu], d2 = qr[mv] - ql[mv];
-  const R a1 = ((u + c) * d0 - d1) * (R(0.5) / c);
+  const R a1 = ((u + c) * d0 - d1) * i2c;
   const R a2 = d2 - v * d0;
-  const R a3 = (d1 - (u - c) * d0) * (R(0.5) / c);
+  const R a3 = (d1 - (u - c) * d0) * i2c;
   const R s1 = u - c, s3 = u + c;
   out[0] = s1 * a1 + s3 * a3;
   out[mu] = s1 * a1 * s1 + s3 * a3 * s3;

@@ -45,14 +45,6 @@ struct StepArgs {
 
 template <int T> struct TileThreads { static constexpr int value = T * T >= 256 ? 256 : T * T; };
 
-// Fast reciprocal / root: the hardware instructions in FP32 (about 1 ulp;
-// the FP32 path is held to 1e-5, and a correctly rounded square root costs
-// some fifteen instructions more), correctly rounded operations in FP64.
-__device__ __forceinline__ float rcp_(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_(double x) { return 1.0 / x; }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
-__device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
-__device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
 
 template <typename R>
 __device__ __forceinline__ R limiter_phi(int lim, R th) {
