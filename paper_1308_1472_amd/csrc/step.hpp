@@ -257,13 +257,14 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
                                                   : (n - 1) * NR + r; };
 
     // ---- phase A: Riemann solves ------------------------------------
+    // (advection: the wave is the jump of the staged state, which phase B
+    // forms where it needs it, so there is no phase A and no barrier after it)
+    if (PHYS != FCX_ADVECTION) {
     for (int idx = tid; idx < NR * NE; idx += NT) {
       const int r = d == 0 ? idx / NE : idx % NR;
       const int e = d == 0 ? idx % NE : idx / NR;
       const int cl = qidx(r, e - 1), cr = qidx(r, e);
-      if (PHYS == FCX_ADVECTION) {
-        wb[0][bidx(r, e)] = qs[0][cr] - qs[0][cl];
-      } else {
+      {
         const R hl = qs[0][cl], hr = qs[0][cr];
         R a1 = 0, a2 = 0, a3 = 0, u = 0, v = 0, c = 1, i2c_ = R(0.5);
         if (hl > R(0) && hr > R(0)) {
@@ -295,6 +296,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
       }
     }
     __syncthreads();
+    }
 
     // ---- phase B: limiter, corrections, transverse splitting ---------
     R keep[EPT][3][MEQN];                  // right-cell terms across the barrier
@@ -307,13 +309,14 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
       const bool inner = (r >= 1 && r <= T);
       R am[MEQN], ap[MEQN], cq[MEQN];
       if (PHYS == FCX_ADVECTION) {
-        const R w = wb[0][bidx(r, e)];
+        auto jump = [&](int ee) { return qs[0][qidx(r, ee)] - qs[0][qidx(r, ee - 1)]; };
+        const R w = jump(e);
         am[0] = fmin(an, R(0)) * w;
         ap[0] = fmax(an, R(0)) * w;
         cq[0] = R(0);
         if (inner) smax = fmax(smax, fabs(an));
         if (w != R(0)) {
-          const R wu = wb[0][bidx(r, an > R(0) ? e - 1 : e + 1)];
+          const R wu = jump(an > R(0) ? e - 1 : e + 1);
           const R th = (wu * w) * rcp_(w * w);
           const R s = fabs(an);
           cq[0] = s * (R(1) - dtdx * s) * limiter_phi(lim, th) * w;
