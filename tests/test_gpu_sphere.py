@@ -304,3 +304,34 @@ def test_run_loop_with_regrids_equals_single_calls():
     with pytest.raises(fcx.FcxError):
         ctx.run(bufs[which], bufs[1 - which], ghost, 1, steps, 0, 1, thr, lmin, lmax,
                 dt, nu, st, fused=True)
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_geometry_after_regrids_equals_a_fresh_upload(precision):
+    """The geometry a regrid builds for the new forest (tables and, in FP32,
+    a step that reads the FP32 copy of them) equals bit for bit that of a
+    context uploaded afresh with the same leaves: a patch's tables depend
+    only on its tree, level and position."""
+    say(f"[sphere] geometry after regrids precision={precision}")
+    import torch
+    trees, lv = _forest(5, 1, 3, 14)
+    cfg = fcx.config(M, precision, fcx.FCX_SPHERE)
+    g = Gpu(cfg, trees, lv)
+    g.set_state(_sphere_state(lv, 3))
+    rng = np.random.default_rng(7)
+    kept = 0
+    for _ in range(2):
+        old = g.ctx.leaves()
+        g.regrid(rng.integers(-1, 2, g.ctx.num_patches()).astype(np.int8), 1, 4)
+        new = g.ctx.leaves()
+        kept += len(set(map(tuple, old.tolist())) & set(map(tuple, new.tolist())))
+    assert kept > 0
+    fresh = Gpu(cfg, trees, g.ctx.leaves())
+    assert torch.equal(g.ctx.sphere_geometry(), fresh.ctx.sphere_geometry())
+    q = g.state()
+    fresh.set_state(q)
+    g.set_state(q)
+    h = 1.0 / (M << 4)
+    g.step(0.2 * h)
+    fresh.step(0.2 * h)
+    assert np.array_equal(g.state(), fresh.state())
