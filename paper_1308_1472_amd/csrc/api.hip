@@ -112,6 +112,7 @@ struct DevForest {
   RefluxItem* reflux = nullptr;
   RefluxAux* aux = nullptr;          // per reflux item: partners, slots, level
   int32_t* counts = nullptr;         // {slots, xi items, eta items} on the device
+  int32_t* order = nullptr;          // dispatch order of the step's tiles (null: identity)
   int32_t* first = nullptr;          // {0, P} for the sum reduction
   int32_t* xkind = nullptr;          // transfer plan from the previous forest
   int32_t* xsrc = nullptr;
@@ -345,6 +346,14 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
                         kind ? P * 4 : 0, src ? P * 4 : 0, NI * sizeof(RefluxAux), 3 * 4};
   for (int k = 0; k < 9; ++k) { off[k] = at; at += align256(sz[k]); }
   off[9] = at;
+  // dispatch order of the planar step's tiles: within the run of launch
+  // slots each XCD takes, patches with a general halo (costlier tiles) come
+  // first; left out when every patch or none has a simple halo
+  size_t nsimple = 0;
+  for (const PatchRec& r : plan.recs) nsimple += (r.flags & kSimpleHalo) != 0;
+  const bool reorder = c->cfg.physics != FCX_SPHERE && nsimple > 0 && nsimple < P;
+  const size_t off_order = at;
+  if (reorder) at += align256(P * 4);
   HIPCHK(c->staging.ensure(at));
   uint8_t* h = c->staging.p;
   {
@@ -388,6 +397,18 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   if (src) std::memcpy(h + off[6], src->data(), sz[6]);
   const int32_t counts[3] = {plan.nslots, dev.n_reflux_x, dev.n_reflux_y};
   std::memcpy(h + off[8], counts, sz[8]);
+  if (reorder) {
+    int32_t* ord = reinterpret_cast<int32_t*>(h + off_order);
+    const size_t per = P >> 3, rem = P & 7;
+    for (size_t x = 0; x < 8; ++x) {
+      const size_t a = x * per + std::min(x, rem), b = a + per + (x < rem ? 1 : 0);
+      size_t k = a;
+      for (size_t p = a; p < b; ++p)
+        if (!(plan.recs[p].flags & kSimpleHalo)) ord[k++] = int32_t(p);
+      for (size_t p = a; p < b; ++p)
+        if (plan.recs[p].flags & kSimpleHalo) ord[k++] = int32_t(p);
+    }
+  }
   HIPCHK(dev.blob.ensure(at));
   if (ordered) {
     if (!c->staged) HIPCHK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
@@ -407,6 +428,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   dev.xsrc = src ? reinterpret_cast<int32_t*>(d + off[6]) : nullptr;
   dev.aux = reinterpret_cast<RefluxAux*>(d + off[7]);
   dev.counts = reinterpret_cast<int32_t*>(d + off[8]);
+  dev.order = reorder ? reinterpret_cast<int32_t*>(d + off_order) : nullptr;
   dev.nslots = plan.nslots;
   dev.P = int64_t(P);
   std::swap(c->plan, c->spare);
@@ -557,6 +579,7 @@ static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
   const int tps = c->cfg.m / T;
   a.ntiles = int32_t(c->cur.P * tps * tps);
   a.ph = kphys(c);
+  a.order = c->cur.order;
   hipLaunchKernelGGL((k_step<R, PHYS, T, NT, FUSED>), dim3(unsigned(a.ntiles)),
                      dim3(NT), 0, s, a);
   HIPCHK(hipGetLastError());

@@ -40,6 +40,9 @@ struct StepArgs {
   int32_t P;
   int32_t m, lm;          // patch size and its log2
   int32_t ntiles;         // total tiles = P * (m / T)^2
+  // with one tile per patch, optionally the patch of each launch slot (the
+  // dispatch order; null: slot order)
+  const int32_t* order = nullptr;
   KPhys ph;
 };
 
@@ -517,12 +520,15 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
   }
 }
 
-// One workgroup per tile, over all tiles of one forest.
+// One workgroup per tile, over all tiles of one forest.  With an order
+// table, each XCD's run of slots takes the patches with a general halo (the
+// costlier tiles) first, so the last tiles to be dispatched are cheap ones.
 template <typename R, int PHYS, int T, int NT, bool FUSED>
 __global__ void __launch_bounds__(NT)
 k_step(StepArgs<R> A) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
-  const int t = xcd_tile(blockIdx.x, A.ntiles);
+  int t = xcd_tile(blockIdx.x, A.ntiles);
+  if (A.order && A.m == T) t = A.order[t];
   const int tps = A.m / T;
   const int p = t / (tps * tps);
   const int tile = t - p * (tps * tps);
