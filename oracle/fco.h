@@ -9,13 +9,13 @@
  * constant with the HIP library it checks.
  *
  * Conventions (2D, quadtrees):
- *   - every tree is the reference square [0,1]^2 (Sec. 2, "each block is a
- *     reference unit cube with its own geometric mapping");
+ *   - every tree is the unit square [0,1]^2 with a mapping of its own
+ *     (Sec. 2);
  *   - a leaf at level l with integer coordinates (ix, iy) in [0, 2^l)^2
  *     covers [ix, ix+1] 2^-l x [iy, iy+1] 2^-l and houses one m x m patch
  *     (Sec. 2, the 1:1 leaf <-> patch correspondence);
- *   - patch cells (i, j), i, j = 1..m; two ghost layers i, j in
- *     {-1, 0, m+1, m+2} (Sec. 3, "two layers of ghost cells");
+ *   - patch cells (i, j), i, j = 1..m, and two ghost layers (Sec. 3) with
+ *     i or j in {-1, 0, m+1, m+2};
  *   - face ids 0 = xi-low, 1 = xi-high, 2 = eta-low, 3 = eta-high;
  *   - per-patch state is stored "framed": q[p][k][(j+1)*(m+4) + (i+1)],
  *     i.e. a (m+4)^2 array per component with i fastest.
@@ -112,6 +112,11 @@ double fco_phi(int32_t limiter, double theta);
 int  fco_riemann(const fco_params *par, int32_t dir, const double *ql,
                  const double *qr, double *waves, double *speeds,
                  double *amdq, double *apdq);
+/* transverse split of a fluctuation psi from the dir-edge with states ql,
+ * qr into the parts moving down (bm) and up (bp) the other direction
+ * (planar physics) */
+int  fco_tsplit(const fco_params *par, int32_t dir, const double *ql,
+                const double *qr, const double *psi, double *bm, double *bp);
 
 #ifdef __cplusplus
 }

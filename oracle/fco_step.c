@@ -155,6 +155,15 @@ static int tsplit_shallow(const fco_params *par, int dir, const double *ql,
   return 0;
 }
 
+int fco_tsplit(const fco_params *par, int32_t dir, const double *ql,
+               const double *qr, const double *psi, double *bm, double *bp) {
+  switch (par->physics) {
+    case FCO_ADVECTION: return tsplit_advection(par, dir, psi, bm, bp);
+    case FCO_SHALLOW: return tsplit_shallow(par, dir, ql, qr, psi, bm, bp);
+    default: return -1;
+  }
+}
+
 /* sphere solvers live in fco_sphere.c; *fl receives the mass flux there */
 static int riemann(const fco_params *par, int dir, const edge_geom *e,
                    const double *ql, const double *qr, double *W, double *s,

@@ -70,6 +70,8 @@ def lib():
         L.fco_phi.argtypes = [i32, dp]
         L.fco_phi.restype = dp
         L.fco_riemann.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
+        L.fco_tsplit.argtypes = [vp, i32, vp, vp, vp, vp, vp]
+        L.fco_tsplit_sphere.argtypes = [vp, vp, vp, vp, vp, vp, i32]
         L.fco_features.argtypes = [vp, vp, vp, vp]
         L.fco_bf16.argtypes = [dp]
         L.fco_bf16.restype = dp
@@ -244,6 +246,18 @@ def riemann(par, direction, ql, qr):
     return W[:nw], s[:nw], am, ap
 
 
+def tsplit(par, direction, ql, qr, psi):
+    """(B-psi, B+psi): the transverse split of a fluctuation psi from the
+    edge of the given direction with states ql, qr."""
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (ql, qr, psi)]
+    bm = np.zeros(par.meqn)
+    bp = np.zeros(par.meqn)
+    if lib().fco_tsplit(C.byref(par), direction, _ptr(a[0]), _ptr(a[1]), _ptr(a[2]),
+                        _ptr(bm), _ptr(bp)) != 0:
+        raise RuntimeError("tsplit failed")
+    return bm, bp
+
+
 # -------------------------------------------------------------------------
 # a plain driver: ghost fill + step, fixed or CFL-controlled dt, regrid
 # -------------------------------------------------------------------------
@@ -339,6 +353,19 @@ def sphere_centre(mesh, p, i, j) -> np.ndarray:
     r = np.zeros(3)
     lib().fco_sphere_centre(mesh.h, p, i, j, _ptr(r))
     return r
+
+
+def tsplit_sphere(par, gamma, n, t, ql, qr, psi, up):
+    """Up-going (up = 1) or down-going (up = 0) part of the fluctuation psi
+    split with the frame (gamma, n, t) of a transverse edge and the Roe
+    averages of the normal edge's states ql, qr."""
+    e = EdgeGeom(gamma, (C.c_double * 3)(*n), (C.c_double * 3)(*t))
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (ql, qr, psi)]
+    out = np.zeros(4)
+    if lib().fco_tsplit_sphere(C.byref(par), _ptr(a[0]), _ptr(a[1]), C.byref(e),
+                               _ptr(a[2]), _ptr(out), int(up)) != 0:
+        raise RuntimeError("tsplit failed")
+    return out
 
 
 def riemann_sphere(par, gamma, n, t, ql, qr):
