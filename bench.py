@@ -47,10 +47,11 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "sphere",
-                                       "mlp", "copy", "all"],
+                                       "mlp", "copy", "cpu", "all"],
                     default="all")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--sphere-steps", type=int, default=1000)
+    ap.add_argument("--sphere64-steps", type=int, default=48)
     ap.add_argument("--tile", type=int, default=0)
     ap.add_argument("--threads", type=int, default=0)
     return ap.parse_args()
@@ -81,6 +82,19 @@ def stored_profile(name, key):
 def stored_traffic(name):
     """HBM bytes per launch (memory counters scaled by a plain copy)."""
     return stored_profile(name, "hbm_bytes_per_launch")
+
+
+STATUS_BITS = {1: "cfl_kept", 2: "negative_depth", 4: "nested_interpolation",
+               8: "rejected_and_redone"}
+# bits that mark a timed step as wrong (a redone attempt is the CFL rule
+# working, not a fault)
+BAD_BITS = 1 | 2 | 4
+
+
+def status_bits(words):
+    """Per status bit, the number of status words (forests) that carry it."""
+    words = [int(w) for w in words]
+    return {name: sum(1 for w in words if w & bit) for bit, name in STATUS_BITS.items()}
 
 
 class Workload:
@@ -164,17 +178,21 @@ TUNE = {"tile": 0, "threads": 0}
 
 
 def run(precision, fused, steps, warmup, uniform_level=None):
+    """Warm-up attempts, then `steps` timed attempts in the library's run
+    loop (reject-and-redo on: only accepted steps count as cell updates)."""
     import torch
     w = Workload(precision, fused, uniform_level, TUNE["tile"], TUNE["threads"])
     if warmup:
         w.advance(warmup)
     torch.cuda.synchronize()
-    w.status.zero_()                      # CFL flags of the timed steps only
+    w.status.zero_()                      # flags of the timed attempts only
+    before = w.ctx.step_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cells = float(w.advance(steps))
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    after = w.ctx.step_stats()
     status = int(w.status.item())
     # the step kernel alone: nk back-to-back launches on the current mesh
     # between two HIP events on the launch stream (the launch is idempotent:
@@ -196,10 +214,12 @@ def run(precision, fused, steps, warmup, uniform_level=None):
     w.numax.zero_()
     out = {
         "seconds": el, "cells": cells, "rate": cells / el,
+        "attempts": steps, "accepted": after[0] - before[0],
+        "rejected": after[1] - before[1],
         "kernel_ms_mean": a.elapsed_time(b) / nk,
         "kernel_cells_mean": float(w.ctx.num_patches() * w.M * w.M),
         "patches_last": w.ctx.num_patches(),
-        "status": status,
+        "status": status, "status_bits": status_bits([status]),
     }
     if uniform_level is not None:
         out["_state"] = q                 # for the FP32-vs-FP64 comparison
@@ -219,26 +239,43 @@ def rel_l1(a, b, meqn, cells):
     return worst
 
 
-def run_batch(steps, warmup, nforests=64, graph_steps=10):
-    """The 64-forest batch: seeded forests (advection or shallow water by
-    seed parity, m in {8, 16, 32}, patch counts log-uniform in 16..16384,
-    levels 2..8), FP32, one launch per tile class (a workgroup per tile or
-    persistent workgroups), captured in a graph of `graph_steps` steps,
-    tunables from the autotuner."""
-    import torch
-    from paper_1308_1472_amd import autotune, fcx
+def _batch_forests(precision, nforests=64):
+    """The seeded forests of the batch: contexts and initial states."""
+    from paper_1308_1472_amd import fcx
     from paper_1308_1472_amd import inputs as I
     ctxs, states = [], []
     for seed in range(nforests):
         spec, trees, pl, raw, fn = I.batch_forest(seed)
         lv = fcx.balance(trees, raw)
         phys = fcx.FCX_ADVECTION if spec["physics"] == "advection" else fcx.FCX_SHALLOW
-        cfg = fcx.config(spec["m"], 32, phys, ax=spec.get("ax", 0.0),
+        cfg = fcx.config(spec["m"], precision, phys, ax=spec.get("ax", 0.0),
                          ay=spec.get("ay", 0.0))
         ctx = fcx.Context(cfg, trees)
         ctx.upload_forest(lv)
         ctxs.append(ctx)
         states.append(I.state_from(lv, spec["m"], fn, pl))
+    return ctxs, states
+
+
+def _probe_dt(n):
+    """A dt far below every forest's stable one: the first step's next-dt
+    rule then sets dt = cfl_desired / (largest wave speed / cell size) per
+    forest, from the forest's own waves."""
+    import torch
+    return torch.full((n,), 1e-7, dtype=torch.float64, device="cuda")
+
+
+def run_batch(steps, warmup, nforests=64, graph_steps=10):
+    """The 64-forest batch: seeded forests (advection or shallow water by
+    seed parity, m in {8, 16, 32}, patch counts log-uniform in 16..16384,
+    levels 2..8), FP32, one launch per tile class (a workgroup per tile or
+    persistent workgroups), captured in a graph of `graph_steps` steps,
+    tunables from the autotuner.  dt per forest from its own first step
+    (probe), then the CFL rule with reject-and-redo; the rate counts the
+    accepted cell updates of the timed replays."""
+    import torch
+    from paper_1308_1472_amd import autotune, fcx
+    ctxs, states = _batch_forests(32, nforests)
     batch = fcx.Batch(ctxs)
     q = torch.empty(batch.state_elems(), dtype=torch.float32, device="cuda")
     for f, st in enumerate(states):
@@ -247,26 +284,25 @@ def run_batch(steps, warmup, nforests=64, graph_steps=10):
     cells = float(sum(st.size // c.meqn for st, c in zip(states, ctxs)))
     # algorithmic bytes: read and write every state value once (FP32)
     step_bytes = float(sum(st.size * 4 * 2 for st in states))
+    adv_bytes = float(sum(st.size * 4 * 2 for st, c in zip(states, ctxs) if c.meqn == 1))
     best, timings = autotune.tune(batch, q, steps=2, reps=2)
     qa, qb = q.clone(), torch.empty_like(q)
     n = batch.n
-    # per-forest dt at Courant number 0.45 of its finest cells
-    dts = []
-    for c, st in zip(ctxs, states):
-        lv = c.leaves()
-        h = 1.0 / (c.cfg.m << int(lv["level"].max()))
-        speed = 1.0 if c.meqn == 1 else 2.0 ** 0.5 * 1.5
-        dts.append(0.45 * h / speed)
-    dt = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    dt = _probe_dt(n)
     nu = torch.zeros(n, dtype=torch.float64, device="cuda")
     status = torch.zeros(n, dtype=torch.int32, device="cuda")
+    batch.step(qa, qb, dt, nu, status)          # the probe step
+    qa, qb = qb, qa
     batch.capture(graph_steps, qa, qb, dt, nu, status)
     for _ in range(max(1, warmup // graph_steps)):
         batch.replay()
     torch.cuda.synchronize()
+    status.zero_()
+    before = batch.step_stats()
     reps = max(1, steps // graph_steps)
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     a.record()
     for _ in range(reps):
@@ -275,16 +311,68 @@ def run_batch(steps, warmup, nforests=64, graph_steps=10):
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     ms = a.elapsed_time(b)
+    after = batch.step_stats()
+    d = after - before
+    acc_cells = float(d[:, 2].sum())
     nst = reps * graph_steps
+    words = status.cpu().tolist()
     return {"forests": n, "patches": batch.num_patches(), "cells": cells,
-            "steps": nst, "seconds": el, "rate": cells * nst / el,
+            "steps": nst, "seconds": el, "rate": acc_cells / el,
+            "accepted_cell_updates": acc_cells,
+            "attempts": int(n * nst), "rejected": int(d[:, 1].sum()),
             "ms_per_step": ms / nst, "tuning": best,
             "autotune_ms_per_step": {k: round(v, 4) for k, v in sorted(timings.items())},
-            "status_flags": int((status != 0).sum().item()),
-            "bytes_per_step": step_bytes}
+            "status_words_nonzero": int(sum(1 for w in words if w)),
+            "status_bits": status_bits(words), "status_bad": int(
+                sum(1 for w in words if w & BAD_BITS)),
+            "bytes_per_step": step_bytes, "advection_bytes_per_step": adv_bytes}
 
 
-def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000):
+def run_batch_fp64_plain(steps=10, nforests=64):
+    """The same 64 forests on the plain FP64 path, forest after forest:
+    ghost fill, step, reflux, next dt (the library's single calls, no
+    batching, no graph), from the same probe dt: the like-for-like
+    reference of the batched FP32 rate."""
+    import torch
+    ctxs, states = _batch_forests(64, nforests)
+    runs = []
+    for c, st in zip(ctxs, states):
+        q = torch.from_numpy(st.ravel().copy()).cuda()
+        runs.append({"c": c, "q": q, "qn": torch.empty_like(q),
+                     "g": torch.empty(c.ghost_elems(), dtype=torch.float64, device="cuda"),
+                     "dt": torch.full((1,), 1e-7, dtype=torch.float64, device="cuda"),
+                     "nu": torch.zeros(1, dtype=torch.float64, device="cuda"),
+                     "st": torch.zeros(1, dtype=torch.int32, device="cuda")})
+
+    def one_step():
+        for r in runs:
+            c = r["c"]
+            c.ghost_fill(r["q"], r["g"])
+            c.patch_step(r["q"], r["g"], r["qn"], r["dt"], r["nu"])
+            c.reflux(r["q"], r["qn"], r["dt"])
+            c.next_dt(r["nu"], r["dt"], r["st"])
+            r["q"], r["qn"] = r["qn"], r["q"]
+
+    one_step()                                   # the probe step
+    for _ in range(3):
+        one_step()
+    torch.cuda.synchronize()
+    for r in runs:
+        r["st"].zero_()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    cells = float(sum(st.size // c.meqn for st, c in zip(states, ctxs)))
+    words = [int(r["st"].item()) for r in runs]
+    return {"steps": steps, "seconds": el, "rate": cells * steps / el,
+            "ms_per_step": el / steps * 1e3, "status_bits": status_bits(words)}
+
+
+def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000,
+               kernel_timing=True, threshold=None):
     """Shallow water on the cubed sphere, adaptive: 6 trees, levels lmin..lmax,
     m x m patches, a seeded sum of Gaussian height bumps on h = 1 at rest.
     The initial mesh refines uniform level lmin by lmax - lmin regrids (|grad h|
@@ -322,7 +410,7 @@ def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000)
 
     lo, hi = math.log(1e-4), math.log(10.0)
     best = None
-    for _ in range(24):
+    for _ in range(0 if threshold is not None else 24):
         mid = 0.5 * (lo + hi)
         ctx, cur = initial(math.exp(mid))
         P = ctx.num_patches()
@@ -334,7 +422,7 @@ def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000)
             lo = mid          # too many patches: raise the threshold
         else:
             hi = mid
-    thr = best[0]
+    thr = threshold if threshold is not None else best[0]
     ctx, cur = initial(thr)
     P0 = ctx.num_patches()
     dt = torch.full((1,), 0.3 * (math.pi / 2) / (m << lmax), dtype=torch.float64,
@@ -351,15 +439,25 @@ def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000)
     if which == 1:
         q_a, q_b = q_b, q_a
     st.zero_()
+    before = ctx.step_stats()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     which, cells = ctx.run(q_a, q_b, ghost, steps, every + 1, every, 1, thr, lmin, lmax,
                            dt, nu, st, fused=False)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    after = ctx.step_stats()
     q_end = (q_b if which == 1 else q_a)[:ctx.state_elems()]
     ctx.conservation_sums(q_end, sums)
     mass = sums[0].item() / m0 - 1.0
+    if not kernel_timing:
+        status = int(st.item())
+        return {"precision": precision, "patches_initial": P0,
+                "patches_last": ctx.num_patches(), "steps": steps, "regrid_every": every,
+                "cells": cells, "accepted": after[0] - before[0],
+                "rejected": after[1] - before[1], "rate": cells / el,
+                "mass_rel_change": mass, "status": status,
+                "status_bits": status_bits([status])}
     # the step kernel alone: back-to-back launches on the final forest,
     # timed with events on the launch stream
     n = ctx.state_elems()
@@ -379,10 +477,14 @@ def run_sphere(steps, precision=32, m=32, lmin=4, lmax=7, every=8, target=50000)
     # two edge frames and the centre (in FP32 for FP32 state: 56 + 12 B)
     bpc = 32.0 + 8.0 + 68.0 if precision == 32 else 64.0 + 8.0 + 136.0
     alg = kcells * bpc
-    return {"threshold": thr, "patches_initial": P0, "patches_last": ctx.num_patches(),
+    status = int(st.item())
+    return {"precision": precision, "threshold": thr, "patches_initial": P0,
+            "patches_last": ctx.num_patches(),
             "steps": steps, "regrid_every": every, "cells": cells,
+            "accepted": after[0] - before[0], "rejected": after[1] - before[1],
             "rate": cells / el, "ms_per_step": el / steps * 1e3,
-            "mass_rel_change": mass, "status": int(st.item()), "dt": dt.item(),
+            "mass_rel_change": mass, "status": status,
+            "status_bits": status_bits([status]), "dt": dt.item(),
             "step_kernel": {"kernel": "k_sphere_step", "cells": kcells, "kernel_ms": kms,
                             "rate": kcells / (kms * 1e-3),
                             "roofline": {"bound": "hbm", "unit": "GB/s",
@@ -444,9 +546,35 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_each": n * 4, "copies": 3}), flush=True)
 
 
-def cpu_baseline(budget_s=12.0):
-    """The CPU FP64 oracle, single-threaded, on the first steps of the same
-    workload (same initial mesh, regrid every 4 steps)."""
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _host_threads():
+    """Threads available to this process: the CPU affinity mask, capped by
+    OMP_NUM_THREADS when that is set."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_baseline(warmup, steps, budget_s=6.0, reps=3):
+    """The CPU FP64 oracle on the same attempts as the GPU's timed window of
+    the headline workload (same initial mesh, dt rule with reject-and-redo,
+    regrid every 4): the first `warmup` attempts untimed, then up to `steps`
+    attempts timed, single-threaded and on every host thread, median of
+    `reps` runs each.  A window longer than `budget_s` of one-thread work is
+    cut to the attempts that fit, and both thread counts time that same cut
+    window (same cell updates)."""
     import numpy as np
     from oracle import oracle as O
     from paper_1308_1472_amd import inputs as I
@@ -454,6 +582,8 @@ def cpu_baseline(budget_s=12.0):
     m, lmin, lmax = Workload.M, Workload.LMIN, Workload.LMAX
     fn = lambda x, y: I.dam_break(x, y)
     par = O.params(m, O.SHALLOW)
+    nthreads = _host_threads()
+    O.set_threads(nthreads)
     lv = O.sfc_sort(I.uniform_leaves(1, lmin))
     for _ in range(2 * (lmax - lmin) + 2):
         mesh = O.Mesh(trees, lv, m)
@@ -466,10 +596,10 @@ def cpu_baseline(budget_s=12.0):
         lv = lv2
     mesh = O.Mesh(trees, lv, m)
     q = I.state_from(lv, m, fn, pl)
+    # the bench's first dt: 0.45 of the finest cell over sqrt(2)
     dt = 0.45 / (m << int(lv["level"].max())) / 2.0 ** 0.5
-    cells, n = 0, 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < budget_s or n < 2:
+
+    def attempt(n, mesh, q, dt):
         if n > 0 and n % Workload.REGRID == 0:
             f = O.framed(q, m)
             O.ghost_fill(mesh, par, f)
@@ -477,16 +607,46 @@ def cpu_baseline(budget_s=12.0):
             mesh2 = O.Mesh(trees, O.regrid(mesh, tg, lmin, lmax), m)
             q = O.interior(O.transfer(mesh, mesh2, par, f), m)
             mesh = mesh2
-        q, nu = O.advance(mesh, par, q, dt)
-        dt *= 0.9 / nu
-        cells += len(mesh) * m * m
-        n += 1
-    el = time.perf_counter() - t0
-    return {"value": cells / el, "unit": "cell-updates/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"first {n} steps of the same adaptive dam break (levels "
-                      f"3-6, m = 16, regrid every 4), FP64, one thread, "
-                      f"{el:.1f} s"}
+        qn, nu = O.advance(mesh, par, q, dt)
+        ok = not nu > 1.0
+        return mesh, (qn if ok else q), dt * 0.9 / nu, (len(mesh) * m * m if ok else 0)
+
+    for n in range(warmup):
+        mesh, q, dt, _ = attempt(n, mesh, q, dt)
+    start = (mesh, q, dt)
+
+    def window(limit, budget):
+        mesh, q, dt = start
+        cells, k = 0, 0
+        t0 = time.perf_counter()
+        while k < limit and (budget is None or time.perf_counter() - t0 < budget):
+            mesh, q, dt, c = attempt(warmup + k, mesh, q, dt)
+            cells += c
+            k += 1
+        return time.perf_counter() - t0, cells, k
+
+    # the window that fits the budget on one thread, then the timed runs
+    O.set_threads(1)
+    _, cells, k = window(steps, budget_s)
+    out = {}
+    for name, t in (("single_thread", 1), ("all_threads", nthreads)):
+        O.set_threads(t)
+        times = sorted(window(k, None)[0] for _ in range(reps))
+        out[name] = {"threads": t, "seconds_median": times[reps // 2],
+                     "rate": cells / times[reps // 2]}
+    O.set_threads(1)
+    return {"value": out["all_threads"]["rate"], "unit": "cell-updates/s",
+            "cores": nthreads, "kind": "oracle",
+            "sample": f"attempts {warmup}..{warmup + k - 1} of the same adaptive dam break "
+                      f"(levels 3-6, m = 16, regrid every 4, dt rule with reject-and-redo), "
+                      f"{cells} cell updates, FP64, the ghost fill and the step's patch "
+                      f"loop split over {nthreads} threads, median of {reps}",
+            "single_thread": out["single_thread"]["rate"],
+            "all_threads": out["all_threads"]["rate"],
+            "seconds_median": {"single_thread": out["single_thread"]["seconds_median"],
+                               "all_threads": out["all_threads"]["seconds_median"]},
+            "cell_updates": cells, "attempts": k,
+            "nproc": os.cpu_count(), "cpu_model": _cpu_model()}
 
 
 def main():
@@ -502,6 +662,9 @@ def main():
         sys.exit(1)
     if args.only == "copy":
         copy_calibration()
+        return
+    if args.only == "cpu":
+        print(json.dumps({"cpu_baseline": cpu_baseline(args.warmup, args.steps)}), flush=True)
         return
     res = {}
     if args.only in ("fp32", "all"):
@@ -522,23 +685,35 @@ def main():
         print(f"# large fp64: {res['large64']}; fp32 vs fp64 rel L1 "
               f"{res['large32']['rel_l1_vs_fp64']:.3e}", file=sys.stderr, flush=True)
     if args.only in ("batch", "all"):
-        res["batch"] = run_batch(args.batch_steps, 10)
+        res["batch"] = run_batch(args.batch_steps, 30)
         print(f"# batch fp32: {res['batch']}", file=sys.stderr, flush=True)
+        res["batch64"] = run_batch_fp64_plain()
+        print(f"# batch fp64 plain: {res['batch64']}", file=sys.stderr, flush=True)
     if args.only in ("sphere", "all"):
         res["sphere"] = run_sphere(args.sphere_steps)
         print(f"# sphere fp32: {res['sphere']}", file=sys.stderr, flush=True)
+        res["sphere64"] = run_sphere(args.sphere64_steps, precision=64, kernel_timing=False,
+                                     threshold=res["sphere"]["threshold"])
+        print(f"# sphere fp64: {res['sphere64']}", file=sys.stderr, flush=True)
     if args.only in ("mlp", "all"):
         res["mlp"] = run_mlp()
         print(f"# mlp: {res['mlp']}", file=sys.stderr, flush=True)
+    # timed legs whose status words carry a bit that marks a wrong step
+    bad = {k: r.get("status_bits") for k, r in res.items()
+           if isinstance(r, dict) and (int(r.get("status", 0)) & BAD_BITS or r.get("status_bad"))}
     head = res.get("fp32") or res.get("fp64") or res.get("large32")
     if head is None:
-        print(json.dumps({k: res.get(k) for k in ("batch", "sphere", "mlp") if k in res}),
-              flush=True)
-        return
+        print(json.dumps({k: res.get(k) for k in ("batch", "batch64", "sphere", "sphere64",
+                                                  "mlp") if k in res}), flush=True)
+        sys.exit(3 if bad else 0)
     steps = args.steps if "fp32" in res or "fp64" in res else args.large_steps
     bytes_per_cell = 24.0 if head is not res.get("fp64") else 48.0
+    ADAPTIVE = ("shallow-water radial dam break, walled unit square, adaptive levels 3-6, "
+                "m=16, regrid every 4 steps")
+    LEVEL8 = ("the same dam break on the uniform level-8 forest (65,536 patches of 16x16, "
+              "16.8 M cells, far beyond the 256 MB last-level cache)")
 
-    def roof(r, bpc, profile):
+    def roof(r, bpc, profile, workload):
         """HBM roofline of the step kernel: algorithmic bytes (read and write
         every state value once) per launch over the launch time measured
         with HIP events on the launch stream."""
@@ -547,6 +722,7 @@ def main():
         out = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
                "traffic": stored_traffic(profile) if profile else None,
+               "workload": workload,
                "kernel": "k_step", "kernel_ms": r["kernel_ms_mean"],
                "bytes_per_launch": alg,
                "profile": "profiles/" + profile if profile else None}
@@ -573,36 +749,46 @@ def main():
         "dtype": "f32" if head is res.get("fp32") else "f64",
         "data": "synthetic",
         "config": {
-            "workload": "shallow-water radial dam break, walled unit square, "
-                        "adaptive levels 3-6, m=16, regrid every 4 steps",
+            "workload": ADAPTIVE,
             "m": 16, "levels": [3, 6], "regrid_every": 4,
             "cells_per_step_mean": head["kernel_cells_mean"],
             "patches_at_end": head["patches_last"],
-            "path": "fused ghost-gather + update, FP32 state, FP64 dt/CFL/sums",
+            "attempts": head["attempts"], "accepted": head["accepted"],
+            "rejected": head["rejected"],
+            "path": "fused ghost-gather + update, FP32 state, FP64 dt/CFL/sums, "
+                    "reject-and-redo CFL rule; value counts accepted cell updates",
         },
         # the adaptive state (about 8 MB in FP32) lives in the 256 MB
         # last-level cache, so the HBM roofline is quoted on the same kernel
         # at uniform level 8 (16.8 M cells, 0.4 GB per step) when it ran
-        "roofline": (roof(res["large32"], 24.0, "k_step_fused_sw_fp32_level8.txt")
+        "roofline": (roof(res["large32"], 24.0, "k_step_fused_sw_fp32_level8.txt", LEVEL8)
                      if "large32" in res else
-                     roof(head, bytes_per_cell, "k_step_fused_sw_fp32_adaptive.txt")),
-        "roofline_adaptive": roof(head, bytes_per_cell, "k_step_fused_sw_fp32_adaptive.txt"),
+                     roof(head, bytes_per_cell, "k_step_fused_sw_fp32_adaptive.txt", ADAPTIVE)),
+        "roofline_adaptive": roof(head, bytes_per_cell, "k_step_fused_sw_fp32_adaptive.txt",
+                                  ADAPTIVE),
+        "status_bits": {k: r["status_bits"] for k, r in res.items()
+                        if isinstance(r, dict) and "status_bits" in r},
     }
     if "fp64" in res:
         out["fp64_plain"] = {"value": res["fp64"]["rate"],
                              "ms_per_step": res["fp64"]["seconds"] / args.steps * 1e3,
                              "kernel_ms": res["fp64"]["kernel_ms_mean"],
-                             "roofline": roof(res["fp64"], 48.0, None)}
+                             "rejected": res["fp64"]["rejected"],
+                             "roofline": roof(res["fp64"], 48.0, None, ADAPTIVE)}
         if "fp32" in res:
             out["speedup_fp32_fused_vs_fp64_plain"] = res["fp32"]["rate"] / res["fp64"]["rate"]
     if "large32" in res:
         out["large_uniform_level8"] = {
             "cells": res["large32"]["kernel_cells_mean"],
+            "steps": args.large_steps,
             "fp32_fused_rate": res["large32"]["rate"],
             "fp64_plain_rate": res["large64"]["rate"],
+            "speedup_fp32_fused_vs_fp64_plain": res["large32"]["rate"] / res["large64"]["rate"],
             "fp32_rel_l1_vs_fp64": res["large32"]["rel_l1_vs_fp64"],
-            "fp32_roofline": roof(res["large32"], 24.0, "k_step_fused_sw_fp32_level8.txt"),
-            "fp64_roofline": roof(res["large64"], 48.0, "k_step_plain_sw_fp64_level8.txt"),
+            "fp32_roofline": roof(res["large32"], 24.0, "k_step_fused_sw_fp32_level8.txt",
+                                  LEVEL8),
+            "fp64_roofline": roof(res["large64"], 48.0, "k_step_plain_sw_fp64_level8.txt",
+                                  LEVEL8),
         }
     if "batch" in res:
         rb = res["batch"]
@@ -613,27 +799,36 @@ def main():
                         "one launch per tile class (a workgroup per tile, or persistent "
                         "workgroups, as the autotuner picks) in a HIP graph",
             "patches": rb["patches"], "cells": rb["cells"], "rate": rb["rate"],
+            "steps": rb["steps"], "attempts": rb["attempts"], "rejected": rb["rejected"],
             "ms_per_step": rb["ms_per_step"], "tuning": rb["tuning"],
             "autotune_ms_per_step": rb["autotune_ms_per_step"],
             "hbm_GBps_algorithmic_whole_step": ach,
             "hbm_frac_whole_step": ach / HBM_PEAK_GBS,
-            "speedup_vs_fp64_plain_adaptive": (rb["rate"] / res["fp64"]["rate"]
-                                               if "fp64" in res else None),
+            "status_words_nonzero": rb["status_words_nonzero"],
+            "status_bits": rb["status_bits"],
         }
+        if "batch64" in res:
+            out["batched_64_forests"]["fp64_plain_same_forests"] = res["batch64"]
+            out["batched_64_forests"]["speedup_vs_fp64_plain_same_forests"] = (
+                rb["rate"] / res["batch64"]["rate"])
     if "sphere" in res:
         out["cubed_sphere"] = dict(res["sphere"], workload=(
             "shallow water on the cubed sphere, 6 trees, adaptive levels 4-7, m=32, "
             "seeded Gaussian height bumps, threshold set for ~50k initial patches, "
             "regrid every 8 steps (|grad h| criterion), FP32 state, FP64 geometry "
             "and sums, plain path with reflux, the library's run loop"))
+        if "sphere64" in res:
+            out["cubed_sphere"]["fp64_state_run"] = res["sphere64"]
     if "mlp" in res:
         out["learned_tagging_mlp"] = res["mlp"]
-    flags = {k: r["status"] for k, r in res.items() if "status" in r and r["status"]}
-    if flags:
-        out["cfl_flags"] = flags
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline()
+    if not args.no_cpu_baseline and "fp32" in res:
+        out["cpu_baseline"] = cpu_baseline(args.warmup, args.steps)
+    if bad:
+        out["flagged_timed_legs"] = bad
     print(json.dumps(out), flush=True)
+    if bad:
+        print(f"timed steps carry error bits: {bad}", file=sys.stderr, flush=True)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

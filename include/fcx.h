@@ -84,11 +84,16 @@ typedef struct {
   int32_t threads;     /* threads per tile workgroup: T*T or 2*T*T
                           (0 = default: 512 for FP64 16 x 16 tiles, else
                           T*T)                                              */
-  int32_t reserved;    /* must be 0                                       */
+  int32_t redo;        /* CFL rule (LeVeque 2002, Sec. 4.4; Clawpack's
+                          time-step control): 1 = an attempt whose largest
+                          Courant number exceeds cfl_max is rejected and
+                          redone with the reduced dt, in fcx_advance,
+                          fcx_run and batches; 0 = such a step is kept and
+                          flagged (status bit 0)                           */
   double g;            /* gravity (shallow water)                         */
   double ax, ay;       /* advection velocity in reference coordinates     */
   double cfl_desired;  /* target Courant number for the next dt           */
-  double cfl_max;      /* larger Courant numbers flag the step            */
+  double cfl_max;      /* larger Courant numbers reject or flag the step  */
 } fcx_config;
 
 const char *fcx_last_error(void);
@@ -186,17 +191,28 @@ int fcx_reflux(fcx_ctx *ctx, const void *q, void *q_new, const double *dt,
 
 /* dt <- dt * cfl_desired / nu_max (unchanged if nu_max == 0); nu_max <- 0;
  * status (device int32): bit 0 set if nu_max > cfl_max (FCX_ECFL), bit 1 if
- * a non-positive depth was met since the last call (FCX_ENEG).  Bits are
- * sticky until the caller clears them. */
+ * a non-positive depth was met since the last call (FCX_ENEG), bit 2 if a
+ * ghost value needed nested interpolation, bit 3 if an attempt was rejected
+ * and redone (redo on; then bit 0 is not set for it).  Bits are sticky
+ * until the caller clears them.  This call never rejects: the caller
+ * decides on a redo (fcx_advance and fcx_run apply the config's rule). */
 int fcx_next_dt(fcx_ctx *ctx, double *nu_max, double *dt, int32_t *status,
                 void *stream);
 
 /* One whole step of the fused path in one call: fcx_fused_step (q ->
  * q_new), then fcx_reflux and fcx_next_dt in one launch (dt is updated for
  * the next step, nu_max cleared, status flags raised); same result as the
- * three calls.  Planar forests only. */
+ * three calls.  With cfg.redo = 1 an attempt whose nu_max exceeds cfl_max is
+ * rejected: q_new receives q unchanged, dt is reduced to
+ * dt * cfl_desired / nu_max and status bit 3 is raised, so the next call
+ * on (q_new -> q) redoes the step.  Planar forests only. */
 int fcx_advance(fcx_ctx *ctx, const void *q, void *q_new, double *dt,
                 double *nu_max, int32_t *status, void *stream);
+
+/* Counters of the steps taken on this context since fcx_create, read after
+ * the device has finished: out[0] accepted steps, out[1] rejected attempts,
+ * out[2] accepted cell updates (interior cells advanced). */
+int fcx_step_stats(const fcx_ctx *ctx, int64_t *out);
 
 /* A run of `steps` whole steps on two caller buffers of `cap` elements
  * each (enough for the finest forest the run can reach): step n = step0 +
@@ -237,12 +253,17 @@ int fcx_regrid_tags(fcx_ctx *ctx, const void *q, const void *ghost,
 
 /* Applies host tags: refine +1, merge families tagged -1, restore balance by
  * refinement.  The context switches to the new forest; the old one is kept
- * for fcx_regrid_transfer.  *n_new receives the new patch count. */
+ * for fcx_regrid_transfer.  *n_new receives the new patch count.
+ * old_to_new (host, caller-allocated, one entry per old patch; NULL: not
+ * wanted) maps each old patch, so that the caller can carry per-patch data
+ * of its own (Sec. 2: the mesher sees only flags): >= 0 the patch is kept
+ * with that new index; -2 - k it was refined, its four children are new
+ * patches k .. k+3; -1 it was merged into a new parent. */
 int fcx_regrid_apply(fcx_ctx *ctx, const int8_t *tags_host, int32_t lmin,
-                     int32_t lmax, int64_t *n_new);
+                     int32_t lmax, int64_t *n_new, int64_t *old_to_new);
 
 /* fcx_ghost_fill of q into ghost, fcx_regrid_tags, the tags to the host
- * and fcx_regrid_apply, in one call (the calling thread polls until the
+ * and fcx_regrid_apply (old_to_new as there), in one call (the calling thread polls until the
  * stream has reached the tags, so it spins for as long as the work queued
  * before them takes).  The new forest's tables are copied to the device in the order of
  * `stream`: later calls that use them go on the same stream or wait for it.
@@ -250,7 +271,7 @@ int fcx_regrid_apply(fcx_ctx *ctx, const int8_t *tags_host, int32_t lmin,
  * *n_new receives the new patch count. */
 int fcx_regrid(fcx_ctx *ctx, const void *q, void *ghost, int32_t criterion,
                double threshold, int32_t lmin, int32_t lmax, int64_t *n_new,
-               void *stream);
+               int64_t *old_to_new, void *stream);
 
 /* Data transfer after fcx_regrid_apply (Sec. 3: interpolate to new fine
  * patches, average to new coarse patches): kept patches copy, refined ones
@@ -273,8 +294,10 @@ int fcx_regrid_transfer(fcx_ctx *ctx, const void *q_old, const void *ghost_old,
  * The contexts must outlive the batch.  The state of all forests is one
  * caller-owned buffer: forest f starts at fcx_batch_state_offset(f) and uses
  * the compact layout of its own context.  dt, nu_max and status are device
- * arrays of n entries (per forest); cfl_desired and cfl_max are those of the
- * first forest. */
+ * arrays of n entries (per forest; status bits as fcx_next_dt's, raised by
+ * the forest they concern); cfl_desired, cfl_max and redo are those of the
+ * first forest (with redo on, a forest's rejected attempt leaves its state
+ * unchanged in q_new and its next attempt uses the reduced dt). */
 int fcx_batch_create(int32_t n, fcx_ctx *const *forests, fcx_batch **out);
 int fcx_batch_destroy(fcx_batch *batch);
 int64_t fcx_batch_state_elems(const fcx_batch *batch);
@@ -300,6 +323,11 @@ int fcx_batch_step(fcx_batch *batch, const void *q, void *q_new, double *dt,
 int fcx_batch_capture(fcx_batch *batch, int32_t steps, void *q_a, void *q_b,
                       double *dt, double *nu_max, int32_t *status);
 int fcx_batch_replay(fcx_batch *batch, void *stream);
+
+/* Per-forest counters since fcx_batch_create, read after the device has
+ * finished: out[3 f + 0] accepted steps, out[3 f + 1] rejected attempts,
+ * out[3 f + 2] accepted cell updates of forest f. */
+int fcx_batch_step_stats(const fcx_batch *batch, int64_t *out);
 
 /* sums[4 f + k]: FP64 conservation sums of forest f (k < meqn; others 0),
  * reduced in a fixed order. */

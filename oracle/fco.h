@@ -70,6 +70,14 @@ int  fco_balance(int32_t ntrees, const fco_tree *trees, int64_t n,
 int  fco_locate_leaf(const fco_mesh *mesh, int32_t tree, int64_t x,
                      int64_t y, int64_t *leaf);
 
+/* ---- threads -------------------------------------------------------- */
+/* Number of threads the ghost fill and the per-patch loop of the step
+ * split whole patches over (default 1; only timing changes: each patch is
+ * computed exactly as with one thread).  The reflux, sums and everything
+ * else stay serial. */
+void fco_set_threads(int32_t n);
+int32_t fco_threads(void);
+
 /* ---- ghost fill, step, sums ---------------------------------------- */
 int  fco_ghost_fill(const fco_mesh *mesh, const fco_params *par, double *q,
                     int32_t *max_depth);

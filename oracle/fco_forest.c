@@ -348,3 +348,10 @@ int fco_balance(int32_t ntrees, const fco_tree *trees, int64_t n,
   free(cur);
   return 0;
 }
+
+/* ---- threads of the per-patch loops ---------------------------------- */
+static int32_t g_threads = 1;
+
+void fco_set_threads(int32_t n) { g_threads = n < 1 ? 1 : n; }
+
+int32_t fco_threads(void) { return g_threads; }

@@ -177,21 +177,30 @@ int fco_ghost_fill(const fco_mesh *mesh, const fco_params *par, double *q,
     return -1;
   const int32_t m = mesh->m, meqn = par->meqn;
   const int64_t F = fco_frame(m);
-  gctx g = {mesh, par, q, 0, 0};
-  double v[FCO_MAXEQ];
-  for (int64_t p = 0; p < mesh->n; ++p)
-    for (int32_t j = -1; j <= m + 2; ++j)
-      for (int32_t i = -1; i <= m + 2; ++i) {
-        int gi = (i < 1 || i > m), gj = (j < 1 || j > m);
-        if (!gi && !gj) continue;
-        /* the four outermost corner cells are never read by the step */
-        if ((i == -1 || i == m + 2) && (j == -1 || j == m + 2)) continue;
-        fco_frame_value(&g, p, i, j, v, 0);
-        for (int k = 0; k < meqn; ++k)
-          q[(p * meqn + k) * F + fco_fidx(m, i, j)] = v[k];
-      }
-  if (max_depth) *max_depth = g.depth_max;
-  return g.error ? -2 : 0;
+  int32_t depth = 0, error = 0;
+  /* every ghost value is evaluated from interior values only, so patches
+   * can be filled in any order (fco_set_threads: whole patches per thread) */
+#pragma omp parallel num_threads(fco_threads()) reduction(max : depth) reduction(| : error)
+  {
+    gctx g = {mesh, par, q, 0, 0};
+    double v[FCO_MAXEQ];
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t p = 0; p < mesh->n; ++p)
+      for (int32_t j = -1; j <= m + 2; ++j)
+        for (int32_t i = -1; i <= m + 2; ++i) {
+          int gi = (i < 1 || i > m), gj = (j < 1 || j > m);
+          if (!gi && !gj) continue;
+          /* the four outermost corner cells are never read by the step */
+          if ((i == -1 || i == m + 2) && (j == -1 || j == m + 2)) continue;
+          fco_frame_value(&g, p, i, j, v, 0);
+          for (int k = 0; k < meqn; ++k)
+            q[(p * meqn + k) * F + fco_fidx(m, i, j)] = v[k];
+        }
+    depth = g.depth_max > depth ? g.depth_max : depth;
+    error |= g.error;
+  }
+  if (max_depth) *max_depth = depth;
+  return error ? -2 : 0;
 }
 
 /* ------------------------------------------------------------------ */

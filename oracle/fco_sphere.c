@@ -103,11 +103,34 @@ static double dot3(const double a[3], const double b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-/* solid angle of the spherical triangle (a, b, c), counter-clockwise */
+/* solid angle of the spherical triangle (a, b, c), counter-clockwise (Van
+ * Oosterom and Strackee).  The triple product a.(b x c) of three nearly
+ * parallel unit vectors is formed as a.((b - a) x (c - a)), equal in exact
+ * arithmetic: the differences of close points are exact and the cross
+ * product of the short vectors keeps full relative accuracy, where b x c
+ * itself would lose it to cancellation (a relative error of order eps / h^2
+ * for a cell of angular size h). */
 static double tri(const double a[3], const double b[3], const double c[3]) {
-  double bc[3];
-  cross3(b, c, bc);
-  return 2.0 * atan2(dot3(a, bc), 1.0 + dot3(a, b) + dot3(b, c) + dot3(c, a));
+  double u[3], v[3], w[3];
+  for (int k = 0; k < 3; ++k) {
+    u[k] = b[k] - a[k];
+    v[k] = c[k] - a[k];
+  }
+  cross3(u, v, w);
+  return 2.0 * atan2(dot3(a, w), 1.0 + dot3(a, b) + dot3(b, c) + dot3(c, a));
+}
+
+/* a x b of two nearly parallel unit vectors, formed as ((a + b) / 2) x
+ * (b - a): equal in exact arithmetic, accurate for close points, and
+ * exactly negated when a and b are swapped (so that a cell edge is the same
+ * whichever side computes it). */
+static void cross_close(const double a[3], const double b[3], double o[3]) {
+  double mid[3], d[3];
+  for (int k = 0; k < 3; ++k) {
+    mid[k] = 0.5 * (a[k] + b[k]);
+    d[k] = b[k] - a[k];
+  }
+  cross3(mid, d, o);
 }
 
 enum { GK = 0, GC = 1, GE = 4, GN = 18 };   /* table offsets, in frames */
@@ -178,7 +201,7 @@ int fco_sphere_build(fco_mesh *mesh) {
           const double *ea = PT(es, i - 1, j - 1);
           const double *eb = dir == 0 ? PT(es, i - 1, j) : PT(es, i, j - 1);
           double cr[3], nn[3], rm[3], tt[3];
-          cross3(ea, eb, cr);
+          cross_close(ea, eb, cr);
           const double len = sqrt(dot3(cr, cr));
           const double sg = dir == 0 ? -1.0 : 1.0;     /* xi-edge: b x a */
           for (int c = 0; c < 3; ++c) nn[c] = sg * cr[c] / len;

@@ -486,43 +486,51 @@ int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
   if ((par->physics == FCO_SPHERE) != (mesh->sphere != 0)) return -1;
   const int32_t m = mesh->m, meqn = par->meqn;
   const int64_t NE = (int64_t)(m + 3) * (m + 2), FR = fco_frame(m);
-  work wk;
-  wk.m = m;
-  wk.meqn = meqn;
-  for (int d = 0; d < 2; ++d) {
-    wk.F[d] = (double *)malloc(sizeof(double) * NE * meqn);
-    wk.AM[d] = (double *)malloc(sizeof(double) * NE * meqn);
-    wk.AP[d] = (double *)malloc(sizeof(double) * NE * meqn);
-    wk.FL[d] = (double *)calloc(NE, sizeof(double));
-  }
-  wk.W = (double *)malloc(sizeof(double) * (m + 3) * MW * meqn);
-  wk.S = (double *)malloc(sizeof(double) * (m + 3) * MW);
-  wk.kap = (double *)malloc(sizeof(double) * FR);
-  wk.eg = (edge_geom *)malloc(sizeof(edge_geom) * (m + 3));
-  wk.tg = NULL;
   double *phi = do_reflux
                     ? (double *)malloc(sizeof(double) * mesh->n * 4 * m * meqn)
                     : NULL;
   double nmax = 0.0;
   int rc = 0;
-  for (int64_t p = 0; p < mesh->n && rc == 0; ++p) {
-    double nu = 0.0;
-    rc = step_patch(mesh, par, p, &q[p * meqn * FR], &qn[p * meqn * FR], dt,
-                    &wk, phi ? &phi[p * 4 * m * meqn] : NULL, &nu);
-    nmax = fmax(nmax, nu);
+  /* patches are independent given the filled frames: with more than one
+   * thread (fco_set_threads) each takes whole patches with a work area of
+   * its own; every patch's arithmetic is the same as with one */
+#pragma omp parallel num_threads(fco_threads()) reduction(max : nmax) reduction(| : rc)
+  {
+    work wk;
+    wk.m = m;
+    wk.meqn = meqn;
+    for (int d = 0; d < 2; ++d) {
+      wk.F[d] = (double *)malloc(sizeof(double) * NE * meqn);
+      wk.AM[d] = (double *)malloc(sizeof(double) * NE * meqn);
+      wk.AP[d] = (double *)malloc(sizeof(double) * NE * meqn);
+      wk.FL[d] = (double *)calloc(NE, sizeof(double));
+    }
+    wk.W = (double *)malloc(sizeof(double) * (m + 3) * MW * meqn);
+    wk.S = (double *)malloc(sizeof(double) * (m + 3) * MW);
+    wk.kap = (double *)malloc(sizeof(double) * FR);
+    wk.eg = (edge_geom *)malloc(sizeof(edge_geom) * (m + 3));
+    wk.tg = NULL;
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t p = 0; p < mesh->n; ++p) {
+      double nu = 0.0;
+      rc |= step_patch(mesh, par, p, &q[p * meqn * FR], &qn[p * meqn * FR], dt,
+                       &wk, phi ? &phi[p * 4 * m * meqn] : NULL, &nu) != 0;
+      nmax = fmax(nmax, nu);
+    }
+    for (int d = 0; d < 2; ++d) {
+      free(wk.F[d]);
+      free(wk.AM[d]);
+      free(wk.AP[d]);
+      free(wk.FL[d]);
+    }
+    free(wk.W);
+    free(wk.S);
+    free(wk.kap);
+    free(wk.eg);
   }
+  if (rc) rc = -1;
   if (rc == 0 && do_reflux) rc = reflux(mesh, par, q, qn, dt, phi);
   if (rc == 0 && mesh->sphere) fco_sphere_project(mesh, par, qn);
-  for (int d = 0; d < 2; ++d) {
-    free(wk.F[d]);
-    free(wk.AM[d]);
-    free(wk.AP[d]);
-    free(wk.FL[d]);
-  }
-  free(wk.W);
-  free(wk.S);
-  free(wk.kap);
-  free(wk.eg);
   free(phi);
   if (numax) *numax = nmax;
   return rc;

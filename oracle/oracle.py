@@ -85,12 +85,24 @@ def lib():
         L.fco_sphere_edge.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
         L.fco_sphere_centre.argtypes = [vp, i64, i32, i32, vp]
         L.fco_rp_sphere.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fco_set_threads.argtypes = [i32]
+        L.fco_threads.restype = i32
         _lib = L
     return _lib
 
 
 def _ptr(a):
     return a.ctypes.data_as(C.c_void_p)
+
+
+def set_threads(n: int) -> None:
+    """Threads over whole patches in the ghost fill and the step's patch
+    loop (results are the same for any count)."""
+    lib().fco_set_threads(int(n))
+
+
+def threads() -> int:
+    return lib().fco_threads()
 
 
 def params(m, physics=ADVECTION, limiter=4, transverse=2, g=1.0, ax=0.0,

@@ -3,6 +3,7 @@
 // dt, sum, tag and transfer kernels.
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
@@ -135,6 +136,8 @@ struct fcx_ctx {
   DevBuf<double> partial;
   DevBuf<int32_t> err;
   DevBuf<uint32_t> ticket;         // last-workgroup ticket of the reflux
+  DevBuf<int64_t> stats;           // {accepted steps, rejected attempts, accepted cells}
+  HostBuf run_host;                // fcx_run: pinned copies of stats
   HostBuf staging;
   int cus = 256;
   size_t lds_per_block = 65536;    // device limit of LDS per workgroup
@@ -263,7 +266,7 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
                                    : (tile == 16 ? (cfg->precision == 64 ? 512 : 256) : 64);
   if (threads != tile * tile && threads != 2 * tile * tile)
     return fail(FCX_EINVAL, "threads must be tile^2 or 2 tile^2");
-  if (cfg->reserved != 0) return fail(FCX_EINVAL, "reserved must be 0");
+  if (cfg->redo != 0 && cfg->redo != 1) return fail(FCX_EINVAL, "redo must be 0 or 1");
   std::vector<fcx_tree> t(trees, trees + n_trees);
   std::string err;
   if (check_connectivity(t, err) != FCX_OK) return fail(FCX_EINVAL, err);
@@ -294,12 +297,14 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
     }
   }
   c->trees = t;
-  if (c->err.ensure(1) != hipSuccess || c->ticket.ensure(1) != hipSuccess) {
+  if (c->err.ensure(1) != hipSuccess || c->ticket.ensure(1) != hipSuccess ||
+      c->stats.ensure(3) != hipSuccess) {
     delete c;
     return fail(FCX_ENOMEM, "hipMalloc failed");
   }
   if (hipMemset(c->err.p, 0, sizeof(int32_t)) != hipSuccess ||
-      hipMemset(c->ticket.p, 0, sizeof(uint32_t)) != hipSuccess) {
+      hipMemset(c->ticket.p, 0, sizeof(uint32_t)) != hipSuccess ||
+      hipMemset(c->stats.p, 0, 3 * sizeof(int64_t)) != hipSuccess) {
     delete c;
     return fail(FCX_EHIP, "hipMemset failed");
   }
@@ -660,8 +665,31 @@ int fcx_fused_step(fcx_ctx* c, const void* q, void* qn, const double* dt,
   return step_dispatch<true>(c, q, nullptr, qn, dt, numax, stream);
 }
 
+// Workgroups that copy a rejected attempt's state (256 threads, a few
+// 16-byte units each, at most one per CU).
+static int64_t redo_grid(const fcx_ctx* c, int64_t n16) {
+  return std::max<int64_t>(1, std::min<int64_t>(c->cus, (n16 + 1023) / 1024));
+}
+
+static NextDtArgs next_args(fcx_ctx* c, double* numax, double* dt, int32_t* status,
+                            int32_t redo) {
+  NextDtArgs nd{};
+  nd.numax = numax;
+  nd.dt = dt;
+  nd.status = status;
+  nd.ticket = c->ticket.p;
+  nd.stats = c->stats.p;
+  nd.cfl_desired = c->cfg.cfl_desired;
+  nd.cfl_max = c->cfg.cfl_max;
+  nd.redo = redo;
+  nd.cells = c->cur.P * c->cfg.m * c->cfg.m;
+  nd.n16 = c->cur.P * c->meqn * c->cfg.m * c->cfg.m * (c->cfg.precision / 8) / 16;
+  return nd;
+}
+
 // All reflux items in one launch; with NEXT the launch also takes the CFL
-// check and next dt (then it runs even without items).
+// check and next dt (then it runs even without items) and, with redo on,
+// the copy of a rejected attempt's state.
 template <typename R, int PHYS, bool NEXT>
 static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
                          hipStream_t s, NextDtArgs nd = {}) {
@@ -669,8 +697,9 @@ static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
   const int32_t n = c->cur.n_reflux_x + c->cur.n_reflux_y;
   if (n == 0 && !NEXT) return FCX_OK;
   const int64_t tot = int64_t(n) * m;
-  const unsigned grid = unsigned(std::max<int64_t>(1, (tot + 255) / 256));
-  nd.ticket = c->ticket.p;
+  int64_t g = std::max<int64_t>(1, (tot + 255) / 256);
+  if (NEXT && nd.redo) g = std::max(g, redo_grid(c, nd.n16));
+  const unsigned grid = unsigned(g);
   hipLaunchKernelGGL((k_reflux<R, PHYS, NEXT>), dim3(grid), dim3(256), 0, s,
                      static_cast<const R*>(q), static_cast<R*>(qn), c->cur.reflux,
                      c->cur.aux, n, reinterpret_cast<const R*>(c->phi.p), dt, m, kphys(c),
@@ -716,8 +745,26 @@ int fcx_next_dt(fcx_ctx* c, double* numax, double* dt, int32_t* status, void* st
   if (!c || !numax || !dt || !status) return fail(FCX_EINVAL, "bad arguments");
   hipLaunchKernelGGL(k_next_dt, dim3(1), dim3(64), 0,
                      static_cast<hipStream_t>(stream), numax, dt, status, c->err.p,
-                     1, c->cfg.cfl_desired, c->cfg.cfl_max);
+                     c->stats.p, c->cfg.cfl_desired, c->cfg.cfl_max,
+                     int64_t(c->cur.P) * c->cfg.m * c->cfg.m);
   HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+// fcx_next_dt with the CFL rule's rejection (redo on): a rejected attempt's
+// q_new receives q.
+static int next_dt_redo(fcx_ctx* c, const void* q, void* qn, double* numax, double* dt,
+                        int32_t* status, hipStream_t s) {
+  const NextDtArgs nd = next_args(c, numax, dt, status, 1);
+  hipLaunchKernelGGL(k_next_dt_redo, dim3(unsigned(redo_grid(c, nd.n16))), dim3(256), 0, s,
+                     static_cast<const uint4*>(q), static_cast<uint4*>(qn), nd, c->err.p);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_step_stats(const fcx_ctx* c, int64_t* out) {
+  if (!c || !out) return fail(FCX_EINVAL, "bad arguments");
+  HIPCHK(hipMemcpy(out, c->stats.p, 3 * sizeof(int64_t), hipMemcpyDeviceToHost));
   return FCX_OK;
 }
 
@@ -794,8 +841,33 @@ int fcx_regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criter
             : launch_tags<float, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
 }
 
+// old_to_new of every old leaf from the transfer plan of the new ones
+// (kind 0: copy of old src, 1: child of old src, 2: parent of the four old
+// leaves from src): >= 0 kept at that index, -2 - k refined with its first
+// child at k, -1 merged into a parent.
+static int fill_old_to_new(const std::vector<int32_t>& kind, const std::vector<int32_t>& src,
+                           int64_t n_old, int64_t* o2n) {
+  const int64_t unset = INT64_MIN;
+  for (int64_t i = 0; i < n_old; ++i) o2n[i] = unset;
+  for (size_t p = 0; p < kind.size(); ++p) {
+    const int64_t s = src[p];
+    if (s < 0 || s >= n_old) return fail(FCX_EINVAL, "transfer plan out of range");
+    if (kind[p] == 0) {
+      o2n[s] = int64_t(p);
+    } else if (kind[p] == 1) {
+      if (o2n[s] == unset) o2n[s] = -2 - int64_t(p);
+    } else {
+      if (s + 3 >= n_old) return fail(FCX_EINVAL, "transfer plan out of range");
+      for (int k = 0; k < 4; ++k) o2n[s + k] = -1;
+    }
+  }
+  for (int64_t i = 0; i < n_old; ++i)
+    if (o2n[i] == unset) return fail(FCX_EINVAL, "an old leaf has no image in the new forest");
+  return FCX_OK;
+}
+
 static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
-                        int64_t* n_new, hipStream_t s, bool ordered) {
+                        int64_t* n_new, int64_t* old_to_new, hipStream_t s, bool ordered) {
   if (!c || !tags || !n_new || lmin < 0 || lmax < lmin || lmax > kMaxLevel)
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
@@ -806,6 +878,10 @@ static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lm
   if (rc != FCX_OK) return fail(rc, err);
   for (int32_t k : kind)
     if (k < 0) return fail(FCX_EINVAL, "new leaf is not a copy, child or parent of old leaves");
+  if (old_to_new) {
+    rc = fill_old_to_new(kind, src, int64_t(c->forest.leaves.size()), old_to_new);
+    if (rc != FCX_OK) return rc;
+  }
   Forest nf;
   nf.adopt(c->trees, std::move(out));
   // the current device forest becomes the old one
@@ -822,8 +898,8 @@ static int regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lm
 }
 
 int fcx_regrid_apply(fcx_ctx* c, const int8_t* tags, int32_t lmin, int32_t lmax,
-                     int64_t* n_new) {
-  return regrid_apply(c, tags, lmin, lmax, n_new, nullptr, false);
+                     int64_t* n_new, int64_t* old_to_new) {
+  return regrid_apply(c, tags, lmin, lmax, n_new, old_to_new, nullptr, false);
 }
 
 template <typename R, int MEQN>
@@ -876,6 +952,7 @@ struct fcx_batch {
   int32_t n = 0;
   int precision = 64;
   double cfl_desired = 0.9, cfl_max = 1.0;
+  int32_t redo = 0;
   std::vector<fcx_ctx*> ctx;
   std::vector<ForestDev> fh;
   std::vector<int64_t> state_off;
@@ -899,7 +976,9 @@ struct fcx_batch {
   int32_t nitems[4] = {0, 0, 0, 0}, item0[4] = {0, 0, 0, 0};
   DevBuf<uint8_t> phi;
   DevBuf<double> partial;
-  DevBuf<int32_t> counters, err;    // counters: persistent launches
+  DevBuf<int32_t> counters, err;    // counters: persistent launches; err: per forest
+  DevBuf<uint32_t> ticket;          // last-workgroup ticket of the next-dt launch
+  DevBuf<int64_t> stats;            // per forest {accepted, rejected, accepted cells}
   HostBuf staging;
   int cus = 256;
   // captured graph
@@ -1038,13 +1117,20 @@ int fcx_batch_create(int32_t n, fcx_ctx* const* forests, fcx_batch** out) {
   b->precision = forests[0]->cfg.precision;
   b->cfl_desired = forests[0]->cfg.cfl_desired;
   b->cfl_max = forests[0]->cfg.cfl_max;
+  b->redo = forests[0]->cfg.redo;
   int dev = 0;
   hipDeviceProp_t prop;
   if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
     b->cus = prop.multiProcessorCount;
   int rc = batch_build(b);
-  if (rc == FCX_OK && b->err.ensure(1) != hipSuccess) rc = fail(FCX_ENOMEM, "hipMalloc failed");
-  if (rc == FCX_OK && hipMemset(b->err.p, 0, 4) != hipSuccess) rc = fail(FCX_EHIP, "hipMemset failed");
+  if (rc == FCX_OK && (b->err.ensure(size_t(n)) != hipSuccess ||
+                       b->ticket.ensure(1) != hipSuccess ||
+                       b->stats.ensure(3 * size_t(n)) != hipSuccess))
+    rc = fail(FCX_ENOMEM, "hipMalloc failed");
+  if (rc == FCX_OK && (hipMemset(b->err.p, 0, 4 * size_t(n)) != hipSuccess ||
+                       hipMemset(b->ticket.p, 0, 4) != hipSuccess ||
+                       hipMemset(b->stats.p, 0, 24 * size_t(n)) != hipSuccess))
+    rc = fail(FCX_EHIP, "hipMemset failed");
   if (rc != FCX_OK) { delete b; return rc; }
   *out = b;
   return FCX_OK;
@@ -1141,12 +1227,30 @@ static int batch_step_t(fcx_batch* b, const void* q, void* qn, double* dt,
     hipLaunchKernelGGL((k_batch_reflux<R>), dim3(unsigned((tot + 255) / 256)), dim3(256),
                        0, s, static_cast<const R*>(q), static_cast<R*>(qn),
                        b->reflux + o, b->reflux_forest + o, n, b->rec, b->phislot,
-                       b->forests, reinterpret_cast<const R*>(b->phi.p), dt, b->err.p);
+                       b->forests, reinterpret_cast<const R*>(b->phi.p), dt, b->err.p,
+                       numax, b->cfl_max, b->redo);
     HIPCHK(hipGetLastError());
   }
-  hipLaunchKernelGGL(k_next_dt, dim3((b->n + 63) / 64), dim3(64), 0, s, numax, dt,
-                     status, b->err.p, b->n, b->cfl_desired, b->cfl_max);
+  NextDtArgs nd{};
+  nd.numax = numax;
+  nd.dt = dt;
+  nd.status = status;
+  nd.ticket = b->ticket.p;
+  nd.stats = b->stats.p;
+  nd.cfl_desired = b->cfl_desired;
+  nd.cfl_max = b->cfl_max;
+  nd.redo = b->redo;
+  hipLaunchKernelGGL((k_batch_next_dt<R>), dim3(unsigned(b->n * kBatchRedoParts)), dim3(256),
+                     0, s, static_cast<const R*>(q), static_cast<R*>(qn), b->forests,
+                     b->first, b->n, nd, b->err.p);
   HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_batch_step_stats(const fcx_batch* b, int64_t* out) {
+  if (!b || !out) return fail(FCX_EINVAL, "bad arguments");
+  HIPCHK(hipMemcpy(out, b->stats.p, 3 * sizeof(int64_t) * size_t(b->n),
+                   hipMemcpyDeviceToHost));
   return FCX_OK;
 }
 
@@ -1337,9 +1441,9 @@ int fcx_advance(fcx_ctx* c, const void* q, void* qn, double* dt, double* numax,
   if (!c || !status) return fail(FCX_EINVAL, "bad arguments");
   int rc = fcx_fused_step(c, q, qn, dt, numax, stream);
   if (rc != FCX_OK) return rc;
-  // reflux and next dt in one launch
+  // reflux and next dt (and the copy of a rejected attempt) in one launch
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const NextDtArgs nd{numax, dt, status, nullptr, c->cfg.cfl_desired, c->cfg.cfl_max};
+  const NextDtArgs nd = next_args(c, numax, dt, status, c->cfg.redo);
   const bool dp = c->cfg.precision == 64;
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_reflux<double, FCX_ADVECTION, true>(c, q, qn, dt, s, nd)
@@ -1351,7 +1455,8 @@ int fcx_advance(fcx_ctx* c, const void* q, void* qn, double* dt, double* numax,
 // ---- tags and mesh change in one call ---------------------------------------
 
 int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double threshold,
-               int32_t lmin, int32_t lmax, int64_t* n_new, void* stream) {
+               int32_t lmin, int32_t lmax, int64_t* n_new, int64_t* old_to_new,
+               void* stream) {
   if (!c || !q || !ghost || !n_new) return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   const int64_t P = c->cur.P;
@@ -1373,7 +1478,7 @@ int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double
     if (e != hipErrorNotReady) HIPCHK(e);
   }
   return regrid_apply(c, reinterpret_cast<const int8_t*>(c->tags_host.p), lmin, lmax, n_new,
-                      s, true);
+                      old_to_new, s, true);
 }
 
 // ---- a run of many steps ----------------------------------------------------
@@ -1393,12 +1498,23 @@ int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* gh
   int cur = 0;
   int64_t cells = 0;
   const int64_t mm = int64_t(c->cfg.m) * c->cfg.m;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool redo = c->cfg.redo != 0;
+  // with redo on, the accepted cell updates are counted on the device: a
+  // copy of the counters before the run and one after it
+  int64_t* counts = nullptr;
+  if (redo) {
+    HIPCHK(c->run_host.ensure(6 * sizeof(int64_t)));
+    counts = reinterpret_cast<int64_t*>(c->run_host.p);
+    HIPCHK(hipMemcpyAsync(counts, c->stats.p, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  }
   for (int32_t k = 0; k < steps; ++k) {
     const int64_t n = int64_t(step0) + k;
     if (regrid_every > 0 && n > 0 && n % regrid_every == 0) {
       if (fcx_ghost_elems(c) > ghost_cap) return fail(FCX_ENOMEM, "ghost capacity exceeded");
       int64_t pn = 0;
-      int rc = fcx_regrid(c, buf[cur], ghost, criterion, threshold, lmin, lmax, &pn, stream);
+      int rc = fcx_regrid(c, buf[cur], ghost, criterion, threshold, lmin, lmax, &pn, nullptr,
+                          stream);
       if (rc != FCX_OK) return rc;
       if (fcx_state_elems(c) > cap) return fail(FCX_ENOMEM, "state capacity exceeded");
       rc = fcx_regrid_transfer(c, buf[cur], ghost, buf[1 - cur], stream);
@@ -1414,11 +1530,19 @@ int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* gh
       rc = fcx_ghost_fill(c, buf[cur], ghost, stream);
       if (rc == FCX_OK) rc = fcx_patch_step(c, buf[cur], ghost, buf[1 - cur], dt, nu_max, stream);
       if (rc == FCX_OK) rc = fcx_reflux(c, buf[cur], buf[1 - cur], dt, stream);
-      if (rc == FCX_OK) rc = fcx_next_dt(c, nu_max, dt, status, stream);
+      if (rc == FCX_OK)
+        rc = redo ? next_dt_redo(c, buf[cur], buf[1 - cur], nu_max, dt, status, s)
+                  : fcx_next_dt(c, nu_max, dt, status, stream);
     }
     if (rc != FCX_OK) return rc;
     cur = 1 - cur;
     cells += c->cur.P * mm;
+  }
+  if (redo) {
+    HIPCHK(hipMemcpyAsync(counts + 3, c->stats.p, 3 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+    cells = counts[5] - counts[2];
   }
   *which = cur;
   *cell_updates = cells;

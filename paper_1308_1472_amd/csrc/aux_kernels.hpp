@@ -130,23 +130,59 @@ __device__ __forceinline__ void reflux_corr(const R* __restrict__ q, const Reflu
   for (int k = 0; k < MEQN; ++k) corr[k] = fine[k] + corr[k];
 }
 
-// CFL check and next dt of forest f (status bits: 1 CFL exceeded,
-// 2 negative depth, 4 nesting error); clears numax and the error word.
+// Status bits of the next-dt step (sticky until the caller clears them).
+constexpr int32_t kStatCfl = 1;         // nu_max > cfl_max in an accepted step
+constexpr int32_t kStatNeg = 2;         // a non-positive depth was met
+constexpr int32_t kStatNested = 4;      // a ghost needed nested interpolation
+constexpr int32_t kStatRedone = 8;      // an attempt was rejected and is redone
+
+// The CFL rule of the wave-propagation method (LeVeque 2002, Sec. 4.4 and
+// the time-step control of Clawpack): with redo on, an attempt whose largest
+// Courant number exceeds cfl_max is rejected (the caller's q_new receives q
+// unchanged, see copy_state) and the next attempt uses the reduced dt.
+__device__ __forceinline__ bool rejected(const double* numax, int f, double cfl_max,
+                                         int32_t redo) {
+  return redo && numax[f] > cfl_max;
+}
+
+// CFL check and next dt of forest f: dt <- dt * cfl_desired / nu_max, the
+// status bits above, error word f read and cleared, numax cleared; stats
+// (null: none) counts per forest {accepted steps, rejected attempts,
+// accepted cell updates}.
 __device__ __forceinline__ void next_dt_one(double* numax, double* dt, int32_t* status,
-                                            int32_t* err, int f, double cfl_desired,
-                                            double cfl_max) {
+                                            int32_t* err, int64_t* stats, int f,
+                                            double cfl_desired, double cfl_max,
+                                            int32_t redo, int64_t cells) {
   const double nu = numax[f];
+  const bool rej = redo && nu > cfl_max;
   int32_t st = 0;
-  if (nu > cfl_max) st |= 1;
-  if (f == 0) {
-    const int32_t e = __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (e & kErrNegDepth) st |= 2;
-    if (e & kErrNested) st |= 4;
-    *err = 0;
-  }
+  if (nu > cfl_max) st |= rej ? kStatRedone : kStatCfl;
+  const int32_t e = __hip_atomic_load(err + f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (e & kErrNegDepth) st |= kStatNeg;
+  if (e & kErrNested) st |= kStatNested;
+  err[f] = 0;
   status[f] |= st;
   if (nu > 0.0) dt[f] = dt[f] * cfl_desired / nu;
   numax[f] = 0.0;
+  if (stats) {
+    int64_t* s = stats + 3 * f;
+    if (rej) {
+      s[1] += 1;
+    } else {
+      s[0] += 1;
+      s[2] += cells;
+    }
+  }
+}
+
+// Copies this workgroup's share (of `parts` equal shares, share `part`) of
+// n16 16-byte units from src to dst.
+__device__ __forceinline__ void copy_share(const uint4* __restrict__ src,
+                                           uint4* __restrict__ dst, int64_t n16, int part,
+                                           int parts) {
+  const int64_t per = (n16 + parts - 1) / parts;
+  const int64_t lo = int64_t(part) * per, hi = lo + per < n16 ? lo + per : n16;
+  for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) dst[i] = src[i];
 }
 
 struct NextDtArgs {
@@ -154,7 +190,11 @@ struct NextDtArgs {
   double* dt;
   int32_t* status;
   uint32_t* ticket;                          // zero between launches
+  int64_t* stats;
   double cfl_desired, cfl_max;
+  int32_t redo;
+  int64_t cells;                             // cell updates of an accepted step
+  int64_t n16;                               // size of the state in 16-byte units
 };
 
 // Reflux: one thread per (coarse-fine face item, coarse cell along it), all
@@ -197,15 +237,21 @@ __device__ __forceinline__ void reflux_cell(const R* __restrict__ q, R* __restri
 }
 
 // All reflux items in one launch.  With NEXT, the workgroup that finishes
-// last also takes the CFL check and the next dt.
+// last also takes the CFL check and the next dt; an attempt that the CFL
+// rule rejects (redo on) skips the corrections, and every workgroup copies
+// its share of q into q_new instead, so that q_new holds the unchanged state.
 template <typename R, int PHYS, bool NEXT>
 __global__ void __launch_bounds__(256)
 k_reflux(const R* __restrict__ q, R* __restrict__ qn,
          const RefluxItem* __restrict__ items, const RefluxAux* __restrict__ aux,
          int32_t nitems, const R* __restrict__ phi, const double* dtp, int m, KPhys ph,
          int32_t* err, NextDtArgs nd) {
+  const bool rej = NEXT && rejected(nd.numax, 0, nd.cfl_max, nd.redo);
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (t < int64_t(nitems) * m)
+  if (rej)
+    copy_share(reinterpret_cast<const uint4*>(q), reinterpret_cast<uint4*>(qn), nd.n16,
+               blockIdx.x, gridDim.x);
+  else if (t < int64_t(nitems) * m)
     reflux_cell<R, PHYS>(q, qn, items, aux, int32_t(t / m), int(t % m) + 1, phi, dtp, m, ph,
                          err);
   if (NEXT) {
@@ -218,19 +264,43 @@ k_reflux(const R* __restrict__ q, R* __restrict__ qn,
     __syncthreads();
     if (last && threadIdx.x == 0) {
       __threadfence();
-      next_dt_one(nd.numax, nd.dt, nd.status, err, 0, nd.cfl_desired, nd.cfl_max);
+      next_dt_one(nd.numax, nd.dt, nd.status, err, nd.stats, 0, nd.cfl_desired, nd.cfl_max,
+                  nd.redo, nd.cells);
       *nd.ticket = 0;
     }
   }
 }
 
 // ---------------------------------------------------------------------------
-__global__ void k_next_dt(double* numax, double* dt, int32_t* status,
-                          int32_t* err, int32_t nforest, double cfl_desired,
-                          double cfl_max) {
-  const int f = blockIdx.x * blockDim.x + threadIdx.x;
-  if (f >= nforest) return;
-  next_dt_one(numax, dt, status, err, f, cfl_desired, cfl_max);
+// Next dt of one forest without a rejection copy (the caller decides).
+__global__ void k_next_dt(double* numax, double* dt, int32_t* status, int32_t* err,
+                          int64_t* stats, double cfl_desired, double cfl_max,
+                          int64_t cells) {
+  if (blockIdx.x == 0 && threadIdx.x == 0)
+    next_dt_one(numax, dt, status, err, stats, 0, cfl_desired, cfl_max, 0, cells);
+}
+
+// Next dt of one forest with the CFL rule's rejection: every workgroup
+// copies its share of q into q_new if the attempt is rejected; the last one
+// takes the next dt.
+__global__ void __launch_bounds__(256)
+k_next_dt_redo(const uint4* __restrict__ q, uint4* __restrict__ qn, NextDtArgs nd,
+               int32_t* err) {
+  if (rejected(nd.numax, 0, nd.cfl_max, nd.redo))
+    copy_share(q, qn, nd.n16, blockIdx.x, gridDim.x);
+  __shared__ bool last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(nd.ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    __threadfence();
+    next_dt_one(nd.numax, nd.dt, nd.status, err, nd.stats, 0, nd.cfl_desired, nd.cfl_max,
+                nd.redo, nd.cells);
+    *nd.ticket = 0;
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -13,6 +13,7 @@
 // The autotuner picks the form.
 #pragma once
 
+#include "aux_kernels.hpp"
 #include "step.hpp"
 
 namespace fcx {
@@ -35,7 +36,7 @@ struct BatchArgs {
   const int32_t* __restrict__ pforest;     // forest of every global patch
   const ForestDev* __restrict__ forests;
   R* phi;
-  int32_t* err;
+  int32_t* err;                            // per forest
   const uint32_t* __restrict__ items;      // (patch << 4) | tile
   int32_t item0, nitems;                   // this class's items
   const int32_t* __restrict__ range;       // persistent: [9] item range of each XCD
@@ -57,7 +58,7 @@ __device__ __forceinline__ StepArgs<R> forest_args(const BatchArgs<R>& B, int f,
   A.rec = B.rec;
   A.phislot = B.phislot;
   A.phi = B.phi + (F.phi_base - int64_t(F.slot_base) * 4 * F.m * F.meqn);
-  A.err = B.err;
+  A.err = B.err + f;
   A.P = 0;
   A.m = F.m;
   A.lm = F.lm;
@@ -135,18 +136,22 @@ __global__ void k_zero_i32(int32_t* a, int n) {
 }
 
 // Reflux of a batch: one thread per (coarse-fine face item, coarse cell);
-// items are grouped by forest, 32 threads per item.
+// items are grouped by forest, 32 threads per item.  Items of a forest whose
+// attempt the CFL rule rejects are skipped (its state is restored by
+// k_batch_next_dt).
 template <typename R>
 __global__ void __launch_bounds__(256)
 k_batch_reflux(const R* q, R* qn, const RefluxItem* __restrict__ items,
                const int32_t* __restrict__ item_forest, int32_t nitems,
                const PatchRec* __restrict__ rec, const int32_t* __restrict__ phislot,
                const ForestDev* __restrict__ forests, const R* phi,
-               const double* dt, int32_t* err) {
+               const double* dt, int32_t* err, const double* numax, double cfl_max,
+               int32_t redo) {
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= int64_t(nitems) * 32) return;
   const int ii = int(t >> 5), tc = int(t & 31) + 1;
   const int f = item_forest[ii];
+  if (rejected(numax, f, cfl_max, redo)) return;
   const ForestDev F = forests[f];
   const int m = F.m;
   if (tc > m) return;
@@ -162,6 +167,7 @@ k_batch_reflux(const R* q, R* qn, const RefluxItem* __restrict__ items,
   const double dxc = ldexp(1.0, -rec[C].level) / m;
   R qc[3], corr[3] = {0, 0, 0};
   const int meqn = F.meqn;
+  int32_t* ef = err + f;
   for (int k = 0; k < meqn; ++k)
     qc[k] = qf[(size_t(C * meqn + k) * m + (jc - 1)) * m + (ic - 1)];
   const R* pf = phf + size_t(phislot[fp]) * 4 * m * meqn;
@@ -174,11 +180,11 @@ k_batch_reflux(const R* q, R* qn, const RefluxItem* __restrict__ items,
     for (int k = 0; k < meqn; ++k)
       qv[k] = qf[(size_t(fp * meqn + k) * m + (fj - 1)) * m + (fi - 1)];
     if (F.physics == FCX_ADVECTION) {
-      if (hi) fluct_sum<R, FCX_ADVECTION>(F.ph, d, qc, qv, fs, err);
-      else fluct_sum<R, FCX_ADVECTION>(F.ph, d, qv, qc, fs, err);
+      if (hi) fluct_sum<R, FCX_ADVECTION>(F.ph, d, qc, qv, fs, ef);
+      else fluct_sum<R, FCX_ADVECTION>(F.ph, d, qv, qc, fs, ef);
     } else {
-      if (hi) fluct_sum<R, FCX_SHALLOW>(F.ph, d, qc, qv, fs, err);
-      else fluct_sum<R, FCX_SHALLOW>(F.ph, d, qv, qc, fs, err);
+      if (hi) fluct_sum<R, FCX_SHALLOW>(F.ph, d, qc, qv, fs, ef);
+      else fluct_sum<R, FCX_SHALLOW>(F.ph, d, qv, qc, fs, ef);
     }
     for (int k = 0; k < meqn; ++k)
       corr[k] += R(0.5 * dxc) * fs[k] - pf[(ff * m + (pos - 1)) * meqn + k];
@@ -188,6 +194,43 @@ k_batch_reflux(const R* q, R* qn, const RefluxItem* __restrict__ items,
   for (int k = 0; k < meqn; ++k)
     qnf[(size_t(C * meqn + k) * m + (jc - 1)) * m + (ic - 1)] -=
         fac * (corr[k] - pc[(fc * m + (tc - 1)) * meqn + k]);
+}
+
+// Per-forest CFL check and next dt of a batch: kBatchRedoParts workgroups
+// per forest copy their shares of a rejected forest's q into q_new; the last
+// workgroup to finish takes the next dt of every forest.
+constexpr int kBatchRedoParts = 8;
+
+template <typename R>
+__global__ void __launch_bounds__(256)
+k_batch_next_dt(const R* q, R* qn, const ForestDev* __restrict__ forests,
+                const int32_t* __restrict__ first, int32_t nforest, NextDtArgs nd,
+                int32_t* err) {
+  const int f = blockIdx.x / kBatchRedoParts, part = blockIdx.x % kBatchRedoParts;
+  if (f < nforest && rejected(nd.numax, f, nd.cfl_max, nd.redo)) {
+    const ForestDev F = forests[f];
+    const int64_t elems = int64_t(first[f + 1] - first[f]) * F.meqn * F.m * F.m;
+    const int64_t units = elems * int64_t(sizeof(R)) / 16;
+    copy_share(reinterpret_cast<const uint4*>(q + F.state_base),
+               reinterpret_cast<uint4*>(qn + F.state_base), units, part, kBatchRedoParts);
+  }
+  __shared__ bool last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(nd.ticket, 1u) == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  for (int g = threadIdx.x; g < nforest; g += blockDim.x) {
+    const ForestDev F = forests[g];
+    const int64_t cells = int64_t(first[g + 1] - first[g]) * F.m * F.m;
+    next_dt_one(nd.numax, nd.dt, nd.status, err, nd.stats, g, nd.cfl_desired, nd.cfl_max,
+                nd.redo, cells);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *nd.ticket = 0;
 }
 
 // Per-patch FP64 partial sums (stride 4) of a batch, fixed thread order.

@@ -93,11 +93,31 @@ __device__ __forceinline__ double dot3(const double* a, const double* b) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 // solid angle of the counter-clockwise spherical triangle (Van Oosterom and
-// Strackee)
+// Strackee), with the triple product taken over the two short sides,
+// a.((b - a) x (c - a)): for a cell of angular size h, a.(b x c) formed
+// directly loses relative accuracy to cancellation (an error of order
+// eps / h^2, about 1e-9 for the finest cells of a level-7 patch of 32 x 32),
+// while the differences of close points are exact and this form keeps it.
 __device__ __forceinline__ double tri_area(const double* a, const double* b, const double* c) {
-  double bc[3];
-  cross3(b, c, bc);
-  return 2.0 * atan2(dot3(a, bc), 1.0 + dot3(a, b) + dot3(b, c) + dot3(c, a));
+  double u[3], v[3], w[3];
+  for (int k = 0; k < 3; ++k) {
+    u[k] = b[k] - a[k];
+    v[k] = c[k] - a[k];
+  }
+  cross3(u, v, w);
+  return 2.0 * atan2(dot3(a, w), 1.0 + dot3(a, b) + dot3(b, c) + dot3(c, a));
+}
+
+// a x b for two close unit vectors as their mean crossed with their
+// difference: accurate where a x b cancels, and exactly negated when a and b
+// swap, so an edge shared by two cells or patches is the same from either.
+__device__ __forceinline__ void cross_near(const double* a, const double* b, double* o) {
+  double mid[3], d[3];
+  for (int k = 0; k < 3; ++k) {
+    mid[k] = 0.5 * (a[k] + b[k]);
+    d[k] = b[k] - a[k];
+  }
+  cross3(mid, d, o);
 }
 
 // frame cell (i, j) lies in a corner region at a cube vertex
@@ -148,7 +168,7 @@ k_sphere_metrics(const PatchRec* __restrict__ rec, int m, int lm, double* __rest
       const double* ea = pt(own, i - 1, j - 1, be);
       const double* eb = dir == 0 ? pt(own, i - 1, j, bf) : pt(own, i, j - 1, bf);
       double cr[3], nn[3], rm[3], tt[3];
-      cross3(ea, eb, cr);
+      cross_near(ea, eb, cr);
       const double len = sqrt(dot3(cr, cr));
       const double sg = dir == 0 ? -1.0 : 1.0;
       for (int c = 0; c < 3; ++c) nn[c] = sg * cr[c] / len;
@@ -406,7 +426,9 @@ k_sphere_step(SphereArgs<R> A) {
     }
     for (int k = 0; k < 4; ++k) { o[kSEam + k] = am[k]; o[kSEap + k] = ap[k]; }
     o[kSEfl] = fl;
-    if (r >= 1 && r <= T) {
+    // Courant numbers of the edges the patch owns (1..T+1 of the tile; the
+    // outer halo edges of a tile on a patch face join two ghost cells)
+    if (r >= 1 && r <= T && e >= 1 && e <= T + 1) {
       const double dtdl = dtk[lf(il, jl)], dtdr = dtk[lf(ir, jr)];
       for (int w = 0; w < 3; ++w) {
         nmax = fmax(nmax, dtdr * fmax(double(s[w]), 0.0));

@@ -40,6 +40,7 @@ EXPORTS = [
     "fcx_batch_replay", "fcx_batch_sums", "fcx_features", "fcx_mlp_forward",
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
     "fcx_sphere_geometry", "fcx_advance", "fcx_regrid", "fcx_run",
+    "fcx_step_stats", "fcx_batch_step_stats",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -55,7 +56,7 @@ class Config(C.Structure):
     _fields_ = [("m", C.c_int32), ("precision", C.c_int32),
                 ("physics", C.c_int32), ("limiter", C.c_int32),
                 ("transverse", C.c_int32), ("tile", C.c_int32),
-                ("threads", C.c_int32), ("reserved", C.c_int32),
+                ("threads", C.c_int32), ("redo", C.c_int32),
                 ("g", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
                 ("cfl_desired", C.c_double), ("cfl_max", C.c_double)]
 
@@ -96,7 +97,7 @@ def lib():
         L.fcx_next_dt.argtypes = [vp, vp, vp, vp, vp]
         L.fcx_conservation_sums.argtypes = [vp, vp, vp, vp]
         L.fcx_regrid_tags.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp]
-        L.fcx_regrid_apply.argtypes = [vp, vp, i32, i32, vp]
+        L.fcx_regrid_apply.argtypes = [vp, vp, i32, i32, vp, vp]
         L.fcx_regrid_transfer.argtypes = [vp, vp, vp, vp, vp]
         L.fcx_batch_create.argtypes = [i32, vp, vp]
         L.fcx_batch_destroy.argtypes = [vp]
@@ -119,7 +120,9 @@ def lib():
         L.fcx_dilate_tags.argtypes = [vp, vp, i32, vp, vp]
         L.fcx_sphere_geometry.argtypes = [vp, vp, vp]
         L.fcx_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp]
-        L.fcx_regrid.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp]
+        L.fcx_regrid.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp, vp]
+        L.fcx_step_stats.argtypes = [vp, vp]
+        L.fcx_batch_step_stats.argtypes = [vp, vp]
         L.fcx_run.argtypes = [vp, i32, vp, vp, i64, vp, i64, i32, i32, i32, i32, dp, i32,
                               i32, vp, vp, vp, vp, vp, vp]
         _lib = L
@@ -179,9 +182,9 @@ def regrid_leaves(trees, leaves, tags, lmin, lmax) -> np.ndarray:
 
 def config(m, precision=64, physics=FCX_SHALLOW, limiter=4, transverse=2,
            tile=0, threads=0, g=1.0, ax=0.0, ay=0.0, cfl_desired=0.9,
-           cfl_max=1.0):
-    return Config(m, precision, physics, limiter, transverse, tile, threads, 0,
-                  g, ax, ay, cfl_desired, cfl_max)
+           cfl_max=1.0, redo=1):
+    return Config(m, precision, physics, limiter, transverse, tile, threads,
+                  int(redo), g, ax, ay, cfl_desired, cfl_max)
 
 
 def _stream(stream):
@@ -357,6 +360,12 @@ class Context:
         _check(lib().fcx_next_dt(self.h, self._d(numax), self._d(dt),
                                  self._d(status, 1, torch.int32), _stream(stream)))
 
+    def step_stats(self):
+        """(accepted steps, rejected attempts, accepted cell updates)."""
+        out = np.zeros(3, dtype=np.int64)
+        _check(lib().fcx_step_stats(self.h, _np_ptr(out)))
+        return tuple(int(v) for v in out)
+
     def conservation_sums(self, q, sums, stream=None):
         _check(lib().fcx_conservation_sums(self.h, self._q(q),
                                            self._d(sums, self.meqn),
@@ -395,14 +404,18 @@ class Context:
                                          _stream(stream)))
         return out.view(self.num_patches(), GEO_FRAMES, m + 4, m + 4)
 
-    def regrid(self, q, ghost, criterion, threshold, lmin, lmax, stream=None) -> int:
+    def regrid(self, q, ghost, criterion, threshold, lmin, lmax, stream=None,
+               old_to_new=False):
         """Ghost fill, tags, and mesh change in one call; returns the new
         patch count (then allocate the new state and call regrid_transfer
-        with q and ghost)."""
+        with q and ghost), and with old_to_new=True also the old-to-new map
+        (see regrid_apply)."""
         n = C.c_int64()
+        o2n = np.zeros(self.num_patches(), dtype=np.int64) if old_to_new else None
         _check(lib().fcx_regrid(self.h, self._q(q), self._g(ghost), criterion, threshold,
-                                lmin, lmax, C.byref(n), _stream(stream)))
-        return n.value
+                                lmin, lmax, C.byref(n),
+                                _np_ptr(o2n) if old_to_new else None, _stream(stream)))
+        return (n.value, o2n) if old_to_new else n.value
 
     def run(self, q0, q1, ghost, steps, step0, regrid_every, criterion, threshold,
             lmin, lmax, dt, numax, status, fused=True, stream=None):
@@ -425,13 +438,18 @@ class Context:
                              C.byref(cells), _stream(stream)))
         return which.value, cells.value
 
-    def regrid_apply(self, tags_host, lmin, lmax) -> int:
+    def regrid_apply(self, tags_host, lmin, lmax, old_to_new=False):
+        """Applies host tags; returns the new patch count, and with
+        old_to_new=True also the map of every old patch: >= 0 kept at that
+        index, -2 - k refined into k .. k+3, -1 merged into a parent."""
         t = np.ascontiguousarray(tags_host, dtype=np.int8)
         if len(t) != self.num_patches():
             raise ValueError("one tag per patch expected")
         n = C.c_int64()
-        _check(lib().fcx_regrid_apply(self.h, _np_ptr(t), lmin, lmax, C.byref(n)))
-        return n.value
+        o2n = np.zeros(len(t), dtype=np.int64) if old_to_new else None
+        _check(lib().fcx_regrid_apply(self.h, _np_ptr(t), lmin, lmax, C.byref(n),
+                                      _np_ptr(o2n) if old_to_new else None))
+        return (n.value, o2n) if old_to_new else n.value
 
     def regrid_transfer(self, q_old, ghost_old, q_new, stream=None):
         # q_old / ghost_old are laid out on the previous forest
@@ -499,6 +517,13 @@ class Batch:
 
     def replay(self, stream=None):
         _check(lib().fcx_batch_replay(self.h, _stream(stream)))
+
+    def step_stats(self):
+        """(n, 3): per forest accepted steps, rejected attempts, accepted
+        cell updates."""
+        out = np.zeros((self.n, 3), dtype=np.int64)
+        _check(lib().fcx_batch_step_stats(self.h, _np_ptr(out)))
+        return out
 
     def sums(self, q, out, stream=None):
         import torch

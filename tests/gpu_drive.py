@@ -99,6 +99,10 @@ class Gpu:
         self.ctx.ghost_fill(self.q, self.ghost)
 
     def step(self, dt=None, fused=False, reflux=True, auto_dt=False):
+        """One attempt through the single calls.  With auto_dt the next dt
+        follows fcx_next_dt, and with the config's redo rule an attempt
+        whose nu exceeds cfl_max is rejected here on the host: the state
+        stays (the public next-dt call never rejects by itself)."""
         if dt is not None:
             self.dt.fill_(dt)
         if fused:
@@ -110,11 +114,14 @@ class Gpu:
             self.ctx.reflux(self.q, self.qn, self.dt)
         nu = float(self.numax.item())
         used = float(self.dt.item())
+        accept = True
         if auto_dt:
             self.ctx.next_dt(self.numax, self.dt, self.status)
+            accept = not (self.cfg.redo and nu > self.cfg.cfl_max)
         else:
             self.numax.zero_()
-        self.q, self.qn = self.qn, self.q
+        if accept:
+            self.q, self.qn = self.qn, self.q
         return nu, used
 
     def conservation_sums(self):
@@ -135,6 +142,17 @@ class Gpu:
         self._alloc()
         self.ctx.regrid_transfer(q_old, g_old, self.q)
         self.torch.cuda.synchronize()
+
+
+def oracle_attempt(mesh, par, q, dt, cfl_desired=0.9, cfl_max=1.0):
+    """One attempt of the oracle under the CFL rule of the wave-propagation
+    method (Clawpack's time-step control): the step is taken with dt; if its
+    largest Courant number exceeds cfl_max it is rejected (the state stays);
+    either way the next dt is dt * cfl_desired / nu.  Returns (state, nu,
+    next dt, accepted)."""
+    qn, nu = O.advance(mesh, par, q, dt)
+    ok = not nu > cfl_max
+    return (qn if ok else q), nu, dt * cfl_desired / nu, ok
 
 
 def oracle_params(cfg):

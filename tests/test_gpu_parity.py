@@ -1,23 +1,35 @@
 """GPU parity: every C-ABI call of the HIP path against the CPU FP64 oracle on
-identical seeded inputs.  FP64 bar: 1e-12 relative to max|q| (the target
-the method's double-precision path is held to); FP32 bar: 1e-5 relative L1
-per component against the FP64 oracle on the same mesh schedule."""
+identical seeded inputs.  FP64 bar: 1e-12 relative, per component, to that
+component's max|q| (the target the method's double-precision path is held
+to; a component whose largest value is below 1e-3 of the largest
+component's is measured against that floor instead); FP32 bar: 1e-5
+relative L1 per component against the FP64 oracle on the same mesh
+schedule."""
 import numpy as np
 import pytest
 
 from oracle import oracle as O
 from paper_1308_1472_amd import fcx
 from paper_1308_1472_amd import inputs as I
-from tests.gpu_drive import (Gpu, ghost_to_frame, needed_mask, oracle_params,
-                             say, smooth_sw_state)
+from tests.gpu_drive import (Gpu, ghost_to_frame, needed_mask, oracle_attempt,
+                             oracle_params, say, smooth_sw_state)
 
 pytestmark = pytest.mark.gpu
 
 FP64_TOL = 1e-12
 
 
-def _rel(a, b):
-    return np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+def _rel(a, b, axis=1):
+    """Largest over components (axis `axis`) of max|a - b| / max|b|, the
+    scale floored at 1e-3 of the largest component's."""
+    a = np.moveaxis(np.asarray(a, float), axis, 0)
+    b = np.moveaxis(np.asarray(b, float), axis, 0)
+    top = max(np.max(np.abs(b)), 1e-300)
+    worst = 0.0
+    for ak, bk in zip(a, b):
+        scale = max(np.max(np.abs(bk)), 1e-3 * top)
+        worst = max(worst, np.max(np.abs(ak - bk)) / scale)
+    return worst
 
 
 def _forest(domain, seed, lmin=2, lmax=5, nsplit=30):
@@ -62,8 +74,8 @@ def test_ghost_fill_matches_oracle(domain, phys, m):
     mesh = O.Mesh(trees, lv, m)
     f = O.framed(q, m)
     O.ghost_fill(mesh, oracle_params(cfg), f)
-    mask = np.broadcast_to(needed_mask(m), got.shape)
-    assert _rel(got[mask], f[mask]) <= 1e-15
+    mk = needed_mask(m)
+    assert _rel(got[:, :, mk], f[:, :, mk]) <= 1e-15
 
 
 @pytest.mark.parametrize("fused", [False, True])
@@ -115,7 +127,8 @@ def test_advection_16_patches_100_steps(fused):
 
 def _sw_adaptive_oracle(trees, pl, m, lmin, lmax, nsteps, regrid_every,
                         fn, thr=0.1, dt0=None):
-    """Oracle reference run: initial mesh loop, CFL-controlled dt, regrid."""
+    """Oracle reference run: initial mesh loop, CFL-controlled dt with the
+    reject-and-redo rule, regrid every `regrid_every` attempts."""
     par = O.params(m, O.SHALLOW)
     lv = O.sfc_sort(I.uniform_leaves(len(trees), lmin))
     for _ in range(lmax - lmin + 1):
@@ -128,7 +141,7 @@ def _sw_adaptive_oracle(trees, pl, m, lmin, lmax, nsteps, regrid_every,
         lv = lv2
     mesh = O.Mesh(trees, lv, m)
     q = I.state_from(lv, m, fn, pl)
-    hist = {"leaves": [lv.copy()], "tags": [], "dt": [], "nu": []}
+    hist = {"leaves": [lv.copy()], "tags": [], "dt": [], "nu": [], "ok": []}
     dt = dt0
     for n in range(nsteps):
         if n > 0 and n % regrid_every == 0:
@@ -141,10 +154,10 @@ def _sw_adaptive_oracle(trees, pl, m, lmin, lmax, nsteps, regrid_every,
             q = O.interior(O.transfer(mesh, mesh2, par, f), m)
             mesh = mesh2
             hist["leaves"].append(lv.copy())
-        q, nu = O.advance(mesh, par, q, dt)
         hist["dt"].append(dt)
+        q, nu, dt, ok = oracle_attempt(mesh, par, q, dt)
         hist["nu"].append(nu)
-        dt = dt * 0.9 / nu
+        hist["ok"].append(ok)
     return lv, q, hist, mesh
 
 
@@ -294,7 +307,9 @@ def test_advance_equals_the_three_calls(precision, m):
     lv = fcx.balance(trees, I.random_leaves(21, 1, 2, 5, 40))
     assert _two_way_coarse_corners(lv) > 0
     q0 = smooth_sw_state(lv, m, pl, 5)
-    cfg = fcx.config(m, precision, fcx.FCX_SHALLOW)
+    # the last step's Courant number exceeds cfl_max: with the redo rule off
+    # it is kept and flagged, as by the separate calls
+    cfg = fcx.config(m, precision, fcx.FCX_SHALLOW, redo=0)
     dtype = torch.float64 if precision == 64 else torch.float32
     dt0 = 0.3 / (m << 5)
     results = []
@@ -363,6 +378,8 @@ def test_native_run_loop_equals_single_calls(fused):
             ctx.ghost_fill(q, g)
             ctx.patch_step(q, g, qn, dt, nu)
             ctx.reflux(q, qn, dt)
+            if nu.item() > cfg.cfl_max:          # the redo rule, on the host
+                qn = q
             ctx.next_dt(nu, dt, st)
         q = qn
     want, want_lv, want_dt = q.cpu().numpy(), ctx.leaves(), dt.item()
@@ -396,13 +413,15 @@ def test_conservation_sums_match_oracle():
         np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-15 * np.abs(want).max())
 
 
+@pytest.mark.parametrize("m", [8, 16, 32])
 @pytest.mark.parametrize("fused", [False, True])
-def test_fp32_within_1e5_of_fp64_oracle(fused):
+def test_fp32_within_1e5_of_fp64_oracle(fused, m):
     """FP32 state and fluxes (FP64 dt, CFL and sums) against the FP64 oracle
-    on the same mesh and dt schedule."""
-    say(f"[fp32] fused={fused}")
+    on the same mesh and dt schedule: one 8x8 tile per patch (m = 8), one
+    16x16 tile (m = 16) and four (m = 32)."""
+    say(f"[fp32] fused={fused} m={m}")
     trees, pl = I.walled_square()
-    m, lmin, lmax = 16, 2, 4
+    lmin, lmax = 2, 4
     fn = lambda x, y: I.dam_break(x, y)
     dt0 = 0.5 / (m << lmax) / 1.8
     lv_o, q_o, hist, _ = _sw_adaptive_oracle(trees, pl, m, lmin, lmax, 12, 4, fn,
@@ -416,7 +435,8 @@ def test_fp32_within_1e5_of_fp64_oracle(fused):
             gpu.regrid(hist["tags"][r], lmin, lmax)
             r += 1
             assert np.array_equal(gpu.ctx.leaves(), hist["leaves"][r])
-        gpu.step(hist["dt"][n], fused=fused)
+        if hist["ok"][n]:                    # attempts the oracle kept
+            gpu.step(hist["dt"][n], fused=fused)
     got = gpu.state()
     for k in range(3):
         err = np.sum(np.abs(got[:, k] - q_o[:, k])) / np.sum(np.abs(q_o[:, k]))

@@ -312,3 +312,39 @@ def test_radial_dam_break_symmetry():
               np.max(np.abs(h - h[:, ::-1])), np.max(np.abs(hu - hv.T)),
               np.max(np.abs(hu + hu[:, ::-1])), np.max(np.abs(hv + hv[::-1, :])))
     assert err <= 1e-10
+
+
+@pytest.mark.parametrize("sphere", [False, True])
+def test_threads_do_not_change_results(sphere):
+    """The ghost fill and the step's patch loop split whole patches over
+    threads (for the CPU baseline's all-core timing): with 1 and with 4
+    threads every value, nu_max and the nesting depth are bit for bit the
+    same, on an adaptive forest with coarse-fine faces and reflux."""
+    from paper_1308_1472_amd import fcx
+    if sphere:
+        trees = I.cubed_sphere()
+        lv = fcx.balance(trees, I.random_leaves(5, 6, 1, 3, 10))
+        m = 8
+        q = I.sphere_bump(lv, m)
+        par = O.params(m, O.SPHERE)
+    else:
+        trees, pl = I.walled_square()
+        lv = O.balance(trees, I.random_leaves(5, 1, 2, 5, 40))
+        m = 8
+        q = I.state_from(lv, m, lambda x, y: I.dam_break(x, y), pl)
+        par = O.params(m, O.SHALLOW)
+    mesh = O.Mesh(trees, lv, m, sphere=sphere)
+    out = []
+    try:
+        for t in (1, 4):
+            O.set_threads(t)
+            f = O.framed(q, m)
+            depth = O.ghost_fill(mesh, par, f)
+            fn, nu = O.step(mesh, par, f, 1e-3, True)
+            out.append((f, fn, nu, depth))
+    finally:
+        O.set_threads(1)
+    (f1, n1, nu1, d1), (f4, n4, nu4, d4) = out
+    assert np.array_equal(f1, f4, equal_nan=True)
+    assert np.array_equal(n1, n4, equal_nan=True)
+    assert nu1 == nu4 and d1 == d4
