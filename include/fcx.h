@@ -237,6 +237,19 @@ int fcx_run(fcx_ctx *ctx, int32_t fused, void *q0, void *q1, int64_t cap,
 int fcx_conservation_sums(fcx_ctx *ctx, const void *q, double *sums,
                           void *stream);
 
+/* fcx_conservation_sums for callers that cannot allocate (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same kernels and the same result bit for bit, but the per-patch
+ * partial sums go to a fixed device array of the library (1048576 doubles,
+ * 8 MiB, on every device the library runs on, held until the process ends)
+ * instead of the context's buffer, and the call allocates nothing.
+ * FCX_EINVAL if patches x components exceeds 1048576.  Every call on one
+ * device shares that array: calls that overlap on one device (different
+ * streams, or host threads) race; order them on one stream.  Nothing in the
+ * array needs clearing between calls. */
+int fcx_conservation_sums_noalloc(fcx_ctx *ctx, const void *q, double *sums,
+                                  void *stream);
+
 /* ---- regrid (Sec. 2: per-patch flags are the only mesher input) ----- */
 
 /* tags (device int8, one per patch): +1 if the criterion exceeds the

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -140,6 +141,7 @@ struct fcx_ctx {
   HostBuf run_host;                // fcx_run: pinned copies of stats
   HostBuf staging;
   int cus = 256;
+  int device = 0;                  // the HIP device the context was created on
   size_t lds_per_block = 65536;    // device limit of LDS per workgroup
   Plan plan;                       // host copy of the current forest's plan
   Plan spare;                      // the previous one, its storage reused
@@ -191,6 +193,36 @@ static bool cube_connectivity(const std::vector<fcx_tree>& t) {
           if (a[e][c] != b[o ? 1 - e : e][c]) return false;
     }
   return true;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free conservation sums: the per-patch FP64
+// partials of fcx_conservation_sums_noalloc live in this file-scope device
+// array (8 MiB on every device the library runs on, held until the process
+// ends).  Host code never passes the array's name to a kernel: each device's
+// copy has its own address, resolved once per device (at fcx_create, with
+// that device current) and kept in g_scratch.
+constexpr int64_t kNoAllocPartials = int64_t(1) << 20;
+static __device__ __align__(256) double scratch[kNoAllocPartials];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static double* g_scratch[kMaxDevices] = {};
+
+static int resolve_scratch(int dev) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FCX_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch[dev]) return FCX_OK;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    return fail(FCX_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch[dev] = static_cast<double*>(ptr);
+  return FCX_OK;
+}
+
+static double* scratch_of(int dev) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return (dev >= 0 && dev < kMaxDevices) ? g_scratch[dev] : nullptr;
 }
 
 // The entry points below are declared extern "C" in fcx.h.
@@ -294,6 +326,14 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
         hipGetDeviceProperties(&prop, dev) == hipSuccess) {
       c->cus = prop.multiProcessorCount;
       c->lds_per_block = prop.sharedMemPerBlock;
+    }
+    c->device = dev;
+  }
+  {
+    const int rc = resolve_scratch(c->device);
+    if (rc != FCX_OK) {
+      delete c;
+      return rc;
     }
   }
   c->trees = t;
@@ -769,40 +809,59 @@ int fcx_step_stats(const fcx_ctx* c, int64_t* out) {
 }
 
 template <typename R, int MEQN>
-static int launch_sums(fcx_ctx* c, const void* q, double* sums, hipStream_t s) {
+static int launch_sums(fcx_ctx* c, const void* q, double* sums, hipStream_t s,
+                       double* partial) {
   hipLaunchKernelGGL((k_sums_patch<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
-                     0, s, static_cast<const R*>(q), c->cur.rec, c->cfg.m,
-                     c->partial.p);
+                     0, s, static_cast<const R*>(q), c->cur.rec, c->cfg.m, partial);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((k_sums_reduce<MEQN>), dim3(1), dim3(1024), 0, s,
-                     c->partial.p, c->cur.first, sums);
+                     partial, c->cur.first, sums);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
 
-int fcx_conservation_sums(fcx_ctx* c, const void* q, double* sums, void* stream) {
-  if (!c || !q || !sums) return fail(FCX_EINVAL, "bad arguments");
-  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
-  hipStream_t s = static_cast<hipStream_t>(stream);
+// Per-patch partials (P * meqn doubles) into `partial`, then the fixed-order
+// reduction.
+static int sums_with(fcx_ctx* c, const void* q, double* sums, hipStream_t s,
+                     double* partial) {
   const bool dp = c->cfg.precision == 64;
   if (c->cfg.physics == FCX_SPHERE) {
     if (dp)
       hipLaunchKernelGGL((k_sphere_sums_patch<double>), dim3(unsigned(c->cur.P)), dim3(256),
                          0, s, static_cast<const double*>(q), c->cur.rec, c->cur.geo.p,
-                         c->cfg.m, c->partial.p);
+                         c->cfg.m, partial);
     else
       hipLaunchKernelGGL((k_sphere_sums_patch<float>), dim3(unsigned(c->cur.P)), dim3(256),
                          0, s, static_cast<const float*>(q), c->cur.rec, c->cur.geo.p,
-                         c->cfg.m, c->partial.p);
+                         c->cfg.m, partial);
     HIPCHK(hipGetLastError());
-    hipLaunchKernelGGL((k_sums_reduce<4>), dim3(1), dim3(1024), 0, s, c->partial.p,
+    hipLaunchKernelGGL((k_sums_reduce<4>), dim3(1), dim3(1024), 0, s, partial,
                        c->cur.first, sums);
     HIPCHK(hipGetLastError());
     return FCX_OK;
   }
   if (c->meqn == 1)
-    return dp ? launch_sums<double, 1>(c, q, sums, s) : launch_sums<float, 1>(c, q, sums, s);
-  return dp ? launch_sums<double, 3>(c, q, sums, s) : launch_sums<float, 3>(c, q, sums, s);
+    return dp ? launch_sums<double, 1>(c, q, sums, s, partial)
+              : launch_sums<float, 1>(c, q, sums, s, partial);
+  return dp ? launch_sums<double, 3>(c, q, sums, s, partial)
+            : launch_sums<float, 3>(c, q, sums, s, partial);
+}
+
+int fcx_conservation_sums(fcx_ctx* c, const void* q, double* sums, void* stream) {
+  if (!c || !q || !sums) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  return sums_with(c, q, sums, static_cast<hipStream_t>(stream), c->partial.p);
+}
+
+int fcx_conservation_sums_noalloc(fcx_ctx* c, const void* q, double* sums, void* stream) {
+  if (!c || !q || !sums) return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cur.P * c->meqn > kNoAllocPartials)
+    return fail(FCX_EINVAL, "fcx_conservation_sums_noalloc: patches x components exceeds "
+                            "its scratch of 1048576 partial sums");
+  double* part = scratch_of(c->device);
+  if (!part) return fail(FCX_ESTATE, "scratch of this device not resolved");
+  return sums_with(c, q, sums, static_cast<hipStream_t>(stream), part);
 }
 
 template <typename R, int MEQN>

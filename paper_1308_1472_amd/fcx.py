@@ -40,7 +40,7 @@ EXPORTS = [
     "fcx_batch_replay", "fcx_batch_sums", "fcx_features", "fcx_mlp_forward",
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
     "fcx_sphere_geometry", "fcx_advance", "fcx_regrid", "fcx_run",
-    "fcx_step_stats", "fcx_batch_step_stats",
+    "fcx_step_stats", "fcx_batch_step_stats", "fcx_conservation_sums_noalloc",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -122,6 +122,7 @@ def lib():
         L.fcx_advance.argtypes = [vp, vp, vp, vp, vp, vp, vp]
         L.fcx_regrid.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp, vp]
         L.fcx_step_stats.argtypes = [vp, vp]
+        L.fcx_conservation_sums_noalloc.argtypes = [vp, vp, vp, vp]
         L.fcx_batch_step_stats.argtypes = [vp, vp]
         L.fcx_run.argtypes = [vp, i32, vp, vp, i64, vp, i64, i32, i32, i32, i32, dp, i32,
                               i32, vp, vp, vp, vp, vp, vp]
@@ -370,6 +371,13 @@ class Context:
         _check(lib().fcx_conservation_sums(self.h, self._q(q),
                                            self._d(sums, self.meqn),
                                            _stream(stream)))
+
+    def conservation_sums_noalloc(self, q, sums, stream=None):
+        """As conservation_sums, with the library's fixed scratch array (the
+        call allocates nothing)."""
+        _check(lib().fcx_conservation_sums_noalloc(self.h, self._q(q),
+                                                   self._d(sums, self.meqn),
+                                                   _stream(stream)))
 
     # ---- regrid -------------------------------------------------------
     def regrid_tags(self, q, ghost, criterion, threshold, lmin, lmax, tags,
