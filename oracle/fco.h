@@ -83,6 +83,18 @@ int  fco_ghost_fill(const fco_mesh *mesh, const fco_params *par, double *q,
                     int32_t *max_depth);
 int  fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
               double *qn, double dt, int32_t reflux, double *numax);
+/* Ghost fill of the level-`level` patches only, at a time inside the
+ * current steps of the coarser levels: a coarser leaf's interior value is
+ * (1 - alpha[l]) qold + alpha[l] q (alpha indexed by that leaf's level). */
+int  fco_ghost_fill_level(const fco_mesh *mesh, const fco_params *par, double *q,
+                          const double *qold, const double *alpha, int32_t level);
+/* One sub-cycled step of the coarsest level present (planar forests):
+ * level l steps with dt 2^-l (dt: the step of a level-0 patch), 2^(l - lmin)
+ * times, coarse to fine with the finer levels' corrections carried back; q
+ * framed in (ghosts ignored), qn framed out (interiors); *numax the largest
+ * Courant number of all the steps. */
+int  fco_step_subcycled(const fco_mesh *mesh, const fco_params *par, const double *q,
+                        double *qn, double dt, double *numax);
 int  fco_sums(const fco_mesh *mesh, const fco_params *par, const double *q,
               double *sums);
 

@@ -44,6 +44,13 @@ typedef struct {
   const double *q;
   int32_t depth_max;
   int32_t error;
+  /* sub-cycling (NULL qold: the state q alone): a leaf coarser than
+   * fill_level contributes (1 - alpha[l]) qold + alpha[l] q, its state
+   * interpolated linearly in time between the start and the end of its
+   * current step */
+  const double *qold;
+  const double *alpha;
+  int32_t fill_level;
 } gctx;
 
 static double minmod(double a, double b) {
@@ -59,6 +66,15 @@ static void interior(const gctx *g, int64_t p, int32_t i, int32_t j,
                      double *out) {
   const int32_t m = g->mesh->m, meqn = g->par->meqn;
   const int64_t F = fco_frame(m);
+  const int32_t lev = g->mesh->leaves[p].level;
+  if (g->qold && lev < g->fill_level) {
+    const double a = g->alpha[lev];
+    for (int k = 0; k < meqn; ++k) {
+      const int64_t o = (p * meqn + k) * F + fco_fidx(m, i, j);
+      out[k] = (1.0 - a) * g->qold[o] + a * g->q[o];
+    }
+    return;
+  }
   for (int k = 0; k < meqn; ++k)
     out[k] = g->q[(p * meqn + k) * F + fco_fidx(m, i, j)];
 }
@@ -182,7 +198,7 @@ int fco_ghost_fill(const fco_mesh *mesh, const fco_params *par, double *q,
    * can be filled in any order (fco_set_threads: whole patches per thread) */
 #pragma omp parallel num_threads(fco_threads()) reduction(max : depth) reduction(| : error)
   {
-    gctx g = {mesh, par, q, 0, 0};
+    gctx g = {mesh, par, q, 0, 0, NULL, NULL, 0};
     double v[FCO_MAXEQ];
 #pragma omp for schedule(dynamic, 16)
     for (int64_t p = 0; p < mesh->n; ++p)
@@ -203,6 +219,36 @@ int fco_ghost_fill(const fco_mesh *mesh, const fco_params *par, double *q,
   return error ? -2 : 0;
 }
 
+int fco_ghost_fill_level(const fco_mesh *mesh, const fco_params *par, double *q,
+                         const double *qold, const double *alpha, int32_t level) {
+  if (!mesh || !par || !q || !qold || !alpha || par->meqn < 1 ||
+      par->meqn > FCO_MAXEQ || par->m != mesh->m)
+    return -1;
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const int64_t F = fco_frame(m);
+  int32_t error = 0;
+#pragma omp parallel num_threads(fco_threads()) reduction(| : error)
+  {
+    gctx g = {mesh, par, q, 0, 0, qold, alpha, level};
+    double v[FCO_MAXEQ];
+#pragma omp for schedule(dynamic, 16)
+    for (int64_t p = 0; p < mesh->n; ++p) {
+      if (mesh->leaves[p].level != level) continue;
+      for (int32_t j = -1; j <= m + 2; ++j)
+        for (int32_t i = -1; i <= m + 2; ++i) {
+          int gi = (i < 1 || i > m), gj = (j < 1 || j > m);
+          if (!gi && !gj) continue;
+          if ((i == -1 || i == m + 2) && (j == -1 || j == m + 2)) continue;
+          fco_frame_value(&g, p, i, j, v, 0);
+          for (int k = 0; k < meqn; ++k)
+            q[(p * meqn + k) * F + fco_fidx(m, i, j)] = v[k];
+        }
+    }
+    error |= g.error;
+  }
+  return error ? -2 : 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* Regrid transfer (Sec. 3: interpolate coarse data to newly created   */
 /* fine patches, average fine data to a newly created coarse patch).   */
@@ -213,7 +259,7 @@ int fco_transfer(const fco_mesh *old_mesh, const fco_mesh *new_mesh,
   if (!old_mesh || !new_mesh || old_mesh->m != new_mesh->m) return -1;
   const int32_t m = new_mesh->m, meqn = par->meqn;
   const int64_t F = fco_frame(m);
-  gctx g = {old_mesh, par, q_old, 0, 0};
+  gctx g = {old_mesh, par, q_old, 0, 0, NULL, NULL, 0};
   double v[FCO_MAXEQ];
   for (int64_t p = 0; p < new_mesh->n; ++p) {
     const fco_leaf *a = &new_mesh->leaves[p];

@@ -536,6 +536,266 @@ int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
   return rc;
 }
 
+/* ---------------- sub-cycled step -------------------------------------- */
+/* Per-level time steps (Sec. 4: one exchange per level and time step, the
+ * levels visited from coarse to fine and correction factors carried back
+ * from fine to coarse; Sec. 3: time-accurate coarse data fill the ghost
+ * cells of finer patches), in the recursive form of the block-structured
+ * AMR codes the paper cites (Berger and Oliger 1984; flux correction of
+ * Berger and Colella 1989).  Level l steps with dt_l = dt 2^-l (dt is the
+ * step of a level-0 patch, so every level runs at the same Courant number):
+ * one step of the coarsest level lmin takes 2^(l - lmin) steps at level l:
+ *
+ *   advance(l, t):  keep the level-l states at time t (old); fill the
+ *     level-l ghost cells at time t (a coarser leaf, which is inside its own
+ *     step, gives (1 - a) old + a new with a its fraction of that step);
+ *     step the level-l patches by dt_l; add this substep's fine-side terms
+ *     to the accumulators psi of their faces that border level l - 1;
+ *     then advance(l + 1, t), advance(l + 1, t + dt_l / 2) and correct the
+ *     level-l cells at faces with level-(l + 1) patches.
+ *
+ * Fine-side term of a substep at one fine face cell, w = dt_l / dt_{l-1}
+ * = 1/2:   w [ dx_f (f(q_f) - f(q_c)) - phi_f ]   with q_f the fine cell at
+ * the substep's start and q_c the coarse cell at the start of the coarse
+ * level's step (f(q_f) - f(q_c) as the sum of the pair's fluctuations,
+ * Roe's property).  The coarse cell then takes
+ *   -dt_{l-1} / dx_c^2 (psi of its two fine cells - phi_c),
+ * which with a single substep (w = 1) is the reflux of the global-dt step.
+ * Planar forests only. */
+
+/* The fine cell across position t (1..m) of face f of patch p, half k2: its
+ * leaf L, cell (fi, fj), face ff towards p and position ft along that face.
+ * Returns 1 if the leaf across is one level finer, 0 if not, < 0 on error. */
+static int cf_pair(const fco_mesh *mesh, int64_t p, int f, int32_t t, int k2,
+                   int64_t *L, int32_t *fi, int32_t *fj, int *ff, int32_t *ft) {
+  const int32_t m = mesh->m;
+  const int d = f / 2, hi = f % 2;
+  const fco_leaf *a = &mesh->leaves[p];
+  const int64_t size = FCO_SIDE >> a->level, cs = size / m;
+  const int64_t x0 = (int64_t)a->ix * size, y0 = (int64_t)a->iy * size;
+  int64_t nrm_out = hi ? size + cs / 4 : -cs / 4;
+  int64_t nrm_in = hi ? size + cs / 8 : -cs / 8;
+  int64_t tan = (int64_t)(t - 1) * cs + (k2 == 0 ? cs / 4 : 3 * cs / 4);
+  int64_t xa, ya, xb, yb;
+  if (d == 0) { xa = x0 + nrm_out; ya = y0 + tan; xb = x0 + nrm_in; yb = ya; }
+  else { xa = x0 + tan; ya = y0 + nrm_out; xb = xa; yb = y0 + nrm_in; }
+  int64_t L2, X, Y, X2, Y2;
+  int32_t fi2, fj2, tt, tt2;
+  if (fine_cell(mesh, a->tree, xa, ya, L, fi, fj, &tt, &X, &Y) != 0 ||
+      fine_cell(mesh, a->tree, xb, yb, &L2, &fi2, &fj2, &tt2, &X2, &Y2) != 0)
+    return -5;
+  if (mesh->leaves[*L].level != a->level + 1) return 0;
+  if (X2 != X) *ff = X2 > X ? 1 : 0;
+  else *ff = Y2 > Y ? 3 : 2;
+  *ft = (*ff < 2) ? *fj : *fi;
+  return 1;
+}
+
+typedef struct {
+  const fco_mesh *mesh;
+  const fco_params *par;
+  int32_t lmin, lmax;
+  double *cur, *old, *tmp;            /* framed states per patch */
+  double *phi, *psi;                  /* [P][4][m][meqn] face terms */
+  double t_old[FCO_S + 1], dtl[FCO_S + 1];
+  work wk;
+  double numax;
+} subcycle;
+
+/* psi of level-lf patches += w [dx_f (f(q_f) - f(q_c)) - phi_f] at their
+ * faces with level lf - 1 (q_f, q_c: states at the starts of the steps) */
+static int accumulate_fine(subcycle *S, int32_t lf, double w) {
+  const fco_mesh *mesh = S->mesh;
+  const fco_params *par = S->par;
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const int64_t FR = fco_frame(m);
+  double W[MW * FCO_MAXEQ], Sp[MW], am[FCO_MAXEQ], ap[FCO_MAXEQ];
+  double ql[FCO_MAXEQ], qr[FCO_MAXEQ];
+  for (int f = 0; f < 4; ++f) {
+    const int d = f / 2, hi = f % 2;
+    for (int64_t p = 0; p < mesh->n; ++p) {
+      if (mesh->leaves[p].level != lf - 1 || fco_wall_face(mesh, p, f)) continue;
+      const double dx = ldexp(1.0, -mesh->leaves[p].level) / m;
+      for (int32_t t = 1; t <= m; ++t) {
+        const int32_t ic = d == 0 ? (hi ? m : 1) : t;
+        const int32_t jc = d == 0 ? t : (hi ? m : 1);
+        for (int k2 = 0; k2 < 2; ++k2) {
+          int64_t L;
+          int32_t fi, fj, ft;
+          int ff;
+          const int r = cf_pair(mesh, p, f, t, k2, &L, &fi, &fj, &ff, &ft);
+          if (r < 0) return r;
+          if (r == 0) break;
+          for (int k = 0; k < meqn; ++k) {
+            const double qc = S->old[(p * meqn + k) * FR + fco_fidx(m, ic, jc)];
+            const double qf = S->old[(L * meqn + k) * FR + fco_fidx(m, fi, fj)];
+            ql[k] = hi ? qc : qf;
+            qr[k] = hi ? qf : qc;
+          }
+          edge_geom eg = {1.0, {0}, {0}};
+          if (riemann(par, d, &eg, ql, qr, W, Sp, am, ap, NULL) < 0) return -4;
+          double *ps = &S->psi[((L * 4 + ff) * m + (ft - 1)) * meqn];
+          const double *pf = &S->phi[((L * 4 + ff) * m + (ft - 1)) * meqn];
+          for (int k = 0; k < meqn; ++k)
+            ps[k] += w * (0.5 * dx * (am[k] + ap[k]) - pf[k]);
+        }
+      }
+    }
+  }
+  return 0;
+}
+
+/* level-lc cells at faces with level lc + 1: -dt / dx^2 (psi - phi_c),
+ * xi faces first, then eta faces */
+static int correct_coarse(subcycle *S, int32_t lc) {
+  const fco_mesh *mesh = S->mesh;
+  const int32_t m = mesh->m, meqn = S->par->meqn;
+  const int64_t FR = fco_frame(m);
+  const double dt = S->dtl[lc];
+  for (int f = 0; f < 4; ++f) {
+    const int d = f / 2, hi = f % 2;
+    for (int64_t p = 0; p < mesh->n; ++p) {
+      if (mesh->leaves[p].level != lc || fco_wall_face(mesh, p, f)) continue;
+      const double dx = ldexp(1.0, -lc) / m;
+      for (int32_t t = 1; t <= m; ++t) {
+        const int32_t ic = d == 0 ? (hi ? m : 1) : t;
+        const int32_t jc = d == 0 ? t : (hi ? m : 1);
+        double corr[FCO_MAXEQ] = {0};
+        int fine = 1;
+        for (int k2 = 0; k2 < 2 && fine; ++k2) {
+          int64_t L;
+          int32_t fi, fj, ft;
+          int ff;
+          const int r = cf_pair(mesh, p, f, t, k2, &L, &fi, &fj, &ff, &ft);
+          if (r < 0) return r;
+          if (r == 0) { fine = 0; break; }
+          const double *ps = &S->psi[((L * 4 + ff) * m + (ft - 1)) * meqn];
+          for (int k = 0; k < meqn; ++k) corr[k] += ps[k];
+        }
+        if (!fine) continue;
+        const double *phic = &S->phi[((p * 4 + f) * m + (t - 1)) * meqn];
+        for (int k = 0; k < meqn; ++k)
+          S->cur[(p * meqn + k) * FR + fco_fidx(m, ic, jc)] -=
+              dt / (dx * dx) * (corr[k] - phic[k]);
+      }
+    }
+  }
+  return 0;
+}
+
+static int advance_level(subcycle *S, int32_t l, double t) {
+  const fco_mesh *mesh = S->mesh;
+  const fco_params *par = S->par;
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const int64_t FR = fco_frame(m), PS = (int64_t)meqn * FR;
+  const double dt = S->dtl[l];
+  /* the level-l states at time t */
+  for (int64_t p = 0; p < mesh->n; ++p)
+    if (mesh->leaves[p].level == l)
+      memcpy(&S->old[p * PS], &S->cur[p * PS], sizeof(double) * PS);
+  S->t_old[l] = t;
+  /* ghost cells of level l at time t */
+  double alpha[FCO_S + 1];
+  for (int32_t lv = 0; lv <= FCO_S; ++lv)
+    alpha[lv] = lv < l && lv >= S->lmin ? (t - S->t_old[lv]) / S->dtl[lv] : 0.0;
+  int rc = fco_ghost_fill_level(mesh, par, S->cur, S->old, alpha, l);
+  if (rc != 0) return rc;
+  /* the level-l patches, then their new interiors */
+  for (int64_t p = 0; p < mesh->n; ++p) {
+    if (mesh->leaves[p].level != l) continue;
+    double nu = 0.0;
+    rc = step_patch(mesh, par, p, &S->cur[p * PS], &S->tmp[p * PS], dt, &S->wk,
+                    &S->phi[p * 4 * m * meqn], &nu);
+    if (rc != 0) return rc;
+    S->numax = fmax(S->numax, nu);
+  }
+  for (int64_t p = 0; p < mesh->n; ++p) {
+    if (mesh->leaves[p].level != l) continue;
+    for (int k = 0; k < meqn; ++k)
+      for (int32_t j = 1; j <= m; ++j)
+        for (int32_t i = 1; i <= m; ++i) {
+          const int64_t o = p * PS + k * FR + fco_fidx(m, i, j);
+          S->cur[o] = S->tmp[o];
+        }
+  }
+  /* this substep's terms at faces with the next coarser level */
+  if (l > S->lmin) {
+    rc = accumulate_fine(S, l, dt / S->dtl[l - 1]);
+    if (rc != 0) return rc;
+  }
+  if (l < S->lmax) {
+    for (int64_t p = 0; p < mesh->n; ++p)
+      if (mesh->leaves[p].level == l + 1)
+        memset(&S->psi[p * 4 * m * meqn], 0, sizeof(double) * 4 * m * meqn);
+    rc = advance_level(S, l + 1, t);
+    if (rc == 0) rc = advance_level(S, l + 1, t + 0.5 * dt);
+    if (rc == 0) rc = correct_coarse(S, l);
+    if (rc != 0) return rc;
+  }
+  return 0;
+}
+
+int fco_step_subcycled(const fco_mesh *mesh, const fco_params *par, const double *q,
+                       double *qn, double dt, double *numax) {
+  if (!mesh || !par || !q || !qn || par->m != mesh->m || par->meqn < 1 ||
+      par->meqn > FCO_MAXEQ || mesh->sphere || par->physics == FCO_SPHERE)
+    return -1;
+  const int32_t m = mesh->m, meqn = par->meqn;
+  const int64_t NE = (int64_t)(m + 3) * (m + 2), FR = fco_frame(m);
+  const int64_t PS = (int64_t)meqn * FR, n = mesh->n;
+  subcycle S;
+  memset(&S, 0, sizeof S);
+  S.mesh = mesh;
+  S.par = par;
+  S.lmin = FCO_S;
+  S.lmax = 0;
+  for (int64_t p = 0; p < n; ++p) {
+    const int32_t l = mesh->leaves[p].level;
+    if (l < S.lmin) S.lmin = l;
+    if (l > S.lmax) S.lmax = l;
+  }
+  for (int32_t l = S.lmin; l <= S.lmax; ++l) S.dtl[l] = ldexp(dt, -l);
+  S.cur = (double *)malloc(sizeof(double) * n * PS);
+  S.old = (double *)malloc(sizeof(double) * n * PS);
+  S.tmp = (double *)malloc(sizeof(double) * n * PS);
+  S.phi = (double *)calloc((size_t)n * 4 * m * meqn, sizeof(double));
+  S.psi = (double *)calloc((size_t)n * 4 * m * meqn, sizeof(double));
+  S.wk.m = m;
+  S.wk.meqn = meqn;
+  for (int d = 0; d < 2; ++d) {
+    S.wk.F[d] = (double *)malloc(sizeof(double) * NE * meqn);
+    S.wk.AM[d] = (double *)malloc(sizeof(double) * NE * meqn);
+    S.wk.AP[d] = (double *)malloc(sizeof(double) * NE * meqn);
+    S.wk.FL[d] = (double *)calloc(NE, sizeof(double));
+  }
+  S.wk.W = (double *)malloc(sizeof(double) * (m + 3) * MW * meqn);
+  S.wk.S = (double *)malloc(sizeof(double) * (m + 3) * MW);
+  S.wk.kap = (double *)malloc(sizeof(double) * FR);
+  S.wk.eg = (edge_geom *)malloc(sizeof(edge_geom) * (m + 3));
+  S.wk.tg = NULL;
+  memcpy(S.cur, q, sizeof(double) * n * PS);
+  memcpy(S.tmp, q, sizeof(double) * n * PS);
+  const int rc = advance_level(&S, S.lmin, 0.0);
+  if (rc == 0) memcpy(qn, S.cur, sizeof(double) * n * PS);
+  if (numax) *numax = S.numax;
+  for (int d = 0; d < 2; ++d) {
+    free(S.wk.F[d]);
+    free(S.wk.AM[d]);
+    free(S.wk.AP[d]);
+    free(S.wk.FL[d]);
+  }
+  free(S.wk.W);
+  free(S.wk.S);
+  free(S.wk.kap);
+  free(S.wk.eg);
+  free(S.cur);
+  free(S.old);
+  free(S.tmp);
+  free(S.phi);
+  free(S.psi);
+  return rc;
+}
+
 /* ---------------- conservation sums ---------------------------------- */
 /* M_k = sum over interior cells of kappa Q_k dxi deta, with Neumaier's
  * compensated summation. */

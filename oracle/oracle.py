@@ -85,6 +85,8 @@ def lib():
         L.fco_sphere_edge.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
         L.fco_sphere_centre.argtypes = [vp, i64, i32, i32, vp]
         L.fco_rp_sphere.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fco_step_subcycled.argtypes = [vp, vp, vp, vp, dp, vp]
+        L.fco_ghost_fill_level.argtypes = [vp, vp, vp, vp, vp, i32]
         L.fco_set_threads.argtypes = [i32]
         L.fco_threads.restype = i32
         _lib = L
@@ -194,6 +196,20 @@ def step(mesh: Mesh, par: Params, qf: np.ndarray, dt: float, reflux=True):
     return qn, numax.value
 
 
+def step_subcycled(mesh: Mesh, par: Params, qf: np.ndarray, dt: float):
+    """One sub-cycled step of the coarsest level (level l steps with
+    dt 2^-l, dt the step of a level-0 patch) from a framed state (ghosts
+    are filled inside); returns (new frame, largest Courant number)."""
+    assert qf.dtype == np.float64 and qf.flags.c_contiguous
+    qn = np.array(qf, copy=True)
+    numax = C.c_double()
+    rc = lib().fco_step_subcycled(mesh.h, C.byref(par), _ptr(qf), _ptr(qn), dt,
+                                  C.byref(numax))
+    if rc != 0:
+        raise RuntimeError(f"fco_step_subcycled failed ({rc})")
+    return qn, numax.value
+
+
 def sums(mesh: Mesh, par: Params, qf: np.ndarray) -> np.ndarray:
     out = np.zeros(par.meqn)
     lib().fco_sums(mesh.h, C.byref(par), _ptr(qf), _ptr(out))
@@ -278,6 +294,13 @@ def advance(mesh, par, q, dt, reflux=True):
     f = framed(q, mesh.m)
     ghost_fill(mesh, par, f)
     fn, nu = step(mesh, par, f, dt, reflux)
+    return interior(fn, mesh.m), nu
+
+
+def advance_subcycled(mesh, par, q, dt):
+    """q: interior -> (interior after one sub-cycled step of the coarsest
+    level, level l stepping with dt 2^-l; nu_max over all its steps)."""
+    fn, nu = step_subcycled(mesh, par, framed(q, mesh.m), dt)
     return interior(fn, mesh.m), nu
 
 
