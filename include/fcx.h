@@ -209,6 +209,26 @@ int fcx_next_dt(fcx_ctx *ctx, double *nu_max, double *dt, int32_t *status,
 int fcx_advance(fcx_ctx *ctx, const void *q, void *q_new, double *dt,
                 double *nu_max, int32_t *status, void *stream);
 
+/* Sub-cycled step (Sec. 4: per-level time steps, coarse to fine, with the
+ * finer levels' correction factors carried back; Sec. 3: time-accurate
+ * coarse data fill the ghost cells of finer patches).  Level l steps with
+ * dt * 2^-l (*dt is the step of a level-0 patch, so all levels run at one
+ * Courant number); one call is one step of the coarsest level present, in
+ * which level l takes 2^(l - lmin) steps.  For each substep of a level: its
+ * ghost cells at the substep's time (a coarser leaf's state interpolated
+ * linearly in time within its own step), its step, and its fine-side face
+ * terms w [dx_f (f(q_f) - f(q_c)) - phi_f], w = 1/2, accumulated at faces
+ * with the next coarser level; after the two substeps of the next finer
+ * level, this level's cells at those faces take -dt_l / dx^2 (sum of the
+ * fine terms - phi_c) (Berger and Colella's flux correction).  Reads q
+ * (never written), writes q_new; `work` (a state of the same size) and
+ * `ghost` are scratch of the caller.  nu_max, dt and status as fcx_advance
+ * (the CFL rule over all the substeps; with cfg.redo a rejected step leaves
+ * q_new = q).  Planar forests; plain launches (no fused gather). */
+int fcx_advance_subcycled(fcx_ctx *ctx, const void *q, void *q_new, void *work,
+                          void *ghost, double *dt, double *nu_max, int32_t *status,
+                          void *stream);
+
 /* Counters of the steps taken on this context since fcx_create, read after
  * the device has finished: out[0] accepted steps, out[1] rejected attempts,
  * out[2] accepted cell updates (interior cells advanced). */
@@ -219,8 +239,10 @@ int fcx_step_stats(const fcx_ctx *ctx, int64_t *out);
  * k first regrids when regrid_every > 0, n > 0 and n % regrid_every == 0
  * (fcx_regrid with the given criterion, then fcx_regrid_transfer into the
  * other buffer, using `ghost` of ghost_cap elements), then advances into
- * the other buffer: fcx_advance if `fused`, else fcx_ghost_fill,
- * fcx_patch_step, fcx_reflux and fcx_next_dt.  The state starts in q0; *which
+ * the other buffer: mode (`fused`) 1: fcx_advance; 0: fcx_ghost_fill,
+ * fcx_patch_step, fcx_reflux and fcx_next_dt; 2: fcx_advance_subcycled
+ * (a step of the coarsest level; *dt is then a level-0 patch's step; the
+ * work buffer is the library's).  The state starts in q0; *which
  * receives the buffer (0 or 1) holding the final state, *cell_updates the
  * number of interior cells advanced.  FCX_ENOMEM if a capacity is short
  * (the state is then where the last completed step left it).  On the

@@ -3,6 +3,7 @@
 // dt, sum, tag and transfer kernels.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <algorithm>
@@ -115,6 +116,8 @@ struct DevForest {
   RefluxAux* aux = nullptr;          // per reflux item: partners, slots, level
   int32_t* counts = nullptr;         // {slots, xi items, eta items} on the device
   int32_t* order = nullptr;          // dispatch order of the step's tiles (null: identity)
+  int32_t* bylevel = nullptr;        // patch ids sorted by level (stable)
+  std::vector<int32_t> level_first;  // host: level l's ids at [first[l], first[l+1])
   int32_t* first = nullptr;          // {0, P} for the sum reduction
   int32_t* xkind = nullptr;          // transfer plan from the previous forest
   int32_t* xsrc = nullptr;
@@ -138,6 +141,12 @@ struct fcx_ctx {
   DevBuf<int32_t> err;
   DevBuf<uint32_t> ticket;         // last-workgroup ticket of the reflux
   DevBuf<int64_t> stats;           // {accepted steps, rejected attempts, accepted cells}
+  DevBuf<uint8_t> psi;             // sub-cycling: fine-side terms per face-term slot
+  DevBuf<double> dtl;              //   dt of every level
+  DevBuf<LevelSrc> tables;         //   per launch of a coarse step: where levels are read
+  int sub_lmin = -1, sub_lmax = -1; //   the level range the tables are for
+  HostBuf sub_host;                //   pinned staging of the tables
+  DevBuf<uint8_t> sub_work;        //   fcx_run: the work buffer of sub-cycled steps
   HostBuf run_host;                // fcx_run: pinned copies of stats
   HostBuf staging;
   int cus = 256;
@@ -399,8 +408,19 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   const bool reorder = c->cfg.physics != FCX_SPHERE && nsimple > 0 && nsimple < P;
   const size_t off_order = at;
   if (reorder) at += align256(P * 4);
+  // patches by level, for the launches of a sub-cycled step
+  const size_t off_bylevel = at;
+  at += align256(P * 4);
   HIPCHK(c->staging.ensure(at));
   uint8_t* h = c->staging.p;
+  {
+    dev.level_first.assign(kLevels + 1, 0);
+    for (const PatchRec& r : plan.recs) dev.level_first[r.level + 1] += 1;
+    for (int l = 0; l < kLevels; ++l) dev.level_first[l + 1] += dev.level_first[l];
+    std::vector<int32_t> fill(dev.level_first.begin(), dev.level_first.end() - 1);
+    int32_t* bl = reinterpret_cast<int32_t*>(h + off_bylevel);
+    for (size_t p = 0; p < P; ++p) bl[fill[plan.recs[p].level]++] = int32_t(p);
+  }
   {
     RefluxItem* items = reinterpret_cast<RefluxItem*>(h + off[3]);
     RefluxAux* aux = reinterpret_cast<RefluxAux*>(h + off[7]);
@@ -474,6 +494,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   dev.aux = reinterpret_cast<RefluxAux*>(d + off[7]);
   dev.counts = reinterpret_cast<int32_t*>(d + off[8]);
   dev.order = reorder ? reinterpret_cast<int32_t*>(d + off_order) : nullptr;
+  dev.bylevel = reinterpret_cast<int32_t*>(d + off_bylevel);
   dev.nslots = plan.nslots;
   dev.P = int64_t(P);
   std::swap(c->plan, c->spare);
@@ -1511,6 +1532,201 @@ int fcx_advance(fcx_ctx* c, const void* q, void* qn, double* dt, double* numax,
             : launch_reflux<float, FCX_SHALLOW, true>(c, q, qn, dt, s, nd);
 }
 
+// ---- sub-cycled step ----------------------------------------------------------
+// One step of the coarsest level with per-level time steps (level l: dt 2^-l),
+// coarse to fine: for each substep of a level, a ghost fill of that level's
+// patches at the substep's time (coarser levels read in the middle of their
+// own steps, interpolated in time), the step of those patches, and the
+// fine-side terms of their faces with the next coarser level; after the two
+// substeps of the next finer level, the correction of this level's cells at
+// faces with it.  Buffers: q (state at the start, never written), q_new
+// (result) and w (work): level lmin steps q -> q_new; a finer level's i-th
+// substep goes q -> w (i = 1), w -> q_new (i even), q_new -> w (i odd > 1),
+// so every level ends in q_new and q stays available for a redo.
+namespace {
+
+struct SubPlan {
+  int lmin, lmax;
+  // the actions of one coarse step, in order: a substep of a level (ghost
+  // fill, step, fine-side terms) or the correction of a level's cells
+  struct Action {
+    int correct;                    // 0: substep of `level`; 1: correct `level`
+    int level, sub, src, dst;       // buffers: 0 q, 1 q_new, 2 w (dst: corrected)
+    int qc_old;                     // coarse level's step-start buffer (psi)
+    int add;                        // psi: accumulate (second fine substep)
+    int table;                      // substeps: index of its level table
+  };
+  std::vector<Action> actions;
+  std::vector<LevelSrc> tables;     // kLevels per substep
+};
+
+struct SubState {
+  int cur[kLevels], old[kLevels];
+  double t0[kLevels];
+};
+
+void sub_recurse(SubPlan& sp, SubState& st, int l, double t, int sub) {
+  const double dtr = std::ldexp(1.0, -(l - sp.lmin));   // in coarse steps
+  const int src = l == sp.lmin ? 0 : (sub == 1 ? 0 : (sub % 2 == 0 ? 2 : 1));
+  const int dst = l == sp.lmin ? 1 : (sub % 2 == 1 ? 2 : 1);
+  // where each level is read at time t
+  const int table = int(sp.tables.size() / kLevels);
+  for (int v = 0; v < kLevels; ++v) {
+    LevelSrc e{st.cur[v], st.cur[v], 0.0};
+    if (v >= sp.lmin && v < l) {
+      const double dv = std::ldexp(1.0, -(v - sp.lmin));
+      e = LevelSrc{st.cur[v], st.old[v], (t - st.t0[v]) / dv};
+    } else if (v == l) {
+      e = LevelSrc{src, src, 0.0};
+    }
+    sp.tables.push_back(e);
+  }
+  sp.actions.push_back(SubPlan::Action{0, l, sub, src, dst, l > sp.lmin ? st.old[l - 1] : -1,
+                                       sub % 2 == 0, table});
+  st.old[l] = src;
+  st.cur[l] = dst;
+  st.t0[l] = t;
+  if (l < sp.lmax) {
+    sub_recurse(sp, st, l + 1, t, 2 * sub - 1);
+    sub_recurse(sp, st, l + 1, t + 0.5 * dtr, 2 * sub);
+    sp.actions.push_back(SubPlan::Action{1, l, sub, -1, st.cur[l], -1, 0, -1});
+  }
+}
+
+}  // namespace
+
+template <typename R, int PHYS, int T, int NT>
+static void launch_step_level(fcx_ctx* c, const R* q, const R* ghost, R* qn, const double* dt,
+                              double* numax, const int32_t* list, int32_t n, hipStream_t s) {
+  StepArgs<R> a;
+  a.q = q;
+  a.ghost = ghost;
+  a.qn = qn;
+  a.dt = dt;
+  a.numax = numax;
+  a.rec = c->cur.rec;
+  a.phislot = c->cur.phislot;
+  a.phi = reinterpret_cast<R*>(c->phi.p);
+  a.err = c->err.p;
+  a.P = int32_t(c->cur.P);
+  a.m = c->cfg.m;
+  a.lm = log2i(c->cfg.m);
+  const int tps = c->cfg.m / T;
+  a.ntiles = n * tps * tps;
+  a.ph = kphys(c);
+  hipLaunchKernelGGL((k_step_level<R, PHYS, T, NT>), dim3(unsigned(a.ntiles)), dim3(NT), 0, s,
+                     a, list);
+}
+
+template <typename R, int PHYS>
+static int subcycled_t(fcx_ctx* c, const void* q, void* qn, void* w, void* ghost, double* dt,
+                       double* numax, int32_t* status, hipStream_t s) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  const int m = c->cfg.m, lm = log2i(m), G = 8 * m + 16;
+  const auto& lf = c->cur.level_first;
+  int lmin = -1, lmax = -1;
+  for (int l = 0; l < kLevels; ++l)
+    if (lf[l + 1] > lf[l]) {
+      if (lmin < 0) lmin = l;
+      lmax = l;
+    }
+  if (lmin < 0) return fail(FCX_ESTATE, "empty forest");
+  SubPlan sp;
+  sp.lmin = lmin;
+  sp.lmax = lmax;
+  SubState st;
+  for (int v = 0; v < kLevels; ++v) { st.cur[v] = 0; st.old[v] = 0; st.t0[v] = 0.0; }
+  sub_recurse(sp, st, lmin, 0.0, 1);
+  // the tables depend on the level range only: upload when it changes
+  if (c->sub_lmin != lmin || c->sub_lmax != lmax) {
+    const size_t bytes = sp.tables.size() * sizeof(LevelSrc);
+    HIPCHK(hipStreamSynchronize(s));          // the pinned copy may be in use
+    HIPCHK(c->sub_host.ensure(bytes));
+    std::memcpy(c->sub_host.p, sp.tables.data(), bytes);
+    HIPCHK(c->tables.ensure(sp.tables.size()));
+    HIPCHK(hipMemcpyAsync(c->tables.p, c->sub_host.p, bytes, hipMemcpyHostToDevice, s));
+    c->sub_lmin = lmin;
+    c->sub_lmax = lmax;
+  }
+  const size_t esz = sizeof(R);
+  HIPCHK(c->psi.ensure(size_t(c->cur.nslots) * 4 * m * MEQN * esz + 256));
+  HIPCHK(c->dtl.ensure(kLevels));
+  hipLaunchKernelGGL(k_level_dts, dim3(1), dim3(kLevels), 0, s, dt, c->dtl.p);
+  R* bufs[3] = {const_cast<R*>(static_cast<const R*>(q)), static_cast<R*>(qn),
+                static_cast<R*>(w)};
+  TimeView<R> tv;
+  for (int b = 0; b < 3; ++b) tv.bufs[b] = bufs[b];
+  const int32_t nitems = c->cur.n_reflux_x + c->cur.n_reflux_y;
+  const bool wide = c->cfg.threads == 2 * c->tile * c->tile;
+  R* psi = reinterpret_cast<R*>(c->psi.p);
+  const R* phi = reinterpret_cast<const R*>(c->phi.p);
+  int64_t cells = 0;
+  const unsigned ig = unsigned(std::max<int64_t>(1, (int64_t(nitems) * m + 255) / 256));
+  for (const SubPlan::Action& A : sp.actions) {
+    if (A.correct) {
+      if (nitems > 0) {
+        hipLaunchKernelGGL((k_subcycle_reflux<R, PHYS>), dim3(ig), dim3(256), 0, s,
+                           bufs[A.dst], c->cur.reflux, c->cur.aux, nitems, phi, psi,
+                           c->dtl.p, m, int32_t(A.level));
+        HIPCHK(hipGetLastError());
+      }
+      continue;
+    }
+    const int32_t n = lf[A.level + 1] - lf[A.level];
+    const int32_t* list = c->cur.bylevel + lf[A.level];
+    if (n > 0) {
+      tv.src = c->tables.p + size_t(A.table) * kLevels;
+      hipLaunchKernelGGL((k_ghost_fill_level<R, PHYS>),
+                         dim3(unsigned((int64_t(n) * G + 255) / 256)), dim3(256), 0, s, list, n,
+                         static_cast<R*>(ghost), c->cur.rec, m, lm, c->err.p, tv);
+      const R* gq = static_cast<const R*>(ghost);
+      const double* dtlev = c->dtl.p + A.level;
+      if (c->tile == 8)
+        wide ? launch_step_level<R, PHYS, 8, 128>(c, bufs[A.src], gq, bufs[A.dst], dtlev, numax,
+                                                  list, n, s)
+             : launch_step_level<R, PHYS, 8, 64>(c, bufs[A.src], gq, bufs[A.dst], dtlev, numax,
+                                                 list, n, s);
+      else
+        wide ? launch_step_level<R, PHYS, 16, 512>(c, bufs[A.src], gq, bufs[A.dst], dtlev,
+                                                   numax, list, n, s)
+             : launch_step_level<R, PHYS, 16, 256>(c, bufs[A.src], gq, bufs[A.dst], dtlev,
+                                                   numax, list, n, s);
+      HIPCHK(hipGetLastError());
+      cells += int64_t(n) * m * m;
+    }
+    if (A.level > lmin && nitems > 0) {
+      hipLaunchKernelGGL((k_psi_accumulate<R, PHYS>), dim3(ig), dim3(256), 0, s,
+                         bufs[A.qc_old], bufs[A.src], c->cur.reflux, c->cur.aux, nitems, phi,
+                         psi, m, kphys(c), int32_t(A.level - 1), 0.5, int32_t(A.add),
+                         c->err.p);
+      HIPCHK(hipGetLastError());
+    }
+  }
+  // CFL check, next dt and (redo on) the copy of a rejected attempt
+  NextDtArgs nd = next_args(c, numax, dt, status, c->cfg.redo);
+  nd.cells = cells;
+  hipLaunchKernelGGL(k_next_dt_redo, dim3(unsigned(redo_grid(c, nd.n16))), dim3(256), 0, s,
+                     static_cast<const uint4*>(q), static_cast<uint4*>(qn), nd, c->err.p);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_advance_subcycled(fcx_ctx* c, const void* q, void* q_new, void* work, void* ghost,
+                          double* dt, double* nu_max, int32_t* status, void* stream) {
+  if (!c || !q || !q_new || !work || !ghost || !dt || !nu_max || !status ||
+      q == q_new || q == work || q_new == work)
+    return fail(FCX_EINVAL, "bad arguments");
+  if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no sub-cycled step on the sphere");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const bool dp = c->cfg.precision == 64;
+  if (c->cfg.physics == FCX_ADVECTION)
+    return dp ? subcycled_t<double, FCX_ADVECTION>(c, q, q_new, work, ghost, dt, nu_max, status, s)
+              : subcycled_t<float, FCX_ADVECTION>(c, q, q_new, work, ghost, dt, nu_max, status, s);
+  return dp ? subcycled_t<double, FCX_SHALLOW>(c, q, q_new, work, ghost, dt, nu_max, status, s)
+            : subcycled_t<float, FCX_SHALLOW>(c, q, q_new, work, ghost, dt, nu_max, status, s);
+}
+
 // ---- tags and mesh change in one call ---------------------------------------
 
 int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double threshold,
@@ -1551,8 +1767,9 @@ int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* gh
       steps < 0 || step0 < 0 || regrid_every < 0 || q0 == q1)
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  if (fused < 0 || fused > 2) return fail(FCX_EINVAL, "mode must be 0, 1 or 2");
   if (c->cfg.physics == FCX_SPHERE && fused)
-    return fail(FCX_EINVAL, "no fused run on the sphere");
+    return fail(FCX_EINVAL, "no fused or sub-cycled run on the sphere");
   void* buf[2] = {q0, q1};
   int cur = 0;
   int64_t cells = 0;
@@ -1582,7 +1799,13 @@ int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* gh
     }
     if (fcx_state_elems(c) > cap) return fail(FCX_ENOMEM, "state capacity exceeded");
     int rc;
-    if (fused) {
+    if (fused == 2) {
+      if (fcx_ghost_elems(c) > ghost_cap) return fail(FCX_ENOMEM, "ghost capacity exceeded");
+      const size_t wbytes = size_t(fcx_state_elems(c)) * (c->cfg.precision / 8);
+      HIPCHK(c->sub_work.ensure(wbytes));
+      rc = fcx_advance_subcycled(c, buf[cur], buf[1 - cur], c->sub_work.p, ghost, dt, nu_max,
+                                 status, stream);
+    } else if (fused) {
       rc = fcx_advance(c, buf[cur], buf[1 - cur], dt, nu_max, status, stream);
     } else {
       if (fcx_ghost_elems(c) > ghost_cap) return fail(FCX_ENOMEM, "ghost capacity exceeded");
@@ -1595,7 +1818,16 @@ int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* gh
     }
     if (rc != FCX_OK) return rc;
     cur = 1 - cur;
-    cells += c->cur.P * mm;
+    if (fused == 2) {
+      const auto& lf = c->cur.level_first;
+      int lmin = -1;
+      for (int l = 0; l < kLevels && lmin < 0; ++l)
+        if (lf[l + 1] > lf[l]) lmin = l;
+      for (int l = lmin; l < kLevels; ++l)
+        cells += int64_t(lf[l + 1] - lf[l]) * mm << (l - lmin);
+    } else {
+      cells += c->cur.P * mm;
+    }
   }
   if (redo) {
     HIPCHK(hipMemcpyAsync(counts + 3, c->stats.p, 3 * sizeof(int64_t), hipMemcpyDeviceToHost,

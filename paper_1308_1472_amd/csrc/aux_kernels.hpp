@@ -304,6 +304,154 @@ k_next_dt_redo(const uint4* __restrict__ q, uint4* __restrict__ qn, NextDtArgs n
 }
 
 // ---------------------------------------------------------------------------
+// Sub-cycling (per-level time steps): the kernels around one level's
+// substep.  Level l steps with dt 2^-l; the launches of one coarse step run
+// coarse to fine (see fcx_advance_subcycled).
+
+// dt of every level from the level-0 step
+__global__ void k_level_dts(const double* __restrict__ dt, double* __restrict__ dtl) {
+  const int l = threadIdx.x;
+  if (l < kLevels) dtl[l] = ldexp(*dt, -l);
+}
+
+// Ghost fill of the patches in `list` (one level) at the time of its
+// substep: every leaf is read through the level table of tv.
+template <typename R, int PHYS>
+__global__ void __launch_bounds__(256)
+k_ghost_fill_level(const int32_t* __restrict__ list, int32_t n, R* __restrict__ ghost,
+                   const PatchRec* __restrict__ rec, int m, int lm, int32_t* err,
+                   TimeView<R> tv) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  const int G = 8 * m + 16;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(n) * G) return;
+  const int slot = int(t / G), g = int(t - int64_t(slot) * G);
+  const int p = list[slot];
+  int i, j;
+  ghost_cell(m, g, i, j);
+  if ((i == -1 || i == m + 2) && (j == -1 || j == m + 2)) return;
+  GhostView<R, MEQN> gv{nullptr, rec, m, lm, err, nullptr, tv};
+  R v[MEQN];
+  frame_value<R, MEQN, PHYS, true, true>(gv, p, i, j, v);
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) ghost[size_t(p * MEQN + k) * G + g] = v[k];
+}
+
+// Fine-side terms of one fine substep at the faces of coarse patches of
+// level lc (the reflux items whose coarse patch has that level): per fine
+// face cell, psi (=, or += when `add`) w [dx_f (f(q_f) - f(q_c)) - phi_f],
+// q_f from qf (the fine states at the substep's start), q_c from qc (the
+// coarse states at the start of the coarse level's step).
+template <typename R, int PHYS>
+__global__ void __launch_bounds__(256)
+k_psi_accumulate(const R* __restrict__ qc_buf, const R* __restrict__ qf_buf,
+                 const RefluxItem* __restrict__ items, const RefluxAux* __restrict__ aux,
+                 int32_t nitems, const R* __restrict__ phi, R* __restrict__ psi, int m,
+                 KPhys ph, int32_t lc, double w, int32_t add, int32_t* err) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(nitems) * m) return;
+  const int32_t ii = int32_t(t / m);
+  const int tc = int(t % m) + 1;
+  const RefluxAux ax = aux[ii];
+  if (ax.level != lc) return;
+  const RefluxItem it = items[ii];
+  const int f = it.face, d = f >> 1, hi = f & 1;
+  const int ic = d == 0 ? (hi ? m : 1) : tc, jc = d == 0 ? tc : (hi ? m : 1);
+  const int k2 = (tc - 1) / (m / 2);
+  const int fp = it.fine[k2], ff = it.fine_face[k2];
+  const double dxc = ldexp(1.0, -ax.level) / m;
+  R qc[MEQN];
+  read_interior<R, MEQN>(qc_buf, m, it.coarse, ic, jc, qc);
+  const R* phf = phi + size_t(ax.slot_f[k2]) * 4 * m * MEQN;
+  R* psf = psi + size_t(ax.slot_f[k2]) * 4 * m * MEQN;
+  for (int s = 0; s < 2; ++s) {
+    int pos = 2 * (tc - 1 - k2 * (m / 2)) + 1 + s;
+    if (it.fine_rev[k2]) pos = m + 1 - pos;
+    const int fi = ff < 2 ? (ff == 0 ? 1 : m) : pos;
+    const int fj = ff < 2 ? pos : (ff == 2 ? 1 : m);
+    R qf[MEQN], fs[MEQN];
+    read_interior<R, MEQN>(qf_buf, m, fp, fi, fj, qf);
+    if (hi) fluct_sum<R, PHYS>(ph, d, qc, qf, fs, err);
+    else fluct_sum<R, PHYS>(ph, d, qf, qc, fs, err);
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) {
+      const size_t o = size_t(ff * m + (pos - 1)) * MEQN + k;
+      const R v = R(w) * (R(0.5 * dxc) * fs[k] - phf[o]);
+      psf[o] = add ? psf[o] + v : v;
+    }
+  }
+}
+
+// Coarse cells of level lc at faces with level lc + 1, after the finer
+// level's two substeps: -dt_lc / dx^2 (psi of the two fine cells - phi_c),
+// xi corrections first at corner cells (the links of RefluxAux, as in
+// k_reflux).
+template <typename R, int MEQN>
+__device__ __forceinline__ void subcycle_corr(const RefluxItem& it, const RefluxAux& ax,
+                                              int tc, const R* __restrict__ phi,
+                                              const R* __restrict__ psi, int m,
+                                              R (&corr)[MEQN], size_t& o, double& dxc) {
+  const int f = it.face, d = f >> 1, hi = f & 1;
+  const int ic = d == 0 ? (hi ? m : 1) : tc, jc = d == 0 ? tc : (hi ? m : 1);
+  const int k2 = (tc - 1) / (m / 2);
+  const int ff = it.fine_face[k2];
+  dxc = ldexp(1.0, -ax.level) / m;
+  o = (size_t(it.coarse * MEQN) * m + (jc - 1)) * m + (ic - 1);
+  const R* phc = phi + size_t(ax.slot_c) * 4 * m * MEQN;
+  const R* psf = psi + size_t(ax.slot_f[k2]) * 4 * m * MEQN;
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) corr[k] = -phc[(f * m + (tc - 1)) * MEQN + k];
+  R fine[MEQN];
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) fine[k] = R(0);
+  for (int s = 0; s < 2; ++s) {
+    int pos = 2 * (tc - 1 - k2 * (m / 2)) + 1 + s;
+    if (it.fine_rev[k2]) pos = m + 1 - pos;
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) fine[k] += psf[(ff * m + (pos - 1)) * MEQN + k];
+  }
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) corr[k] = fine[k] + corr[k];
+}
+
+template <typename R, int PHYS>
+__global__ void __launch_bounds__(256)
+k_subcycle_reflux(R* __restrict__ qn, const RefluxItem* __restrict__ items,
+                  const RefluxAux* __restrict__ aux, int32_t nitems,
+                  const R* __restrict__ phi, const R* __restrict__ psi,
+                  const double* __restrict__ dtl, int m, int32_t lc) {
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= int64_t(nitems) * m) return;
+  const int32_t i = int32_t(t / m);
+  const int tc = int(t % m) + 1;
+  const RefluxAux ax = aux[i];
+  if (ax.level != lc) return;
+  const RefluxItem it = items[i];
+  const int end = tc == 1 ? 0 : (tc == m ? 1 : -1);
+  const int32_t link = end >= 0 ? ax.link[end] : -1;
+  if (it.face >= 2 && link >= 0) return;
+  R c0[MEQN], c1[MEQN];
+  size_t o, o1;
+  double dxc, dxc1;
+  subcycle_corr<R, MEQN>(it, ax, tc, phi, psi, m, c0, o, dxc);
+  const bool two = it.face < 2 && link >= 0;
+  if (two)
+    subcycle_corr<R, MEQN>(items[link], aux[link], it.face == 0 ? 1 : m, phi, psi, m, c1,
+                           o1, dxc1);
+  const R fac = R(dtl[lc] / (dxc * dxc));
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) {
+    const size_t ok = o + size_t(k) * m * m;
+    R v = qn[ok];
+    v -= fac * c0[k];
+    if (two) v -= fac * c1[k];
+    qn[ok] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Conservation sums: per-patch FP64 partials in a fixed thread order, then
 // a fixed pairwise reduction over patches.
 template <typename R, int MEQN>

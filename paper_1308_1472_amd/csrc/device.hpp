@@ -79,6 +79,23 @@ __device__ __forceinline__ void resolve_walls(int32_t flags, int m, int& i,
   }
 }
 
+// Sub-cycling: where the state of each level is read at the time of one
+// level's substep.  By level: the buffer (index into bufs) holding the state
+// at the substep's time, or, for a coarser level in the middle of its own
+// step (alpha > 0), the buffers of the start (old) and end (cur) of that
+// step, mixed (1 - alpha) old + alpha cur.
+struct LevelSrc {
+  int32_t cur, old;
+  double alpha;
+};
+constexpr int kLevels = 32;
+
+template <typename R>
+struct TimeView {
+  const R* bufs[3];
+  const LevelSrc* src;            // [kLevels], in device memory
+};
+
 template <typename R, int MEQN>
 struct GhostView {
   const R* __restrict__ q;
@@ -86,7 +103,30 @@ struct GhostView {
   int m, lm;                      // m = 2^lm
   int32_t* err;
   const double* geo = nullptr;    // sphere: per-patch geometry tables
+  TimeView<R> tv{};               // sub-cycling (frame_value with TIMED)
 };
+
+// Interior cell (i, j) of leaf p: from q, or (TIMED) from the buffer(s) of
+// p's level at the time of the current substep.
+template <typename R, int MEQN, bool TIMED>
+__device__ __forceinline__ void leaf_cell(const GhostView<R, MEQN>& g, int p, int i, int j,
+                                          R (&out)[MEQN]) {
+  if constexpr (!TIMED) {
+    read_interior<R, MEQN>(g.q, g.m, p, i, j, out);
+  } else {
+    // (1 - alpha) old + alpha cur; alpha = 0 is the step's start (old),
+    // and levels read at their own time have old = cur
+    const LevelSrc s = g.tv.src[g.rec[p].level];
+    read_interior<R, MEQN>(g.tv.bufs[s.old], g.m, p, i, j, out);
+    if (s.alpha != 0.0) {
+      R c[MEQN];
+      read_interior<R, MEQN>(g.tv.bufs[s.cur], g.m, p, i, j, c);
+      const R a = R(s.alpha), b = R(1.0 - s.alpha);
+#pragma unroll
+      for (int k = 0; k < MEQN; ++k) out[k] = b * out[k] + a * c[k];
+    }
+  }
+}
 
 // capacity of interior cell (i, j) of patch p from a sphere geometry table
 // (kappa is the first frame of (m+4)^2 values, then 17 more frames)
@@ -150,18 +190,18 @@ __device__ __forceinline__ int32_t holder(const GhostView<R, MEQN>& g,
 // coarser leaf if ALLOW_INTERP (its slope stencil uses frame values of the
 // coarse leaf, which never need interpolation themselves under full 2:1
 // balance with m >= 4).
-template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP>
+template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP, bool TIMED = false>
 __device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
                           int32_t X, int32_t Y, R (&out)[MEQN]);
 
-template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP>
+template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP, bool TIMED = false>
 __device__ void frame_value(const GhostView<R, MEQN>& g, int p, int i, int j,
                             R (&out)[MEQN]) {
   const PatchRec& r = g.rec[p];
   bool nx = false, ny = false;
   resolve_walls(r.flags, g.m, i, j, nx, ny);
   if (i >= 1 && i <= g.m && j >= 1 && j <= g.m) {
-    read_interior<R, MEQN>(g.q, g.m, p, i, j, out);
+    leaf_cell<R, MEQN, TIMED>(g, p, i, j, out);
   } else {
     int32_t X, Y;
     const int32_t nb = holder(g, r, i, j, X, Y);
@@ -173,12 +213,12 @@ __device__ void frame_value(const GhostView<R, MEQN>& g, int p, int i, int j,
       int32_t Xa, Ya, Xb, Yb;
       const int32_t na = holder(g, r, i, mj, Xa, Ya);
       const int32_t nb2 = holder(g, r, mi, j, Xb, Yb);
-      from_leaf<R, MEQN, PHYS, ALLOW_INTERP>(g, r.level, na, Xa, Ya, a);
-      from_leaf<R, MEQN, PHYS, ALLOW_INTERP>(g, r.level, nb2, Xb, Yb, b);
+      from_leaf<R, MEQN, PHYS, ALLOW_INTERP, TIMED>(g, r.level, na, Xa, Ya, a);
+      from_leaf<R, MEQN, PHYS, ALLOW_INTERP, TIMED>(g, r.level, nb2, Xb, Yb, b);
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) out[k] = R(0.5) * (a[k] + b[k]);
     } else {
-      from_leaf<R, MEQN, PHYS, ALLOW_INTERP>(g, r.level, nb, X, Y, out);
+      from_leaf<R, MEQN, PHYS, ALLOW_INTERP, TIMED>(g, r.level, nb, X, Y, out);
     }
   }
   if (PHYS == FCX_SHALLOW) {
@@ -187,7 +227,7 @@ __device__ void frame_value(const GhostView<R, MEQN>& g, int p, int i, int j,
   }
 }
 
-template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP>
+template <typename R, int MEQN, int PHYS, bool ALLOW_INTERP, bool TIMED>
 __device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
                           int32_t X, int32_t Y, R (&out)[MEQN]) {
   const PatchRec& n = g.rec[nb];
@@ -195,15 +235,15 @@ __device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
   const int csh = shn - g.lm;                    // log2 of n's cell size
   const int32_t u = X - (n.ix << shn), v = Y - (n.iy << shn);
   if (n.level == lev) {
-    read_interior<R, MEQN>(g.q, g.m, nb, (u >> csh) + 1, (v >> csh) + 1, out);
+    leaf_cell<R, MEQN, TIMED>(g, nb, (u >> csh) + 1, (v >> csh) + 1, out);
   } else if (n.level == lev + 1) {
     // the centre is the common corner of four cells of the finer leaf
     const int i0 = u >> csh, j0 = v >> csh;
     R a[MEQN], b[MEQN], c[MEQN], d[MEQN];
-    read_interior<R, MEQN>(g.q, g.m, nb, i0, j0, a);
-    read_interior<R, MEQN>(g.q, g.m, nb, i0 + 1, j0, b);
-    read_interior<R, MEQN>(g.q, g.m, nb, i0, j0 + 1, c);
-    read_interior<R, MEQN>(g.q, g.m, nb, i0 + 1, j0 + 1, d);
+    leaf_cell<R, MEQN, TIMED>(g, nb, i0, j0, a);
+    leaf_cell<R, MEQN, TIMED>(g, nb, i0 + 1, j0, b);
+    leaf_cell<R, MEQN, TIMED>(g, nb, i0, j0 + 1, c);
+    leaf_cell<R, MEQN, TIMED>(g, nb, i0 + 1, j0 + 1, d);
     if (PHYS == FCX_SPHERE) {
       // capacity-weighted mean
       const R ka = R(geo_kappa(g.geo, g.m, nb, i0, j0));
@@ -225,11 +265,11 @@ __device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
     const R dx = (2 * u > (2 * ic - 1) * cs) ? R(0.25) : R(-0.25);
     const R dy = (2 * v > (2 * jc - 1) * cs) ? R(0.25) : R(-0.25);
     R qc[MEQN], qe[MEQN], qw[MEQN], qn[MEQN], qs[MEQN];
-    read_interior<R, MEQN>(g.q, g.m, nb, ic, jc, qc);
-    frame_value<R, MEQN, PHYS, false>(g, nb, ic + 1, jc, qe);
-    frame_value<R, MEQN, PHYS, false>(g, nb, ic - 1, jc, qw);
-    frame_value<R, MEQN, PHYS, false>(g, nb, ic, jc + 1, qn);
-    frame_value<R, MEQN, PHYS, false>(g, nb, ic, jc - 1, qs);
+    leaf_cell<R, MEQN, TIMED>(g, nb, ic, jc, qc);
+    frame_value<R, MEQN, PHYS, false, TIMED>(g, nb, ic + 1, jc, qe);
+    frame_value<R, MEQN, PHYS, false, TIMED>(g, nb, ic - 1, jc, qw);
+    frame_value<R, MEQN, PHYS, false, TIMED>(g, nb, ic, jc + 1, qn);
+    frame_value<R, MEQN, PHYS, false, TIMED>(g, nb, ic, jc - 1, qs);
 #pragma unroll
     for (int k = 0; k < MEQN; ++k) {
       const R sx = minmod(qe[k] - qc[k], qc[k] - qw[k]);
@@ -240,7 +280,7 @@ __device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
     // a slope stencil reached a coarser leaf: cannot happen on a 2:1
     // balanced forest; flag it and use the coarse cell value
     atomicOr(g.err, kErrNested);
-    read_interior<R, MEQN>(g.q, g.m, nb, (u >> csh) + 1, (v >> csh) + 1, out);
+    leaf_cell<R, MEQN, TIMED>(g, nb, (u >> csh) + 1, (v >> csh) + 1, out);
   }
 }
 

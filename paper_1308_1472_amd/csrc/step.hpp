@@ -535,4 +535,17 @@ k_step(StepArgs<R> A) {
   tile_step<R, PHYS, T, NT, FUSED>(A, p, tile % tps, tile / tps, lds);
 }
 
+// One workgroup per tile of the patches in `list` (one level of a
+// sub-cycled step); plain path (ghosts from the ghost buffer).
+template <typename R, int PHYS, int T, int NT>
+__global__ void __launch_bounds__(NT)
+k_step_level(StepArgs<R> A, const int32_t* __restrict__ list) {
+  __shared__ TileLds<R, PHYS, T, NT> lds;
+  const int t = xcd_tile(blockIdx.x, A.ntiles);
+  const int tps = A.m / T;
+  const int p = list[t / (tps * tps)];
+  const int tile = t % (tps * tps);
+  tile_step<R, PHYS, T, NT, false>(A, p, tile % tps, tile / tps, lds);
+}
+
 }  // namespace fcx

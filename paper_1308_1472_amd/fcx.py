@@ -41,6 +41,7 @@ EXPORTS = [
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
     "fcx_sphere_geometry", "fcx_advance", "fcx_regrid", "fcx_run",
     "fcx_step_stats", "fcx_batch_step_stats", "fcx_conservation_sums_noalloc",
+    "fcx_advance_subcycled",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -123,6 +124,7 @@ def lib():
         L.fcx_regrid.argtypes = [vp, vp, vp, i32, dp, i32, i32, vp, vp, vp]
         L.fcx_step_stats.argtypes = [vp, vp]
         L.fcx_conservation_sums_noalloc.argtypes = [vp, vp, vp, vp]
+        L.fcx_advance_subcycled.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fcx_batch_step_stats.argtypes = [vp, vp]
         L.fcx_run.argtypes = [vp, i32, vp, vp, i64, vp, i64, i32, i32, i32, i32, dp, i32,
                               i32, vp, vp, vp, vp, vp, vp]
@@ -352,6 +354,15 @@ class Context:
                                  self._d(numax), self._d(status, 1, torch.int32),
                                  _stream(stream)))
 
+    def advance_subcycled(self, q, q_new, work, ghost, dt, numax, status, stream=None):
+        """One sub-cycled step of the coarsest level (dt: a level-0 patch's
+        step; level l steps with dt 2^-l)."""
+        import torch
+        _check(lib().fcx_advance_subcycled(self.h, self._q(q), self._q(q_new),
+                                           self._q(work), self._g(ghost), self._d(dt),
+                                           self._d(numax), self._d(status, 1, torch.int32),
+                                           _stream(stream)))
+
     def reflux(self, q, q_new, dt, stream=None):
         _check(lib().fcx_reflux(self.h, self._q(q), self._q(q_new), self._d(dt),
                                 _stream(stream)))
@@ -427,7 +438,8 @@ class Context:
 
     def run(self, q0, q1, ghost, steps, step0, regrid_every, criterion, threshold,
             lmin, lmax, dt, numax, status, fused=True, stream=None):
-        """`steps` whole steps with periodic regrids on two capacity buffers;
+        """`steps` whole steps with periodic regrids on two capacity buffers
+        (fused: True / 1 fused steps, False / 0 plain, 2 sub-cycled);
         returns (index of the buffer with the result, cell updates)."""
         import torch
         dtype = torch.float64 if self.cfg.precision == 64 else torch.float32
