@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "sphere",
-                                       "mlp", "copy", "cpu", "all"],
+                                       "mlp", "copy", "cpu", "subcycle", "all"],
                     default="all")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--sphere-steps", type=int, default=1000)
@@ -148,8 +148,10 @@ class Workload:
         hmin = 1.0 / (self.M << int(leaves["level"].max()))
         # start at half the target Courant number: the first steps of a dam
         # break raise the largest wave speed
-        self.dt = torch.full((1,), 0.45 * hmin / 2.0 ** 0.5, dtype=torch.float64,
-                             device=dev)
+        dt0 = 0.45 * hmin / 2.0 ** 0.5
+        if fused == 2:                    # sub-cycled: the step of a level-0 patch
+            dt0 *= float(1 << int(leaves["level"].max()))
+        self.dt = torch.full((1,), dt0, dtype=torch.float64, device=dev)
         self.numax = torch.zeros(1, dtype=torch.float64, device=dev)
         self.status = torch.zeros(1, dtype=torch.int32, device=dev)
         self.n = 0
@@ -162,11 +164,12 @@ class Workload:
         n = self.ctx.state_elems()
         return self.buf[self.cur][:n], self.buf[1 - self.cur][:n]
 
-    def advance(self, steps):
+    def advance(self, steps, every=None):
         """`steps` steps in the library's run loop; returns cell updates."""
+        every = self.REGRID if every is None else every
         which, cells = self.ctx.run(
             self.buf[self.cur], self.buf[1 - self.cur], self.ghost, steps, self.n,
-            0 if self.uniform else self.REGRID, 1, self.THR, self.LMIN, self.LMAX,
+            0 if self.uniform else every, 1, self.THR, self.LMIN, self.LMAX,
             self.dt, self.numax, self.status, fused=self.fused)
         if which == 1:
             self.cur = 1 - self.cur
@@ -223,6 +226,42 @@ def run(precision, fused, steps, warmup, uniform_level=None):
     }
     if uniform_level is not None:
         out["_state"] = q                 # for the FP32-vs-FP64 comparison
+    return out
+
+
+def run_time_stepping(coarse_steps=24, precision=32):
+    """The meshing-strategy comparison of the paper on one GPU: the adaptive
+    dam break advanced with one global dt (fused and plain steps, regrid
+    every 4 steps) and sub-cycled (level l steps with its own dt, regrid
+    every 4 and every 1 coarsest-level steps), each from t = 0 for about the
+    same simulated time; reports simulated time per second of wall clock
+    (time to solution) and cell updates per second."""
+    import torch
+    out = {}
+    variants = (("global_fused_regrid4", True, 4, 8 * coarse_steps),
+                ("global_plain_regrid4", False, 4, 8 * coarse_steps),
+                ("subcycled_regrid4", 2, 4, coarse_steps),
+                ("subcycled_regrid1", 2, 1, coarse_steps))
+    for name, mode, every, steps in variants:
+        Workload(precision, mode).advance(4, every)          # warm-up
+        torch.cuda.synchronize()
+        w = Workload(precision, mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cells = float(w.advance(steps, every))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        acc, rej, _ = w.ctx.step_stats()
+        sim = w.ctx.sim_time()
+        status = int(w.status.item())
+        out[name] = {"attempts": steps, "accepted": acc, "rejected": rej,
+                     "regrid_every": every, "seconds": el, "sim_time": sim,
+                     "sim_time_per_s": sim / el, "cell_updates": cells,
+                     "rate": cells / el, "patches_last": w.ctx.num_patches(),
+                     "status": status, "status_bits": status_bits([status])}
+    base = out["global_fused_regrid4"]["sim_time_per_s"]
+    for name in out:
+        out[name]["time_to_solution_speedup_vs_global_fused"] = out[name]["sim_time_per_s"] / base
     return out
 
 
@@ -695,16 +734,22 @@ def main():
         res["sphere64"] = run_sphere(args.sphere64_steps, precision=64, kernel_timing=False,
                                      threshold=res["sphere"]["threshold"])
         print(f"# sphere fp64: {res['sphere64']}", file=sys.stderr, flush=True)
+    if args.only in ("subcycle", "all"):
+        res["subcycle"] = run_time_stepping()
+        print(f"# time stepping: {res['subcycle']}", file=sys.stderr, flush=True)
     if args.only in ("mlp", "all"):
         res["mlp"] = run_mlp()
         print(f"# mlp: {res['mlp']}", file=sys.stderr, flush=True)
     # timed legs whose status words carry a bit that marks a wrong step
     bad = {k: r.get("status_bits") for k, r in res.items()
            if isinstance(r, dict) and (int(r.get("status", 0)) & BAD_BITS or r.get("status_bad"))}
+    for k, r in res.get("subcycle", {}).items():
+        if r["status"] & BAD_BITS:
+            bad["subcycle/" + k] = r["status_bits"]
     head = res.get("fp32") or res.get("fp64") or res.get("large32")
     if head is None:
         print(json.dumps({k: res.get(k) for k in ("batch", "batch64", "sphere", "sphere64",
-                                                  "mlp") if k in res}), flush=True)
+                                                  "subcycle", "mlp") if k in res}), flush=True)
         sys.exit(3 if bad else 0)
     steps = args.steps if "fp32" in res or "fp64" in res else args.large_steps
     bytes_per_cell = 24.0 if head is not res.get("fp64") else 48.0
@@ -819,6 +864,10 @@ def main():
             "and sums, plain path with reflux, the library's run loop"))
         if "sphere64" in res:
             out["cubed_sphere"]["fp64_state_run"] = res["sphere64"]
+    if "subcycle" in res:
+        out["time_stepping"] = dict(res["subcycle"], workload=(
+            ADAPTIVE + ", FP32; global dt (fused or plain steps) against per-level dt "
+            "(sub-cycled, plain launches), each from t = 0"))
     if "mlp" in res:
         out["learned_tagging_mlp"] = res["mlp"]
     if not args.no_cpu_baseline and "fp32" in res:

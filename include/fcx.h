@@ -234,6 +234,11 @@ int fcx_advance_subcycled(fcx_ctx *ctx, const void *q, void *q_new, void *work,
  * out[2] accepted cell updates (interior cells advanced). */
 int fcx_step_stats(const fcx_ctx *ctx, int64_t *out);
 
+/* Simulated time covered by the accepted steps of this context since
+ * fcx_create (the sum of their dt; a sub-cycled step counts the step of its
+ * coarsest level), read after the device has finished. */
+int fcx_sim_time(const fcx_ctx *ctx, double *t);
+
 /* A run of `steps` whole steps on two caller buffers of `cap` elements
  * each (enough for the finest forest the run can reach): step n = step0 +
  * k first regrids when regrid_every > 0, n > 0 and n % regrid_every == 0

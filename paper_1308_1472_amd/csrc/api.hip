@@ -141,6 +141,7 @@ struct fcx_ctx {
   DevBuf<int32_t> err;
   DevBuf<uint32_t> ticket;         // last-workgroup ticket of the reflux
   DevBuf<int64_t> stats;           // {accepted steps, rejected attempts, accepted cells}
+  DevBuf<double> tsim;             // simulated time of the accepted steps
   DevBuf<uint8_t> psi;             // sub-cycling: fine-side terms per face-term slot
   DevBuf<double> dtl;              //   dt of every level
   DevBuf<LevelSrc> tables;         //   per launch of a coarse step: where levels are read
@@ -347,13 +348,14 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   }
   c->trees = t;
   if (c->err.ensure(1) != hipSuccess || c->ticket.ensure(1) != hipSuccess ||
-      c->stats.ensure(3) != hipSuccess) {
+      c->stats.ensure(3) != hipSuccess || c->tsim.ensure(1) != hipSuccess) {
     delete c;
     return fail(FCX_ENOMEM, "hipMalloc failed");
   }
   if (hipMemset(c->err.p, 0, sizeof(int32_t)) != hipSuccess ||
       hipMemset(c->ticket.p, 0, sizeof(uint32_t)) != hipSuccess ||
-      hipMemset(c->stats.p, 0, 3 * sizeof(int64_t)) != hipSuccess) {
+      hipMemset(c->stats.p, 0, 3 * sizeof(int64_t)) != hipSuccess ||
+      hipMemset(c->tsim.p, 0, sizeof(double)) != hipSuccess) {
     delete c;
     return fail(FCX_EHIP, "hipMemset failed");
   }
@@ -745,6 +747,8 @@ static NextDtArgs next_args(fcx_ctx* c, double* numax, double* dt, int32_t* stat
   nd.redo = redo;
   nd.cells = c->cur.P * c->cfg.m * c->cfg.m;
   nd.n16 = c->cur.P * c->meqn * c->cfg.m * c->cfg.m * (c->cfg.precision / 8) / 16;
+  nd.tsim = c->tsim.p;
+  nd.tscale = 1.0;
   return nd;
 }
 
@@ -807,7 +811,7 @@ int fcx_next_dt(fcx_ctx* c, double* numax, double* dt, int32_t* status, void* st
   hipLaunchKernelGGL(k_next_dt, dim3(1), dim3(64), 0,
                      static_cast<hipStream_t>(stream), numax, dt, status, c->err.p,
                      c->stats.p, c->cfg.cfl_desired, c->cfg.cfl_max,
-                     int64_t(c->cur.P) * c->cfg.m * c->cfg.m);
+                     int64_t(c->cur.P) * c->cfg.m * c->cfg.m, c->tsim.p);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -826,6 +830,12 @@ static int next_dt_redo(fcx_ctx* c, const void* q, void* qn, double* numax, doub
 int fcx_step_stats(const fcx_ctx* c, int64_t* out) {
   if (!c || !out) return fail(FCX_EINVAL, "bad arguments");
   HIPCHK(hipMemcpy(out, c->stats.p, 3 * sizeof(int64_t), hipMemcpyDeviceToHost));
+  return FCX_OK;
+}
+
+int fcx_sim_time(const fcx_ctx* c, double* t) {
+  if (!c || !t) return fail(FCX_EINVAL, "bad arguments");
+  HIPCHK(hipMemcpy(t, c->tsim.p, sizeof(double), hipMemcpyDeviceToHost));
   return FCX_OK;
 }
 
@@ -1705,6 +1715,7 @@ static int subcycled_t(fcx_ctx* c, const void* q, void* qn, void* w, void* ghost
   // CFL check, next dt and (redo on) the copy of a rejected attempt
   NextDtArgs nd = next_args(c, numax, dt, status, c->cfg.redo);
   nd.cells = cells;
+  nd.tscale = std::ldexp(1.0, -lmin);       // a coarse step lasts dt 2^-lmin
   hipLaunchKernelGGL(k_next_dt_redo, dim3(unsigned(redo_grid(c, nd.n16))), dim3(256), 0, s,
                      static_cast<const uint4*>(q), static_cast<uint4*>(qn), nd, c->err.p);
   HIPCHK(hipGetLastError());

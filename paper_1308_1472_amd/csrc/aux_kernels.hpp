@@ -152,8 +152,10 @@ __device__ __forceinline__ bool rejected(const double* numax, int f, double cfl_
 __device__ __forceinline__ void next_dt_one(double* numax, double* dt, int32_t* status,
                                             int32_t* err, int64_t* stats, int f,
                                             double cfl_desired, double cfl_max,
-                                            int32_t redo, int64_t cells) {
+                                            int32_t redo, int64_t cells,
+                                            double* tsim = nullptr, double tscale = 1.0) {
   const double nu = numax[f];
+  if (tsim && !(redo && nu > cfl_max)) tsim[f] += dt[f] * tscale;
   const bool rej = redo && nu > cfl_max;
   int32_t st = 0;
   if (nu > cfl_max) st |= rej ? kStatRedone : kStatCfl;
@@ -195,6 +197,8 @@ struct NextDtArgs {
   int32_t redo;
   int64_t cells;                             // cell updates of an accepted step
   int64_t n16;                               // size of the state in 16-byte units
+  double* tsim;                              // simulated time of accepted steps
+  double tscale;                             //   per unit of dt
 };
 
 // Reflux: one thread per (coarse-fine face item, coarse cell along it), all
@@ -265,7 +269,7 @@ k_reflux(const R* __restrict__ q, R* __restrict__ qn,
     if (last && threadIdx.x == 0) {
       __threadfence();
       next_dt_one(nd.numax, nd.dt, nd.status, err, nd.stats, 0, nd.cfl_desired, nd.cfl_max,
-                  nd.redo, nd.cells);
+                  nd.redo, nd.cells, nd.tsim, nd.tscale);
       *nd.ticket = 0;
     }
   }
@@ -275,9 +279,9 @@ k_reflux(const R* __restrict__ q, R* __restrict__ qn,
 // Next dt of one forest without a rejection copy (the caller decides).
 __global__ void k_next_dt(double* numax, double* dt, int32_t* status, int32_t* err,
                           int64_t* stats, double cfl_desired, double cfl_max,
-                          int64_t cells) {
+                          int64_t cells, double* tsim) {
   if (blockIdx.x == 0 && threadIdx.x == 0)
-    next_dt_one(numax, dt, status, err, stats, 0, cfl_desired, cfl_max, 0, cells);
+    next_dt_one(numax, dt, status, err, stats, 0, cfl_desired, cfl_max, 0, cells, tsim);
 }
 
 // Next dt of one forest with the CFL rule's rejection: every workgroup
@@ -298,7 +302,7 @@ k_next_dt_redo(const uint4* __restrict__ q, uint4* __restrict__ qn, NextDtArgs n
   if (last && threadIdx.x == 0) {
     __threadfence();
     next_dt_one(nd.numax, nd.dt, nd.status, err, nd.stats, 0, nd.cfl_desired, nd.cfl_max,
-                nd.redo, nd.cells);
+                nd.redo, nd.cells, nd.tsim, nd.tscale);
     *nd.ticket = 0;
   }
 }

@@ -41,7 +41,7 @@ EXPORTS = [
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
     "fcx_sphere_geometry", "fcx_advance", "fcx_regrid", "fcx_run",
     "fcx_step_stats", "fcx_batch_step_stats", "fcx_conservation_sums_noalloc",
-    "fcx_advance_subcycled",
+    "fcx_advance_subcycled", "fcx_sim_time",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -125,6 +125,7 @@ def lib():
         L.fcx_step_stats.argtypes = [vp, vp]
         L.fcx_conservation_sums_noalloc.argtypes = [vp, vp, vp, vp]
         L.fcx_advance_subcycled.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        L.fcx_sim_time.argtypes = [vp, vp]
         L.fcx_batch_step_stats.argtypes = [vp, vp]
         L.fcx_run.argtypes = [vp, i32, vp, vp, i64, vp, i64, i32, i32, i32, i32, dp, i32,
                               i32, vp, vp, vp, vp, vp, vp]
@@ -377,6 +378,12 @@ class Context:
         out = np.zeros(3, dtype=np.int64)
         _check(lib().fcx_step_stats(self.h, _np_ptr(out)))
         return tuple(int(v) for v in out)
+
+    def sim_time(self) -> float:
+        """Simulated time of the accepted steps since the context was made."""
+        t = C.c_double()
+        _check(lib().fcx_sim_time(self.h, C.byref(t)))
+        return t.value
 
     def conservation_sums(self, q, sums, stream=None):
         _check(lib().fcx_conservation_sums(self.h, self._q(q),
