@@ -47,7 +47,7 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "sphere",
-                                       "mlp", "copy", "cpu", "subcycle", "all"],
+                                       "mlp", "copy", "cpu", "subcycle", "meshing", "all"],
                     default="all")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--sphere-steps", type=int, default=1000)
@@ -262,6 +262,96 @@ def run_time_stepping(coarse_steps=24, precision=32):
     base = out["global_fused_regrid4"]["sim_time_per_s"]
     for name in out:
         out[name]["time_to_solution_speedup_vs_global_fused"] = out[name]["sim_time_per_s"] / base
+    return out
+
+
+def run_meshing(precision=32, m=8, lmin=3, lmax=8, T=0.25, thr=0.5):
+    """The meshing strategies of the paper's advection example (its wall-clock
+    table: uniform or adaptive mesh, remesh every step or every 4, global or
+    sub-cycled time steps) on one GPU.  Stand-in flow: the paper's swirl
+    velocity field is not given, so the 0/1 disk (radius 1/4, centre (1/2,
+    1/2)) is carried by the constant velocity a = (1, 1/2) on the periodic
+    unit square, m = 8, levels 3-8 (uniform: level 8), refined where
+    max - min of q over a patch exceeds 1/2 (coarsened below), CFL 0.9, to
+    t = T.  Reports wall clock to T, cell updates, and the L1 error against
+    the translated disk."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1308_1472_amd import fcx
+    from paper_1308_1472_amd import inputs as I
+    trees, pl = I.periodic_square()
+    ax, ay = 1.0, 0.5
+    cx, cy = 0.5, 0.5
+    disk = lambda x, y: np.where((x - cx) ** 2 + (y - cy) ** 2 < 0.0625, 1.0, 0.0)
+    dtype = torch.float32 if precision == 32 else torch.float64
+
+    def make(mode, uniform):
+        cfg = fcx.config(m, precision, fcx.FCX_ADVECTION, ax=ax, ay=ay)
+        ctx = fcx.Context(cfg, trees)
+        if uniform:
+            leaves = fcx.sfc_sort(I.uniform_leaves(1, lmax))
+        else:
+            leaves = fcx.sfc_sort(I.uniform_leaves(1, lmin))
+            for _ in range(2 * (lmax - lmin) + 2):
+                ctx.upload_forest(leaves)
+                q = torch.from_numpy(I.state_from(leaves, m, disk, pl).ravel()).to(dtype).cuda()
+                g = torch.empty(ctx.ghost_elems(), dtype=dtype, device="cuda")
+                ctx.regrid(q, g, 0, thr, lmin, lmax)
+                new = ctx.leaves()
+                if len(new) == len(leaves) and (new == leaves).all():
+                    break
+                leaves = new
+        ctx.upload_forest(leaves)
+        pmax = 1 << (2 * lmax)
+        bufs = [torch.empty(pmax * m * m, dtype=dtype, device="cuda") for _ in range(2)]
+        ghost = torch.empty(pmax * (8 * m + 16), dtype=dtype, device="cuda")
+        q0 = I.state_from(leaves, m, disk, pl)
+        bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
+        # CFL 0.9 with |a| = 1 on the finest cells (sub-cycled: a level-0
+        # patch's step, each level scaled by its own size)
+        dt = 0.9 / m if mode == 2 else 0.9 / (m << lmax)
+        return ctx, bufs, ghost, torch.full((1,), dt, dtype=torch.float64, device="cuda")
+
+    def exact_l1(ctx, q):
+        lv = ctx.leaves()
+        want = I.state_from(lv, m, lambda x, y: disk((x - ax * T) % 1.0, (y - ay * T) % 1.0),
+                            pl)
+        got = q.double().cpu().numpy().reshape(want.shape)
+        h = np.ldexp(1.0, -lv["level"].astype(int)) / m
+        return float(np.sum(np.abs(got - want)[:, 0] * (h ** 2)[:, None, None]))
+
+    strategies = (("uniform", 1, 0, True), ("amr_every_step_global", 1, 1, False),
+                  ("amr_every_4_global", 1, 4, False), ("amr_every_step_subcycle", 2, 1, False),
+                  ("amr_every_4_subcycle", 2, 4, False))
+    out = {}
+    for name, mode, every, uniform in strategies:
+        for rep in range(2):                      # the first run warms up
+            ctx, bufs, ghost, dt = make(mode, uniform)
+            nu = torch.zeros_like(dt)
+            st = torch.zeros(1, dtype=torch.int32, device="cuda")
+            span = dt.item() * (math.ldexp(1.0, -lmin) if mode == 2 else 1.0)
+            steps = int(math.ceil(T / span - 1e-9))
+            sums = torch.zeros(1, dtype=torch.float64, device="cuda")
+            ctx.conservation_sums(bufs[0][:ctx.state_elems()], sums)
+            m0 = sums.item()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            which, cells = ctx.run(bufs[0], bufs[1], ghost, steps, 0, every, 0, thr, lmin,
+                                   lmax, dt, nu, st, fused=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        qf = bufs[which][:ctx.state_elems()]
+        ctx.conservation_sums(qf, sums)
+        status = int(st.item())
+        out[name] = {"seconds": el, "steps": steps, "sim_time": ctx.sim_time(),
+                     "cell_updates": cells, "rate": cells / el,
+                     "patches_last": ctx.num_patches(), "l1_error": exact_l1(ctx, qf),
+                     "mass_rel_change": sums.item() / m0 - 1.0, "status": status,
+                     "status_bits": status_bits([status])}
+    base = out["uniform"]["seconds"]
+    for name in out:
+        out[name]["speedup_vs_uniform"] = base / out[name]["seconds"]
     return out
 
 
@@ -737,19 +827,24 @@ def main():
     if args.only in ("subcycle", "all"):
         res["subcycle"] = run_time_stepping()
         print(f"# time stepping: {res['subcycle']}", file=sys.stderr, flush=True)
+    if args.only in ("meshing", "all"):
+        res["meshing"] = run_meshing()
+        print(f"# meshing strategies: {res['meshing']}", file=sys.stderr, flush=True)
     if args.only in ("mlp", "all"):
         res["mlp"] = run_mlp()
         print(f"# mlp: {res['mlp']}", file=sys.stderr, flush=True)
     # timed legs whose status words carry a bit that marks a wrong step
     bad = {k: r.get("status_bits") for k, r in res.items()
            if isinstance(r, dict) and (int(r.get("status", 0)) & BAD_BITS or r.get("status_bad"))}
-    for k, r in res.get("subcycle", {}).items():
-        if r["status"] & BAD_BITS:
-            bad["subcycle/" + k] = r["status_bits"]
+    for leg in ("subcycle", "meshing"):
+        for k, r in res.get(leg, {}).items():
+            if r["status"] & BAD_BITS:
+                bad[leg + "/" + k] = r["status_bits"]
     head = res.get("fp32") or res.get("fp64") or res.get("large32")
     if head is None:
         print(json.dumps({k: res.get(k) for k in ("batch", "batch64", "sphere", "sphere64",
-                                                  "subcycle", "mlp") if k in res}), flush=True)
+                                                  "subcycle", "meshing", "mlp") if k in res}),
+              flush=True)
         sys.exit(3 if bad else 0)
     steps = args.steps if "fp32" in res or "fp64" in res else args.large_steps
     bytes_per_cell = 24.0 if head is not res.get("fp64") else 48.0
@@ -868,6 +963,12 @@ def main():
         out["time_stepping"] = dict(res["subcycle"], workload=(
             ADAPTIVE + ", FP32; global dt (fused or plain steps) against per-level dt "
             "(sub-cycled, plain launches), each from t = 0"))
+    if "meshing" in res:
+        out["meshing_strategies"] = dict(res["meshing"], workload=(
+            "the paper's advection example on one GPU with a stand-in flow (its swirl "
+            "field is not given): 0/1 disk carried by a = (1, 1/2) on the periodic unit "
+            "square, m = 8, levels 3-8 (uniform: level 8), max - min > 1/2 refines, "
+            "CFL 0.9, FP32, to t = 0.25"))
     if "mlp" in res:
         out["learned_tagging_mlp"] = res["mlp"]
     if not args.no_cpu_baseline and "fp32" in res:
