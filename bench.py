@@ -59,7 +59,7 @@ def parse():
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("step.hpp", "device.hpp"):
+    for f in ("step.hpp", "advect.hpp", "batch.hpp", "device.hpp"):
         with open(os.path.join(ROOT, "paper_1308_1472_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]

@@ -83,7 +83,8 @@ typedef struct {
   int32_t tile;        /* cells per LDS tile side: 8 or 16 (0 = default) */
   int32_t threads;     /* threads per tile workgroup: T*T or 2*T*T
                           (0 = default: 512 for FP64 16 x 16 tiles, else
-                          T*T)                                              */
+                          T*T); advection tiles ignore it: one
+                          wavefront per tile, four tiles per workgroup   */
   int32_t redo;        /* CFL rule (LeVeque 2002, Sec. 4.4; Clawpack's
                           time-step control): 1 = an attempt whose largest
                           Courant number exceeds cfl_max is rejected and
@@ -345,9 +346,10 @@ int64_t fcx_batch_state_offset(const fcx_batch *batch, int32_t f);
 int64_t fcx_batch_num_patches(const fcx_batch *batch);
 
 /* Tunables (chosen by the autotuner): tile of forests with m >= 16 (8 or
- * 16), threads per 8 x 8 tile (64 or 128) and per 16 x 16 tile (256 or 512),
- * launch form (0: a workgroup per tile; 1: persistent).  Drops any captured
- * graph. */
+ * 16), threads per 8 x 8 tile (64 or 128) and per 16 x 16 tile (256 or 512;
+ * advection tiles run one wavefront each whatever these say), launch form
+ * (0: a workgroup per tile, or per four advection tiles; 1: persistent).
+ * Drops any captured graph. */
 int fcx_batch_set_tuning(fcx_batch *batch, int32_t tile_big, int32_t threads8,
                          int32_t threads16, int32_t persistent);
 

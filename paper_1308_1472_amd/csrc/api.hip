@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "advect.hpp"
 #include "aux_kernels.hpp"
 #include "batch.hpp"
 #include "forest.hpp"
@@ -648,8 +649,17 @@ static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
   a.ntiles = int32_t(c->cur.P * tps * tps);
   a.ph = kphys(c);
   a.order = c->cur.order;
-  hipLaunchKernelGGL((k_step<R, PHYS, T, NT, FUSED>), dim3(unsigned(a.ntiles)),
-                     dim3(NT), 0, s, a);
+  if constexpr (PHYS == FCX_ADVECTION) {
+    // advection tiles: one wavefront each, kAdvWaves per workgroup
+    const dim3 grid(unsigned((a.ntiles + kAdvWaves - 1) / kAdvWaves));
+    if (c->cfg.limiter == 4 && c->cfg.transverse == 2)
+      hipLaunchKernelGGL((k_adv_step<R, T, FUSED, 1>), grid, dim3(64 * kAdvWaves), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_adv_step<R, T, FUSED, 0>), grid, dim3(64 * kAdvWaves), 0, s, a);
+  } else {
+    hipLaunchKernelGGL((k_step<R, PHYS, T, NT, FUSED>), dim3(unsigned(a.ntiles)),
+                       dim3(NT), 0, s, a);
+  }
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -1056,7 +1066,8 @@ struct fcx_batch {
   int32_t* phislot = nullptr;
   int32_t* pforest = nullptr;
   ForestDev* forests = nullptr;
-  uint32_t* items = nullptr;
+  BatchItem* items = nullptr;
+  AdvItem* advitems = nullptr;        // [item index], advection classes only
   int32_t* range = nullptr;           // [class][9]: item range of each XCD
   RefluxItem* reflux = nullptr;
   int32_t* reflux_forest = nullptr;
@@ -1064,6 +1075,8 @@ struct fcx_batch {
   int32_t n_reflux_x = 0, n_reflux_y = 0;
   // work classes: 8 x 8 or large tiles, times advection or shallow water
   int32_t nitems[4] = {0, 0, 0, 0}, item0[4] = {0, 0, 0, 0};
+  int32_t nsimple[4] = {0, 0, 0, 0};  // advection classes: simple-halo items first
+  bool mc2[4] = {true, true, true, true};  // every forest: MC limiter, transverse 2
   DevBuf<uint8_t> phi;
   DevBuf<double> partial;
   DevBuf<int32_t> counters, err;    // counters: persistent launches; err: per forest
@@ -1088,8 +1101,9 @@ static int batch_build(fcx_batch* b) {
   std::vector<int32_t> phislot, pforest, first(1, 0);
   std::vector<RefluxItem> rx, ry;
   std::vector<int32_t> rfx, rfy;
-  std::vector<uint32_t> items[4];
+  std::vector<BatchItem> items[4];
   int64_t phi_elems = 0, slot_base = 0;
+  for (int k = 0; k < 4; ++k) b->mc2[k] = true;
   b->fh.clear();
   b->state_off.clear();
   int64_t sbase = 0, pbase = 0;
@@ -1121,10 +1135,13 @@ static int batch_build(fcx_batch* b) {
       pforest.push_back(f);
       const int T = F.m == 8 ? 8 : b->tile_big;
       const int cls = (T == 8 ? 0 : 2) + (F.physics == FCX_SHALLOW ? 1 : 0);
+      if (c->cfg.limiter != 4 || c->cfg.transverse != 2) b->mc2[cls] = false;
       const int tps = F.m / T;
-      for (int t = 0; t < tps * tps; ++t) {
-        items[cls].push_back((uint32_t(pbase + p) << 4) | uint32_t(t));
-      }
+      const int64_t qoff = sbase + p * F.meqn * F.m * F.m;
+      for (int t = 0; t < tps * tps; ++t)
+        items[cls].push_back(BatchItem{int32_t(pbase + p), uint32_t(qoff), phislot.back(),
+                                       (t % tps) | ((t / tps) << 4) | (F.lm << 8) |
+                                           (f << 12)});
     }
     for (auto it : plan.reflux) {
       it.coarse += int32_t(pbase);
@@ -1138,8 +1155,12 @@ static int batch_build(fcx_batch* b) {
     pbase += P;
     first.push_back(int32_t(pbase));
   }
-  if (sbase >= (int64_t(1) << 31) || pbase >= (int64_t(1) << 27))
-    return fail(FCX_EINVAL, "batch too large");
+  // 32-bit element offsets: every forest's patches are addressed as
+  // (global patch id) x (patch size) from a shifted base
+  bool fits = sbase < (int64_t(1) << 31) && pbase < (int64_t(1) << 27);
+  for (const ForestDev& F : b->fh)
+    fits = fits && int64_t(pbase) * F.meqn * F.m * F.m < (int64_t(1) << 31);
+  if (!fits) return fail(FCX_EINVAL, "batch too large");
   b->P = pbase;
   b->state_elems = sbase;
   b->n_reflux_x = int32_t(rx.size());
@@ -1149,9 +1170,17 @@ static int batch_build(fcx_batch* b) {
   // the items of the four classes, one after the other; for persistent
   // launches each class is cut into eight equal runs, one per XCD (the
   // items of a class cost the same)
-  std::vector<uint32_t> all;
+  std::vector<BatchItem> all;
   std::vector<int32_t> ranges(4 * 9, 0);
   for (int cls = 0; cls < 4; ++cls) {
+    if (cls == 0 || cls == 2) {
+      // advection: the tiles of simple-halo patches first (own launch)
+      auto simple = [&](const BatchItem& it) {
+        return (recs[size_t(it.patch)].flags & kSimpleHalo) != 0;
+      };
+      std::stable_partition(items[cls].begin(), items[cls].end(), simple);
+      b->nsimple[cls] = int32_t(std::count_if(items[cls].begin(), items[cls].end(), simple));
+    }
     b->item0[cls] = int32_t(all.size());
     b->nitems[cls] = int32_t(items[cls].size());
     for (int x = 0; x <= 8; ++x)
@@ -1159,17 +1188,40 @@ static int batch_build(fcx_batch* b) {
           b->item0[cls] + int32_t(int64_t(b->nitems[cls]) * x / 8);
     all.insert(all.end(), items[cls].begin(), items[cls].end());
   }
+  // advection items with their tiles' halo offsets (simple-halo patches;
+  // the mirror of each axis is the sign of the velocity in the precision
+  // the kernels compute in)
+  std::vector<AdvItem> adv(all.size());
+  for (int cls = 0; cls < 4; cls += 2) {
+    for (int32_t k = b->item0[cls]; k < b->item0[cls] + b->nitems[cls]; ++k) {
+      const BatchItem& it = all[size_t(k)];
+      const ForestDev& F = b->fh[size_t(it.forest())];
+      const PatchRec& r = recs[size_t(it.patch)];
+      AdvItem& a = adv[size_t(k)];
+      a.h = it;
+      a.pad = 0;
+      a.halo = AdvHalo{};
+      if (!(r.flags & kSimpleHalo)) continue;
+      const bool mx = b->precision == 64 ? F.ph.ax < 0.0 : float(F.ph.ax) < 0.0f;
+      const bool my = b->precision == 64 ? F.ph.ay < 0.0 : float(F.ph.ay) < 0.0f;
+      const int T = F.m == 8 ? 8 : b->tile_big;
+      a.halo = adv_halo_offsets(T, F.m, F.lm, it.patch, it.tx(), it.ty(), mx, my, r.flags,
+                                r.nbr);
+    }
+  }
   // one packed upload
-  const size_t sz[9] = {recs.size() * sizeof(PatchRec), phislot.size() * 4,
-                        pforest.size() * 4, b->fh.size() * sizeof(ForestDev),
-                        all.size() * 4, rx.size() * sizeof(RefluxItem),
-                        rfx.size() * 4, first.size() * 4, ranges.size() * 4};
-  const void* src[9] = {recs.data(), phislot.data(), pforest.data(), b->fh.data(),
-                        all.data(), rx.data(), rfx.data(), first.data(), ranges.data()};
-  size_t off[9], at = 0;
-  for (int k = 0; k < 9; ++k) { off[k] = at; at += align256(sz[k]); }
+  const size_t sz[10] = {recs.size() * sizeof(PatchRec), phislot.size() * 4,
+                         pforest.size() * 4, b->fh.size() * sizeof(ForestDev),
+                         all.size() * sizeof(BatchItem), rx.size() * sizeof(RefluxItem),
+                         rfx.size() * 4, first.size() * 4, ranges.size() * 4,
+                         adv.size() * sizeof(AdvItem)};
+  const void* src[10] = {recs.data(), phislot.data(), pforest.data(), b->fh.data(),
+                         all.data(), rx.data(), rfx.data(), first.data(), ranges.data(),
+                         adv.data()};
+  size_t off[10], at = 0;
+  for (int k = 0; k < 10; ++k) { off[k] = at; at += align256(sz[k]); }
   HIPCHK(b->staging.ensure(at));
-  for (int k = 0; k < 9; ++k)
+  for (int k = 0; k < 10; ++k)
     if (sz[k]) std::memcpy(b->staging.p + off[k], src[k], sz[k]);
   HIPCHK(b->blob.ensure(at));
   HIPCHK(hipMemcpy(b->blob.p, b->staging.p, at, hipMemcpyHostToDevice));
@@ -1178,7 +1230,8 @@ static int batch_build(fcx_batch* b) {
   b->phislot = reinterpret_cast<int32_t*>(d + off[1]);
   b->pforest = reinterpret_cast<int32_t*>(d + off[2]);
   b->forests = reinterpret_cast<ForestDev*>(d + off[3]);
-  b->items = reinterpret_cast<uint32_t*>(d + off[4]);
+  b->items = reinterpret_cast<BatchItem*>(d + off[4]);
+  b->advitems = reinterpret_cast<AdvItem*>(d + off[9]);
   b->reflux = reinterpret_cast<RefluxItem*>(d + off[5]);
   b->reflux_forest = reinterpret_cast<int32_t*>(d + off[6]);
   b->first = reinterpret_cast<int32_t*>(d + off[7]);
@@ -1192,6 +1245,7 @@ static int batch_build(fcx_batch* b) {
 
 int fcx_batch_create(int32_t n, fcx_ctx* const* forests, fcx_batch** out) {
   if (n <= 0 || !forests || !out) return fail(FCX_EINVAL, "bad arguments");
+  if (n >= (1 << 19)) return fail(FCX_EINVAL, "too many forests in one batch");
   *out = nullptr;
   for (int f = 0; f < n; ++f) {
     if (!forests[f] || !forests[f]->have_forest)
@@ -1268,23 +1322,53 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
   B.phi = reinterpret_cast<R*>(b->phi.p);
   B.err = b->err.p;
   B.items = b->items;
+  B.advitems = b->advitems;
   B.item0 = b->item0[cls];
   B.nitems = b->nitems[cls];
   B.range = b->range + cls * 9;
   B.counters = b->counters.p + cls * 8 * kCounterStride;
+  // advection: one wavefront per item, kAdvWaves per workgroup
+  constexpr bool ADV = PHYS == FCX_ADVECTION;
+  constexpr int threads = ADV ? 64 * kAdvWaves : NT;
   if (b->persistent) {
     // about as many workgroups as the LDS lets be resident (at most one per
     // item), a multiple of 8 so that every XCD starts on its own counter;
     // any beyond residency start late, find the ranges spent and exit
-    const int lds = int(sizeof(TileLds<R, PHYS, T, NT>));
-    const int per_cu = std::max(1, std::min(160 * 1024 / (lds + 64), 32 * 64 / NT));
-    int grid = std::min(b->cus * per_cu, (b->nitems[cls] + 7) / 8 * 8);
+    const int lds = ADV ? int(kAdvWaves * sizeof(AdvLds<R, T>))
+                        : int(sizeof(TileLds<R, PHYS, T, NT>));
+    const int per_cu = std::max(1, std::min(160 * 1024 / (lds + 64), 32 * 64 / threads));
+    const int per_wg = ADV ? kAdvWaves : 1;
+    int grid = std::min(b->cus * per_cu, (b->nitems[cls] + per_wg * 8 - 1) / (per_wg * 8) * 8);
     grid = std::max(8, (grid + 7) / 8 * 8);
     // a fill kernel, not a memset: the launch may be captured into a graph
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(8 * kCounterStride), 0, s, B.counters,
                        8 * kCounterStride);
-    hipLaunchKernelGGL((k_batch_persist<R, PHYS, T, NT>), dim3(unsigned(grid)), dim3(NT), 0, s,
-                       B);
+    if constexpr (ADV)
+      hipLaunchKernelGGL((k_batch_adv_persist<R, T>), dim3(unsigned(grid)), dim3(threads), 0,
+                         s, B);
+    else
+      hipLaunchKernelGGL((k_batch_persist<R, PHYS, T, NT>), dim3(unsigned(grid)), dim3(NT), 0,
+                         s, B);
+  } else if constexpr (ADV) {
+    const int32_t ns = b->nsimple[cls], ng = b->nitems[cls] - ns;
+    const dim3 gs(unsigned((ns + kAdvWaves - 1) / kAdvWaves));
+    const dim3 gg(unsigned((ng + kAdvWaves - 1) / kAdvWaves));
+    const bool spec = b->mc2[cls];
+    if (ns > 0) {
+      B.nitems = ns;
+      if (spec)
+        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloStrips, 1>), gs, dim3(threads), 0, s, B);
+      else
+        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloStrips, 0>), gs, dim3(threads), 0, s, B);
+    }
+    if (ng > 0) {
+      B.item0 = b->item0[cls] + ns;
+      B.nitems = ng;
+      if (spec)
+        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloGeneral, 1>), gg, dim3(threads), 0, s, B);
+      else
+        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloGeneral, 0>), gg, dim3(threads), 0, s, B);
+    }
   } else {
     hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT>), dim3(unsigned(b->nitems[cls])),
                        dim3(NT), 0, s, B);
@@ -1624,8 +1708,13 @@ static void launch_step_level(fcx_ctx* c, const R* q, const R* ghost, R* qn, con
   const int tps = c->cfg.m / T;
   a.ntiles = n * tps * tps;
   a.ph = kphys(c);
-  hipLaunchKernelGGL((k_step_level<R, PHYS, T, NT>), dim3(unsigned(a.ntiles)), dim3(NT), 0, s,
-                     a, list);
+  if constexpr (PHYS == FCX_ADVECTION)
+    hipLaunchKernelGGL((k_adv_step_level<R, T>),
+                       dim3(unsigned((a.ntiles + kAdvWaves - 1) / kAdvWaves)),
+                       dim3(64 * kAdvWaves), 0, s, a, list);
+  else
+    hipLaunchKernelGGL((k_step_level<R, PHYS, T, NT>), dim3(unsigned(a.ntiles)), dim3(NT), 0,
+                       s, a, list);
 }
 
 template <typename R, int PHYS>

@@ -13,8 +13,8 @@
 // The autotuner picks the form.
 #pragma once
 
+#include "advect.hpp"
 #include "aux_kernels.hpp"
-#include "step.hpp"
 
 namespace fcx {
 
@@ -23,6 +23,29 @@ struct ForestDev {
   int32_t patch_base, slot_base, pad0, pad1;
   int64_t state_base, phi_base;            // in elements
   KPhys ph;
+};
+
+// One work item: a tile of a patch, with what its loads need (the patch's
+// state offset and size) so that they can be issued as soon as the item is
+// read; the forest's record is read beside them.
+struct alignas(16) BatchItem {
+  int32_t patch;                           // global patch id
+  uint32_t qoff;                           // patch's state offset, in elements
+  int32_t slot;                            // global face-term slot, -1: none
+  int32_t info;                            // tile column | row << 4 | log2(m) << 8
+                                           // | forest << 12
+  __device__ __host__ int tx() const { return info & 15; }
+  __device__ __host__ int ty() const { return (info >> 4) & 15; }
+  __device__ __host__ int lm() const { return (info >> 8) & 15; }
+  __device__ __host__ int forest() const { return info >> 12; }
+};
+
+// A work item of an advection class with the tile's halo offsets formed
+// when the batch is built (velocity signs and neighbours are fixed then).
+struct alignas(16) AdvItem {
+  BatchItem h;
+  AdvHalo halo;
+  int32_t pad;
 };
 
 template <typename R>
@@ -37,31 +60,33 @@ struct BatchArgs {
   const ForestDev* __restrict__ forests;
   R* phi;
   int32_t* err;                            // per forest
-  const uint32_t* __restrict__ items;      // (patch << 4) | tile
+  const BatchItem* __restrict__ items;
+  const AdvItem* __restrict__ advitems;    // the same items with halo offsets
   int32_t item0, nitems;                   // this class's items
   const int32_t* __restrict__ range;       // persistent: [9] item range of each XCD
   int32_t* counters;                       //   and [8 * kCounterStride] counters, zero at launch
 };
 
-// Step arguments of one forest, with base pointers shifted so that global
+// Step arguments of one work item: base pointers shifted so that global
 // patch ids and global phi slots index them directly.
-template <typename R>
-__device__ __forceinline__ StepArgs<R> forest_args(const BatchArgs<R>& B, int f,
-                                                   const ForestDev& F) {
+template <typename R, int MEQN>
+__device__ __forceinline__ StepArgs<R> item_args(const BatchArgs<R>& B, const BatchItem& w) {
   StepArgs<R> A;
-  const int64_t per = int64_t(F.meqn) << (2 * F.lm);
-  A.q = B.q + (F.state_base - int64_t(F.patch_base) * per);
-  A.qn = B.qn + (F.state_base - int64_t(F.patch_base) * per);
+  const int f = w.forest(), lm = w.lm(), m = 1 << lm;
+  const int64_t shift = int64_t(w.qoff) - (int64_t(w.patch) * MEQN << (2 * lm));
+  A.q = B.q + shift;
+  A.qn = B.qn + shift;
   A.ghost = nullptr;
   A.dt = B.dt + f;
   A.numax = B.numax + f;
   A.rec = B.rec;
   A.phislot = B.phislot;
-  A.phi = B.phi + (F.phi_base - int64_t(F.slot_base) * 4 * F.m * F.meqn);
+  const ForestDev& F = B.forests[f];
+  A.phi = B.phi + (F.phi_base - int64_t(F.slot_base) * 4 * m * MEQN);
   A.err = B.err + f;
   A.P = 0;
-  A.m = F.m;
-  A.lm = F.lm;
+  A.m = m;
+  A.lm = lm;
   A.ntiles = 0;
   A.ph = F.ph;
   return A;
@@ -75,14 +100,11 @@ template <typename R, int PHYS, int T, int NT>
 __global__ void __launch_bounds__(NT)
 k_batch_step(BatchArgs<R> B) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
+  constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   const int it = B.item0 + xcd_tile(blockIdx.x, B.nitems);
-  const uint32_t w = B.items[it];
-  const int p = int(w >> 4), tile = int(w & 15);
-  const int f = B.pforest[p];
-  const ForestDev F = B.forests[f];
-  const StepArgs<R> A = forest_args(B, f, F);
-  const int tps = F.m / T;
-  tile_step<R, PHYS, T, NT, true>(A, p, tile % tps, tile / tps, lds);
+  const BatchItem w = B.items[it];
+  const StepArgs<R> A = item_args<R, MEQN>(B, w);
+  tile_step<R, PHYS, T, NT, true>(A, w.patch, w.tx(), w.ty(), lds);
 }
 
 // Persistent launch over the work items of one class.  Thread 0 takes items
@@ -115,18 +137,73 @@ k_batch_persist(BatchArgs<R> B) {
     if (it < 0) break;
     int ticket = 0;
     if (threadIdx.x == 0 && tries < 8) ticket = atomicAdd(&B.counters[x * kCounterStride], 1);
-    const uint32_t w = __builtin_amdgcn_readfirstlane(B.items[it]);
-    const int p = int(w >> 4), tile = int(w & 15);
-    const int f = __builtin_amdgcn_readfirstlane(B.pforest[p]);
-    const ForestDev F = B.forests[f];
-    const StepArgs<R> A = forest_args(B, f, F);
-    const int tps = F.m / T;
+    BatchItem w;
+    w.patch = __builtin_amdgcn_readfirstlane(B.items[it].patch);
+    w.qoff = __builtin_amdgcn_readfirstlane(B.items[it].qoff);
+    w.slot = __builtin_amdgcn_readfirstlane(B.items[it].slot);
+    w.info = __builtin_amdgcn_readfirstlane(B.items[it].info);
+    const StepArgs<R> A = item_args<R, PhysTraits<PHYS>::MEQN>(B, w);
     int tid = int(threadIdx.x);
     asm volatile("" : "+v"(tid));
-    tile_step<R, PHYS, T, NT, true>(A, p, tile % tps, tile / tps, lds, tid);
+    tile_step<R, PHYS, T, NT, true>(A, w.patch, w.tx(), w.ty(), lds, tid);
     __syncthreads();                     // item_sh and the tile's LDS are free
     if (threadIdx.x == 0) item_sh = tries < 8 ? resolve(ticket) : -1;
     __syncthreads();
+  }
+}
+
+// Advection: one wavefront per work item, kAdvWaves items per workgroup.
+// The items of a class are ordered patches with a simple halo first; the
+// two runs are separate launches (HALO kHaloStrips, kHaloGeneral), so that
+// the simple tiles' kernel carries none of the general gather.  SPEC: 1 when
+// every forest of the class uses the MC limiter and transverse mode 2
+// (fixed when compiling), else 0.
+template <typename R, int T, int HALO, int SPEC>
+__global__ void __launch_bounds__(64 * kAdvWaves, 8)
+k_batch_adv(BatchArgs<R> B) {
+  __shared__ AdvLds<R, T> lds[kAdvWaves];
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int k = adv_slot(B.nitems, wv);
+  if (k >= B.nitems) return;
+  const AdvItem& ai = B.advitems[B.item0 + k];
+  const BatchItem w = ai.h;
+  const StepArgs<R> A = item_args<R, 1>(B, w);
+  adv_tile_step<R, T, HALO, SPEC ? 4 : -1, SPEC ? 2 : -1>(
+      A, w.patch, w.slot, w.tx(), w.ty(), lds[wv], int(threadIdx.x) & 63,
+      HALO == kHaloStrips ? &ai.halo : nullptr);
+}
+
+// Persistent form: every wavefront takes items on its own, through the
+// counter of its XCD (stealing from the other XCDs' ranges once its own is
+// spent), until every range is spent.
+template <typename R, int T>
+__global__ void __launch_bounds__(64 * kAdvWaves, 8)
+k_batch_adv_persist(BatchArgs<R> B) {
+  __shared__ AdvLds<R, T> lds[kAdvWaves];
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
+  const int lane = int(threadIdx.x) & 63;
+  int x = blockIdx.x & 7, tries = 0;
+  for (;;) {
+    int it = -1;
+    while (tries < 8) {
+      int k = 0;
+      if (lane == 0) k = atomicAdd(&B.counters[x * kCounterStride], 1);
+      k = __builtin_amdgcn_readfirstlane(k);
+      if (B.range[x] + k < B.range[x + 1]) { it = B.range[x] + k; break; }
+      ++tries;
+      x = (x + 1) & 7;
+    }
+    if (it < 0) break;
+    BatchItem w;
+    w.patch = __builtin_amdgcn_readfirstlane(B.items[it].patch);
+    w.qoff = __builtin_amdgcn_readfirstlane(B.items[it].qoff);
+    w.slot = __builtin_amdgcn_readfirstlane(B.items[it].slot);
+    w.info = __builtin_amdgcn_readfirstlane(B.items[it].info);
+    const StepArgs<R> A = item_args<R, 1>(B, w);
+    int l = lane;
+    asm volatile("" : "+v"(l));
+    adv_tile_step<R, T, kHaloAny>(A, w.patch, w.slot, w.tx(), w.ty(), lds[wv], l);
+    wave_sync();                           // the tile's LDS is free
   }
 }
 

@@ -22,6 +22,15 @@ __device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float rsq_(float x) { return __builtin_amdgcn_rsqf(x); }
 
+// LDS written by some lanes of a wavefront and read by others (a
+// wavefront's LDS accesses are performed in program order; the fences keep
+// the compiler from moving them across).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // error bits raised by kernels
 constexpr int32_t kErrNegDepth = 2;
 constexpr int32_t kErrNested = 4;
@@ -65,7 +74,7 @@ __device__ __forceinline__ void read_interior(const R* __restrict__ q, int m,
 // Mirror (i, j) across the physical walls of a patch: xi walls first, then
 // eta walls; a reflecting wall flips the normal momentum, an extrapolation
 // wall repeats the first interior cell.
-__device__ __forceinline__ void resolve_walls(int32_t flags, int m, int& i,
+__host__ __device__ __forceinline__ void resolve_walls(int32_t flags, int m, int& i,
                                               int& j, bool& negx, bool& negy) {
   if (i < 1 && (flags & 1)) {
     if (flags & 16) i = 1; else { i = 1 - i; negx = !negx; }

@@ -100,6 +100,27 @@ __device__ __forceinline__ void simple_halo(const R* __restrict__ q,
   }
 }
 
+// Value of frame cell (i, j) of patch p outside its interior: gathered from
+// the neighbours' interiors (fused path) or read from the ghost buffer.
+template <typename R, int MEQN, int PHYS, bool FUSED>
+__device__ __forceinline__ void halo_value(const StepArgs<R>& A, const PatchRec& rp,
+                                           bool simple, int p, int i, int j,
+                                           R (&v)[MEQN]) {
+  if (FUSED) {
+    if (simple) {
+      simple_halo<R, MEQN, PHYS>(A.q, rp, A.m, A.lm, p, i, j, v);
+    } else {
+      GhostView<R, MEQN> gv{A.q, A.rec, A.m, A.lm, A.err};
+      frame_value<R, MEQN, PHYS, true>(gv, p, i, j, v);
+    }
+  } else {
+    const int G = 8 * A.m + 16;
+    const uint32_t o = uint32_t(p) * MEQN * G + ghost_index(A.m, i, j);
+#pragma unroll
+    for (int k = 0; k < MEQN; ++k) v[k] = A.ghost[o + uint32_t(k) * G];
+  }
+}
+
 // LDS layout of one tile update (carved from a caller-provided buffer so that
 // kernels handling several physics share one allocation).
 template <typename R, int PHYS, int T, int NT>
@@ -214,18 +235,8 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
       const uint32_t o = pbase + (uint32_t(j - 1) << lm) + (i - 1);
 #pragma unroll
       for (int k = 0; k < MEQN; ++k) v[k] = A.q[o + (uint32_t(k) << (2 * lm))];
-    } else if (FUSED) {
-      if (simple) {
-        simple_halo<R, MEQN, PHYS>(A.q, rp, m, lm, p, i, j, v);
-      } else {
-        GhostView<R, MEQN> gv{A.q, A.rec, m, lm, A.err};
-        frame_value<R, MEQN, PHYS, true>(gv, p, i, j, v);
-      }
     } else {
-      const int G = 8 * m + 16;
-      const uint32_t o = uint32_t(p) * MEQN * G + ghost_index(m, i, j);
-#pragma unroll
-      for (int k = 0; k < MEQN; ++k) v[k] = A.ghost[o + uint32_t(k) * G];
+      halo_value<R, MEQN, PHYS, FUSED>(A, rp, simple, p, i, j, v);
     }
     stage((cj + 1) * F + (ci + 1), v);
   }
