@@ -91,17 +91,6 @@ struct AdvLds {
   EdgePQ<R> y0[T + 1];                      // y-edges 1..T+1 of column 0
 };
 
-// min / max of two finite values: one v_med3 in FP32 (a median with an
-// infinity), without the NaN-quieting fmin / fmax need
-__device__ __forceinline__ float min_(float a, float b) {
-  return __builtin_amdgcn_fmed3f(a, b, -__builtin_inff());
-}
-__device__ __forceinline__ float max_(float a, float b) {
-  return __builtin_amdgcn_fmed3f(a, b, __builtin_inff());
-}
-__device__ __forceinline__ double min_(double a, double b) { return fmin(a, b); }
-__device__ __forceinline__ double max_(double a, double b) { return fmax(a, b); }
-
 // phi(theta) w for theta = wu / w, limiter `lim` (0 none, 1 minmod,
 // 2 superbee, 3 van Leer, else MC); zero where w wu <= 0 (theta <= 0).
 template <typename R>
@@ -455,7 +444,7 @@ k_adv_step(StepArgs<R> A) {
 
 // One wavefront per tile of the patches in `list` (one level of a
 // sub-cycled step); plain path.
-template <typename R, int T>
+template <typename R, int T, int SPEC>
 __global__ void __launch_bounds__(64 * kAdvWaves, 8)
 k_adv_step_level(StepArgs<R> A, const int32_t* __restrict__ list) {
   __shared__ AdvLds<R, T> lds[kAdvWaves];
@@ -465,8 +454,8 @@ k_adv_step_level(StepArgs<R> A, const int32_t* __restrict__ list) {
   const int tps = A.m / T;
   const int p = list[t / (tps * tps)];
   const int tile = t % (tps * tps);
-  adv_tile_step<R, T, kHaloGhostBuf>(A, p, A.phislot[p], tile % tps, tile / tps, lds[wv],
-                                     int(threadIdx.x) & 63);
+  adv_tile_step<R, T, kHaloGhostBuf, SPEC ? 4 : -1, SPEC ? 2 : -1>(
+      A, p, A.phislot[p], tile % tps, tile / tps, lds[wv], int(threadIdx.x) & 63);
 }
 
 }  // namespace fcx

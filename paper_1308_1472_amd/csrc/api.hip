@@ -656,8 +656,11 @@ static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
       hipLaunchKernelGGL((k_adv_step<R, T, FUSED, 1>), grid, dim3(64 * kAdvWaves), 0, s, a);
     else
       hipLaunchKernelGGL((k_adv_step<R, T, FUSED, 0>), grid, dim3(64 * kAdvWaves), 0, s, a);
+  } else if (c->cfg.limiter == 4 && c->cfg.transverse == 2) {
+    hipLaunchKernelGGL((k_step<R, PHYS, T, NT, FUSED, 1>), dim3(unsigned(a.ntiles)),
+                       dim3(NT), 0, s, a);
   } else {
-    hipLaunchKernelGGL((k_step<R, PHYS, T, NT, FUSED>), dim3(unsigned(a.ntiles)),
+    hipLaunchKernelGGL((k_step<R, PHYS, T, NT, FUSED, 0>), dim3(unsigned(a.ntiles)),
                        dim3(NT), 0, s, a);
   }
   HIPCHK(hipGetLastError());
@@ -1343,12 +1346,20 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
     // a fill kernel, not a memset: the launch may be captured into a graph
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(8 * kCounterStride), 0, s, B.counters,
                        8 * kCounterStride);
-    if constexpr (ADV)
-      hipLaunchKernelGGL((k_batch_adv_persist<R, T>), dim3(unsigned(grid)), dim3(threads), 0,
-                         s, B);
-    else
-      hipLaunchKernelGGL((k_batch_persist<R, PHYS, T, NT>), dim3(unsigned(grid)), dim3(NT), 0,
-                         s, B);
+    if constexpr (ADV) {
+      if (b->mc2[cls])
+        hipLaunchKernelGGL((k_batch_adv_persist<R, T, 1>), dim3(unsigned(grid)),
+                           dim3(threads), 0, s, B);
+      else
+        hipLaunchKernelGGL((k_batch_adv_persist<R, T, 0>), dim3(unsigned(grid)),
+                           dim3(threads), 0, s, B);
+    } else if (b->mc2[cls]) {
+      hipLaunchKernelGGL((k_batch_persist<R, PHYS, T, NT, 1>), dim3(unsigned(grid)), dim3(NT),
+                         0, s, B);
+    } else {
+      hipLaunchKernelGGL((k_batch_persist<R, PHYS, T, NT, 0>), dim3(unsigned(grid)), dim3(NT),
+                         0, s, B);
+    }
   } else if constexpr (ADV) {
     const int32_t ns = b->nsimple[cls], ng = b->nitems[cls] - ns;
     const dim3 gs(unsigned((ns + kAdvWaves - 1) / kAdvWaves));
@@ -1369,8 +1380,11 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
       else
         hipLaunchKernelGGL((k_batch_adv<R, T, kHaloGeneral, 0>), gg, dim3(threads), 0, s, B);
     }
+  } else if (b->mc2[cls]) {
+    hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT, 1>), dim3(unsigned(b->nitems[cls])),
+                       dim3(NT), 0, s, B);
   } else {
-    hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT>), dim3(unsigned(b->nitems[cls])),
+    hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT, 0>), dim3(unsigned(b->nitems[cls])),
                        dim3(NT), 0, s, B);
   }
   HIPCHK(hipGetLastError());
@@ -1708,13 +1722,24 @@ static void launch_step_level(fcx_ctx* c, const R* q, const R* ghost, R* qn, con
   const int tps = c->cfg.m / T;
   a.ntiles = n * tps * tps;
   a.ph = kphys(c);
-  if constexpr (PHYS == FCX_ADVECTION)
-    hipLaunchKernelGGL((k_adv_step_level<R, T>),
-                       dim3(unsigned((a.ntiles + kAdvWaves - 1) / kAdvWaves)),
-                       dim3(64 * kAdvWaves), 0, s, a, list);
-  else
-    hipLaunchKernelGGL((k_step_level<R, PHYS, T, NT>), dim3(unsigned(a.ntiles)), dim3(NT), 0,
-                       s, a, list);
+  // the limiter and transverse mode fixed when compiling exactly where the
+  // global-dt step fixes them (the two then round alike)
+  const bool spec = c->cfg.limiter == 4 && c->cfg.transverse == 2;
+  const dim3 agrid(unsigned((a.ntiles + kAdvWaves - 1) / kAdvWaves));
+  if constexpr (PHYS == FCX_ADVECTION) {
+    if (spec)
+      hipLaunchKernelGGL((k_adv_step_level<R, T, 1>), agrid, dim3(64 * kAdvWaves), 0, s, a,
+                         list);
+    else
+      hipLaunchKernelGGL((k_adv_step_level<R, T, 0>), agrid, dim3(64 * kAdvWaves), 0, s, a,
+                         list);
+  } else if (spec) {
+    hipLaunchKernelGGL((k_step_level<R, PHYS, T, NT, 1>), dim3(unsigned(a.ntiles)), dim3(NT),
+                       0, s, a, list);
+  } else {
+    hipLaunchKernelGGL((k_step_level<R, PHYS, T, NT, 0>), dim3(unsigned(a.ntiles)), dim3(NT),
+                       0, s, a, list);
+  }
 }
 
 template <typename R, int PHYS>

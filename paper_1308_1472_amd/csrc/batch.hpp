@@ -96,7 +96,7 @@ __device__ __forceinline__ StepArgs<R> item_args(const BatchArgs<R>& B, const Ba
 constexpr int kCounterStride = 32;
 
 // One workgroup per work item of one class (tile size and physics).
-template <typename R, int PHYS, int T, int NT>
+template <typename R, int PHYS, int T, int NT, int SPEC>
 __global__ void __launch_bounds__(NT)
 k_batch_step(BatchArgs<R> B) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
@@ -104,7 +104,7 @@ k_batch_step(BatchArgs<R> B) {
   const int it = B.item0 + xcd_tile(blockIdx.x, B.nitems);
   const BatchItem w = B.items[it];
   const StepArgs<R> A = item_args<R, MEQN>(B, w);
-  tile_step<R, PHYS, T, NT, true>(A, w.patch, w.tx(), w.ty(), lds);
+  tile_step<R, PHYS, T, NT, true, SPEC>(A, w.patch, w.tx(), w.ty(), lds);
 }
 
 // Persistent launch over the work items of one class.  Thread 0 takes items
@@ -114,7 +114,7 @@ k_batch_step(BatchArgs<R> B) {
 // index is hidden from the optimizer per item: otherwise the index arithmetic
 // derived from it is hoisted out of the loop and held in registers across
 // tiles (128 registers per thread under a four-wave cap, against 87 so).
-template <typename R, int PHYS, int T, int NT>
+template <typename R, int PHYS, int T, int NT, int SPEC>
 __global__ void __launch_bounds__(NT)
 k_batch_persist(BatchArgs<R> B) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
@@ -145,7 +145,7 @@ k_batch_persist(BatchArgs<R> B) {
     const StepArgs<R> A = item_args<R, PhysTraits<PHYS>::MEQN>(B, w);
     int tid = int(threadIdx.x);
     asm volatile("" : "+v"(tid));
-    tile_step<R, PHYS, T, NT, true>(A, w.patch, w.tx(), w.ty(), lds, tid);
+    tile_step<R, PHYS, T, NT, true, SPEC>(A, w.patch, w.tx(), w.ty(), lds, tid);
     __syncthreads();                     // item_sh and the tile's LDS are free
     if (threadIdx.x == 0) item_sh = tries < 8 ? resolve(ticket) : -1;
     __syncthreads();
@@ -176,7 +176,7 @@ k_batch_adv(BatchArgs<R> B) {
 // Persistent form: every wavefront takes items on its own, through the
 // counter of its XCD (stealing from the other XCDs' ranges once its own is
 // spent), until every range is spent.
-template <typename R, int T>
+template <typename R, int T, int SPEC>
 __global__ void __launch_bounds__(64 * kAdvWaves, 8)
 k_batch_adv_persist(BatchArgs<R> B) {
   __shared__ AdvLds<R, T> lds[kAdvWaves];
@@ -202,7 +202,8 @@ k_batch_adv_persist(BatchArgs<R> B) {
     const StepArgs<R> A = item_args<R, 1>(B, w);
     int l = lane;
     asm volatile("" : "+v"(l));
-    adv_tile_step<R, T, kHaloAny>(A, w.patch, w.slot, w.tx(), w.ty(), lds[wv], l);
+    adv_tile_step<R, T, kHaloAny, SPEC ? 4 : -1, SPEC ? 2 : -1>(A, w.patch, w.slot, w.tx(),
+                                                               w.ty(), lds[wv], l);
     wave_sync();                           // the tile's LDS is free
   }
 }

@@ -49,14 +49,25 @@ struct StepArgs {
 template <int T> struct TileThreads { static constexpr int value = T * T >= 256 ? 256 : T * T; };
 
 
+// min / max of two finite values: one v_med3 in FP32 (a median with an
+// infinity), without the NaN-quieting fmin / fmax need
+__device__ __forceinline__ float min_(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, -__builtin_inff());
+}
+__device__ __forceinline__ float max_(float a, float b) {
+  return __builtin_amdgcn_fmed3f(a, b, __builtin_inff());
+}
+__device__ __forceinline__ double min_(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ double max_(double a, double b) { return fmax(a, b); }
+
 template <typename R>
 __device__ __forceinline__ R limiter_phi(int lim, R th) {
   switch (lim) {
     case 0: return R(1);
-    case 1: return fmax(R(0), fmin(R(1), th));
-    case 2: return fmax(R(0), fmax(fmin(R(1), R(2) * th), fmin(R(2), th)));
+    case 1: return max_(R(0), min_(R(1), th));
+    case 2: return max_(R(0), max_(min_(R(1), R(2) * th), min_(R(2), th)));
     case 3: return (th + fabs(th)) * rcp_(R(1) + fabs(th));
-    default: return fmax(R(0), fmin(fmin(R(0.5) * (R(1) + th), R(2)), R(2) * th));
+    default: return max_(R(0), min_(min_(R(0.5) * (R(1) + th), R(2)), R(2) * th));
   }
 }
 
@@ -143,10 +154,12 @@ struct TileLds {
   double red[NT / 64 > 0 ? NT / 64 : 1];
 };
 
-template <typename R, int PHYS, int T, int NT, bool FUSED>
 // tid_in: the thread's index when the caller has hidden it from the
 // optimizer (a loop over tiles then recomputes what depends on it per tile
 // rather than keeping it in registers across tiles); -1: threadIdx.x.
+// SPEC: 1 fixes the MC limiter and transverse mode 2 when compiling; 0
+// takes the forest's at run time.
+template <typename R, int PHYS, int T, int NT, bool FUSED, int SPEC = 0>
 __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, int ty,
                                           TileLds<R, PHYS, T, NT>& L, int tid_in = -1) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
@@ -250,7 +263,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
   // largest |speed| over interior edges; the Courant number is formed once
   // at the end (monotone rounding: the same as the largest product)
   R smax = R(0);
-  const int lim = A.ph.limiter, trans = A.ph.transverse;
+  const int lim = SPEC ? 4 : A.ph.limiter, trans = SPEC ? 2 : A.ph.transverse;
   const R half_dtdx = R(0.5) * dtdx;
   const R ghalf = R(0.5 * A.ph.g);
 
@@ -325,10 +338,10 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
       if (PHYS == FCX_ADVECTION) {
         auto jump = [&](int ee) { return qs[0][qidx(r, ee)] - qs[0][qidx(r, ee - 1)]; };
         const R w = jump(e);
-        am[0] = fmin(an, R(0)) * w;
-        ap[0] = fmax(an, R(0)) * w;
+        am[0] = min_(an, R(0)) * w;
+        ap[0] = max_(an, R(0)) * w;
         cq[0] = R(0);
-        if (inner) smax = fmax(smax, fabs(an));
+        if (inner) smax = max_(smax, fabs(an));
         if (w != R(0)) {
           const R wu = jump(an > R(0) ? e - 1 : e + 1);
           const R th = (wu * w) * rcp_(w * w);
@@ -342,8 +355,8 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
         const R u = wb[3][b], v = wb[4][b], c = wb[5][b];
         const R a1 = wb[0][b], a2 = wb[1][b], a3 = wb[2][b];
         const R s1 = u - c, s3 = u + c;
-        const R b1m = fmin(s1, R(0)) * a1, b2m = fmin(u, R(0)) * a2, b3m = fmin(s3, R(0)) * a3;
-        const R b1p = fmax(s1, R(0)) * a1, b2p = fmax(u, R(0)) * a2, b3p = fmax(s3, R(0)) * a3;
+        const R b1m = min_(s1, R(0)) * a1, b2m = min_(u, R(0)) * a2, b3m = min_(s3, R(0)) * a3;
+        const R b1p = max_(s1, R(0)) * a1, b2p = max_(u, R(0)) * a2, b3p = max_(s3, R(0)) * a3;
         const R m0 = b1m + b3m, p0 = b1p + b3p;
         R amh[3] = {m0, b1m * s1 + b3m * s3, m0 * v + b2m};
         R aph[3] = {p0, b1p * s1 + b3p * s3, p0 * v + b2p};
@@ -373,7 +386,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
         }
         const R g13 = g[0] + g[2];
         R cqh[3] = {g13, g[0] * s1 + g[2] * s3, g13 * v + g[1]};
-        if (inner) smax = fmax(smax, fmax(fabs(s1), fabs(s3)));
+        if (inner) smax = max_(smax, max_(fabs(s1), fabs(s3)));
         am[0] = amh[0]; am[mu] = amh[1]; am[mv] = amh[2];
         ap[0] = aph[0]; ap[mu] = aph[1]; ap[mv] = aph[2];
         cq[0] = cqh[0]; cq[mu] = cqh[1]; cq[mv] = cqh[2];
@@ -391,7 +404,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
           apt[k] = ap[k] - (trans == 2 ? cq[k] : R(0));
         }
         if (PHYS == FCX_ADVECTION) {
-          const R bm = -half_dtdx * fmin(at, R(0)), bp = -half_dtdx * fmax(at, R(0));
+          const R bm = -half_dtdx * min_(at, R(0)), bp = -half_dtdx * max_(at, R(0));
           ldn[0] = bm * amt[0];
           lup[0] = bp * amt[0];
           rdn[0] = bm * apt[0];
@@ -400,10 +413,10 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
           const int b = bidx(r, e);
           const R u = wb[3][b], v = wb[4][b], c = wb[5][b];
           const R i2c = wb[6][b];
-          const R lmn[3] = {-half_dtdx * fmin(v - c, R(0)), -half_dtdx * fmin(v, R(0)),
-                            -half_dtdx * fmin(v + c, R(0))};
-          const R lmx[3] = {-half_dtdx * fmax(v - c, R(0)), -half_dtdx * fmax(v, R(0)),
-                            -half_dtdx * fmax(v + c, R(0))};
+          const R lmn[3] = {-half_dtdx * min_(v - c, R(0)), -half_dtdx * min_(v, R(0)),
+                            -half_dtdx * min_(v + c, R(0))};
+          const R lmx[3] = {-half_dtdx * max_(v - c, R(0)), -half_dtdx * max_(v, R(0)),
+                            -half_dtdx * max_(v + c, R(0))};
 #pragma unroll
           for (int side = 0; side < 2; ++side) {
             const R* psi = side == 0 ? amt : apt;
@@ -534,7 +547,7 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
 // One workgroup per tile, over all tiles of one forest.  With an order
 // table, each XCD's run of slots takes the patches with a general halo (the
 // costlier tiles) first, so the last tiles to be dispatched are cheap ones.
-template <typename R, int PHYS, int T, int NT, bool FUSED>
+template <typename R, int PHYS, int T, int NT, bool FUSED, int SPEC>
 __global__ void __launch_bounds__(NT)
 k_step(StepArgs<R> A) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
@@ -543,12 +556,12 @@ k_step(StepArgs<R> A) {
   const int tps = A.m / T;
   const int p = t / (tps * tps);
   const int tile = t - p * (tps * tps);
-  tile_step<R, PHYS, T, NT, FUSED>(A, p, tile % tps, tile / tps, lds);
+  tile_step<R, PHYS, T, NT, FUSED, SPEC>(A, p, tile % tps, tile / tps, lds);
 }
 
 // One workgroup per tile of the patches in `list` (one level of a
 // sub-cycled step); plain path (ghosts from the ghost buffer).
-template <typename R, int PHYS, int T, int NT>
+template <typename R, int PHYS, int T, int NT, int SPEC>
 __global__ void __launch_bounds__(NT)
 k_step_level(StepArgs<R> A, const int32_t* __restrict__ list) {
   __shared__ TileLds<R, PHYS, T, NT> lds;
@@ -556,7 +569,7 @@ k_step_level(StepArgs<R> A, const int32_t* __restrict__ list) {
   const int tps = A.m / T;
   const int p = list[t / (tps * tps)];
   const int tile = t % (tps * tps);
-  tile_step<R, PHYS, T, NT, false>(A, p, tile % tps, tile / tps, lds);
+  tile_step<R, PHYS, T, NT, false, SPEC>(A, p, tile % tps, tile / tps, lds);
 }
 
 }  // namespace fcx
