@@ -947,6 +947,17 @@ def main():
             "status_words_nonzero": rb["status_words_nonzero"],
             "status_bits": rb["status_bits"],
         }
+        prof = "k_batch_adv_fp32_16.txt"
+        if stored_profile(prof, "class_us") is not None:
+            # from the committed rocprofv3 summary (kernel times inside the
+            # graph replays are not visible to events on the stream)
+            us = stored_profile(prof, "class_us")
+            out["batched_64_forests"]["advection_16x16_class"] = {
+                "kernels": "k_batch_adv (simple halos) + k_batch_adv (general halos)",
+                "cells": stored_profile(prof, "class_cells"), "kernel_us": us,
+                "bytes_per_cell": 8.0, "hbm_frac": stored_profile(prof, "class_hbm_frac"),
+                "valu_lane_ops_per_cell": stored_profile(prof, "valu_lane_ops_per_cell"),
+                "source": "profiles/" + prof}
         if "batch64" in res:
             out["batched_64_forests"]["fp64_plain_same_forests"] = res["batch64"]
             out["batched_64_forests"]["speedup_vs_fp64_plain_same_forests"] = (
