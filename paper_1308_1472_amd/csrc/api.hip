@@ -743,8 +743,13 @@ int fcx_fused_step(fcx_ctx* c, const void* q, void* qn, const double* dt,
 
 // Workgroups that copy a rejected attempt's state (256 threads, a few
 // 16-byte units each, at most one per CU).
+// Workgroups of a launch that ends in the last-workgroup ticket (reflux +
+// next dt, next dt with redo): every one of them takes the ticket with an
+// agent-scope fence and atomic, so they are few (a rejected attempt's copy,
+// rare, then runs on fewer workgroups).
 static int64_t redo_grid(const fcx_ctx* c, int64_t n16) {
-  return std::max<int64_t>(1, std::min<int64_t>(c->cus, (n16 + 1023) / 1024));
+  (void)c;
+  return std::max<int64_t>(1, std::min<int64_t>(32, (n16 + 1023) / 1024));
 }
 
 static NextDtArgs next_args(fcx_ctx* c, double* numax, double* dt, int32_t* status,
@@ -776,7 +781,9 @@ static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
   if (n == 0 && !NEXT) return FCX_OK;
   const int64_t tot = int64_t(n) * m;
   int64_t g = std::max<int64_t>(1, (tot + 255) / 256);
-  if (NEXT && nd.redo) g = std::max(g, redo_grid(c, nd.n16));
+  // with NEXT every workgroup takes the last-workgroup ticket: a small grid
+  // (the reflux loops over its cells)
+  if (NEXT) g = std::max(std::min<int64_t>(g, 32), nd.redo ? redo_grid(c, nd.n16) : 1);
   const unsigned grid = unsigned(g);
   hipLaunchKernelGGL((k_reflux<R, PHYS, NEXT>), dim3(grid), dim3(256), 0, s,
                      static_cast<const R*>(q), static_cast<R*>(qn), c->cur.reflux,

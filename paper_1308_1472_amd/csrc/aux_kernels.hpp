@@ -251,13 +251,17 @@ k_reflux(const R* __restrict__ q, R* __restrict__ qn,
          int32_t nitems, const R* __restrict__ phi, const double* dtp, int m, KPhys ph,
          int32_t* err, NextDtArgs nd) {
   const bool rej = NEXT && rejected(nd.numax, 0, nd.cfl_max, nd.redo);
-  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (rej)
+  if (rej) {
     copy_share(reinterpret_cast<const uint4*>(q), reinterpret_cast<uint4*>(qn), nd.n16,
                blockIdx.x, gridDim.x);
-  else if (t < int64_t(nitems) * m)
-    reflux_cell<R, PHYS>(q, qn, items, aux, int32_t(t / m), int(t % m) + 1, phi, dtp, m, ph,
-                         err);
+  } else {
+    // grid-stride: with NEXT the grid is kept small (every workgroup takes
+    // the ticket)
+    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(nitems) * m;
+         t += int64_t(gridDim.x) * blockDim.x)
+      reflux_cell<R, PHYS>(q, qn, items, aux, int32_t(t / m), int(t % m) + 1, phi, dtp, m, ph,
+                           err);
+  }
   if (NEXT) {
     __shared__ bool last;
     __syncthreads();
