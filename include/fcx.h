@@ -82,9 +82,11 @@ typedef struct {
                           second-order corrections                         */
   int32_t tile;        /* cells per LDS tile side: 8 or 16 (0 = default) */
   int32_t threads;     /* threads per tile workgroup: T*T or 2*T*T
-                          (0 = default: 512 for FP64 16 x 16 tiles, else
-                          T*T); advection tiles ignore it: one
-                          wavefront per tile, four tiles per workgroup   */
+                          (0 = left to the library: 2*T*T for FP64
+                          16 x 16 tiles and for FP32 16 x 16 tiles of a
+                          forest with at most four tiles per compute
+                          unit, else T*T); advection tiles ignore it:
+                          one wavefront per tile, four per workgroup     */
   int32_t redo;        /* CFL rule (LeVeque 2002, Sec. 4.4; Clawpack's
                           time-step control): 1 = an attempt whose largest
                           Courant number exceeds cfl_max is rejected and

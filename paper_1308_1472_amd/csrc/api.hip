@@ -152,6 +152,7 @@ struct fcx_ctx {
   HostBuf run_host;                // fcx_run: pinned copies of stats
   HostBuf staging;
   int cus = 256;
+  bool threads_auto = false;         // threads per tile left to the library
   int device = 0;                  // the HIP device the context was created on
   size_t lds_per_block = 65536;    // device limit of LDS per workgroup
   Plan plan;                       // host copy of the current forest's plan
@@ -328,6 +329,7 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   c->cfg = *cfg;
   c->cfg.tile = tile;
   c->cfg.threads = threads;
+  c->threads_auto = cfg->threads == 0;
   c->tile = tile;
   c->meqn = cfg->physics == FCX_ADVECTION ? 1 : (cfg->physics == FCX_SHALLOW ? 3 : 4);
   {
@@ -629,6 +631,18 @@ int fcx_ghost_fill(fcx_ctx* c, const void* q, void* ghost, void* stream) {
             : launch_ghost<float, FCX_SHALLOW>(c, q, ghost, s);
 }
 
+// Two threads per cell of a tile: as configured, or, left to the library,
+// for FP64 16 x 16 tiles (more resident waves at their register count) and
+// for FP32 16 x 16 tiles of a forest with at most four tiles per CU (a launch
+// of one or two rounds of tiles is bound by one tile's latency, which two
+// threads per cell shorten; larger forests are bound by instructions).
+static bool wide_tiles(const fcx_ctx* c, int64_t patches) {
+  if (!c->threads_auto) return c->cfg.threads == 2 * c->tile * c->tile;
+  if (c->tile != 16) return false;
+  const int64_t tiles = patches * (c->cfg.m / 16) * (c->cfg.m / 16);
+  return c->cfg.precision == 64 || tiles <= 4 * int64_t(c->cus);
+}
+
 template <typename R, int PHYS, int T, int NT, bool FUSED>
 static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                          const double* dt, double* numax, hipStream_t s) {
@@ -670,7 +684,7 @@ static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
 template <typename R, int PHYS, bool FUSED>
 static int launch_step_m(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                          const double* dt, double* numax, hipStream_t s) {
-  const bool wide = c->cfg.threads == 2 * c->tile * c->tile;
+  const bool wide = wide_tiles(c, c->cur.P);
   if (c->tile == 8)
     return wide ? launch_step_t<R, PHYS, 8, 128, FUSED>(c, q, ghost, qn, dt, numax, s)
                 : launch_step_t<R, PHYS, 8, 64, FUSED>(c, q, ghost, qn, dt, numax, s);
@@ -1788,7 +1802,7 @@ static int subcycled_t(fcx_ctx* c, const void* q, void* qn, void* w, void* ghost
   TimeView<R> tv;
   for (int b = 0; b < 3; ++b) tv.bufs[b] = bufs[b];
   const int32_t nitems = c->cur.n_reflux_x + c->cur.n_reflux_y;
-  const bool wide = c->cfg.threads == 2 * c->tile * c->tile;
+  const bool wide = wide_tiles(c, c->cur.P);   // as the global-dt step
   R* psi = reinterpret_cast<R*>(c->psi.p);
   const R* phi = reinterpret_cast<const R*>(c->phi.p);
   int64_t cells = 0;

@@ -208,13 +208,14 @@ struct NextDtArgs {
 // at its low / high end, for an eta item the xi items there), so the result
 // does not depend on the order the threads run in; such a thread computes
 // both corrections before it updates the cell.
-template <typename R, int PHYS>
+// keep(): whether to write the corrections, asked after the loads are issued
+template <typename R, int PHYS, typename Keep>
 __device__ __forceinline__ void reflux_cell(const R* __restrict__ q, R* __restrict__ qn,
                                             const RefluxItem* __restrict__ items,
                                             const RefluxAux* __restrict__ aux, int32_t i,
                                             int tc, const R* __restrict__ phi,
                                             const double* dtp, int m, const KPhys& ph,
-                                            int32_t* err) {
+                                            int32_t* err, Keep keep) {
   constexpr int MEQN = PhysTraits<PHYS>::MEQN;
   const RefluxItem it = items[i];
   const RefluxAux ax = aux[i];
@@ -230,13 +231,15 @@ __device__ __forceinline__ void reflux_cell(const R* __restrict__ q, R* __restri
     reflux_corr<R, PHYS>(q, items[link], aux[link], it.face == 0 ? 1 : m, phi, m, ph, err,
                          c1, o1, dxc1);
   const R fac = R(*dtp / (dxc * dxc));
+  R v[MEQN];
+#pragma unroll
+  for (int k = 0; k < MEQN; ++k) v[k] = qn[o + size_t(k) * m * m];
+  if (!keep()) return;
 #pragma unroll
   for (int k = 0; k < MEQN; ++k) {
-    const size_t ok = o + size_t(k) * m * m;
-    R v = qn[ok];
-    v -= fac * c0[k];
-    if (two) v -= fac * c1[k];
-    qn[ok] = v;
+    v[k] -= fac * c0[k];
+    if (two) v[k] -= fac * c1[k];
+    qn[o + size_t(k) * m * m] = v[k];
   }
 }
 
@@ -250,18 +253,19 @@ k_reflux(const R* __restrict__ q, R* __restrict__ qn,
          const RefluxItem* __restrict__ items, const RefluxAux* __restrict__ aux,
          int32_t nitems, const R* __restrict__ phi, const double* dtp, int m, KPhys ph,
          int32_t* err, NextDtArgs nd) {
-  const bool rej = NEXT && rejected(nd.numax, 0, nd.cfl_max, nd.redo);
-  if (rej) {
+  // the CFL check's operand is loaded first and waited for only where a
+  // correction is about to be written (its latency overlaps the reflux loads)
+  const double nu = NEXT && nd.redo ? *nd.numax : 0.0;
+  auto keep = [&]() { return !(NEXT && nd.redo && nu > nd.cfl_max); };
+  // grid-stride: with NEXT the grid is kept small (every workgroup takes the
+  // ticket)
+  for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(nitems) * m;
+       t += int64_t(gridDim.x) * blockDim.x)
+    reflux_cell<R, PHYS>(q, qn, items, aux, int32_t(t / m), int(t % m) + 1, phi, dtp, m, ph,
+                         err, keep);
+  if (!keep())
     copy_share(reinterpret_cast<const uint4*>(q), reinterpret_cast<uint4*>(qn), nd.n16,
                blockIdx.x, gridDim.x);
-  } else {
-    // grid-stride: with NEXT the grid is kept small (every workgroup takes
-    // the ticket)
-    for (int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; t < int64_t(nitems) * m;
-         t += int64_t(gridDim.x) * blockDim.x)
-      reflux_cell<R, PHYS>(q, qn, items, aux, int32_t(t / m), int(t % m) + 1, phi, dtp, m, ph,
-                           err);
-  }
   if (NEXT) {
     __shared__ bool last;
     __syncthreads();
