@@ -481,8 +481,14 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   }
   HIPCHK(dev.blob.ensure(at));
   if (ordered) {
+    // a kernel reads the pinned staging (the runtime's asynchronous copy of
+    // a buffer this size kept the calling thread tens of microseconds)
     if (!c->staged) HIPCHK(hipEventCreateWithFlags(&c->staged, hipEventDisableTiming));
-    HIPCHK(hipMemcpyAsync(dev.blob.p, h, at, hipMemcpyHostToDevice, s));
+    const int64_t n16 = int64_t(at / 16);
+    hipLaunchKernelGGL(k_copy16, dim3(unsigned(std::min<int64_t>(1024, (n16 + 255) / 256))),
+                       dim3(256), 0, s, reinterpret_cast<const uint4*>(h),
+                       reinterpret_cast<uint4*>(dev.blob.p), n16);
+    HIPCHK(hipGetLastError());
     HIPCHK(hipEventRecord(c->staged, s));
     c->staged_pending = true;
   } else {
@@ -930,39 +936,49 @@ int fcx_conservation_sums_noalloc(fcx_ctx* c, const void* q, double* sums, void*
 }
 
 template <typename R, int MEQN>
+// mirror: pinned host memory that receives the final tags as well (null:
+// none); the kernels write it directly, so no copy follows them
 static int launch_tags(fcx_ctx* c, const void* q, const void* ghost, int criterion,
-                       double thr, int lmin, int lmax, int8_t* tags, hipStream_t s) {
+                       double thr, int lmin, int lmax, int8_t* tags, hipStream_t s,
+                       int8_t* mirror = nullptr) {
   const int m = c->cfg.m;
   const double* geo = c->cfg.physics == FCX_SPHERE ? c->cur.geo.p : nullptr;
   hipLaunchKernelGGL((k_tag_refine<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
                      0, s, static_cast<const R*>(q), static_cast<const R*>(ghost),
-                     c->cur.rec, m, criterion, thr, lmax, tags, geo);
+                     c->cur.rec, m, criterion, thr, lmax, tags, geo, mirror);
   HIPCHK(hipGetLastError());
   hipLaunchKernelGGL((k_tag_family<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
                      size_t(m) * m * sizeof(double) * (geo ? 4 : 1), s,
                      static_cast<const R*>(q), c->cur.rec, c->cur.family, m, criterion,
-                     thr, lmin, tags, geo);
+                     thr, lmin, tags, geo, mirror);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
 
-int fcx_regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criterion,
-                    double thr, int32_t lmin, int32_t lmax, int8_t* tags,
-                    void* stream) {
+static int regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criterion,
+                       double thr, int32_t lmin, int32_t lmax, int8_t* tags, void* stream,
+                       int8_t* mirror) {
   if (!c || !q || !tags || (criterion != 0 && criterion != 1) ||
       (criterion == 1 && !ghost))
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
+  int8_t* mi = mirror;
   if (c->meqn == 1)
-    return dp ? launch_tags<double, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
-              : launch_tags<float, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
+    return dp ? launch_tags<double, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s, mi)
+              : launch_tags<float, 1>(c, q, ghost, criterion, thr, lmin, lmax, tags, s, mi);
   if (c->meqn == 4)
-    return dp ? launch_tags<double, 4>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
-              : launch_tags<float, 4>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
-  return dp ? launch_tags<double, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s)
-            : launch_tags<float, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s);
+    return dp ? launch_tags<double, 4>(c, q, ghost, criterion, thr, lmin, lmax, tags, s, mi)
+              : launch_tags<float, 4>(c, q, ghost, criterion, thr, lmin, lmax, tags, s, mi);
+  return dp ? launch_tags<double, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s, mi)
+            : launch_tags<float, 3>(c, q, ghost, criterion, thr, lmin, lmax, tags, s, mi);
+}
+
+int fcx_regrid_tags(fcx_ctx* c, const void* q, const void* ghost, int32_t criterion,
+                    double thr, int32_t lmin, int32_t lmax, int8_t* tags,
+                    void* stream) {
+  return regrid_tags(c, q, ghost, criterion, thr, lmin, lmax, tags, stream, nullptr);
 }
 
 // old_to_new of every old leaf from the transfer plan of the new ones
@@ -1885,10 +1901,12 @@ int fcx_regrid(fcx_ctx* c, const void* q, void* ghost, int32_t criterion, double
   HIPCHK(c->tags_host.ensure(size_t(P)));
   int rc = fcx_ghost_fill(c, q, ghost, stream);
   if (rc != FCX_OK) return rc;
-  rc = fcx_regrid_tags(c, q, ghost, criterion, threshold, lmin, lmax, c->tags_dev.p, stream);
+  // the tag kernels write the tags into pinned host memory as well (no copy
+  // after them)
+  rc = regrid_tags(c, q, ghost, criterion, threshold, lmin, lmax, c->tags_dev.p, stream,
+                   reinterpret_cast<int8_t*>(c->tags_host.p));
   if (rc != FCX_OK) return rc;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  HIPCHK(hipMemcpyAsync(c->tags_host.p, c->tags_dev.p, size_t(P), hipMemcpyDeviceToHost, s));
   // the host planner is the next step of the critical path: poll for the
   // tags rather than sleep until the runtime wakes this thread
   if (!c->tags_ready) HIPCHK(hipEventCreateWithFlags(&c->tags_ready, hipEventDisableTiming));

@@ -187,6 +187,15 @@ __device__ __forceinline__ void copy_share(const uint4* __restrict__ src,
   for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x) dst[i] = src[i];
 }
 
+// Grid-stride copy of n16 16-byte units (the source may be pinned host
+// memory).
+__global__ void __launch_bounds__(256)
+k_copy16(const uint4* __restrict__ src, uint4* __restrict__ dst, int64_t n16) {
+  for (int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x; i < n16;
+       i += int64_t(gridDim.x) * blockDim.x)
+    dst[i] = src[i];
+}
+
 struct NextDtArgs {
   double* numax;
   double* dt;
@@ -539,7 +548,7 @@ __global__ void __launch_bounds__(256)
 k_tag_refine(const R* __restrict__ q, const R* __restrict__ ghost,
              const PatchRec* __restrict__ rec, int m, int criterion,
              double thr, int lmax, int8_t* __restrict__ tags,
-             const double* __restrict__ geo) {
+             const double* __restrict__ geo, int8_t* mirror) {
 #pragma clang fp contract(off)
   __shared__ double rlo[4], rhi[4];
   __shared__ int rflag[4];
@@ -591,6 +600,7 @@ k_tag_refine(const R* __restrict__ q, const R* __restrict__ ghost,
     flag |= rflag[0];
     const bool crit = criterion == 0 ? (hi - lo) > thr : flag != 0;
     tags[p] = (crit && rec[p].level < lmax) ? int8_t(1) : int8_t(0);
+    if (mirror) mirror[p] = tags[p];
   }
 }
 
@@ -601,7 +611,7 @@ __global__ void __launch_bounds__(256)
 k_tag_family(const R* __restrict__ q, const PatchRec* __restrict__ rec,
              const int32_t* __restrict__ family, int m, int criterion,
              double thr, int lmin, int8_t* __restrict__ tags,
-             const double* __restrict__ geo) {
+             const double* __restrict__ geo, int8_t* mirror) {
 #pragma clang fp contract(off)
   // m * m averaged parent values, then (sphere) their 3 m * m centres
   extern __shared__ double par[];
@@ -684,7 +694,10 @@ k_tag_family(const R* __restrict__ q, const PatchRec* __restrict__ rec,
     }
     const bool crit = criterion == 0 ? (hi - lo) > thr : flag != 0;
     if (!crit)
-      for (int c = 0; c < 4; ++c) tags[p + c] = int8_t(-1);
+      for (int c = 0; c < 4; ++c) {
+        tags[p + c] = int8_t(-1);
+        if (mirror) mirror[p + c] = int8_t(-1);
+      }
   }
 }
 
