@@ -441,6 +441,7 @@ def run_batch(steps, warmup, nforests=64, graph_steps=10):
     el = time.perf_counter() - t0
     ms = a.elapsed_time(b)
     after = batch.step_stats()
+    items, simple = batch.class_items()
     d = after - before
     acc_cells = float(d[:, 2].sum())
     nst = reps * graph_steps
@@ -454,7 +455,8 @@ def run_batch(steps, warmup, nforests=64, graph_steps=10):
             "status_words_nonzero": int(sum(1 for w in words if w)),
             "status_bits": status_bits(words), "status_bad": int(
                 sum(1 for w in words if w & BAD_BITS)),
-            "bytes_per_step": step_bytes, "advection_bytes_per_step": adv_bytes}
+            "bytes_per_step": step_bytes, "advection_bytes_per_step": adv_bytes,
+            "class_items": items, "class_items_simple_halo": simple}
 
 
 def run_batch_fp64_plain(steps=10, nforests=64):

@@ -350,8 +350,9 @@ int64_t fcx_batch_num_patches(const fcx_batch *batch);
 /* Tunables (chosen by the autotuner): tile of forests with m >= 16 (8 or
  * 16), threads per 8 x 8 tile (64 or 128) and per 16 x 16 tile (256 or 512;
  * advection tiles run one wavefront each whatever these say), launch form
- * (0: a workgroup per tile, or per four advection tiles; 1: persistent).
- * Drops any captured graph. */
+ * (0: a workgroup per tile -- for advection, resident wavefronts that each
+ * walk a run of the tiles with a simple halo, and a workgroup per four of
+ * the others; 1: persistent workgroups).  Drops any captured graph. */
 int fcx_batch_set_tuning(fcx_batch *batch, int32_t tile_big, int32_t threads8,
                          int32_t threads16, int32_t persistent);
 
@@ -367,6 +368,13 @@ int fcx_batch_step(fcx_batch *batch, const void *q, void *q_new, double *dt,
 int fcx_batch_capture(fcx_batch *batch, int32_t steps, void *q_a, void *q_b,
                       double *dt, double *nu_max, int32_t *status);
 int fcx_batch_replay(fcx_batch *batch, void *stream);
+
+/* The work split of the current tuning: items[c] tiles of class c (0:
+ * advection 8 x 8, 1: shallow water 8 x 8, 2: advection with the tuned tile
+ * of forests with m >= 16, 3: shallow water with it), of which simple[c]
+ * have a halo of strip copies only (advection classes; 0 for the others).
+ * items and simple are host arrays of 4 entries. */
+int fcx_batch_class_items(const fcx_batch *batch, int32_t *items, int32_t *simple);
 
 /* Per-forest counters since fcx_batch_create, read after the device has
  * finished: out[3 f + 0] accepted steps, out[3 f + 1] rejected attempts,

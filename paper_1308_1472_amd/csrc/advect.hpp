@@ -81,14 +81,27 @@ struct alignas(2 * sizeof(R)) EdgePQ {
   R P, Q;
 };
 
+// Row stride of a tile's frame (columns -1 .. T+1) in LDS: one more than
+// the frame's width, which spreads the lane groups' rows over the LDS banks
+// (measured: no slower for 16 x 16 tiles, faster for 8 x 8).
+template <int T>
+constexpr int adv_frame_stride() {
+  return T + 4;
+}
+
 template <typename R, int T>
 struct AdvLds {
-  static constexpr int F = T + 3;           // frame columns / rows -1 .. T+1
-  R qs[F * F];
-  EdgePQ<R> xt[T];                          // x-edges T+1 of rows 1..T
-  EdgePQ<R> yt[T];                          // y-edges T+1 of columns 1..T
-  EdgePQ<R> x0[T + 1];                      // x-edges 1..T+1 of row 0
-  EdgePQ<R> y0[T + 1];                      // y-edges 1..T+1 of column 0
+  static constexpr int F = adv_frame_stride<T>();
+  R qs[F * (T + 3)];                        // rows -1 .. T+1
+  // the edges beside the tile's own, in the order they are computed:
+  // x-edges T+1 of rows 1..T, x-edges 1..T+1 of row 0, y-edges T+1 of
+  // columns 1..T, y-edges 1..T+1 of column 0
+  EdgePQ<R> ext[4 * T + 2];
+  R sink[64];                               // stores of lanes past the halo's end
+  __device__ const EdgePQ<R>& xt(int r) const { return ext[r]; }       // row r + 1
+  __device__ const EdgePQ<R>& x0(int e) const { return ext[T + e]; }   // edge e + 1
+  __device__ const EdgePQ<R>& yt(int c) const { return ext[2 * T + 1 + c]; }
+  __device__ const EdgePQ<R>& y0(int e) const { return ext[3 * T + 1 + e]; }
 };
 
 // phi(theta) w for theta = wu / w, limiter `lim` (0 none, 1 minmod,
@@ -111,12 +124,32 @@ __device__ __forceinline__ R limited_wave(int lim, R w, R wu) {
   return (w * wu > R(0)) ? copysign(v, w) : R(0);
 }
 
+// In FP32, minmod(x, y) (the one of smaller magnitude where the signs
+// agree, else zero) is the median of x, y and 0: one v_med3.  The MC
+// limited wave is minmod((w + wu) / 2, 2 w, 2 wu) =
+// minmod(2 minmod(w, wu), (w + wu) / 2), and half of
+// minmod(4 minmod(w, wu), w + wu): the same value, rounded the same (the
+// sum rounds once either way; the scalings are exact), as the form above.
+__device__ __forceinline__ float minmod_(float x, float y) {
+  return __builtin_amdgcn_fmed3f(x, y, 0.0f);
+}
+
 // (P, Q) of the edge between a cell (value q0) and the one below it (q1),
 // with q2 below that; kh = a (1 - a dt/dx) / 2.
 template <typename R>
 __device__ __forceinline__ EdgePQ<R> edge_pq(int lim, R a, R kh, R q0, R q1, R q2) {
-  const R w = q0 - q1;
-  const R Q = kh * limited_wave(lim, w, q1 - q2);
+  const R w = q0 - q1, wu = q1 - q2;
+  R Q;
+  if constexpr (sizeof(R) == 4) {
+    if (lim == 1)
+      Q = kh * minmod_(w, wu);
+    else if (lim >= 4)
+      Q = (R(0.5) * kh) * minmod_(R(4) * minmod_(w, wu), w + wu);
+    else
+      Q = kh * limited_wave(lim, w, wu);
+  } else {
+    Q = kh * limited_wave(lim, w, wu);
+  }
   return EdgePQ<R>{a * w - Q, Q};
 }
 
@@ -144,7 +177,7 @@ struct AdvHalo {
   int32_t corner[5];
 };
 
-__host__ __device__ __forceinline__ void adv_halo_cell(int T, int h, int& c, int& d) {
+__host__ __device__ constexpr void adv_halo_cell(int T, int h, int& c, int& d) {
   if (h < 6 * T) {
     const int s = h / T, t = h % T + 1;
     c = s == 2 ? -1 : (s == 3 ? 0 : (s == 5 ? T + 1 : t));
@@ -155,6 +188,35 @@ __host__ __device__ __forceinline__ void adv_halo_cell(int T, int h, int& c, int
     d = e < 3 ? 0 : (e == 3 ? -1 : T + 1);
   }
 }
+
+// The LDS index (frame cell (c, d) at (d + 1) F + c + 1, F the frame stride) of halo cell
+// h, without branches (selects only, so that it stays out of loops over
+// tiles: it depends on the lane alone).
+template <int T>
+__host__ __device__ constexpr int adv_halo_lds(int h) {
+  constexpr int F = adv_frame_stride<T>();
+  const int s = h / T, t = h % T + 1;
+  const bool row = s == 0 || s == 1 || s == 4;
+  const int rb = s == 0 ? 0 : (s == 1 ? F : (T + 2) * F);
+  const int cc = s == 2 ? 0 : (s == 3 ? 1 : T + 2);
+  const int rowv = rb + t + 1, colv = (t + 1) * F + cc;     // (both formed, then chosen)
+  const int strip = row ? rowv : colv;
+  const int e = h - 6 * T;
+  const int corner =
+      e == 0 ? F : (e == 1 ? F + 1 : (e == 2 ? F + T + 2 : (e == 3 ? 1 : (T + 2) * F + 1)));
+  return h < 6 * T ? strip : corner;
+}
+
+template <int T>
+constexpr bool adv_halo_lds_agrees() {
+  for (int h = 0; h < 6 * T + 5; ++h) {
+    int c = 0, d = 0;
+    adv_halo_cell(T, h, c, d);
+    if (adv_halo_lds<T>(h) != (d + 1) * adv_frame_stride<T>() + c + 1) return false;
+  }
+  return true;
+}
+static_assert(adv_halo_lds_agrees<8>() && adv_halo_lds_agrees<16>(), "halo LDS index");
 
 // nbr: the patch's 12 neighbour slots (faces two each, then corners).
 __host__ __device__ __forceinline__ AdvHalo adv_halo_offsets(int T, int m, int lm, int p,
@@ -208,23 +270,37 @@ __host__ __device__ __forceinline__ AdvHalo adv_halo_offsets(int T, int m, int l
 // the patch's and its same-level neighbours' cells, for patches flagged
 // kSimpleHalo; the general gather (averages, interpolation, rotated trees);
 // or either of the last two, chosen per patch.
-enum AdvHaloSource { kHaloGhostBuf = 0, kHaloStrips = 1, kHaloGeneral = 2, kHaloAny = 3 };
+// kHaloStripWords: strip halos whose offsets are held one dword per lane
+// (base[s] at lane hl0 + s, corner[e] at lane hl0 + 6 + e).
+enum AdvHaloSource {
+  kHaloGhostBuf = 0,
+  kHaloStrips = 1,
+  kHaloGeneral = 2,
+  kHaloAny = 3,
+  kHaloStripWords = 4
+};
 
-// One wavefront advances one T x T tile (T = 8 or 16) with its own LDS.
-// LIM and TRANS fix the limiter and transverse mode when compiling (-1: the
-// forest's, at run time).
-// slot: the patch's face-term slot (-1: none); desc: the tile's halo
-// offsets formed beforehand (strip halos; null: formed here).
-template <typename R, int T, int HALO, int LIM = -1, int TRANS = -1>
-__device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int slot, int tx,
-                                              int ty, AdvLds<R, T>& L, int lane,
-                                              const AdvHalo* desc = nullptr) {
+// A tile's values as loaded: a lane's own cells and its halo cells.
+template <typename R, int T>
+struct AdvRegs {
+  static constexpr int RPL = T * T / 64;
+  static constexpr int HPT = (6 * T + 5 + 63) / 64;
+  R qv[RPL], vh[HPT];
+};
+
+// Loads of one tile into registers (no LDS): every load is issued here and
+// nothing waits for them.  desc: the tile's halo offsets formed beforehand
+// (strip halos; null: formed here); mirror: bit 0 / bit 1 set where the x /
+// y velocity is negative (-1: read from the velocity here); hwords, hl0:
+// the offsets held in lanes (kHaloStripWords).
+template <typename R, int T, int HALO>
+__device__ __forceinline__ void adv_tile_load(const StepArgs<R>& A, int p, int tx, int ty,
+                                              int lane, const AdvHalo* desc,
+                                              AdvRegs<R, T>& g, int mirror = -1,
+                                              int32_t hwords = 0, int hl0 = 0) {
   constexpr int NT = 64, RPL = T * T / NT;   // lanes, own rows per lane
   static_assert(T * T % NT == 0 && RPL >= 1, "one wavefront per tile");
-  constexpr int F = AdvLds<R, T>::F;
   constexpr int NH = 6 * T + 5;              // halo cells of the mirrored frame
-  constexpr int NX = 4 * T + 2;              // edges on the first row / column
-                                             // and the upper sides
   constexpr int HPT = (NH + NT - 1) / NT;    // halo cells per lane
   const int m = A.m, lm = A.lm;
   const int n = lane % T + 1, grp = lane / T;      // own column, lane group
@@ -232,21 +308,40 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
   const PatchRec& rp = A.rec[p];
   const uint32_t pbase = uint32_t(p) << (2 * lm);
   const int i0 = tx * T, j0 = ty * T;
-  const R axr = R(A.ph.ax), ayr = R(A.ph.ay);
-  const bool mx = axr < R(0), my = ayr < R(0);
+  const bool mx = mirror >= 0 ? (mirror & 1) != 0 : R(A.ph.ax) < R(0);
+  const bool my = mirror >= 0 ? (mirror & 2) != 0 : R(A.ph.ay) < R(0);
   // tile cell (c, d) of the mirrored frame <-> tile cell of the patch
   auto flip_x = [&](int c) { return mx ? T + 1 - c : c; };
   auto flip_y = [&](int d) { return my ? T + 1 - d : d; };
-  auto at = [&](int c, int d) { return (d + 1) * F + (c + 1); };
   auto cell = [&](int i, int j) { return pbase + (uint32_t(j - 1) << lm) + (i - 1); };
 
-  // ---- stage: own cells (registers and LDS; for each k the lanes read
-  // whole tile rows), then the halo; every load is issued before the
-  // first LDS store waits for one --------------------------------------
-  R qv[RPL], vh[HPT];
-  const int ip = i0 + flip_x(n);
+  // own cells (for each k the lanes read whole tile rows), then the halo
+  R* qv = g.qv;
+  R* vh = g.vh;
+  {
+    // a lane's rows are consecutive: one address, then a uniform stride
+    const R* qp = A.q + cell(i0 + flip_x(n), j0 + flip_y(r0));
+    const int32_t rs = my ? -m : m;
 #pragma unroll
-  for (int k = 0; k < RPL; ++k) qv[k] = A.q[cell(ip, j0 + flip_y(r0 + k))];
+    for (int k = 0; k < RPL; ++k) qv[k] = qp[k * rs];
+  }
+  if constexpr (HALO == kHaloStripWords) {
+    // each lane takes its strip's (or corner's) offset from the lane that
+    // holds it; lanes past the last corner read the last one again (their
+    // value is not used), so that no load is under a branch
+    const int32_t step_row = mx ? -1 : 1, step_col = my ? -m : m;
+#pragma unroll
+    for (int k = 0; k < HPT; ++k) {
+      const int h = lane + k * NT;
+      const bool strip = h < 6 * T;
+      const int s = h / T, t = strip ? h % T + 1 : 0;
+      const int wi = strip ? s : 6 + (h - 6 * T < 4 ? h - 6 * T : 4);
+      const int32_t b = __builtin_amdgcn_ds_bpermute((hl0 + wi) << 2, hwords);
+      const bool row = s == 0 || s == 1 || s == 4;
+      vh[k] = A.q[b + t * (row ? step_row : step_col)];
+    }
+    return;
+  }
   const int32_t flags = rp.flags;
   const bool simple = (flags & kSimpleHalo) != 0;
   auto halo_pos = [&](int h, int& c, int& d) { adv_halo_cell(T, h, c, d); };
@@ -277,11 +372,13 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
           if (q > s_first && q <= s_last) b = s == q ? H.base[q] : b;
         const bool row = s == 0 || s == 1 || s == 4;
         vh[k] = A.q[b + t * (row ? step_row : step_col)];
-      } else if (h < NH) {
+      } else {
+        // corners; lanes past the last one read the last one again (their
+        // value is not used), so that the load is not under a branch
         const int e = h - 6 * T;
         int32_t b = H.corner[0];
 #pragma unroll
-        for (int q = 1; q < 5; ++q) b = e == q ? H.corner[q] : b;
+        for (int q = 1; q < 5; ++q) b = e == q || (q == 4 && e > 4) ? H.corner[q] : b;
         vh[k] = A.q[b];
       }
     }
@@ -306,22 +403,52 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
       }
     }
   }
+}
+
+// The rest of a tile's update from its loaded values: LDS staging, edges,
+// cells, face terms.  LIM and TRANS fix the limiter and transverse mode when
+// compiling (-1: the forest's, at run time); slot: the patch's face-term slot
+// (-1: none); level: the patch's refinement level; dt: the time step.  With
+// NU the tile's Courant number goes into *A.numax here; it is returned
+// either way.
+template <typename R, int T, int LIM = -1, int TRANS = -1, bool NU = true>
+__device__ __forceinline__ double adv_tile_rest(const StepArgs<R>& A, int p, int slot, int tx,
+                                                int ty, AdvLds<R, T>& L, int lane,
+                                                const AdvRegs<R, T>& g, int level, double dt) {
+  constexpr int NT = 64, RPL = T * T / NT;
+  constexpr int F = AdvLds<R, T>::F;
+  constexpr int NH = 6 * T + 5;              // halo cells of the mirrored frame
+  constexpr int NX = 4 * T + 2;              // edges on the first row / column
+                                             // and the upper sides
+  constexpr int HPT = (NH + NT - 1) / NT;    // halo cells per lane
+  const int m = A.m, lm = A.lm;
+  const int n = lane % T + 1, grp = lane / T;
+  const int r0 = RPL * grp + 1;
+  const uint32_t pbase = uint32_t(p) << (2 * lm);
+  const int i0 = tx * T, j0 = ty * T;
+  const R axr = R(A.ph.ax), ayr = R(A.ph.ay);
+  const bool mx = axr < R(0), my = ayr < R(0);
+  auto flip_x = [&](int c) { return mx ? T + 1 - c : c; };
+  auto flip_y = [&](int d) { return my ? T + 1 - d : d; };
+  auto at = [&](int c, int d) { return (d + 1) * F + (c + 1); };
+  auto cell = [&](int i, int j) { return pbase + (uint32_t(j - 1) << lm) + (i - 1); };
+  const R* qv = g.qv;
+  const R* vh = g.vh;
 #pragma unroll
   for (int k = 0; k < RPL; ++k) L.qs[at(n, r0 + k)] = qv[k];
+  // (lanes past the halo's last cell store into a sink: no branch)
 #pragma unroll
   for (int k = 0; k < HPT; ++k) {
     const int h = lane + k * NT;
-    if (h < NH) {
-      int c, d;
-      halo_pos(h, c, d);
-      L.qs[at(c, d)] = vh[k];
-    }
+    R* dst = h < NH ? &L.qs[adv_halo_lds<T>(h)] : &L.sink[lane];
+    *dst = vh[k];
   }
-  const double dtdx_d = ldexp(*A.dt, rp.level + lm);       // dx = 2^-(level + lm)
+  const double dtdx_d = ldexp(dt, level + lm);             // dx = 2^-(level + lm)
   const R dtdx = R(dtdx_d);
   const R ax = fabs(axr), ay = fabs(ayr);
   // the Courant number: the same on every edge of the tile
-  if (lane == 0) atomic_max_pos(A.numax, dtdx_d * double(fmax(ax, ay)));
+  const double cfl = dtdx_d * double(fmax(ax, ay));
+  if (NU && lane == 0) atomic_max_pos(A.numax, cfl);
   wave_sync();
 
   // ---- edges -------------------------------------------------------------
@@ -341,21 +468,22 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
       ey[k] = edge_pq(lim, ay, kyh, qv[k], q1, q2);
     }
   }
-  // the extra edges go to the last lanes (the first ones staged more halo)
+  // the extra edges go to the last lanes (the first ones staged more halo);
+  // one edge evaluation per pass, its cells and direction chosen per lane
+  // by selects: the LDS index of the edge's upper cell is base + x * mul
+#pragma unroll
   for (int x = NT - 1 - lane; x < NX; x += NT) {
-    if (x < T) {                                 // x-edges T+1, rows 1..T
-      const int b = at(T + 1, x + 1);
-      L.xt[x] = edge_pq(lim, ax, kxh, L.qs[b], L.qs[b - 1], L.qs[b - 2]);
-    } else if (x < 2 * T + 1) {                  // x-edges 1..T+1 of row 0
-      const int b = at(x - T + 1, 0);
-      L.x0[x - T] = edge_pq(lim, ax, kxh, L.qs[b], L.qs[b - 1], L.qs[b - 2]);
-    } else if (x < 3 * T + 1) {                  // y-edges T+1, columns 1..T
-      const int b = at(x - 2 * T, T + 1);
-      L.yt[x - 2 * T - 1] = edge_pq(lim, ay, kyh, L.qs[b], L.qs[b - F], L.qs[b - 2 * F]);
-    } else {                                     // y-edges 1..T+1 of column 0
-      const int b = at(0, x - 3 * T);
-      L.y0[x - 3 * T - 1] = edge_pq(lim, ay, kyh, L.qs[b], L.qs[b - F], L.qs[b - 2 * F]);
-    }
+    const bool s1 = x >= T, s2 = x >= 2 * T + 1, s3 = x >= 3 * T + 1;
+    int base = 2 * F + T + 2, mul = F;           // x-edges T+1, rows 1..T: at(T+1, x+1)
+    base = s1 ? F - T + 2 : base;                // x-edges 1..T+1 of row 0: at(x-T+1, 0)
+    mul = s1 ? 1 : mul;
+    base = s2 ? (T + 2) * F - 2 * T + 1 : base;  // y-edges T+1: at(x-2T, T+1)
+    base = s3 ? (1 - 3 * T) * F + 1 : base;      // y-edges 1..T+1 of column 0: at(0, x-3T)
+    mul = s3 ? F : mul;
+    const int b = base + x * mul;
+    const int st = s2 ? F : 1;
+    L.ext[x] = edge_pq(lim, s2 ? ay : ax, s2 ? kyh : kxh, L.qs[b], L.qs[b - st],
+                       L.qs[b - 2 * st]);
   }
   wave_sync();
 
@@ -368,12 +496,13 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
 #pragma unroll
   for (int k = 0; k < RPL; ++k) {
     const R right = dpp_move<kDppRowShl1>(ex[k].Q);  // x-edge n+1, same row
-    qx2[k] = n == T ? L.xt[r0 + k - 1].Q : right;
+    const R last = L.xt(r0 + k - 1).Q;               // (read by every lane: no branch)
+    qx2[k] = n == T ? last : right;
     U[k] = trans_source(trans, ex[k], qx2[k]);
   }
   {
     const R above = lane_fetch(lane + T, ey[0].Q);   // y-edge of the row above
-    const R top = L.yt[n - 1].Q;
+    const R top = L.yt(n - 1).Q;
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
       qy2[k] = k + 1 < RPL ? ey[k + 1].Q : (grp == NT / T - 1 ? top : above);
@@ -381,14 +510,15 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
     }
   }
   const R u_low = lane_fetch(lane - T, U[RPL - 1]);  // source of the row below
-  const R u_row0 = trans_source(trans, L.x0[n - 1], L.x0[n].Q);
+  const R u_row0 = trans_source(trans, L.x0(n - 1), L.x0(n).Q);
   R u_dn[RPL], v_dn[RPL];
 #pragma unroll
   for (int k = 0; k < RPL; ++k) {
     const int r = r0 + k;
     u_dn[k] = k > 0 ? U[k - 1] : (grp > 0 ? u_low : u_row0);
     const R v_left = dpp_move<kDppRowShr1>(V[k]);     // column n-1, same row
-    v_dn[k] = n > 1 ? v_left : trans_source(trans, L.y0[r - 1], L.y0[r].Q);
+    const R v_first = trans_source(trans, L.y0(r - 1), L.y0(r).Q);   // (every lane)
+    v_dn[k] = n > 1 ? v_left : v_first;
     const R X = (qx2[k] + ex[k].P) + by * (U[k] - u_dn[k]);
     const R Y = (qy2[k] + ey[k].P) + bx * (V[k] - v_dn[k]);
     A.qn[cell(i0 + flip_x(n), j0 + flip_y(r))] = (qv[k] - dtdx * X) - dtdx * Y;
@@ -397,7 +527,7 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
     // terms through the patch faces, for the reflux: a face that is the
     // lower side in the mirrored frame takes the lower-edge terms
     R* ph = A.phi + size_t(slot) * 4 * m;
-    const R dxr = R(ldexp(1.0, -rp.level - lm));
+    const R dxr = R(ldexp(1.0, -level - lm));
 #pragma unroll
     for (int k = 0; k < RPL; ++k) {
       const int i = i0 + flip_x(n), j = j0 + flip_y(r0 + k);
@@ -409,6 +539,17 @@ __device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int s
       if (j == m) ph[3 * m + (i - 1)] = dxr * (my ? vyl : vyh);
     }
   }
+  return cfl;
+}
+
+// One wavefront advances one T x T tile (T = 8 or 16) with its own LDS.
+template <typename R, int T, int HALO, int LIM = -1, int TRANS = -1>
+__device__ __forceinline__ void adv_tile_step(const StepArgs<R>& A, int p, int slot, int tx,
+                                              int ty, AdvLds<R, T>& L, int lane,
+                                              const AdvHalo* desc = nullptr) {
+  AdvRegs<R, T> g;
+  adv_tile_load<R, T, HALO>(A, p, tx, ty, lane, desc, g);
+  adv_tile_rest<R, T, LIM, TRANS>(A, p, slot, tx, ty, L, lane, g, A.rec[p].level, *A.dt);
 }
 
 // Tiles (wavefronts) per workgroup: a CU holds only so many workgroups, and

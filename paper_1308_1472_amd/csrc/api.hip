@@ -1239,11 +1239,12 @@ static int batch_build(fcx_batch* b) {
       const PatchRec& r = recs[size_t(it.patch)];
       AdvItem& a = adv[size_t(k)];
       a.h = it;
-      a.pad = 0;
+      a.aux = 0;
       a.halo = AdvHalo{};
       if (!(r.flags & kSimpleHalo)) continue;
       const bool mx = b->precision == 64 ? F.ph.ax < 0.0 : float(F.ph.ax) < 0.0f;
       const bool my = b->precision == 64 ? F.ph.ay < 0.0 : float(F.ph.ay) < 0.0f;
+      a.aux = r.level | int(mx) << 8 | int(my) << 9;
       const int T = F.m == 8 ? 8 : b->tile_big;
       a.halo = adv_halo_offsets(T, F.m, F.lm, it.patch, it.tx(), it.ty(), mx, my, r.flags,
                                 r.nbr);
@@ -1403,11 +1404,14 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
     const dim3 gg(unsigned((ng + kAdvWaves - 1) / kAdvWaves));
     const bool spec = b->mc2[cls];
     if (ns > 0) {
+      // the strip-halo items: resident wavefronts walking runs of items
       B.nitems = ns;
+      const dim3 gr(
+          unsigned(std::min<int64_t>(int64_t(b->cus) * AdvRunBlocks<R, T>::value, gs.x)));
       if (spec)
-        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloStrips, 1>), gs, dim3(threads), 0, s, B);
+        hipLaunchKernelGGL((k_batch_adv_run<R, T, 1>), gr, dim3(threads), 0, s, B);
       else
-        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloStrips, 0>), gs, dim3(threads), 0, s, B);
+        hipLaunchKernelGGL((k_batch_adv_run<R, T, 0>), gr, dim3(threads), 0, s, B);
     }
     if (ng > 0) {
       B.item0 = b->item0[cls] + ns;
@@ -1469,6 +1473,15 @@ static int batch_step_t(fcx_batch* b, const void* q, void* qn, double* dt,
                      0, s, static_cast<const R*>(q), static_cast<R*>(qn), b->forests,
                      b->first, b->n, nd, b->err.p);
   HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
+int fcx_batch_class_items(const fcx_batch* b, int32_t* items, int32_t* simple) {
+  if (!b || !items || !simple) return fail(FCX_EINVAL, "bad arguments");
+  for (int c = 0; c < 4; ++c) {
+    items[c] = b->nitems[c];
+    simple[c] = (c == 0 || c == 2) ? b->nsimple[c] : 0;
+  }
   return FCX_OK;
 }
 

@@ -41,7 +41,7 @@ EXPORTS = [
     "fcx_mlp_backward", "fcx_adam_step", "fcx_learned_tags", "fcx_dilate_tags",
     "fcx_sphere_geometry", "fcx_advance", "fcx_regrid", "fcx_run",
     "fcx_step_stats", "fcx_batch_step_stats", "fcx_conservation_sums_noalloc",
-    "fcx_advance_subcycled", "fcx_sim_time",
+    "fcx_advance_subcycled", "fcx_sim_time", "fcx_batch_class_items",
 ]
 
 MLP_INPUTS, MLP_HIDDEN, MLP_CLASSES, MLP_PARAMS = 16, 64, 3, 5443
@@ -127,6 +127,7 @@ def lib():
         L.fcx_advance_subcycled.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fcx_sim_time.argtypes = [vp, vp]
         L.fcx_batch_step_stats.argtypes = [vp, vp]
+        L.fcx_batch_class_items.argtypes = [vp, vp, vp]
         L.fcx_run.argtypes = [vp, i32, vp, vp, i64, vp, i64, i32, i32, i32, i32, dp, i32,
                               i32, vp, vp, vp, vp, vp, vp]
         _lib = L
@@ -551,6 +552,15 @@ class Batch:
         out = np.zeros((self.n, 3), dtype=np.int64)
         _check(lib().fcx_batch_step_stats(self.h, _np_ptr(out)))
         return out
+
+    def class_items(self):
+        """(items, simple): per tile class (advection 8x8, shallow water
+        8x8, advection with the tuned tile, shallow water with it) the work
+        items of the current tuning and those with a strip-copy halo."""
+        items = np.zeros(4, dtype=np.int32)
+        simple = np.zeros(4, dtype=np.int32)
+        _check(lib().fcx_batch_class_items(self.h, _np_ptr(items), _np_ptr(simple)))
+        return items.tolist(), simple.tolist()
 
     def sums(self, q, out, stream=None):
         import torch

@@ -106,6 +106,16 @@ def test_fp32(m):
                  steps=3)
 
 
+@pytest.mark.parametrize("limiter", [0, 1, 2, 3, 4])
+def test_fp32_limiters(limiter):
+    """FP32 tiles: minmod and MC take their median-of-three forms."""
+    say(f"[advect] fp32 limiter={limiter}")
+    trees, lv, q = _case("periodic", 16, 13)
+    for ax, ay in [(0.7, -0.45), (-0.35, 0.9)]:
+        _compare(fcx.config(16, 32, fcx.FCX_ADVECTION, limiter=limiter, ax=ax, ay=ay),
+                 trees, lv, q, True, steps=3)
+
+
 @pytest.mark.parametrize("domain", ["walled", "extrap", "brick_translated", "periodic"])
 @pytest.mark.parametrize("uniform", [True, False])
 @pytest.mark.parametrize("m", [8, 16, 32])

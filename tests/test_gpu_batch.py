@@ -172,6 +172,87 @@ def test_batch_sums_match_oracle():
         assert np.all(got[f, c.meqn:] == 0)
 
 
+# Advection forests of uniform leaves (every halo a strip copy) with every
+# velocity sign, walls and translated trees, and enough tiles that each
+# wavefront of the strip-halo launch walks several items (on 256 CUs: 5120
+# wavefronts for 16 x 16 tiles, 6144 for 8 x 8) and some walks cross from one
+# forest into the next.  The 16 x 16 class mixes limiters (limiter and
+# transverse mode read at run time), the 8 x 8 class is MC only (fixed when
+# compiling).  (m, domain, level, ax, ay, limiter)
+LONG_RUNS = [(16, "periodic", 6, 0.8, 0.55, 4), (16, "walled", 6, -0.7, 0.45, 4),
+             (32, "periodic", 5, 0.6, -0.9, 4), (16, "brick", 5, -0.5, -0.65, 1),
+             (8, "walled", 6, 0.9, -0.2, 4), (8, "periodic", 6, -0.3, 0.75, 4),
+             (8, "periodic", 5, 0.0, -0.7, 4)]
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+def test_long_runs_of_strip_halo_tiles(precision):
+    """Each forest of the batch equals its own fused step and reflux bit for
+    bit, with the same next dt (the Courant number is carried per forest
+    along a walk); two of them also against the oracle."""
+    import torch
+    say(f"[batch] long runs of strip-halo tiles precision={precision}")
+    ctxs, meshes, states, pars, dts = [], [], [], [], []
+    for k, (m, dom, level, ax, ay, lim) in enumerate(LONG_RUNS):
+        if dom == "brick":
+            trees, pl = I.brick(3, 2, periodic=(True, False)); nt = 6
+        elif dom == "walled":
+            trees, pl = I.walled_square(); nt = 1
+        else:
+            trees, pl = I.periodic_square(); nt = 1
+        lv = fcx.sfc_sort(I.uniform_leaves(nt, level))
+        cfg = fcx.config(m, precision, fcx.FCX_ADVECTION, ax=ax, ay=ay, limiter=lim)
+        ctx = fcx.Context(cfg, trees)
+        ctx.upload_forest(lv)
+        q = I.state_from(lv, m, lambda x, y: I.gaussian(x, y, 0.3 + 0.05 * k, 0.55, 0.02)
+                         + 0.2 * np.sin(4 * x + k) * np.cos(3 * y), pl)
+        ctxs.append(ctx)
+        meshes.append((trees, lv))
+        states.append(q)
+        pars.append(oracle_params(cfg))
+        dts.append(0.45 / ((m << level) * max(abs(ax), abs(ay))))
+    batch = fcx.Batch(ctxs)
+    dtype = torch.float64 if precision == 64 else torch.float32
+    qb = torch.empty(batch.state_elems(), dtype=dtype, device="cuda")
+    for f, q in enumerate(states):
+        o = batch.state_offset(f)
+        qb[o:o + q.size].copy_(torch.from_numpy(q.ravel()))
+    n = batch.n
+    dt = torch.tensor(dts, dtype=torch.float64, device="cuda")
+    nu = torch.zeros(n, dtype=torch.float64, device="cuda")
+    st = torch.zeros(n, dtype=torch.int32, device="cuda")
+    qn = torch.empty_like(qb)
+    batch.step(qb, qn, dt, nu, st)
+    got = _split(batch, ctxs, qn)
+    assert int(st.sum().item()) == 0
+    for f, ctx in enumerate(ctxs):
+        q = torch.from_numpy(states[f].ravel().copy()).to(dtype).cuda()
+        q2 = torch.empty_like(q)
+        d1 = torch.tensor([dts[f]], dtype=torch.float64, device="cuda")
+        nu1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+        ctx.fused_step(q, q2, d1, nu1)
+        ctx.reflux(q, q2, d1)
+        own = q2.double().cpu().numpy().reshape(got[f].shape)
+        if LONG_RUNS[f][0] == 8 or LONG_RUNS[f][5] != 4:
+            assert np.array_equal(got[f], own), f
+        else:
+            # an MC forest in a class that reads the limiter at run time:
+            # the arithmetic is the same, the compiler's fused multiply-adds
+            # are not all
+            err = np.max(np.abs(got[f] - own)) / np.max(np.abs(own))
+            assert err <= (1e-15 if precision == 64 else 1e-6), (f, err)
+        assert abs(dt[f].item() - dts[f] * 0.9 / nu1.item()) <= 1e-15 * dts[f], f
+        if f in (2, 4):
+            trees, lv = meshes[f]
+            want, nu_o = O.advance(O.Mesh(trees, lv, ctx.cfg.m), pars[f], states[f], dts[f])
+            # (FP32 tiles take the velocity in FP32)
+            assert abs(nu1.item() - nu_o) <= (1e-14 if precision == 64 else 1e-6) * nu_o
+            if precision == 64:
+                assert np.max(np.abs(got[f] - want)) <= 1e-12 * np.max(np.abs(want))
+            else:
+                assert np.sum(np.abs(got[f] - want)) <= 1e-5 * np.sum(np.abs(want))
+
+
 def test_autotuner_picks_a_valid_config(tmp_path, monkeypatch):
     from paper_1308_1472_amd import autotune
     say("[batch] autotune")
