@@ -1249,6 +1249,17 @@ static int batch_build(fcx_batch* b) {
       a.halo = adv_halo_offsets(T, F.m, F.lm, it.patch, it.tx(), it.ty(), mx, my, r.flags,
                                 r.nbr);
     }
+    // one simple-halo item per forest reports the forest's Courant number:
+    // the first of its finest level (the number is the same on every tile
+    // of a level and grows with the level)
+    std::vector<int32_t> best(b->fh.size(), -1);
+    for (int32_t k = b->item0[cls]; k < b->item0[cls] + b->nsimple[cls]; ++k) {
+      const int f = all[size_t(k)].forest();
+      const int32_t cur = best[size_t(f)];
+      if (cur < 0 || adv[size_t(k)].level() > adv[size_t(cur)].level()) best[size_t(f)] = k;
+    }
+    for (int32_t k : best)
+      if (k >= 0) adv[size_t(k)].aux |= kAdvReports;
   }
   // one packed upload
   const size_t sz[10] = {recs.size() * sizeof(PatchRec), phislot.size() * 4,

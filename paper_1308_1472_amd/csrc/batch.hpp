@@ -44,10 +44,13 @@ struct alignas(16) BatchItem {
 
 // A work item of an advection class with the tile's halo offsets formed
 // when the batch is built (velocity signs and neighbours are fixed then).
+constexpr int32_t kAdvReports = 1 << 10;
 struct alignas(16) AdvItem {
   BatchItem h;
   AdvHalo halo;                            // simple-halo patches only
   int32_t aux;                             // patch level | x mirror << 8 | y mirror << 9
+                                           // | kAdvReports: the item that
+                                           // reports its forest's Courant number
   __device__ __host__ int level() const { return aux & 255; }
   __device__ __host__ int mirror() const { return (aux >> 8) & 3; }
 };
@@ -178,22 +181,24 @@ k_batch_adv(BatchArgs<R> B) {
       HALO == kHaloStrips ? &ai.halo : nullptr);
 }
 
-// Strip-halo items, every wavefront walking a contiguous run of them (runs
-// of consecutive wavefronts are consecutive, and each XCD takes a
-// contiguous set of runs): the loads of the next item are issued before the
-// current item is computed, so that one tile's memory latency overlaps the
-// arithmetic of the one before.  An item's 16 dwords arrive two items ahead
-// by a vector load, one dword per lane (the halo offsets stay there and
-// each lane takes its own by a lane permute), so that no wait for the
-// current tile's values waits on the scalar cache or the next tile.  Items
-// are ordered by forest, so a run meets few forests: a forest's record and
-// time step are read when the run enters it, and its Courant number is
-// kept until the run leaves it.
+// Strip-halo items walked by resident wavefronts: wavefront w of W takes
+// items w, w + W, w + 2W, ... (consecutive wavefronts on one XCD), so that
+// the tiles in flight at any time are a compact window of the item order
+// (neighbours in space-filling-curve order) and share their halo cells in
+// the L2.  The loads of the next item are issued before the current item is
+// computed, so that one tile's memory latency overlaps the arithmetic of
+// the one before.  Whatever an item needs beside its cells arrives by
+// vector loads, one dword per lane: its 16 dwords two items ahead (the halo
+// offsets stay there and each lane takes its own by a lane permute), its
+// forest's record and time step with its cells; so no wait for the current
+// tile's values waits on the scalar cache or on the next tile.  A forest's
+// Courant number is the same on all its tiles of one level: one item per
+// forest, of its finest level, reports it.
 // Resident workgroups per CU a launch is sized for (the register budget:
 // two tiles' values live at once).
 template <typename R, int T>
 struct AdvRunBlocks {
-  static constexpr int value = T == 8 ? 6 : (sizeof(R) == 4 ? 5 : 3);
+  static constexpr int value = T == 8 ? 6 : (sizeof(R) == 4 ? 4 : 3);
 };
 template <typename R, int T, int SPEC>
 __global__ void __launch_bounds__(64 * kAdvWaves, (AdvRunBlocks<R, T>::value))
@@ -205,27 +210,28 @@ k_batch_adv_run(BatchArgs<R> B) {
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x) >> 6);
   const int lane = int(threadIdx.x) & 63;
   const int nw = int(gridDim.x) * kAdvWaves;
-  const int wid = xcd_tile(blockIdx.x, int(gridDim.x)) * kAdvWaves + wv;
-  const int lo = int(int64_t(wid) * B.nitems / nw);
-  const int hi = int(int64_t(wid + 1) * B.nitems / nw);
-  if (lo >= hi) return;
+  const int n = B.nitems;
+  int it = xcd_tile(blockIdx.x, int(gridDim.x)) * kAdvWaves + wv;
+  if (it >= n) return;
   const int32_t* words = reinterpret_cast<const int32_t*>(B.advitems + B.item0);
   // (every lane loads, none under a branch: a wait for one item's values
-  // then never counts on a load that may not have been issued)
-  auto fetch = [&](int it) { return words[size_t(it) * 16 + (lane & 15)]; };
+  // then never counts on a load that may not have been issued; past the
+  // walk's end the current item is read again, not used)
+  auto fetch = [&](int k, int cur) {
+    return words[size_t(k < n ? k : cur) * 16 + (lane & 15)];
+  };
   struct Item {
     BatchItem w;
-    int level, mirror;
-  };
+    int aux;
+    int32_t fw;                            // lane k < FW: dword k of the forest record;
+  };                                       // FW, FW + 1: its time step
   // an item from its dwords (uniform values), and the issue of its loads
   auto start = [&](int32_t d, Item& c, AdvRegs<R, T>& g) {
     c.w.patch = __builtin_amdgcn_readlane(d, 0);
     c.w.qoff = uint32_t(__builtin_amdgcn_readlane(d, 1));
     c.w.slot = __builtin_amdgcn_readlane(d, 2);
     c.w.info = __builtin_amdgcn_readlane(d, 3);
-    const int aux = __builtin_amdgcn_readlane(d, 15);
-    c.level = aux & 255;
-    c.mirror = (aux >> 8) & 3;
+    c.aux = __builtin_amdgcn_readlane(d, offsetof(AdvItem, aux) / 4);
     StepArgs<R> A{};
     const int lm = c.w.lm();
     A.rec = B.rec;
@@ -233,77 +239,55 @@ k_batch_adv_run(BatchArgs<R> B) {
     A.m = 1 << lm;
     A.lm = lm;
     adv_tile_load<R, T, kHaloStripWords>(A, c.w.patch, c.w.tx(), c.w.ty(), lane, nullptr, g,
-                                         c.mirror, d, offsetof(AdvItem, halo) / 4);
-  };
-  // the forest the run is in: its record's values and its Courant number
-  int f_run = -1;
-  double nu_run = 0, dt = 0;
-  int64_t phi_base = 0;
-  int32_t slot_base = 0;
-  KPhys ph{};
-  auto record = [&](int f) {                // a forest's record and time step
+                                         (c.aux >> 8) & 3, d, offsetof(AdvItem, halo) / 4);
+    const int f = c.w.forest();
     const int32_t* fr = reinterpret_cast<const int32_t*>(B.forests + f);
     const int32_t* dr = reinterpret_cast<const int32_t*>(B.dt + f);
-    return *(lane < FW ? fr + lane : dr + (lane - FW < 2 ? lane - FW : 1));
+    c.fw = *(lane < FW ? fr + lane : dr + (lane - FW < 2 ? lane - FW : 1));
   };
-  // the records of the first and the last item's forests are read with the
-  // first item's cells; others (forests of a few items) when entered
-  const int32_t dl = fetch(hi - 1);
-  int f_first = 0, f_last = 0;
-  int32_t rec_first = 0, rec_last = 0;
-  auto enter = [&](int f) {
-    if (f_run >= 0 && lane == 0) atomic_max_pos(B.numax + f_run, nu_run);
-    f_run = f;
-    nu_run = 0;
-    const int32_t v = f == f_first ? rec_first : (f == f_last ? rec_last : record(f));
-    auto word2 = [&](int k) {
-      return (int64_t(uint32_t(__builtin_amdgcn_readlane(v, k + 1))) << 32) |
-             uint32_t(__builtin_amdgcn_readlane(v, k));
-    };
-    constexpr int PH = offsetof(ForestDev, ph) / 4;
-    phi_base = word2(offsetof(ForestDev, phi_base) / 4);
-    slot_base = __builtin_amdgcn_readlane(v, offsetof(ForestDev, slot_base) / 4);
-    ph.ax = __longlong_as_double(word2(PH + offsetof(KPhys, ax) / 4));
-    ph.ay = __longlong_as_double(word2(PH + offsetof(KPhys, ay) / 4));
-    ph.limiter = __builtin_amdgcn_readlane(v, PH + offsetof(KPhys, limiter) / 4);
-    ph.transverse = __builtin_amdgcn_readlane(v, PH + offsetof(KPhys, transverse) / 4);
-    dt = __longlong_as_double(word2(FW));
+  auto word2 = [&](int32_t v, int k) {
+    return (int64_t(uint32_t(__builtin_amdgcn_readlane(v, k + 1))) << 32) |
+           uint32_t(__builtin_amdgcn_readlane(v, k));
   };
   Item cur;
   AdvRegs<R, T> g;
-  const int32_t d0 = fetch(lo);
-  int32_t d1 = fetch(lo + 1 < hi ? lo + 1 : lo);
+  const int32_t d0 = fetch(it, it);
+  int32_t d1 = fetch(it + nw, it);
   start(d0, cur, g);
-  f_first = cur.w.forest();
-  f_last = __builtin_amdgcn_readlane(dl, 3) >> 12;
-  rec_first = record(f_first);
-  rec_last = record(f_last);
-  // the loop keeps the dwords of item it + 1 in d1; past the last item the
-  // last one is read again (not used)
-  for (int it = lo;; ++it) {
-    const bool more = it + 1 < hi;
-    const int32_t d2 = fetch(it + 2 < hi ? it + 2 : hi - 1);
+  // the loop keeps the dwords of item it + W in d1
+  for (;;) {
+    const bool more = it + nw < n;
+    const int32_t d2 = fetch(it + 2 * nw, more ? it + nw : it);
     Item nxt;
     AdvRegs<R, T> gn;
     start(d1, nxt, gn);
     d1 = d2;
-    if (cur.w.forest() != f_run) enter(cur.w.forest());
+    // this item's arguments from its forest's record
+    constexpr int PH = offsetof(ForestDev, ph) / 4;
     StepArgs<R> A{};
     const int lm = cur.w.lm(), m = 1 << lm;
     A.qn = B.qn + (int64_t(cur.w.qoff) - (int64_t(cur.w.patch) << (2 * lm)));
+    const int64_t phi_base = word2(cur.fw, offsetof(ForestDev, phi_base) / 4);
+    const int32_t slot_base =
+        __builtin_amdgcn_readlane(cur.fw, offsetof(ForestDev, slot_base) / 4);
     A.phi = B.phi + (phi_base - int64_t(slot_base) * 4 * m);
     A.m = m;
     A.lm = lm;
-    A.ph = ph;
-    nu_run = fmax(nu_run, adv_tile_rest<R, T, SPEC ? 4 : -1, SPEC ? 2 : -1, false>(
-                              A, cur.w.patch, cur.w.slot, cur.w.tx(), cur.w.ty(), lds[wv],
-                              lane, g, cur.level, dt));
+    A.ph.ax = __longlong_as_double(word2(cur.fw, PH + offsetof(KPhys, ax) / 4));
+    A.ph.ay = __longlong_as_double(word2(cur.fw, PH + offsetof(KPhys, ay) / 4));
+    A.ph.limiter = __builtin_amdgcn_readlane(cur.fw, PH + offsetof(KPhys, limiter) / 4);
+    A.ph.transverse = __builtin_amdgcn_readlane(cur.fw, PH + offsetof(KPhys, transverse) / 4);
+    const double dt = __longlong_as_double(word2(cur.fw, FW));
+    const double nu = adv_tile_rest<R, T, SPEC ? 4 : -1, SPEC ? 2 : -1, false>(
+        A, cur.w.patch, cur.w.slot, cur.w.tx(), cur.w.ty(), lds[wv], lane, g,
+        cur.aux & 255, dt);
+    if ((cur.aux & kAdvReports) && lane == 0) atomic_max_pos(B.numax + cur.w.forest(), nu);
     wave_sync();                           // the tile's LDS is free
     if (!more) break;
+    it += nw;
     cur = nxt;
     g = gn;
   }
-  if (lane == 0) atomic_max_pos(B.numax + f_run, nu_run);
 }
 
 // Persistent form: every wavefront takes items on its own, through the
