@@ -249,17 +249,16 @@ k_batch_adv_run(BatchArgs<R> B) {
     return (int64_t(uint32_t(__builtin_amdgcn_readlane(v, k + 1))) << 32) |
            uint32_t(__builtin_amdgcn_readlane(v, k));
   };
-  Item cur;
-  AdvRegs<R, T> g;
   const int32_t d0 = fetch(it, it);
-  int32_t d1 = fetch(it + nw, it);
-  start(d0, cur, g);
-  // the loop keeps the dwords of item it + W in d1
-  for (;;) {
+  int32_t d1 = fetch(it + nw, it);        // the dwords of item it + W
+  // one item: issue the next item's loads (into nxt, gn), then compute this
+  // one (cur, g); false once the walk ends.  The loop below alternates the
+  // two register sets, so that no loaded value is copied between them (a
+  // copy would wait for its load).
+  auto item = [&](const Item& cur, const AdvRegs<R, T>& g, Item& nxt,
+                  AdvRegs<R, T>& gn) -> bool {
     const bool more = it + nw < n;
     const int32_t d2 = fetch(it + 2 * nw, more ? it + nw : it);
-    Item nxt;
-    AdvRegs<R, T> gn;
     start(d1, nxt, gn);
     d1 = d2;
     // this item's arguments from its forest's record
@@ -283,10 +282,13 @@ k_batch_adv_run(BatchArgs<R> B) {
         cur.aux & 255, dt);
     if ((cur.aux & kAdvReports) && lane == 0) atomic_max_pos(B.numax + cur.w.forest(), nu);
     wave_sync();                           // the tile's LDS is free
-    if (!more) break;
     it += nw;
-    cur = nxt;
-    g = gn;
+    return more;
+  };
+  Item ia, ib;
+  AdvRegs<R, T> ga, gb;
+  start(d0, ia, ga);
+  while (item(ia, ga, ib, gb) && item(ib, gb, ia, ga)) {
   }
 }
 
