@@ -38,7 +38,16 @@ typedef struct {
   int32_t nbr_tree[4], nbr_face[4], orient[4], bc[4];
 } fco_tree;
 
-enum { FCO_ADVECTION = 0, FCO_SHALLOW = 1, FCO_SPHERE = 2 };
+/* FCO_SWIRL: a scalar carried by a prescribed divergence-free flow (the
+ * paper's Sec. 5 advection example, whose field the paper does not give;
+ * the stand-in here is the classic swirl stream function
+ *   psi(x, y, t) = sin^2(pi x) sin^2(pi y) cos(pi t / T) / pi
+ * on each tree's unit square, period T = par->period).  The equation is
+ * the colour equation q_t + u q_x + v q_y = 0 with (u, v) = (psi_y, -psi_x);
+ * every cell edge carries the normal velocity of psi's difference between
+ * the edge's two corners over its length (so the discrete field is exactly
+ * divergence free), taken at the middle of the step (par->time + dt / 2). */
+enum { FCO_ADVECTION = 0, FCO_SHALLOW = 1, FCO_SPHERE = 2, FCO_SWIRL = 3 };
 
 typedef struct {
   int32_t m;           /* cells per patch side (even, >= 4)            */
@@ -49,6 +58,8 @@ typedef struct {
   int32_t pad;
   double g;            /* gravity (shallow water)                      */
   double ax, ay;       /* advection velocity (computational coords)    */
+  double period;       /* FCO_SWIRL: period T of the flow              */
+  double time;         /* FCO_SWIRL: time of the state a step starts from */
 } fco_params;
 
 typedef struct fco_mesh fco_mesh;
@@ -132,6 +143,12 @@ double fco_phi(int32_t limiter, double theta);
 int  fco_riemann(const fco_params *par, int32_t dir, const double *ql,
                  const double *qr, double *waves, double *speeds,
                  double *amdq, double *apdq);
+/* FCO_SWIRL: the stream function, and the normal velocity of the
+ * dir-edge at coordinate a (x for dir 0, y for dir 1) spanning [b0, b1] in
+ * the other coordinate, at time t (tree coordinates) */
+double fco_swirl_psi(const fco_params *par, double x, double y, double t);
+double fco_swirl_edge(const fco_params *par, int32_t dir, double a, double b0,
+                      double b1, double t);
 /* transverse split of a fluctuation psi from the dir-edge with states ql,
  * qr into the parts moving down (bm) and up (bp) the other direction
  * (planar physics) */

@@ -47,6 +47,7 @@ int fco_wall_face(const fco_mesh *mesh, int64_t p, int32_t f);
 typedef struct {
   double gamma;
   double n[3], t[3];
+  double vel;          /* FCO_SWIRL: the edge's normal velocity */
 } fco_edge_geom;
 
 /* sphere solver pieces (fco_sphere.c) */

@@ -78,6 +78,31 @@ static int rp_advection(const fco_params *par, int dir, const double *ql,
   return 1;
 }
 
+/* colour equation with the edge's own normal velocity (FCO_SWIRL) */
+static int rp_swirl(const edge_geom *e, const double *ql, const double *qr,
+                    double *W, double *s, double *am, double *ap) {
+  W[0] = qr[0] - ql[0];
+  s[0] = e->vel;
+  am[0] = fmin(e->vel, 0.0) * W[0];
+  ap[0] = fmax(e->vel, 0.0) * W[0];
+  return 1;
+}
+
+static const double kPi = 3.14159265358979323846;
+
+double fco_swirl_psi(const fco_params *par, double x, double y, double t) {
+  const double sx = sin(kPi * x), sy = sin(kPi * y);
+  return sx * sx * sy * sy * cos(kPi * t / par->period) / kPi;
+}
+
+double fco_swirl_edge(const fco_params *par, int32_t dir, double a, double b0,
+                      double b1, double t) {
+  if (dir == 0)   /* u = psi_y across an x = a edge */
+    return (fco_swirl_psi(par, a, b1, t) - fco_swirl_psi(par, a, b0, t)) / (b1 - b0);
+  /* v = -psi_x across a y = a edge */
+  return -(fco_swirl_psi(par, b1, a, t) - fco_swirl_psi(par, b0, a, t)) / (b1 - b0);
+}
+
 typedef struct { double u, v, c; } roe_avg;
 
 /* Roe averages of the edge pair, velocities in the (normal, tangential)
@@ -172,6 +197,7 @@ static int riemann(const fco_params *par, int dir, const edge_geom *e,
     case FCO_ADVECTION: return rp_advection(par, dir, ql, qr, W, s, am, ap);
     case FCO_SHALLOW: return rp_shallow(par, dir, ql, qr, W, s, am, ap);
     case FCO_SPHERE: return fco_rp_sphere(par, e, ql, qr, W, s, am, ap, fl);
+    case FCO_SWIRL: return rp_swirl(e, ql, qr, W, s, am, ap);
     default: return -1;
   }
 }
@@ -213,6 +239,14 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
   const fco_leaf *a = &mesh->leaves[p];
   const double dx = ldexp(1.0, -a->level) / m;   /* computational spacing */
   const int64_t NE = (int64_t)(m + 3) * (m + 2);
+  /* FCO_SWIRL: tree coordinates of the patch's corner and the mid-step time;
+   * the edge between cells n-1 and n of direction d at cell c of the other
+   * direction lies at (n - 1) dx and spans [(c - 1) dx, c dx] */
+  const double x0 = ldexp((double)a->ix, -a->level), y0 = ldexp((double)a->iy, -a->level);
+  const double tmid = par->time + 0.5 * dt;
+#define SWIRL_VEL(d, n, c)                                                           \
+  fco_swirl_edge(par, (d), ((d) == 0 ? x0 : y0) + ((n) - 1) * dx,                    \
+                 ((d) == 0 ? y0 : x0) + ((c) - 1) * dx, ((d) == 0 ? y0 : x0) + (c) * dx, tmid)
   for (int d = 0; d < 2; ++d) {
     memset(wk->F[d], 0, sizeof(double) * NE * meqn);
     memset(wk->AM[d], 0, sizeof(double) * NE * meqn);
@@ -245,6 +279,7 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
         } else {
           eg->gamma = 1.0;
         }
+        if (par->physics == FCO_SWIRL) eg->vel = SWIRL_VEL(d, e, r);
         nw = riemann(par, d, eg, ql, qr, &wk->W[e * MW * meqn], &wk->S[e * MW],
                      &wk->AM[d][eidx(m, e, r) * meqn],
                      &wk->AP[d][eidx(m, e, r) * meqn], &wk->FL[d][eidx(m, e, r)]);
@@ -297,6 +332,13 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
           int rc;
           if (par->physics == FCO_ADVECTION) {
             rc = tsplit_advection(par, d, psi, bm, bp);
+          } else if (par->physics == FCO_SWIRL) {
+            /* down through the receiving cell's lower transverse edge, up
+             * through its upper one, each at that edge's own velocity */
+            const double vlo = SWIRL_VEL(1 - d, r, col), vhi = SWIRL_VEL(1 - d, r + 1, col);
+            bm[0] = fmin(vlo, 0.0) * psi[0];
+            bp[0] = fmax(vhi, 0.0) * psi[0];
+            rc = 0;
           } else if (par->physics == FCO_SHALLOW) {
             rc = tsplit_shallow(par, d, ql, qr, psi, bm, bp);
           } else {
@@ -362,6 +404,7 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
         }
   }
 #undef KAP
+#undef SWIRL_VEL
   *numax = nmax;
   return 0;
 }
@@ -529,7 +572,8 @@ int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
     free(wk.eg);
   }
   if (rc) rc = -1;
-  if (rc == 0 && do_reflux) rc = reflux(mesh, par, q, qn, dt, phi);
+  /* the colour equation is not in conservation form: no reflux */
+  if (rc == 0 && do_reflux && par->physics != FCO_SWIRL) rc = reflux(mesh, par, q, qn, dt, phi);
   if (rc == 0 && mesh->sphere) fco_sphere_project(mesh, par, qn);
   free(phi);
   if (numax) *numax = nmax;
@@ -738,7 +782,8 @@ static int advance_level(subcycle *S, int32_t l, double t) {
 int fco_step_subcycled(const fco_mesh *mesh, const fco_params *par, const double *q,
                        double *qn, double dt, double *numax) {
   if (!mesh || !par || !q || !qn || par->m != mesh->m || par->meqn < 1 ||
-      par->meqn > FCO_MAXEQ || mesh->sphere || par->physics == FCO_SPHERE)
+      par->meqn > FCO_MAXEQ || mesh->sphere || par->physics == FCO_SPHERE ||
+      par->physics == FCO_SWIRL)
     return -1;
   const int32_t m = mesh->m, meqn = par->meqn;
   const int64_t NE = (int64_t)(m + 3) * (m + 2), FR = fco_frame(m);

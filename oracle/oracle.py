@@ -24,7 +24,7 @@ LEAF_DTYPE = np.dtype([("tree", "<i4"), ("level", "<i4"), ("ix", "<i4"),
 TREE_DTYPE = np.dtype([("nbr_tree", "<i4", (4,)), ("nbr_face", "<i4", (4,)),
                        ("orient", "<i4", (4,)), ("bc", "<i4", (4,))])
 
-ADVECTION, SHALLOW, SPHERE = 0, 1, 2
+ADVECTION, SHALLOW, SPHERE, SWIRL = 0, 1, 2, 3
 S = 30
 SIDE = 1 << S
 
@@ -33,7 +33,7 @@ class Params(C.Structure):
     _fields_ = [("m", C.c_int32), ("meqn", C.c_int32), ("physics", C.c_int32),
                 ("limiter", C.c_int32), ("transverse", C.c_int32),
                 ("pad", C.c_int32), ("g", C.c_double), ("ax", C.c_double),
-                ("ay", C.c_double)]
+                ("ay", C.c_double), ("period", C.c_double), ("time", C.c_double)]
 
 
 def build(force: bool = False) -> str:
@@ -69,6 +69,10 @@ def lib():
         L.fco_transfer.argtypes = [vp, vp, vp, vp, vp]
         L.fco_phi.argtypes = [i32, dp]
         L.fco_phi.restype = dp
+        L.fco_swirl_psi.argtypes = [vp, dp, dp, dp]
+        L.fco_swirl_psi.restype = dp
+        L.fco_swirl_edge.argtypes = [vp, i32, dp, dp, dp, dp]
+        L.fco_swirl_edge.restype = dp
         L.fco_riemann.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp]
         L.fco_tsplit.argtypes = [vp, i32, vp, vp, vp, vp, vp]
         L.fco_tsplit_sphere.argtypes = [vp, vp, vp, vp, vp, vp, i32]
@@ -108,9 +112,11 @@ def threads() -> int:
 
 
 def params(m, physics=ADVECTION, limiter=4, transverse=2, g=1.0, ax=0.0,
-           ay=0.0):
-    meqn = {ADVECTION: 1, SHALLOW: 3, SPHERE: 4}[physics]
-    return Params(m, meqn, physics, limiter, transverse, 0, g, ax, ay)
+           ay=0.0, period=1.0, time=0.0):
+    """SWIRL: the prescribed swirl flow of period `period`; `time` is the
+    time of the state the next step starts from (the caller advances it)."""
+    meqn = {ADVECTION: 1, SHALLOW: 3, SPHERE: 4, SWIRL: 1}[physics]
+    return Params(m, meqn, physics, limiter, transverse, 0, g, ax, ay, period, time)
 
 
 def sfc_sort(leaves: np.ndarray) -> np.ndarray:
@@ -286,6 +292,17 @@ def tsplit(par, direction, ql, qr, psi):
     return bm, bp
 
 
+def swirl_psi(par, x, y, t) -> float:
+    """The swirl stream function (SWIRL) at tree coordinates (x, y), time t."""
+    return lib().fco_swirl_psi(C.byref(par), x, y, t)
+
+
+def swirl_edge(par, direction, a, b0, b1, t) -> float:
+    """Normal velocity of the `direction` edge at coordinate a spanning
+    [b0, b1] in the other coordinate (SWIRL)."""
+    return lib().fco_swirl_edge(C.byref(par), direction, a, b0, b1, t)
+
+
 # -------------------------------------------------------------------------
 # a plain driver: ghost fill + step, fixed or CFL-controlled dt, regrid
 # -------------------------------------------------------------------------
@@ -368,7 +385,8 @@ def dilate_tags(mesh, tg, lmax) -> np.ndarray:
 # cubed sphere geometry and solver pieces
 # -------------------------------------------------------------------------
 class EdgeGeom(C.Structure):
-    _fields_ = [("gamma", C.c_double), ("n", C.c_double * 3), ("t", C.c_double * 3)]
+    _fields_ = [("gamma", C.c_double), ("n", C.c_double * 3), ("t", C.c_double * 3),
+                ("vel", C.c_double)]
 
 
 def sphere_kappa(mesh, p, i, j) -> float:
