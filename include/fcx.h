@@ -51,7 +51,18 @@ extern "C" {
 #define FCX_ENEG (-6)      /* non-positive depth met by a Riemann solve    */
 #define FCX_ESTATE (-7)    /* call out of order (e.g. no forest uploaded)  */
 
-enum { FCX_ADVECTION = 0, FCX_SHALLOW = 1, FCX_SPHERE = 2 };
+/* FCX_SWIRL: a scalar carried by a prescribed divergence-free flow, the
+ * colour equation q_t + u q_x + v q_y = 0 with (u, v) = (psi_y, -psi_x) and
+ * the stream function psi(x, y, t) = sin^2(pi x) sin^2(pi y) cos(pi t / T)
+ * / pi on each tree's unit square (T = period): a stand-in for the
+ * unpublished field of the paper's Sec. 5 advection example.  Each cell
+ * edge carries the normal velocity of psi's difference between its two
+ * corners over its length (the discrete field is exactly divergence free),
+ * at the middle of the step: t is the context's simulated time
+ * (fcx_sim_time) plus dt / 2.  The equation is not in conservation form,
+ * so fcx_reflux leaves the state as it is.  Planar forests, global time
+ * step only (fcx_advance_subcycled and batches refuse it). */
+enum { FCX_ADVECTION = 0, FCX_SHALLOW = 1, FCX_SPHERE = 2, FCX_SWIRL = 3 };
 
 typedef struct fcx_ctx fcx_ctx;
 typedef struct fcx_batch fcx_batch;
@@ -73,9 +84,10 @@ typedef struct {
 typedef struct {
   int32_t m;           /* cells per patch side: 8, 16 or 32               */
   int32_t precision;   /* 32 or 64: element type of q and ghost           */
-  int32_t physics;     /* FCX_ADVECTION (meqn 1), FCX_SHALLOW (meqn 3) or
+  int32_t physics;     /* FCX_ADVECTION (meqn 1), FCX_SHALLOW (meqn 3),
                           FCX_SPHERE (meqn 4: h and 3D momentum on the
-                          cubed sphere; see fcx_sphere_geometry)          */
+                          cubed sphere; see fcx_sphere_geometry) or
+                          FCX_SWIRL (meqn 1)                              */
   int32_t limiter;     /* wave limiter: 0 none, 1 minmod, 2 superbee,
                           3 van Leer, 4 MC (LeVeque 2002, Sec. 6.12)      */
   int32_t transverse;  /* 0 none, 1 fluctuations, 2 fluctuations and
@@ -97,6 +109,7 @@ typedef struct {
   double ax, ay;       /* advection velocity in reference coordinates     */
   double cfl_desired;  /* target Courant number for the next dt           */
   double cfl_max;      /* larger Courant numbers reject or flag the step  */
+  double period;       /* FCX_SWIRL: period T of the flow (> 0)           */
 } fcx_config;
 
 const char *fcx_last_error(void);

@@ -296,8 +296,10 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   if (cfg->precision != 32 && cfg->precision != 64)
     return fail(FCX_EINVAL, "precision must be 32 or 64");
   if (cfg->physics != FCX_ADVECTION && cfg->physics != FCX_SHALLOW &&
-      cfg->physics != FCX_SPHERE)
+      cfg->physics != FCX_SPHERE && cfg->physics != FCX_SWIRL)
     return fail(FCX_EINVAL, "unknown physics");
+  if (cfg->physics == FCX_SWIRL && !(cfg->period > 0))
+    return fail(FCX_EINVAL, "the swirl flow needs a positive period");
   if (cfg->limiter < 0 || cfg->limiter > 4 || cfg->transverse < 0 ||
       cfg->transverse > 2)
     return fail(FCX_EINVAL, "bad limiter or transverse mode");
@@ -331,7 +333,9 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   c->cfg.threads = threads;
   c->threads_auto = cfg->threads == 0;
   c->tile = tile;
-  c->meqn = cfg->physics == FCX_ADVECTION ? 1 : (cfg->physics == FCX_SHALLOW ? 3 : 4);
+  c->meqn = (cfg->physics == FCX_ADVECTION || cfg->physics == FCX_SWIRL)
+                ? 1
+                : (cfg->physics == FCX_SHALLOW ? 3 : 4);
   {
     int dev = 0;
     hipDeviceProp_t prop;
@@ -606,7 +610,8 @@ int fcx_patch_table(fcx_ctx* c, int64_t cap_items, void* recs, int32_t* phislot,
 
 // ---------------------------------------------------------------------------
 static KPhys kphys(const fcx_ctx* c) {
-  return KPhys{c->cfg.g, c->cfg.ax, c->cfg.ay, c->cfg.limiter, c->cfg.transverse};
+  return KPhys{c->cfg.g, c->cfg.ax, c->cfg.ay, c->cfg.limiter, c->cfg.transverse,
+               c->cfg.period};
 }
 
 template <typename R, int PHYS>
@@ -627,7 +632,8 @@ int fcx_ghost_fill(fcx_ctx* c, const void* q, void* ghost, void* stream) {
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
-  if (c->cfg.physics == FCX_ADVECTION)
+  // (a scalar either way: the prescribed flow's ghost cells are advection's)
+  if (c->cfg.physics == FCX_ADVECTION || c->cfg.physics == FCX_SWIRL)
     return dp ? launch_ghost<double, FCX_ADVECTION>(c, q, ghost, s)
               : launch_ghost<float, FCX_ADVECTION>(c, q, ghost, s);
   if (c->cfg.physics == FCX_SPHERE)
@@ -669,6 +675,7 @@ static int launch_step_t(fcx_ctx* c, const void* q, const void* ghost, void* qn,
   a.ntiles = int32_t(c->cur.P * tps * tps);
   a.ph = kphys(c);
   a.order = c->cur.order;
+  a.tsim = c->tsim.p;
   if constexpr (PHYS == FCX_ADVECTION) {
     // advection tiles: one wavefront each, kAdvWaves per workgroup
     const dim3 grid(unsigned((a.ntiles + kAdvWaves - 1) / kAdvWaves));
@@ -747,6 +754,9 @@ static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_step_m<double, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s)
               : launch_step_m<float, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s);
+  if (c->cfg.physics == FCX_SWIRL)
+    return dp ? launch_step_m<double, FCX_SWIRL, FUSED>(c, q, ghost, qn, dt, numax, s)
+              : launch_step_m<float, FCX_SWIRL, FUSED>(c, q, ghost, qn, dt, numax, s);
   return dp ? launch_step_m<double, FCX_SHALLOW, FUSED>(c, q, ghost, qn, dt, numax, s)
             : launch_step_m<float, FCX_SHALLOW, FUSED>(c, q, ghost, qn, dt, numax, s);
 }
@@ -797,7 +807,9 @@ template <typename R, int PHYS, bool NEXT>
 static int launch_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt,
                          hipStream_t s, NextDtArgs nd = {}) {
   const int m = c->cfg.m;
-  const int32_t n = c->cur.n_reflux_x + c->cur.n_reflux_y;
+  // (the prescribed-flow advection is not in conservation form: no items)
+  const int32_t n =
+      c->cfg.physics == FCX_SWIRL ? 0 : c->cur.n_reflux_x + c->cur.n_reflux_y;
   if (n == 0 && !NEXT) return FCX_OK;
   const int64_t tot = int64_t(n) * m;
   int64_t g = std::max<int64_t>(1, (tot + 255) / 256);
@@ -839,7 +851,7 @@ int fcx_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt, void* stre
   if (c->cfg.physics == FCX_SPHERE)
     return dp ? launch_sphere_reflux<double>(c, q, qn, dt, s)
               : launch_sphere_reflux<float>(c, q, qn, dt, s);
-  if (c->cfg.physics == FCX_ADVECTION)
+  if (c->cfg.physics == FCX_ADVECTION || c->cfg.physics == FCX_SWIRL)
     return dp ? launch_reflux<double, FCX_ADVECTION, false>(c, q, qn, dt, s)
               : launch_reflux<float, FCX_ADVECTION, false>(c, q, qn, dt, s);
   return dp ? launch_reflux<double, FCX_SHALLOW, false>(c, q, qn, dt, s)
@@ -1304,8 +1316,8 @@ int fcx_batch_create(int32_t n, fcx_ctx* const* forests, fcx_batch** out) {
       return fail(FCX_ESTATE, "every context needs an uploaded forest");
     if (forests[f]->cfg.precision != forests[0]->cfg.precision)
       return fail(FCX_EINVAL, "all forests of a batch share one precision");
-    if (forests[f]->cfg.physics == FCX_SPHERE)
-      return fail(FCX_EINVAL, "sphere forests are not batched");
+    if (forests[f]->cfg.physics == FCX_SPHERE || forests[f]->cfg.physics == FCX_SWIRL)
+      return fail(FCX_EINVAL, "sphere and prescribed-flow forests are not batched");
   }
   fcx_batch* b = new fcx_batch;
   b->n = n;
@@ -1694,7 +1706,7 @@ int fcx_advance(fcx_ctx* c, const void* q, void* qn, double* dt, double* numax,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const NextDtArgs nd = next_args(c, numax, dt, status, c->cfg.redo);
   const bool dp = c->cfg.precision == 64;
-  if (c->cfg.physics == FCX_ADVECTION)
+  if (c->cfg.physics == FCX_ADVECTION || c->cfg.physics == FCX_SWIRL)
     return dp ? launch_reflux<double, FCX_ADVECTION, true>(c, q, qn, dt, s, nd)
               : launch_reflux<float, FCX_ADVECTION, true>(c, q, qn, dt, s, nd);
   return dp ? launch_reflux<double, FCX_SHALLOW, true>(c, q, qn, dt, s, nd)
@@ -1904,6 +1916,8 @@ int fcx_advance_subcycled(fcx_ctx* c, const void* q, void* q_new, void* work, vo
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no sub-cycled step on the sphere");
+  if (c->cfg.physics == FCX_SWIRL)
+    return fail(FCX_EINVAL, "no sub-cycled step for the prescribed flow");
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
   if (c->cfg.physics == FCX_ADVECTION)

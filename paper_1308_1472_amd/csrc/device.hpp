@@ -38,12 +38,14 @@ constexpr int32_t kErrNested = 4;
 struct KPhys {
   double g, ax, ay;
   int32_t limiter, transverse;
+  double period;                           // FCX_SWIRL: period of the flow
 };
 
 template <int PHYS> struct PhysTraits;
 template <> struct PhysTraits<FCX_ADVECTION> { static constexpr int MEQN = 1; };
 template <> struct PhysTraits<FCX_SHALLOW> { static constexpr int MEQN = 3; };
 template <> struct PhysTraits<FCX_SPHERE> { static constexpr int MEQN = 4; };
+template <> struct PhysTraits<FCX_SWIRL> { static constexpr int MEQN = 1; };
 
 __device__ __forceinline__ void xf_apply(int32_t code, int32_t x, int32_t y,
                                          int32_t& xo, int32_t& yo) {

@@ -44,6 +44,7 @@ struct StepArgs {
   // dispatch order; null: slot order)
   const int32_t* order = nullptr;
   KPhys ph;
+  const double* tsim = nullptr;   // FCX_SWIRL: time of the state q
 };
 
 template <int T> struct TileThreads { static constexpr int value = T * T >= 256 ? 256 : T * T; };
@@ -137,7 +138,7 @@ __device__ __forceinline__ void halo_value(const StepArgs<R>& A, const PatchRec&
 template <typename R, int PHYS, int T, int NT>
 struct TileLds {
   static constexpr int MEQN = PhysTraits<PHYS>::MEQN;
-  static constexpr int WD = PHYS == FCX_ADVECTION ? 1 : 7;   // wave data per edge
+  static constexpr int WD = PHYS == FCX_SHALLOW ? 7 : 1;     // wave data per edge
   // per-cell primitives (sqrt h, u, v) are kept for FP64 shallow water; in
   // FP32 each edge forms them from the state (an rsqrt and a few products),
   // which leaves room in the LDS for one more resident tile per CU
@@ -152,6 +153,9 @@ struct TileLds {
   R tdn[MEQN][NR * T];        //   and lower transverse edge
   R fb[2][MEQN][T];           // normal terms at the tile's two faces
   double red[NT / 64 > 0 ? NT / 64 : 1];
+  // FCX_SWIRL: sin^2(pi x) at the tile frame's corner columns -2 .. T+2
+  // (x0 + (i0 + a - 2) dx, a = 0 .. T+4), sin^2(pi y) likewise
+  double sw[PHYS == FCX_SWIRL ? 2 : 1][PHYS == FCX_SWIRL ? T + 5 : 1];
 };
 
 // tid_in: the thread's index when the caller has hidden it from the
@@ -253,6 +257,23 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
     }
     stage((cj + 1) * F + (ci + 1), v);
   }
+  // FCX_SWIRL: the stream function is separable, psi = k sx(x) sy(y) with
+  // k = cos(pi t / T) / pi, so the tile needs sin^2 at its frame's corner
+  // lines only (FP64); an edge's normal velocity is then a product and a
+  // difference of these (the stream function's difference over the edge)
+  double swk = 0;                           // k / dx
+  if constexpr (PHYS == FCX_SWIRL) {
+    const double pi = 3.14159265358979323846;
+    const double tmid = *A.tsim + 0.5 * dtv;
+    swk = cos(pi * tmid / A.ph.period) / pi / dxd;
+    const double x0 = ldexp(double(rp.ix), -level), y0 = ldexp(double(rp.iy), -level);
+    for (int k = tid; k < 2 * (T + 5); k += NT) {
+      const int ax = k / (T + 5), a = k % (T + 5);
+      const double c = (ax == 0 ? x0 + double(i0 + a - 2) * dxd : y0 + double(j0 + a - 2) * dxd);
+      const double sn = sin(pi * c);
+      L.sw[ax][a] = sn * sn;
+    }
+  }
   __syncthreads();
 
   R dq[CPT][MEQN], phx[CPT][MEQN], phy[CPT][MEQN];
@@ -282,11 +303,24 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
                                                   : (n - 1) * T + (r - 1); };
     auto uidx = [&](int r, int n) { return d == 0 ? r * T + (n - 1)
                                                   : (n - 1) * NR + r; };
+    // FCX_SWIRL: normal velocity of the direction-dd edge between frame
+    // cells e - 1 and e (of direction dd) at frame cell r of the other
+    // direction: u = psi_y (dd = 0), v = -psi_x (dd = 1)
+    auto swirl_vel = [&](int dd, int e, int r) -> R {
+      if constexpr (PHYS == FCX_SWIRL) {
+        const double* nrm = L.sw[dd];
+        const double* trn = L.sw[1 - dd];
+        const double v = nrm[e + 1] * (trn[r + 2] - trn[r + 1]) * swk;
+        return R(dd == 0 ? v : -v);
+      } else {
+        return R(0);
+      }
+    };
 
     // ---- phase A: Riemann solves ------------------------------------
     // (advection: the wave is the jump of the staged state, which phase B
     // forms where it needs it, so there is no phase A and no barrier after it)
-    if (PHYS != FCX_ADVECTION) {
+    if (PHYS != FCX_ADVECTION && PHYS != FCX_SWIRL) {
     for (int idx = tid; idx < NR * NE; idx += NT) {
       const int r = d == 0 ? idx / NE : idx % NR;
       const int e = d == 0 ? idx % NE : idx / NR;
@@ -335,17 +369,19 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
       const int e = d == 0 ? idx % (T + 1) + 1 : idx / NR + 1;
       const bool inner = (r >= 1 && r <= T);
       R am[MEQN], ap[MEQN], cq[MEQN];
-      if (PHYS == FCX_ADVECTION) {
+      if (PHYS == FCX_ADVECTION || PHYS == FCX_SWIRL) {
+        // the edge's speed: constant, or the prescribed flow's
+        const R ae = PHYS == FCX_SWIRL ? swirl_vel(d, e, r) : an;
         auto jump = [&](int ee) { return qs[0][qidx(r, ee)] - qs[0][qidx(r, ee - 1)]; };
         const R w = jump(e);
-        am[0] = min_(an, R(0)) * w;
-        ap[0] = max_(an, R(0)) * w;
+        am[0] = min_(ae, R(0)) * w;
+        ap[0] = max_(ae, R(0)) * w;
         cq[0] = R(0);
-        if (inner) smax = max_(smax, fabs(an));
+        if (inner) smax = max_(smax, fabs(ae));
         if (w != R(0)) {
-          const R wu = jump(an > R(0) ? e - 1 : e + 1);
+          const R wu = jump(ae > R(0) ? e - 1 : e + 1);
           const R th = (wu * w) * rcp_(w * w);
-          const R s = fabs(an);
+          const R s = fabs(ae);
           cq[0] = s * (R(1) - dtdx * s) * limiter_phi(lim, th) * w;
         }
       } else {
@@ -409,6 +445,18 @@ __device__ __forceinline__ void tile_step(const StepArgs<R>& A, int p, int tx, i
           lup[0] = bp * amt[0];
           rdn[0] = bm * apt[0];
           rup[0] = bp * apt[0];
+        } else if (PHYS == FCX_SWIRL) {
+          // each part leaves its receiving cell (column e - 1 for the
+          // left-going one, e for the right-going one) down through the
+          // cell's lower transverse edge and up through its upper one, at
+          // those edges' own velocities
+          const int od = 1 - d;
+          const R vll = swirl_vel(od, r, e - 1), vlh = swirl_vel(od, r + 1, e - 1);
+          const R vrl = swirl_vel(od, r, e), vrh = swirl_vel(od, r + 1, e);
+          ldn[0] = -half_dtdx * min_(vll, R(0)) * amt[0];
+          lup[0] = -half_dtdx * max_(vlh, R(0)) * amt[0];
+          rdn[0] = -half_dtdx * min_(vrl, R(0)) * apt[0];
+          rup[0] = -half_dtdx * max_(vrh, R(0)) * apt[0];
         } else {
           const int b = bidx(r, e);
           const R u = wb[3][b], v = wb[4][b], c = wb[5][b];

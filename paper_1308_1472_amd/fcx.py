@@ -20,7 +20,7 @@ LEAF_DTYPE = np.dtype([("tree", "<i4"), ("level", "<i4"), ("ix", "<i4"),
 TREE_DTYPE = np.dtype([("nbr_tree", "<i4", (4,)), ("nbr_face", "<i4", (4,)),
                        ("orient", "<i4", (4,)), ("bc", "<i4", (4,))])
 
-FCX_ADVECTION, FCX_SHALLOW, FCX_SPHERE = 0, 1, 2
+FCX_ADVECTION, FCX_SHALLOW, FCX_SPHERE, FCX_SWIRL = 0, 1, 2, 3
 GEO_FRAMES = 18          # geometry table frames per patch (fcx_sphere_geometry)
 ERRORS = {-1: "FCX_EINVAL", -2: "FCX_EBALANCE", -3: "FCX_ENOMEM",
           -4: "FCX_EHIP", -5: "FCX_ECFL", -6: "FCX_ENEG", -7: "FCX_ESTATE"}
@@ -59,7 +59,8 @@ class Config(C.Structure):
                 ("transverse", C.c_int32), ("tile", C.c_int32),
                 ("threads", C.c_int32), ("redo", C.c_int32),
                 ("g", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
-                ("cfl_desired", C.c_double), ("cfl_max", C.c_double)]
+                ("cfl_desired", C.c_double), ("cfl_max", C.c_double),
+                ("period", C.c_double)]
 
 
 _lib = None
@@ -187,9 +188,10 @@ def regrid_leaves(trees, leaves, tags, lmin, lmax) -> np.ndarray:
 
 def config(m, precision=64, physics=FCX_SHALLOW, limiter=4, transverse=2,
            tile=0, threads=0, g=1.0, ax=0.0, ay=0.0, cfl_desired=0.9,
-           cfl_max=1.0, redo=1):
+           cfl_max=1.0, redo=1, period=1.0):
+    """period: FCX_SWIRL's flow period."""
     return Config(m, precision, physics, limiter, transverse, tile, threads,
-                  int(redo), g, ax, ay, cfl_desired, cfl_max)
+                  int(redo), g, ax, ay, cfl_desired, cfl_max, period)
 
 
 def _stream(stream):
@@ -256,7 +258,7 @@ class Context:
 
     def __init__(self, cfg: Config, trees):
         self.cfg = cfg
-        self.meqn = {FCX_ADVECTION: 1, FCX_SHALLOW: 3, FCX_SPHERE: 4}[cfg.physics]
+        self.meqn = {FCX_ADVECTION: 1, FCX_SHALLOW: 3, FCX_SPHERE: 4, FCX_SWIRL: 1}[cfg.physics]
         self.trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
         h = C.c_void_p()
         _check(lib().fcx_create(C.byref(cfg), len(self.trees),
