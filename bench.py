@@ -47,7 +47,8 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "sphere",
-                                       "mlp", "copy", "cpu", "subcycle", "meshing", "all"],
+                                       "mlp", "copy", "cpu", "subcycle", "meshing", "swirl",
+                                       "all"],
                     default="all")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--sphere-steps", type=int, default=1000)
@@ -350,6 +351,91 @@ def run_meshing(precision=32, m=8, lmin=3, lmax=8, T=0.25, thr=0.5):
                      "mass_rel_change": sums.item() / m0 - 1.0, "status": status,
                      "status_bits": status_bits([status])}
     base = out["uniform"]["seconds"]
+    for name in out:
+        out[name]["speedup_vs_uniform"] = base / out[name]["seconds"]
+    return out
+
+
+def run_swirl(precision=32, m=8, lmin=3, lmax=6, T=2.0, thr=0.2):
+    """The paper's advection example (Sec. 5, Example 1): q = 1 on the left
+    half of the unit square and 0 on the right, carried by a twisting flow
+    that the paper does not give.  Stand-in flow (FCX_SWIRL): the swirl
+    stream function sin^2(pi x) sin^2(pi y) cos(pi t / T) / pi, which
+    reverses at T / 2, so the exact state after one period T is the initial
+    one.  Walled square, m = 8, levels 3-6 (the paper's 64^2 to 512^2),
+    refined where max - min of q over a patch exceeds 0.2 (the front smears
+    as it winds up), CFL 0.9 with the redo rule; uniform level 6 for
+    comparison.  Runs fcx_run in chunks, each sized from the remaining time
+    over the current dt, until the simulated time reaches T (it ends at most
+    one step past T); reports wall clock, cell updates, rate and the L1 error
+    against the initial state."""
+    import numpy as np
+    import torch
+    from paper_1308_1472_amd import fcx
+    from paper_1308_1472_amd import inputs as I
+    trees, pl = I.walled_square()
+    halves = lambda x, y: np.where(x < 0.5, 1.0, 0.0) + 0.0 * y
+    dtype = torch.float32 if precision == 32 else torch.float64
+
+    def make(uniform):
+        cfg = fcx.config(m, precision, fcx.FCX_SWIRL, period=T)
+        ctx = fcx.Context(cfg, trees)
+        if uniform:
+            leaves = fcx.sfc_sort(I.uniform_leaves(1, lmax))
+        else:
+            leaves = fcx.sfc_sort(I.uniform_leaves(1, lmin))
+            for _ in range(2 * (lmax - lmin) + 2):
+                ctx.upload_forest(leaves)
+                q = torch.from_numpy(I.state_from(leaves, m, halves, pl).ravel()).to(dtype).cuda()
+                g = torch.empty(ctx.ghost_elems(), dtype=dtype, device="cuda")
+                ctx.regrid(q, g, 0, thr, lmin, lmax)
+                new = ctx.leaves()
+                if len(new) == len(leaves) and (new == leaves).all():
+                    break
+                leaves = new
+        ctx.upload_forest(leaves)
+        pmax = 1 << (2 * lmax)
+        bufs = [torch.empty(pmax * m * m, dtype=dtype, device="cuda") for _ in range(2)]
+        ghost = torch.empty(pmax * (8 * m + 16), dtype=dtype, device="cuda")
+        q0 = I.state_from(leaves, m, halves, pl)
+        bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
+        return ctx, bufs, ghost, torch.full((1,), 0.9 / (m << lmax), dtype=torch.float64,
+                                           device="cuda")
+
+    out = {}
+    for name, every, uniform in (("uniform_level6", 0, True), ("amr_every_4", 4, False),
+                                 ("amr_every_step", 1, False)):
+        for rep in range(2):                      # the first run warms up
+            ctx, bufs, ghost, dt = make(uniform)
+            nu = torch.zeros_like(dt)
+            st = torch.zeros(1, dtype=torch.int32, device="cuda")
+            attempts, cells, which, k = 0, 0, 0, 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while True:
+                left = T - ctx.sim_time()
+                if left <= 0:
+                    break
+                chunk = max(1, min(256, int(left / dt.item())))
+                a, b = bufs[which], bufs[1 - which]
+                w, c = ctx.run(a, b, ghost, chunk, k, every, 0, thr, lmin, lmax, dt, nu, st,
+                               fused=1)
+                which = which if w == 0 else 1 - which
+                attempts, cells, k = attempts + chunk, cells + c, k + chunk
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        lv = ctx.leaves()
+        want = I.state_from(lv, m, halves, pl)
+        got = bufs[which][:ctx.state_elems()].double().cpu().numpy().reshape(want.shape)
+        h = np.ldexp(1.0, -lv["level"].astype(int)) / m
+        l1 = float(np.sum(np.abs(got - want)[:, 0] * (h ** 2)[:, None, None]))
+        acc, rej, _ = ctx.step_stats()
+        status = int(st.item())
+        out[name] = {"seconds": el, "attempts": attempts, "accepted": acc, "rejected": rej,
+                     "sim_time": ctx.sim_time(), "cell_updates": cells, "rate": cells / el,
+                     "patches_last": ctx.num_patches(), "l1_error_vs_initial": l1,
+                     "status": status, "status_bits": status_bits([status])}
+    base = out["uniform_level6"]["seconds"]
     for name in out:
         out[name]["speedup_vs_uniform"] = base / out[name]["seconds"]
     return out
@@ -832,20 +918,24 @@ def main():
     if args.only in ("meshing", "all"):
         res["meshing"] = run_meshing()
         print(f"# meshing strategies: {res['meshing']}", file=sys.stderr, flush=True)
+    if args.only in ("swirl", "all"):
+        res["swirl"] = run_swirl()
+        print(f"# example 1 (stand-in swirl): {res['swirl']}", file=sys.stderr, flush=True)
     if args.only in ("mlp", "all"):
         res["mlp"] = run_mlp()
         print(f"# mlp: {res['mlp']}", file=sys.stderr, flush=True)
     # timed legs whose status words carry a bit that marks a wrong step
     bad = {k: r.get("status_bits") for k, r in res.items()
            if isinstance(r, dict) and (int(r.get("status", 0)) & BAD_BITS or r.get("status_bad"))}
-    for leg in ("subcycle", "meshing"):
+    for leg in ("subcycle", "meshing", "swirl"):
         for k, r in res.get(leg, {}).items():
             if r["status"] & BAD_BITS:
                 bad[leg + "/" + k] = r["status_bits"]
     head = res.get("fp32") or res.get("fp64") or res.get("large32")
     if head is None:
         print(json.dumps({k: res.get(k) for k in ("batch", "batch64", "sphere", "sphere64",
-                                                  "subcycle", "meshing", "mlp") if k in res}),
+                                                  "subcycle", "meshing", "swirl", "mlp")
+                          if k in res}),
               flush=True)
         sys.exit(3 if bad else 0)
     steps = args.steps if "fp32" in res or "fp64" in res else args.large_steps
@@ -982,6 +1072,12 @@ def main():
             "field is not given): 0/1 disk carried by a = (1, 1/2) on the periodic unit "
             "square, m = 8, levels 3-8 (uniform: level 8), max - min > 1/2 refines, "
             "CFL 0.9, FP32, to t = 0.25"))
+    if "swirl" in res:
+        out["example1_swirl"] = dict(res["swirl"], workload=(
+            "the paper's advection example 1 with a stand-in twisting flow (the swirl "
+            "stream function, reversing at T/2 = 1): 0/1 halves on the walled unit square, "
+            "m = 8, levels 3-6 (uniform: level 6), max - min > 0.2 refines, CFL 0.9 with "
+            "redo, FP32, over one period T = 2 (exact state: the initial one)"))
     if "mlp" in res:
         out["learned_tagging_mlp"] = res["mlp"]
     if not args.no_cpu_baseline and "fp32" in res:
