@@ -47,7 +47,17 @@ typedef struct {
  * every cell edge carries the normal velocity of psi's difference between
  * the edge's two corners over its length (so the discrete field is exactly
  * divergence free), taken at the middle of the step (par->time + dt / 2). */
-enum { FCO_ADVECTION = 0, FCO_SHALLOW = 1, FCO_SPHERE = 2, FCO_SWIRL = 3 };
+/* FCO_ROTATION: the colour equation on the cubed sphere carried by a rigid
+ * rotation (the paper's Sec. 5 sphere example), velocity u = Omega w x r with
+ * unit axis w = par->axis normalised and Omega = 2 pi / par->period.  u is
+ * the surface curl of the stream function psi = Omega w.r, so the flux of u
+ * through a great-circle edge from corner a to corner b is psi's difference
+ * between them, Omega w.(b - a), up to the orientation of the edge: every
+ * edge carries that flux over its computational length, signed towards
+ * higher index (exactly divergence free).  The update is the capacity form
+ * of the colour equation; no reflux (not a conservation law). */
+enum { FCO_ADVECTION = 0, FCO_SHALLOW = 1, FCO_SPHERE = 2, FCO_SWIRL = 3,
+       FCO_ROTATION = 4 };
 
 typedef struct {
   int32_t m;           /* cells per patch side (even, >= 4)            */
@@ -60,6 +70,7 @@ typedef struct {
   double ax, ay;       /* advection velocity (computational coords)    */
   double period;       /* FCO_SWIRL: period T of the flow              */
   double time;         /* FCO_SWIRL: time of the state a step starts from */
+  double axis[3];      /* FCO_ROTATION: rotation axis (any length > 0)   */
 } fco_params;
 
 typedef struct fco_mesh fco_mesh;
@@ -149,6 +160,11 @@ int  fco_riemann(const fco_params *par, int32_t dir, const double *ql,
 double fco_swirl_psi(const fco_params *par, double x, double y, double t);
 double fco_swirl_edge(const fco_params *par, int32_t dir, double a, double b0,
                       double b1, double t);
+/* FCO_ROTATION: the flux of the rigid rotation through the low-side
+ * dir-edge of frame cell (i, j) of patch p over the computational cell
+ * size, signed towards higher index (mesh built with sphere = 1) */
+double fco_rotation_edge(const fco_mesh *mesh, const fco_params *par, int64_t p,
+                         int32_t dir, int32_t i, int32_t j);
 /* transverse split of a fluctuation psi from the dir-edge with states ql,
  * qr into the parts moving down (bm) and up (bp) the other direction
  * (planar physics) */

@@ -133,7 +133,9 @@ static void cross_close(const double a[3], const double b[3], double o[3]) {
   cross3(mid, d, o);
 }
 
-enum { GK = 0, GC = 1, GE = 4, GN = 18 };   /* table offsets, in frames */
+/* table offsets, in frames: capacity, centre, edges (gamma, n, t per
+ * direction), and the chord b - a of each low-side edge (per direction) */
+enum { GK = 0, GC = 1, GE = 4, GD = 18, GN = 24 };
 
 /* corner points of patch p: canonical (carried into the tree that holds
  * them) and the patch's own face mapping extended (used for the corner
@@ -209,6 +211,8 @@ int fco_sphere_build(fco_mesh *mesh) {
           const double rl = sqrt(dot3(rm, rm));
           for (int c = 0; c < 3; ++c) rm[c] /= rl;
           cross3(rm, nn, tt);
+          double *ch = &g[GD * FR + (dir * FR + f) * 3];
+          for (int c = 0; c < 3; ++c) ch[c] = eb[c] - ea[c];
           double *e = &g[GE * FR + (dir * FR + f) * 7];
           e[0] = atan2(len, dot3(ea, eb)) / dx;
           for (int c = 0; c < 3; ++c) e[1 + c] = nn[c];
@@ -243,6 +247,21 @@ void fco_sphere_centre(const fco_mesh *mesh, int64_t p, int32_t i, int32_t j,
   const int64_t FR = fco_frame(mesh->m);
   const double *c = &mesh->geo[p * GN * FR + GC * FR + 3 * fco_fidx(mesh->m, i, j)];
   for (int k = 0; k < 3; ++k) r[k] = c[k];
+}
+
+double fco_rotation_edge(const fco_mesh *mesh, const fco_params *par, int64_t p,
+                         int32_t dir, int32_t i, int32_t j) {
+  const int64_t FR = fco_frame(mesh->m);
+  const double *ch = &mesh->geo[p * GN * FR + GD * FR + (dir * FR + fco_fidx(mesh->m, i, j)) * 3];
+  const double *w = par->axis;
+  const double wl = sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  const double omega = 2.0 * 3.14159265358979323846 / par->period;
+  const double dx = ldexp(1.0, -mesh->leaves[p].level) / mesh->m;
+  /* the xi-edge runs from corner (i-1, j-1) to (i-1, j) and higher i lies
+   * to its right; the eta-edge runs from (i-1, j-1) to (i, j-1) with higher
+   * j to its left: the flux towards higher index is +dpsi and -dpsi */
+  const double dpsi = omega * (w[0] * ch[0] + w[1] * ch[1] + w[2] * ch[2]) / wl;
+  return (dir == 0 ? dpsi : -dpsi) / dx;
 }
 
 /* ---- solver ------------------------------------------------------------ */

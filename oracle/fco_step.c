@@ -78,7 +78,8 @@ static int rp_advection(const fco_params *par, int dir, const double *ql,
   return 1;
 }
 
-/* colour equation with the edge's own normal velocity (FCO_SWIRL) */
+/* colour equation with the edge's own normal velocity (FCO_SWIRL,
+ * FCO_ROTATION) */
 static int rp_swirl(const edge_geom *e, const double *ql, const double *qr,
                     double *W, double *s, double *am, double *ap) {
   W[0] = qr[0] - ql[0];
@@ -197,7 +198,8 @@ static int riemann(const fco_params *par, int dir, const edge_geom *e,
     case FCO_ADVECTION: return rp_advection(par, dir, ql, qr, W, s, am, ap);
     case FCO_SHALLOW: return rp_shallow(par, dir, ql, qr, W, s, am, ap);
     case FCO_SPHERE: return fco_rp_sphere(par, e, ql, qr, W, s, am, ap, fl);
-    case FCO_SWIRL: return rp_swirl(e, ql, qr, W, s, am, ap);
+    case FCO_SWIRL:
+    case FCO_ROTATION: return rp_swirl(e, ql, qr, W, s, am, ap);
     default: return -1;
   }
 }
@@ -280,6 +282,7 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
           eg->gamma = 1.0;
         }
         if (par->physics == FCO_SWIRL) eg->vel = SWIRL_VEL(d, e, r);
+        if (par->physics == FCO_ROTATION) eg->vel = fco_rotation_edge(mesh, par, p, d, ir, jr);
         nw = riemann(par, d, eg, ql, qr, &wk->W[e * MW * meqn], &wk->S[e * MW],
                      &wk->AM[d][eidx(m, e, r) * meqn],
                      &wk->AP[d][eidx(m, e, r) * meqn], &wk->FL[d][eidx(m, e, r)]);
@@ -332,10 +335,20 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
           int rc;
           if (par->physics == FCO_ADVECTION) {
             rc = tsplit_advection(par, d, psi, bm, bp);
-          } else if (par->physics == FCO_SWIRL) {
+          } else if (par->physics == FCO_SWIRL || par->physics == FCO_ROTATION) {
             /* down through the receiving cell's lower transverse edge, up
              * through its upper one, each at that edge's own velocity */
-            const double vlo = SWIRL_VEL(1 - d, r, col), vhi = SWIRL_VEL(1 - d, r + 1, col);
+            double vlo, vhi;
+            if (par->physics == FCO_SWIRL) {
+              vlo = SWIRL_VEL(1 - d, r, col);
+              vhi = SWIRL_VEL(1 - d, r + 1, col);
+            } else {
+              int32_t ci, cj, ui, uj;
+              cell_of(d, col, r, &ci, &cj);
+              cell_of(d, col, r + 1, &ui, &uj);
+              vlo = fco_rotation_edge(mesh, par, p, 1 - d, ci, cj);
+              vhi = fco_rotation_edge(mesh, par, p, 1 - d, ui, uj);
+            }
             bm[0] = fmin(vlo, 0.0) * psi[0];
             bp[0] = fmax(vhi, 0.0) * psi[0];
             rc = 0;
@@ -370,7 +383,7 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
       double dtd = dt / (KAP(i, j) * dx);
       for (int k = 0; k < meqn; ++k) {
         double fx, gy;
-        if (mesh->sphere && k == 0) {   /* mass in flux form */
+        if (par->physics == FCO_SPHERE && k == 0) {   /* mass in flux form */
           fx = wk->FL[0][eidx(m, i + 1, j)] - wk->FL[0][eidx(m, i, j)];
           gy = wk->FL[1][eidx(m, j + 1, i)] - wk->FL[1][eidx(m, j, i)];
         } else {
@@ -394,7 +407,7 @@ static int step_patch(const fco_mesh *mesh, const fco_params *par, int64_t p,
           const int fd = f / 2;
           const int64_t ei = eidx(m, (f & 1) ? m + 1 : 1, t);
           double fluct;
-          if (mesh->sphere && k == 0)   /* flux form: -F in, +F out */
+          if (par->physics == FCO_SPHERE && k == 0)   /* flux form: -F in, +F out */
             fluct = (f & 1) ? wk->FL[fd][ei] : -wk->FL[fd][ei];
           else
             fluct = (f & 1) ? wk->AM[fd][ei * meqn + k] : wk->AP[fd][ei * meqn + k];
@@ -526,7 +539,8 @@ int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
   if (!mesh || !par || !q || !qn || par->m != mesh->m || par->meqn < 1 ||
       par->meqn > FCO_MAXEQ)
     return -1;
-  if ((par->physics == FCO_SPHERE) != (mesh->sphere != 0)) return -1;
+  if ((par->physics == FCO_SPHERE || par->physics == FCO_ROTATION) != (mesh->sphere != 0))
+    return -1;
   const int32_t m = mesh->m, meqn = par->meqn;
   const int64_t NE = (int64_t)(m + 3) * (m + 2), FR = fco_frame(m);
   double *phi = do_reflux
@@ -573,8 +587,9 @@ int fco_step(const fco_mesh *mesh, const fco_params *par, const double *q,
   }
   if (rc) rc = -1;
   /* the colour equation is not in conservation form: no reflux */
-  if (rc == 0 && do_reflux && par->physics != FCO_SWIRL) rc = reflux(mesh, par, q, qn, dt, phi);
-  if (rc == 0 && mesh->sphere) fco_sphere_project(mesh, par, qn);
+  if (rc == 0 && do_reflux && par->physics != FCO_SWIRL && par->physics != FCO_ROTATION)
+    rc = reflux(mesh, par, q, qn, dt, phi);
+  if (rc == 0 && par->physics == FCO_SPHERE) fco_sphere_project(mesh, par, qn);
   free(phi);
   if (numax) *numax = nmax;
   return rc;

@@ -24,7 +24,7 @@ LEAF_DTYPE = np.dtype([("tree", "<i4"), ("level", "<i4"), ("ix", "<i4"),
 TREE_DTYPE = np.dtype([("nbr_tree", "<i4", (4,)), ("nbr_face", "<i4", (4,)),
                        ("orient", "<i4", (4,)), ("bc", "<i4", (4,))])
 
-ADVECTION, SHALLOW, SPHERE, SWIRL = 0, 1, 2, 3
+ADVECTION, SHALLOW, SPHERE, SWIRL, ROTATION = 0, 1, 2, 3, 4
 S = 30
 SIDE = 1 << S
 
@@ -33,7 +33,8 @@ class Params(C.Structure):
     _fields_ = [("m", C.c_int32), ("meqn", C.c_int32), ("physics", C.c_int32),
                 ("limiter", C.c_int32), ("transverse", C.c_int32),
                 ("pad", C.c_int32), ("g", C.c_double), ("ax", C.c_double),
-                ("ay", C.c_double), ("period", C.c_double), ("time", C.c_double)]
+                ("ay", C.c_double), ("period", C.c_double), ("time", C.c_double),
+                ("axis", C.c_double * 3)]
 
 
 def build(force: bool = False) -> str:
@@ -88,6 +89,8 @@ def lib():
         L.fco_sphere_kappa.restype = dp
         L.fco_sphere_edge.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp]
         L.fco_sphere_centre.argtypes = [vp, i64, i32, i32, vp]
+        L.fco_rotation_edge.argtypes = [vp, vp, i64, i32, i32, i32]
+        L.fco_rotation_edge.restype = dp
         L.fco_rp_sphere.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp]
         L.fco_step_subcycled.argtypes = [vp, vp, vp, vp, dp, vp]
         L.fco_ghost_fill_level.argtypes = [vp, vp, vp, vp, vp, i32]
@@ -112,11 +115,14 @@ def threads() -> int:
 
 
 def params(m, physics=ADVECTION, limiter=4, transverse=2, g=1.0, ax=0.0,
-           ay=0.0, period=1.0, time=0.0):
+           ay=0.0, period=1.0, time=0.0, axis=(0.0, 0.0, 1.0)):
     """SWIRL: the prescribed swirl flow of period `period`; `time` is the
-    time of the state the next step starts from (the caller advances it)."""
-    meqn = {ADVECTION: 1, SHALLOW: 3, SPHERE: 4, SWIRL: 1}[physics]
-    return Params(m, meqn, physics, limiter, transverse, 0, g, ax, ay, period, time)
+    time of the state the next step starts from (the caller advances it).
+    ROTATION: a rigid rotation of the sphere about `axis`, one turn per
+    `period`."""
+    meqn = {ADVECTION: 1, SHALLOW: 3, SPHERE: 4, SWIRL: 1, ROTATION: 1}[physics]
+    return Params(m, meqn, physics, limiter, transverse, 0, g, ax, ay, period, time,
+                  (C.c_double * 3)(*axis))
 
 
 def sfc_sort(leaves: np.ndarray) -> np.ndarray:
@@ -400,6 +406,12 @@ def sphere_edge(mesh, p, direction, i, j):
     t = np.zeros(3)
     lib().fco_sphere_edge(mesh.h, p, direction, i, j, C.byref(g), _ptr(n), _ptr(t))
     return g.value, n, t
+
+
+def rotation_edge(mesh, par, p, direction, i, j) -> float:
+    """ROTATION: flux of the rotation through the low-side edge of frame
+    cell (i, j) over the computational cell size, towards higher index."""
+    return lib().fco_rotation_edge(mesh.h, C.byref(par), p, direction, i, j)
 
 
 def sphere_centre(mesh, p, i, j) -> np.ndarray:

@@ -454,6 +454,21 @@ def sphere_bumps(leaves, m, n=16, seed=0, amp=0.1, width=30.0):
     return q
 
 
+def sphere_scalar(leaves, m, fn):
+    """(P, 1, m, m) scalar state fn(r) at the cell centres, r of shape
+    (P, 3, m, m) (unit vectors)."""
+    return np.asarray(fn(sphere_centres(leaves, m)), dtype=np.float64)[:, None]
+
+
+def sphere_halves(leaves, m, normal=(0.35, -0.5, 0.79)):
+    """q = 1 on the half of the sphere that `normal` points into, 0 on the
+    other: a 0/1 state whose interface (a great circle) is not aligned with
+    the cube's edges.  (P, 1, m, m)."""
+    w = np.asarray(normal, float) / np.linalg.norm(normal)
+    return sphere_scalar(leaves, m,
+                         lambda r: (np.einsum("pkij,k->pij", r, w) > 0).astype(np.float64))
+
+
 def sphere_bump(leaves, m, lat=0.3, lon=0.5, amp=0.1, width=100.0):
     """h = 1 + amp exp(-width d^2), d the great-circle distance to the
     point (lat, lon); fluid at rest.  (P, 4, m, m): h, hu, hv, hw."""
