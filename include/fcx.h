@@ -62,7 +62,23 @@ extern "C" {
  * (fcx_sim_time) plus dt / 2.  The equation is not in conservation form,
  * so fcx_reflux leaves the state as it is.  Planar forests, global time
  * step only (fcx_advance_subcycled and batches refuse it). */
-enum { FCX_ADVECTION = 0, FCX_SHALLOW = 1, FCX_SPHERE = 2, FCX_SWIRL = 3 };
+/* FCX_ROTATION (Sec. 5, the sphere example: a 0/1 colour field carried by
+ * a rigid rotation of the sphere): the colour equation on the cubed sphere
+ * (the six trees and geometry of FCX_SPHERE, see fcx_sphere_geometry) with
+ * velocity u = Omega w x r, w = axis / |axis|, Omega = 2 pi / period.  u is
+ * the surface curl of psi = Omega w.r, so the flux of u through a cell
+ * edge is psi's difference between the edge's corners: each edge carries
+ * it over the computational cell size, signed towards higher index,
+ * formed as Omega (2 / dxi) sin(gamma dxi / 2) (w.t) from the edge's
+ * arc-length factor gamma and tangent t (the chord between the corners
+ * has length 2 sin(theta / 2) and the direction of t).  The update is the
+ * capacity form of the colour equation (divided by kappa); no reflux (not
+ * a conservation law).  Plain steps only: fcx_patch_step, fcx_ghost_fill,
+ * fcx_next_dt, fcx_conservation_sums (capacity weighted), the regrid
+ * calls and fcx_run with fused = 0; fused and sub-cycled steps, features
+ * and batches return FCX_EINVAL. */
+enum { FCX_ADVECTION = 0, FCX_SHALLOW = 1, FCX_SPHERE = 2, FCX_SWIRL = 3,
+       FCX_ROTATION = 4 };
 
 typedef struct fcx_ctx fcx_ctx;
 typedef struct fcx_batch fcx_batch;
@@ -87,7 +103,7 @@ typedef struct {
   int32_t physics;     /* FCX_ADVECTION (meqn 1), FCX_SHALLOW (meqn 3),
                           FCX_SPHERE (meqn 4: h and 3D momentum on the
                           cubed sphere; see fcx_sphere_geometry) or
-                          FCX_SWIRL (meqn 1)                              */
+                          FCX_SWIRL or FCX_ROTATION (meqn 1)              */
   int32_t limiter;     /* wave limiter: 0 none, 1 minmod, 2 superbee,
                           3 van Leer, 4 MC (LeVeque 2002, Sec. 6.12)      */
   int32_t transverse;  /* 0 none, 1 fluctuations, 2 fluctuations and
@@ -109,7 +125,9 @@ typedef struct {
   double ax, ay;       /* advection velocity in reference coordinates     */
   double cfl_desired;  /* target Courant number for the next dt           */
   double cfl_max;      /* larger Courant numbers reject or flag the step  */
-  double period;       /* FCX_SWIRL: period T of the flow (> 0)           */
+  double period;       /* FCX_SWIRL: period T of the flow (> 0);
+                          FCX_ROTATION: time of one turn (> 0)            */
+  double axis[3];      /* FCX_ROTATION: rotation axis (nonzero)           */
 } fcx_config;
 
 const char *fcx_last_error(void);
@@ -430,7 +448,7 @@ int fcx_batch_sums(fcx_batch *batch, const void *q, double *sums, void *stream);
  * the tree are mapped in the tree that holds them); at a cube vertex, where
  * no tree covers the corner region, that region uses the patch's own face
  * mapping extended. */
-int fcx_sphere_geometry(fcx_ctx *ctx, double *geo, void *stream);
+int fcx_sphere_geometry(fcx_ctx *ctx, double *geo, void *stream);   /* FCX_SPHERE, FCX_ROTATION */
 
 /* ---- learned tagging (an extension of the Sec. 5 criterion tags) ------
  *

@@ -296,10 +296,14 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   if (cfg->precision != 32 && cfg->precision != 64)
     return fail(FCX_EINVAL, "precision must be 32 or 64");
   if (cfg->physics != FCX_ADVECTION && cfg->physics != FCX_SHALLOW &&
-      cfg->physics != FCX_SPHERE && cfg->physics != FCX_SWIRL)
+      cfg->physics != FCX_SPHERE && cfg->physics != FCX_SWIRL &&
+      cfg->physics != FCX_ROTATION)
     return fail(FCX_EINVAL, "unknown physics");
-  if (cfg->physics == FCX_SWIRL && !(cfg->period > 0))
-    return fail(FCX_EINVAL, "the swirl flow needs a positive period");
+  if ((cfg->physics == FCX_SWIRL || cfg->physics == FCX_ROTATION) && !(cfg->period > 0))
+    return fail(FCX_EINVAL, "the prescribed flow needs a positive period");
+  if (cfg->physics == FCX_ROTATION &&
+      !(cfg->axis[0] * cfg->axis[0] + cfg->axis[1] * cfg->axis[1] + cfg->axis[2] * cfg->axis[2] > 0))
+    return fail(FCX_EINVAL, "the rotation needs a nonzero axis");
   if (cfg->limiter < 0 || cfg->limiter > 4 || cfg->transverse < 0 ||
       cfg->transverse > 2)
     return fail(FCX_EINVAL, "bad limiter or transverse mode");
@@ -323,9 +327,9 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
         if (T.bc[f] == 0 && (T.nbr_face[f] != (f ^ 1) || T.orient[f] != 0))
           return fail(FCX_EINVAL, "shallow water needs axis-aligned tree gluing");
   }
-  if (cfg->physics == FCX_SPHERE && !cube_connectivity(t))
+  if (sphere_phys(cfg->physics) && !cube_connectivity(t))
     return fail(FCX_EINVAL, "the sphere needs the six cube faces glued as the cube");
-  if (cfg->physics == FCX_SPHERE && cfg->m % kSphereTile != 0)
+  if (sphere_phys(cfg->physics) && cfg->m % kSphereTile != 0)
     return fail(FCX_EINVAL, "the sphere needs m a multiple of 8");
   fcx_ctx* c = new fcx_ctx;
   c->cfg = *cfg;
@@ -333,7 +337,8 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   c->cfg.threads = threads;
   c->threads_auto = cfg->threads == 0;
   c->tile = tile;
-  c->meqn = (cfg->physics == FCX_ADVECTION || cfg->physics == FCX_SWIRL)
+  c->meqn = (cfg->physics == FCX_ADVECTION || cfg->physics == FCX_SWIRL ||
+             cfg->physics == FCX_ROTATION)
                 ? 1
                 : (cfg->physics == FCX_SHALLOW ? 3 : 4);
   {
@@ -414,7 +419,7 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   // first; left out when every patch or none has a simple halo
   size_t nsimple = 0;
   for (const PatchRec& r : plan.recs) nsimple += (r.flags & kSimpleHalo) != 0;
-  const bool reorder = c->cfg.physics != FCX_SPHERE && nsimple > 0 && nsimple < P;
+  const bool reorder = !sphere_phys(c->cfg.physics) && nsimple > 0 && nsimple < P;
   const size_t off_order = at;
   if (reorder) at += align256(P * 4);
   // patches by level, for the launches of a sub-cycled step
@@ -524,7 +529,7 @@ static int finish_upload(fcx_ctx* c, hipStream_t s = nullptr, bool ordered = fal
   const size_t esz = c->cfg.precision == 64 ? 8 : 4;
   HIPCHK(c->phi.ensure(size_t(c->cur.nslots) * 4 * c->cfg.m * c->meqn * esz));
   HIPCHK(c->partial.ensure(size_t(P) * c->meqn));
-  if (c->cfg.physics == FCX_SPHERE) {
+  if (sphere_phys(c->cfg.physics)) {
     const int m = c->cfg.m;
     const size_t FR = size_t(m + 4) * (m + 4);
     HIPCHK(c->cur.geo.ensure(size_t(P) * kGeoN * FR));
@@ -639,6 +644,9 @@ int fcx_ghost_fill(fcx_ctx* c, const void* q, void* ghost, void* stream) {
   if (c->cfg.physics == FCX_SPHERE)
     return dp ? launch_ghost<double, FCX_SPHERE>(c, q, ghost, s)
               : launch_ghost<float, FCX_SPHERE>(c, q, ghost, s);
+  if (c->cfg.physics == FCX_ROTATION)
+    return dp ? launch_ghost<double, FCX_ROTATION>(c, q, ghost, s)
+              : launch_ghost<float, FCX_ROTATION>(c, q, ghost, s);
   return dp ? launch_ghost<double, FCX_SHALLOW>(c, q, ghost, s)
             : launch_ghost<float, FCX_SHALLOW>(c, q, ghost, s);
 }
@@ -737,6 +745,33 @@ static int launch_sphere_step(fcx_ctx* c, const void* q, const void* ghost, void
   return FCX_OK;
 }
 
+template <typename R, int T>
+static int launch_rotation_step(fcx_ctx* c, const void* q, const void* ghost, void* qn,
+                                const double* dt, double* numax, hipStream_t s) {
+  RotationArgs a;
+  a.q = q;
+  a.ghost = ghost;
+  a.qn = qn;
+  a.dt = dt;
+  a.numax = numax;
+  a.rec = c->cur.rec;
+  a.geo = c->cur.geo.p;
+  a.m = c->cfg.m;
+  a.limiter = c->cfg.limiter;
+  a.transverse = c->cfg.transverse;
+  const double* w = c->cfg.axis;
+  const double om = 2.0 * 3.14159265358979323846 / c->cfg.period /
+                    std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  a.wx = om * w[0];
+  a.wy = om * w[1];
+  a.wz = om * w[2];
+  const int tps = a.m / T;
+  const int64_t grid = c->cur.P * tps * tps;
+  hipLaunchKernelGGL((k_rotation_step<R, T>), dim3(unsigned(grid)), dim3(256), 0, s, a);
+  HIPCHK(hipGetLastError());
+  return FCX_OK;
+}
+
 template <bool FUSED>
 static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                          const double* dt, double* numax, void* stream) {
@@ -750,6 +785,14 @@ static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
     if (FUSED) return fail(FCX_EINVAL, "no fused step on the sphere");
     return dp ? launch_sphere_step<double>(c, q, ghost, qn, dt, numax, s)
               : launch_sphere_step<float>(c, q, ghost, qn, dt, numax, s);
+  }
+  if (c->cfg.physics == FCX_ROTATION) {
+    if (FUSED) return fail(FCX_EINVAL, "no fused step on the sphere");
+    if (c->cfg.m % 16 == 0)
+      return dp ? launch_rotation_step<double, 16>(c, q, ghost, qn, dt, numax, s)
+                : launch_rotation_step<float, 16>(c, q, ghost, qn, dt, numax, s);
+    return dp ? launch_rotation_step<double, 8>(c, q, ghost, qn, dt, numax, s)
+              : launch_rotation_step<float, 8>(c, q, ghost, qn, dt, numax, s);
   }
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_step_m<double, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s)
@@ -846,6 +889,8 @@ static int launch_sphere_reflux(fcx_ctx* c, const void* q, void* qn, const doubl
 int fcx_reflux(fcx_ctx* c, const void* q, void* qn, const double* dt, void* stream) {
   if (!c || !q || !qn || !dt) return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
+  // (the rotation's colour equation is not in conservation form)
+  if (c->cfg.physics == FCX_ROTATION) return FCX_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
   if (c->cfg.physics == FCX_SPHERE)
@@ -910,15 +955,30 @@ static int sums_with(fcx_ctx* c, const void* q, double* sums, hipStream_t s,
   const bool dp = c->cfg.precision == 64;
   if (c->cfg.physics == FCX_SPHERE) {
     if (dp)
-      hipLaunchKernelGGL((k_sphere_sums_patch<double>), dim3(unsigned(c->cur.P)), dim3(256),
+      hipLaunchKernelGGL((k_sphere_sums_patch<double, 4>), dim3(unsigned(c->cur.P)), dim3(256),
                          0, s, static_cast<const double*>(q), c->cur.rec, c->cur.geo.p,
                          c->cfg.m, partial);
     else
-      hipLaunchKernelGGL((k_sphere_sums_patch<float>), dim3(unsigned(c->cur.P)), dim3(256),
+      hipLaunchKernelGGL((k_sphere_sums_patch<float, 4>), dim3(unsigned(c->cur.P)), dim3(256),
                          0, s, static_cast<const float*>(q), c->cur.rec, c->cur.geo.p,
                          c->cfg.m, partial);
     HIPCHK(hipGetLastError());
     hipLaunchKernelGGL((k_sums_reduce<4>), dim3(1), dim3(1024), 0, s, partial,
+                       c->cur.first, sums);
+    HIPCHK(hipGetLastError());
+    return FCX_OK;
+  }
+  if (c->cfg.physics == FCX_ROTATION) {
+    if (dp)
+      hipLaunchKernelGGL((k_sphere_sums_patch<double, 1>), dim3(unsigned(c->cur.P)), dim3(256),
+                         0, s, static_cast<const double*>(q), c->cur.rec, c->cur.geo.p,
+                         c->cfg.m, partial);
+    else
+      hipLaunchKernelGGL((k_sphere_sums_patch<float, 1>), dim3(unsigned(c->cur.P)), dim3(256),
+                         0, s, static_cast<const float*>(q), c->cur.rec, c->cur.geo.p,
+                         c->cfg.m, partial);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL((k_sums_reduce<1>), dim3(1), dim3(1024), 0, s, partial,
                        c->cur.first, sums);
     HIPCHK(hipGetLastError());
     return FCX_OK;
@@ -954,7 +1014,7 @@ static int launch_tags(fcx_ctx* c, const void* q, const void* ghost, int criteri
                        double thr, int lmin, int lmax, int8_t* tags, hipStream_t s,
                        int8_t* mirror = nullptr) {
   const int m = c->cfg.m;
-  const double* geo = c->cfg.physics == FCX_SPHERE ? c->cur.geo.p : nullptr;
+  const double* geo = sphere_phys(c->cfg.physics) ? c->cur.geo.p : nullptr;
   hipLaunchKernelGGL((k_tag_refine<R, MEQN>), dim3(unsigned(c->cur.P)), dim3(256),
                      0, s, static_cast<const R*>(q), static_cast<const R*>(ghost),
                      c->cur.rec, m, criterion, thr, lmax, tags, geo, mirror);
@@ -1067,12 +1127,12 @@ static int launch_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
   return FCX_OK;
 }
 
-template <typename R>
+template <typename R, int MEQN>
 static int launch_transfer_sphere(fcx_ctx* c, const void* qo, const void* go, void* qn,
                                   hipStream_t s) {
   const int m = c->cfg.m;
-  const int64_t tot = c->cur.P * 4 * (m / 2) * (m / 2);
-  hipLaunchKernelGGL((k_transfer_sphere<R>), dim3(unsigned((tot + 255) / 256)), dim3(256),
+  const int64_t tot = c->cur.P * MEQN * (m / 2) * (m / 2);
+  hipLaunchKernelGGL((k_transfer_sphere<R, MEQN>), dim3(unsigned((tot + 255) / 256)), dim3(256),
                      0, s, static_cast<const R*>(qo), static_cast<const R*>(go),
                      static_cast<R*>(qn), c->cur.rec, c->cur.xkind, c->cur.xsrc,
                      c->old.geo.p, c->cur.geo.p, int32_t(c->cur.P), m);
@@ -1087,8 +1147,11 @@ int fcx_regrid_transfer(fcx_ctx* c, const void* qo, const void* go, void* qn,
   hipStream_t s = static_cast<hipStream_t>(stream);
   const bool dp = c->cfg.precision == 64;
   if (c->cfg.physics == FCX_SPHERE)
-    return dp ? launch_transfer_sphere<double>(c, qo, go, qn, s)
-              : launch_transfer_sphere<float>(c, qo, go, qn, s);
+    return dp ? launch_transfer_sphere<double, 4>(c, qo, go, qn, s)
+              : launch_transfer_sphere<float, 4>(c, qo, go, qn, s);
+  if (c->cfg.physics == FCX_ROTATION)
+    return dp ? launch_transfer_sphere<double, 1>(c, qo, go, qn, s)
+              : launch_transfer_sphere<float, 1>(c, qo, go, qn, s);
   if (c->meqn == 1)
     return dp ? launch_transfer<double, 1>(c, qo, go, qn, s)
               : launch_transfer<float, 1>(c, qo, go, qn, s);
@@ -1316,7 +1379,7 @@ int fcx_batch_create(int32_t n, fcx_ctx* const* forests, fcx_batch** out) {
       return fail(FCX_ESTATE, "every context needs an uploaded forest");
     if (forests[f]->cfg.precision != forests[0]->cfg.precision)
       return fail(FCX_EINVAL, "all forests of a batch share one precision");
-    if (forests[f]->cfg.physics == FCX_SPHERE || forests[f]->cfg.physics == FCX_SWIRL)
+    if (sphere_phys(forests[f]->cfg.physics) || forests[f]->cfg.physics == FCX_SWIRL)
       return fail(FCX_EINVAL, "sphere and prescribed-flow forests are not batched");
   }
   fcx_batch* b = new fcx_batch;
@@ -1578,7 +1641,7 @@ int fcx_features(fcx_ctx* c, const void* q, const void* ghost, float* feats,
                  void* stream) {
   if (!c || !q || !ghost || !feats) return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
-  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no features on the sphere");
+  if (sphere_phys(c->cfg.physics)) return fail(FCX_EINVAL, "no features on the sphere");
   if (c->cur.P == 0) return FCX_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
   const unsigned grid = unsigned(c->cur.P);
@@ -1688,7 +1751,7 @@ int fcx_dilate_tags(fcx_ctx* c, const int8_t* in, int32_t lmax, int8_t* out,
 int fcx_sphere_geometry(fcx_ctx* c, double* geo, void* stream) {
   if (!c || !geo) return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
-  if (c->cfg.physics != FCX_SPHERE) return fail(FCX_EINVAL, "not a sphere context");
+  if (!sphere_phys(c->cfg.physics)) return fail(FCX_EINVAL, "not a sphere context");
   const size_t FR = size_t(c->cfg.m + 4) * (c->cfg.m + 4);
   HIPCHK(hipMemcpyAsync(geo, c->cur.geo.p, sizeof(double) * c->cur.P * kGeoN * FR,
                         hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
@@ -1915,7 +1978,7 @@ int fcx_advance_subcycled(fcx_ctx* c, const void* q, void* q_new, void* work, vo
       q == q_new || q == work || q_new == work)
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
-  if (c->cfg.physics == FCX_SPHERE) return fail(FCX_EINVAL, "no sub-cycled step on the sphere");
+  if (sphere_phys(c->cfg.physics)) return fail(FCX_EINVAL, "no sub-cycled step on the sphere");
   if (c->cfg.physics == FCX_SWIRL)
     return fail(FCX_EINVAL, "no sub-cycled step for the prescribed flow");
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -1970,7 +2033,7 @@ int fcx_run(fcx_ctx* c, int32_t fused, void* q0, void* q1, int64_t cap, void* gh
     return fail(FCX_EINVAL, "bad arguments");
   if (!c->have_forest) return fail(FCX_ESTATE, "no forest uploaded");
   if (fused < 0 || fused > 2) return fail(FCX_EINVAL, "mode must be 0, 1 or 2");
-  if (c->cfg.physics == FCX_SPHERE && fused)
+  if (sphere_phys(c->cfg.physics) && fused)
     return fail(FCX_EINVAL, "no fused or sub-cycled run on the sphere");
   void* buf[2] = {q0, q1};
   int cur = 0;

@@ -752,7 +752,7 @@ k_transfer(const R* __restrict__ qo, const R* __restrict__ go,
 // on the plane (limited slopes) and then shifted by one common amount so that
 // their capacity-weighted sum equals the old cell's content (a coarse cell
 // has four times a child's computational area).  Arithmetic in FP64.
-template <typename R>
+template <typename R, int MEQN>
 __global__ void __launch_bounds__(256)
 k_transfer_sphere(const R* __restrict__ qo, const R* __restrict__ go,
                   R* __restrict__ qn, const PatchRec* __restrict__ rec_new,
@@ -760,7 +760,6 @@ k_transfer_sphere(const R* __restrict__ qo, const R* __restrict__ go,
                   const double* __restrict__ geo_old, const double* __restrict__ geo_new,
                   int32_t P, int m) {
 #pragma clang fp contract(off)
-  constexpr int MEQN = 4;
   const int hb = m / 2, nb = hb * hb;
   const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (t >= int64_t(P) * MEQN * nb) return;

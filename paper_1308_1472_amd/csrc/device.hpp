@@ -46,6 +46,11 @@ template <> struct PhysTraits<FCX_ADVECTION> { static constexpr int MEQN = 1; };
 template <> struct PhysTraits<FCX_SHALLOW> { static constexpr int MEQN = 3; };
 template <> struct PhysTraits<FCX_SPHERE> { static constexpr int MEQN = 4; };
 template <> struct PhysTraits<FCX_SWIRL> { static constexpr int MEQN = 1; };
+template <> struct PhysTraits<FCX_ROTATION> { static constexpr int MEQN = 1; };
+// physics on the cubed sphere (capacity-weighted means across levels)
+__host__ __device__ constexpr bool sphere_phys(int p) {
+  return p == FCX_SPHERE || p == FCX_ROTATION;
+}
 
 __device__ __forceinline__ void xf_apply(int32_t code, int32_t x, int32_t y,
                                          int32_t& xo, int32_t& yo) {
@@ -255,7 +260,7 @@ __device__ void from_leaf(const GhostView<R, MEQN>& g, int lev, int32_t nb,
     leaf_cell<R, MEQN, TIMED>(g, nb, i0 + 1, j0, b);
     leaf_cell<R, MEQN, TIMED>(g, nb, i0, j0 + 1, c);
     leaf_cell<R, MEQN, TIMED>(g, nb, i0 + 1, j0 + 1, d);
-    if (PHYS == FCX_SPHERE) {
+    if (sphere_phys(PHYS)) {
       // capacity-weighted mean
       const R ka = R(geo_kappa(g.geo, g.m, nb, i0, j0));
       const R kb = R(geo_kappa(g.geo, g.m, nb, i0 + 1, j0));

@@ -642,28 +642,181 @@ k_sphere_reflux(const R* q, R* qn, const RefluxItem* __restrict__ items, int32_t
 }
 
 // Per-patch FP64 partial sums of kappa q dxi^2.
-template <typename R>
+template <typename R, int MEQN>
 __global__ void __launch_bounds__(256)
 k_sphere_sums_patch(const R* __restrict__ q, const PatchRec* __restrict__ rec,
                     const double* __restrict__ geo, int m, double* __restrict__ partial) {
-  __shared__ double red[4][4];
+  __shared__ double red[4][MEQN];
   const int p = blockIdx.x, tid = threadIdx.x, FR = (m + 4) * (m + 4);
   const double dx = ldexp(1.0, -rec[p].level) / m;
   const double* kap = geo + size_t(p) * kGeoN * FR + kGeoK * FR;
-  double acc[4] = {0, 0, 0, 0};
+  double acc[MEQN] = {};
   for (int c = tid; c < m * m; c += 256) {
     const double kk = kap[fidx(m, c % m + 1, c / m + 1)];
-    for (int k = 0; k < 4; ++k) acc[k] += kk * double(q[size_t(p * 4 + k) * m * m + c]);
+    for (int k = 0; k < MEQN; ++k) acc[k] += kk * double(q[size_t(p * MEQN + k) * m * m + c]);
   }
-  for (int k = 0; k < 4; ++k) {
+  for (int k = 0; k < MEQN; ++k) {
     double v = acc[k];
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
     if ((tid & 63) == 0) red[tid >> 6][k] = v;
   }
   __syncthreads();
-  if (tid < 4)
-    partial[size_t(p) * 4 + tid] =
+  if (tid < MEQN)
+    partial[size_t(p) * MEQN + tid] =
         ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid])) * dx * dx;
+}
+
+// ---------------------------------------------------------------------------
+// the colour equation carried by a rigid rotation (FCX_ROTATION)
+
+struct RotationArgs {
+  const void* q;
+  const void* ghost;
+  void* qn;
+  const double* dt;
+  double* numax;
+  const PatchRec* __restrict__ rec;
+  const double* __restrict__ geo;
+  int m, limiter, transverse;
+  double wx, wy, wz;   // Omega times the unit axis
+};
+
+// One workgroup per T x T tile of a patch, all in LDS:
+//   phase 0: the tile's state with its 2-cell halo, dt / (kappa dx) of every
+//     frame cell, and the flux of every edge of both directions (edges
+//     e = 0 .. T+2 between cells e-1 and e, rows r = 0 .. T+1);
+//   phase 1: the waves (jumps) and the Courant numbers;
+//   phase 2: limited corrections and the transverse parts, which leave
+//     the receiving cell through its own transverse edges at their fluxes;
+//   phase 3: each cell's update, q - dt / (kappa dx) (fluctuations +
+//     differences of the correction fluxes) per direction.
+// The flux of an edge is Omega w.(b - a) (+ for xi-edges, - for eta-edges,
+// a, b its corners in index order) over dx; the chord b - a is 2 sin(theta
+// / 2) times the edge's tangent t (+t for xi-edges, -t for eta-edges), with
+// theta = gamma dx the arc's angle, so the flux is (2 / dx) sin(theta / 2)
+// (Omega w).t for either direction.  Formed in FP64 from the FP64 geometry.
+template <typename R, int T>
+__global__ void __launch_bounds__(256)
+k_rotation_step(RotationArgs A) {
+  constexpr int FT = T + 4, FRT = FT * FT, M2 = T + 2, NE = (T + 3) * (T + 2);
+  __shared__ R Qs[FRT];
+  __shared__ double dtk[FRT];
+  __shared__ R S[2][NE], Wv[2][NE], CQ[2][NE], TR[2][NE][4];
+  __shared__ double red[4];
+  const R* q = static_cast<const R*>(A.q);
+  const R* ghost = static_cast<const R*>(A.ghost);
+  const int m = A.m, FR = (m + 4) * (m + 4), G = 8 * m + 16, tps = m / T;
+  const int p = blockIdx.x / (tps * tps), tile = blockIdx.x - p * (tps * tps);
+  const int i0 = (tile % tps) * T, j0 = (tile / tps) * T;
+  const double dt = *A.dt;
+  const double dx = ldexp(1.0, -A.rec[p].level) / m;
+  const double* geo = A.geo + size_t(p) * kGeoN * FR;
+  auto lf = [](int i, int j) { return (j + 1) * FT + (i + 1); };   // tile frame
+  auto ei = [](int e, int r) { return e * M2 + r; };
+  // phase 0
+  for (int f = threadIdx.x; f < FRT; f += blockDim.x) {
+    const int i = i0 + f % FT - 1, j = j0 + f / FT - 1;
+    const bool outer = (i == -1 || i == m + 2) && (j == -1 || j == m + 2);
+    R v;
+    if (i >= 1 && i <= m && j >= 1 && j <= m)
+      v = q[(size_t(p) * m + (j - 1)) * m + (i - 1)];
+    else
+      v = outer ? R(0) : ghost[size_t(p) * G + ghost_index(m, i, j)];
+    Qs[f] = v;
+    dtk[f] = dt / (geo[kGeoK * FR + fidx(m, i, j)] * dx);
+  }
+  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+    // the low-side d-edge of the cell on the edge's high side
+    const int ir = d == 0 ? e : r, jr = d == 0 ? r : e;
+    const double* g = geo + kGeoE * FR + (size_t(d) * FR + fidx(m, i0 + ir, j0 + jr)) * 7;
+    const double wt = A.wx * g[4] + A.wy * g[5] + A.wz * g[6];
+    S[d][er] = R((2.0 / dx) * sin(0.5 * g[0] * dx) * wt);
+  }
+  __syncthreads();
+  // phase 1
+  double nmax = 0.0;
+  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+    const int il = d == 0 ? e - 1 : r, jl = d == 0 ? r : e - 1;
+    const int ir = d == 0 ? e : r, jr = d == 0 ? r : e;
+    Wv[d][er] = Qs[lf(ir, jr)] - Qs[lf(il, jl)];
+    if (r >= 1 && r <= T && e >= 1 && e <= T + 1) {
+      const double sw = double(S[d][er]);
+      nmax = fmax(nmax, dtk[lf(ir, jr)] * fmax(sw, 0.0));
+      nmax = fmax(nmax, dtk[lf(il, jl)] * fmax(-sw, 0.0));
+    }
+  }
+  __syncthreads();
+  // phase 2
+  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
+    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
+    if (e < 1 || e > T + 1) continue;
+    const int il = d == 0 ? e - 1 : r, jl = d == 0 ? r : e - 1;
+    const int ir = d == 0 ? e : r, jr = d == 0 ? r : e;
+    const double dtdl = dtk[lf(il, jl)], dtdr = dtk[lf(ir, jr)];
+    const R sw = S[d][er], wc = Wv[d][er];
+    R cq = R(0);
+    if (wc != R(0)) {
+      const R wu = Wv[d][ei(sw > R(0) ? e - 1 : e + 1, r)];
+      const R lim = limiter_phi<R>(A.limiter, (wu * wc) * rcp_(wc * wc));
+      const R as = fabs(sw);
+      cq = as * (R(1) - R(0.5 * (dtdl + dtdr)) * as) * lim * wc;
+    }
+    CQ[d][er] = cq;
+    const int o = 1 - d;
+    if (A.transverse == 0) {
+      for (int k = 0; k < 4; ++k) TR[d][er][k] = R(0);
+      continue;
+    }
+    const R c2 = A.transverse == 2 ? cq : R(0);
+    const R amt = fmin(sw, R(0)) * wc + c2, apt = fmax(sw, R(0)) * wc - c2;
+    for (int side = 0; side < 2; ++side) {
+      const int col = side == 0 ? e - 1 : e;
+      const R h = R(-0.5 * (side == 0 ? dtdl : dtdr));
+      const R ps = side == 0 ? amt : apt;
+      // the receiving cell's lower and upper o-edges
+      const R slo = S[o][ei(r, col)], shi = S[o][ei(r + 1, col)];
+      TR[d][er][side * 2 + 0] = h * (fmin(slo, R(0)) * ps);
+      TR[d][er][side * 2 + 1] = h * (fmax(shi, R(0)) * ps);
+    }
+  }
+  __syncthreads();
+  // phase 3: total correction flux of edge (e, r) in direction d: its own
+  // half correction, then the transverse parts of the other direction's
+  // edges whose receiving cells it bounds
+  auto Ftot = [&](int d, int e, int r) -> R {
+    const int o = 1 - d;
+    R v = R(0.5) * CQ[d][ei(e, r)];
+    v += TR[o][ei(r, e - 1)][3];
+    v += TR[o][ei(r + 1, e - 1)][1];
+    v += TR[o][ei(r, e)][2];
+    v += TR[o][ei(r + 1, e)][0];
+    return v;
+  };
+  auto fl = [&](int d, int e, int r, bool ap) -> R {
+    const R sw = S[d][ei(e, r)], wv = Wv[d][ei(e, r)];
+    return ap ? fmax(sw, R(0)) * wv : fmin(sw, R(0)) * wv;
+  };
+  R* qn = static_cast<R*>(A.qn);
+  for (int c = threadIdx.x; c < T * T; c += blockDim.x) {
+    const int i = c % T + 1, j = c / T + 1;
+    const int f = lf(i, j);
+    const R dtd = R(dtk[f]);
+    R fx = fl(0, i, j, true) + fl(0, i + 1, j, false);
+    R gy = fl(1, j, i, true) + fl(1, j + 1, i, false);
+    fx = fx + (Ftot(0, i + 1, j) - Ftot(0, i, j));
+    gy = gy + (Ftot(1, j + 1, i) - Ftot(1, j, i));
+    qn[(size_t(p) * m + (j0 + j - 1)) * m + (i0 + i - 1)] = Qs[f] - dtd * fx - dtd * gy;
+  }
+  for (int off = 32; off > 0; off >>= 1) nmax = fmax(nmax, __shfl_xor(nmax, off));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = nmax;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = red[0];
+    for (int w = 1; w < int(blockDim.x >> 6); ++w) v = fmax(v, red[w]);
+    atomic_max_pos(A.numax, v);
+  }
 }
 
 }  // namespace fcx

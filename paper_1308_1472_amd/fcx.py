@@ -20,7 +20,7 @@ LEAF_DTYPE = np.dtype([("tree", "<i4"), ("level", "<i4"), ("ix", "<i4"),
 TREE_DTYPE = np.dtype([("nbr_tree", "<i4", (4,)), ("nbr_face", "<i4", (4,)),
                        ("orient", "<i4", (4,)), ("bc", "<i4", (4,))])
 
-FCX_ADVECTION, FCX_SHALLOW, FCX_SPHERE, FCX_SWIRL = 0, 1, 2, 3
+FCX_ADVECTION, FCX_SHALLOW, FCX_SPHERE, FCX_SWIRL, FCX_ROTATION = 0, 1, 2, 3, 4
 GEO_FRAMES = 18          # geometry table frames per patch (fcx_sphere_geometry)
 ERRORS = {-1: "FCX_EINVAL", -2: "FCX_EBALANCE", -3: "FCX_ENOMEM",
           -4: "FCX_EHIP", -5: "FCX_ECFL", -6: "FCX_ENEG", -7: "FCX_ESTATE"}
@@ -60,7 +60,7 @@ class Config(C.Structure):
                 ("threads", C.c_int32), ("redo", C.c_int32),
                 ("g", C.c_double), ("ax", C.c_double), ("ay", C.c_double),
                 ("cfl_desired", C.c_double), ("cfl_max", C.c_double),
-                ("period", C.c_double)]
+                ("period", C.c_double), ("axis", C.c_double * 3)]
 
 
 _lib = None
@@ -188,10 +188,12 @@ def regrid_leaves(trees, leaves, tags, lmin, lmax) -> np.ndarray:
 
 def config(m, precision=64, physics=FCX_SHALLOW, limiter=4, transverse=2,
            tile=0, threads=0, g=1.0, ax=0.0, ay=0.0, cfl_desired=0.9,
-           cfl_max=1.0, redo=1, period=1.0):
-    """period: FCX_SWIRL's flow period."""
+           cfl_max=1.0, redo=1, period=1.0, axis=(0.0, 0.0, 1.0)):
+    """period: FCX_SWIRL's flow period, FCX_ROTATION's time of one turn;
+    axis: FCX_ROTATION's rotation axis."""
     return Config(m, precision, physics, limiter, transverse, tile, threads,
-                  int(redo), g, ax, ay, cfl_desired, cfl_max, period)
+                  int(redo), g, ax, ay, cfl_desired, cfl_max, period,
+                  (C.c_double * 3)(*axis))
 
 
 def _stream(stream):
@@ -258,7 +260,8 @@ class Context:
 
     def __init__(self, cfg: Config, trees):
         self.cfg = cfg
-        self.meqn = {FCX_ADVECTION: 1, FCX_SHALLOW: 3, FCX_SPHERE: 4, FCX_SWIRL: 1}[cfg.physics]
+        self.meqn = {FCX_ADVECTION: 1, FCX_SHALLOW: 3, FCX_SPHERE: 4, FCX_SWIRL: 1,
+                     FCX_ROTATION: 1}[cfg.physics]
         self.trees = np.ascontiguousarray(trees, dtype=TREE_DTYPE)
         h = C.c_void_p()
         _check(lib().fcx_create(C.byref(cfg), len(self.trees),

@@ -157,9 +157,10 @@ def oracle_attempt(mesh, par, q, dt, cfl_desired=0.9, cfl_max=1.0):
 
 def oracle_params(cfg):
     phys = {fcx.FCX_ADVECTION: O.ADVECTION, fcx.FCX_SHALLOW: O.SHALLOW,
-            fcx.FCX_SPHERE: O.SPHERE, fcx.FCX_SWIRL: O.SWIRL}[cfg.physics]
+            fcx.FCX_SPHERE: O.SPHERE, fcx.FCX_SWIRL: O.SWIRL,
+            fcx.FCX_ROTATION: O.ROTATION}[cfg.physics]
     return O.params(cfg.m, phys, limiter=cfg.limiter, transverse=cfg.transverse,
-                    g=cfg.g, ax=cfg.ax, ay=cfg.ay, period=cfg.period)
+                    g=cfg.g, ax=cfg.ax, ay=cfg.ay, period=cfg.period, axis=tuple(cfg.axis))
 
 
 def smooth_sw_state(leaves, m, pl, seed):

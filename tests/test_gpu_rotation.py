@@ -1,0 +1,171 @@
+"""GPU parity of the advection by a rigid rotation of the cubed sphere
+(FCX_ROTATION: the colour equation in capacity form with edge fluxes from
+the rotation's stream function, the flow of the paper's Sec. 5 sphere
+example) against the CPU oracle: FP64 within 1e-12 relative to max|q| and
+Courant numbers within 1e-12, FP32 within 1e-5 relative L1 (Courant numbers
+1e-6), on adaptive sphere forests with 8 x 8 and 16 x 16 tiles, from the
+0/1 halves of the example and from a smooth state; capacity-weighted ghost
+cells and sums; the run loop with regrids and the CFL redo rule against
+the oracle's sequence; a uniform state kept bit for bit; the calls that
+refuse it.
+
+(The kernel forms an edge's flux from its arc angle and tangent, the
+oracle from the chord between its corners: the two agree to a few units in
+the last place of the flux, relative to the chord's length.)"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1308_1472_amd import fcx
+from paper_1308_1472_amd import inputs as I
+from tests.gpu_drive import Gpu, ghost_to_frame, needed_mask, oracle_attempt, oracle_params, say
+
+pytestmark = pytest.mark.gpu
+
+AXIS = (0.3, -0.4, 0.866)
+
+
+def _forest(seed, lmin=1, lmax=3, n=12):
+    trees = I.cubed_sphere()
+    return trees, fcx.balance(trees, I.random_leaves(seed, 6, lmin, lmax, n))
+
+
+def _blob(lv, m):
+    c = np.array([0.6, 0.0, 0.8])
+    return I.sphere_scalar(lv, m, lambda r: np.exp(-6.0 * np.sum((r - c[None, :, None, None]) ** 2,
+                                                                 axis=1)))
+
+
+@pytest.mark.parametrize("precision", [64, 32])
+@pytest.mark.parametrize("m", [8, 16, 32])
+@pytest.mark.parametrize("state", ["halves", "blob"])
+def test_steps_match_oracle(precision, m, state):
+    say(f"[rotation] steps precision={precision} m={m} state={state}")
+    trees, lv = _forest(3 + m, 1, 3 if m < 32 else 2, 12)
+    assert len(set(lv["level"].tolist())) >= 2
+    q0 = I.sphere_halves(lv, m) if state == "halves" else _blob(lv, m)
+    cfg = fcx.config(m, precision, fcx.FCX_ROTATION, period=2.5, axis=AXIS)
+    gpu = Gpu(cfg, trees, lv)
+    gpu.set_state(q0)
+    mesh = O.Mesh(trees, lv, m, sphere=True)
+    par = oracle_params(cfg)
+    dt = 0.4 * (np.pi / 2) / (m << int(lv["level"].max())) * 2.5 / (2 * np.pi)
+    want = q0
+    for k in range(4):
+        nu, used = gpu.step(dt if k == 0 else None, auto_dt=True)
+        qn, nu_o = O.advance(mesh, par, want, used)
+        assert nu_o <= 1.0
+        tol = 1e-12 if precision == 64 else 1e-6
+        assert abs(nu - nu_o) <= tol * nu_o, (k, nu, nu_o)
+        want = qn
+    got = gpu.state()
+    if precision == 64:
+        assert np.max(np.abs(got - want)) <= 1e-12 * np.max(np.abs(want))
+    else:
+        assert np.sum(np.abs(got - want)) <= 1e-5 * np.sum(np.abs(want))
+
+
+def test_ghost_fill_and_sums_match_oracle():
+    say("[rotation] ghost fill + sums")
+    m = 8
+    trees, lv = _forest(7, 1, 3, 14)
+    cfg = fcx.config(m, 64, fcx.FCX_ROTATION, axis=AXIS)
+    g = Gpu(cfg, trees, lv)
+    q = _blob(lv, m) + 0.25 * I.sphere_halves(lv, m)
+    g.set_state(q)
+    g.fill()
+    got = ghost_to_frame(g.ghosts(), g.state(), m)
+    mesh = O.Mesh(trees, lv, m, sphere=True)
+    par = oracle_params(cfg)
+    f = O.framed(q, m)
+    O.ghost_fill(mesh, par, f)
+    mk = needed_mask(m)
+    assert np.max(np.abs(got[:, :, mk] - f[:, :, mk])) <= 1e-13
+    s = g.conservation_sums()
+    assert abs(s[0] / O.sums(mesh, par, f)[0] - 1) <= 1e-13
+
+
+def test_uniform_state_is_kept_bitwise():
+    say("[rotation] uniform state")
+    trees, lv = _forest(9, 1, 3, 16)
+    for precision in (64, 32):
+        cfg = fcx.config(16, precision, fcx.FCX_ROTATION, axis=AXIS)
+        g = Gpu(cfg, trees, lv)
+        # (a power of two: its capacity-weighted means across levels are
+        # exact, so every jump stays zero)
+        q0 = np.full((len(lv), 1, 16, 16), 0.5)
+        g.set_state(q0)
+        for _ in range(3):
+            g.step(0.002)
+        assert np.array_equal(g.state(), q0)
+
+
+def test_run_loop_with_regrids_matches_oracle():
+    """fcx_run (plain steps, a criterion regrid every 2 steps, the CFL rule
+    with redo) against the oracle's sequence of the same operations."""
+    import torch
+    say("[rotation] run loop")
+    m, lmin, lmax, every, thr, steps = 8, 1, 4, 2, 0.25, 7
+    trees, lv0 = _forest(12, 1, 3, 12)
+    q0 = I.sphere_halves(lv0, m)
+    cfg = fcx.config(m, 64, fcx.FCX_ROTATION, period=3.0, axis=AXIS)
+    par = oracle_params(cfg)
+    mesh = O.Mesh(trees, lv0, m, sphere=True)
+    dt0 = 0.5 * (np.pi / 2) / (m << 3) * 3.0 / (2 * np.pi)
+    lv, q, dt = lv0, q0.copy(), dt0
+    rejected = 0
+    for n in range(steps):
+        if n > 0 and n % every == 0:
+            f = O.framed(q, m)
+            O.ghost_fill(mesh, par, f)
+            tg = O.tags(mesh, par, f, 1, thr, lmin, lmax)
+            lv = O.regrid(mesh, tg, lmin, lmax)
+            mesh2 = O.Mesh(trees, lv, m, sphere=True)
+            q = O.interior(O.transfer(mesh, mesh2, par, f), m)
+            mesh = mesh2
+        q, nu, dt, ok = oracle_attempt(mesh, par, q, dt)
+        rejected += not ok
+    assert not np.array_equal(lv, lv0)
+    ctx = fcx.Context(cfg, trees)
+    ctx.upload_forest(lv0)
+    dtt = torch.full((1,), dt0, dtype=torch.float64, device="cuda")
+    nut = torch.zeros_like(dtt)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pmax = 6 * (1 << (2 * lmax))
+    bufs = [torch.zeros(pmax * m * m, dtype=torch.float64, device="cuda") for _ in range(2)]
+    bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
+    ghost = torch.empty(pmax * (8 * m + 16), dtype=torch.float64, device="cuda")
+    which, cells = ctx.run(bufs[0], bufs[1], ghost, steps, 0, every, 1, thr, lmin, lmax,
+                           dtt, nut, st, fused=0)
+    assert np.array_equal(ctx.leaves(), lv)
+    got = bufs[which][:ctx.state_elems()].cpu().numpy().reshape(q.shape)
+    assert np.max(np.abs(got - q)) <= 1e-12 * np.max(np.abs(q))
+    assert abs(dtt.item() / dt - 1) <= 1e-12
+    assert ctx.step_stats()[:2] == (steps - rejected, rejected)
+
+
+def test_refused_calls():
+    import torch
+    say("[rotation] refused calls")
+    trees, lv = _forest(1)
+    with pytest.raises(fcx.FcxError):
+        fcx.Context(fcx.config(8, 64, fcx.FCX_ROTATION, period=0.0), trees)
+    with pytest.raises(fcx.FcxError):
+        fcx.Context(fcx.config(8, 64, fcx.FCX_ROTATION, axis=(0.0, 0.0, 0.0)), trees)
+    with pytest.raises(fcx.FcxError):
+        fcx.Context(fcx.config(8, 64, fcx.FCX_ROTATION), I.walled_square()[0])
+    cfg = fcx.config(8, 64, fcx.FCX_ROTATION)
+    ctx = fcx.Context(cfg, trees)
+    ctx.upload_forest(lv)
+    with pytest.raises(fcx.FcxError):
+        fcx.Batch([ctx])
+    n = ctx.state_elems()
+    a = [torch.zeros(n, dtype=torch.float64, device="cuda") for _ in range(3)]
+    g = torch.zeros(ctx.ghost_elems(), dtype=torch.float64, device="cuda")
+    dt = torch.full((1,), 1e-3, dtype=torch.float64, device="cuda")
+    nu = torch.zeros_like(dt)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    with pytest.raises(fcx.FcxError):
+        ctx.fused_step(a[0], a[1], dt, nu)
+    with pytest.raises(fcx.FcxError):
+        ctx.advance_subcycled(a[0], a[1], a[2], g, dt, nu, st)
