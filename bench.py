@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only", choices=["fp32", "fp64", "large", "batch", "sphere",
                                        "mlp", "copy", "cpu", "subcycle", "meshing", "swirl",
-                                       "all"],
+                                       "rotation", "all"],
                     default="all")
     ap.add_argument("--batch-steps", type=int, default=100)
     ap.add_argument("--sphere-steps", type=int, default=1000)
@@ -436,6 +436,92 @@ def run_swirl(precision=32, m=8, lmin=3, lmax=6, T=2.0, thr=0.2):
                      "patches_last": ctx.num_patches(), "l1_error_vs_initial": l1,
                      "status": status, "status_bits": status_bits([status])}
     base = out["uniform_level6"]["seconds"]
+    for name in out:
+        out[name]["speedup_vs_uniform"] = base / out[name]["seconds"]
+    return out
+
+
+def run_rotation(precision=32, m=8, lmin=2, lmax=5, T=1.0, thr=0.2,
+                 axis=(0.3, -0.4, 0.866)):
+    """The paper's sphere example (Sec. 5, Example 2): q = 1 on one half of
+    the sphere and 0 on the other, the halves split by a great circle that
+    follows no cube edge, carried by a rigid rotation (FCX_ROTATION) once
+    around a tilted axis, so the exact state after the period T is the
+    initial one.  On the six-tree cubed sphere (the paper maps two trees,
+    one per hemisphere), m = 8, levels 2-5 (32^2 to 256^2 cells per cube
+    face), refined where max - min of q over a patch exceeds 0.2, CFL 0.9
+    with the redo rule, plain steps; uniform level 5 for comparison.  Runs
+    fcx_run in chunks until the simulated time reaches T (at most one step
+    past it); reports wall clock, cell updates, rate and the L1 error
+    (area weighted) against the initial state."""
+    import numpy as np
+    import torch
+    from paper_1308_1472_amd import fcx
+    from paper_1308_1472_amd import inputs as I
+    trees = I.cubed_sphere()
+    dtype = torch.float32 if precision == 32 else torch.float64
+
+    def make(uniform):
+        cfg = fcx.config(m, precision, fcx.FCX_ROTATION, period=T, axis=axis)
+        ctx = fcx.Context(cfg, trees)
+        if uniform:
+            leaves = fcx.sfc_sort(I.uniform_leaves(6, lmax))
+        else:
+            leaves = fcx.sfc_sort(I.uniform_leaves(6, lmin))
+            for _ in range(2 * (lmax - lmin) + 2):
+                ctx.upload_forest(leaves)
+                q = torch.from_numpy(I.sphere_halves(leaves, m).ravel()).to(dtype).cuda()
+                g = torch.empty(ctx.ghost_elems(), dtype=dtype, device="cuda")
+                ctx.regrid(q, g, 0, thr, lmin, lmax)
+                new = ctx.leaves()
+                if len(new) == len(leaves) and (new == leaves).all():
+                    break
+                leaves = new
+        ctx.upload_forest(leaves)
+        pmax = 6 << (2 * lmax)
+        bufs = [torch.empty(pmax * m * m, dtype=dtype, device="cuda") for _ in range(2)]
+        ghost = torch.empty(pmax * (8 * m + 16), dtype=dtype, device="cuda")
+        q0 = I.sphere_halves(leaves, m)
+        bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
+        dt0 = 0.5 * (np.pi / 2) / (m << lmax) * T / (2 * np.pi)
+        return ctx, bufs, ghost, torch.full((1,), dt0, dtype=torch.float64, device="cuda")
+
+    out = {}
+    for name, every, uniform in (("uniform_level5", 0, True), ("amr_every_4", 4, False),
+                                 ("amr_every_step", 1, False)):
+        for rep in range(2):                      # the first run warms up
+            ctx, bufs, ghost, dt = make(uniform)
+            nu = torch.zeros_like(dt)
+            st = torch.zeros(1, dtype=torch.int32, device="cuda")
+            attempts, cells, which, k = 0, 0, 0, 0
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            while True:
+                left = T - ctx.sim_time()
+                if left <= 0:
+                    break
+                chunk = max(1, min(256, int(left / dt.item())))
+                a, b = bufs[which], bufs[1 - which]
+                w, c = ctx.run(a, b, ghost, chunk, k, every, 0, thr, lmin, lmax, dt, nu, st,
+                               fused=0)
+                which = which if w == 0 else 1 - which
+                attempts, cells, k = attempts + chunk, cells + c, k + chunk
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        lv = ctx.leaves()
+        want = I.sphere_halves(lv, m)
+        got = bufs[which][:ctx.state_elems()].double().cpu().numpy().reshape(want.shape)
+        geo = ctx.sphere_geometry().cpu().numpy()
+        kap = geo[:, 0].reshape(len(lv), m + 4, m + 4)[:, 2:m + 2, 2:m + 2]
+        h = np.ldexp(1.0, -lv["level"].astype(int)) / m
+        l1 = float(np.sum(np.abs(got - want)[:, 0] * kap * (h ** 2)[:, None, None]))
+        acc, rej, _ = ctx.step_stats()
+        status = int(st.item())
+        out[name] = {"seconds": el, "attempts": attempts, "accepted": acc, "rejected": rej,
+                     "sim_time": ctx.sim_time(), "cell_updates": cells, "rate": cells / el,
+                     "patches_last": ctx.num_patches(), "l1_error_vs_initial": l1,
+                     "status": status, "status_bits": status_bits([status])}
+    base = out["uniform_level5"]["seconds"]
     for name in out:
         out[name]["speedup_vs_uniform"] = base / out[name]["seconds"]
     return out
@@ -921,20 +1007,24 @@ def main():
     if args.only in ("swirl", "all"):
         res["swirl"] = run_swirl()
         print(f"# example 1 (stand-in swirl): {res['swirl']}", file=sys.stderr, flush=True)
+    if args.only in ("rotation", "all"):
+        res["rotation"] = run_rotation()
+        print(f"# example 2 (sphere rotation): {res['rotation']}", file=sys.stderr, flush=True)
     if args.only in ("mlp", "all"):
         res["mlp"] = run_mlp()
         print(f"# mlp: {res['mlp']}", file=sys.stderr, flush=True)
     # timed legs whose status words carry a bit that marks a wrong step
     bad = {k: r.get("status_bits") for k, r in res.items()
            if isinstance(r, dict) and (int(r.get("status", 0)) & BAD_BITS or r.get("status_bad"))}
-    for leg in ("subcycle", "meshing", "swirl"):
+    for leg in ("subcycle", "meshing", "swirl", "rotation"):
         for k, r in res.get(leg, {}).items():
             if r["status"] & BAD_BITS:
                 bad[leg + "/" + k] = r["status_bits"]
     head = res.get("fp32") or res.get("fp64") or res.get("large32")
     if head is None:
         print(json.dumps({k: res.get(k) for k in ("batch", "batch64", "sphere", "sphere64",
-                                                  "subcycle", "meshing", "swirl", "mlp")
+                                                  "subcycle", "meshing", "swirl", "rotation",
+                                                  "mlp")
                           if k in res}),
               flush=True)
         sys.exit(3 if bad else 0)
@@ -1078,6 +1168,13 @@ def main():
             "stream function, reversing at T/2 = 1): 0/1 halves on the walled unit square, "
             "m = 8, levels 3-6 (uniform: level 6), max - min > 0.2 refines, CFL 0.9 with "
             "redo, FP32, over one period T = 2 (exact state: the initial one)"))
+    if "rotation" in res:
+        out["example2_rotation"] = dict(res["rotation"], workload=(
+            "the paper's sphere example 2: 0/1 halves (split by a great circle off the cube "
+            "edges) carried once around the tilted axis (0.3, -0.4, 0.866) by a rigid "
+            "rotation, on the six-tree cubed sphere (the paper uses two trees), m = 8, "
+            "levels 2-5 (uniform: level 5), max - min > 0.2 refines, CFL 0.9 with redo, "
+            "FP32, plain steps, over one turn T = 1 (exact state: the initial one)"))
     if "mlp" in res:
         out["learned_tagging_mlp"] = res["mlp"]
     if not args.no_cpu_baseline and "fp32" in res:
