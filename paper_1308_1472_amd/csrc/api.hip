@@ -127,6 +127,7 @@ struct DevForest {
   int64_t P = 0;
   DevBuf<double> geo;                // sphere: per-patch geometry tables
   DevBuf<float> geo32;               //   and, for FP32 state, edges and centres in FP32
+  DevBuf<double> flux;               // FCX_ROTATION: the edge fluxes of every patch
 };
 
 struct fcx_ctx {
@@ -521,6 +522,14 @@ static int upload_plan(fcx_ctx* c, const Forest& f, DevForest& dev,
   return FCX_OK;
 }
 
+// FCX_ROTATION: Omega times the unit axis
+static double3 rotation_vector(const fcx_ctx* c) {
+  const double* w = c->cfg.axis;
+  const double om = 2.0 * 3.14159265358979323846 / c->cfg.period /
+                    std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+  return make_double3(om * w[0], om * w[1], om * w[2]);
+}
+
 // Device tables that follow the plan: face-term slots, sum partials and, on
 // the sphere, the geometry of every patch (computed on stream s; without
 // `ordered` the call waits for it).
@@ -537,7 +546,13 @@ static int finish_upload(fcx_ctx* c, hipStream_t s = nullptr, bool ordered = fal
     hipLaunchKernelGGL(k_sphere_metrics, dim3(unsigned(P)), dim3(256), lds, s,
                        c->cur.rec, m, log2i(m), c->cur.geo.p);
     HIPCHK(hipGetLastError());
-    if (c->cfg.precision == 32) {
+    if (c->cfg.physics == FCX_ROTATION) {
+      const int64_t nf = P * 2 * int64_t(FR);
+      HIPCHK(c->cur.flux.ensure(size_t(nf)));
+      hipLaunchKernelGGL(k_rotation_fluxes, dim3(unsigned((nf + 255) / 256)), dim3(256), 0, s,
+                         c->cur.geo.p, c->cur.flux.p, c->cur.rec, P, m, rotation_vector(c));
+      HIPCHK(hipGetLastError());
+    } else if (c->cfg.precision == 32) {
       const int64_t n32 = P * kG32N * int64_t(FR);
       HIPCHK(c->cur.geo32.ensure(size_t(n32)));
       hipLaunchKernelGGL(k_sphere_geo32, dim3(unsigned((n32 + 255) / 256)), dim3(256), 0, s,
@@ -745,7 +760,7 @@ static int launch_sphere_step(fcx_ctx* c, const void* q, const void* ghost, void
   return FCX_OK;
 }
 
-template <typename R, int T>
+template <typename R, int T, int NT>
 static int launch_rotation_step(fcx_ctx* c, const void* q, const void* ghost, void* qn,
                                 const double* dt, double* numax, hipStream_t s) {
   RotationArgs a;
@@ -756,18 +771,13 @@ static int launch_rotation_step(fcx_ctx* c, const void* q, const void* ghost, vo
   a.numax = numax;
   a.rec = c->cur.rec;
   a.geo = c->cur.geo.p;
+  a.flux = c->cur.flux.p;
   a.m = c->cfg.m;
   a.limiter = c->cfg.limiter;
   a.transverse = c->cfg.transverse;
-  const double* w = c->cfg.axis;
-  const double om = 2.0 * 3.14159265358979323846 / c->cfg.period /
-                    std::sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-  a.wx = om * w[0];
-  a.wy = om * w[1];
-  a.wz = om * w[2];
   const int tps = a.m / T;
   const int64_t grid = c->cur.P * tps * tps;
-  hipLaunchKernelGGL((k_rotation_step<R, T>), dim3(unsigned(grid)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((k_rotation_step<R, T, NT>), dim3(unsigned(grid)), dim3(NT), 0, s, a);
   HIPCHK(hipGetLastError());
   return FCX_OK;
 }
@@ -789,10 +799,10 @@ static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
   if (c->cfg.physics == FCX_ROTATION) {
     if (FUSED) return fail(FCX_EINVAL, "no fused step on the sphere");
     if (c->cfg.m % 16 == 0)
-      return dp ? launch_rotation_step<double, 16>(c, q, ghost, qn, dt, numax, s)
-                : launch_rotation_step<float, 16>(c, q, ghost, qn, dt, numax, s);
-    return dp ? launch_rotation_step<double, 8>(c, q, ghost, qn, dt, numax, s)
-              : launch_rotation_step<float, 8>(c, q, ghost, qn, dt, numax, s);
+      return dp ? launch_rotation_step<double, 16, 256>(c, q, ghost, qn, dt, numax, s)
+                : launch_rotation_step<float, 16, 256>(c, q, ghost, qn, dt, numax, s);
+    return dp ? launch_rotation_step<double, 8, 256>(c, q, ghost, qn, dt, numax, s)
+              : launch_rotation_step<float, 8, 256>(c, q, ghost, qn, dt, numax, s);
   }
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_step_m<double, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s)

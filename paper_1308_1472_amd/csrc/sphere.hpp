@@ -677,9 +677,32 @@ struct RotationArgs {
   double* numax;
   const PatchRec* __restrict__ rec;
   const double* __restrict__ geo;
+  const double* __restrict__ flux;   // k_rotation_fluxes' table
   int m, limiter, transverse;
-  double wx, wy, wz;   // Omega times the unit axis
 };
+
+// The flux of every edge of a patch's frame over the computational cell
+// size, signed towards higher index: per patch two frames of (m+4)^2, the
+// low-side xi-edge then the low-side eta-edge of each frame cell.  The flux
+// of an edge is Omega w.(b - a) (+ for xi-edges, - for eta-edges, a, b its
+// corners in index order) over dx; the chord b - a is 2 sin(theta / 2)
+// times the edge's tangent t (+t for xi-edges, -t for eta-edges), with
+// theta = gamma dx the arc's angle, so the flux is (2 / dx) sin(theta / 2)
+// (Omega w).t for either direction.  Formed in FP64 from the FP64 geometry
+// once per forest (the flow is steady).
+__global__ void __launch_bounds__(256)
+k_rotation_fluxes(const double* __restrict__ geo, double* __restrict__ flux,
+                  const PatchRec* __restrict__ rec, int64_t P, int m, double3 w) {
+  const int FR = (m + 4) * (m + 4);
+  const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (t >= P * 2 * FR) return;
+  const int64_t p = t / (2 * FR);
+  const int df = int(t - p * 2 * FR), d = df / FR, f = df - d * FR;
+  const double dx = ldexp(1.0, -rec[p].level) / m;
+  const double* g = geo + size_t(p) * kGeoN * FR + kGeoE * FR + (size_t(d) * FR + f) * 7;
+  const double wt = w.x * g[4] + w.y * g[5] + w.z * g[6];
+  flux[t] = (2.0 / dx) * sin(0.5 * g[0] * dx) * wt;
+}
 
 // One workgroup per T x T tile of a patch, all in LDS:
 //   phase 0: the tile's state with its 2-cell halo, dt / (kappa dx) of every
@@ -690,19 +713,15 @@ struct RotationArgs {
 //     the receiving cell through its own transverse edges at their fluxes;
 //   phase 3: each cell's update, q - dt / (kappa dx) (fluctuations +
 //     differences of the correction fluxes) per direction.
-// The flux of an edge is Omega w.(b - a) (+ for xi-edges, - for eta-edges,
-// a, b its corners in index order) over dx; the chord b - a is 2 sin(theta
-// / 2) times the edge's tangent t (+t for xi-edges, -t for eta-edges), with
-// theta = gamma dx the arc's angle, so the flux is (2 / dx) sin(theta / 2)
-// (Omega w).t for either direction.  Formed in FP64 from the FP64 geometry.
-template <typename R, int T>
-__global__ void __launch_bounds__(256)
+// The edge fluxes come from k_rotation_fluxes' table, rounded to R.
+template <typename R, int T, int NT>
+__global__ void __launch_bounds__(NT)
 k_rotation_step(RotationArgs A) {
   constexpr int FT = T + 4, FRT = FT * FT, M2 = T + 2, NE = (T + 3) * (T + 2);
   __shared__ R Qs[FRT];
   __shared__ double dtk[FRT];
   __shared__ R S[2][NE], Wv[2][NE], CQ[2][NE], TR[2][NE][4];
-  __shared__ double red[4];
+  __shared__ double red[NT / 64];
   const R* q = static_cast<const R*>(A.q);
   const R* ghost = static_cast<const R*>(A.ghost);
   const int m = A.m, FR = (m + 4) * (m + 4), G = 8 * m + 16, tps = m / T;
@@ -725,13 +744,12 @@ k_rotation_step(RotationArgs A) {
     Qs[f] = v;
     dtk[f] = dt / (geo[kGeoK * FR + fidx(m, i, j)] * dx);
   }
+  const double* fl0 = A.flux + size_t(p) * 2 * FR;
   for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
     const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
     // the low-side d-edge of the cell on the edge's high side
     const int ir = d == 0 ? e : r, jr = d == 0 ? r : e;
-    const double* g = geo + kGeoE * FR + (size_t(d) * FR + fidx(m, i0 + ir, j0 + jr)) * 7;
-    const double wt = A.wx * g[4] + A.wy * g[5] + A.wz * g[6];
-    S[d][er] = R((2.0 / dx) * sin(0.5 * g[0] * dx) * wt);
+    S[d][er] = R(fl0[d * FR + fidx(m, i0 + ir, j0 + jr)]);
   }
   __syncthreads();
   // phase 1
