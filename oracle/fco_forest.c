@@ -235,7 +235,9 @@ fco_mesh *fco_mesh_new(int32_t ntrees, const fco_tree *trees, int64_t n,
     while (mesh->hslot[h] >= 0) h = (h + 1) & (uint64_t)(cap - 1);
     mesh->hslot[h] = s;
   }
-  if (sphere && (ntrees != 6 || fco_sphere_build(mesh) != 0)) {
+  mesh->pillow = sphere && ntrees == 2;
+  if (sphere && ((ntrees != 6 && !fco_pillow_trees(ntrees, trees)) ||
+                 fco_sphere_build(mesh) != 0)) {
     fco_mesh_free(mesh);
     return NULL;
   }

@@ -11,7 +11,9 @@ struct fco_mesh {
   int64_t n;
   fco_leaf *leaves;
   int32_t m;
-  int32_t sphere;     /* 1: trees are the six gnomonic cubed-sphere faces */
+  int32_t sphere;     /* 1: trees are the six gnomonic cubed-sphere faces,
+                         or the two hemispheres of the pillow sphere   */
+  int32_t pillow;     /* sphere of two trees (fco_sphere.c)             */
   int32_t maxlevel;
   int64_t hcap;
   int64_t *hslot;     /* open-addressing table of leaf indices, -1 = free */
@@ -37,6 +39,8 @@ int fco_cross_face(const fco_tree *trees, int32_t t, int32_t f, int64_t *x,
                    int64_t *y, int32_t *tout);
 /* geometry tables of a sphere mesh (called by fco_mesh_new) */
 int fco_sphere_build(fco_mesh *mesh);
+/* 1 if the two trees are glued as the pillow sphere (fco_sphere.c) */
+int fco_pillow_trees(int32_t ntrees, const fco_tree *trees);
 /* leaf (index) containing an in-tree point, -1 if none */
 int64_t fco_leaf_at(const fco_mesh *mesh, int32_t tree, int64_t x, int64_t y);
 /* 1 if face f of leaf p lies on a physical boundary of its tree */

@@ -14,6 +14,24 @@
  * unit sphere.  T(0) = -1, T(1) = 1 and T(1 - s) = -T(s) exactly, so a
  * point on a cube edge gets the same coordinates from either face.
  *
+ * Pillow sphere (two trees; the paper's Sec. 5 sphere example maps one
+ * quadtree to each hemisphere, after Calhoun, Helzel and LeVeque).  The map
+ * here is this oracle's own choice of such a map: with x = 2 xi - 1, y =
+ * 2 eta - 1 and d = max(|x|, |y|), the square of half-width d goes to the
+ * circle of polar angle theta = d pi / 2 about the tree's pole, each point
+ * along its own direction (x, y) / |(x, y)|:
+ *   tree 0: (sin theta x / rho, sin theta y / rho, cos theta), rho = |(x, y)|;
+ *   tree 1: the same with the second and third components negated (so that
+ *     both trees are right-handed seen from outside).
+ * The square's boundary (d = 1) goes to the equator, exactly (sin = 1,
+ * cos = 0 there); tree 0's face eta = 0 meets tree 1's face eta = 1 and
+ * its face eta = 1 meets tree 1's eta = 0 (tangential coordinates the same
+ * way), and the faces xi = 0 and xi = 1 meet their namesakes with the
+ * tangential coordinate reversed.  Each square corner is a point where only
+ * the two trees' corner cells meet (each with a straight angle); the region
+ * beyond it, reached across either face, is the own tree's corner mirrored
+ * through that point.
+ *
  * Geometry of a patch, for its cells and its two ghost layers: a corner
  * point outside the patch's tree is carried into the tree that contains it
  * and mapped there, so ghost cells have the geometry of the cells whose
@@ -65,12 +83,52 @@ static double tline(int64_t X) {
   return d < 0 ? -t : t;
 }
 
-static void face_point(int32_t t, int64_t X, int64_t Y, double r[3]) {
+int fco_pillow_trees(int32_t ntrees, const fco_tree *trees) {
+  static const int32_t NF[4] = {0, 1, 3, 2}, OR[4] = {1, 1, 0, 0};
+  if (ntrees != 2) return 0;
+  for (int t = 0; t < 2; ++t)
+    for (int f = 0; f < 4; ++f)
+      if (trees[t].bc[f] != 0 || trees[t].nbr_tree[f] != 1 - t ||
+          trees[t].nbr_face[f] != NF[f] || trees[t].orient[f] != OR[f])
+        return 0;
+  return 1;
+}
+
+static void pillow_point(int32_t t, int64_t X, int64_t Y, double r[3]) {
+  const double x = ldexp((double)(2 * X - FCO_SIDE), -FCO_S);
+  const double y = ldexp((double)(2 * Y - FCO_SIDE), -FCO_S);
+  const double d = fmax(fabs(x), fabs(y));
+  double s = 0.0, c = 1.0, ux = 0.0, uy = 0.0;
+  if (d > 0.0) {
+    const double rho = sqrt(x * x + y * y);
+    ux = x / rho;
+    uy = y / rho;
+    if (d == 1.0) {
+      s = 1.0;
+      c = 0.0;
+    } else {
+      s = sin(d * 1.57079632679489661923);
+      c = cos(d * 1.57079632679489661923);
+    }
+  }
+  r[0] = s * ux;
+  r[1] = t == 1 ? 0.0 - s * uy : s * uy;
+  r[2] = t == 1 ? 0.0 - c : c;
+}
+
+static void cube_point(int32_t t, int64_t X, int64_t Y, double r[3]) {
   const double a = tline(X), b = tline(Y);
   double p[3];
   for (int c = 0; c < 3; ++c) p[c] = FACE[t][0][c] + a * FACE[t][1][c] + b * FACE[t][2][c];
   const double s = sqrt(p[0] * p[0] + p[1] * p[1] + p[2] * p[2]);
   for (int c = 0; c < 3; ++c) r[c] = p[c] / s;
+}
+
+static void face_point(const fco_mesh *mesh, int32_t t, int64_t X, int64_t Y, double r[3]) {
+  if (mesh->pillow)
+    pillow_point(t, X, Y, r);
+  else
+    cube_point(t, X, Y, r);
 }
 
 /* sphere point of tree coordinates (X, Y) of tree t, carried into the tree
@@ -91,7 +149,7 @@ static void map_point(const fco_mesh *mesh, int32_t t, int64_t X, int64_t Y,
       y = Y;
     }
   }
-  face_point(t2, x, y, r);
+  face_point(mesh, t2, x, y, r);
 }
 
 static void cross3(const double a[3], const double b[3], double o[3]) {
@@ -150,7 +208,7 @@ static void patch_corners(const fco_mesh *mesh, int64_t p, double *cor, double *
     for (int I = -2; I <= m + 2; ++I) {
       const int64_t X = x0 + I * cs, Y = y0 + J * cs;
       map_point(mesh, a->tree, X, Y, &cor[3 * ((J + 2) * NC + (I + 2))]);
-      face_point(a->tree, X, Y, &ext[3 * ((J + 2) * NC + (I + 2))]);
+      face_point(mesh, a->tree, X, Y, &ext[3 * ((J + 2) * NC + (I + 2))]);
     }
 }
 

@@ -425,14 +425,50 @@ def dam_break_spec(seed: int) -> dict:
             "radius": 0.15 + 0.15 * g.uniform(), "h_in": 1.5 + 1.5 * g.uniform()}
 
 
-def sphere_centres(leaves: np.ndarray, m: int) -> np.ndarray:
-    """Unit vectors of the mapped cell centres, shape (P, 3, m, m)."""
+def pillow_sphere() -> np.ndarray:
+    """Connectivity of the two-tree (pillow) sphere: tree t's faces 0 and 1
+    meet the other tree's faces 0 and 1 with the tangential coordinate
+    reversed, its face 2 meets the other's face 3 and its face 3 the other's
+    face 2, the same way."""
+    trees = np.zeros(2, dtype=TREE_DTYPE)
+    trees["bc"] = BC_CONNECTED
+    for t in range(2):
+        trees["nbr_tree"][t] = 1 - t
+        trees["nbr_face"][t] = [0, 1, 3, 2]
+        trees["orient"][t] = [1, 1, 0, 0]
+    return trees
+
+
+def pillow_point(tree, xi, eta):
+    """The two-tree sphere map: with x = 2 xi - 1, y = 2 eta - 1 and d =
+    max(|x|, |y|), the point at polar angle d pi / 2 about the tree's pole
+    along the direction (x, y); tree 1 negates the second and third
+    components.  Shape (3,) + shape of xi."""
+    x = 2.0 * np.asarray(xi, float) - 1.0
+    y = 2.0 * np.asarray(eta, float) - 1.0
+    d = np.maximum(np.abs(x), np.abs(y))
+    rho = np.sqrt(x * x + y * y)
+    safe = np.where(rho > 0, rho, 1.0)
+    th = 0.5 * np.pi * d
+    s = np.where(d >= 1.0, 1.0, np.sin(th))
+    c = np.where(d >= 1.0, 0.0, np.cos(th))
+    p = np.stack([s * x / safe, s * y / safe, c])
+    if tree == 1:
+        p[1] = -p[1]
+        p[2] = -p[2]
+    return p
+
+
+def sphere_centres(leaves: np.ndarray, m: int, pillow: bool = False) -> np.ndarray:
+    """Unit vectors of the mapped cell centres, shape (P, 3, m, m), on the
+    cubed sphere or (pillow) the two-tree sphere."""
     xi, eta = cell_centres(leaves, m)
     out = np.empty((len(leaves), 3, m, m))
-    for t in range(6):
+    for t in range(2 if pillow else 6):
         s = leaves["tree"] == t
         if s.any():
-            out[s] = np.moveaxis(sphere_point(t, xi[s], eta[s]), 0, 1)
+            f = pillow_point if pillow else sphere_point
+            out[s] = np.moveaxis(f(t, xi[s], eta[s]), 0, 1)
     return out
 
 
@@ -454,19 +490,20 @@ def sphere_bumps(leaves, m, n=16, seed=0, amp=0.1, width=30.0):
     return q
 
 
-def sphere_scalar(leaves, m, fn):
+def sphere_scalar(leaves, m, fn, pillow=False):
     """(P, 1, m, m) scalar state fn(r) at the cell centres, r of shape
     (P, 3, m, m) (unit vectors)."""
-    return np.asarray(fn(sphere_centres(leaves, m)), dtype=np.float64)[:, None]
+    return np.asarray(fn(sphere_centres(leaves, m, pillow)), dtype=np.float64)[:, None]
 
 
-def sphere_halves(leaves, m, normal=(0.35, -0.5, 0.79)):
+def sphere_halves(leaves, m, normal=(0.35, -0.5, 0.79), pillow=False):
     """q = 1 on the half of the sphere that `normal` points into, 0 on the
     other: a 0/1 state whose interface (a great circle) is not aligned with
-    the cube's edges.  (P, 1, m, m)."""
+    the trees' edges.  (P, 1, m, m)."""
     w = np.asarray(normal, float) / np.linalg.norm(normal)
     return sphere_scalar(leaves, m,
-                         lambda r: (np.einsum("pkij,k->pij", r, w) > 0).astype(np.float64))
+                         lambda r: (np.einsum("pkij,k->pij", r, w) > 0).astype(np.float64),
+                         pillow)
 
 
 def sphere_bump(leaves, m, lat=0.3, lon=0.5, amp=0.1, width=100.0):
