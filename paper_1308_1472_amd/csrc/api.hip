@@ -154,6 +154,7 @@ struct fcx_ctx {
   HostBuf staging;
   int cus = 256;
   bool threads_auto = false;         // threads per tile left to the library
+  bool pillow = false;               // sphere of two trees (else the cube's six)
   int device = 0;                  // the HIP device the context was created on
   size_t lds_per_block = 65536;    // device limit of LDS per workgroup
   Plan plan;                       // host copy of the current forest's plan
@@ -205,6 +206,20 @@ static bool cube_connectivity(const std::vector<fcx_tree>& t) {
         for (int c = 0; c < 3; ++c)
           if (a[e][c] != b[o ? 1 - e : e][c]) return false;
     }
+  return true;
+}
+
+// The two trees glued as the pillow sphere (each tree a hemisphere): faces
+// 0 and 1 meet their namesakes reversed, face 2 meets face 3 and face 3
+// face 2 the same way.
+static bool pillow_connectivity(const std::vector<fcx_tree>& t) {
+  if (t.size() != 2) return false;
+  static const int nf[4] = {0, 1, 3, 2}, orr[4] = {1, 1, 0, 0};
+  for (int tr = 0; tr < 2; ++tr)
+    for (int f = 0; f < 4; ++f)
+      if (t[tr].bc[f] != 0 || t[tr].nbr_tree[f] != 1 - tr || t[tr].nbr_face[f] != nf[f] ||
+          t[tr].orient[f] != orr[f])
+        return false;
   return true;
 }
 
@@ -328,8 +343,11 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
         if (T.bc[f] == 0 && (T.nbr_face[f] != (f ^ 1) || T.orient[f] != 0))
           return fail(FCX_EINVAL, "shallow water needs axis-aligned tree gluing");
   }
-  if (sphere_phys(cfg->physics) && !cube_connectivity(t))
-    return fail(FCX_EINVAL, "the sphere needs the six cube faces glued as the cube");
+  const bool pillow = cfg->physics == FCX_ROTATION && pillow_connectivity(t);
+  if (sphere_phys(cfg->physics) && !pillow && !cube_connectivity(t))
+    return fail(FCX_EINVAL, cfg->physics == FCX_ROTATION
+                                ? "the rotation needs the cube's six trees or the pillow's two"
+                                : "the sphere needs the six cube faces glued as the cube");
   if (sphere_phys(cfg->physics) && cfg->m % kSphereTile != 0)
     return fail(FCX_EINVAL, "the sphere needs m a multiple of 8");
   fcx_ctx* c = new fcx_ctx;
@@ -337,6 +355,7 @@ int fcx_create(const fcx_config* cfg, int32_t n_trees, const fcx_tree* trees,
   c->cfg.tile = tile;
   c->cfg.threads = threads;
   c->threads_auto = cfg->threads == 0;
+  c->pillow = pillow;
   c->tile = tile;
   c->meqn = (cfg->physics == FCX_ADVECTION || cfg->physics == FCX_SWIRL ||
              cfg->physics == FCX_ROTATION)
@@ -544,7 +563,7 @@ static int finish_upload(fcx_ctx* c, hipStream_t s = nullptr, bool ordered = fal
     HIPCHK(c->cur.geo.ensure(size_t(P) * kGeoN * FR));
     const size_t lds = sizeof(double) * 3 * (m + 5) * (m + 5);
     hipLaunchKernelGGL(k_sphere_metrics, dim3(unsigned(P)), dim3(256), lds, s,
-                       c->cur.rec, m, log2i(m), c->cur.geo.p);
+                       c->cur.rec, m, log2i(m), c->cur.geo.p, int(c->pillow));
     HIPCHK(hipGetLastError());
     if (c->cfg.physics == FCX_ROTATION) {
       const int64_t nf = P * 2 * int64_t(FR);

@@ -56,14 +56,49 @@ __device__ inline void face_point(int t, int32_t X, int32_t Y, double* r) {
   for (int c = 0; c < 3; ++c) r[c] = p[c] / s;
 }
 
+// The pillow sphere (two trees, one per hemisphere): with x = 2 xi - 1,
+// y = 2 eta - 1 and d = max(|x|, |y|), the square of half-width d goes to
+// the circle of polar angle d pi / 2 about the tree's pole, each point along
+// its direction (x, y) / |(x, y)|; tree 1 negates the second and third
+// components (both trees right-handed seen from outside).  The boundary
+// (d = 1) lands on the equator exactly, and glued faces give identical
+// points: faces 0 and 1 meet their namesakes reversed, face 2 meets face 3.
+__device__ inline void pillow_point(int t, int32_t X, int32_t Y, double* r) {
+  const double x = ldexp(double(2 * int64_t(X) - kSide), -kS);
+  const double y = ldexp(double(2 * int64_t(Y) - kSide), -kS);
+  const double d = fmax(fabs(x), fabs(y));
+  double s = 0.0, c = 1.0, ux = 0.0, uy = 0.0;
+  if (d > 0.0) {
+    const double rho = sqrt(x * x + y * y);
+    ux = x / rho;
+    uy = y / rho;
+    if (d == 1.0) {
+      s = 1.0;
+      c = 0.0;
+    } else {
+      s = sin(d * 1.57079632679489661923);
+      c = cos(d * 1.57079632679489661923);
+    }
+  }
+  r[0] = s * ux;
+  r[1] = t == 1 ? 0.0 - s * uy : s * uy;
+  r[2] = t == 1 ? 0.0 - c : c;
+}
+
+__device__ inline void tree_point(bool pillow, int t, int32_t X, int32_t Y, double* r) {
+  if (pillow) pillow_point(t, X, Y, r);
+  else face_point(t, X, Y, r);
+}
+
 // Sphere point of tree coordinates (X, Y) of patch r's tree, carried into
-// the tree that holds it (trees closed; own face extended at a cube vertex).
+// the tree that holds it (trees closed; own face extended at a cube vertex;
+// beyond a pillow corner, the point mirrored into the own tree).
 __device__ inline void patch_point(const PatchRec* __restrict__ rec, const PatchRec& r,
-                                   int32_t X, int32_t Y, double* out) {
+                                   int32_t X, int32_t Y, double* out, bool pillow) {
   const int tree = r.flags >> kTreeShift;
   const int32_t side = int32_t(kSide);
   const bool ox = X < 0 || X > side, oy = Y < 0 || Y > side;
-  if (!ox && !oy) { face_point(tree, X, Y, out); return; }
+  if (!ox && !oy) { tree_point(pillow, tree, X, Y, out); return; }
   int32_t code, nb;
   if (ox && !oy) {
     const int f = X < 0 ? 0 : 1;
@@ -77,11 +112,11 @@ __device__ inline void patch_point(const PatchRec* __restrict__ rec, const Patch
     const int c = (X > 0) + 2 * (Y > 0);
     nb = r.nbr[8 + c];
     code = r.xf[4 + c];
-    if (nb < 0) { face_point(tree, X, Y, out); return; }   // cube vertex
+    if (nb < 0) { tree_point(pillow, tree, X, Y, out); return; }   // cube vertex
   }
   int32_t X2, Y2;
   xf_apply(code, X, Y, X2, Y2);
-  face_point(rec[nb].flags >> kTreeShift, X2, Y2, out);
+  tree_point(pillow, rec[nb].flags >> kTreeShift, X2, Y2, out);
 }
 
 __device__ __forceinline__ void cross3(const double* a, const double* b, double* o) {
@@ -130,7 +165,8 @@ __device__ __forceinline__ bool vertex_cell(const PatchRec& r, int m, int i, int
 // corner grid of (m+5)^2 points; own-face points are recomputed where a
 // cube-vertex region needs them).
 __global__ void __launch_bounds__(256)
-k_sphere_metrics(const PatchRec* __restrict__ rec, int m, int lm, double* __restrict__ geo) {
+k_sphere_metrics(const PatchRec* __restrict__ rec, int m, int lm, double* __restrict__ geo,
+                 int pillow) {
   extern __shared__ double can[];
   const int NC = m + 5, FR = (m + 4) * (m + 4);
   const int p = blockIdx.x;
@@ -141,7 +177,7 @@ k_sphere_metrics(const PatchRec* __restrict__ rec, int m, int lm, double* __rest
   const int32_t x0 = r.ix << sh, y0 = r.iy << sh;
   for (int k = threadIdx.x; k < NC * NC; k += blockDim.x) {
     const int32_t X = x0 + (k % NC - 2) * cs, Y = y0 + (k / NC - 2) * cs;
-    patch_point(rec, r, X, Y, can + 3 * k);
+    patch_point(rec, r, X, Y, can + 3 * k, pillow != 0);
   }
   __syncthreads();
   const double dx = ldexp(1.0, -r.level) / m;
@@ -149,7 +185,7 @@ k_sphere_metrics(const PatchRec* __restrict__ rec, int m, int lm, double* __rest
   // corner (I, J): canonical from LDS, or the own face mapping into buf
   auto pt = [&](bool own, int I, int J, double* buf) -> const double* {
     if (!own) return can + 3 * ((J + 2) * NC + (I + 2));
-    face_point(tree, x0 + I * cs, y0 + J * cs, buf);
+    tree_point(pillow != 0, tree, x0 + I * cs, y0 + J * cs, buf);
     return buf;
   };
   for (int f = threadIdx.x; f < FR; f += blockDim.x) {
@@ -160,7 +196,7 @@ k_sphere_metrics(const PatchRec* __restrict__ rec, int m, int lm, double* __rest
                  *C = pt(vc, i, j, bc), *D = pt(vc, i - 1, j, bd);
     g[kGeoK * FR + f] = (tri_area(A, B, C) + tri_area(A, C, D)) / (dx * dx);
     patch_point(rec, r, x0 + (2 * i - 1) * (cs >> 1), y0 + (2 * j - 1) * (cs >> 1),
-                g + kGeoC * FR + 3 * f);
+                g + kGeoC * FR + 3 * f, pillow != 0);
     for (int dir = 0; dir < 2; ++dir) {
       const bool vn = dir == 0 ? vertex_cell(r, m, i - 1, j) : vertex_cell(r, m, i, j - 1);
       const bool own = vc && vn;

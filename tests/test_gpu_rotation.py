@@ -1,7 +1,8 @@
 """GPU parity of the advection by a rigid rotation of the cubed sphere
 (FCX_ROTATION: the colour equation in capacity form with edge fluxes from
 the rotation's stream function, the flow of the paper's Sec. 5 sphere
-example) against the CPU oracle: FP64 within 1e-12 relative to max|q| and
+example) against the CPU oracle, on the six-tree cubed sphere and on the
+two-tree (pillow) sphere of the example (geometry tables too): FP64 within 1e-12 relative to max|q| and
 Courant numbers within 1e-12, FP32 within 1e-5 relative L1 (Courant numbers
 1e-6), on adaptive sphere forests with 8 x 8 and 16 x 16 tiles, from the
 0/1 halves of the example and from a smooth state; capacity-weighted ghost
@@ -25,25 +26,58 @@ pytestmark = pytest.mark.gpu
 AXIS = (0.3, -0.4, 0.866)
 
 
-def _forest(seed, lmin=1, lmax=3, n=12):
-    trees = I.cubed_sphere()
-    return trees, fcx.balance(trees, I.random_leaves(seed, 6, lmin, lmax, n))
+def _forest(seed, lmin=1, lmax=3, n=12, pillow=False):
+    trees = I.pillow_sphere() if pillow else I.cubed_sphere()
+    return trees, fcx.balance(trees, I.random_leaves(seed, len(trees), lmin, lmax, n))
 
 
-def _blob(lv, m):
+def _blob(lv, m, pillow=False):
     c = np.array([0.6, 0.0, 0.8])
     return I.sphere_scalar(lv, m, lambda r: np.exp(-6.0 * np.sum((r - c[None, :, None, None]) ** 2,
-                                                                 axis=1)))
+                                                                 axis=1)), pillow)
+
+
+@pytest.mark.parametrize("seed", [None, 5])
+def test_pillow_geometry_matches_oracle(seed):
+    say(f"[rotation] pillow geometry seed={seed}")
+    m = 8
+    trees = I.pillow_sphere()
+    lv = fcx.sfc_sort(I.uniform_leaves(2, 2)) if seed is None else \
+        fcx.balance(trees, I.random_leaves(seed, 2, 1, 4, 14))
+    ctx = fcx.Context(fcx.config(m, 64, fcx.FCX_ROTATION), trees)
+    ctx.upload_forest(lv)
+    got = ctx.sphere_geometry().cpu().numpy()
+    mesh = O.Mesh(trees, lv, m, sphere=True)
+    FR = (m + 4) ** 2
+    cen = got[:, 1:4].reshape(len(lv), FR, 3)
+    edges = [got[:, 4 + 7 * d:11 + 7 * d].reshape(len(lv), FR, 7) for d in (0, 1)]
+    kap = got[:, 0].reshape(len(lv), FR)
+    for p in range(len(lv)):
+        for f in range(FR):
+            i, j = f % (m + 4) - 1, f // (m + 4) - 1
+            if i in (-1, m + 2) and j in (-1, m + 2):
+                continue
+            assert abs(kap[p, f] / O.sphere_kappa(mesh, p, i, j) - 1) <= 1e-13
+            np.testing.assert_allclose(cen[p, f], O.sphere_centre(mesh, p, i, j), rtol=0, atol=1e-14)
+            for d in (0, 1):
+                g, n, t = O.sphere_edge(mesh, p, d, i, j)
+                np.testing.assert_allclose(edges[d][p, f], np.concatenate([[g], n, t]),
+                                           rtol=1e-13, atol=1e-14)
 
 
 @pytest.mark.parametrize("precision", [64, 32])
 @pytest.mark.parametrize("m", [8, 16, 32])
-@pytest.mark.parametrize("state", ["halves", "blob"])
+@pytest.mark.parametrize("state", ["halves", "blob", "pillow"])
 def test_steps_match_oracle(precision, m, state):
     say(f"[rotation] steps precision={precision} m={m} state={state}")
-    trees, lv = _forest(3 + m, 1, 3 if m < 32 else 2, 12)
+    pillow = state == "pillow"
+    if pillow:      # two trees: levels 1-3 at every m
+        trees, lv = _forest(3 + m, 1, 3, 4 if m == 32 else 12, True)
+    else:
+        trees, lv = _forest(3 + m, 1, 3 if m < 32 else 2, 12)
     assert len(set(lv["level"].tolist())) >= 2
-    q0 = I.sphere_halves(lv, m) if state == "halves" else _blob(lv, m)
+    q0 = _blob(lv, m, True) + I.sphere_halves(lv, m, pillow=True) if pillow else \
+        (I.sphere_halves(lv, m) if state == "halves" else _blob(lv, m))
     cfg = fcx.config(m, precision, fcx.FCX_ROTATION, period=2.5, axis=AXIS)
     gpu = Gpu(cfg, trees, lv)
     gpu.set_state(q0)
@@ -100,14 +134,15 @@ def test_uniform_state_is_kept_bitwise():
         assert np.array_equal(g.state(), q0)
 
 
-def test_run_loop_with_regrids_matches_oracle():
+@pytest.mark.parametrize("pillow", [False, True])
+def test_run_loop_with_regrids_matches_oracle(pillow):
     """fcx_run (plain steps, a criterion regrid every 2 steps, the CFL rule
     with redo) against the oracle's sequence of the same operations."""
     import torch
-    say("[rotation] run loop")
+    say(f"[rotation] run loop pillow={pillow}")
     m, lmin, lmax, every, thr, steps = 8, 1, 4, 2, 0.25, 7
-    trees, lv0 = _forest(12, 1, 3, 12)
-    q0 = I.sphere_halves(lv0, m)
+    trees, lv0 = _forest(12, 1, 3, 12, pillow)
+    q0 = I.sphere_halves(lv0, m, pillow=pillow)
     cfg = fcx.config(m, 64, fcx.FCX_ROTATION, period=3.0, axis=AXIS)
     par = oracle_params(cfg)
     mesh = O.Mesh(trees, lv0, m, sphere=True)
@@ -131,7 +166,7 @@ def test_run_loop_with_regrids_matches_oracle():
     dtt = torch.full((1,), dt0, dtype=torch.float64, device="cuda")
     nut = torch.zeros_like(dtt)
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
-    pmax = 6 * (1 << (2 * lmax))
+    pmax = len(trees) * (1 << (2 * lmax))
     bufs = [torch.zeros(pmax * m * m, dtype=torch.float64, device="cuda") for _ in range(2)]
     bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
     ghost = torch.empty(pmax * (8 * m + 16), dtype=torch.float64, device="cuda")
@@ -154,6 +189,9 @@ def test_refused_calls():
         fcx.Context(fcx.config(8, 64, fcx.FCX_ROTATION, axis=(0.0, 0.0, 0.0)), trees)
     with pytest.raises(fcx.FcxError):
         fcx.Context(fcx.config(8, 64, fcx.FCX_ROTATION), I.walled_square()[0])
+    # the two-tree sphere carries the rotation only
+    with pytest.raises(fcx.FcxError):
+        fcx.Context(fcx.config(8, 64, fcx.FCX_SPHERE), I.pillow_sphere())
     cfg = fcx.config(8, 64, fcx.FCX_ROTATION)
     ctx = fcx.Context(cfg, trees)
     ctx.upload_forest(lv)
