@@ -441,36 +441,38 @@ def run_swirl(precision=32, m=8, lmin=3, lmax=6, T=2.0, thr=0.2):
     return out
 
 
-def run_rotation(precision=32, m=8, lmin=2, lmax=5, T=1.0, thr=0.2,
+def run_rotation(precision=32, m=8, lmin=3, lmax=6, T=1.0, thr=0.2,
                  axis=(0.3, -0.4, 0.866)):
     """The paper's sphere example (Sec. 5, Example 2): q = 1 on one half of
     the sphere and 0 on the other, the halves split by a great circle that
-    follows no cube edge, carried by a rigid rotation (FCX_ROTATION) once
+    follows no tree edge, carried by a rigid rotation (FCX_ROTATION) once
     around a tilted axis, so the exact state after the period T is the
-    initial one.  On the six-tree cubed sphere (the paper maps two trees,
-    one per hemisphere), m = 8, levels 2-5 (32^2 to 256^2 cells per cube
-    face), refined where max - min of q over a patch exceeds 0.2, CFL 0.9
-    with the redo rule, plain steps; uniform level 5 for comparison.  Runs
-    fcx_run in chunks until the simulated time reaches T (at most one step
-    past it); reports wall clock, cell updates, rate and the L1 error
-    (area weighted) against the initial state."""
+    initial one.  On the two-tree (pillow) sphere of the example, one tree
+    per hemisphere, m = 8, levels 3-6 (64^2 to 512^2 cells per hemisphere),
+    refined where max - min of q over a patch exceeds 0.2, CFL 0.9 with the
+    redo rule, plain steps; uniform level 6 for comparison.  Runs fcx_run in
+    chunks until the simulated time reaches T (at most one step past it);
+    reports wall clock, cell updates, rate and the L1 error (area weighted)
+    against the initial state."""
     import numpy as np
     import torch
     from paper_1308_1472_amd import fcx
     from paper_1308_1472_amd import inputs as I
-    trees = I.cubed_sphere()
+    trees = I.pillow_sphere()
+    nt = len(trees)
     dtype = torch.float32 if precision == 32 else torch.float64
 
     def make(uniform):
         cfg = fcx.config(m, precision, fcx.FCX_ROTATION, period=T, axis=axis)
         ctx = fcx.Context(cfg, trees)
         if uniform:
-            leaves = fcx.sfc_sort(I.uniform_leaves(6, lmax))
+            leaves = fcx.sfc_sort(I.uniform_leaves(nt, lmax))
         else:
-            leaves = fcx.sfc_sort(I.uniform_leaves(6, lmin))
+            leaves = fcx.sfc_sort(I.uniform_leaves(nt, lmin))
             for _ in range(2 * (lmax - lmin) + 2):
                 ctx.upload_forest(leaves)
-                q = torch.from_numpy(I.sphere_halves(leaves, m).ravel()).to(dtype).cuda()
+                q = torch.from_numpy(I.sphere_halves(leaves, m, pillow=True).ravel()).to(
+                    dtype).cuda()
                 g = torch.empty(ctx.ghost_elems(), dtype=dtype, device="cuda")
                 ctx.regrid(q, g, 0, thr, lmin, lmax)
                 new = ctx.leaves()
@@ -478,16 +480,16 @@ def run_rotation(precision=32, m=8, lmin=2, lmax=5, T=1.0, thr=0.2,
                     break
                 leaves = new
         ctx.upload_forest(leaves)
-        pmax = 6 << (2 * lmax)
+        pmax = nt << (2 * lmax)
         bufs = [torch.empty(pmax * m * m, dtype=dtype, device="cuda") for _ in range(2)]
         ghost = torch.empty(pmax * (8 * m + 16), dtype=dtype, device="cuda")
-        q0 = I.sphere_halves(leaves, m)
+        q0 = I.sphere_halves(leaves, m, pillow=True)
         bufs[0][:q0.size].copy_(torch.from_numpy(q0.ravel()))
         dt0 = 0.5 * (np.pi / 2) / (m << lmax) * T / (2 * np.pi)
         return ctx, bufs, ghost, torch.full((1,), dt0, dtype=torch.float64, device="cuda")
 
     out = {}
-    for name, every, uniform in (("uniform_level5", 0, True), ("amr_every_4", 4, False),
+    for name, every, uniform in (("uniform_level6", 0, True), ("amr_every_4", 4, False),
                                  ("amr_every_step", 1, False)):
         for rep in range(2):                      # the first run warms up
             ctx, bufs, ghost, dt = make(uniform)
@@ -509,7 +511,7 @@ def run_rotation(precision=32, m=8, lmin=2, lmax=5, T=1.0, thr=0.2,
             torch.cuda.synchronize()
             el = time.perf_counter() - t0
         lv = ctx.leaves()
-        want = I.sphere_halves(lv, m)
+        want = I.sphere_halves(lv, m, pillow=True)
         got = bufs[which][:ctx.state_elems()].double().cpu().numpy().reshape(want.shape)
         geo = ctx.sphere_geometry().cpu().numpy()
         kap = geo[:, 0].reshape(len(lv), m + 4, m + 4)[:, 2:m + 2, 2:m + 2]
@@ -521,7 +523,7 @@ def run_rotation(precision=32, m=8, lmin=2, lmax=5, T=1.0, thr=0.2,
                      "sim_time": ctx.sim_time(), "cell_updates": cells, "rate": cells / el,
                      "patches_last": ctx.num_patches(), "l1_error_vs_initial": l1,
                      "status": status, "status_bits": status_bits([status])}
-    base = out["uniform_level5"]["seconds"]
+    base = out["uniform_level6"]["seconds"]
     for name in out:
         out[name]["speedup_vs_uniform"] = base / out[name]["seconds"]
     return out
@@ -1170,10 +1172,10 @@ def main():
             "redo, FP32, over one period T = 2 (exact state: the initial one)"))
     if "rotation" in res:
         out["example2_rotation"] = dict(res["rotation"], workload=(
-            "the paper's sphere example 2: 0/1 halves (split by a great circle off the cube "
+            "the paper's sphere example 2: 0/1 halves (split by a great circle off the tree "
             "edges) carried once around the tilted axis (0.3, -0.4, 0.866) by a rigid "
-            "rotation, on the six-tree cubed sphere (the paper uses two trees), m = 8, "
-            "levels 2-5 (uniform: level 5), max - min > 0.2 refines, CFL 0.9 with redo, "
+            "rotation, on the two-tree (pillow) sphere, one tree per hemisphere, m = 8, "
+            "levels 3-6 (uniform: level 6), max - min > 0.2 refines, CFL 0.9 with redo, "
             "FP32, plain steps, over one turn T = 1 (exact state: the initial one)"))
     if "mlp" in res:
         out["learned_tagging_mlp"] = res["mlp"]
