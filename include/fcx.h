@@ -64,7 +64,11 @@ extern "C" {
  * step only (fcx_advance_subcycled and batches refuse it). */
 /* FCX_ROTATION (Sec. 5, the sphere example: a 0/1 colour field carried by
  * a rigid rotation of the sphere): the colour equation on the cubed sphere
- * (the six trees and geometry of FCX_SPHERE, see fcx_sphere_geometry) with
+ * (the six trees and geometry of FCX_SPHERE, see fcx_sphere_geometry) or on
+ * the two-tree (pillow) sphere of the example, one tree per hemisphere:
+ * tree t's faces 0 and 1 glued to the other tree's faces 0 and 1 with
+ * orient 1, its face 2 to the other's face 3 and face 3 to face 2 with
+ * orient 0 (fcx_create recognises either gluing), with
  * velocity u = Omega w x r, w = axis / |axis|, Omega = 2 pi / period.  u is
  * the surface curl of psi = Omega w.r, so the flux of u through a cell
  * edge is psi's difference between the edge's corners: each edge carries
@@ -447,7 +451,13 @@ int fcx_batch_sums(fcx_batch *batch, const void *q, double *sums, void *stream);
  * Ghost cells carry the geometry of the cells they copy (points outside
  * the tree are mapped in the tree that holds them); at a cube vertex, where
  * no tree covers the corner region, that region uses the patch's own face
- * mapping extended. */
+ * mapping extended.
+ * Two-tree sphere (FCX_ROTATION only): with x = 2 xi - 1, y = 2 eta - 1 and
+ * d = max(|x|, |y|), tree 0's point is (sin(th) x / rho, sin(th) y / rho,
+ * cos(th)), th = d pi / 2, rho = |(x, y)|; tree 1 negates the second and
+ * third components.  Beyond a square corner (where only the two trees'
+ * corner cells meet) the ghost region is the own tree's corner mirrored
+ * through that point. */
 int fcx_sphere_geometry(fcx_ctx *ctx, double *geo, void *stream);   /* FCX_SPHERE, FCX_ROTATION */
 
 /* ---- learned tagging (an extension of the Sec. 5 criterion tags) ------
