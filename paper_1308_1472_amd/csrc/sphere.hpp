@@ -744,10 +744,11 @@ k_rotation_fluxes(const double* __restrict__ geo, double* __restrict__ flux,
 //   phase 0: the tile's state with its 2-cell halo, dt / (kappa dx) of every
 //     frame cell, and the flux of every edge of both directions (edges
 //     e = 0 .. T+2 between cells e-1 and e, rows r = 0 .. T+1);
-//   phase 1: the waves (jumps) and the Courant numbers;
-//   phase 2: limited corrections and the transverse parts, which leave
-//     the receiving cell through its own transverse edges at their fluxes;
-//   phase 3: each cell's update, q - dt / (kappa dx) (fluctuations +
+//   phase 1: at edges 1 .. T+1, the waves (jumps of the staged state), the
+//     Courant numbers, limited corrections and the transverse parts, which
+//     leave the receiving cell through its own transverse edges at their
+//     fluxes;
+//   phase 2: each cell's update, q - dt / (kappa dx) (fluctuations +
 //     differences of the correction fluxes) per direction.
 // The edge fluxes come from k_rotation_fluxes' table, rounded to R.
 template <typename R, int T, int NT>
@@ -756,7 +757,7 @@ k_rotation_step(RotationArgs A) {
   constexpr int FT = T + 4, FRT = FT * FT, M2 = T + 2, NE = (T + 3) * (T + 2);
   __shared__ R Qs[FRT];
   __shared__ double dtk[FRT];
-  __shared__ R S[2][NE], Wv[2][NE], CQ[2][NE], TR[2][NE][4];
+  __shared__ R S[2][NE], CQ[2][NE], TR[2][NE][4];
   __shared__ double red[NT / 64];
   const R* q = static_cast<const R*>(A.q);
   const R* ghost = static_cast<const R*>(A.ghost);
@@ -788,31 +789,28 @@ k_rotation_step(RotationArgs A) {
     S[d][er] = R(fl0[d * FR + fidx(m, i0 + ir, j0 + jr)]);
   }
   __syncthreads();
-  // phase 1
+  // phase 1: at edges 1..T+1 of both directions, the wave (the jump, read
+  // from the staged state), the Courant numbers, the limited correction and
+  // the transverse parts
   double nmax = 0.0;
-  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
-    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
-    const int il = d == 0 ? e - 1 : r, jl = d == 0 ? r : e - 1;
-    const int ir = d == 0 ? e : r, jr = d == 0 ? r : e;
-    Wv[d][er] = Qs[lf(ir, jr)] - Qs[lf(il, jl)];
-    if (r >= 1 && r <= T && e >= 1 && e <= T + 1) {
-      const double sw = double(S[d][er]);
-      nmax = fmax(nmax, dtk[lf(ir, jr)] * fmax(sw, 0.0));
-      nmax = fmax(nmax, dtk[lf(il, jl)] * fmax(-sw, 0.0));
-    }
-  }
-  __syncthreads();
-  // phase 2
-  for (int it = threadIdx.x; it < 2 * NE; it += blockDim.x) {
-    const int d = it / NE, er = it % NE, e = er / M2, r = er % M2;
-    if (e < 1 || e > T + 1) continue;
+  auto wave = [&](int d, int e, int r) -> R {
+    return d == 0 ? Qs[lf(e, r)] - Qs[lf(e - 1, r)] : Qs[lf(r, e)] - Qs[lf(r, e - 1)];
+  };
+  constexpr int NI = (T + 1) * M2;
+  for (int it = threadIdx.x; it < 2 * NI; it += blockDim.x) {
+    const int d = it / NI, ir_ = it % NI, e = 1 + ir_ / M2, r = ir_ % M2;
+    const int er = ei(e, r);
     const int il = d == 0 ? e - 1 : r, jl = d == 0 ? r : e - 1;
     const int ir = d == 0 ? e : r, jr = d == 0 ? r : e;
     const double dtdl = dtk[lf(il, jl)], dtdr = dtk[lf(ir, jr)];
-    const R sw = S[d][er], wc = Wv[d][er];
+    const R sw = S[d][er], wc = Qs[lf(ir, jr)] - Qs[lf(il, jl)];
+    if (r >= 1 && r <= T) {
+      nmax = fmax(nmax, dtdr * fmax(double(sw), 0.0));
+      nmax = fmax(nmax, dtdl * fmax(-double(sw), 0.0));
+    }
     R cq = R(0);
     if (wc != R(0)) {
-      const R wu = Wv[d][ei(sw > R(0) ? e - 1 : e + 1, r)];
+      const R wu = wave(d, sw > R(0) ? e - 1 : e + 1, r);
       const R lim = limiter_phi<R>(A.limiter, (wu * wc) * rcp_(wc * wc));
       const R as = fabs(sw);
       cq = as * (R(1) - R(0.5 * (dtdl + dtdr)) * as) * lim * wc;
@@ -836,7 +834,7 @@ k_rotation_step(RotationArgs A) {
     }
   }
   __syncthreads();
-  // phase 3: total correction flux of edge (e, r) in direction d: its own
+  // phase 2: total correction flux of edge (e, r) in direction d: its own
   // half correction, then the transverse parts of the other direction's
   // edges whose receiving cells it bounds
   auto Ftot = [&](int d, int e, int r) -> R {
@@ -849,7 +847,7 @@ k_rotation_step(RotationArgs A) {
     return v;
   };
   auto fl = [&](int d, int e, int r, bool ap) -> R {
-    const R sw = S[d][ei(e, r)], wv = Wv[d][ei(e, r)];
+    const R sw = S[d][ei(e, r)], wv = wave(d, e, r);
     return ap ? fmax(sw, R(0)) * wv : fmin(sw, R(0)) * wv;
   };
   R* qn = static_cast<R*>(A.qn);
