@@ -820,8 +820,8 @@ static int step_dispatch(fcx_ctx* c, const void* q, const void* ghost, void* qn,
     if (c->cfg.m % 16 == 0)
       return dp ? launch_rotation_step<double, 16, 256>(c, q, ghost, qn, dt, numax, s)
                 : launch_rotation_step<float, 16, 256>(c, q, ghost, qn, dt, numax, s);
-    return dp ? launch_rotation_step<double, 8, 256>(c, q, ghost, qn, dt, numax, s)
-              : launch_rotation_step<float, 8, 256>(c, q, ghost, qn, dt, numax, s);
+    return dp ? launch_rotation_step<double, 8, 128>(c, q, ghost, qn, dt, numax, s)
+              : launch_rotation_step<float, 8, 128>(c, q, ghost, qn, dt, numax, s);
   }
   if (c->cfg.physics == FCX_ADVECTION)
     return dp ? launch_step_m<double, FCX_ADVECTION, FUSED>(c, q, ghost, qn, dt, numax, s)
