@@ -207,3 +207,46 @@ def test_refused_calls():
         ctx.fused_step(a[0], a[1], dt, nu)
     with pytest.raises(fcx.FcxError):
         ctx.advance_subcycled(a[0], a[1], a[2], g, dt, nu, st)
+
+
+@pytest.mark.parametrize("mesh", ["uniform_level6", "adaptive_3_6"])
+def test_example2_configuration_within_1e5_of_oracle(mesh):
+    """The configuration the Example 2 benchmark times: the two-tree sphere,
+    m = 8, FP32, the 0/1 halves; uniform level 6 (8192 patches, 524k cells)
+    or the adaptive levels 3-6 mesh the criterion builds from the halves;
+    three steps with the benchmark's first dt and the CFL rule, against the
+    FP64 oracle within 1e-5 relative L1."""
+    import torch
+    say(f"[rotation] example 2 configuration {mesh}")
+    m, lmin, lmax, T, thr = 8, 3, 6, 1.0, 0.2
+    axis = (0.3, -0.4, 0.866)
+    trees = I.pillow_sphere()
+    cfg = fcx.config(m, 32, fcx.FCX_ROTATION, period=T, axis=axis)
+    if mesh == "uniform_level6":
+        lv = fcx.sfc_sort(I.uniform_leaves(2, lmax))
+    else:
+        ctx = fcx.Context(cfg, trees)
+        lv = fcx.sfc_sort(I.uniform_leaves(2, lmin))
+        for _ in range(2 * (lmax - lmin) + 2):
+            ctx.upload_forest(lv)
+            q = torch.from_numpy(I.sphere_halves(lv, m, pillow=True).ravel()).float().cuda()
+            g = torch.empty(ctx.ghost_elems(), dtype=torch.float32, device="cuda")
+            ctx.regrid(q, g, 0, thr, lmin, lmax)
+            new = ctx.leaves()
+            if len(new) == len(lv) and (new == lv).all():
+                break
+            lv = new
+        assert len(set(lv["level"].tolist())) >= 3
+    q0 = I.sphere_halves(lv, m, pillow=True)
+    gpu = Gpu(cfg, trees, lv)
+    gpu.set_state(q0)
+    omesh = O.Mesh(trees, lv, m, sphere=True)
+    par = oracle_params(cfg)
+    dt = 0.5 * (np.pi / 2) / (m << lmax) * T / (2 * np.pi)
+    want = q0
+    for k in range(3):
+        nu, used = gpu.step(dt if k == 0 else None, auto_dt=True)
+        want, nu_o = O.advance(omesh, par, want, used)
+        assert abs(nu - nu_o) <= 1e-6 * nu_o
+    got = gpu.state()
+    assert np.sum(np.abs(got - want)) <= 1e-5 * np.sum(np.abs(want))
