@@ -136,3 +136,39 @@ def test_refused_calls():
     st = torch.zeros(1, dtype=torch.int32, device="cuda")
     with pytest.raises(fcx.FcxError):
         ctx.advance_subcycled(a[0], a[1], a[2], g, dt, nu, st)
+
+
+@pytest.mark.parametrize("mesh", ["uniform_level6", "adaptive_3_6"])
+def test_example1_configuration_within_1e5_of_oracle(mesh):
+    """The configuration the Example 1 benchmark times: the walled unit
+    square, m = 8, FP32 fused steps, the 0/1 halves, the swirl of period 2;
+    uniform level 6 (4096 patches) or a seeded adaptive forest of levels
+    3-6 (the benchmark's own adaptive mesh starts as uniform level 3: the
+    halves' interface lies on patch edges until the flow moves it); three
+    steps with the benchmark's first dt and the CFL rule, against the FP64
+    oracle within 1e-5 relative L1."""
+    say(f"[swirl] example 1 configuration {mesh}")
+    m, lmin, lmax, T = 8, 3, 6, 2.0
+    trees, pl = I.walled_square()
+    halves = lambda x, y: np.where(x < 0.5, 1.0, 0.0) + 0.0 * y
+    cfg = fcx.config(m, 32, fcx.FCX_SWIRL, period=T)
+    if mesh == "uniform_level6":
+        lv = fcx.sfc_sort(I.uniform_leaves(1, lmax))
+    else:
+        lv = fcx.balance(trees, I.random_leaves(21, 1, lmin, lmax, 60))
+        assert len(set(lv["level"].tolist())) >= 3
+    q0 = I.state_from(lv, m, halves, pl)
+    gpu = Gpu(cfg, trees, lv)
+    gpu.set_state(q0)
+    omesh = O.Mesh(trees, lv, m)
+    par = oracle_params(cfg)
+    want, t = q0, 0.0
+    for k in range(3):
+        nu, used = gpu.step(0.9 / (m << lmax) if k == 0 else None, fused=True, auto_dt=True)
+        par.time = t
+        qn, nu_o = O.advance(omesh, par, want, used)
+        assert abs(nu - nu_o) <= 1e-6 * nu_o
+        if not nu_o > cfg.cfl_max:
+            want, t = qn, t + used
+    got = gpu.state()
+    assert np.sum(np.abs(got - want)) <= 1e-5 * np.sum(np.abs(want))
