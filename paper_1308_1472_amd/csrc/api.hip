@@ -1232,10 +1232,22 @@ struct fcx_batch {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // the general-halo advection tiles of a class run on `side`, beside the
+  // strip walk of the same class (fork before the walk, join before the
+  // reflux): the walk leaves registers free for one of their wavefronts per
+  // SIMD, and their launch is latency-bound
+  hipStream_t side = nullptr;
+  hipEvent_t fork[4] = {}, join[4] = {};
+  bool joined[4] = {};
   ~fcx_batch() {
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap) (void)hipStreamDestroy(cap);
+    for (int k = 0; k < 4; ++k) {
+      if (fork[k]) (void)hipEventDestroy(fork[k]);
+      if (join[k]) (void)hipEventDestroy(join[k]);
+    }
+    if (side) (void)hipStreamDestroy(side);
   }
 };
 
@@ -1518,6 +1530,16 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
     const dim3 gs(unsigned((ns + kAdvWaves - 1) / kAdvWaves));
     const dim3 gg(unsigned((ng + kAdvWaves - 1) / kAdvWaves));
     const bool spec = b->mc2[cls];
+    // both runs present: the general tiles go to the side stream, forked
+    // here (after the work before this class) and joined before the reflux
+    const bool fork = ns > 0 && ng > 0;
+    if (fork) {
+      if (!b->side) HIPCHK(hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking));
+      if (!b->fork[cls]) HIPCHK(hipEventCreateWithFlags(&b->fork[cls], hipEventDisableTiming));
+      if (!b->join[cls]) HIPCHK(hipEventCreateWithFlags(&b->join[cls], hipEventDisableTiming));
+      HIPCHK(hipEventRecord(b->fork[cls], s));
+      HIPCHK(hipStreamWaitEvent(b->side, b->fork[cls], 0));
+    }
     if (ns > 0) {
       // the strip-halo items: resident wavefronts walking runs of items
       B.nitems = ns;
@@ -1531,10 +1553,16 @@ static int launch_batch_class(fcx_batch* b, int cls, const void* q, void* qn,
     if (ng > 0) {
       B.item0 = b->item0[cls] + ns;
       B.nitems = ng;
+      hipStream_t sg = fork ? b->side : s;
       if (spec)
-        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloGeneral, 1>), gg, dim3(threads), 0, s, B);
+        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloGeneral, 1>), gg, dim3(threads), 0, sg, B);
       else
-        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloGeneral, 0>), gg, dim3(threads), 0, s, B);
+        hipLaunchKernelGGL((k_batch_adv<R, T, kHaloGeneral, 0>), gg, dim3(threads), 0, sg, B);
+      if (fork) {
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipEventRecord(b->join[cls], b->side));
+        b->joined[cls] = true;
+      }
     }
   } else if (b->mc2[cls]) {
     hipLaunchKernelGGL((k_batch_step<R, PHYS, T, NT, 1>), dim3(unsigned(b->nitems[cls])),
@@ -1563,6 +1591,11 @@ static int batch_step_t(fcx_batch* b, const void* q, void* qn, double* dt,
     rc = t16 ? launch_batch_class<R, FCX_SHALLOW, 16, 512>(b, 3, q, qn, dt, numax, s)
              : launch_batch_class<R, FCX_SHALLOW, 16, 256>(b, 3, q, qn, dt, numax, s);
   if (rc != FCX_OK) return rc;
+  for (int k = 0; k < 4; ++k)
+    if (b->joined[k]) {
+      HIPCHK(hipStreamWaitEvent(s, b->join[k], 0));
+      b->joined[k] = false;
+    }
   for (int axis = 0; axis < 2; ++axis) {
     const int32_t n = axis == 0 ? b->n_reflux_x : b->n_reflux_y;
     if (n == 0) continue;
