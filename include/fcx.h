@@ -392,7 +392,12 @@ int fcx_batch_set_tuning(fcx_batch *batch, int32_t tile_big, int32_t threads8,
                          int32_t threads16, int32_t persistent);
 
 /* One step of every forest: fused ghost gather + update (per forest: its own
- * dt), reflux, per-forest next dt as fcx_next_dt.  q_new must not alias q. */
+ * dt), reflux, per-forest next dt as fcx_next_dt.  q_new must not alias q.
+ * With launch form 0, an advection class whose tiles have both kinds of
+ * halo runs its general-halo tiles on a stream of the batch's own, forked
+ * from `stream` before the class and joined back into it before the reflux
+ * (so the step stays ordered on `stream`, and a capture of `stream` takes
+ * both branches); calls that overlap on one batch race. */
 int fcx_batch_step(fcx_batch *batch, const void *q, void *q_new, double *dt,
                    double *nu_max, int32_t *status, void *stream);
 
