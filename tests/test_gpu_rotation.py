@@ -99,13 +99,14 @@ def test_steps_match_oracle(precision, m, state):
         assert np.sum(np.abs(got - want)) <= 1e-5 * np.sum(np.abs(want))
 
 
-def test_ghost_fill_and_sums_match_oracle():
-    say("[rotation] ghost fill + sums")
+@pytest.mark.parametrize("pillow", [False, True])
+def test_ghost_fill_and_sums_match_oracle(pillow):
+    say(f"[rotation] ghost fill + sums pillow={pillow}")
     m = 8
-    trees, lv = _forest(7, 1, 3, 14)
+    trees, lv = _forest(7, 1, 3, 14, pillow)
     cfg = fcx.config(m, 64, fcx.FCX_ROTATION, axis=AXIS)
     g = Gpu(cfg, trees, lv)
-    q = _blob(lv, m) + 0.25 * I.sphere_halves(lv, m)
+    q = _blob(lv, m, pillow) + 0.25 * I.sphere_halves(lv, m, pillow=pillow)
     g.set_state(q)
     g.fill()
     got = ghost_to_frame(g.ghosts(), g.state(), m)

@@ -208,3 +208,35 @@ def test_rotation_on_the_pillow_converges():
     assert steady[0] / steady[1] > 3.0 and steady[1] / steady[2] > 3.0, steady
     assert turn[0] / turn[1] > 3.0 and turn[1] / turn[2] > 3.0, turn
     assert steady[-1] < 5e-3 and turn[-1] < 0.03
+
+
+def test_corner_ghosts_are_the_own_corner_mirrored():
+    """Beyond a square corner (where only the two trees' corner cells meet)
+    the ghost cells hold the own tree's cells mirrored through the corner:
+    frame cell (1 - a, 1 - b) of the corner patch holds its cell (a, b)."""
+    trees = I.pillow_sphere()
+    lv = O.sfc_sort(I.uniform_leaves(2, 1))
+    mesh = _mesh(lv)
+    par = O.params(M, O.ROTATION, axis=AXIS)
+    q = np.random.default_rng(3).random((len(lv), 1, M, M))
+    f = O.framed(q, M)
+    O.ghost_fill(mesh, par, f)
+    seen = 0
+    for p, a in enumerate(lv):
+        n = 1 << int(a["level"])
+        for cx in (0, 1):
+            for cy in (0, 1):
+                if int(a["ix"]) != cx * (n - 1) or int(a["iy"]) != cy * (n - 1):
+                    continue
+                seen += 1
+                for da in (1, 2):
+                    for db in (1, 2):
+                        # own cell (i, j) counted from the corner, and its mirror
+                        i = da if cx == 0 else M + 1 - da
+                        j = db if cy == 0 else M + 1 - db
+                        gi = 1 - da if cx == 0 else M + da
+                        gj = 1 - db if cy == 0 else M + db
+                        if (gi in (-1, M + 2)) and (gj in (-1, M + 2)):
+                            continue           # outermost corner: never used
+                        assert f[p, 0, gj + 1, gi + 1] == f[p, 0, j + 1, i + 1]
+    assert seen == 8          # four corners in each of the two trees
